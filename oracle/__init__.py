@@ -91,6 +91,8 @@ def lib():
         L.orc_join.restype = ctypes.c_int
         L.orc_join.argtypes = [VP, VP, ctypes.c_int32, P(Params), P(VP), P(ctypes.c_int64),
                                P(VP), P(ctypes.c_int64), P(Stats)]
+        L.orc_join_candidates.restype = ctypes.c_int
+        L.orc_join_candidates.argtypes = L.orc_join.argtypes
         L.orc_search.restype = ctypes.c_int
         L.orc_search.argtypes = [VP, VP, ctypes.c_int32, P(Params), VP, VP, ctypes.c_int32,
                                  P(Params), P(VP), P(ctypes.c_int64), P(VP), P(ctypes.c_int64)]
@@ -203,16 +205,18 @@ def _take_u64(ptr, n):
     return a
 
 
-def join(chars, offsets, params):
-    """Returns (candidates, pairs, stats): sorted uint64 arrays lo<<32|hi and a dict."""
+def join(chars, offsets, params, verify=True):
+    """Returns (candidates, pairs, stats): sorted uint64 arrays lo<<32|hi and a dict.
+    With verify=False the verification stage is skipped and pairs is empty."""
     chars = _u8(chars)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     n = len(offsets) - 1
     cp, pp = ctypes.c_void_p(), ctypes.c_void_p()
     nc, npairs = ctypes.c_int64(), ctypes.c_int64()
     st = Stats()
-    lib().orc_join(_ptr(chars), _ptr(offsets), n, ctypes.byref(params), ctypes.byref(cp),
-                   ctypes.byref(nc), ctypes.byref(pp), ctypes.byref(npairs), ctypes.byref(st))
+    fn = lib().orc_join if verify else lib().orc_join_candidates
+    fn(_ptr(chars), _ptr(offsets), n, ctypes.byref(params), ctypes.byref(cp),
+       ctypes.byref(nc), ctypes.byref(pp), ctypes.byref(npairs), ctypes.byref(st))
     cand = _take_u64(cp, nc.value)
     pairs = _take_u64(pp, npairs.value)
     return cand, pairs, {"records": st.records, "candidates": st.candidates,

@@ -384,9 +384,9 @@ static int64_t verify_pairs(const uint8_t *chars, const int64_t *off, const int6
 
 /* Join.  Outputs (malloc'ed, free with orc_free): the deduplicated candidate pairs
  * and the accepted pairs, both as sorted u64 (min id << 32 | max id). */
-int orc_join(const uint8_t *chars, const int64_t *offsets, int32_t n, const orc_params *p,
-             uint64_t **cand_out, int64_t *ncand, uint64_t **pairs_out, int64_t *npairs,
-             orc_stats *stats) {
+static int join_impl(const uint8_t *chars, const int64_t *offsets, int32_t n, const orc_params *p,
+                     uint64_t **cand_out, int64_t *ncand, uint64_t **pairs_out, int64_t *npairs,
+                     orc_stats *stats, int do_verify) {
     int nt = p->threads > 0 ? p->threads : 1;
     /* S0: per-string K and the sorted order */
     int64_t *K = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
@@ -454,12 +454,25 @@ int orc_join(const uint8_t *chars, const int64_t *offsets, int32_t n, const orc_
     uint64_t *c2 = (uint64_t *)malloc(sizeof(uint64_t) * ((size_t)cc + 1));
     memcpy(c2, cand, sizeof(uint64_t) * (size_t)cc);
     /* S3: verification */
-    int64_t no = verify_pairs(chars, offsets, K, cand, cc, nt);
+    int64_t no = do_verify ? verify_pairs(chars, offsets, K, cand, cc, nt) : 0;
     if (stats) { stats->records = R; stats->candidates = cc; stats->output = no; stats->pair_tests = tests; }
     *cand_out = c2; *ncand = cc;
     *pairs_out = cand; *npairs = no;
     free(rec); free(rstart); free(order); free(K);
     return 0;
+}
+
+int orc_join(const uint8_t *chars, const int64_t *offsets, int32_t n, const orc_params *p,
+             uint64_t **cand_out, int64_t *ncand, uint64_t **pairs_out, int64_t *npairs,
+             orc_stats *stats) {
+    return join_impl(chars, offsets, n, p, cand_out, ncand, pairs_out, npairs, stats, 1);
+}
+
+/* The join without its verification stage: candidates only (*npairs = 0). */
+int orc_join_candidates(const uint8_t *chars, const int64_t *offsets, int32_t n,
+                        const orc_params *p, uint64_t **cand_out, int64_t *ncand,
+                        uint64_t **pairs_out, int64_t *npairs, orc_stats *stats) {
+    return join_impl(chars, offsets, n, p, cand_out, ncand, pairs_out, npairs, stats, 0);
 }
 
 /* Search: the index holds every partition of the index strings (no eviction); each

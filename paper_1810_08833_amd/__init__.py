@@ -1,0 +1,326 @@
+"""MinJoin on MI355X: Python binding of libminjoin.so (C-ABI in include/minjoin.h).
+
+The binding only marshals arguments: strings live in torch tensors on the GPU
+(``chars``: uint8 symbol codes, ``offsets``: int64, n + 1 entries), the stream is
+torch's current HIP stream, and every step of the method runs in the library's HIP
+kernels.  Pair results are uint64 values ``a << 32 | b`` copied to host NumPy arrays.
+
+If the library is not built (``python -m paper_1810_08833_amd.build``) every call raises
+``RuntimeError``: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libminjoin.so")
+
+MJ_OK, MJ_EINVAL, MJ_ENOMEM, MJ_EDEVICE, MJ_ECAPACITY = 0, 1, 2, 3, 4
+STATUS_NAMES = {0: "MJ_OK", 1: "MJ_EINVAL", 2: "MJ_ENOMEM", 3: "MJ_EDEVICE", 4: "MJ_ECAPACITY"}
+STAGES = ["setup", "partition", "sort", "group_filter", "dedup", "verify", "output", "unused"]
+
+
+class MjStrings(ctypes.Structure):
+    _fields_ = [("chars", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("sigma", ctypes.c_int32)]
+
+
+class MjParams(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("t_div", ctypes.c_int32), ("t_fixed", ctypes.c_int32),
+                ("reps", ctypes.c_int32), ("seed", ctypes.c_uint64), ("k", ctypes.c_int64),
+                ("k_per_string", ctypes.c_void_p), ("pi_table", ctypes.c_void_p)]
+
+
+class MjStats(ctypes.Structure):
+    _fields_ = [("records", ctypes.c_int64), ("groups", ctypes.c_int64),
+                ("pair_tests", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("output", ctypes.c_int64), ("band_cells", ctypes.c_int64),
+                ("stage_ms", ctypes.c_float * 8)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k in ("records", "groups", "pair_tests", "candidates",
+                                           "output", "band_cells")}
+        d["stage_ms"] = {STAGES[i]: float(self.stage_ms[i]) for i in range(7)}
+        return d
+
+
+EXPORTS = ["mj_ctx_create", "mj_ctx_destroy", "mj_last_error", "mj_version", "mj_join",
+           "mj_partition", "mj_candidates", "mj_verify", "mj_index_build", "mj_index_free",
+           "mj_index_records", "mj_search", "mj_pairs_count", "mj_pairs_device",
+           "mj_pairs_copy_to_host", "mj_pairs_free", "mj_records_count",
+           "mj_records_copy_to_host", "mj_records_free"]
+
+_lib = None
+
+
+class MinJoinError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libminjoin.so and declares its C signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libminjoin.so is not built (%s); run "
+                           "`python -m paper_1810_08833_amd.build`" % path)
+    L = ctypes.CDLL(path)
+    P, VP, I64 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int64
+    L.mj_ctx_create.argtypes = [ctypes.c_int, P(VP)]
+    L.mj_ctx_destroy.argtypes = [VP]
+    L.mj_ctx_destroy.restype = None
+    L.mj_last_error.restype = ctypes.c_char_p
+    L.mj_version.restype = ctypes.c_char_p
+    L.mj_join.argtypes = [VP, P(MjStrings), P(MjParams), VP, P(VP), P(MjStats)]
+    L.mj_candidates.argtypes = [VP, P(MjStrings), P(MjParams), VP, P(VP), P(MjStats)]
+    L.mj_partition.argtypes = [VP, P(MjStrings), P(MjParams), VP, P(VP)]
+    L.mj_verify.argtypes = [VP, P(MjStrings), P(MjParams), VP, I64, VP, VP]
+    L.mj_index_build.argtypes = [VP, P(MjStrings), P(MjParams), VP, P(VP)]
+    L.mj_index_free.argtypes = [VP]
+    L.mj_index_free.restype = None
+    L.mj_index_records.argtypes = [VP]
+    L.mj_index_records.restype = I64
+    L.mj_search.argtypes = [VP, VP, P(MjStrings), P(MjParams), VP, P(VP), P(MjStats)]
+    L.mj_pairs_count.argtypes = [VP]
+    L.mj_pairs_count.restype = I64
+    L.mj_pairs_device.argtypes = [VP]
+    L.mj_pairs_device.restype = VP
+    L.mj_pairs_copy_to_host.argtypes = [VP, VP, I64]
+    L.mj_pairs_free.argtypes = [VP]
+    L.mj_pairs_free.restype = None
+    L.mj_records_count.argtypes = [VP]
+    L.mj_records_count.restype = I64
+    L.mj_records_copy_to_host.argtypes = [VP, VP, VP, VP, VP, I64]
+    L.mj_records_free.argtypes = [VP]
+    L.mj_records_free.restype = None
+    for fn in ("mj_ctx_create", "mj_join", "mj_candidates", "mj_partition", "mj_verify",
+               "mj_index_build", "mj_search", "mj_pairs_copy_to_host", "mj_records_copy_to_host"):
+        getattr(L, fn).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != MJ_OK:
+        raise MinJoinError(status, load_library().mj_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """Owns an mj_ctx (device workspace) on one GPU."""
+
+    def __init__(self, device: Optional[int] = None):
+        torch = _torch()
+        L = load_library()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        _check(L.mj_ctx_create(self.device, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            load_library().mj_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context(device: Optional[int] = None) -> Context:
+    torch = _torch()
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _default_ctx:
+        _default_ctx[dev] = Context(dev)
+    return _default_ctx[dev]
+
+
+@dataclass
+class DeviceStrings:
+    """Strings resident on the GPU: uint8 codes + int64 offsets (torch tensors)."""
+    chars: "object"
+    offsets: "object"
+    sigma: int
+
+    @property
+    def n(self) -> int:
+        return int(self.offsets.numel()) - 1
+
+    @classmethod
+    def from_host(cls, chars, offsets, sigma, device=None):
+        torch = _torch()
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        c = torch.from_numpy(np.ascontiguousarray(chars, dtype=np.uint8))
+        if c.numel() == 0:
+            c = torch.zeros(1, dtype=torch.uint8)
+        return cls(c.to(dev), torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).to(dev),
+                   int(sigma))
+
+    def struct(self) -> MjStrings:
+        s = MjStrings()
+        s.chars = self.chars.data_ptr()
+        s.offsets = self.offsets.data_ptr()
+        s.n = self.n
+        s.sigma = self.sigma
+        return s
+
+
+@dataclass
+class Params:
+    """Method parameters: q-gram length, K (uniform or per string), T rule, seed."""
+    q: int
+    k: int = -1
+    k_per_string: Optional[object] = None   # torch int32 tensor on the GPU
+    t_div: int = 1
+    t_fixed: int = 0
+    reps: int = 1
+    seed: int = 0
+    pi_table: Optional[object] = None       # torch uint64/int64 tensor on the GPU
+
+    def struct(self) -> MjParams:
+        p = MjParams()
+        p.q, p.t_div, p.t_fixed, p.reps = self.q, self.t_div, self.t_fixed, self.reps
+        p.seed = self.seed
+        p.k = self.k if self.k_per_string is None else -1
+        p.k_per_string = None if self.k_per_string is None else self.k_per_string.data_ptr()
+        p.pi_table = None if self.pi_table is None else self.pi_table.data_ptr()
+        return p
+
+
+def _take_pairs(h) -> np.ndarray:
+    L = load_library()
+    n = L.mj_pairs_count(h)
+    out = np.zeros(max(n, 1), dtype=np.uint64)
+    st = L.mj_pairs_copy_to_host(h, out.ctypes.data_as(ctypes.c_void_p), len(out))
+    L.mj_pairs_free(h)
+    _check(st)
+    return out[:n]
+
+
+def join(strings: DeviceStrings, params: Params, ctx: Optional[Context] = None, stream=None):
+    """All pairs i < j with ED <= K sharing a filtered partition (Alg. 3).
+    Returns (pairs uint64 array, stats dict)."""
+    L = load_library()
+    ctx = ctx or default_context()
+    s, p, st, h = strings.struct(), params.struct(), MjStats(), ctypes.c_void_p()
+    _check(L.mj_join(ctx.handle, ctypes.byref(s), ctypes.byref(p), _stream_ptr(stream),
+                     ctypes.byref(h), ctypes.byref(st)))
+    return _take_pairs(h), st.as_dict()
+
+
+def candidates(strings: DeviceStrings, params: Params, ctx: Optional[Context] = None, stream=None):
+    """Distinct candidate pairs before verification (Alg. 3 up to the dedup)."""
+    L = load_library()
+    ctx = ctx or default_context()
+    s, p, st, h = strings.struct(), params.struct(), MjStats(), ctypes.c_void_p()
+    _check(L.mj_candidates(ctx.handle, ctypes.byref(s), ctypes.byref(p), _stream_ptr(stream),
+                           ctypes.byref(h), ctypes.byref(st)))
+    return _take_pairs(h), st.as_dict()
+
+
+RECORD_DTYPE = np.dtype([("key", "<u8"), ("sid", "<i4"), ("pos", "<i4"), ("len", "<i4")])
+
+
+def partition(strings: DeviceStrings, params: Params, ctx: Optional[Context] = None, stream=None):
+    """Partition records of every string and repetition (Alg. 1-2), host structured array
+    ordered by (repetition, string, position)."""
+    L = load_library()
+    ctx = ctx or default_context()
+    s, p, h = strings.struct(), params.struct(), ctypes.c_void_p()
+    _check(L.mj_partition(ctx.handle, ctypes.byref(s), ctypes.byref(p), _stream_ptr(stream),
+                          ctypes.byref(h)))
+    n = L.mj_records_count(h)
+    cap = max(n, 1)
+    key = np.zeros(cap, np.uint64)
+    sid = np.zeros(cap, np.int32)
+    pos = np.zeros(cap, np.int32)
+    ln = np.zeros(cap, np.int32)
+    st = L.mj_records_copy_to_host(h, key.ctypes.data, sid.ctypes.data, pos.ctypes.data,
+                                   ln.ctypes.data, cap)
+    L.mj_records_free(h)
+    _check(st)
+    out = np.zeros(n, RECORD_DTYPE)
+    out["key"], out["sid"], out["pos"], out["len"] = key[:n], sid[:n], pos[:n], ln[:n]
+    return out
+
+
+def verify(strings: DeviceStrings, params: Params, pairs, ctx: Optional[Context] = None,
+           stream=None) -> np.ndarray:
+    """Banded verification of the given pairs (a << 32 | b): bool array ED <= max(K_a, K_b)."""
+    torch = _torch()
+    L = load_library()
+    ctx = ctx or default_context()
+    dev = strings.chars.device
+    pt = torch.from_numpy(np.ascontiguousarray(pairs, dtype=np.uint64).view(np.int64)).to(dev)
+    n = int(pt.numel())
+    flags = torch.zeros(max(n, 1), dtype=torch.uint8, device=dev)
+    s, p = strings.struct(), params.struct()
+    _check(L.mj_verify(ctx.handle, ctypes.byref(s), ctypes.byref(p),
+                       ctypes.c_void_p(pt.data_ptr() if n else 0), n,
+                       ctypes.c_void_p(flags.data_ptr()), _stream_ptr(stream)))
+    return flags[:n].cpu().numpy().astype(bool)
+
+
+class Index:
+    """Device-resident partition index over a string collection (for search)."""
+
+    def __init__(self, strings: DeviceStrings, params: Params, ctx: Optional[Context] = None,
+                 stream=None):
+        L = load_library()
+        self.ctx = ctx or default_context()
+        s, p, h = strings.struct(), params.struct(), ctypes.c_void_p()
+        _check(L.mj_index_build(self.ctx.handle, ctypes.byref(s), ctypes.byref(p),
+                                _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+        self.sigma = strings.sigma
+
+    @property
+    def records(self) -> int:
+        return load_library().mj_index_records(self.handle)
+
+    def search(self, queries: DeviceStrings, k: int = -1, k_per_query=None, stream=None):
+        """(query id << 32 | string id) pairs with ED <= K_query; returns (pairs, stats)."""
+        L = load_library()
+        qp = Params(q=1, k=k, k_per_string=k_per_query)
+        s, p, st, h = queries.struct(), qp.struct(), MjStats(), ctypes.c_void_p()
+        _check(L.mj_search(self.ctx.handle, self.handle, ctypes.byref(s), ctypes.byref(p),
+                           _stream_ptr(stream), ctypes.byref(h), ctypes.byref(st)))
+        return _take_pairs(h), st.as_dict()
+
+    def close(self):
+        if self.handle:
+            load_library().mj_index_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def version() -> str:
+    return load_library().mj_version().decode()

@@ -1,0 +1,562 @@
+// C-ABI of libminjoin: argument checks, stage sequencing on the caller's stream, count
+// read-backs between stages, per-stage HIP-event timers and result ownership.
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "mj_common.h"
+
+using namespace mj;
+
+struct mj_ctx {
+    int device = 0;
+    Workspace ws;
+    uint64_t *pinned = nullptr;  // host scratch for read-backs (4 KiB)
+    hipEvent_t ev[9] = {};
+};
+
+struct mj_pairs {
+    uint64_t *d = nullptr;
+    int64_t n = 0;
+};
+
+struct mj_records {
+    RecBuf rb;
+};
+
+struct mj_index {
+    int device = 0;
+    PartitionParams pp{};
+    int32_t n = 0, sigma = 0, bits = 0;
+    int64_t total = 0;
+    uint8_t *chars = nullptr;
+    int64_t *offsets = nullptr;
+    int32_t *len = nullptr, *kk = nullptr;
+    uint32_t *planes = nullptr;
+    int64_t plane_words = 0;
+    int np = 0;
+    RecBuf rec;  // sorted by (key, val)
+};
+
+static thread_local std::string g_err = "no error";
+
+static mj_status fail(mj_status st, const std::string &m) {
+    g_err = m;
+    return st;
+}
+
+#define MJ_API_BEGIN try {
+#define MJ_API_END                                            \
+    }                                                         \
+    catch (const mj::Error &e) {                              \
+        return fail(e.status, e.what());                      \
+    }                                                         \
+    catch (const std::exception &e) {                         \
+        return fail(MJ_EDEVICE, e.what());                    \
+    }                                                         \
+    catch (...) {                                             \
+        return fail(MJ_EDEVICE, "unknown error");             \
+    }
+
+extern "C" const char *mj_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *mj_version(void) { return "minjoin-mi355x 0.1 (gfx950)"; }
+
+extern "C" mj_status mj_ctx_create(int device, mj_ctx **out) {
+    if (!out) return fail(MJ_EINVAL, "out is NULL");
+    MJ_API_BEGIN
+    int count = 0;
+    MJ_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(MJ_EINVAL, "bad device index");
+    MJ_HIP(hipSetDevice(device));
+    mj_ctx *c = new mj_ctx();
+    c->device = device;
+    if (hipHostMalloc((void **)&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return fail(MJ_ENOMEM, "pinned host allocation failed");
+    }
+    for (auto &e : c->ev) MJ_HIP(hipEventCreate(&e));
+    *out = c;
+    return MJ_OK;
+    MJ_API_END
+}
+
+extern "C" void mj_ctx_destroy(mj_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+}
+
+// ---------------------------------------------------------------- helpers
+static int ceil_log2(uint64_t v) {
+    int b = 0;
+    while (b < 63 && (1ull << b) < v) b++;
+    return b;
+}
+
+static void check_params(const mj_params *p, int sigma, bool need_k) {
+    if (!p) throw Error(MJ_EINVAL, "params is NULL");
+    if (sigma < 2 || sigma > 256) throw Error(MJ_EINVAL, "sigma must be in 2..256");
+    int b = symbol_bits(sigma);
+    if (p->q < 1 || (int64_t)p->q * b > 64) throw Error(MJ_EINVAL, "q must satisfy 1 <= q*ceil(log2 sigma) <= 64");
+    if (p->t_fixed <= 0 && p->t_div < 1) throw Error(MJ_EINVAL, "t_div must be >= 1");
+    if (p->reps < 0 || p->reps > 64) throw Error(MJ_EINVAL, "reps must be in 0..64");
+    if (need_k) {
+        if (p->k < -1) throw Error(MJ_EINVAL, "k must be >= 0 or -1");
+        if (p->k == -1 && !p->k_per_string) throw Error(MJ_EINVAL, "k == -1 needs k_per_string");
+        if (p->k > 0x3FFFFFFF) throw Error(MJ_EINVAL, "k too large");
+    }
+    if (p->pi_table && (int64_t)p->q * b > 24) throw Error(MJ_EINVAL, "pi_table needs q*b <= 24");
+}
+
+static void check_strings(const mj_strings *s) {
+    if (!s) throw Error(MJ_EINVAL, "strings is NULL");
+    if (s->n < 0) throw Error(MJ_EINVAL, "n must be >= 0");
+    if (s->n > 0 && (!s->offsets)) throw Error(MJ_EINVAL, "offsets is NULL");
+}
+
+static PartitionParams to_pp(const mj_params *p, int bits) {
+    PartitionParams pp;
+    pp.q = p->q;
+    pp.bits = bits;
+    pp.t_div = std::max(1, p->t_div);
+    pp.t_fixed = p->t_fixed;
+    pp.reps = p->reps > 0 ? p->reps : 1;
+    pp.seed = p->seed;
+    pp.k = p->k;
+    pp.k_per_string = p->k_per_string;
+    pp.pi_table = p->pi_table;
+    return pp;
+}
+
+static DevStrings view(const mj_strings *s, hipStream_t st, uint64_t *pinned) {
+    DevStrings d;
+    d.chars = s->chars;
+    d.offsets = s->offsets;
+    d.n = s->n;
+    d.sigma = s->sigma;
+    d.bits = symbol_bits(s->sigma);
+    d.total = s->n > 0 ? read_back<int64_t>(s->offsets + s->n, st, pinned) : 0;
+    if (d.total < 0) throw Error(MJ_EINVAL, "offsets[n] < 0");
+    if (d.total > 0 && !s->chars) throw Error(MJ_EINVAL, "chars is NULL");
+    return d;
+}
+
+// All partitions of all repetitions, sorted by (key, payload).
+static void sorted_records(const DevStrings &d, const PartitionParams &pp, int32_t halo, RecBuf &rb,
+                           Workspace &ws, hipStream_t s, uint64_t *pinned) {
+    for (int rho = 0; rho < pp.reps; rho++) partition_records(d, pp, rho, halo, rb, ws, s, pinned);
+    int64_t R = rb.count;
+    if (R > 1) {
+        int bb = std::min(22, std::max(1, ceil_log2((uint64_t)(R / 128 + 1))));
+        sort_pairs(rb.key, rb.val, R, 64 - bb, bb, ws, s);
+    }
+}
+
+static mj_pairs *compact_pairs(const uint64_t *pairs, const uint8_t *flags, int64_t n, Workspace &ws,
+                               hipStream_t s, uint64_t *pinned) {
+    mj_pairs *out = new mj_pairs();
+    if (n == 0) {
+        out->d = (uint64_t *)dev_alloc(16);
+        out->n = 0;
+        return out;
+    }
+    // flags are 0/1 here (2 would mean an unhandled band, rejected earlier)
+    int64_t *idx = ws.get_n<int64_t>(n + 1);
+    int64_t c = compact_flags(flags, n, idx, ws, s, pinned);
+    out->d = (uint64_t *)dev_alloc((size_t)(c + 1) * 8);
+    gather_u64(pairs, idx, out->d, c, s);
+    out->n = c;
+    return out;
+}
+
+__global__ void k_check_flags(const uint8_t *f, int64_t n, uint32_t *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        if (f[i] > 1) atomicOr(bad, 1u);
+}
+
+static void check_flags(const uint8_t *f, int64_t n, Workspace &ws, hipStream_t s, uint64_t *pinned) {
+    if (n <= 0) return;
+    uint32_t *bad = ws.get_n<uint32_t>(2);
+    fill_u32(bad, 0, 1, s);
+    unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_check_flags, dim3(g), dim3(256), 0, s, f, n, bad);
+    MJ_LAUNCH_CHECK();
+    if (read_back<uint32_t>(bad, s, pinned)) throw Error(MJ_ECAPACITY, "threshold K exceeds the verifier's band limit (K <= 2047)");
+}
+
+struct StageTimer {
+    mj_ctx *ctx;
+    hipStream_t s;
+    int next = 0;
+    StageTimer(mj_ctx *c, hipStream_t st) : ctx(c), s(st) { mark(); }
+    void mark() {
+        if (next < 9) MJ_HIP(hipEventRecord(ctx->ev[next++], s));
+    }
+    void fill(mj_stats *st) {
+        if (!st) return;
+        MJ_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < 8; i++) {
+            float ms = 0.f;
+            if (i + 1 < next) MJ_HIP(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+            st->stage_ms[i] = ms;
+        }
+    }
+};
+
+struct Released {
+    Workspace &ws;
+    ~Released() { ws.release_all(); }
+};
+
+// ---------------------------------------------------------------- join pipeline
+// Runs the join up to `upto`: 1 = candidates, 2 = output.  Fills stats.
+static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
+                          hipStream_t s, int upto, mj_stats *stats) {
+    Workspace &ws = ctx->ws;
+    Released rel{ws};
+    StageTimer tm(ctx, s);
+    DevStrings d = view(strings, s, ctx->pinned);
+    PartitionParams pp = to_pp(params, d.bits);
+    int32_t halo = prepare_strings(d, pp, ws, s, ctx->pinned);
+    if (upto >= 2) pack_planes(d, verify_planes(d.bits), ws, s);
+    tm.mark();  // 0 setup
+    RecBuf rb;
+    struct RbFree { RecBuf &r; ~RbFree() { r.release(); } } rbf{rb};
+    for (int rho = 0; rho < pp.reps; rho++) partition_records(d, pp, rho, halo, rb, ws, s, ctx->pinned);
+    tm.mark();  // 1 partition: anchors and records
+    int64_t R = rb.count;
+    if (R > 1) {
+        int bb = std::min(22, std::max(1, ceil_log2((uint64_t)(R / 128 + 1))));
+        sort_pairs(rb.key, rb.val, R, 64 - bb, bb, ws, s);
+    }
+    tm.mark();  // 2 sort
+    GroupInfo g = find_groups(rb.key, R, ws, s, ctx->pinned);
+    if (g.tests > (uint64_t)0x7FFFFFFF)
+        throw Error(MJ_ECAPACITY, "record-pair tests exceed 2^31 (" + std::to_string(g.tests) + ")");
+    int64_t cap = (int64_t)g.tests;
+    uint64_t *cand = ws.get_n<uint64_t>(cap + 1);
+    int64_t c0 = emit_candidates(rb.val, g, d, cand, cap, ws, s, ctx->pinned);
+    tm.mark();  // 3 group + filter
+    uint64_t *uniq = nullptr;
+    int64_t C = dedup_pairs(cand, c0, d.n, ws, s, ctx->pinned, &uniq);
+    tm.mark();  // 4 dedup
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->records = R;
+        stats->groups = g.groups;
+        stats->pair_tests = (int64_t)g.tests;
+        stats->candidates = C;
+    }
+    if (upto == 1) {
+        mj_pairs *out = new mj_pairs();
+        out->d = uniq;
+        out->n = C;
+        tm.fill(stats);
+        return out;
+    }
+    struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
+    uint8_t *flags = ws.get_n<uint8_t>(C + 1);
+    int64_t cells = verify_pairs(uniq, C, d, d, 0, flags, ws, s, ctx->pinned);
+    check_flags(flags, C, ws, s, ctx->pinned);
+    tm.mark();  // 5 verify
+    mj_pairs *out = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);
+    tm.mark();  // 6 output
+    if (stats) {
+        stats->output = out->n;
+        stats->band_cells = cells;
+    }
+    tm.fill(stats);
+    return out;
+}
+
+extern "C" mj_status mj_join(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
+                             void *stream, mj_pairs **out, mj_stats *stats) {
+    if (!ctx || !out) return fail(MJ_EINVAL, "ctx/out is NULL");
+    MJ_API_BEGIN
+    check_strings(strings);
+    check_params(params, strings->sigma, true);
+    MJ_HIP(hipSetDevice(ctx->device));
+    *out = run_join(ctx, strings, params, (hipStream_t)stream, 2, stats);
+    return MJ_OK;
+    MJ_API_END
+}
+
+extern "C" mj_status mj_candidates(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
+                                   void *stream, mj_pairs **out, mj_stats *stats) {
+    if (!ctx || !out) return fail(MJ_EINVAL, "ctx/out is NULL");
+    MJ_API_BEGIN
+    check_strings(strings);
+    check_params(params, strings->sigma, true);
+    MJ_HIP(hipSetDevice(ctx->device));
+    *out = run_join(ctx, strings, params, (hipStream_t)stream, 1, stats);
+    return MJ_OK;
+    MJ_API_END
+}
+
+extern "C" mj_status mj_partition(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
+                                  void *stream, mj_records **out) {
+    if (!ctx || !out) return fail(MJ_EINVAL, "ctx/out is NULL");
+    MJ_API_BEGIN
+    check_strings(strings);
+    check_params(params, strings->sigma, true);
+    MJ_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &ws = ctx->ws;
+    Released rel{ws};
+    DevStrings d = view(strings, s, ctx->pinned);
+    PartitionParams pp = to_pp(params, d.bits);
+    int32_t halo = prepare_strings(d, pp, ws, s, ctx->pinned);
+    mj_records *r = new mj_records();
+    r->rb.with_len = true;
+    try {
+        for (int rho = 0; rho < pp.reps; rho++)
+            partition_records(d, pp, rho, halo, r->rb, ws, s, ctx->pinned);
+        MJ_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        r->rb.release();
+        delete r;
+        throw;
+    }
+    *out = r;
+    return MJ_OK;
+    MJ_API_END
+}
+
+extern "C" mj_status mj_verify(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
+                               const uint64_t *pairs, int64_t n, uint8_t *flags, void *stream) {
+    if (!ctx) return fail(MJ_EINVAL, "ctx is NULL");
+    if (n < 0 || (n > 0 && (!pairs || !flags))) return fail(MJ_EINVAL, "bad pair list");
+    MJ_API_BEGIN
+    check_strings(strings);
+    check_params(params, strings->sigma, true);
+    MJ_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &ws = ctx->ws;
+    Released rel{ws};
+    DevStrings d = view(strings, s, ctx->pinned);
+    PartitionParams pp = to_pp(params, d.bits);
+    (void)prepare_strings(d, pp, ws, s, ctx->pinned);
+    pack_planes(d, verify_planes(d.bits), ws, s);
+    verify_pairs(pairs, n, d, d, 0, flags, ws, s, ctx->pinned);
+    check_flags(flags, n, ws, s, ctx->pinned);
+    MJ_HIP(hipStreamSynchronize(s));
+    return MJ_OK;
+    MJ_API_END
+}
+
+// ---------------------------------------------------------------- search
+extern "C" mj_status mj_index_build(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
+                                    void *stream, mj_index **out) {
+    if (!ctx || !out) return fail(MJ_EINVAL, "ctx/out is NULL");
+    MJ_API_BEGIN
+    check_strings(strings);
+    check_params(params, strings->sigma, true);
+    MJ_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &ws = ctx->ws;
+    Released rel{ws};
+    DevStrings d = view(strings, s, ctx->pinned);
+    PartitionParams pp = to_pp(params, d.bits);
+    pp.k_per_string = nullptr;  // not kept: the index stores per-string K below
+    mj_index *ix = new mj_index();
+    try {
+        ix->device = ctx->device;
+        ix->n = d.n;
+        ix->sigma = d.sigma;
+        ix->bits = d.bits;
+        ix->total = d.total;
+        ix->np = verify_planes(d.bits);
+        ix->chars = (uint8_t *)dev_alloc((size_t)d.total + 16);
+        ix->offsets = (int64_t *)dev_alloc(((size_t)d.n + 1) * 8);
+        ix->len = (int32_t *)dev_alloc(((size_t)d.n + 1) * 4);
+        ix->kk = (int32_t *)dev_alloc(((size_t)d.n + 1) * 4);
+        if (d.total) MJ_HIP(hipMemcpyAsync(ix->chars, d.chars, (size_t)d.total, hipMemcpyDeviceToDevice, s));
+        MJ_HIP(hipMemcpyAsync(ix->offsets, d.offsets, ((size_t)d.n + 1) * 8, hipMemcpyDeviceToDevice, s));
+        DevStrings di = d;
+        di.chars = ix->chars;
+        di.offsets = ix->offsets;
+        PartitionParams pk = to_pp(params, d.bits);
+        int32_t halo = prepare_strings(di, pk, ws, s, ctx->pinned);
+        if (d.n) {
+            MJ_HIP(hipMemcpyAsync(ix->len, di.len, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s));
+            MJ_HIP(hipMemcpyAsync(ix->kk, di.kk, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s));
+        }
+        pack_planes(di, ix->np, ws, s);
+        ix->plane_words = di.plane_words;
+        ix->planes = (uint32_t *)dev_alloc((size_t)ix->np * di.plane_words * 4);
+        MJ_HIP(hipMemcpyAsync(ix->planes, di.planes, (size_t)ix->np * di.plane_words * 4,
+                              hipMemcpyDeviceToDevice, s));
+        sorted_records(di, pk, halo, ix->rec, ws, s, ctx->pinned);
+        MJ_HIP(hipStreamSynchronize(s));
+        ix->pp = pp;
+    } catch (...) {
+        mj_index_free(ix);
+        throw;
+    }
+    *out = ix;
+    return MJ_OK;
+    MJ_API_END
+}
+
+extern "C" void mj_index_free(mj_index *ix) {
+    if (!ix) return;
+    (void)hipSetDevice(ix->device);
+    dev_free(ix->chars);
+    dev_free(ix->offsets);
+    dev_free(ix->len);
+    dev_free(ix->kk);
+    dev_free(ix->planes);
+    ix->rec.release();
+    delete ix;
+}
+
+extern "C" int64_t mj_index_records(const mj_index *ix) { return ix ? ix->rec.count : 0; }
+
+extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings *queries,
+                               const mj_params *qparams, void *stream, mj_pairs **out,
+                               mj_stats *stats) {
+    if (!ctx || !ix || !out) return fail(MJ_EINVAL, "ctx/index/out is NULL");
+    MJ_API_BEGIN
+    check_strings(queries);
+    if (!qparams) throw Error(MJ_EINVAL, "qparams is NULL");
+    if (queries->sigma > ix->sigma || queries->sigma < 2)
+        throw Error(MJ_EINVAL, "query alphabet must not exceed the index alphabet");
+    if (qparams->k < -1 || (qparams->k == -1 && !qparams->k_per_string))
+        throw Error(MJ_EINVAL, "bad query threshold");
+    MJ_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &ws = ctx->ws;
+    Released rel{ws};
+    StageTimer tm(ctx, s);
+    DevStrings qd = view(queries, s, ctx->pinned);
+    qd.sigma = ix->sigma;
+    qd.bits = ix->bits;
+    PartitionParams qp = ix->pp;  // q, seed, T rule, reps of the index
+    qp.k = qparams->k;
+    qp.k_per_string = qparams->k_per_string;
+    int32_t halo = prepare_strings(qd, qp, ws, s, ctx->pinned);
+    pack_planes(qd, ix->np, ws, s);
+    tm.mark();  // 0 setup
+    RecBuf rb;
+    struct RbFree { RecBuf &r; ~RbFree() { r.release(); } } rbf{rb};
+    for (int rho = 0; rho < qp.reps; rho++) partition_records(qd, qp, rho, halo, rb, ws, s, ctx->pinned);
+    tm.mark();  // 1 partition
+    if (rb.count > 1) {
+        int bb = std::min(22, std::max(1, ceil_log2((uint64_t)(rb.count / 128 + 1))));
+        sort_pairs(rb.key, rb.val, rb.count, 64 - bb, bb, ws, s);
+    }
+    tm.mark();  // 2 sort
+    DevStrings id;
+    id.chars = ix->chars;
+    id.offsets = ix->offsets;
+    id.n = ix->n;
+    id.sigma = ix->sigma;
+    id.bits = ix->bits;
+    id.total = ix->total;
+    id.len = ix->len;
+    id.kk = ix->kk;
+    id.planes = ix->planes;
+    id.plane_words = ix->plane_words;
+    uint64_t tests = 0;
+    int64_t need = probe_candidates(rb.key, rb.val, rb.count, ix->rec.key, ix->rec.val, ix->rec.count,
+                                    qd, id, nullptr, -1, &tests, ws, s, ctx->pinned);
+    (void)need;
+    if (tests > (uint64_t)0x7FFFFFFF)
+        throw Error(MJ_ECAPACITY, "record-pair tests exceed 2^31");
+    uint64_t *cand = ws.get_n<uint64_t>(tests + 1);
+    int64_t c0 = tests ? probe_candidates(rb.key, rb.val, rb.count, ix->rec.key, ix->rec.val,
+                                          ix->rec.count, qd, id, cand, (int64_t)tests, &tests, ws, s,
+                                          ctx->pinned)
+                       : 0;
+    tm.mark();  // 3 probe + filter
+    uint64_t *uniq = nullptr;
+    int32_t maxid = std::max(qd.n, 1);
+    int64_t C = dedup_pairs(cand, c0, maxid, ws, s, ctx->pinned, &uniq);
+    struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
+    tm.mark();  // 4 dedup
+    uint8_t *flags = ws.get_n<uint8_t>(C + 1);
+    int64_t cells = verify_pairs(uniq, C, qd, id, 1, flags, ws, s, ctx->pinned);
+    check_flags(flags, C, ws, s, ctx->pinned);
+    tm.mark();  // 5 verify
+    mj_pairs *res = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);
+    tm.mark();  // 6 output
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->records = rb.count;
+        stats->pair_tests = (int64_t)tests;
+        stats->candidates = C;
+        stats->output = res->n;
+        stats->band_cells = cells;
+    }
+    tm.fill(stats);
+    *out = res;
+    return MJ_OK;
+    MJ_API_END
+}
+
+// ---------------------------------------------------------------- results
+extern "C" int64_t mj_pairs_count(const mj_pairs *p) { return p ? p->n : 0; }
+extern "C" const uint64_t *mj_pairs_device(const mj_pairs *p) { return p ? p->d : nullptr; }
+
+extern "C" mj_status mj_pairs_copy_to_host(const mj_pairs *p, uint64_t *dst, int64_t cap) {
+    if (!p) return fail(MJ_EINVAL, "pairs is NULL");
+    if (cap < p->n || (p->n > 0 && !dst)) return fail(MJ_EINVAL, "destination too small");
+    MJ_API_BEGIN
+    if (p->n) MJ_HIP(hipMemcpy(dst, p->d, (size_t)p->n * 8, hipMemcpyDeviceToHost));
+    return MJ_OK;
+    MJ_API_END
+}
+
+extern "C" void mj_pairs_free(mj_pairs *p) {
+    if (!p) return;
+    dev_free(p->d);
+    delete p;
+}
+
+extern "C" int64_t mj_records_count(const mj_records *r) { return r ? r->rb.count : 0; }
+
+__global__ void k_split_records(const uint64_t *val, int64_t n, int32_t *sid, int32_t *pos) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) {
+        sid[i] = (int32_t)(val[i] >> 32);
+        pos[i] = (int32_t)(uint32_t)val[i];
+    }
+}
+
+extern "C" mj_status mj_records_copy_to_host(const mj_records *r, uint64_t *key, int32_t *sid,
+                                             int32_t *pos, int32_t *len, int64_t cap) {
+    if (!r) return fail(MJ_EINVAL, "records is NULL");
+    int64_t n = r->rb.count;
+    if (cap < n) return fail(MJ_EINVAL, "destination too small");
+    MJ_API_BEGIN
+    if (n == 0) return MJ_OK;
+    if (key) MJ_HIP(hipMemcpy(key, r->rb.key, (size_t)n * 8, hipMemcpyDeviceToHost));
+    if (len && r->rb.len) MJ_HIP(hipMemcpy(len, r->rb.len, (size_t)n * 4, hipMemcpyDeviceToHost));
+    if (sid || pos) {
+        int32_t *ds = (int32_t *)dev_alloc((size_t)n * 4), *dp = (int32_t *)dev_alloc((size_t)n * 4);
+        unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 16384);
+        hipLaunchKernelGGL(k_split_records, dim3(g), dim3(256), 0, 0, r->rb.val, n, ds, dp);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess && sid) e = hipMemcpy(sid, ds, (size_t)n * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && pos) e = hipMemcpy(pos, dp, (size_t)n * 4, hipMemcpyDeviceToHost);
+        dev_free(ds);
+        dev_free(dp);
+        MJ_HIP(e);
+    }
+    return MJ_OK;
+    MJ_API_END
+}
+
+extern "C" void mj_records_free(mj_records *r) {
+    if (!r) return;
+    r->rb.release();
+    delete r;
+}

@@ -1,0 +1,316 @@
+// Join stage: groups of records with equal bucket key (the hash table D of Alg. 3),
+// candidate emission through the length and position filters (Alg. 3; Sec. 3),
+// candidate dedup, and the probe of a resident index for search.
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "mj_common.h"
+
+namespace mj {
+
+static unsigned grid_for(int64_t n, int block, unsigned cap = 65535u) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    return (unsigned)std::min<int64_t>(g, cap);
+}
+
+static int ceil_log2(uint64_t v) {
+    int b = 0;
+    while (b < 63 && (1ull << b) < v) b++;
+    return b;
+}
+
+// ---------------------------------------------------------------- groups
+// A group is a maximal run of equal keys in the sorted records; only runs of length
+// >= 2 can produce pairs.  start flag: first of a run of >= 2; end flag: last of one.
+__global__ void k_group_flags(const uint64_t *key, int64_t R, uint8_t *fs, uint8_t *fe) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < R; i += stride) {
+        uint64_t k = key[i];
+        bool same_prev = i > 0 && key[i - 1] == k;
+        bool same_next = i + 1 < R && key[i + 1] == k;
+        fs[i] = (!same_prev && same_next) ? 1 : 0;
+        fe[i] = (same_prev && !same_next) ? 1 : 0;
+    }
+}
+
+__global__ void k_group_tests(const int64_t *gs, const int64_t *ge, int64_t G, uint64_t *cnt) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; g < G; g += stride) {
+        uint64_t sz = (uint64_t)(ge[g] - gs[g] + 1);
+        cnt[g] = sz * (sz - 1) / 2;
+    }
+}
+
+GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t s,
+                      uint64_t *host_scratch) {
+    GroupInfo gi;
+    if (R < 2) return gi;
+    uint8_t *fs = ws.get_n<uint8_t>(R);
+    uint8_t *fe = ws.get_n<uint8_t>(R);
+    hipLaunchKernelGGL(k_group_flags, dim3(grid_for(R, 256, 16384)), dim3(256), 0, s, key, R, fs, fe);
+    MJ_LAUNCH_CHECK();
+    int64_t *gs = ws.get_n<int64_t>(R / 2 + 2);
+    int64_t *ge = ws.get_n<int64_t>(R / 2 + 2);
+    int64_t G1 = compact_flags(fs, R, gs, ws, s, host_scratch);
+    int64_t G2 = compact_flags(fe, R, ge, ws, s, host_scratch);
+    if (G1 != G2) throw Error(MJ_EDEVICE, "group boundary mismatch");
+    gi.groups = G1;
+    gi.gstart = gs;
+    if (G1 == 0) return gi;
+    uint64_t *cnt = ws.get_n<uint64_t>(G1 + 1);
+    gi.tstart = ws.get_n<uint64_t>(G1 + 1);
+    hipLaunchKernelGGL(k_group_tests, dim3(grid_for(G1, 256, 16384)), dim3(256), 0, s, gs, ge, G1, cnt);
+    MJ_LAUNCH_CHECK();
+    exclusive_scan_u64(cnt, gi.tstart, G1, ws, s);
+    gi.tests = read_back<uint64_t>(gi.tstart + G1, s, host_scratch);
+    return gi;
+}
+
+// ---------------------------------------------------------------- candidate emission
+// Pair tests are numbered consecutively across groups; each thread takes EMIT_CHUNK
+// consecutive tests, so a huge group is spread over many threads.  Inside a group of
+// size z, test u is the pair (a, b), a < b, with u = b(b-1)/2 + a.
+// Filter (Alg. 3): |m_i - m_j| <= K and |pos_i - pos_j| + |(m_i-pos_i) - (m_j-pos_j)| <= K,
+// evaluated as max(|m_i - m_j|, |(2pos_i - m_i) - (2pos_j - m_j)|) <= K (the same test,
+// since |u| + |v| = max(|u + v|, |u - v|)).
+constexpr int EMIT_CHUNK = 16;
+
+__device__ __forceinline__ int64_t iabs64(int64_t v) { return v < 0 ? -v : v; }
+
+__device__ __forceinline__ bool pass_filter(int64_t mi, int64_t pi, int64_t mj, int64_t pj,
+                                            int64_t K) {
+    int64_t d1 = iabs64(mi - mj);
+    int64_t d2 = iabs64((2 * pi - mi) - (2 * pj - mj));
+    return (d1 > d2 ? d1 : d2) <= K;
+}
+
+// Wave-aggregated append of `v` where `pass` holds.
+__device__ __forceinline__ void append(bool pass, uint64_t v, unsigned long long *counter,
+                                       uint64_t *out, int64_t cap) {
+    uint64_t mask = __ballot(pass);
+    if (mask == 0) return;
+    const int lane = threadIdx.x & 63;
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (pass) {
+        unsigned long long idx = base + __popcll(mask & ((1ull << lane) - 1));
+        if ((int64_t)idx < cap) out[idx] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_emit(const uint64_t *__restrict__ val,
+                                              const int64_t *__restrict__ gs,
+                                              const uint64_t *__restrict__ ts, int64_t G,
+                                              uint64_t P, const int32_t *__restrict__ len,
+                                              const int32_t *__restrict__ kk, uint64_t *out,
+                                              int64_t cap, unsigned long long *counter) {
+    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * EMIT_CHUNK; ;
+         t0 += nthreads * EMIT_CHUNK) {
+        // uniform loop exit: every lane of the wave leaves together
+        uint64_t wave_first = t0 - (uint64_t)(threadIdx.x & 63) * EMIT_CHUNK;
+        if (wave_first >= P) break;
+        bool active = t0 < P;
+        int64_t g = 0;
+        uint64_t a = 0, b = 1;
+        if (active) {
+            int64_t lo = 0, hi = G;  // largest g with ts[g] <= t0
+            while (hi - lo > 1) {
+                int64_t mid = (lo + hi) >> 1;
+                if (ts[mid] <= t0) lo = mid; else hi = mid;
+            }
+            g = lo;
+            uint64_t u = t0 - ts[g];
+            b = (uint64_t)((1.0 + sqrt(1.0 + 8.0 * (double)u)) * 0.5);
+            while (b > 1 && b * (b - 1) / 2 > u) b--;
+            while ((b + 1) * b / 2 <= u) b++;
+            a = u - b * (b - 1) / 2;
+        }
+        for (int c = 0; c < EMIT_CHUNK; c++) {
+            uint64_t t = t0 + c;
+            bool live = active && t < P;
+            bool pass = false;
+            uint64_t pairkey = 0;
+            if (live) {
+                int64_t s0 = gs[g];
+                uint64_t va = val[s0 + (int64_t)a], vb = val[s0 + (int64_t)b];
+                int32_t ia = (int32_t)(va >> 32), ib = (int32_t)(vb >> 32);
+                if (ia != ib) {
+                    int64_t ma = len[ia], mb = len[ib];
+                    int64_t K = max(kk[ia], kk[ib]);
+                    pass = pass_filter(ma, (int64_t)(uint32_t)va, mb, (int64_t)(uint32_t)vb, K);
+                    uint64_t lo = (uint64_t)min(ia, ib), hi = (uint64_t)max(ia, ib);
+                    pairkey = (lo << 32) | hi;
+                }
+                // next test: (a+1, b); else (0, b+1); a group of z records ends at b = z,
+                // which is when b(b-1)/2 equals its test count
+                a++;
+                if (a == b) {
+                    a = 0;
+                    b++;
+                    if (b * (b - 1) / 2 == ts[g + 1] - ts[g]) {
+                        g++;
+                        b = 1;
+                    }
+                }
+            }
+            append(pass, pairkey, counter, out, cap);
+        }
+    }
+}
+
+int64_t emit_candidates(const uint64_t *val, const GroupInfo &g, const DevStrings &d,
+                        uint64_t *out, int64_t cap, Workspace &ws, hipStream_t s,
+                        uint64_t *host_scratch) {
+    if (g.groups == 0 || g.tests == 0) return 0;
+    unsigned long long *counter = (unsigned long long *)ws.get_n<uint64_t>(2);
+    fill_u64((uint64_t *)counter, 0, 1, s);
+    uint64_t threads = (g.tests + EMIT_CHUNK - 1) / EMIT_CHUNK;
+    unsigned grid = (unsigned)std::min<uint64_t>((threads + 255) / 256, 1u << 16);
+    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(256), 0, s, val, g.gstart, g.tstart, g.groups,
+                       g.tests, d.len, d.kk, out, cap, counter);
+    MJ_LAUNCH_CHECK();
+    uint64_t c = read_back<uint64_t>((const uint64_t *)counter, s, host_scratch);
+    if ((int64_t)c > cap) throw Error(MJ_ECAPACITY, "candidate buffer overflow");
+    return (int64_t)c;
+}
+
+// ---------------------------------------------------------------- dedup
+__global__ void k_unique_flags(const uint64_t *p, int64_t n, uint8_t *f) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) f[i] = (i == 0 || p[i] != p[i - 1]) ? 1 : 0;
+}
+
+int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t max_id, Workspace &ws, hipStream_t s,
+                    uint64_t *host_scratch, uint64_t **result) {
+    if (n == 0) {
+        *result = (uint64_t *)dev_alloc(16);
+        return 0;
+    }
+    int bb = std::min(22, std::max(1, ceil_log2((uint64_t)(n / 128 + 1))));
+    int top = 32 + ceil_log2((uint64_t)max_id + 1);  // pairs < 2^top
+    if (top > 64) top = 64;
+    int shift = std::max(0, top - bb);
+    sort_pairs(pairs, nullptr, n, shift, bb, ws, s);
+    uint8_t *f = ws.get_n<uint8_t>(n);
+    hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, pairs, n, f);
+    MJ_LAUNCH_CHECK();
+    int64_t *idx = ws.get_n<int64_t>(n + 1);
+    int64_t u = compact_flags(f, n, idx, ws, s, host_scratch);
+    uint64_t *res = (uint64_t *)dev_alloc((size_t)(u + 1) * 8);
+    gather_u64(pairs, idx, res, u, s);
+    *result = res;
+    return u;
+}
+
+// ---------------------------------------------------------------- search probe
+// For each query record, the equal-key range of the sorted index records.
+__global__ void k_probe_ranges(const uint64_t *qkey, int64_t RQ, const uint64_t *ikey, int64_t RI,
+                               int64_t *lo_out, uint64_t *cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < RQ; i += stride) {
+        uint64_t k = qkey[i];
+        int64_t lo = 0, hi = RI;  // first index with ikey >= k
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (ikey[mid] < k) lo = mid + 1; else hi = mid;
+        }
+        int64_t e = lo, hi2 = RI;  // first index with ikey > k
+        while (e < hi2) {
+            int64_t mid = (e + hi2) >> 1;
+            if (ikey[mid] <= k) e = mid + 1; else hi2 = mid;
+        }
+        lo_out[i] = lo;
+        cnt[i] = (uint64_t)(e - lo);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_probe_emit(const uint64_t *__restrict__ qval,
+                                                    const int64_t *__restrict__ lo_arr,
+                                                    const uint64_t *__restrict__ ts, int64_t RQ,
+                                                    uint64_t P, const uint64_t *__restrict__ ival,
+                                                    const int32_t *__restrict__ qlen,
+                                                    const int32_t *__restrict__ qk,
+                                                    const int32_t *__restrict__ ilen,
+                                                    uint64_t *out, int64_t cap,
+                                                    unsigned long long *counter) {
+    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * EMIT_CHUNK; ;
+         t0 += nthreads * EMIT_CHUNK) {
+        uint64_t wave_first = t0 - (uint64_t)(threadIdx.x & 63) * EMIT_CHUNK;
+        if (wave_first >= P) break;
+        bool active = t0 < P;
+        int64_t r = 0;
+        uint64_t j = 0;
+        if (active) {
+            int64_t lo = 0, hi = RQ;  // largest r with ts[r] <= t0
+            while (hi - lo > 1) {
+                int64_t mid = (lo + hi) >> 1;
+                if (ts[mid] <= t0) lo = mid; else hi = mid;
+            }
+            r = lo;
+            j = t0 - ts[r];
+        }
+        for (int c = 0; c < EMIT_CHUNK; c++) {
+            uint64_t t = t0 + c;
+            bool live = active && t < P;
+            bool pass = false;
+            uint64_t pairkey = 0;
+            if (live) {
+                // skip query records with empty ranges
+                while (j >= ts[r + 1] - ts[r]) {
+                    j = 0;
+                    r++;
+                }
+                uint64_t qv = qval[r];
+                uint64_t iv = ival[lo_arr[r] + (int64_t)j];
+                int32_t qi = (int32_t)(qv >> 32), si = (int32_t)(iv >> 32);
+                pass = pass_filter(qlen[qi], (int64_t)(uint32_t)qv, ilen[si], (int64_t)(uint32_t)iv,
+                                   qk[qi]);
+                pairkey = ((uint64_t)(uint32_t)qi << 32) | (uint64_t)(uint32_t)si;
+                j++;
+            }
+            append(pass, pairkey, counter, out, cap);
+        }
+    }
+}
+
+int64_t probe_candidates(const uint64_t *qkey, const uint64_t *qval, int64_t RQ,
+                         const uint64_t *ikey, const uint64_t *ival, int64_t RI,
+                         const DevStrings &qd, const DevStrings &id, uint64_t *out, int64_t cap,
+                         uint64_t *tests_out, Workspace &ws, hipStream_t s, uint64_t *host_scratch) {
+    *tests_out = 0;
+    if (RQ == 0 || RI == 0) return 0;
+    int64_t *lo = ws.get_n<int64_t>(RQ + 1);
+    uint64_t *cnt = ws.get_n<uint64_t>(RQ + 1);
+    uint64_t *ts = ws.get_n<uint64_t>(RQ + 1);
+    hipLaunchKernelGGL(k_probe_ranges, dim3(grid_for(RQ, 256, 16384)), dim3(256), 0, s, qkey, RQ,
+                       ikey, RI, lo, cnt);
+    MJ_LAUNCH_CHECK();
+    exclusive_scan_u64(cnt, ts, RQ, ws, s);
+    uint64_t P = read_back<uint64_t>(ts + RQ, s, host_scratch);
+    *tests_out = P;
+    if (P == 0) return 0;
+    if (cap < 0) return -(int64_t)P;
+    unsigned long long *counter = (unsigned long long *)ws.get_n<uint64_t>(2);
+    fill_u64((uint64_t *)counter, 0, 1, s);
+    uint64_t threads = (P + EMIT_CHUNK - 1) / EMIT_CHUNK;
+    unsigned grid = (unsigned)std::min<uint64_t>((threads + 255) / 256, 1u << 16);
+    hipLaunchKernelGGL(k_probe_emit, dim3(grid), dim3(256), 0, s, qval, lo, ts, RQ, P, ival,
+                       qd.len, qd.kk, id.len, out, cap, counter);
+    MJ_LAUNCH_CHECK();
+    uint64_t c = read_back<uint64_t>((const uint64_t *)counter, s, host_scratch);
+    if ((int64_t)c > cap) throw Error(MJ_ECAPACITY, "candidate buffer overflow");
+    return (int64_t)c;
+}
+
+}  // namespace mj

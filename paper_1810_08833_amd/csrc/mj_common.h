@@ -1,0 +1,178 @@
+// Internal declarations shared by the HIP sources of libminjoin (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/minjoin.h"
+
+namespace mj {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    mj_status status;
+    Error(mj_status s, const std::string &m) : std::runtime_error(m), status(s) {}
+};
+
+#define MJ_HIP(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw ::mj::Error(MJ_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define MJ_LAUNCH_CHECK() MJ_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- constants
+constexpr uint64_t GAMMA = 0x9E3779B97F4A7C15ull;    // salt increment for the q-gram hash
+constexpr uint64_t GAMMA_B = 0x632BE59BD9B4E019ull;  // separates the partition-key base
+constexpr uint64_t P61 = (1ull << 61) - 1;           // Mersenne prime of the Karp-Rabin key
+
+// SplitMix64 output function: a bijection on 64-bit words (Steele, Lea & Flood 2014).
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// a * b mod 2^61-1 for a, b < 2^61.
+__device__ __forceinline__ uint64_t mulmod61(uint64_t a, uint64_t b) {
+    uint64_t lo = a * b;
+    uint64_t hi = __umul64hi(a, b);
+    uint64_t r = (lo & P61) + ((hi << 3) | (lo >> 61));
+    return r >= P61 ? r - P61 : r;
+}
+
+inline int symbol_bits(int sigma) {
+    int b = 1;
+    while ((1 << b) < sigma) b++;
+    return b;
+}
+
+// ---------------------------------------------------------------- workspace
+// Grow-only cache of device blocks; blocks handed out during one call are released
+// together at its end and reused by the next call.
+class Workspace {
+  public:
+    ~Workspace();
+    void *get(size_t bytes);
+    template <class T> T *get_n(size_t n) { return static_cast<T *>(get(n * sizeof(T) + 16)); }
+    void release_all();
+    size_t bytes_held() const { return held_; }
+
+  private:
+    struct Block { void *p; size_t n; bool used; };
+    std::vector<Block> blocks_;
+    size_t held_ = 0;
+};
+
+// Owned device allocation (results).
+void *dev_alloc(size_t bytes);
+void dev_free(void *p);
+
+// ---------------------------------------------------------------- primitives (prims.hip)
+void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+// out[0..n] = exclusive prefix sums of in[0..n), out[n] = total.
+void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, Workspace &ws, hipStream_t s);
+void exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, Workspace &ws, hipStream_t s);
+// Indices i (ascending) with flags[i] != 0; returns count (reads it back).
+int64_t compact_flags(const uint8_t *flags, int64_t n, int64_t *idx_out, Workspace &ws,
+                      hipStream_t s, uint64_t *host_scratch);
+// Sort (key, val) pairs ascending by (key, val) in place.  Buckets are
+// (key >> shift); shift must make bucket ids < 2^bucket_bits.
+void sort_pairs(uint64_t *key, uint64_t *val, int64_t n, int shift, int bucket_bits,
+                Workspace &ws, hipStream_t s);
+// Gather: out_k[i] = key[idx[i]] (and val).
+void gather_u64(const uint64_t *src, const int64_t *idx, uint64_t *dst, int64_t n, hipStream_t s);
+
+// Read one device value back (synchronises the stream).
+template <class T>
+T read_back(const T *dev, hipStream_t s, void *pinned) {
+    MJ_HIP(hipMemcpyAsync(pinned, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipStreamSynchronize(s));
+    T v;
+    memcpy(&v, pinned, sizeof(T));
+    return v;
+}
+
+// ---------------------------------------------------------------- device views
+// A string collection prepared on the device.
+struct DevStrings {
+    const uint8_t *chars = nullptr;
+    const int64_t *offsets = nullptr;
+    int32_t n = 0;
+    int32_t sigma = 0;
+    int32_t bits = 0;        // b = ceil(log2 sigma)
+    int64_t total = 0;       // offsets[n]
+    int32_t *len = nullptr;  // m_i
+    int32_t *kk = nullptr;   // K_i
+    int32_t *rr = nullptr;   // r_i (repetition-independent)
+    uint32_t *planes = nullptr;  // bit planes: planes[p * plane_words + w]
+    int64_t plane_words = 0;
+};
+
+struct PartitionParams {
+    int q, bits, t_div, t_fixed, reps;
+    uint64_t seed;
+    int64_t k;
+    const int32_t *k_per_string;
+    const uint64_t *pi_table;
+};
+
+// Growable, owned arrays of partition records: key f, payload (sid << 32 | pos), and
+// optionally the length.
+struct RecBuf {
+    uint64_t *key = nullptr;
+    uint64_t *val = nullptr;
+    uint32_t *len = nullptr;
+    int64_t cap = 0, count = 0;
+    bool with_len = false;
+    void reserve(int64_t need, hipStream_t s);
+    void release();
+};
+
+// partition.hip
+int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
+                        uint64_t *host_scratch);       // returns the halo radius needed
+void pack_planes(DevStrings &d, int planes, Workspace &ws, hipStream_t s);
+// Appends the records of every partition of repetition rho to `out`; returns how many.
+int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho, int32_t halo,
+                          RecBuf &out, Workspace &ws, hipStream_t s, uint64_t *host_scratch);
+
+// join.hip
+struct GroupInfo {
+    int64_t groups = 0;
+    uint64_t tests = 0;
+    int64_t *gstart = nullptr;   // group start index in the sorted records
+    uint64_t *tstart = nullptr;  // exclusive prefix of pair tests, groups + 1 entries
+};
+GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t s,
+                      uint64_t *host_scratch);
+// Emit candidate pair keys for all pair tests; returns count emitted (<= cap).
+int64_t emit_candidates(const uint64_t *val, const GroupInfo &g, const DevStrings &d,
+                        uint64_t *out, int64_t cap, Workspace &ws, hipStream_t s,
+                        uint64_t *host_scratch);
+// Sort + unique in place; returns unique count.
+int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t max_id, Workspace &ws, hipStream_t s,
+                    uint64_t *host_scratch, uint64_t **result);
+// Search: probe sorted index keys with sorted query records.
+int64_t probe_candidates(const uint64_t *qkey, const uint64_t *qval, int64_t RQ,
+                         const uint64_t *ikey, const uint64_t *ival, int64_t RI,
+                         const DevStrings &qd, const DevStrings &id, uint64_t *out,
+                         int64_t cap, uint64_t *tests_out, Workspace &ws, hipStream_t s,
+                         uint64_t *host_scratch);
+
+// verify.hip
+// flags[i] = ED(A[a], B[b]) <= K for pairs[i] = a << 32 | b; K = max(K_a, K_b) when
+// kmode == 0, else K_a.  Returns band cells processed (device counter read back).
+int64_t verify_pairs(const uint64_t *pairs, int64_t n, const DevStrings &A, const DevStrings &B,
+                     int kmode, uint8_t *flags, Workspace &ws, hipStream_t s,
+                     uint64_t *host_scratch);
+int verify_planes(int bits);   // planes the verifier needs for b bits per symbol
+
+}  // namespace mj

@@ -1,0 +1,367 @@
+// Partition stage: per-string parameters, bit-plane packing, anchors (Find-Anchor,
+// Alg. 2) and partition records (Partition-String, Alg. 1, with the bucket key f of
+// Alg. 3).
+#include <string.h>
+
+#include <algorithm>
+
+#include "mj_common.h"
+
+namespace mj {
+
+static unsigned grid_for(int64_t n, int block, unsigned cap = 65535u) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    return (unsigned)std::min<int64_t>(g, cap);
+}
+
+// Largest s in [0, n) with off[s] <= g; for 0 <= g < off[n] that string is non-empty
+// and contains position g.
+__device__ __forceinline__ int32_t owner_of(const int64_t *off, int32_t n, int64_t g) {
+    int32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- per-string setup
+// m_i, K_i, and r_i = max(1, floor((m - q + 1 - T) / (2T + 2))) with T from the rule of
+// Remark 1 (Alg. 2 defines r).  The halo needed by the anchor kernel is the largest r
+// of a string that has interior positions.
+__global__ void k_prepare(const int64_t *off, int32_t n, int q, int64_t kuni, const int32_t *kps,
+                          int t_div, int t_fixed, int32_t *len, int32_t *kk, int32_t *rr,
+                          uint32_t *halo, uint32_t *err) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t m = off[i + 1] - off[i];
+    int64_t K = kuni >= 0 ? kuni : (int64_t)kps[i];
+    if (m < 0 || m > 0x7FFFFFFFLL) atomicOr(err, 1u);
+    if (K < 0) atomicOr(err, 2u);
+    if (K > 0x3FFFFFFFLL) K = 0x3FFFFFFFLL;
+    int64_t T = t_fixed > 0 ? (int64_t)t_fixed : (K + t_div - 1) / t_div;
+    if (T < 1) T = 1;
+    int64_t num = m - q + 1 - T;
+    int64_t r = num <= 0 ? 1 : num / (2 * T + 2);
+    if (r < 1) r = 1;
+    int64_t npos = m - q + 1;
+    if (npos - 1 - r >= r) {
+        if (r > 0x7FFFFFFFLL) r = 0x7FFFFFFFLL;
+        atomicMax(halo, (uint32_t)std::min<int64_t>(r, 0xFFFFFFFFLL));
+    }
+    len[i] = (int32_t)m;
+    kk[i] = (int32_t)(K < 0 ? 0 : K);
+    rr[i] = (int32_t)std::min<int64_t>(r, 0x7FFFFFFFLL);
+}
+
+int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
+                        uint64_t *host_scratch) {
+    int32_t n = d.n;
+    d.len = ws.get_n<int32_t>(n + 1);
+    d.kk = ws.get_n<int32_t>(n + 1);
+    d.rr = ws.get_n<int32_t>(n + 1);
+    uint32_t *flags = ws.get_n<uint32_t>(4);
+    fill_u32(flags, 0, 2, s);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_prepare, dim3((n + 255) / 256), dim3(256), 0, s, d.offsets, n, p.q,
+                           p.k, p.k_per_string, p.t_div, p.t_fixed, d.len, d.kk, d.rr, flags,
+                           flags + 1);
+        MJ_LAUNCH_CHECK();
+    }
+    MJ_HIP(hipMemcpyAsync(host_scratch, flags, 8, hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipStreamSynchronize(s));
+    uint32_t hv[2];
+    memcpy(hv, host_scratch, 8);
+    if (hv[1] & 1u) throw Error(MJ_EINVAL, "offsets must be non-decreasing with lengths < 2^31");
+    if (hv[1] & 2u) throw Error(MJ_EINVAL, "K must be >= 0");
+    return (int32_t)hv[0];
+}
+
+// ---------------------------------------------------------------- bit planes
+// planes[p][w] bit t = bit p of the symbol at global position 32w + t (0 past the end).
+__global__ void k_pack_planes(const uint8_t *chars, int64_t total, uint32_t *planes,
+                              int64_t plane_words, int np) {
+    int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; w < plane_words; w += stride) {
+        uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int64_t base = w * 32;
+        for (int t = 0; t < 32; t++) {
+            int64_t g = base + t;
+            uint32_t c = g < total ? chars[g] : 0u;
+#pragma unroll
+            for (int p = 0; p < 8; p++) acc[p] |= ((c >> p) & 1u) << t;
+        }
+        for (int p = 0; p < np; p++) planes[(int64_t)p * plane_words + w] = acc[p];
+    }
+}
+
+void pack_planes(DevStrings &d, int np, Workspace &ws, hipStream_t s) {
+    d.plane_words = (d.total + 31) / 32 + 96;  // padding: windows may read past the end
+    d.planes = ws.get_n<uint32_t>((size_t)np * d.plane_words);
+    hipLaunchKernelGGL(k_pack_planes, dim3(grid_for(d.plane_words, 256, 16384)), dim3(256), 0, s,
+                       d.chars, d.total, d.planes, d.plane_words, np);
+    MJ_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- anchors
+// One workgroup handles a tile of TP positions of the concatenated strings plus a halo
+// of H positions on each side (H >= every radius used).  It hashes every q-gram of the
+// region into LDS, then finds strict minima with a sparse table built by doubling:
+// after level k, cur[a] = min h[a .. a + 2^k - 1].  A position p of radius r is tested
+// at level k = floor(log2 r): the left window [p-r, p-1] is min(cur[p-r], cur[p-2^k])
+// and the right window [p+1, p+r] is min(cur[p+1], cur[p+1+r-2^k]).  Anchors and string
+// starts are written as one bit per position.
+constexpr int AT_THREADS = 256;
+constexpr int AT_REGION_MAX = 4096;              // TP + 2H
+constexpr int AT_RUN = AT_REGION_MAX / AT_THREADS;  // region positions per thread
+constexpr int AT_OWN = AT_REGION_MAX / AT_THREADS;  // tile positions per thread (max)
+constexpr int AT_MAX_HALO = 1920;
+
+__global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
+    const uint8_t *__restrict__ chars, const int64_t *__restrict__ off, int32_t n, int64_t total,
+    int q, int bits, uint64_t salt, const uint64_t *__restrict__ table,
+    const int32_t *__restrict__ rr, int TP, int H, uint64_t *__restrict__ bitmap) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int NR = TP + 2 * H;
+    uint64_t *cur = reinterpret_cast<uint64_t *>(smem_raw);
+    uint16_t *pinfo = reinterpret_cast<uint16_t *>(cur + NR);
+    uint8_t *ch = reinterpret_cast<uint8_t *>(pinfo + TP);
+    __shared__ int kmax_s;
+    const int tid = threadIdx.x;
+    const int64_t tile_start = (int64_t)blockIdx.x * TP;
+    const int64_t base = tile_start - H;
+    if (tid == 0) kmax_s = 0;
+    // symbols of the region (q - 1 extra for the last q-grams)
+    for (int idx = tid; idx < NR + q; idx += AT_THREADS) {
+        int64_t g = base + idx;
+        ch[idx] = (g >= 0 && g < total) ? chars[g] : (uint8_t)0;
+    }
+    __syncthreads();
+    const uint64_t gmask = (q * bits >= 64) ? ~0ull : ((1ull << (q * bits)) - 1);
+    // hashes: each thread walks a contiguous run, rolling the packed q-gram code
+    {
+        const int RL = (NR + AT_THREADS - 1) / AT_THREADS;
+        int run0 = tid * RL, run1 = min(NR, run0 + RL);
+        int32_t sidx = -1;
+        int64_t sbeg = 0, send = 0;
+        bool have = false;
+        uint64_t G = 0;
+        int lmax = 0;
+        for (int idx = run0; idx < run1; idx++) {
+            int64_t g = base + idx;
+            uint64_t h = ~0ull;
+            uint16_t info = 0;
+            if (g >= 0 && g < total) {
+                if (sidx < 0) {
+                    sidx = owner_of(off, n, g);
+                    sbeg = off[sidx];
+                    send = off[sidx + 1];
+                }
+                while (g >= send) {
+                    sidx++;
+                    sbeg = off[sidx];
+                    send = off[sidx + 1];
+                    have = false;
+                }
+                int64_t i = g - sbeg;
+                int64_t npos = (send - sbeg) - q + 1;
+                if (i < npos) {
+                    if (have) {
+                        G = ((G << bits) | ch[idx + q - 1]) & gmask;
+                    } else {
+                        G = 0;
+                        for (int k = 0; k < q; k++) G = (G << bits) | ch[idx + k];
+                        G &= gmask;
+                    }
+                    have = true;
+                    h = table ? table[G] : mix64(G ^ salt);
+                } else {
+                    have = false;
+                }
+                if (idx >= H && idx < H + TP) {
+                    int32_t r = rr[sidx];
+                    bool interior = (i >= r) && (i <= npos - 1 - r);
+                    info = (uint16_t)((interior ? r : 0) | (i == 0 ? 0x8000 : 0));
+                    if (interior) lmax = max(lmax, 31 - __clz(r));
+                }
+            }
+            cur[idx] = h;
+            if (idx >= H && idx < H + TP) pinfo[idx - H] = info;
+        }
+        if (lmax > 0) atomicMax(&kmax_s, lmax);
+    }
+    __syncthreads();
+    const int NC = TP / AT_THREADS;
+    uint64_t hp[AT_OWN];
+    uint16_t inf[AT_OWN];
+    bool anc[AT_OWN];
+#pragma unroll
+    for (int c = 0; c < AT_OWN; c++) {
+        if (c < NC) {
+            int p = tid + AT_THREADS * c;
+            hp[c] = cur[H + p];
+            inf[c] = pinfo[p];
+        } else {
+            hp[c] = 0;
+            inf[c] = 0;
+        }
+        anc[c] = false;
+    }
+    const int kmax = kmax_s;
+    for (int k = 0; k <= kmax; k++) {
+        const int w = 1 << k;
+#pragma unroll
+        for (int c = 0; c < AT_OWN; c++) {
+            int r = inf[c] & 0x7FFF;
+            if (c < NC && r != 0 && (31 - __clz(r)) == k) {
+                int idx = H + tid + AT_THREADS * c;
+                uint64_t L = min(cur[idx - r], cur[idx - w]);
+                uint64_t R = min(cur[idx + 1], cur[idx + 1 + r - w]);
+                anc[c] = (hp[c] < L) && (hp[c] < R);
+            }
+        }
+        if (k == kmax) break;
+        uint64_t tmp[AT_RUN];
+#pragma unroll
+        for (int j = 0; j < AT_RUN; j++) {
+            int a = tid + AT_THREADS * j;
+            if (a < NR) {
+                uint64_t v = cur[a];
+                if (a + w < NR) v = min(v, cur[a + w]);
+                tmp[j] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < AT_RUN; j++) {
+            int a = tid + AT_THREADS * j;
+            if (a < NR) cur[a] = tmp[j];
+        }
+        __syncthreads();
+    }
+    // one bit per position: string start or anchor
+    const int lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+    for (int c = 0; c < AT_OWN; c++) {
+        if (c < NC) {
+            int64_t chunk = tile_start + (int64_t)AT_THREADS * c + 64 * wid;
+            int64_t g = chunk + lane;
+            bool flag = g < total && (((inf[c] & 0x8000) != 0) || anc[c]);
+            uint64_t mask = __ballot(flag);
+            if (lane == 0 && chunk < total) bitmap[chunk >> 6] = mask;
+        }
+    }
+}
+
+__global__ void k_word_popc(const uint64_t *bm, int64_t nw, uint32_t *cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < nw; i += stride) cnt[i] = (uint32_t)__popcll(bm[i]);
+}
+
+__global__ void k_anchor_scatter(const uint64_t *bm, int64_t nw, const uint32_t *pre,
+                                 int64_t *apos, int64_t total) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < nw; i += stride) {
+        uint64_t w = bm[i];
+        uint32_t rank = pre[i];
+        while (w) {
+            int b = __ffsll((unsigned long long)w) - 1;
+            apos[rank++] = i * 64 + b;
+            w &= w - 1;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) apos[pre[nw]] = total;
+}
+
+// Partition records between consecutive flagged positions: key f = M(Phi xor S) with
+// Phi the Karp-Rabin polynomial of the content over GF(2^61-1), length folded in as the
+// leading coefficient; payload (string id << 32 | start position).
+__global__ void k_records(const int64_t *__restrict__ apos, int64_t R,
+                          const int64_t *__restrict__ off, int32_t n,
+                          const uint8_t *__restrict__ chars, uint64_t B, uint64_t salt_f,
+                          uint64_t *key, uint64_t *val, uint32_t *len) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; k < R; k += stride) {
+        int64_t g0 = apos[k], g1 = apos[k + 1];
+        int32_t sidx = owner_of(off, n, g0);
+        int64_t L = g1 - g0;
+        uint64_t h = (uint64_t)L % P61;
+        for (int64_t g = g0; g < g1; g++) {
+            h = mulmod61(h, B) + (uint64_t)chars[g] + 1;
+            if (h >= P61) h -= P61;
+        }
+        key[k] = mix64(h ^ salt_f);
+        val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - off[sidx]);
+        if (len) len[k] = (uint32_t)L;
+    }
+}
+
+void RecBuf::reserve(int64_t need, hipStream_t s) {
+    if (need <= cap) return;
+    int64_t nc = std::max<int64_t>(need, cap + cap / 2);
+    uint64_t *k2 = (uint64_t *)dev_alloc((size_t)nc * 8);
+    uint64_t *v2 = (uint64_t *)dev_alloc((size_t)nc * 8);
+    uint32_t *l2 = with_len ? (uint32_t *)dev_alloc((size_t)nc * 4) : nullptr;
+    if (count > 0) {
+        MJ_HIP(hipMemcpyAsync(k2, key, (size_t)count * 8, hipMemcpyDeviceToDevice, s));
+        MJ_HIP(hipMemcpyAsync(v2, val, (size_t)count * 8, hipMemcpyDeviceToDevice, s));
+        if (with_len) MJ_HIP(hipMemcpyAsync(l2, len, (size_t)count * 4, hipMemcpyDeviceToDevice, s));
+        MJ_HIP(hipStreamSynchronize(s));
+    }
+    dev_free(key); dev_free(val); dev_free(len);
+    key = k2; val = v2; len = l2; cap = nc;
+}
+
+void RecBuf::release() {
+    dev_free(key); dev_free(val); dev_free(len);
+    key = val = nullptr; len = nullptr; cap = count = 0;
+}
+
+int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho, int32_t halo,
+                          RecBuf &out, Workspace &ws, hipStream_t s, uint64_t *host_scratch) {
+    if (d.total == 0) return 0;
+    int H = std::max<int32_t>(halo, 1);
+    if (H > AT_MAX_HALO)
+        throw Error(MJ_ECAPACITY, "radius " + std::to_string(H) + " exceeds the supported 1920");
+    int TP = ((AT_REGION_MAX - 2 * H) / AT_THREADS) * AT_THREADS;
+    if (TP < AT_THREADS) TP = AT_THREADS;
+    int64_t ntiles = (d.total + TP - 1) / TP;
+    int64_t nw = (d.total + 63) / 64;
+    uint64_t *bitmap = ws.get_n<uint64_t>(nw + 1);
+    size_t lds = (size_t)(TP + 2 * H) * 8 + (size_t)TP * 2 + (size_t)(TP + 2 * H + p.q + 16);
+    uint64_t seed = p.seed + (uint64_t)rho;
+    uint64_t salt = mix64(seed + GAMMA);
+    if (ntiles > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many tiles");
+    hipLaunchKernelGGL(k_anchor_tiles, dim3((unsigned)ntiles), dim3(AT_THREADS), lds, s, d.chars,
+                       d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, d.rr, TP, H, bitmap);
+    MJ_LAUNCH_CHECK();
+    uint32_t *cnt = ws.get_n<uint32_t>(nw + 1);
+    uint32_t *pre = ws.get_n<uint32_t>(nw + 1);
+    hipLaunchKernelGGL(k_word_popc, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s, bitmap, nw, cnt);
+    MJ_LAUNCH_CHECK();
+    exclusive_scan_u32(cnt, pre, nw, ws, s);
+    int64_t R = (int64_t)read_back<uint32_t>(pre + nw, s, host_scratch);
+    int64_t base = out.count;
+    out.reserve(base + R + 1, s);
+    int64_t *apos = ws.get_n<int64_t>(R + 1);
+    hipLaunchKernelGGL(k_anchor_scatter, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s, bitmap,
+                       nw, pre, apos, d.total);
+    MJ_LAUNCH_CHECK();
+    uint64_t B = 2 + mix64(p.seed ^ GAMMA_B) % (P61 - 3);
+    uint64_t salt_f = mix64(p.seed + GAMMA);
+    if (R > 0) {
+        hipLaunchKernelGGL(k_records, dim3(grid_for(R, 256, 65535)), dim3(256), 0, s, apos, R,
+                           d.offsets, d.n, d.chars, B, salt_f, out.key + base, out.val + base,
+                           out.with_len ? out.len + base : nullptr);
+        MJ_LAUNCH_CHECK();
+    }
+    out.count = base + R;
+    return R;
+}
+
+}  // namespace mj

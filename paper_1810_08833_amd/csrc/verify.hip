@@ -1,0 +1,425 @@
+// Verification (Alg. 3; Sec. 3): decide ED(x, y) <= K for every candidate pair.
+//
+// Bit-parallel path (one pair per lane).  The longer string is the pattern (rows), the
+// shorter the text (columns).  Column j keeps the vertical deltas of a window of NW
+// 32-bit words of rows; the window starts at word floor((j-1)/32) - ceil(K/32), so it
+// covers every row i with |i - j| <= K when NW >= 2 ceil(K/32) + 1, and it moves by one
+// word every 32 columns for every lane at once.  Each column applies Myers' bit-vector
+// recurrence for global edit distance (hin = +1 at the top) to the whole window as one
+// multi-word integer.  Rows above the window are treated as one more than their left
+// neighbour, a word entering at the bottom as one more than the row above it, and rows
+// above the first pattern row as never-matching rows: every such value is at least the
+// true distance, and every cell on an optimal path of cost <= K lies inside the window,
+// so the computed value at (m, n) is <= K exactly when ED <= K.  The same holds for the
+// early exit: when every window value exceeds K the pair is rejected.
+//
+// Pattern and text symbols come from bit planes (plane p holds bit p of each symbol),
+// so the match mask of 32 pattern rows against one text symbol is the AND over planes
+// of XNOR(plane word, text bit).
+//
+// Wide path (K above the register-resident window): one wavefront per pair computes the
+// banded dynamic program row by row, saturated at K+1; the left-to-right dependency of
+// a row is resolved with a wavefront prefix-min scan.
+#include <string.h>
+
+#include <algorithm>
+
+#include "mj_common.h"
+
+namespace mj {
+
+static unsigned grid_for(int64_t n, int block, unsigned cap = 65535u) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    return (unsigned)std::min<int64_t>(g, cap);
+}
+
+int verify_planes(int bits) {
+    if (bits <= 2) return 2;
+    if (bits <= 4) return 4;
+    if (bits <= 6) return 6;
+    return 8;
+}
+
+struct VSet {
+    int32_t n;
+    const uint8_t *chars;
+    const int64_t *off;
+    const int32_t *len;
+    const int32_t *kk;
+    const uint32_t *planes;
+    int64_t pw;
+};
+
+__device__ __forceinline__ uint32_t load_word(const uint32_t *plane, int64_t bitpos) {
+    // 32 symbols' bits starting at global bit position bitpos (>= 0)
+    int64_t w = bitpos >> 5;
+    uint32_t sh = (uint32_t)(bitpos & 31);
+    uint32_t lo = plane[w], hi = plane[w + 1];
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+constexpr int BP_MAX_C = 8;  // ceil(K/32) handled by the bit-parallel kernels (K <= 256)
+
+template <int NW, int NP>
+__global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ pairs,
+                                                   const int64_t *__restrict__ sel, int64_t n,
+                                                   VSet A, VSet B, int kmode,
+                                                   uint8_t *__restrict__ flags,
+                                                   unsigned long long *cells) {
+    int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t my_cells = 0;
+    if (it < n) {
+        int64_t pi = sel ? sel[it] : it;
+        uint64_t pr = pairs[pi];
+        int32_t ia = (int32_t)(pr >> 32), ib = (int32_t)(uint32_t)pr;
+        int32_t ma = A.len[ia], mb = B.len[ib];
+        int32_t K = kmode == 0 ? max(A.kk[ia], B.kk[ib]) : A.kk[ia];
+        // pattern X (rows) = longer string, text Y (columns) = shorter
+        bool a_is_x = ma >= mb;
+        const uint32_t *PX = a_is_x ? A.planes : B.planes;
+        const uint32_t *PY = a_is_x ? B.planes : A.planes;
+        int64_t pwx = a_is_x ? A.pw : B.pw, pwy = a_is_x ? B.pw : A.pw;
+        int64_t offx = a_is_x ? A.off[ia] : B.off[ib];
+        int64_t offy = a_is_x ? B.off[ib] : A.off[ia];
+        int32_t mp = a_is_x ? ma : mb, nt = a_is_x ? mb : ma;
+        uint8_t result;
+        const int c = (K + 31) >> 5;
+        if (mp - nt > K) {
+            result = 0;
+        } else if (nt == 0) {
+            result = mp <= K;
+        } else if (2 * c + 1 > NW) {
+            result = 2;  // not handled by this instance (host bins pairs so this never happens)
+        } else {
+            uint32_t Pv[NW], Mv[NW], V[NW];
+            uint32_t PL[NP][NW];
+            int wlo = -c;
+#pragma unroll
+            for (int s = 0; s < NW; s++) {
+                int w = wlo + s;
+                bool real = w >= 0;
+                Pv[s] = real ? ~0u : 0u;
+                Mv[s] = real ? 0u : ~0u;
+                V[s] = real ? ~0u : 0u;
+#pragma unroll
+                for (int p = 0; p < NP; p++)
+                    PL[p][s] = real ? load_word(PX + p * pwx, offx + 32 * (int64_t)w) : 0u;
+            }
+            int S = c >= 1 ? 32 * (c - 1) : 32;  // value of the bottom row of word 0
+            bool rejected = false;
+            int jb = 0;
+            for (; jb < nt; jb += 32) {
+                if (jb > 0) {
+                    // early exit: a lower bound of every window value, word by word
+                    int Sw = S, lb = S - __popc(Pv[0]);
+#pragma unroll
+                    for (int s = 1; s < NW; s++) {
+                        Sw += __popc(Pv[s]) - __popc(Mv[s]);
+                        lb = min(lb, Sw - __popc(Pv[s]));
+                    }
+                    if (lb > K) {
+                        rejected = true;
+                        break;
+                    }
+                    // move the window down one word
+                    S += __popc(Pv[1]) - __popc(Mv[1]);
+#pragma unroll
+                    for (int s = 0; s + 1 < NW; s++) {
+                        Pv[s] = Pv[s + 1];
+                        Mv[s] = Mv[s + 1];
+                        V[s] = V[s + 1];
+#pragma unroll
+                        for (int p = 0; p < NP; p++) PL[p][s] = PL[p][s + 1];
+                    }
+                    wlo++;
+                    int w = wlo + NW - 1;
+                    Pv[NW - 1] = ~0u;
+                    Mv[NW - 1] = 0u;
+                    V[NW - 1] = ~0u;
+#pragma unroll
+                    for (int p = 0; p < NP; p++)
+                        PL[p][NW - 1] = load_word(PX + p * pwx, offx + 32 * (int64_t)w);
+                }
+                uint32_t TY[NP];
+#pragma unroll
+                for (int p = 0; p < NP; p++) TY[p] = load_word(PY + p * pwy, offy + jb);
+                const int cols = min(32, nt - jb);
+                for (int t = 0; t < cols; t++) {
+                    uint32_t nt_[NP];
+#pragma unroll
+                    for (int p = 0; p < NP; p++)
+                        nt_[p] = ~(uint32_t)__builtin_amdgcn_sbfe((int)TY[p], (unsigned)t, 1u);
+                    uint32_t carry = 0, phc = 1, mhc = 0;
+                    int dS = 0;
+#pragma unroll
+                    for (int s = 0; s < NW; s++) {
+                        uint32_t eq = V[s];
+#pragma unroll
+                        for (int p = 0; p < NP; p++) eq &= PL[p][s] ^ nt_[p];
+                        uint32_t pv = Pv[s], mv = Mv[s];
+                        uint32_t xv = eq | mv;
+                        uint64_t sum = (uint64_t)(eq & pv) + pv + carry;
+                        carry = (uint32_t)(sum >> 32);
+                        uint32_t xh = ((uint32_t)sum ^ pv) | eq;
+                        uint32_t ph = mv | ~(xh | pv);
+                        uint32_t mh = pv & xh;
+                        if (s == 0) dS = (int)(ph >> 31) - (int)(mh >> 31);
+                        uint32_t phs = (ph << 1) | phc;
+                        phc = ph >> 31;
+                        uint32_t mhs = (mh << 1) | mhc;
+                        mhc = mh >> 31;
+                        Pv[s] = mhs | ~(xv | phs);
+                        Mv[s] = phs & xv;
+                    }
+                    S += dS;
+                }
+            }
+            my_cells = (uint64_t)min(jb, nt) * (uint64_t)(2 * K + 1);
+            if (rejected) {
+                result = 0;
+            } else {
+                // value at row mp, relative to the reference row 32*wlo + 32
+                int rel = mp - (32 * wlo + 32);
+                int val = S;
+                if (rel >= 0) {
+#pragma unroll
+                    for (int s = 1; s < NW; s++) {
+                        int cnt = min(32, max(0, 32 + rel - 32 * s));
+                        uint32_t mk = cnt >= 32 ? ~0u : ((1u << cnt) - 1u);
+                        val += __popc(Pv[s] & mk) - __popc(Mv[s] & mk);
+                    }
+                } else {
+                    uint32_t mk = ~0u << (32 + rel);
+                    val -= __popc(Pv[0] & mk) - __popc(Mv[0] & mk);
+                }
+                result = val <= K;
+            }
+        }
+        flags[pi] = result;
+    }
+    // wave-reduced cell counter
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint32_t lo = (uint32_t)my_cells, hi = (uint32_t)(my_cells >> 32);
+        lo = __shfl_down(lo, d, 64);
+        hi = __shfl_down(hi, d, 64);
+        my_cells += ((uint64_t)hi << 32) | lo;
+    }
+    if ((threadIdx.x & 63) == 0 && my_cells) atomicAdd(cells, (unsigned long long)my_cells);
+}
+
+// ---------------------------------------------------------------- wide path
+constexpr int DP_MAX_NT = 64;  // cells per lane: band up to 64 * 64 = 4096 (K <= 2047)
+
+__global__ __launch_bounds__(64) void k_verify_dp(const uint64_t *__restrict__ pairs,
+                                                  const int64_t *__restrict__ sel, int64_t n,
+                                                  VSet A, VSet B, int kmode,
+                                                  uint8_t *__restrict__ flags,
+                                                  unsigned long long *cells) {
+    const int lane = threadIdx.x;
+    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+        int64_t pi = sel ? sel[it] : it;
+        uint64_t pr = pairs[pi];
+        int32_t ia = (int32_t)(pr >> 32), ib = (int32_t)(uint32_t)pr;
+        int32_t ma = A.len[ia], mb = B.len[ib];
+        int32_t K = kmode == 0 ? max(A.kk[ia], B.kk[ib]) : A.kk[ia];
+        // rows over the shorter string x, columns over the longer y
+        bool a_short = ma <= mb;
+        const uint8_t *X = a_short ? A.chars + A.off[ia] : B.chars + B.off[ib];
+        const uint8_t *Y = a_short ? B.chars + B.off[ib] : A.chars + A.off[ia];
+        int32_t mx = a_short ? ma : mb, ny = a_short ? mb : ma;
+        uint8_t result = 0;
+        const int W = 2 * K + 1;
+        const int NT = (W + 63) / 64;
+        const int CAP = K + 1;
+        uint64_t rows_done = 0;
+        if (ny - mx > K) {
+            result = 0;
+        } else if (NT > DP_MAX_NT) {
+            result = 2;
+        } else {
+            int prev[DP_MAX_NT], cur[DP_MAX_NT];
+            for (int t = 0; t < DP_MAX_NT; t++) {
+                int d = lane * NT + t;
+                int j = d - K;
+                prev[t] = (t < NT && d < W && j >= 0 && j <= ny) ? min(j, CAP) : CAP;
+            }
+            bool ok = true;
+            for (int i = 1; i <= mx && ok; i++) {
+                int xc = X[i - 1];
+                int up_next = __shfl_down(prev[0], 1, 64);  // first cell of the next lane
+                if (lane == 63) up_next = CAP;
+                int run = 0x3FFFFFFF;  // lane-local prefix min of U[d] - d
+                int pm[DP_MAX_NT];
+                for (int t = 0; t < NT; t++) {
+                    int d = lane * NT + t;
+                    int j = i - K + d;
+                    int U;
+                    if (d >= W || j < 0 || j > ny) {
+                        U = 0x3FFFFFFF;
+                    } else if (j == 0) {
+                        U = i;
+                    } else {
+                        int up = (t + 1 < NT) ? prev[t + 1] : up_next;
+                        if (d + 1 >= W) up = CAP;
+                        int diag = prev[t] + (xc != Y[j - 1] ? 1 : 0);
+                        U = min(up + 1, diag);
+                    }
+                    run = min(run, U - d);
+                    pm[t] = run;
+                }
+                // exclusive prefix min of lane totals
+                int ex = run;
+                for (int dd = 1; dd < 64; dd <<= 1) {
+                    int o = __shfl_up(ex, dd, 64);
+                    if (lane >= dd) ex = min(ex, o);
+                }
+                int excl = __shfl_up(ex, 1, 64);
+                if (lane == 0) excl = 0x3FFFFFFF;
+                int rmin = CAP;
+                for (int t = 0; t < NT; t++) {
+                    int d = lane * NT + t;
+                    int j = i - K + d;
+                    int v = min(pm[t], excl);
+                    v = (v >= 0x3FFFFFFF - 4 * W) ? CAP : v + d;
+                    v = min(v, CAP);
+                    if (d >= W || j < 0 || j > ny) v = CAP;
+                    cur[t] = v;
+                    rmin = min(rmin, v);
+                }
+                for (int dd = 32; dd >= 1; dd >>= 1) rmin = min(rmin, __shfl_xor(rmin, dd, 64));
+                for (int t = 0; t < NT; t++) prev[t] = cur[t];
+                rows_done++;
+                if (rmin > K) ok = false;
+            }
+            if (ok) {
+                int dfin = ny - mx + K;
+                int owner = dfin / NT, tt = dfin % NT;
+                int v = CAP;
+                for (int t = 0; t < NT; t++)
+                    if (t == tt) v = prev[t];
+                v = __shfl(v, owner, 64);
+                result = v <= K;
+            }
+        }
+        if (lane == 0) {
+            flags[pi] = result;
+            atomicAdd(cells, (unsigned long long)(rows_done * (uint64_t)W));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+// bin of a pair: c = ceil(K/32) for c <= BP_MAX_C (bit-parallel), else the wide path
+// Pairs naming a string id outside the collections go to the last bin, which is never
+// launched; the host reports them as invalid arguments.
+__global__ void k_bin_pairs(const uint64_t *pairs, int64_t n, VSet A, VSet B, int kmode,
+                            uint8_t *bin, uint32_t *counts) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) {
+        uint64_t pr = pairs[i];
+        uint32_t ua = (uint32_t)(pr >> 32), ub = (uint32_t)pr;
+        if (ua >= (uint32_t)A.n || ub >= (uint32_t)B.n) {
+            bin[i] = (uint8_t)(BP_MAX_C + 2);
+            atomicAdd(&counts[BP_MAX_C + 2], 1u);
+            continue;
+        }
+        int32_t ia = (int32_t)ua, ib = (int32_t)ub;
+        int32_t K = kmode == 0 ? max(A.kk[ia], B.kk[ib]) : A.kk[ia];
+        int c = (K + 31) >> 5;
+        int b = c <= BP_MAX_C ? c : BP_MAX_C + 1;
+        bin[i] = (uint8_t)b;
+        atomicAdd(&counts[b], 1u);
+    }
+}
+
+__global__ void k_bin_scatter(const uint8_t *bin, int64_t n, const uint32_t *boff, uint32_t *fill,
+                              int64_t *sel) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) {
+        int b = bin[i];
+        uint32_t p = boff[b] + atomicAdd(&fill[b], 1u);
+        sel[p] = i;
+    }
+}
+
+using BpKernel = void (*)(const uint64_t *, const int64_t *, int64_t, VSet, VSet, int, uint8_t *,
+                          unsigned long long *);
+
+template <int NP>
+static BpKernel bp_kernel_for(int c) {
+    switch (c) {
+        case 0: return k_verify_bp<1, NP>;
+        case 1: return k_verify_bp<3, NP>;
+        case 2: return k_verify_bp<5, NP>;
+        case 3: return k_verify_bp<7, NP>;
+        case 4: return k_verify_bp<9, NP>;
+        case 5: return k_verify_bp<11, NP>;
+        case 6: return k_verify_bp<13, NP>;
+        case 7: return k_verify_bp<15, NP>;
+        default: return k_verify_bp<17, NP>;
+    }
+}
+
+static BpKernel bp_kernel(int c, int np) {
+    switch (np) {
+        case 2: return bp_kernel_for<2>(c);
+        case 4: return bp_kernel_for<4>(c);
+        case 6: return bp_kernel_for<6>(c);
+        default: return bp_kernel_for<8>(c);
+    }
+}
+
+static VSet vset(const DevStrings &d) {
+    return VSet{d.n, d.chars, d.offsets, d.len, d.kk, d.planes, d.plane_words};
+}
+
+int64_t verify_pairs(const uint64_t *pairs, int64_t n, const DevStrings &A, const DevStrings &B,
+                     int kmode, uint8_t *flags, Workspace &ws, hipStream_t s,
+                     uint64_t *host_scratch) {
+    if (n <= 0) return 0;
+    if (A.planes == nullptr || B.planes == nullptr) throw Error(MJ_EINVAL, "strings not packed");
+    int np = verify_planes(std::max(A.bits, B.bits));
+    VSet va = vset(A), vb = vset(B);
+    unsigned long long *cells = (unsigned long long *)ws.get_n<uint64_t>(2);
+    fill_u64((uint64_t *)cells, 0, 1, s);
+    const int NB = BP_MAX_C + 3;  // bit-parallel bins 0..8, wide path, invalid ids
+    uint8_t *bin = ws.get_n<uint8_t>(n);
+    uint32_t *counts = ws.get_n<uint32_t>(NB + 1);
+    uint32_t *boff = ws.get_n<uint32_t>(NB + 1);
+    uint32_t *fillc = ws.get_n<uint32_t>(NB + 1);
+    int64_t *sel = ws.get_n<int64_t>(n);
+    fill_u32(counts, 0, NB, s);
+    fill_u32(fillc, 0, NB, s);
+    hipLaunchKernelGGL(k_bin_pairs, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, pairs, n, va, vb,
+                       kmode, bin, counts);
+    MJ_LAUNCH_CHECK();
+    exclusive_scan_u32(counts, boff, NB, ws, s);
+    MJ_HIP(hipMemcpyAsync(host_scratch, boff, sizeof(uint32_t) * (NB + 1), hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipStreamSynchronize(s));
+    uint32_t hoff[NB + 1];
+    memcpy(hoff, host_scratch, sizeof(hoff));
+    if (hoff[NB] != hoff[NB - 1]) throw Error(MJ_EINVAL, "pair names a string id out of range");
+    hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, bin, n, boff,
+                       fillc, sel);
+    MJ_LAUNCH_CHECK();
+    for (int b = 0; b < NB - 1; b++) {
+        int64_t cnt = (int64_t)hoff[b + 1] - hoff[b];
+        if (cnt <= 0) continue;
+        const int64_t *bsel = sel + hoff[b];
+        if (b <= BP_MAX_C) {
+            BpKernel kfn = bp_kernel(b, np);
+            hipLaunchKernelGGL(kfn, dim3(grid_for(cnt, 256, 0x7FFFFFFF)), dim3(256), 0, s, pairs, bsel,
+                               cnt, va, vb, kmode, flags, cells);
+        } else {
+            hipLaunchKernelGGL(k_verify_dp, dim3(grid_for(cnt, 1, 1u << 20)), dim3(64), 0, s, pairs,
+                               bsel, cnt, va, vb, kmode, flags, cells);
+        }
+        MJ_LAUNCH_CHECK();
+    }
+    return (int64_t)read_back<uint64_t>((const uint64_t *)cells, s, host_scratch);
+}
+
+}  // namespace mj

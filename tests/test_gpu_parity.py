@@ -1,0 +1,255 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle, element by
+element on the same seeded inputs.  Everything here is integer work, so the bar is
+bit-exact equality."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1810_08833_amd import datagen as dg
+from tests import worked_example as wex
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mj():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1810_08833_amd as mj
+    mj.load_library()
+    return mj
+
+
+def dev(mj, S):
+    return mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
+
+
+def sort_records(keys, sids, poss, lens):
+    order = np.lexsort((lens, poss, sids, keys))
+    return keys[order], sids[order], poss[order], lens[order]
+
+
+def assert_records_equal(got, want):
+    a = sort_records(got["key"], got["sid"], got["pos"], got["len"])
+    b = sort_records(want["key"], want["sid"], want["pos"], want["len"])
+    assert len(a[0]) == len(b[0])
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def mixed_collection(seed):
+    """Ragged lengths: empty strings, strings shorter than q, a homopolymer run,
+    duplicates, and clustered copies."""
+    rng = np.random.default_rng(seed)
+    base = dg.dna_small(seed=seed, n_clusters=30, copies=6)
+    extra = [np.zeros(0, np.uint8), np.array([1, 2], np.uint8), np.zeros(700, np.uint8),
+             np.full(64, 3, np.uint8), rng.integers(0, 4, 3).astype(np.uint8)]
+    strs = [base.get(i) for i in range(base.n)] + extra + [base.get(0), base.get(5)]
+    order = rng.permutation(len(strs))
+    return dg.from_list([strs[i] for i in order], 4)
+
+
+# ---------------------------------------------------------------- worked example
+def test_worked_example_end_to_end(mj):
+    import torch
+    say("worked example")
+    g, table, strings, chars, offsets = wex.load()
+    ds = mj.DeviceStrings.from_host(chars, offsets, 4)
+    tab = torch.from_numpy(table.view(np.int64)).cuda()
+    p = mj.Params(q=3, k=4, t_fixed=3, pi_table=tab)
+    rec = mj.partition(ds, p)
+    parts = [[] for _ in range(5)]
+    for r in sorted(rec.tolist(), key=lambda r: (r[1], r[2])):
+        parts[r[1]].append(g["strings"][r[1]][r[2]:r[2] + r[3]])
+    assert parts == g["partitions"]
+    cand, _ = mj.candidates(ds, p)
+    assert wex.pairs_1based(cand) == g["candidates_1based"]
+    out, st = mj.join(ds, p)
+    assert wex.pairs_1based(out) == g["output_1based"]
+    assert st["candidates"] == 4 and st["output"] == 3
+
+
+# ---------------------------------------------------------------- stage parity
+CASES = {
+    "dna_mixed_T_from_K": dict(make=lambda: mixed_collection(3), q=4, k=60, t_div=1),
+    "dna_mixed_t_div3": dict(make=lambda: mixed_collection(4), q=4, k=60, t_div=3),
+    "dna_reps3": dict(make=lambda: mixed_collection(5), q=5, k=40, t_div=4, reps=3),
+    "dna_small_fixedT": dict(make=lambda: dg.dna_small(seed=8, n_clusters=20, copies=5), q=4,
+                             k=70, t_fixed=7),
+    "protein_per_string_K": dict(make=lambda: dg.protein(seed=6, n=1500), q=4, k_frac=(8, 100),
+                                 t_div=1),
+    "text_q6": dict(make=lambda: dg.text(seed=7, n=1500), q=6, k=120, t_div=2),
+}
+
+
+def run_case(mj, name):
+    import torch
+    c = CASES[name]
+    S = c["make"]()
+    kw = dict(t_div=c.get("t_div", 1), t_fixed=c.get("t_fixed", 0), reps=c.get("reps", 1))
+    if "k_frac" in c:
+        kq = dg.k_fraction(S.lengths(), *c["k_frac"])
+        op = oracle.make_params(c["q"], S.sigma, k_per_string=kq, **kw)
+        gp = mj.Params(q=c["q"], k_per_string=torch.from_numpy(kq).cuda(), **kw)
+    else:
+        op = oracle.make_params(c["q"], S.sigma, k=c["k"], **kw)
+        gp = mj.Params(q=c["q"], k=c["k"], **kw)
+    return S, op, gp
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_partition_records_identical(mj, name):
+    say("partition", name)
+    S, op, gp = run_case(mj, name)
+    got = mj.partition(dev(mj, S), gp)
+    want = oracle.partition_all(S.chars, S.offsets, op)
+    assert len(got) > S.n  # several tiles' worth of partitions
+    assert_records_equal(got, want)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_candidates_and_output_identical(mj, name):
+    say("join", name)
+    S, op, gp = run_case(mj, name)
+    cand_w, out_w, st_w = oracle.join(S.chars, S.offsets, op)
+    ds = dev(mj, S)
+    cand_g, st_c = mj.candidates(ds, gp)
+    assert np.array_equal(cand_g, cand_w)
+    out_g, st = mj.join(ds, gp)
+    assert np.array_equal(out_g, out_w)
+    assert st["candidates"] == len(cand_w) and st["output"] == len(out_w)
+
+
+def test_empty_and_degenerate_collections(mj):
+    say("degenerate collections")
+    for strs in ([], [np.zeros(0, np.uint8)], [np.zeros(0, np.uint8)] * 3,
+                 [np.array([1], np.uint8)], [np.array([1, 2, 3], np.uint8)] * 2):
+        S = dg.from_list(strs, 4)
+        ds = dev(mj, S)
+        p = mj.Params(q=4, k=2, t_div=1)
+        want_c, want_o, _ = oracle.join(S.chars, S.offsets, oracle.make_params(4, 4, k=2, t_div=1))
+        got_o, st = mj.join(ds, p)
+        assert np.array_equal(got_o, want_o)
+        assert len(mj.partition(ds, p)) == len(
+            oracle.partition_all(S.chars, S.offsets, oracle.make_params(4, 4, k=2, t_div=1)))
+
+
+# ---------------------------------------------------------------- verification
+def near_threshold_pairs(rng, K, count, sigma=4):
+    strs, pairs = [], []
+    for t in range(count):
+        L = int(rng.integers(max(1, K // 2), 4 * K + 40))
+        x = rng.integers(0, sigma, L).astype(np.uint8)
+        rate = min(0.9, rng.uniform(0.6, 1.4) * (K + 1) / L)
+        y = dg.mutate(rng, x, rate, sigma)
+        a, b = len(strs), len(strs) + 1
+        strs += [x, y]
+        pairs.append((a << 32) | b if t % 2 == 0 else (b << 32) | a)
+    # a few degenerate ones: empty strings and length gaps at the limit
+    e = len(strs)
+    strs += [np.zeros(0, np.uint8), rng.integers(0, sigma, K).astype(np.uint8),
+             rng.integers(0, sigma, K + 1).astype(np.uint8)]
+    pairs += [(e << 32) | (e + 1), (e << 32) | (e + 2), ((e + 1) << 32) | (e + 2)]
+    return dg.from_list(strs, sigma), np.array(pairs, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("K", [0, 1, 7, 31, 32, 33, 60, 150, 255, 256, 257, 400])
+def test_verify_matches_banded_oracle(mj, K):
+    say("verify K=%d" % K)
+    rng = np.random.default_rng(1000 + K)
+    S, pairs = near_threshold_pairs(rng, K, 120 if K < 300 else 40)
+    got = mj.verify(dev(mj, S), mj.Params(q=4, k=K, t_div=1), pairs)
+    want = oracle.verify_list(S.chars, S.offsets, oracle.make_params(4, 4, k=K), pairs)
+    assert np.array_equal(got, want)
+    assert 0 < want.sum() < len(want)
+
+
+def test_verify_per_pair_thresholds_across_bins(mj):
+    import torch
+    say("verify mixed K bins")
+    rng = np.random.default_rng(77)
+    strs, pairs, ks = [], [], []
+    for t in range(300):
+        K = int(rng.choice([3, 20, 45, 90, 130, 200, 250, 300, 520]))
+        L = int(rng.integers(K + 5, 5 * K + 50))
+        x = rng.integers(0, 25, L).astype(np.uint8)
+        y = dg.mutate(rng, x, min(0.9, rng.uniform(0.6, 1.4) * (K + 1) / L), 25)
+        a = len(strs)
+        strs += [x, y]
+        ks += [K, int(rng.integers(0, K + 1))]
+        pairs.append((a << 32) | (a + 1))
+    S = dg.from_list(strs, 25)
+    kq = np.array(ks, dtype=np.int32)
+    pairs = np.array(pairs, dtype=np.uint64)
+    got = mj.verify(dev(mj, S), mj.Params(q=3, k_per_string=torch.from_numpy(kq).cuda()), pairs)
+    want = oracle.verify_list(S.chars, S.offsets, oracle.make_params(3, 25, k_per_string=kq), pairs)
+    assert np.array_equal(got, want)
+
+
+# ---------------------------------------------------------------- search
+def test_search_matches_oracle(mj):
+    import torch
+    say("search")
+    S = dg.dna_small(seed=21, n_clusters=25, copies=6)
+    ids = np.arange(S.n)
+    I, Q = S.subset(ids[ids % 3 != 0]), S.subset(ids[ids % 3 == 0])
+    kq = dg.k_fraction(Q.lengths(), 1, 10)
+    ki = dg.k_fraction(I.lengths(), 1, 10)
+    index = mj.Index(dev(mj, I), mj.Params(q=4, k_per_string=torch.from_numpy(ki).cuda(), t_div=1))
+    got, st = index.search(dev(mj, Q), k_per_query=torch.from_numpy(kq).cuda())
+    _, want = oracle.search(I.chars, I.offsets, oracle.make_params(4, 4, k_per_string=ki, t_div=1),
+                            Q.chars, Q.offsets, oracle.make_params(4, 4, k_per_string=kq, t_div=1))
+    assert len(want) > 0
+    assert np.array_equal(got, want)
+    # a second batch on the same resident index gives the same answer
+    got2, _ = index.search(dev(mj, Q), k_per_query=torch.from_numpy(kq).cuda())
+    assert np.array_equal(got2, want)
+    index.close()
+
+
+# ---------------------------------------------------------------- full workloads
+def test_dna_small_workload_identical(mj):
+    say("dna_small full (1,000 strings, K=60)")
+    S = dg.dna_small()
+    op = oracle.make_params(4, 4, k=60, t_div=1)
+    cand_w, out_w, _ = oracle.join(S.chars, S.offsets, op)
+    out_g, st = mj.join(dev(mj, S), mj.Params(q=4, k=60, t_div=1))
+    assert st["candidates"] == len(cand_w)
+    assert np.array_equal(out_g, out_w)
+
+
+def test_dna_long_workload_sampled(mj):
+    """The 50,000-string long-read workload in the configuration the benchmark times:
+    candidates compared in full, the verification on a sample of candidates, records
+    on a sample of strings."""
+    say("dna_long full size (50,000 strings, K=150, t_div=2)")
+    S = dg.dna_long()
+    op = oracle.make_params(5, 4, k=150, t_div=2)
+    ds = dev(mj, S)
+    gp = mj.Params(q=5, k=150, t_div=2)
+    cand_w, _, _ = oracle.join(S.chars, S.offsets, op, verify=False)
+    cand_g, _ = mj.candidates(ds, gp)
+    assert np.array_equal(cand_g, cand_w)
+    out_g, st = mj.join(ds, gp)
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(len(cand_w), size=min(1500, len(cand_w)), replace=False))
+    flags = oracle.verify_list(S.chars, S.offsets, op, cand_w[sample])
+    in_out = np.isin(cand_w[sample], out_g)
+    assert np.array_equal(in_out, flags)
+    assert np.all(np.isin(out_g, cand_w))
+    ids = np.sort(rng.choice(S.n, size=300, replace=False))
+    sub = S.subset(ids)
+    want = oracle.partition_all(sub.chars, sub.offsets, op)
+    got = mj.partition(ds, gp)
+    sel = np.isin(got["sid"], ids)
+    got = got[sel]
+    got["sid"] = np.searchsorted(ids, got["sid"])
+    assert_records_equal(got, want)
