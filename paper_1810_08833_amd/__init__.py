@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libminjoin.so")
 
 MJ_OK, MJ_EINVAL, MJ_ENOMEM, MJ_EDEVICE, MJ_ECAPACITY = 0, 1, 2, 3, 4
 STATUS_NAMES = {0: "MJ_OK", 1: "MJ_EINVAL", 2: "MJ_ENOMEM", 3: "MJ_EDEVICE", 4: "MJ_ECAPACITY"}
+KERNELS = ["anchors", "records", "emit", "verify"]
 STAGES = ["setup", "partition", "sort", "group_filter", "dedup", "verify", "output", "unused"]
 
 
@@ -40,12 +41,15 @@ class MjStats(ctypes.Structure):
     _fields_ = [("records", ctypes.c_int64), ("groups", ctypes.c_int64),
                 ("pair_tests", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("output", ctypes.c_int64), ("band_cells", ctypes.c_int64),
-                ("stage_ms", ctypes.c_float * 8)]
+                ("stage_ms", ctypes.c_float * 8), ("kernel_ms", ctypes.c_float * 4),
+                ("kernel_launches", ctypes.c_int32 * 4), ("positions", ctypes.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k in ("records", "groups", "pair_tests", "candidates",
-                                           "output", "band_cells")}
+                                           "output", "band_cells", "positions")}
         d["stage_ms"] = {STAGES[i]: float(self.stage_ms[i]) for i in range(7)}
+        d["kernel_ms"] = {KERNELS[i]: float(self.kernel_ms[i]) for i in range(4)}
+        d["kernel_launches"] = {KERNELS[i]: int(self.kernel_launches[i]) for i in range(4)}
         return d
 
 

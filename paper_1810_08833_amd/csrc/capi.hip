@@ -14,6 +14,7 @@ struct mj_ctx {
     Workspace ws;
     uint64_t *pinned = nullptr;  // host scratch for read-backs (4 KiB)
     hipEvent_t ev[9] = {};
+    KTimer kt;
 };
 
 struct mj_pairs {
@@ -77,6 +78,7 @@ extern "C" mj_status mj_ctx_create(int device, mj_ctx **out) {
         return fail(MJ_ENOMEM, "pinned host allocation failed");
     }
     for (auto &e : c->ev) MJ_HIP(hipEventCreate(&e));
+    c->kt.create();
     *out = c;
     return MJ_OK;
     MJ_API_END
@@ -87,6 +89,7 @@ extern "C" void mj_ctx_destroy(mj_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    ctx->kt.destroy();
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
 }
@@ -106,6 +109,7 @@ static void check_params(const mj_params *p, int sigma, bool need_k) {
     if (p->t_fixed <= 0 && p->t_div < 1) throw Error(MJ_EINVAL, "t_div must be >= 1");
     if (p->reps < 0 || p->reps > 64) throw Error(MJ_EINVAL, "reps must be in 0..64");
     if (need_k) {
+        if (p->k > 2047) throw Error(MJ_ECAPACITY, "threshold K exceeds the verifier's band limit (K <= 2047)");
         if (p->k < -1) throw Error(MJ_EINVAL, "k must be >= 0 or -1");
         if (p->k == -1 && !p->k_per_string) throw Error(MJ_EINVAL, "k == -1 needs k_per_string");
         if (p->k > 0x3FFFFFFF) throw Error(MJ_EINVAL, "k too large");
@@ -195,7 +199,10 @@ struct StageTimer {
     mj_ctx *ctx;
     hipStream_t s;
     int next = 0;
-    StageTimer(mj_ctx *c, hipStream_t st) : ctx(c), s(st) { mark(); }
+    StageTimer(mj_ctx *c, hipStream_t st) : ctx(c), s(st) {
+        ctx->kt.reset();
+        mark();
+    }
     void mark() {
         if (next < 9) MJ_HIP(hipEventRecord(ctx->ev[next++], s));
     }
@@ -207,6 +214,7 @@ struct StageTimer {
             if (i + 1 < next) MJ_HIP(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
             st->stage_ms[i] = ms;
         }
+        ctx->kt.collect(st->kernel_ms, st->kernel_launches);
     }
 };
 
@@ -229,7 +237,8 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     tm.mark();  // 0 setup
     RecBuf rb;
     struct RbFree { RecBuf &r; ~RbFree() { r.release(); } } rbf{rb};
-    for (int rho = 0; rho < pp.reps; rho++) partition_records(d, pp, rho, halo, rb, ws, s, ctx->pinned);
+    for (int rho = 0; rho < pp.reps; rho++)
+        partition_records(d, pp, rho, halo, rb, ws, s, ctx->pinned, &ctx->kt);
     tm.mark();  // 1 partition: anchors and records
     int64_t R = rb.count;
     if (R > 1) {
@@ -242,7 +251,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
         throw Error(MJ_ECAPACITY, "record-pair tests exceed 2^31 (" + std::to_string(g.tests) + ")");
     int64_t cap = (int64_t)g.tests;
     uint64_t *cand = ws.get_n<uint64_t>(cap + 1);
-    int64_t c0 = emit_candidates(rb.val, g, d, cand, cap, ws, s, ctx->pinned);
+    int64_t c0 = emit_candidates(rb.val, g, d, cand, cap, ws, s, ctx->pinned, &ctx->kt);
     tm.mark();  // 3 group + filter
     uint64_t *uniq = nullptr;
     int64_t C = dedup_pairs(cand, c0, d.n, ws, s, ctx->pinned, &uniq);
@@ -253,6 +262,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
         stats->groups = g.groups;
         stats->pair_tests = (int64_t)g.tests;
         stats->candidates = C;
+        stats->positions = d.total * pp.reps;
     }
     if (upto == 1) {
         mj_pairs *out = new mj_pairs();
@@ -263,8 +273,8 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     }
     struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
     uint8_t *flags = ws.get_n<uint8_t>(C + 1);
-    int64_t cells = verify_pairs(uniq, C, d, d, 0, flags, ws, s, ctx->pinned);
-    check_flags(flags, C, ws, s, ctx->pinned);
+    int64_t cells = verify_pairs(uniq, C, d, d, 0, flags, ws, s, ctx->pinned, &ctx->kt, params->k);
+    if (params->k < 0) check_flags(flags, C, ws, s, ctx->pinned);
     tm.mark();  // 5 verify
     mj_pairs *out = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);
     tm.mark();  // 6 output
@@ -430,6 +440,7 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
         throw Error(MJ_EINVAL, "query alphabet must not exceed the index alphabet");
     if (qparams->k < -1 || (qparams->k == -1 && !qparams->k_per_string))
         throw Error(MJ_EINVAL, "bad query threshold");
+    if (qparams->k > 2047) throw Error(MJ_ECAPACITY, "threshold K exceeds the verifier's band limit (K <= 2047)");
     MJ_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     Workspace &ws = ctx->ws;
@@ -446,7 +457,8 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
     tm.mark();  // 0 setup
     RecBuf rb;
     struct RbFree { RecBuf &r; ~RbFree() { r.release(); } } rbf{rb};
-    for (int rho = 0; rho < qp.reps; rho++) partition_records(qd, qp, rho, halo, rb, ws, s, ctx->pinned);
+    for (int rho = 0; rho < qp.reps; rho++)
+        partition_records(qd, qp, rho, halo, rb, ws, s, ctx->pinned, &ctx->kt);
     tm.mark();  // 1 partition
     if (rb.count > 1) {
         int bb = std::min(22, std::max(1, ceil_log2((uint64_t)(rb.count / 128 + 1))));
@@ -482,8 +494,8 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
     struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
     tm.mark();  // 4 dedup
     uint8_t *flags = ws.get_n<uint8_t>(C + 1);
-    int64_t cells = verify_pairs(uniq, C, qd, id, 1, flags, ws, s, ctx->pinned);
-    check_flags(flags, C, ws, s, ctx->pinned);
+    int64_t cells = verify_pairs(uniq, C, qd, id, 1, flags, ws, s, ctx->pinned, &ctx->kt, qparams->k);
+    if (qparams->k < 0) check_flags(flags, C, ws, s, ctx->pinned);
     tm.mark();  // 5 verify
     mj_pairs *res = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);
     tm.mark();  // 6 output
@@ -494,6 +506,7 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
         stats->candidates = C;
         stats->output = res->n;
         stats->band_cells = cells;
+        stats->positions = qd.total * qp.reps;
     }
     tm.fill(stats);
     *out = res;

@@ -168,15 +168,17 @@ __global__ __launch_bounds__(256) void k_emit(const uint64_t *__restrict__ val,
 
 int64_t emit_candidates(const uint64_t *val, const GroupInfo &g, const DevStrings &d,
                         uint64_t *out, int64_t cap, Workspace &ws, hipStream_t s,
-                        uint64_t *host_scratch) {
+                        uint64_t *host_scratch, KTimer *kt) {
     if (g.groups == 0 || g.tests == 0) return 0;
     unsigned long long *counter = (unsigned long long *)ws.get_n<uint64_t>(2);
     fill_u64((uint64_t *)counter, 0, 1, s);
     uint64_t threads = (g.tests + EMIT_CHUNK - 1) / EMIT_CHUNK;
     unsigned grid = (unsigned)std::min<uint64_t>((threads + 255) / 256, 1u << 16);
+    int th = kt ? kt->begin(KTimer::EMIT, s) : -1;
     hipLaunchKernelGGL(k_emit, dim3(grid), dim3(256), 0, s, val, g.gstart, g.tstart, g.groups,
                        g.tests, d.len, d.kk, out, cap, counter);
     MJ_LAUNCH_CHECK();
+    if (kt) kt->end(th, s);
     uint64_t c = read_back<uint64_t>((const uint64_t *)counter, s, host_scratch);
     if ((int64_t)c > cap) throw Error(MJ_ECAPACITY, "candidate buffer overflow");
     return (int64_t)c;

@@ -74,6 +74,23 @@ class Workspace {
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
 
+// ---------------------------------------------------------------- kernel timers
+// HIP events recorded on the launching stream around each launch of a hot kernel;
+// summed per slot after the call has synchronised.
+struct KTimer {
+    enum { ANCHORS = 0, RECORDS = 1, EMIT = 2, VERIFY = 3, SLOTS = 4, POOL = 96 };
+    hipEvent_t ev[POOL] = {};
+    int used = 0;
+    int slot_of[POOL / 2] = {};
+    void create();
+    void destroy();
+    void reset() { used = 0; }
+    // returns a handle for end(); -1 when the pool is exhausted (launch not timed)
+    int begin(int slot, hipStream_t s);
+    void end(int h, hipStream_t s);
+    void collect(float *ms, int32_t *launches);  // stream must be synchronised
+};
+
 // ---------------------------------------------------------------- primitives (prims.hip)
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
@@ -142,7 +159,8 @@ int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, 
 void pack_planes(DevStrings &d, int planes, Workspace &ws, hipStream_t s);
 // Appends the records of every partition of repetition rho to `out`; returns how many.
 int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho, int32_t halo,
-                          RecBuf &out, Workspace &ws, hipStream_t s, uint64_t *host_scratch);
+                          RecBuf &out, Workspace &ws, hipStream_t s, uint64_t *host_scratch,
+                          KTimer *kt = nullptr);
 
 // join.hip
 struct GroupInfo {
@@ -156,7 +174,7 @@ GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t
 // Emit candidate pair keys for all pair tests; returns count emitted (<= cap).
 int64_t emit_candidates(const uint64_t *val, const GroupInfo &g, const DevStrings &d,
                         uint64_t *out, int64_t cap, Workspace &ws, hipStream_t s,
-                        uint64_t *host_scratch);
+                        uint64_t *host_scratch, KTimer *kt = nullptr);
 // Sort + unique in place; returns unique count.
 int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t max_id, Workspace &ws, hipStream_t s,
                     uint64_t *host_scratch, uint64_t **result);
@@ -169,10 +187,12 @@ int64_t probe_candidates(const uint64_t *qkey, const uint64_t *qval, int64_t RQ,
 
 // verify.hip
 // flags[i] = ED(A[a], B[b]) <= K for pairs[i] = a << 32 | b; K = max(K_a, K_b) when
-// kmode == 0, else K_a.  Returns band cells processed (device counter read back).
+// kmode == 0, else K_a.  uniform_k >= 0 promises that every pair's K equals it and that
+// all ids are valid (pairs produced by the library): then no binning pass is needed.
+// Returns band cells processed (device counter read back).
 int64_t verify_pairs(const uint64_t *pairs, int64_t n, const DevStrings &A, const DevStrings &B,
                      int kmode, uint8_t *flags, Workspace &ws, hipStream_t s,
-                     uint64_t *host_scratch);
+                     uint64_t *host_scratch, KTimer *kt = nullptr, int64_t uniform_k = -1);
 int verify_planes(int bits);   // planes the verifier needs for b bits per symbol
 
 }  // namespace mj

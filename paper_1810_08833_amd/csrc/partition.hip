@@ -323,7 +323,8 @@ void RecBuf::release() {
 }
 
 int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho, int32_t halo,
-                          RecBuf &out, Workspace &ws, hipStream_t s, uint64_t *host_scratch) {
+                          RecBuf &out, Workspace &ws, hipStream_t s, uint64_t *host_scratch,
+                          KTimer *kt) {
     if (d.total == 0) return 0;
     int H = std::max<int32_t>(halo, 1);
     if (H > AT_MAX_HALO)
@@ -337,9 +338,11 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho
     uint64_t seed = p.seed + (uint64_t)rho;
     uint64_t salt = mix64(seed + GAMMA);
     if (ntiles > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many tiles");
+    int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
     hipLaunchKernelGGL(k_anchor_tiles, dim3((unsigned)ntiles), dim3(AT_THREADS), lds, s, d.chars,
                        d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, d.rr, TP, H, bitmap);
     MJ_LAUNCH_CHECK();
+    if (kt) kt->end(th, s);
     uint32_t *cnt = ws.get_n<uint32_t>(nw + 1);
     uint32_t *pre = ws.get_n<uint32_t>(nw + 1);
     hipLaunchKernelGGL(k_word_popc, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s, bitmap, nw, cnt);
@@ -355,10 +358,12 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho
     uint64_t B = 2 + mix64(p.seed ^ GAMMA_B) % (P61 - 3);
     uint64_t salt_f = mix64(p.seed + GAMMA);
     if (R > 0) {
+        int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
         hipLaunchKernelGGL(k_records, dim3(grid_for(R, 256, 65535)), dim3(256), 0, s, apos, R,
                            d.offsets, d.n, d.chars, B, salt_f, out.key + base, out.val + base,
                            out.with_len ? out.len + base : nullptr);
         MJ_LAUNCH_CHECK();
+        if (kt) kt->end(tr, s);
     }
     out.count = base + R;
     return R;

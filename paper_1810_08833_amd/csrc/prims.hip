@@ -58,6 +58,42 @@ void dev_free(void *p) {
     if (p) (void)hipFree(p);
 }
 
+// ---------------------------------------------------------------- kernel timers
+void KTimer::create() {
+    for (auto &e : ev) MJ_HIP(hipEventCreate(&e));
+}
+
+void KTimer::destroy() {
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+}
+
+int KTimer::begin(int slot, hipStream_t s) {
+    if (used + 2 > POOL) return -1;
+    int h = used;
+    used += 2;
+    slot_of[h / 2] = slot;
+    MJ_HIP(hipEventRecord(ev[h], s));
+    return h;
+}
+
+void KTimer::end(int h, hipStream_t s) {
+    if (h >= 0) MJ_HIP(hipEventRecord(ev[h + 1], s));
+}
+
+void KTimer::collect(float *ms, int32_t *launches) {
+    for (int i = 0; i < SLOTS; i++) {
+        ms[i] = 0.f;
+        launches[i] = 0;
+    }
+    for (int h = 0; h + 1 < used; h += 2) {
+        float t = 0.f;
+        MJ_HIP(hipEventElapsedTime(&t, ev[h], ev[h + 1]));
+        ms[slot_of[h / 2]] += t;
+        launches[slot_of[h / 2]] += 1;
+    }
+}
+
 // ---------------------------------------------------------------- fills
 template <class T>
 __global__ void k_fill(T *p, T v, int64_t n) {

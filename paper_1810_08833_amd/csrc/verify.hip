@@ -312,26 +312,32 @@ __global__ __launch_bounds__(64) void k_verify_dp(const uint64_t *__restrict__ p
 // ---------------------------------------------------------------- dispatch
 // bin of a pair: c = ceil(K/32) for c <= BP_MAX_C (bit-parallel), else the wide path
 // Pairs naming a string id outside the collections go to the last bin, which is never
-// launched; the host reports them as invalid arguments.
+// launched; the host reports them as invalid arguments.  Counts are gathered per block in
+// LDS, then added to the global counters once per block.
 __global__ void k_bin_pairs(const uint64_t *pairs, int64_t n, VSet A, VSet B, int kmode,
                             uint8_t *bin, uint32_t *counts) {
+    constexpr int NBIN = BP_MAX_C + 3;
+    __shared__ uint32_t local[NBIN];
+    if (threadIdx.x < NBIN) local[threadIdx.x] = 0;
+    __syncthreads();
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) {
         uint64_t pr = pairs[i];
         uint32_t ua = (uint32_t)(pr >> 32), ub = (uint32_t)pr;
+        int b;
         if (ua >= (uint32_t)A.n || ub >= (uint32_t)B.n) {
-            bin[i] = (uint8_t)(BP_MAX_C + 2);
-            atomicAdd(&counts[BP_MAX_C + 2], 1u);
-            continue;
+            b = BP_MAX_C + 2;
+        } else {
+            int32_t K = kmode == 0 ? max(A.kk[ua], B.kk[ub]) : A.kk[ua];
+            int c = (K + 31) >> 5;
+            b = c <= BP_MAX_C ? c : BP_MAX_C + 1;
         }
-        int32_t ia = (int32_t)ua, ib = (int32_t)ub;
-        int32_t K = kmode == 0 ? max(A.kk[ia], B.kk[ib]) : A.kk[ia];
-        int c = (K + 31) >> 5;
-        int b = c <= BP_MAX_C ? c : BP_MAX_C + 1;
         bin[i] = (uint8_t)b;
-        atomicAdd(&counts[b], 1u);
+        atomicAdd(&local[b], 1u);
     }
+    __syncthreads();
+    if (threadIdx.x < NBIN && local[threadIdx.x]) atomicAdd(&counts[threadIdx.x], local[threadIdx.x]);
 }
 
 __global__ void k_bin_scatter(const uint8_t *bin, int64_t n, const uint32_t *boff, uint32_t *fill,
@@ -378,13 +384,28 @@ static VSet vset(const DevStrings &d) {
 
 int64_t verify_pairs(const uint64_t *pairs, int64_t n, const DevStrings &A, const DevStrings &B,
                      int kmode, uint8_t *flags, Workspace &ws, hipStream_t s,
-                     uint64_t *host_scratch) {
+                     uint64_t *host_scratch, KTimer *kt, int64_t uniform_k) {
     if (n <= 0) return 0;
     if (A.planes == nullptr || B.planes == nullptr) throw Error(MJ_EINVAL, "strings not packed");
     int np = verify_planes(std::max(A.bits, B.bits));
     VSet va = vset(A), vb = vset(B);
     unsigned long long *cells = (unsigned long long *)ws.get_n<uint64_t>(2);
     fill_u64((uint64_t *)cells, 0, 1, s);
+    if (uniform_k >= 0) {
+        // every pair has the same threshold and valid ids: one launch, no binning
+        int c = (int)((uniform_k + 31) >> 5);
+        int th = kt ? kt->begin(KTimer::VERIFY, s) : -1;
+        if (c <= BP_MAX_C) {
+            hipLaunchKernelGGL(bp_kernel(c, np), dim3(grid_for(n, 256, 0x7FFFFFFF)), dim3(256), 0, s,
+                               pairs, (const int64_t *)nullptr, n, va, vb, kmode, flags, cells);
+        } else {
+            hipLaunchKernelGGL(k_verify_dp, dim3(grid_for(n, 1, 1u << 20)), dim3(64), 0, s, pairs,
+                               (const int64_t *)nullptr, n, va, vb, kmode, flags, cells);
+        }
+        MJ_LAUNCH_CHECK();
+        if (kt) kt->end(th, s);
+        return (int64_t)read_back<uint64_t>((const uint64_t *)cells, s, host_scratch);
+    }
     const int NB = BP_MAX_C + 3;  // bit-parallel bins 0..8, wide path, invalid ids
     uint8_t *bin = ws.get_n<uint8_t>(n);
     uint32_t *counts = ws.get_n<uint32_t>(NB + 1);
@@ -409,6 +430,7 @@ int64_t verify_pairs(const uint64_t *pairs, int64_t n, const DevStrings &A, cons
         int64_t cnt = (int64_t)hoff[b + 1] - hoff[b];
         if (cnt <= 0) continue;
         const int64_t *bsel = sel + hoff[b];
+        int th = kt ? kt->begin(KTimer::VERIFY, s) : -1;
         if (b <= BP_MAX_C) {
             BpKernel kfn = bp_kernel(b, np);
             hipLaunchKernelGGL(kfn, dim3(grid_for(cnt, 256, 0x7FFFFFFF)), dim3(256), 0, s, pairs, bsel,
@@ -418,6 +440,7 @@ int64_t verify_pairs(const uint64_t *pairs, int64_t n, const DevStrings &A, cons
                                bsel, cnt, va, vb, kmode, flags, cells);
         }
         MJ_LAUNCH_CHECK();
+        if (kt) kt->end(th, s);
     }
     return (int64_t)read_back<uint64_t>((const uint64_t *)cells, s, host_scratch);
 }
