@@ -117,6 +117,88 @@ def copy_calibration(gib):
     print(json.dumps({"copy_bytes": n, "launches": 3}))
 
 
+def serve(args):
+    """Serving: a resident index over uniform random DNA strings (lengths U[1000,10000]),
+    queries replayed at their Poisson arrival times into the continuous-batching server.
+    Prints one JSON line with queries/s and p50/p99 latency."""
+    import torch
+    import paper_1810_08833_amd as mj
+    from paper_1810_08833_amd import datagen as dg
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    S = dg.dna_index(n=args.serve_strings)
+    Q, src, arrivals = dg.dna_queries(S, n=args.serve_queries, rate_per_s=args.serve_rate)
+    print("[serve] index %d strings (%d symbols), %d queries, generated in %.1f s"
+          % (S.n, S.offsets[-1], Q.n, time.perf_counter() - t_gen), file=sys.stderr, flush=True)
+    ds = mj.DeviceStrings.from_host(S.chars, S.offsets, 4)
+    ki = torch.from_numpy(dg.k_fraction(S.lengths(), 1, 10)).cuda()
+    torch.cuda.synchronize()
+    t_b = time.perf_counter()
+    index = mj.Index(ds, mj.Params(q=5, k_per_string=ki, t_div=args.serve_t_div))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t_b
+    del ds
+    kq = dg.k_fraction(Q.lengths(), 1, 10)
+    # ground truth: each mutated query against its source, threshold K_query
+    mut = np.nonzero(src >= 0)[0]
+    pairs_c = dg.from_list([x for i in mut for x in (Q.get(int(i)), S.get(int(src[i])))], 4)
+    kc = np.repeat(kq[mut], 2).astype(np.int32)
+    pc = mj.DeviceStrings.from_host(pairs_c.chars, pairs_c.offsets, 4)
+    pl = (np.arange(len(mut), dtype=np.uint64) * 2 << np.uint64(32)) | (np.arange(len(mut), dtype=np.uint64) * 2 + 1)
+    within = mj.verify(pc, mj.Params(q=5, k_per_string=torch.from_numpy(kc).cuda()), pl)
+    truth = {int(mut[i]): int(src[mut[i]]) for i in range(len(mut)) if within[i]}
+    server = mj.Server(index, workers=args.serve_workers, max_batch=4096,
+                       memory_budget=args.serve_budget_gib << 30)
+    # warm-up (workspaces, verifier tuning) outside the measured replay
+    for t in range(min(64, Q.n)):
+        server.submit(Q.get(t), int(kq[t]), 1 << 40 | t)
+    got = 0
+    while got < min(64, Q.n):
+        got += len(server.poll(timeout_ms=60000))
+    replies = []
+    t0 = time.perf_counter()
+    for i in range(Q.n):
+        target = t0 + arrivals[i] - arrivals[0]
+        while True:
+            now = time.perf_counter()
+            if now >= target:
+                break
+            replies += server.poll(timeout_ms=0)
+            if target - now > 0.0003:
+                time.sleep(min(0.0005, target - now - 0.0002))
+        server.submit(Q.get(i), int(kq[i]), i)
+    while len(replies) < Q.n:
+        replies += server.poll(timeout_ms=60000)
+    server.close()
+    lat = np.array([r["done_ms"] - r["submit_ms"] for r in replies])
+    first = min(r["submit_ms"] for r in replies)
+    last = max(r["done_ms"] for r in replies)
+    found = sum(1 for r in replies if r["tag"] in truth and truth[r["tag"]] in set(r["ids"].tolist()))
+    line = {
+        "metric": "serving: queries/s with p50/p99 latency (continuous batching)",
+        "value": Q.n / ((last - first) * 1e-3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "dna_index: %d uniform DNA strings, lengths U[1000,10000]; %d queries "
+                               "(half mutated copies at 5-15%%, half random), Poisson %d/s, "
+                               "K=ceil(0.1|q|), q=5, T=ceil(K/%d)" % (S.n, Q.n, args.serve_rate,
+                                                                      args.serve_t_div),
+                   "workers": args.serve_workers, "memory_budget_gib": args.serve_budget_gib},
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "mean_batch": float(np.mean([r["batch_size"] for r in replies])),
+        "max_batch": int(max(r["batch_size"] for r in replies)),
+        "recall": found / max(1, len(truth)),
+        "true_pairs": len(truth),
+        "index_records": index.records,
+        "index_build_s": build_s,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +208,13 @@ def main():
     ap.add_argument("--t-div", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-clusters", type=int, default=1000)
+    ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
+    ap.add_argument("--serve-strings", type=int, default=1_000_000)
+    ap.add_argument("--serve-queries", type=int, default=4096)
+    ap.add_argument("--serve-rate", type=int, default=2000)
+    ap.add_argument("--serve-t-div", type=int, default=1)
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-budget-gib", type=int, default=32)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain copy of this many GiB (rocprofv3 counter scale)")
     args = ap.parse_args()
@@ -136,6 +225,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
+        return
+    if args.serve:
+        serve(args)
         return
 
     import torch
@@ -159,19 +251,26 @@ def main():
     flags = mj.verify(ds, params, truth_pairs, ctx=ctx)
     truth = truth_pairs[flags]
 
-    out = None
-    for _ in range(args.warmup):
-        out, st = mj.join(ds, params, ctx=ctx)
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out, st = mj.join(ds, params, ctx=ctx)
-        stats.append(st)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms = dt * 1e3 / args.steps
-    print("[bench] %d steps in %.3f s" % (args.steps, dt), file=sys.stderr, flush=True)
+    def timed(verifier):
+        params.verifier = verifier
+        out = None
+        for _ in range(args.warmup):
+            out, st = mj.join(ds, params, ctx=ctx)
+        torch.cuda.synchronize()
+        stats = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out, st = mj.join(ds, params, ctx=ctx)
+            stats.append(st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return out, stats, dt * 1e3 / args.steps
+
+    plain_out, plain_stats, plain_ms = timed(mj.VERIFY_PLAIN)
+    print("[bench] plain: %.3f ms/step" % plain_ms, file=sys.stderr, flush=True)
+    out, stats, ms = timed(mj.VERIFY_BATCHED)
+    print("[bench] batched: %.3f ms/step" % ms, file=sys.stderr, flush=True)
+    assert np.array_equal(out, plain_out), "batched and plain verifiers disagree"
 
     recall = float(np.isin(truth, out).mean()) if len(truth) else 1.0
     last = stats[-1]
@@ -181,13 +280,13 @@ def main():
     dominant = max(kms, key=kms.get)
 
     # roofline of the dominant kernel
-    src = os.path.join(ROOT, "paper_1810_08833_amd", "csrc", "verify.hip")
+    src = os.path.join(ROOT, "paper_1810_08833_amd", "csrc", "verify_lg.hip")
     if dominant == "verify":
         cells = float(np.sum([s["band_cells"] for s in stats]))
         ops = cells / 32.0 * OPS_PER_WORD_COLUMN
         achieved = ops / (kms["verify"] * 1e-3) / 1e12
         traffic = measured_traffic(src)
-        roof = {"kernel": "k_verify_bp", "bound": "alu", "achieved": achieved,
+        roof = {"kernel": "k_verify_persist", "bound": "alu", "achieved": achieved,
                 "peak": INT_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / INT_PEAK_TOPS,
                 "traffic": traffic,
                 "avg_launch_ms": kms["verify"] / max(1, kln["verify"]),
@@ -215,7 +314,12 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "strings": S.n, "symbols": int(S.offsets[-1]),
-                   "K": cfg["k"], "q": cfg["q"], "t_div": cfg["t_div"], "path": "plain"},
+                   "K": cfg["k"], "q": cfg["q"], "t_div": cfg["t_div"], "path": "batched",
+                   "verify_lanes_per_pair": last["verify_group"],
+                   "verify_words_per_lane": last["verify_words"]},
+        "plain": {"value": S.n / (plain_ms * 1e-3), "ms_per_step": plain_ms,
+                  "verify_kernel_ms": float(np.mean([s["kernel_ms"]["verify"] for s in plain_stats]))},
+        "batched_vs_plain": plain_ms / ms,
         "verified_pairs_per_s": last["candidates"] / (verify_ms * 1e-3),
         "candidates": last["candidates"],
         "output_pairs": int(len(out)),

@@ -69,7 +69,11 @@ typedef struct {
  *            pair uses max(K_i, K_j); a search pair uses the query's K.
  *   pi_table optional device uint64[2^(q*b)] replacing Pi (indexed by the packed
  *            q-gram, first symbol most significant, b = ceil(log2 sigma) bits each);
- *            NULL for the seeded hash.  Needs q * b <= 24. */
+ *            NULL for the seeded hash.  Needs q * b <= 24.
+ *   verifier MJ_VERIFY_BATCHED (0): all candidates in one persistent launch, a pair per
+ *            lane group, longest pairs first, group width timed once per context;
+ *            MJ_VERIFY_PLAIN (1): a pair per lane, one launch per band size.  Both give
+ *            the same decisions. */
 typedef struct {
     int32_t q;
     int32_t t_div;
@@ -79,7 +83,11 @@ typedef struct {
     int64_t k;
     const int32_t *k_per_string;
     const uint64_t *pi_table;
+    int32_t verifier;
+    int32_t reserved;
 } mj_params;
+
+enum { MJ_VERIFY_BATCHED = 0, MJ_VERIFY_PLAIN = 1 };
 
 /* Per-call counters and stage times (milliseconds between HIP events recorded on the
  * call's stream, so they include the host read-backs between stages).  Stage order:
@@ -100,6 +108,8 @@ typedef struct {
     float kernel_ms[4];
     int32_t kernel_launches[4];
     int64_t positions;   /* symbols scanned by the anchor kernel, over all repetitions */
+    int32_t verify_group;  /* lanes per pair of the batched verifier (0: plain) */
+    int32_t verify_words;  /* band words per lane of the batched verifier */
 } mj_stats;
 
 /* ---- context ---------------------------------------------------------------- */
@@ -158,6 +168,54 @@ int64_t mj_index_records(const mj_index *index);
 mj_status mj_search(mj_ctx *ctx, const mj_index *index, const mj_strings *queries,
                     const mj_params *qparams, void *stream, mj_pairs **out,
                     mj_stats *stats);
+
+/* ---- serving: continuous batching over a resident index ------------------------
+ * Callers that submit queries one at a time (a request stream).  Worker threads each own
+ * a HIP stream and a workspace on the index's device; a free worker admits every queued
+ * request that fits (up to max_batch queries, and while the estimated device memory of
+ * all batches in flight stays within memory_budget), so requests that arrive while other
+ * batches run on the GPU join the next batch and the batches of different workers
+ * overlap on the device.  A query's answer is the same as mj_search gives it alone:
+ * queries of one batch do not interact. */
+
+typedef struct mj_server mj_server;
+
+typedef struct {
+    int32_t workers;        /* batches in flight at once, 1..16 */
+    int32_t max_batch;      /* queries per batch, 1..65536 */
+    int64_t memory_budget;  /* bytes; a request's estimate is 96 bytes per symbol + 4 KiB */
+} mj_server_config;
+
+typedef struct {
+    uint64_t tag;           /* caller's tag from mj_server_submit */
+    int32_t status;         /* mj_status of the batch that answered the request */
+    int32_t count;          /* matching string ids written at ids[offset .. offset+count) */
+    int64_t offset;
+    int32_t batch_size;     /* queries in the batch that answered it */
+    int32_t worker;
+    double submit_ms;       /* times in ms since the server started */
+    double start_ms;        /* its batch was admitted */
+    double done_ms;         /* its batch completed */
+} mj_reply;
+
+/* The index must outlive the server.  EINVAL on bad config. */
+mj_status mj_server_create(int device, const mj_index *index, const mj_server_config *cfg,
+                           mj_server **out);
+/* Copies the query (host symbol codes, length len >= 0) and queues it with threshold k
+ * (0 <= k <= 2047).  EINVAL if the request alone exceeds the memory budget. */
+mj_status mj_server_submit(mj_server *srv, const uint8_t *codes, int32_t len, int32_t k,
+                           uint64_t tag);
+/* Waits up to timeout_ms (0: no wait; < 0: until one reply) for completed requests and
+ * moves up to max_replies of them to replies[], their matching ids (ascending) to
+ * ids[0 .. ids_cap); stops early when ids_cap would be exceeded.  *n_replies and *n_ids
+ * give what was written. */
+mj_status mj_server_poll(mj_server *srv, mj_reply *replies, int32_t max_replies, uint32_t *ids,
+                         int64_t ids_cap, int32_t timeout_ms, int32_t *n_replies,
+                         int64_t *n_ids);
+/* Requests queued or in flight (not yet polled). */
+int64_t mj_server_pending(const mj_server *srv);
+/* Finishes the batches in flight, drops queued requests, joins the workers. */
+void mj_server_destroy(mj_server *srv);
 
 /* ---- results ----------------------------------------------------------------- */
 

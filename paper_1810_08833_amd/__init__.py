@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libminjoin.so")
 
 MJ_OK, MJ_EINVAL, MJ_ENOMEM, MJ_EDEVICE, MJ_ECAPACITY = 0, 1, 2, 3, 4
+VERIFY_BATCHED, VERIFY_PLAIN = 0, 1
 STATUS_NAMES = {0: "MJ_OK", 1: "MJ_EINVAL", 2: "MJ_ENOMEM", 3: "MJ_EDEVICE", 4: "MJ_ECAPACITY"}
 KERNELS = ["anchors", "records", "emit", "verify"]
 STAGES = ["setup", "partition", "sort", "group_filter", "dedup", "verify", "output", "unused"]
@@ -34,7 +35,8 @@ class MjStrings(ctypes.Structure):
 class MjParams(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int32), ("t_div", ctypes.c_int32), ("t_fixed", ctypes.c_int32),
                 ("reps", ctypes.c_int32), ("seed", ctypes.c_uint64), ("k", ctypes.c_int64),
-                ("k_per_string", ctypes.c_void_p), ("pi_table", ctypes.c_void_p)]
+                ("k_per_string", ctypes.c_void_p), ("pi_table", ctypes.c_void_p),
+                ("verifier", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class MjStats(ctypes.Structure):
@@ -42,22 +44,37 @@ class MjStats(ctypes.Structure):
                 ("pair_tests", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("output", ctypes.c_int64), ("band_cells", ctypes.c_int64),
                 ("stage_ms", ctypes.c_float * 8), ("kernel_ms", ctypes.c_float * 4),
-                ("kernel_launches", ctypes.c_int32 * 4), ("positions", ctypes.c_int64)]
+                ("kernel_launches", ctypes.c_int32 * 4), ("positions", ctypes.c_int64),
+                ("verify_group", ctypes.c_int32), ("verify_words", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k in ("records", "groups", "pair_tests", "candidates",
-                                           "output", "band_cells", "positions")}
+                                           "output", "band_cells", "positions", "verify_group",
+                                           "verify_words")}
         d["stage_ms"] = {STAGES[i]: float(self.stage_ms[i]) for i in range(7)}
         d["kernel_ms"] = {KERNELS[i]: float(self.kernel_ms[i]) for i in range(4)}
         d["kernel_launches"] = {KERNELS[i]: int(self.kernel_launches[i]) for i in range(4)}
         return d
 
 
+class MjServerConfig(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("memory_budget", ctypes.c_int64)]
+
+
+class MjReply(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("count", ctypes.c_int32),
+                ("offset", ctypes.c_int64), ("batch_size", ctypes.c_int32),
+                ("worker", ctypes.c_int32), ("submit_ms", ctypes.c_double),
+                ("start_ms", ctypes.c_double), ("done_ms", ctypes.c_double)]
+
+
 EXPORTS = ["mj_ctx_create", "mj_ctx_destroy", "mj_last_error", "mj_version", "mj_join",
            "mj_partition", "mj_candidates", "mj_verify", "mj_index_build", "mj_index_free",
            "mj_index_records", "mj_search", "mj_pairs_count", "mj_pairs_device",
            "mj_pairs_copy_to_host", "mj_pairs_free", "mj_records_count",
-           "mj_records_copy_to_host", "mj_records_free"]
+           "mj_records_copy_to_host", "mj_records_free", "mj_server_create", "mj_server_submit",
+           "mj_server_poll", "mj_server_pending", "mj_server_destroy"]
 
 _lib = None
 
@@ -105,6 +122,16 @@ def load_library(path: str = LIB_PATH):
     L.mj_records_copy_to_host.argtypes = [VP, VP, VP, VP, VP, I64]
     L.mj_records_free.argtypes = [VP]
     L.mj_records_free.restype = None
+    L.mj_server_create.argtypes = [ctypes.c_int, VP, P(MjServerConfig), P(VP)]
+    L.mj_server_submit.argtypes = [VP, VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64]
+    L.mj_server_poll.argtypes = [VP, P(MjReply), ctypes.c_int32, VP, I64, ctypes.c_int32,
+                                 P(ctypes.c_int32), P(I64)]
+    L.mj_server_pending.argtypes = [VP]
+    L.mj_server_pending.restype = I64
+    L.mj_server_destroy.argtypes = [VP]
+    L.mj_server_destroy.restype = None
+    for fn in ("mj_server_create", "mj_server_submit", "mj_server_poll"):
+        getattr(L, fn).restype = ctypes.c_int
     for fn in ("mj_ctx_create", "mj_join", "mj_candidates", "mj_partition", "mj_verify",
                "mj_index_build", "mj_search", "mj_pairs_copy_to_host", "mj_records_copy_to_host"):
         getattr(L, fn).restype = ctypes.c_int
@@ -203,9 +230,11 @@ class Params:
     reps: int = 1
     seed: int = 0
     pi_table: Optional[object] = None       # torch uint64/int64 tensor on the GPU
+    verifier: int = VERIFY_BATCHED          # or VERIFY_PLAIN
 
     def struct(self) -> MjParams:
         p = MjParams()
+        p.verifier = self.verifier
         p.q, p.t_div, p.t_fixed, p.reps = self.q, self.t_div, self.t_fixed, self.reps
         p.seed = self.seed
         p.k = self.k if self.k_per_string is None else -1
@@ -305,10 +334,11 @@ class Index:
     def records(self) -> int:
         return load_library().mj_index_records(self.handle)
 
-    def search(self, queries: DeviceStrings, k: int = -1, k_per_query=None, stream=None):
+    def search(self, queries: DeviceStrings, k: int = -1, k_per_query=None, stream=None,
+               verifier: int = VERIFY_BATCHED):
         """(query id << 32 | string id) pairs with ED <= K_query; returns (pairs, stats)."""
         L = load_library()
-        qp = Params(q=1, k=k, k_per_string=k_per_query)
+        qp = Params(q=1, k=k, k_per_string=k_per_query, verifier=verifier)
         s, p, st, h = queries.struct(), qp.struct(), MjStats(), ctypes.c_void_p()
         _check(L.mj_search(self.ctx.handle, self.handle, ctypes.byref(s), ctypes.byref(p),
                            _stream_ptr(stream), ctypes.byref(h), ctypes.byref(st)))
@@ -317,6 +347,55 @@ class Index:
     def close(self):
         if self.handle:
             load_library().mj_index_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching search over a resident Index (native worker threads, one HIP
+    stream each; admission by a device-memory budget)."""
+
+    def __init__(self, index: Index, workers: int = 4, max_batch: int = 4096,
+                 memory_budget: int = 16 << 30):
+        L = load_library()
+        cfg = MjServerConfig(workers, max_batch, memory_budget)
+        h = ctypes.c_void_p()
+        _check(L.mj_server_create(index.ctx.device, index.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self.index = index  # keep the index alive
+
+    def submit(self, codes, k: int, tag: int):
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        _check(load_library().mj_server_submit(self.handle, codes.ctypes.data_as(ctypes.c_void_p),
+                                               len(codes), int(k), int(tag)))
+
+    def pending(self) -> int:
+        return load_library().mj_server_pending(self.handle)
+
+    def poll(self, timeout_ms: int = -1, max_replies: int = 4096, ids_cap: int = 1 << 20):
+        """Returns a list of dicts: tag, ids (np.uint32), batch_size, worker, status and
+        submit/start/done times in ms."""
+        L = load_library()
+        reps = (MjReply * max_replies)()
+        ids = np.zeros(ids_cap, dtype=np.uint32)
+        nr, ni = ctypes.c_int32(), ctypes.c_int64()
+        _check(L.mj_server_poll(self.handle, reps, max_replies, ids.ctypes.data_as(ctypes.c_void_p),
+                                ids_cap, int(timeout_ms), ctypes.byref(nr), ctypes.byref(ni)))
+        out = []
+        for r in reps[:nr.value]:
+            out.append({"tag": r.tag, "status": r.status, "ids": ids[r.offset:r.offset + r.count].copy(),
+                        "batch_size": r.batch_size, "worker": r.worker, "submit_ms": r.submit_ms,
+                        "start_ms": r.start_ms, "done_ms": r.done_ms})
+        return out
+
+    def close(self):
+        if self.handle:
+            load_library().mj_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

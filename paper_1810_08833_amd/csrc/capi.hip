@@ -5,40 +5,9 @@
 #include <algorithm>
 #include <string>
 
-#include "mj_common.h"
+#include "capi_internal.h"
 
 using namespace mj;
-
-struct mj_ctx {
-    int device = 0;
-    Workspace ws;
-    uint64_t *pinned = nullptr;  // host scratch for read-backs (4 KiB)
-    hipEvent_t ev[9] = {};
-    KTimer kt;
-};
-
-struct mj_pairs {
-    uint64_t *d = nullptr;
-    int64_t n = 0;
-};
-
-struct mj_records {
-    RecBuf rb;
-};
-
-struct mj_index {
-    int device = 0;
-    PartitionParams pp{};
-    int32_t n = 0, sigma = 0, bits = 0;
-    int64_t total = 0;
-    uint8_t *chars = nullptr;
-    int64_t *offsets = nullptr;
-    int32_t *len = nullptr, *kk = nullptr;
-    uint32_t *planes = nullptr;
-    int64_t plane_words = 0;
-    int np = 0;
-    RecBuf rec;  // sorted by (key, val)
-};
 
 static thread_local std::string g_err = "no error";
 
@@ -46,6 +15,8 @@ static mj_status fail(mj_status st, const std::string &m) {
     g_err = m;
     return st;
 }
+
+mj_status mj_fail(mj_status st, const std::string &m) { return fail(st, m); }
 
 #define MJ_API_BEGIN try {
 #define MJ_API_END                                            \
@@ -115,6 +86,8 @@ static void check_params(const mj_params *p, int sigma, bool need_k) {
         if (p->k > 0x3FFFFFFF) throw Error(MJ_EINVAL, "k too large");
     }
     if (p->pi_table && (int64_t)p->q * b > 24) throw Error(MJ_EINVAL, "pi_table needs q*b <= 24");
+    if (p->verifier != MJ_VERIFY_BATCHED && p->verifier != MJ_VERIFY_PLAIN)
+        throw Error(MJ_EINVAL, "verifier must be MJ_VERIFY_BATCHED or MJ_VERIFY_PLAIN");
 }
 
 static void check_strings(const mj_strings *s) {
@@ -195,6 +168,25 @@ static void check_flags(const uint8_t *f, int64_t n, Workspace &ws, hipStream_t 
     if (read_back<uint32_t>(bad, s, pinned)) throw Error(MJ_ECAPACITY, "threshold K exceeds the verifier's band limit (K <= 2047)");
 }
 
+// Verification of library-produced pairs with the chosen verifier.
+static int64_t run_verify(mj_ctx *ctx, const uint64_t *pairs, int64_t n, const DevStrings &A,
+                          const DevStrings &B, int kmode, int64_t uniform_k, int verifier,
+                          uint8_t *flags, hipStream_t s, mj_stats *stats) {
+    if (verifier == MJ_VERIFY_BATCHED) {
+        int64_t cells = verify_pairs_batched(pairs, n, A, B, kmode, flags, ctx->ws, s, ctx->pinned,
+                                             &ctx->kt, &ctx->tune);
+        if (stats) {
+            stats->verify_group = ctx->tune.last_g;
+            stats->verify_words = ctx->tune.last_nwl;
+        }
+        return cells;
+    }
+    int64_t cells = verify_pairs(pairs, n, A, B, kmode, flags, ctx->ws, s, ctx->pinned, &ctx->kt,
+                                 uniform_k);
+    if (uniform_k < 0) check_flags(flags, n, ctx->ws, s, ctx->pinned);
+    return cells;
+}
+
 struct StageTimer {
     mj_ctx *ctx;
     hipStream_t s;
@@ -273,8 +265,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     }
     struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
     uint8_t *flags = ws.get_n<uint8_t>(C + 1);
-    int64_t cells = verify_pairs(uniq, C, d, d, 0, flags, ws, s, ctx->pinned, &ctx->kt, params->k);
-    if (params->k < 0) check_flags(flags, C, ws, s, ctx->pinned);
+    int64_t cells = run_verify(ctx, uniq, C, d, d, 0, params->k, params->verifier, flags, s, stats);
     tm.mark();  // 5 verify
     mj_pairs *out = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);
     tm.mark();  // 6 output
@@ -354,8 +345,12 @@ extern "C" mj_status mj_verify(mj_ctx *ctx, const mj_strings *strings, const mj_
     PartitionParams pp = to_pp(params, d.bits);
     (void)prepare_strings(d, pp, ws, s, ctx->pinned);
     pack_planes(d, verify_planes(d.bits), ws, s);
-    verify_pairs(pairs, n, d, d, 0, flags, ws, s, ctx->pinned);
-    check_flags(flags, n, ws, s, ctx->pinned);
+    if (params->verifier == MJ_VERIFY_BATCHED) {
+        verify_pairs_batched(pairs, n, d, d, 0, flags, ws, s, ctx->pinned, nullptr, &ctx->tune);
+    } else {
+        verify_pairs(pairs, n, d, d, 0, flags, ws, s, ctx->pinned);
+        check_flags(flags, n, ws, s, ctx->pinned);
+    }
     MJ_HIP(hipStreamSynchronize(s));
     return MJ_OK;
     MJ_API_END
@@ -446,6 +441,7 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
     Workspace &ws = ctx->ws;
     Released rel{ws};
     StageTimer tm(ctx, s);
+    if (stats) memset(stats, 0, sizeof(*stats));
     DevStrings qd = view(queries, s, ctx->pinned);
     qd.sigma = ix->sigma;
     qd.bits = ix->bits;
@@ -494,13 +490,11 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
     struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
     tm.mark();  // 4 dedup
     uint8_t *flags = ws.get_n<uint8_t>(C + 1);
-    int64_t cells = verify_pairs(uniq, C, qd, id, 1, flags, ws, s, ctx->pinned, &ctx->kt, qparams->k);
-    if (qparams->k < 0) check_flags(flags, C, ws, s, ctx->pinned);
+    int64_t cells = run_verify(ctx, uniq, C, qd, id, 1, qparams->k, qparams->verifier, flags, s, stats);
     tm.mark();  // 5 verify
     mj_pairs *res = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);
     tm.mark();  // 6 output
     if (stats) {
-        memset(stats, 0, sizeof(*stats));
         stats->records = rb.count;
         stats->pair_tests = (int64_t)tests;
         stats->candidates = C;

@@ -195,4 +195,16 @@ int64_t verify_pairs(const uint64_t *pairs, int64_t n, const DevStrings &A, cons
                      uint64_t *host_scratch, KTimer *kt = nullptr, int64_t uniform_k = -1);
 int verify_planes(int bits);   // planes the verifier needs for b bits per symbol
 
+// verify_lg.hip: one persistent launch for all pairs (lane groups, longest first).
+// The lane-group width is timed once per (ceil(Kmax/32), planes) and kept in `tune`.
+struct VerifyTuning {
+    int best_g[64][4] = {};
+    int last_g = 0, last_nwl = 0;
+};
+int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings &A,
+                             const DevStrings &B, int kmode, uint8_t *flags, Workspace &ws,
+                             hipStream_t s, uint64_t *host_scratch, KTimer *kt,
+                             VerifyTuning *tune);
+int persist_max_c();
+
 }  // namespace mj

@@ -108,36 +108,49 @@ void pack_planes(DevStrings &d, int np, Workspace &ws, hipStream_t s) {
 // ---------------------------------------------------------------- anchors
 // One workgroup handles a tile of TP positions of the concatenated strings plus a halo
 // of H positions on each side (H >= every radius used).  It hashes every q-gram of the
-// region into LDS, then finds strict minima with a sparse table built by doubling:
-// after level k, cur[a] = min h[a .. a + 2^k - 1].  A position p of radius r is tested
-// at level k = floor(log2 r): the left window [p-r, p-1] is min(cur[p-r], cur[p-2^k])
-// and the right window [p+1, p+r] is min(cur[p+1], cur[p+1+r-2^k]).  Anchors and string
-// starts are written as one bit per position.
+// region into LDS, then finds strict minima with a sparse table built by doubling in two
+// LDS buffers: after level k, the current buffer holds min h[a .. a + 2^k - 1] at a.  A
+// position p of radius r is tested at level k = floor(log2 r): the left window
+// [p-r, p-1] is min(cur[p-r], cur[p-2^k]) and the right window [p+1, p+r] is
+// min(cur[p+1], cur[p+1+r-2^k]).  String boundaries inside the region come from an LDS
+// copy of the offsets of the strings it overlaps.  Anchors and string starts are written
+// as one bit per position.
 constexpr int AT_THREADS = 256;
-constexpr int AT_REGION_MAX = 4096;              // TP + 2H
-constexpr int AT_RUN = AT_REGION_MAX / AT_THREADS;  // region positions per thread
-constexpr int AT_OWN = AT_REGION_MAX / AT_THREADS;  // tile positions per thread (max)
-constexpr int AT_MAX_HALO = 1920;
+constexpr int AT_STR_MAX = 512;  // strings of one region held in LDS (else global search)
 
+template <int REGION>
 __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     const uint8_t *__restrict__ chars, const int64_t *__restrict__ off, int32_t n, int64_t total,
     int q, int bits, uint64_t salt, const uint64_t *__restrict__ table,
     const int32_t *__restrict__ rr, int TP, int H, uint64_t *__restrict__ bitmap) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int RUN = REGION / AT_THREADS;  // region positions per thread (max)
+    __shared__ uint64_t bufA[REGION];
+    __shared__ uint64_t bufB[REGION];
+    __shared__ uint16_t pinfo[REGION];
+    __shared__ uint8_t ch[REGION + 64];
+    __shared__ int64_t soff[AT_STR_MAX + 1];
+    __shared__ int32_t s0_s, ns_s, kmax_s;
     const int NR = TP + 2 * H;
-    uint64_t *cur = reinterpret_cast<uint64_t *>(smem_raw);
-    uint16_t *pinfo = reinterpret_cast<uint16_t *>(cur + NR);
-    uint8_t *ch = reinterpret_cast<uint8_t *>(pinfo + TP);
-    __shared__ int kmax_s;
     const int tid = threadIdx.x;
     const int64_t tile_start = (int64_t)blockIdx.x * TP;
     const int64_t base = tile_start - H;
-    if (tid == 0) kmax_s = 0;
-    // symbols of the region (q - 1 extra for the last q-grams)
+    if (tid == 0) {
+        kmax_s = 0;
+        int64_t g0 = base < 0 ? 0 : base;
+        int64_t g1 = min(base + NR, total) - 1;
+        int32_t s0 = g0 < total ? owner_of(off, n, g0) : n;
+        int32_t s1 = g1 >= g0 ? owner_of(off, n, g1) : s0;
+        s0_s = s0;
+        ns_s = (s1 - s0 + 1 <= AT_STR_MAX) ? (s1 - s0 + 1) : -1;
+    }
     for (int idx = tid; idx < NR + q; idx += AT_THREADS) {
         int64_t g = base + idx;
         ch[idx] = (g >= 0 && g < total) ? chars[g] : (uint8_t)0;
     }
+    __syncthreads();
+    const int32_t s0 = s0_s, ns = ns_s;
+    if (ns > 0)
+        for (int t = tid; t <= ns; t += AT_THREADS) soff[t] = off[s0 + t];
     __syncthreads();
     const uint64_t gmask = (q * bits >= 64) ? ~0ull : ((1ull << (q * bits)) - 1);
     // hashes: each thread walks a contiguous run, rolling the packed q-gram code
@@ -155,14 +168,25 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             uint16_t info = 0;
             if (g >= 0 && g < total) {
                 if (sidx < 0) {
-                    sidx = owner_of(off, n, g);
-                    sbeg = off[sidx];
-                    send = off[sidx + 1];
+                    if (ns > 0) {  // largest t with soff[t] <= g
+                        int lo = 0, hi = ns;
+                        while (hi - lo > 1) {
+                            int mid = (lo + hi) >> 1;
+                            if (soff[mid] <= g) lo = mid; else hi = mid;
+                        }
+                        sidx = s0 + lo;
+                        sbeg = soff[lo];
+                        send = soff[lo + 1];
+                    } else {
+                        sidx = owner_of(off, n, g);
+                        sbeg = off[sidx];
+                        send = off[sidx + 1];
+                    }
                 }
                 while (g >= send) {
                     sidx++;
-                    sbeg = off[sidx];
-                    send = off[sidx + 1];
+                    sbeg = send;
+                    send = (ns > 0) ? soff[sidx - s0 + 1] : off[sidx + 1];
                     have = false;
                 }
                 int64_t i = g - sbeg;
@@ -187,68 +211,57 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                     if (interior) lmax = max(lmax, 31 - __clz(r));
                 }
             }
-            cur[idx] = h;
-            if (idx >= H && idx < H + TP) pinfo[idx - H] = info;
+            bufA[idx] = h;
+            pinfo[idx] = info;
         }
+        (void)RUN;
         if (lmax > 0) atomicMax(&kmax_s, lmax);
     }
     __syncthreads();
     const int NC = TP / AT_THREADS;
-    uint64_t hp[AT_OWN];
-    uint16_t inf[AT_OWN];
-    bool anc[AT_OWN];
+    constexpr int OWN = REGION / AT_THREADS;
+    uint64_t hp[OWN];
+    uint16_t inf[OWN];
+    uint32_t anc = 0;
 #pragma unroll
-    for (int c = 0; c < AT_OWN; c++) {
-        if (c < NC) {
-            int p = tid + AT_THREADS * c;
-            hp[c] = cur[H + p];
-            inf[c] = pinfo[p];
-        } else {
-            hp[c] = 0;
-            inf[c] = 0;
-        }
-        anc[c] = false;
+    for (int c = 0; c < OWN; c++) {
+        int p = tid + AT_THREADS * c;
+        hp[c] = c < NC ? bufA[H + p] : 0;
+        inf[c] = c < NC ? pinfo[H + p] : 0;
     }
     const int kmax = kmax_s;
+    uint64_t *cur = bufA, *nxt = bufB;
     for (int k = 0; k <= kmax; k++) {
         const int w = 1 << k;
 #pragma unroll
-        for (int c = 0; c < AT_OWN; c++) {
+        for (int c = 0; c < OWN; c++) {
             int r = inf[c] & 0x7FFF;
             if (c < NC && r != 0 && (31 - __clz(r)) == k) {
                 int idx = H + tid + AT_THREADS * c;
                 uint64_t L = min(cur[idx - r], cur[idx - w]);
                 uint64_t R = min(cur[idx + 1], cur[idx + 1 + r - w]);
-                anc[c] = (hp[c] < L) && (hp[c] < R);
+                if (hp[c] < L && hp[c] < R) anc |= 1u << c;
             }
         }
         if (k == kmax) break;
-        uint64_t tmp[AT_RUN];
-#pragma unroll
-        for (int j = 0; j < AT_RUN; j++) {
-            int a = tid + AT_THREADS * j;
-            if (a < NR) {
-                uint64_t v = cur[a];
-                if (a + w < NR) v = min(v, cur[a + w]);
-                tmp[j] = v;
-            }
+        for (int a = tid; a < NR; a += AT_THREADS) {
+            uint64_t v = cur[a];
+            if (a + w < NR) v = min(v, cur[a + w]);
+            nxt[a] = v;
         }
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < AT_RUN; j++) {
-            int a = tid + AT_THREADS * j;
-            if (a < NR) cur[a] = tmp[j];
-        }
-        __syncthreads();
+        uint64_t *t = cur;
+        cur = nxt;
+        nxt = t;
     }
     // one bit per position: string start or anchor
     const int lane = tid & 63, wid = tid >> 6;
 #pragma unroll
-    for (int c = 0; c < AT_OWN; c++) {
+    for (int c = 0; c < OWN; c++) {
         if (c < NC) {
             int64_t chunk = tile_start + (int64_t)AT_THREADS * c + 64 * wid;
             int64_t g = chunk + lane;
-            bool flag = g < total && (((inf[c] & 0x8000) != 0) || anc[c]);
+            bool flag = g < total && (((inf[c] & 0x8000) != 0) || ((anc >> c) & 1u));
             uint64_t mask = __ballot(flag);
             if (lane == 0 && chunk < total) bitmap[chunk >> 6] = mask;
         }
@@ -327,20 +340,26 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho
                           KTimer *kt) {
     if (d.total == 0) return 0;
     int H = std::max<int32_t>(halo, 1);
-    if (H > AT_MAX_HALO)
+    if (H > 1920)
         throw Error(MJ_ECAPACITY, "radius " + std::to_string(H) + " exceeds the supported 1920");
-    int TP = ((AT_REGION_MAX - 2 * H) / AT_THREADS) * AT_THREADS;
-    if (TP < AT_THREADS) TP = AT_THREADS;
+    // the smaller region (more workgroups per CU) when the halo leaves room for 1024+ positions
+    const int region = (2048 - 2 * H >= 1024) ? 2048 : 4096;
+    int TP = ((region - 2 * H) / AT_THREADS) * AT_THREADS;
     int64_t ntiles = (d.total + TP - 1) / TP;
     int64_t nw = (d.total + 63) / 64;
     uint64_t *bitmap = ws.get_n<uint64_t>(nw + 1);
-    size_t lds = (size_t)(TP + 2 * H) * 8 + (size_t)TP * 2 + (size_t)(TP + 2 * H + p.q + 16);
     uint64_t seed = p.seed + (uint64_t)rho;
     uint64_t salt = mix64(seed + GAMMA);
     if (ntiles > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many tiles");
     int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
-    hipLaunchKernelGGL(k_anchor_tiles, dim3((unsigned)ntiles), dim3(AT_THREADS), lds, s, d.chars,
-                       d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, d.rr, TP, H, bitmap);
+    if (region == 2048)
+        hipLaunchKernelGGL(k_anchor_tiles<2048>, dim3((unsigned)ntiles), dim3(AT_THREADS), 0, s,
+                           d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, d.rr, TP,
+                           H, bitmap);
+    else
+        hipLaunchKernelGGL(k_anchor_tiles<4096>, dim3((unsigned)ntiles), dim3(AT_THREADS), 0, s,
+                           d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, d.rr, TP,
+                           H, bitmap);
     MJ_LAUNCH_CHECK();
     if (kt) kt->end(th, s);
     uint32_t *cnt = ws.get_n<uint32_t>(nw + 1);

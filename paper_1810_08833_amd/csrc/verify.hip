@@ -25,6 +25,7 @@
 #include <algorithm>
 
 #include "mj_common.h"
+#include "verify_common.h"
 
 namespace mj {
 
@@ -39,24 +40,6 @@ int verify_planes(int bits) {
     if (bits <= 4) return 4;
     if (bits <= 6) return 6;
     return 8;
-}
-
-struct VSet {
-    int32_t n;
-    const uint8_t *chars;
-    const int64_t *off;
-    const int32_t *len;
-    const int32_t *kk;
-    const uint32_t *planes;
-    int64_t pw;
-};
-
-__device__ __forceinline__ uint32_t load_word(const uint32_t *plane, int64_t bitpos) {
-    // 32 symbols' bits starting at global bit position bitpos (>= 0)
-    int64_t w = bitpos >> 5;
-    uint32_t sh = (uint32_t)(bitpos & 31);
-    uint32_t lo = plane[w], hi = plane[w + 1];
-    return __builtin_amdgcn_alignbit(hi, lo, sh);
 }
 
 constexpr int BP_MAX_C = 8;  // ceil(K/32) handled by the bit-parallel kernels (K <= 256)
@@ -122,8 +105,12 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
                         rejected = true;
                         break;
                     }
-                    // move the window down one word
-                    S += __popc(Pv[1]) - __popc(Mv[1]);
+                    // move the window down one word; the reference row moves to the bottom
+                    // of word 1 (for a one-word window, the new word's made-up +1 rows)
+                    if constexpr (NW >= 2)
+                        S += __popc(Pv[1]) - __popc(Mv[1]);
+                    else
+                        S += 32;
 #pragma unroll
                     for (int s = 0; s + 1 < NW; s++) {
                         Pv[s] = Pv[s + 1];
@@ -378,9 +365,6 @@ static BpKernel bp_kernel(int c, int np) {
     }
 }
 
-static VSet vset(const DevStrings &d) {
-    return VSet{d.n, d.chars, d.offsets, d.len, d.kk, d.planes, d.plane_words};
-}
 
 int64_t verify_pairs(const uint64_t *pairs, int64_t n, const DevStrings &A, const DevStrings &B,
                      int kmode, uint8_t *flags, Workspace &ws, hipStream_t s,

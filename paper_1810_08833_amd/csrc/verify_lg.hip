@@ -1,0 +1,494 @@
+// Batched verification (Alg. 3; Sec. 3): one persistent launch for all candidates.
+//
+// A pair is owned by a lane group of G lanes; the band window of NW = NWL * G words is
+// split into G contiguous chunks, one per lane.  Per column each lane runs Myers'
+// bit-vector recurrence on its chunk; the two cross-lane dependencies of a column are
+// resolved inside the group: the carry of the multi-word addition with a carry-lookahead
+// scan over the lanes (each lane adds with carry-in 0, reports carry-out and whether its
+// chunk would propagate a carry, then adds its resolved carry-in), and the bits shifted
+// from one chunk into the next.  The window and its one-word moves every 32 columns are
+// those of the per-lane kernel, so the decision ED <= K is the same.
+//
+// Groups take pairs from a queue in order of decreasing length (longest first) and,
+// whenever their pair ends (accepted, rejected early, or out of columns), refill at the
+// next 32-column block boundary, so lanes do not idle behind longer pairs of their wave.
+// The number of lanes per pair G is chosen per (band words, alphabet planes) by timing
+// the candidate configurations once per context.
+#include <string.h>
+
+#include <algorithm>
+
+#include "mj_common.h"
+#include "verify_common.h"
+
+namespace mj {
+
+static unsigned grid_for(int64_t n, int block, unsigned cap = 65535u) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    return (unsigned)std::min<int64_t>(g, cap);
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t gshfl_up(uint32_t v, int d) {
+    return G > 1 ? (uint32_t)__shfl_up((int)v, d, G) : v;
+}
+template <int G>
+__device__ __forceinline__ uint32_t gshfl_down(uint32_t v, int d) {
+    return G > 1 ? (uint32_t)__shfl_down((int)v, d, G) : v;
+}
+template <int G>
+__device__ __forceinline__ int gshfl_xor(int v, int d) {
+    return G > 1 ? __shfl_xor(v, d, G) : v;
+}
+
+template <int NWL, int G, int NP>
+__global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restrict__ pairs,
+                                                        const int64_t *__restrict__ order,
+                                                        int64_t n, VSet A, VSet B, int kmode,
+                                                        uint8_t *__restrict__ flags,
+                                                        unsigned long long *cells,
+                                                        unsigned long long *next) {
+    constexpr int NW = NWL * G;
+    const int lane = threadIdx.x & 63;
+    const int g = lane & (G - 1);
+    const int leader_lane = lane - g;
+    bool active = false, exhausted = false;
+    int64_t pi = 0;
+    int32_t K = 0, mp = 0, nt = 0, wlo = 0, jb = 0, S = 0;
+    int64_t offx = 0, offy = 0, pwx = 0, pwy = 0;
+    const uint32_t *PX = nullptr, *PY = nullptr;
+    uint32_t Pv[NWL], Mv[NWL], V[NWL], PL[NP][NWL];
+    uint64_t my_cells = 0;
+#pragma unroll
+    for (int s = 0; s < NWL; s++) {
+        Pv[s] = Mv[s] = V[s] = 0;
+#pragma unroll
+        for (int p = 0; p < NP; p++) PL[p][s] = 0;
+    }
+    for (;;) {
+        // ---- refill: each group without a pair takes the next one
+        const bool need = !active && !exhausted;
+        const uint64_t req = __ballot(need && g == 0);
+        long long got = -1;
+        if (req) {
+            int first = __ffsll((unsigned long long)req) - 1;
+            unsigned long long base = 0;
+            if (lane == first) base = atomicAdd(next, (unsigned long long)__popcll(req));
+            base = __shfl(base, first, 64);
+            if (need && g == 0) got = (long long)(base + __popcll(req & ((1ull << lane) - 1)));
+        }
+        got = __shfl(got, leader_lane, 64);
+        if (need) {
+            if (got < 0 || got >= n) {
+                exhausted = true;
+            } else {
+                pi = order ? order[got] : got;
+                uint64_t pr = pairs[pi];
+                int32_t ia = (int32_t)(pr >> 32), ib = (int32_t)(uint32_t)pr;
+                int32_t ma = A.len[ia], mb = B.len[ib];
+                K = kmode == 0 ? max(A.kk[ia], B.kk[ib]) : A.kk[ia];
+                bool a_is_x = ma >= mb;
+                PX = a_is_x ? A.planes : B.planes;
+                PY = a_is_x ? B.planes : A.planes;
+                pwx = a_is_x ? A.pw : B.pw;
+                pwy = a_is_x ? B.pw : A.pw;
+                offx = a_is_x ? A.off[ia] : B.off[ib];
+                offy = a_is_x ? B.off[ib] : A.off[ia];
+                mp = a_is_x ? ma : mb;
+                nt = a_is_x ? mb : ma;
+                const int c = (K + 31) >> 5;
+                uint8_t result = 0;
+                bool trivial = true;
+                if (mp - nt > K) {
+                    result = 0;
+                } else if (nt == 0) {
+                    result = mp <= K;
+                } else if (2 * c + 1 > NW) {
+                    result = 2;
+                } else {
+                    trivial = false;
+                }
+                if (trivial) {
+                    if (g == 0) flags[pi] = result;
+                } else {
+                    active = true;
+                    wlo = -c;
+                    jb = 0;
+                    S = c >= 1 ? 32 * (c - 1) : 32;
+#pragma unroll
+                    for (int s = 0; s < NWL; s++) {
+                        int w = wlo + g * NWL + s;
+                        bool real = w >= 0;
+                        Pv[s] = real ? ~0u : 0u;
+                        Mv[s] = real ? 0u : ~0u;
+                        V[s] = real ? ~0u : 0u;
+#pragma unroll
+                        for (int p = 0; p < NP; p++)
+                            PL[p][s] = real ? load_word(PX + p * pwx, offx + 32 * (int64_t)w) : 0u;
+                    }
+                }
+            }
+        }
+        if (__all(!active && exhausted)) break;
+        if (!active) continue;
+
+        // ---- one block of up to 32 columns
+        uint32_t TY[NP];
+#pragma unroll
+        for (int p = 0; p < NP; p++) TY[p] = load_word(PY + p * pwy, offy + jb);
+        const int cols = min(32, nt - jb);
+        for (int t = 0; t < cols; t++) {
+            uint32_t ntm[NP];
+#pragma unroll
+            for (int p = 0; p < NP; p++)
+                ntm[p] = ~(uint32_t)__builtin_amdgcn_sbfe((int)TY[p], (unsigned)t, 1u);
+            uint32_t eqv[NWL], sm[NWL];
+            uint32_t carry = 0, all1 = ~0u;
+#pragma unroll
+            for (int s = 0; s < NWL; s++) {
+                uint32_t eq = V[s];
+#pragma unroll
+                for (int p = 0; p < NP; p++) eq &= PL[p][s] ^ ntm[p];
+                eqv[s] = eq;
+                uint64_t x = (uint64_t)(eq & Pv[s]) + Pv[s] + carry;
+                sm[s] = (uint32_t)x;
+                carry = (uint32_t)(x >> 32);
+                all1 &= sm[s];
+            }
+            if constexpr (G > 1) {
+                // carry-lookahead over the group: (carry-out, propagate) combined low to high
+                uint32_t cc = carry, pp = (all1 == ~0u) ? 1u : 0u;
+#pragma unroll
+                for (int d = 1; d < G; d <<= 1) {
+                    uint32_t clo = gshfl_up<G>(cc, d), plo = gshfl_up<G>(pp, d);
+                    if (g >= d) {
+                        cc = cc | (pp & clo);
+                        pp = pp & plo;
+                    }
+                }
+                uint32_t cin = gshfl_up<G>(cc, 1);
+                if (g == 0) cin = 0;
+#pragma unroll
+                for (int s = 0; s < NWL; s++) {
+                    uint64_t x = (uint64_t)sm[s] + cin;
+                    sm[s] = (uint32_t)x;
+                    cin = (uint32_t)(x >> 32);
+                }
+            }
+            uint32_t ph[NWL], mh[NWL];
+#pragma unroll
+            for (int s = 0; s < NWL; s++) {
+                uint32_t xh = (sm[s] ^ Pv[s]) | eqv[s];
+                ph[s] = Mv[s] | ~(xh | Pv[s]);
+                mh[s] = Pv[s] & xh;
+            }
+            uint32_t phc = 1, mhc = 0;
+            if constexpr (G > 1) {
+                uint32_t tb = (ph[NWL - 1] >> 31) | ((mh[NWL - 1] >> 31) << 1);
+                uint32_t tin = gshfl_up<G>(tb, 1);
+                if (g != 0) {
+                    phc = tin & 1u;
+                    mhc = tin >> 1;
+                }
+            }
+            S += (int)(ph[0] >> 31) - (int)(mh[0] >> 31);  // meaningful in the group's lane 0
+#pragma unroll
+            for (int s = 0; s < NWL; s++) {
+                uint32_t xv = eqv[s] | Mv[s];
+                uint32_t phs = (ph[s] << 1) | phc;
+                phc = ph[s] >> 31;
+                uint32_t mhs = (mh[s] << 1) | mhc;
+                mhc = mh[s] >> 31;
+                Pv[s] = mhs | ~(xv | phs);
+                Mv[s] = phs & xv;
+            }
+        }
+        jb += cols;
+        if (g == 0) my_cells += (uint64_t)cols * (uint64_t)(2 * K + 1);
+        const int S0 = __shfl(S, leader_lane, 64);
+        int dl[NWL];
+        int E = 0;
+#pragma unroll
+        for (int s = 0; s < NWL; s++) {
+            dl[s] = __popc(Pv[s]) - __popc(Mv[s]);
+            if (!(g == 0 && s == 0)) E += dl[s];
+        }
+        if (jb >= nt) {
+            // value at row mp, relative to the reference row 32*wlo + 32 (bottom of slot 0)
+            int rel = mp - (32 * wlo + 32);
+            int part = 0;
+            if (rel >= 0) {
+#pragma unroll
+                for (int s = 0; s < NWL; s++) {
+                    int gs = g * NWL + s;
+                    if (gs >= 1) {
+                        int cnt = min(32, max(0, 32 + rel - 32 * gs));
+                        uint32_t mk = cnt >= 32 ? ~0u : ((1u << cnt) - 1u);
+                        part += __popc(Pv[s] & mk) - __popc(Mv[s] & mk);
+                    }
+                }
+            } else if (g == 0) {
+                uint32_t mk = ~0u << (32 + rel);
+                part = -(__popc(Pv[0] & mk) - __popc(Mv[0] & mk));
+            }
+#pragma unroll
+            for (int d = 1; d < G; d <<= 1) part += gshfl_xor<G>(part, d);
+            if (g == 0) flags[pi] = (S0 + part) <= K;
+            active = false;
+            continue;
+        }
+        // early exit: a lower bound of every window value (word by word, over the group)
+        int incl = E;
+#pragma unroll
+        for (int d = 1; d < G; d <<= 1) {
+            int v = (int)gshfl_up<G>((uint32_t)incl, d);
+            if (g >= d) incl += v;
+        }
+        int Sw = S0 + (incl - E);
+        int lb = 0x3FFFFFFF;
+#pragma unroll
+        for (int s = 0; s < NWL; s++) {
+            if (!(g == 0 && s == 0)) Sw += dl[s];
+            lb = min(lb, Sw - __popc(Pv[s]));
+        }
+#pragma unroll
+        for (int d = 1; d < G; d <<= 1) lb = min(lb, gshfl_xor<G>(lb, d));
+        if (lb > K) {
+            if (g == 0) flags[pi] = 0;
+            active = false;
+            continue;
+        }
+        // move the window down one word: global slot s takes slot s + 1
+        int d1;
+        if constexpr (NW == 1)
+            d1 = 32;
+        else if constexpr (NWL >= 2)
+            d1 = dl[1];
+        else
+            d1 = (int)gshfl_down<G>((uint32_t)dl[0], 1);
+        S += d1;
+        uint32_t inP = gshfl_down<G>(Pv[0], 1), inM = gshfl_down<G>(Mv[0], 1);
+        uint32_t inV = gshfl_down<G>(V[0], 1);
+        uint32_t inL[NP];
+#pragma unroll
+        for (int p = 0; p < NP; p++) inL[p] = gshfl_down<G>(PL[p][0], 1);
+#pragma unroll
+        for (int s = 0; s + 1 < NWL; s++) {
+            Pv[s] = Pv[s + 1];
+            Mv[s] = Mv[s + 1];
+            V[s] = V[s + 1];
+#pragma unroll
+            for (int p = 0; p < NP; p++) PL[p][s] = PL[p][s + 1];
+        }
+        wlo++;
+        if (g == G - 1) {
+            int w = wlo + NW - 1;
+            Pv[NWL - 1] = ~0u;
+            Mv[NWL - 1] = 0u;
+            V[NWL - 1] = ~0u;
+#pragma unroll
+            for (int p = 0; p < NP; p++)
+                PL[p][NWL - 1] = load_word(PX + p * pwx, offx + 32 * (int64_t)w);
+        } else {
+            Pv[NWL - 1] = inP;
+            Mv[NWL - 1] = inM;
+            V[NWL - 1] = inV;
+#pragma unroll
+            for (int p = 0; p < NP; p++) PL[p][NWL - 1] = inL[p];
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint32_t lo = (uint32_t)my_cells, hi = (uint32_t)(my_cells >> 32);
+        lo = __shfl_down(lo, d, 64);
+        hi = __shfl_down(hi, d, 64);
+        my_cells += ((uint64_t)hi << 32) | lo;
+    }
+    if (lane == 0 && my_cells) atomicAdd(cells, (unsigned long long)my_cells);
+}
+
+// ---------------------------------------------------------------- configurations
+using PersistKernel = void (*)(const uint64_t *, const int64_t *, int64_t, VSet, VSet, int,
+                               uint8_t *, unsigned long long *, unsigned long long *);
+
+constexpr int NWL_CHOICES[] = {1, 2, 3, 4, 6, 9};
+constexpr int G_CHOICES[] = {1, 2, 4, 8};
+
+template <int NWL, int G>
+static PersistKernel by_np(int np) {
+    switch (np) {
+        case 2: return k_verify_persist<NWL, G, 2>;
+        case 4: return k_verify_persist<NWL, G, 4>;
+        case 6: return k_verify_persist<NWL, G, 6>;
+        default: return k_verify_persist<NWL, G, 8>;
+    }
+}
+
+template <int G>
+static PersistKernel by_nwl(int nwl, int np) {
+    switch (nwl) {
+        case 1: return by_np<1, G>(np);
+        case 2: return by_np<2, G>(np);
+        case 3: return by_np<3, G>(np);
+        case 4: return by_np<4, G>(np);
+        case 6: return by_np<6, G>(np);
+        default: return by_np<9, G>(np);
+    }
+}
+
+static PersistKernel persist_kernel(int nwl, int g, int np) {
+    switch (g) {
+        case 1: return by_nwl<1>(nwl, np);
+        case 2: return by_nwl<2>(nwl, np);
+        case 4: return by_nwl<4>(nwl, np);
+        default: return by_nwl<8>(nwl, np);
+    }
+}
+
+// smallest supported NWL with NWL * G >= nw, or 0
+static int nwl_for(int nw, int g) {
+    for (int v : NWL_CHOICES)
+        if (v * g >= nw) return v;
+    return 0;
+}
+
+int persist_max_c() { return (9 * 8 - 1) / 2; }
+
+// ---------------------------------------------------------------- longest-first order
+constexpr int LPT_BINS = 4096;
+
+__global__ void k_pair_cmax(const uint64_t *pairs, int64_t n, VSet A, VSet B, int kmode,
+                            uint32_t *cmax, uint32_t *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t m = 0;
+    for (; i < n; i += stride) {
+        uint64_t pr = pairs[i];
+        uint32_t ua = (uint32_t)(pr >> 32), ub = (uint32_t)pr;
+        if (ua >= (uint32_t)A.n || ub >= (uint32_t)B.n) {
+            atomicOr(bad, 1u);
+            continue;
+        }
+        int32_t K = kmode == 0 ? max(A.kk[ua], B.kk[ub]) : A.kk[ua];
+        m = max(m, (uint32_t)((K + 31) >> 5));
+    }
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(cmax, m);
+}
+
+__device__ __forceinline__ int lpt_bin(const uint64_t pr, const VSet &A, const VSet &B) {
+    int32_t nt = min(A.len[(uint32_t)(pr >> 32)], B.len[(uint32_t)pr]);
+    return LPT_BINS - 1 - min(nt >> 4, LPT_BINS - 1);  // longest first
+}
+
+__global__ void k_lpt_hist(const uint64_t *pairs, int64_t n, VSet A, VSet B, uint32_t *cnt) {
+    __shared__ uint32_t h[LPT_BINS];
+    for (int t = threadIdx.x; t < LPT_BINS; t += blockDim.x) h[t] = 0;
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) atomicAdd(&h[lpt_bin(pairs[i], A, B)], 1u);
+    __syncthreads();
+    for (int t = threadIdx.x; t < LPT_BINS; t += blockDim.x)
+        if (h[t]) atomicAdd(&cnt[t], h[t]);
+}
+
+__global__ void k_lpt_scatter(const uint64_t *pairs, int64_t n, VSet A, VSet B,
+                              const uint32_t *off, uint32_t *fill, int64_t *order) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) {
+        int b = lpt_bin(pairs[i], A, B);
+        order[off[b] + atomicAdd(&fill[b], 1u)] = i;
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+static void launch_persist(int nwl, int g, int np, const uint64_t *pairs, const int64_t *order,
+                           int64_t n, const VSet &va, const VSet &vb, int kmode, uint8_t *flags,
+                           unsigned long long *cells, unsigned long long *next, hipStream_t s) {
+    fill_u64((uint64_t *)next, 0, 1, s);
+    // enough groups to keep every SIMD busy, but no more than the pairs need
+    int64_t groups_per_block = 256 / g;
+    int64_t blocks = (n + groups_per_block - 1) / groups_per_block;
+    blocks = std::min<int64_t>(blocks, 256 * 8);
+    hipLaunchKernelGGL(persist_kernel(nwl, g, np), dim3((unsigned)std::max<int64_t>(blocks, 1)),
+                       dim3(256), 0, s, pairs, order, n, va, vb, kmode, flags, cells, next);
+    MJ_LAUNCH_CHECK();
+}
+
+int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings &A,
+                             const DevStrings &B, int kmode, uint8_t *flags, Workspace &ws,
+                             hipStream_t s, uint64_t *host_scratch, KTimer *kt,
+                             VerifyTuning *tune) {
+    if (n <= 0) return 0;
+    if (A.planes == nullptr || B.planes == nullptr) throw Error(MJ_EINVAL, "strings not packed");
+    const int np = verify_planes(std::max(A.bits, B.bits));
+    VSet va = vset(A), vb = vset(B);
+    unsigned long long *cells = (unsigned long long *)ws.get_n<uint64_t>(2);
+    unsigned long long *next = (unsigned long long *)ws.get_n<uint64_t>(2);
+    uint32_t *cm = ws.get_n<uint32_t>(4);
+    fill_u64((uint64_t *)cells, 0, 1, s);
+    fill_u32(cm, 0, 2, s);
+    hipLaunchKernelGGL(k_pair_cmax, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, pairs, n, va, vb,
+                       kmode, cm, cm + 1);
+    MJ_LAUNCH_CHECK();
+    // longest pairs first
+    uint32_t *cnt = ws.get_n<uint32_t>(LPT_BINS + 1);
+    uint32_t *off = ws.get_n<uint32_t>(LPT_BINS + 1);
+    uint32_t *fillc = ws.get_n<uint32_t>(LPT_BINS + 1);
+    int64_t *order = ws.get_n<int64_t>(n);
+    MJ_HIP(hipMemcpyAsync(host_scratch, cm, 8, hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipStreamSynchronize(s));
+    uint32_t hv[2];
+    memcpy(hv, host_scratch, 8);
+    if (hv[1]) throw Error(MJ_EINVAL, "pair names a string id out of range");
+    const int cmax = (int)hv[0];
+    if (cmax > persist_max_c())
+        throw Error(MJ_ECAPACITY, "threshold K above the batched verifier's band limit (K <= 1120)");
+    fill_u32(cnt, 0, LPT_BINS, s);
+    fill_u32(fillc, 0, LPT_BINS, s);
+    hipLaunchKernelGGL(k_lpt_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, pairs, n, va, vb, cnt);
+    MJ_LAUNCH_CHECK();
+    exclusive_scan_u32(cnt, off, LPT_BINS, ws, s);
+    hipLaunchKernelGGL(k_lpt_scatter, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, pairs, n, va,
+                       vb, off, fillc, order);
+    MJ_LAUNCH_CHECK();
+
+    const int nw = 2 * cmax + 1;
+    const int npi = np / 2 - 1;
+    int best_g = tune ? tune->best_g[std::min(cmax, 63)][npi] : 0;
+    if (best_g == 0) {
+        // time each lane-group width once on this call's pairs; keep the fastest
+        hipEvent_t e0, e1;
+        MJ_HIP(hipEventCreate(&e0));
+        MJ_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        for (int g : G_CHOICES) {
+            int nwl = nwl_for(nw, g);
+            if (nwl == 0) continue;
+            MJ_HIP(hipEventRecord(e0, s));
+            launch_persist(nwl, g, np, pairs, order, n, va, vb, kmode, flags, cells, next, s);
+            MJ_HIP(hipEventRecord(e1, s));
+            MJ_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            MJ_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_g = g;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (tune && n >= 4096) tune->best_g[std::min(cmax, 63)][npi] = best_g;
+        fill_u64((uint64_t *)cells, 0, 1, s);
+    }
+    int th = kt ? kt->begin(KTimer::VERIFY, s) : -1;
+    launch_persist(nwl_for(nw, best_g), best_g, np, pairs, order, n, va, vb, kmode, flags, cells,
+                   next, s);
+    if (kt) kt->end(th, s);
+    if (tune) tune->last_g = best_g, tune->last_nwl = nwl_for(nw, best_g);
+    return (int64_t)read_back<uint64_t>((const uint64_t *)cells, s, host_scratch);
+}
+
+}  // namespace mj

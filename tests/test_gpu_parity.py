@@ -126,6 +126,9 @@ def test_candidates_and_output_identical(mj, name):
     out_g, st = mj.join(ds, gp)
     assert np.array_equal(out_g, out_w)
     assert st["candidates"] == len(cand_w) and st["output"] == len(out_w)
+    gp.verifier = mj.VERIFY_PLAIN
+    out_p, _ = mj.join(ds, gp)
+    assert np.array_equal(out_p, out_w)
 
 
 def test_empty_and_degenerate_collections(mj):
@@ -161,20 +164,23 @@ def near_threshold_pairs(rng, K, count, sigma=4):
     return dg.from_list(strs, sigma), np.array(pairs, dtype=np.uint64)
 
 
+@pytest.mark.parametrize("verifier", ["batched", "plain"])
 @pytest.mark.parametrize("K", [0, 1, 7, 31, 32, 33, 60, 150, 255, 256, 257, 400])
-def test_verify_matches_banded_oracle(mj, K):
-    say("verify K=%d" % K)
+def test_verify_matches_banded_oracle(mj, K, verifier):
+    say("verify K=%d %s" % (K, verifier))
     rng = np.random.default_rng(1000 + K)
     S, pairs = near_threshold_pairs(rng, K, 120 if K < 300 else 40)
-    got = mj.verify(dev(mj, S), mj.Params(q=4, k=K, t_div=1), pairs)
+    v = mj.VERIFY_BATCHED if verifier == "batched" else mj.VERIFY_PLAIN
+    got = mj.verify(dev(mj, S), mj.Params(q=4, k=K, t_div=1, verifier=v), pairs)
     want = oracle.verify_list(S.chars, S.offsets, oracle.make_params(4, 4, k=K), pairs)
     assert np.array_equal(got, want)
     assert 0 < want.sum() < len(want)
 
 
-def test_verify_per_pair_thresholds_across_bins(mj):
+@pytest.mark.parametrize("verifier", ["batched", "plain"])
+def test_verify_per_pair_thresholds_across_bins(mj, verifier):
     import torch
-    say("verify mixed K bins")
+    say("verify mixed K bins", verifier)
     rng = np.random.default_rng(77)
     strs, pairs, ks = [], [], []
     for t in range(300):
@@ -189,7 +195,9 @@ def test_verify_per_pair_thresholds_across_bins(mj):
     S = dg.from_list(strs, 25)
     kq = np.array(ks, dtype=np.int32)
     pairs = np.array(pairs, dtype=np.uint64)
-    got = mj.verify(dev(mj, S), mj.Params(q=3, k_per_string=torch.from_numpy(kq).cuda()), pairs)
+    v = mj.VERIFY_BATCHED if verifier == "batched" else mj.VERIFY_PLAIN
+    got = mj.verify(dev(mj, S), mj.Params(q=3, k_per_string=torch.from_numpy(kq).cuda(), verifier=v),
+                    pairs)
     want = oracle.verify_list(S.chars, S.offsets, oracle.make_params(3, 25, k_per_string=kq), pairs)
     assert np.array_equal(got, want)
 
@@ -239,6 +247,9 @@ def test_dna_long_workload_sampled(mj):
     cand_g, _ = mj.candidates(ds, gp)
     assert np.array_equal(cand_g, cand_w)
     out_g, st = mj.join(ds, gp)
+    gp.verifier = mj.VERIFY_PLAIN
+    out_p, _ = mj.join(ds, gp)
+    assert np.array_equal(out_p, out_g)  # batched and plain verifiers agree at full size
     rng = np.random.default_rng(0)
     sample = np.sort(rng.choice(len(cand_w), size=min(1500, len(cand_w)), replace=False))
     flags = oracle.verify_list(S.chars, S.offsets, op, cand_w[sample])
@@ -253,3 +264,49 @@ def test_dna_long_workload_sampled(mj):
     got = got[sel]
     got["sid"] = np.searchsorted(ids, got["sid"])
     assert_records_equal(got, want)
+
+
+# ---------------------------------------------------------------- serving
+def test_server_answers_equal_alone_and_in_the_mix(mj):
+    """Continuous batching: each request's answer in the mix equals its answer alone
+    (and the oracle's), while batches of several requests and several workers run."""
+    import torch
+    say("server")
+    rng = np.random.default_rng(90)
+    I = dg.random_strings(91, 300, 300, 1500)
+    Ikq = dg.k_fraction(I.lengths(), 1, 10)
+    index = mj.Index(dev(mj, I), mj.Params(q=4, k_per_string=torch.from_numpy(Ikq).cuda(), t_div=1))
+    queries = []
+    for t in range(120):
+        if t % 2 == 0:
+            src = I.get(int(rng.integers(0, I.n)))
+            queries.append(dg.mutate(rng, src, rng.uniform(0.01, 0.12), 4))
+        else:
+            queries.append(rng.integers(0, 4, int(rng.integers(1, 1500))).astype(np.uint8))
+    ks = [int(v) for v in dg.k_fraction([len(q) for q in queries], 1, 10)]
+    alone = []
+    for q, k in zip(queries, ks):
+        Q = dg.from_list([q], 4)
+        got, _ = index.search(dev(mj, Q), k=k)
+        alone.append(np.sort((got & np.uint64(0xFFFFFFFF)).astype(np.uint32)))
+    Q = dg.from_list(queries, 4)
+    _, want = oracle.search(I.chars, I.offsets, oracle.make_params(4, 4, k_per_string=Ikq, t_div=1),
+                            Q.chars, Q.offsets, oracle.make_params(4, 4, k_per_string=np.array(ks, np.int32), t_div=1))
+    srv = mj.Server(index, workers=3, max_batch=16, memory_budget=1 << 26)
+    for t, (q, k) in enumerate(zip(queries, ks)):
+        srv.submit(q, k, t)
+    replies = []
+    while len(replies) < len(queries):
+        replies += srv.poll(timeout_ms=10000)
+    srv.close()
+    by_tag = {r["tag"]: r for r in replies}
+    assert sorted(by_tag) == list(range(len(queries)))
+    for t in range(len(queries)):
+        r = by_tag[t]
+        assert r["status"] == 0
+        assert np.array_equal(r["ids"], alone[t])
+        ref = np.sort((want[(want >> np.uint64(32)) == t] & np.uint64(0xFFFFFFFF)).astype(np.uint32))
+        assert np.array_equal(r["ids"], ref)
+    assert max(r["batch_size"] for r in replies) > 1
+    assert sum(len(a) for a in alone) > 0
+    index.close()
