@@ -199,7 +199,8 @@ int verify_planes(int bits);   // planes the verifier needs for b bits per symbo
 // The lane-group width is timed once per (ceil(Kmax/32), planes) and kept in `tune`.
 struct VerifyTuning {
     int best_g[64][4] = {};
-    int last_g = 0, last_nwl = 0;
+    int best_blocks[64][4] = {};
+    int last_g = 0, last_nwl = 0, last_blocks = 0;
 };
 int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings &A,
                              const DevStrings &B, int kmode, uint8_t *flags, Workspace &ws,

@@ -80,18 +80,41 @@ int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, 
 
 // ---------------------------------------------------------------- bit planes
 // planes[p][w] bit t = bit p of the symbol at global position 32w + t (0 past the end).
+// With 16-byte aligned symbols a thread reads its 32 symbols as two 16-byte loads.
+__device__ __forceinline__ void pack_bytes(uint32_t word, int t0, uint32_t acc[8]) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        uint32_t c = (word >> (8 * k)) & 0xFFu;
+#pragma unroll
+        for (int p = 0; p < 8; p++) acc[p] |= ((c >> p) & 1u) << (t0 + k);
+    }
+}
+
 __global__ void k_pack_planes(const uint8_t *chars, int64_t total, uint32_t *planes,
-                              int64_t plane_words, int np) {
+                              int64_t plane_words, int np, int aligned) {
     int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; w < plane_words; w += stride) {
         uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         int64_t base = w * 32;
-        for (int t = 0; t < 32; t++) {
-            int64_t g = base + t;
-            uint32_t c = g < total ? chars[g] : 0u;
+        if (aligned && base + 32 <= total) {
+            const uint4 *v = reinterpret_cast<const uint4 *>(chars + base);
+            uint4 a = v[0], b = v[1];
+            pack_bytes(a.x, 0, acc);
+            pack_bytes(a.y, 4, acc);
+            pack_bytes(a.z, 8, acc);
+            pack_bytes(a.w, 12, acc);
+            pack_bytes(b.x, 16, acc);
+            pack_bytes(b.y, 20, acc);
+            pack_bytes(b.z, 24, acc);
+            pack_bytes(b.w, 28, acc);
+        } else {
+            for (int t = 0; t < 32; t++) {
+                int64_t g = base + t;
+                uint32_t c = g < total ? chars[g] : 0u;
 #pragma unroll
-            for (int p = 0; p < 8; p++) acc[p] |= ((c >> p) & 1u) << t;
+                for (int p = 0; p < 8; p++) acc[p] |= ((c >> p) & 1u) << t;
+            }
         }
         for (int p = 0; p < np; p++) planes[(int64_t)p * plane_words + w] = acc[p];
     }
@@ -100,168 +123,275 @@ __global__ void k_pack_planes(const uint8_t *chars, int64_t total, uint32_t *pla
 void pack_planes(DevStrings &d, int np, Workspace &ws, hipStream_t s) {
     d.plane_words = (d.total + 31) / 32 + 96;  // padding: windows may read past the end
     d.planes = ws.get_n<uint32_t>((size_t)np * d.plane_words);
+    int aligned = ((uintptr_t)d.chars & 15) == 0 ? 1 : 0;
     hipLaunchKernelGGL(k_pack_planes, dim3(grid_for(d.plane_words, 256, 16384)), dim3(256), 0, s,
-                       d.chars, d.total, d.planes, d.plane_words, np);
+                       d.chars, d.total, d.planes, d.plane_words, np, aligned);
     MJ_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------- anchors
 // One workgroup handles a tile of TP positions of the concatenated strings plus a halo
 // of H positions on each side (H >= every radius used).  It hashes every q-gram of the
-// region into LDS, then finds strict minima with a sparse table built by doubling in two
-// LDS buffers: after level k, the current buffer holds min h[a .. a + 2^k - 1] at a.  A
-// position p of radius r is tested at level k = floor(log2 r): the left window
-// [p-r, p-1] is min(cur[p-r], cur[p-2^k]) and the right window [p+1, p+r] is
-// min(cur[p+1], cur[p+1+r-2^k]).  String boundaries inside the region come from an LDS
-// copy of the offsets of the strings it overlaps.  Anchors and string starts are written
-// as one bit per position.
+// region into LDS; string boundaries come from an LDS copy of the offsets of the strings
+// the region overlaps.  A position p is an anchor when h[p] is strictly smaller than
+// every other value in [p-r, p+r].  Two exact tests:
+//  * block test (every interior radius of the tile >= 15): a 16-position aligned block
+//    lies inside the window of each of its positions, so an anchor is the unique minimum
+//    of its block; only those candidates are checked against the rest of their window,
+//    whole blocks through their minima and the two partial blocks element by element;
+//  * sparse table (otherwise): doubling in two LDS buffers, after level k the current
+//    buffer holds min h[a .. a + 2^k - 1] at a; p is tested at level k = floor(log2 r):
+//    left window min(cur[p-r], cur[p-2^k]), right window min(cur[p+1], cur[p+1+r-2^k]).
+// Anchors and string starts are written as one bit per position.
 constexpr int AT_THREADS = 256;
-constexpr int AT_STR_MAX = 512;  // strings of one region held in LDS (else global search)
+constexpr int AT_BLOCK = 16;
+
+// DPP moves inside rows of 16 lanes; a lane whose source is outside its row keeps `old`.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_or(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+// One step of an inclusive scan over a row of 16 lanes: combine with the lane D below
+// (prefix) or D above (suffix).  (v, arg, uniq): minimum, its index, and whether it is
+// attained once; the sentinel ~0 (never a stored hash of a tested position) is the
+// identity for lanes without a partner.
+template <int D>
+__device__ __forceinline__ void prefix_step(uint64_t &v, int &arg, int &uniq) {
+    constexpr int C = 0x110 + D;  // row_shr:D
+    uint32_t lo = dpp_or<C>(0xFFFFFFFFu, (uint32_t)v), hi = dpp_or<C>(0xFFFFFFFFu, (uint32_t)(v >> 32));
+    int oa = (int)dpp_or<C>(0xFFFFFFFFu, (uint32_t)arg);
+    int ou = (int)dpp_or<C>(1u, (uint32_t)uniq);
+    uint64_t ov = ((uint64_t)hi << 32) | lo;
+    if (ov < v) {
+        v = ov;
+        arg = oa;
+        uniq = ou;
+    } else if (ov == v) {
+        uniq = 0;
+    }
+}
+template <int D>
+__device__ __forceinline__ void suffix_step(uint64_t &v) {
+    constexpr int C = 0x100 + D;  // row_shl:D
+    uint32_t lo = dpp_or<C>(0xFFFFFFFFu, (uint32_t)v), hi = dpp_or<C>(0xFFFFFFFFu, (uint32_t)(v >> 32));
+    uint64_t ov = ((uint64_t)hi << 32) | lo;
+    v = ov < v ? ov : v;
+}
+
+// Per-tile descriptor: the strings overlapping the tile's region (first id, count), and
+// for up to TD_STR of them their offsets and radii, so that the anchor kernel reads all
+// it needs about string boundaries in one coalesced load.  One thread per tile: the
+// binary searches' latency overlaps across tiles.
+constexpr int TD_STR = 8;
+struct TileDesc {
+    int32_t s0, ns;             // ns = -1: more than TD_STR strings (search per position)
+    int64_t off[TD_STR + 1];
+    int32_t r[TD_STR];
+    int32_t pad[4];             // 128 bytes
+};
+static_assert(sizeof(TileDesc) == 128, "tile descriptor size");
+
+__global__ void k_tile_desc(const int64_t *__restrict__ off, const int32_t *__restrict__ rr,
+                            int32_t n, int64_t total, int64_t ntiles, int TP, int H,
+                            TileDesc *__restrict__ td) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const int NR = TP + 2 * H;
+    int64_t base = t * TP - H;
+    int64_t g0 = base < 0 ? 0 : base;
+    int64_t g1 = min(base + NR, total) - 1;
+    int32_t s0 = g0 < total ? owner_of(off, n, g0) : n;
+    int32_t s1 = g1 >= g0 ? owner_of(off, n, g1) : s0;
+    TileDesc d;
+    d.s0 = s0;
+    d.ns = (s1 - s0 + 1 <= TD_STR) ? (s1 - s0 + 1) : -1;
+    for (int k = 0; k <= TD_STR; k++) d.off[k] = (d.ns >= 0 && k <= d.ns) ? off[s0 + k] : 0;
+    for (int k = 0; k < TD_STR; k++) d.r[k] = (d.ns >= 0 && k < d.ns) ? rr[s0 + k] : 0;
+    for (int k = 0; k < 4; k++) d.pad[k] = 0;
+    td[t] = d;
+}
 
 template <int REGION>
 __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     const uint8_t *__restrict__ chars, const int64_t *__restrict__ off, int32_t n, int64_t total,
     int q, int bits, uint64_t salt, const uint64_t *__restrict__ table,
-    const int32_t *__restrict__ rr, int TP, int H, uint64_t *__restrict__ bitmap) {
-    constexpr int RUN = REGION / AT_THREADS;  // region positions per thread (max)
+    const int32_t *__restrict__ rr, int TP, int H, const TileDesc *__restrict__ tdesc,
+    uint64_t *__restrict__ bitmap) {
     __shared__ uint64_t bufA[REGION];
     __shared__ uint64_t bufB[REGION];
     __shared__ uint16_t pinfo[REGION];
     __shared__ uint8_t ch[REGION + 64];
-    __shared__ int64_t soff[AT_STR_MAX + 1];
-    __shared__ int32_t s0_s, ns_s, kmax_s;
+    __shared__ uint32_t aflag[REGION / 32];
+    __shared__ TileDesc td;
+    __shared__ int16_t barg[REGION / AT_BLOCK];
+    __shared__ uint64_t bmin[REGION / AT_BLOCK];
+    __shared__ int32_t kmax_s, rmin_s;
     const int NR = TP + 2 * H;
     const int tid = threadIdx.x;
     const int64_t tile_start = (int64_t)blockIdx.x * TP;
     const int64_t base = tile_start - H;
     if (tid == 0) {
         kmax_s = 0;
-        int64_t g0 = base < 0 ? 0 : base;
-        int64_t g1 = min(base + NR, total) - 1;
-        int32_t s0 = g0 < total ? owner_of(off, n, g0) : n;
-        int32_t s1 = g1 >= g0 ? owner_of(off, n, g1) : s0;
-        s0_s = s0;
-        ns_s = (s1 - s0 + 1 <= AT_STR_MAX) ? (s1 - s0 + 1) : -1;
+        rmin_s = 0x7FFFFFFF;
     }
+    if (tid < 32) reinterpret_cast<uint32_t *>(&td)[tid] = reinterpret_cast<const uint32_t *>(tdesc + blockIdx.x)[tid];
     for (int idx = tid; idx < NR + q; idx += AT_THREADS) {
         int64_t g = base + idx;
         ch[idx] = (g >= 0 && g < total) ? chars[g] : (uint8_t)0;
     }
+    for (int w = tid; w < REGION / 32; w += AT_THREADS) aflag[w] = 0;
     __syncthreads();
-    const int32_t s0 = s0_s, ns = ns_s;
-    if (ns > 0)
-        for (int t = tid; t <= ns; t += AT_THREADS) soff[t] = off[s0 + t];
-    __syncthreads();
+    const int32_t s0 = td.s0, ns = td.ns;
     const uint64_t gmask = (q * bits >= 64) ? ~0ull : ((1ull << (q * bits)) - 1);
-    // hashes: each thread walks a contiguous run, rolling the packed q-gram code
+    // hashes: one position per thread at a time (consecutive threads, consecutive positions)
     {
-        const int RL = (NR + AT_THREADS - 1) / AT_THREADS;
-        int run0 = tid * RL, run1 = min(NR, run0 + RL);
-        int32_t sidx = -1;
-        int64_t sbeg = 0, send = 0;
-        bool have = false;
-        uint64_t G = 0;
-        int lmax = 0;
-        for (int idx = run0; idx < run1; idx++) {
+        int lmax = 0, lrmin = 0x7FFFFFFF;
+        for (int idx = tid; idx < NR; idx += AT_THREADS) {
             int64_t g = base + idx;
             uint64_t h = ~0ull;
             uint16_t info = 0;
-            if (g >= 0 && g < total) {
-                if (sidx < 0) {
-                    if (ns > 0) {  // largest t with soff[t] <= g
-                        int lo = 0, hi = ns;
-                        while (hi - lo > 1) {
-                            int mid = (lo + hi) >> 1;
-                            if (soff[mid] <= g) lo = mid; else hi = mid;
-                        }
-                        sidx = s0 + lo;
-                        sbeg = soff[lo];
-                        send = soff[lo + 1];
-                    } else {
-                        sidx = owner_of(off, n, g);
-                        sbeg = off[sidx];
-                        send = off[sidx + 1];
-                    }
+            int32_t r = 0;
+            int64_t sbeg = 0, send = 0;
+            bool valid;
+            if (ns >= 0) {
+                // the string holding g: a short scan over the tile's strings (uniform trip count)
+                valid = g >= 0 && g < total;
+                int t = 0;
+                for (int k = 1; k < ns; k++) t += (td.off[k] <= g) ? 1 : 0;
+                sbeg = td.off[t];
+                send = td.off[t + 1];
+                r = td.r[t];
+            } else {
+                valid = g >= 0 && g < total;
+                if (valid) {
+                    int32_t sidx = owner_of(off, n, g);
+                    sbeg = off[sidx];
+                    send = off[sidx + 1];
+                    r = rr[sidx];
                 }
-                while (g >= send) {
-                    sidx++;
-                    sbeg = send;
-                    send = (ns > 0) ? soff[sidx - s0 + 1] : off[sidx + 1];
-                    have = false;
-                }
+            }
+            if (valid) {
                 int64_t i = g - sbeg;
                 int64_t npos = (send - sbeg) - q + 1;
                 if (i < npos) {
-                    if (have) {
-                        G = ((G << bits) | ch[idx + q - 1]) & gmask;
-                    } else {
-                        G = 0;
-                        for (int k = 0; k < q; k++) G = (G << bits) | ch[idx + k];
-                        G &= gmask;
-                    }
-                    have = true;
+                    uint64_t G = 0;
+                    for (int k = 0; k < q; k++) G = (G << bits) | ch[idx + k];
+                    G &= gmask;
                     h = table ? table[G] : mix64(G ^ salt);
-                } else {
-                    have = false;
                 }
-                if (idx >= H && idx < H + TP) {
-                    int32_t r = rr[sidx];
-                    bool interior = (i >= r) && (i <= npos - 1 - r);
-                    info = (uint16_t)((interior ? r : 0) | (i == 0 ? 0x8000 : 0));
-                    if (interior) lmax = max(lmax, 31 - __clz(r));
+                bool interior = (i >= r) && (i <= npos - 1 - r);
+                info = (uint16_t)((interior ? r : 0) | (i == 0 ? 0x8000 : 0));
+                if (interior && idx >= H && idx < H + TP) {
+                    lmax = max(lmax, 31 - __clz(r));
+                    lrmin = min(lrmin, r);
                 }
             }
             bufA[idx] = h;
             pinfo[idx] = info;
         }
-        (void)RUN;
         if (lmax > 0) atomicMax(&kmax_s, lmax);
+        if (lrmin < 0x7FFFFFFF) atomicMin(&rmin_s, lrmin);
     }
     __syncthreads();
     const int NC = TP / AT_THREADS;
     constexpr int OWN = REGION / AT_THREADS;
-    uint64_t hp[OWN];
-    uint16_t inf[OWN];
-    uint32_t anc = 0;
-#pragma unroll
-    for (int c = 0; c < OWN; c++) {
-        int p = tid + AT_THREADS * c;
-        hp[c] = c < NC ? bufA[H + p] : 0;
-        inf[c] = c < NC ? pinfo[H + p] : 0;
-    }
-    const int kmax = kmax_s;
-    uint64_t *cur = bufA, *nxt = bufB;
-    for (int k = 0; k <= kmax; k++) {
-        const int w = 1 << k;
-#pragma unroll
-        for (int c = 0; c < OWN; c++) {
-            int r = inf[c] & 0x7FFF;
-            if (c < NC && r != 0 && (31 - __clz(r)) == k) {
-                int idx = H + tid + AT_THREADS * c;
-                uint64_t L = min(cur[idx - r], cur[idx - w]);
-                uint64_t R = min(cur[idx + 1], cur[idx + 1 + r - w]);
-                if (hp[c] < L && hp[c] < R) anc |= 1u << c;
+    if (rmin_s >= AT_BLOCK - 1) {
+        // ---- block test: bufA <- suffix minima, bufB <- prefix minima (within blocks)
+        for (int j0 = 0; j0 < NR; j0 += AT_THREADS) {  // uniform trip count for the DPP scans
+            const int idx = j0 + tid;
+            uint64_t v = idx < NR ? bufA[idx] : ~0ull;
+            uint64_t sv = v;
+            int arg = idx, uniq = 1;
+            prefix_step<1>(v, arg, uniq);
+            prefix_step<2>(v, arg, uniq);
+            prefix_step<4>(v, arg, uniq);
+            prefix_step<8>(v, arg, uniq);
+            suffix_step<1>(sv);
+            suffix_step<2>(sv);
+            suffix_step<4>(sv);
+            suffix_step<8>(sv);
+            if (idx < NR) {
+                bufB[idx] = v;
+                bufA[idx] = sv;
+            }
+            if ((tid & (AT_BLOCK - 1)) == AT_BLOCK - 1 && idx - (AT_BLOCK - 1) < NR) {
+                const int bk = idx / AT_BLOCK;
+                bmin[bk] = v;
+                barg[bk] = (int16_t)(uniq ? arg : -1);
             }
         }
-        if (k == kmax) break;
-        for (int a = tid; a < NR; a += AT_THREADS) {
-            uint64_t v = cur[a];
-            if (a + w < NR) v = min(v, cur[a + w]);
-            nxt[a] = v;
+        __syncthreads();
+        const int NBK = (NR + AT_BLOCK - 1) / AT_BLOCK;
+        for (int bk = tid; bk < NBK; bk += AT_THREADS) {
+            const int p = barg[bk];
+            if (p < H || p >= H + TP) continue;  // no unique minimum, or not a tile position
+            const int r = pinfo[p] & 0x7FFF;
+            if (r == 0) continue;  // not an interior position
+            const uint64_t hv = bmin[bk];
+            bool ok = true;
+            const int L = p - r, lb = L / AT_BLOCK;
+            if (lb < bk) {
+                ok = hv < bufA[L];
+                for (int b2 = lb + 1; ok && b2 < bk; b2++) ok = hv < bmin[b2];
+            }
+            const int R = p + r, rb = R / AT_BLOCK;
+            if (ok && rb > bk) {
+                for (int b2 = bk + 1; ok && b2 < rb; b2++) ok = hv < bmin[b2];
+                if (ok) ok = hv < bufB[R];
+            }
+            if (ok) atomicOr(&aflag[(p - H) >> 5], 1u << ((p - H) & 31));
         }
         __syncthreads();
-        uint64_t *t = cur;
-        cur = nxt;
-        nxt = t;
+    } else {
+        // ---- sparse table
+        const int kmax = kmax_s;
+        uint64_t hp[OWN];
+        uint16_t inf[OWN];
+#pragma unroll
+        for (int c = 0; c < OWN; c++) {
+            int p = tid + AT_THREADS * c;
+            hp[c] = c < NC ? bufA[H + p] : 0;
+            inf[c] = c < NC ? pinfo[H + p] : 0;
+        }
+        uint64_t *cur = bufA, *nxt = bufB;
+        for (int k = 0; k <= kmax; k++) {
+            const int w = 1 << k;
+#pragma unroll
+            for (int c = 0; c < OWN; c++) {
+                int r = inf[c] & 0x7FFF;
+                if (c < NC && r != 0 && (31 - __clz(r)) == k) {
+                    int idx = H + tid + AT_THREADS * c;
+                    uint64_t L = min(cur[idx - r], cur[idx - w]);
+                    uint64_t R = min(cur[idx + 1], cur[idx + 1 + r - w]);
+                    if (hp[c] < L && hp[c] < R) {
+                        int pp = tid + AT_THREADS * c;
+                        atomicOr(&aflag[pp >> 5], 1u << (pp & 31));
+                    }
+                }
+            }
+            if (k == kmax) break;
+            for (int a = tid; a < NR; a += AT_THREADS) {
+                uint64_t v = cur[a];
+                if (a + w < NR) v = min(v, cur[a + w]);
+                nxt[a] = v;
+            }
+            __syncthreads();
+            uint64_t *t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        __syncthreads();
     }
     // one bit per position: string start or anchor
     const int lane = tid & 63, wid = tid >> 6;
 #pragma unroll
     for (int c = 0; c < OWN; c++) {
         if (c < NC) {
+            int p = AT_THREADS * c + 64 * wid + lane;
             int64_t chunk = tile_start + (int64_t)AT_THREADS * c + 64 * wid;
             int64_t g = chunk + lane;
-            bool flag = g < total && (((inf[c] & 0x8000) != 0) || ((anc >> c) & 1u));
+            bool flag = g < total && (((pinfo[H + p] & 0x8000) != 0) || ((aflag[p >> 5] >> (p & 31)) & 1u));
             uint64_t mask = __ballot(flag);
             if (lane == 0 && chunk < total) bitmap[chunk >> 6] = mask;
         }
@@ -352,14 +482,18 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho
     uint64_t salt = mix64(seed + GAMMA);
     if (ntiles > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many tiles");
     int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
+    TileDesc *ts = ws.get_n<TileDesc>(ntiles + 1);
+    hipLaunchKernelGGL(k_tile_desc, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s,
+                       d.offsets, d.rr, d.n, d.total, ntiles, TP, H, ts);
+    MJ_LAUNCH_CHECK();
     if (region == 2048)
         hipLaunchKernelGGL(k_anchor_tiles<2048>, dim3((unsigned)ntiles), dim3(AT_THREADS), 0, s,
                            d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, d.rr, TP,
-                           H, bitmap);
+                           H, ts, bitmap);
     else
         hipLaunchKernelGGL(k_anchor_tiles<4096>, dim3((unsigned)ntiles), dim3(AT_THREADS), 0, s,
                            d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, d.rr, TP,
-                           H, bitmap);
+                           H, ts, bitmap);
     MJ_LAUNCH_CHECK();
     if (kt) kt->end(th, s);
     uint32_t *cnt = ws.get_n<uint32_t>(nw + 1);

@@ -29,13 +29,29 @@ static unsigned grid_for(int64_t n, int block, unsigned cap = 65535u) {
     return (unsigned)std::min<int64_t>(g, cap);
 }
 
+// Moves inside a lane group.  Groups of G <= 16 lanes are aligned inside DPP rows of 16
+// lanes, so a row shift by d brings lane g the value of lane g - d of its own group for
+// every g >= d (the others read 0 and are not used); these run on the VALU, not LDS.
+template <int D>
+__device__ __forceinline__ uint32_t row_shr(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + D, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t row_shl1(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x101, 0xF, 0xF, true);
+}
+template <int G, int D>
+__device__ __forceinline__ uint32_t gshfl_up_c(uint32_t v) {
+    if constexpr (G == 1) return v;
+    else return row_shr<D>(v);
+}
 template <int G>
 __device__ __forceinline__ uint32_t gshfl_up(uint32_t v, int d) {
     return G > 1 ? (uint32_t)__shfl_up((int)v, d, G) : v;
 }
 template <int G>
-__device__ __forceinline__ uint32_t gshfl_down(uint32_t v, int d) {
-    return G > 1 ? (uint32_t)__shfl_down((int)v, d, G) : v;
+__device__ __forceinline__ uint32_t gshfl_down1(uint32_t v) {
+    if constexpr (G == 1) return v;
+    else return row_shl1(v);
 }
 template <int G>
 __device__ __forceinline__ int gshfl_xor(int v, int d) {
@@ -159,15 +175,19 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
             if constexpr (G > 1) {
                 // carry-lookahead over the group: (carry-out, propagate) combined low to high
                 uint32_t cc = carry, pp = (all1 == ~0u) ? 1u : 0u;
-#pragma unroll
-                for (int d = 1; d < G; d <<= 1) {
-                    uint32_t clo = gshfl_up<G>(cc, d), plo = gshfl_up<G>(pp, d);
-                    if (g >= d) {
-                        cc = cc | (pp & clo);
-                        pp = pp & plo;
-                    }
+                if constexpr (G >= 2) {
+                    uint32_t clo = gshfl_up_c<G, 1>(cc), plo = gshfl_up_c<G, 1>(pp);
+                    if (g >= 1) { cc = cc | (pp & clo); pp = pp & plo; }
                 }
-                uint32_t cin = gshfl_up<G>(cc, 1);
+                if constexpr (G >= 4) {
+                    uint32_t clo = gshfl_up_c<G, 2>(cc), plo = gshfl_up_c<G, 2>(pp);
+                    if (g >= 2) { cc = cc | (pp & clo); pp = pp & plo; }
+                }
+                if constexpr (G >= 8) {
+                    uint32_t clo = gshfl_up_c<G, 4>(cc), plo = gshfl_up_c<G, 4>(pp);
+                    if (g >= 4) { cc = cc | (pp & clo); pp = pp & plo; }
+                }
+                uint32_t cin = gshfl_up_c<G, 1>(cc);
                 if (g == 0) cin = 0;
 #pragma unroll
                 for (int s = 0; s < NWL; s++) {
@@ -186,7 +206,7 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
             uint32_t phc = 1, mhc = 0;
             if constexpr (G > 1) {
                 uint32_t tb = (ph[NWL - 1] >> 31) | ((mh[NWL - 1] >> 31) << 1);
-                uint32_t tin = gshfl_up<G>(tb, 1);
+                uint32_t tin = gshfl_up_c<G, 1>(tb);
                 if (g != 0) {
                     phc = tin & 1u;
                     mhc = tin >> 1;
@@ -266,13 +286,13 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
         else if constexpr (NWL >= 2)
             d1 = dl[1];
         else
-            d1 = (int)gshfl_down<G>((uint32_t)dl[0], 1);
+            d1 = (int)gshfl_down1<G>((uint32_t)dl[0]);
         S += d1;
-        uint32_t inP = gshfl_down<G>(Pv[0], 1), inM = gshfl_down<G>(Mv[0], 1);
-        uint32_t inV = gshfl_down<G>(V[0], 1);
+        uint32_t inP = gshfl_down1<G>(Pv[0]), inM = gshfl_down1<G>(Mv[0]);
+        uint32_t inV = gshfl_down1<G>(V[0]);
         uint32_t inL[NP];
 #pragma unroll
-        for (int p = 0; p < NP; p++) inL[p] = gshfl_down<G>(PL[p][0], 1);
+        for (int p = 0; p < NP; p++) inL[p] = gshfl_down1<G>(PL[p][0]);
 #pragma unroll
         for (int s = 0; s + 1 < NWL; s++) {
             Pv[s] = Pv[s + 1];
@@ -311,7 +331,7 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
 using PersistKernel = void (*)(const uint64_t *, const int64_t *, int64_t, VSet, VSet, int,
                                uint8_t *, unsigned long long *, unsigned long long *);
 
-constexpr int NWL_CHOICES[] = {1, 2, 3, 4, 6, 9};
+constexpr int NWL_CHOICES[] = {1, 2, 3, 4, 5, 6, 9, 11};
 constexpr int G_CHOICES[] = {1, 2, 4, 8};
 
 template <int NWL, int G>
@@ -331,8 +351,10 @@ static PersistKernel by_nwl(int nwl, int np) {
         case 2: return by_np<2, G>(np);
         case 3: return by_np<3, G>(np);
         case 4: return by_np<4, G>(np);
+        case 5: return by_np<5, G>(np);
         case 6: return by_np<6, G>(np);
-        default: return by_np<9, G>(np);
+        case 9: return by_np<9, G>(np);
+        default: return by_np<11, G>(np);
     }
 }
 
@@ -352,7 +374,7 @@ static int nwl_for(int nw, int g) {
     return 0;
 }
 
-int persist_max_c() { return (9 * 8 - 1) / 2; }
+int persist_max_c() { return (11 * 8 - 1) / 2; }
 
 // ---------------------------------------------------------------- longest-first order
 constexpr int LPT_BINS = 4096;
@@ -404,14 +426,15 @@ __global__ void k_lpt_scatter(const uint64_t *pairs, int64_t n, VSet A, VSet B,
 }
 
 // ---------------------------------------------------------------- dispatch
-static void launch_persist(int nwl, int g, int np, const uint64_t *pairs, const int64_t *order,
-                           int64_t n, const VSet &va, const VSet &vb, int kmode, uint8_t *flags,
-                           unsigned long long *cells, unsigned long long *next, hipStream_t s) {
+static void launch_persist(int nwl, int g, int np, int max_blocks, const uint64_t *pairs,
+                           const int64_t *order, int64_t n, const VSet &va, const VSet &vb,
+                           int kmode, uint8_t *flags, unsigned long long *cells,
+                           unsigned long long *next, hipStream_t s) {
     fill_u64((uint64_t *)next, 0, 1, s);
-    // enough groups to keep every SIMD busy, but no more than the pairs need
+    // at most max_blocks resident workgroups, and no more than the pairs need
     int64_t groups_per_block = 256 / g;
     int64_t blocks = (n + groups_per_block - 1) / groups_per_block;
-    blocks = std::min<int64_t>(blocks, 256 * 8);
+    blocks = std::min<int64_t>(blocks, max_blocks);
     hipLaunchKernelGGL(persist_kernel(nwl, g, np), dim3((unsigned)std::max<int64_t>(blocks, 1)),
                        dim3(256), 0, s, pairs, order, n, va, vb, kmode, flags, cells, next);
     MJ_LAUNCH_CHECK();
@@ -445,7 +468,7 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     if (hv[1]) throw Error(MJ_EINVAL, "pair names a string id out of range");
     const int cmax = (int)hv[0];
     if (cmax > persist_max_c())
-        throw Error(MJ_ECAPACITY, "threshold K above the batched verifier's band limit (K <= 1120)");
+        throw Error(MJ_ECAPACITY, "threshold K above the batched verifier's band limit (K <= 1376)");
     fill_u32(cnt, 0, LPT_BINS, s);
     fill_u32(fillc, 0, LPT_BINS, s);
     hipLaunchKernelGGL(k_lpt_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, pairs, n, va, vb, cnt);
@@ -457,37 +480,51 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
 
     const int nw = 2 * cmax + 1;
     const int npi = np / 2 - 1;
-    int best_g = tune ? tune->best_g[std::min(cmax, 63)][npi] : 0;
+    const int ci = std::min(cmax, 63);
+    int best_g = tune ? tune->best_g[ci][npi] : 0;
+    int best_blocks = tune ? tune->best_blocks[ci][npi] : 0;
     if (best_g == 0) {
-        // time each lane-group width once on this call's pairs; keep the fastest
+        // time each (lanes per pair, resident workgroups) once on this call's pairs and
+        // keep the fastest; small calls are not representative and are not cached
         hipEvent_t e0, e1;
         MJ_HIP(hipEventCreate(&e0));
         MJ_HIP(hipEventCreate(&e1));
         float best = 1e30f;
+        best_g = 0;
         for (int g : G_CHOICES) {
             int nwl = nwl_for(nw, g);
             if (nwl == 0) continue;
-            MJ_HIP(hipEventRecord(e0, s));
-            launch_persist(nwl, g, np, pairs, order, n, va, vb, kmode, flags, cells, next, s);
-            MJ_HIP(hipEventRecord(e1, s));
-            MJ_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            MJ_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                best_g = g;
+            for (int mb : {512, 1024, 2048}) {
+                MJ_HIP(hipEventRecord(e0, s));
+                launch_persist(nwl, g, np, mb, pairs, order, n, va, vb, kmode, flags, cells, next, s);
+                MJ_HIP(hipEventRecord(e1, s));
+                MJ_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                MJ_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    best_g = g;
+                    best_blocks = mb;
+                }
             }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        if (tune && n >= 4096) tune->best_g[std::min(cmax, 63)][npi] = best_g;
+        if (tune && n >= 4096) {
+            tune->best_g[ci][npi] = best_g;
+            tune->best_blocks[ci][npi] = best_blocks;
+        }
         fill_u64((uint64_t *)cells, 0, 1, s);
     }
     int th = kt ? kt->begin(KTimer::VERIFY, s) : -1;
-    launch_persist(nwl_for(nw, best_g), best_g, np, pairs, order, n, va, vb, kmode, flags, cells,
-                   next, s);
+    launch_persist(nwl_for(nw, best_g), best_g, np, best_blocks, pairs, order, n, va, vb, kmode,
+                   flags, cells, next, s);
     if (kt) kt->end(th, s);
-    if (tune) tune->last_g = best_g, tune->last_nwl = nwl_for(nw, best_g);
+    if (tune) {
+        tune->last_g = best_g;
+        tune->last_nwl = nwl_for(nw, best_g);
+        tune->last_blocks = best_blocks;
+    }
     return (int64_t)read_back<uint64_t>((const uint64_t *)cells, s, host_scratch);
 }
 
