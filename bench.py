@@ -77,9 +77,10 @@ def file_sha(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel_src):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source; else None."""
+def measured_traffic(kernel_src, config):
+    """HBM bytes per launch of the verifier configuration `config` ("<words, lanes,
+    planes>") from the committed rocprofv3 counter summary, if the counters were taken on
+    the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "verify_traffic_dna_long.json")
     if not os.path.exists(path):
         return None
@@ -87,7 +88,7 @@ def measured_traffic(kernel_src):
         t = json.load(f)
     if t.get("source_sha256") != file_sha(kernel_src):
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_launch_by_config", {}).get(config)
 
 
 def cpu_baseline(workload, cfg, clusters):
@@ -285,8 +286,9 @@ def main():
         cells = float(np.sum([s["band_cells"] for s in stats]))
         ops = cells / 32.0 * OPS_PER_WORD_COLUMN
         achieved = ops / (kms["verify"] * 1e-3) / 1e12
-        traffic = measured_traffic(src)
-        roof = {"kernel": "k_verify_persist", "bound": "alu", "achieved": achieved,
+        vcfg = "<%d, %d, 2>" % (last["verify_words"], last["verify_group"])
+        traffic = measured_traffic(src, vcfg)
+        roof = {"kernel": "k_verify_persist" + vcfg, "bound": "alu", "achieved": achieved,
                 "peak": INT_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / INT_PEAK_TOPS,
                 "traffic": traffic,
                 "avg_launch_ms": kms["verify"] / max(1, kln["verify"]),
