@@ -213,7 +213,7 @@ def main():
     ap.add_argument("--serve-strings", type=int, default=1_000_000)
     ap.add_argument("--serve-queries", type=int, default=4096)
     ap.add_argument("--serve-rate", type=int, default=2000)
-    ap.add_argument("--serve-t-div", type=int, default=1)
+    ap.add_argument("--serve-t-div", type=int, default=2)
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=int, default=32)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -248,8 +248,9 @@ def main():
     # ground truth for recall (outside the timed region): every intra-cluster pair with
     # ED <= K, decided by the verifier; copies of different seeds are unrelated random
     # strings, far beyond K
+    # (its own context: the verifier's one-time configuration timing belongs to the join)
     truth_pairs = intra_cluster_pairs(S)
-    flags = mj.verify(ds, params, truth_pairs, ctx=ctx)
+    flags = mj.verify(ds, params, truth_pairs, ctx=mj.Context(0))
     truth = truth_pairs[flags]
 
     def timed(verifier):

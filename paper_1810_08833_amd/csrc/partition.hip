@@ -172,6 +172,20 @@ __device__ __forceinline__ void prefix_step(uint64_t &v, int &arg, int &uniq) {
     }
 }
 template <int D>
+__device__ __forceinline__ void prefix_min_step(uint64_t &v) {
+    constexpr int C = 0x110 + D;  // row_shr:D
+    uint32_t lo = dpp_or<C>(0xFFFFFFFFu, (uint32_t)v), hi = dpp_or<C>(0xFFFFFFFFu, (uint32_t)(v >> 32));
+    uint64_t ov = ((uint64_t)hi << 32) | lo;
+    v = ov < v ? ov : v;
+}
+// The value of the neighbouring lane in the row (CTRL = row_shr:1 or row_shl:1), ~0 at
+// the row's edge.
+template <int CTRL>
+__device__ __forceinline__ uint64_t shift_in(uint64_t v) {
+    uint32_t lo = dpp_or<CTRL>(0xFFFFFFFFu, (uint32_t)v), hi = dpp_or<CTRL>(0xFFFFFFFFu, (uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <int D>
 __device__ __forceinline__ void suffix_step(uint64_t &v) {
     constexpr int C = 0x100 + D;  // row_shl:D
     uint32_t lo = dpp_or<C>(0xFFFFFFFFu, (uint32_t)v), hi = dpp_or<C>(0xFFFFFFFFu, (uint32_t)(v >> 32));
@@ -244,48 +258,63 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     __syncthreads();
     const int32_t s0 = td.s0, ns = td.ns;
     const uint64_t gmask = (q * bits >= 64) ? ~0ull : ((1ull << (q * bits)) - 1);
-    // hashes: one position per thread at a time (consecutive threads, consecutive positions)
+    // hashes: each thread rolls the packed q-gram code over RUN consecutive positions
     {
+        constexpr int RUN = REGION / AT_THREADS;
         int lmax = 0, lrmin = 0x7FFFFFFF;
-        for (int idx = tid; idx < NR; idx += AT_THREADS) {
-            int64_t g = base + idx;
+        uint64_t G = 0;
+        int64_t have_end = -1;  // G is valid for the previous position when it is in the same string
+        const int idx0 = tid * RUN;
+        int t = 0;
+        if (ns >= 0) {
+            const int64_t g0 = base + idx0;
+            for (int k = 1; k < ns; k++) t += (td.off[k] <= g0) ? 1 : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < RUN; j++) {
+            const int idx = idx0 + j;
+            if (idx >= NR) break;
+            const int64_t g = base + idx;
             uint64_t h = ~0ull;
             uint16_t info = 0;
             int32_t r = 0;
             int64_t sbeg = 0, send = 0;
-            bool valid;
+            bool valid = g >= 0 && g < total;
             if (ns >= 0) {
-                // the string holding g: a short scan over the tile's strings (uniform trip count)
-                valid = g >= 0 && g < total;
-                int t = 0;
-                for (int k = 1; k < ns; k++) t += (td.off[k] <= g) ? 1 : 0;
+                while (t + 1 < ns && td.off[t + 1] <= g) t++;
                 sbeg = td.off[t];
                 send = td.off[t + 1];
                 r = td.r[t];
-            } else {
-                valid = g >= 0 && g < total;
-                if (valid) {
-                    int32_t sidx = owner_of(off, n, g);
-                    sbeg = off[sidx];
-                    send = off[sidx + 1];
-                    r = rr[sidx];
-                }
+            } else if (valid) {
+                int32_t sidx = owner_of(off, n, g);
+                sbeg = off[sidx];
+                send = off[sidx + 1];
+                r = rr[sidx];
             }
             if (valid) {
-                int64_t i = g - sbeg;
-                int64_t npos = (send - sbeg) - q + 1;
+                const int64_t i = g - sbeg;
+                const int64_t npos = (send - sbeg) - q + 1;
                 if (i < npos) {
-                    uint64_t G = 0;
-                    for (int k = 0; k < q; k++) G = (G << bits) | ch[idx + k];
-                    G &= gmask;
+                    if (have_end == send && i > 0 && j > 0) {
+                        G = ((G << bits) | ch[idx + q - 1]) & gmask;
+                    } else {
+                        G = 0;
+                        for (int k = 0; k < q; k++) G = (G << bits) | ch[idx + k];
+                        G &= gmask;
+                    }
+                    have_end = send;
                     h = table ? table[G] : mix64(G ^ salt);
+                } else {
+                    have_end = -1;
                 }
-                bool interior = (i >= r) && (i <= npos - 1 - r);
+                const bool interior = (i >= r) && (i <= npos - 1 - r);
                 info = (uint16_t)((interior ? r : 0) | (i == 0 ? 0x8000 : 0));
                 if (interior && idx >= H && idx < H + TP) {
                     lmax = max(lmax, 31 - __clz(r));
                     lrmin = min(lrmin, r);
                 }
+            } else {
+                have_end = -1;
             }
             bufA[idx] = h;
             pinfo[idx] = info;
@@ -297,29 +326,34 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     const int NC = TP / AT_THREADS;
     constexpr int OWN = REGION / AT_THREADS;
     if (rmin_s >= AT_BLOCK - 1) {
-        // ---- block test: bufA <- suffix minima, bufB <- prefix minima (within blocks)
+        // ---- block test: bufA <- suffix minima, bufB <- prefix minima (within blocks).
+        // The block's unique minimum is the position strictly below the prefix minimum
+        // before it and the suffix minimum after it (neighbouring lanes of the scans).
         for (int j0 = 0; j0 < NR; j0 += AT_THREADS) {  // uniform trip count for the DPP scans
             const int idx = j0 + tid;
-            uint64_t v = idx < NR ? bufA[idx] : ~0ull;
-            uint64_t sv = v;
-            int arg = idx, uniq = 1;
-            prefix_step<1>(v, arg, uniq);
-            prefix_step<2>(v, arg, uniq);
-            prefix_step<4>(v, arg, uniq);
-            prefix_step<8>(v, arg, uniq);
+            const uint64_t hv = idx < NR ? bufA[idx] : ~0ull;
+            uint64_t pv = hv, sv = hv;
+            prefix_min_step<1>(pv);
+            prefix_min_step<2>(pv);
+            prefix_min_step<4>(pv);
+            prefix_min_step<8>(pv);
             suffix_step<1>(sv);
             suffix_step<2>(sv);
             suffix_step<4>(sv);
             suffix_step<8>(sv);
+            const uint64_t before = shift_in<0x111>(pv);  // prefix minimum of the lane below
+            const uint64_t after = shift_in<0x101>(sv);   // suffix minimum of the lane above
             if (idx < NR) {
-                bufB[idx] = v;
+                bufB[idx] = pv;
                 bufA[idx] = sv;
             }
-            if ((tid & (AT_BLOCK - 1)) == AT_BLOCK - 1 && idx - (AT_BLOCK - 1) < NR) {
-                const int bk = idx / AT_BLOCK;
-                bmin[bk] = v;
-                barg[bk] = (int16_t)(uniq ? arg : -1);
-            }
+            if ((tid & (AT_BLOCK - 1)) == 0 && idx < NR) barg[idx / AT_BLOCK] = -1;
+            if ((tid & (AT_BLOCK - 1)) == AT_BLOCK - 1 && idx - (AT_BLOCK - 1) < NR)
+                bmin[idx / AT_BLOCK] = pv;
+            // at most one lane per block satisfies this (a strict minimum of the block)
+            const bool uniq = idx < NR && hv < before && hv < after;
+            __syncthreads();
+            if (uniq) barg[idx / AT_BLOCK] = (int16_t)idx;
         }
         __syncthreads();
         const int NBK = (NR + AT_BLOCK - 1) / AT_BLOCK;
@@ -422,24 +456,52 @@ __global__ void k_anchor_scatter(const uint64_t *bm, int64_t nw, const uint32_t 
 
 // Partition records between consecutive flagged positions: key f = M(Phi xor S) with
 // Phi the Karp-Rabin polynomial of the content over GF(2^61-1), length folded in as the
-// leading coefficient; payload (string id << 32 | start position).
+// leading coefficient; payload (string id << 32 | start position).  The owning string
+// comes from the descriptor of the tile holding the partition's first position; symbols
+// are read four at a time from aligned 32-bit words.
+__device__ __forceinline__ uint64_t horner_step(uint64_t h, uint64_t B, uint32_t c) {
+    h = mulmod61(h, B) + (uint64_t)c + 1;
+    return h >= P61 ? h - P61 : h;
+}
+
 __global__ void k_records(const int64_t *__restrict__ apos, int64_t R,
                           const int64_t *__restrict__ off, int32_t n,
-                          const uint8_t *__restrict__ chars, uint64_t B, uint64_t salt_f,
+                          const uint8_t *__restrict__ chars, int aligned4,
+                          const TileDesc *__restrict__ td, int TP, uint64_t B, uint64_t salt_f,
                           uint64_t *key, uint64_t *val, uint32_t *len) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; k < R; k += stride) {
-        int64_t g0 = apos[k], g1 = apos[k + 1];
-        int32_t sidx = owner_of(off, n, g0);
-        int64_t L = g1 - g0;
-        uint64_t h = (uint64_t)L % P61;
-        for (int64_t g = g0; g < g1; g++) {
-            h = mulmod61(h, B) + (uint64_t)chars[g] + 1;
-            if (h >= P61) h -= P61;
+        const int64_t g0 = apos[k], g1 = apos[k + 1];
+        const TileDesc &d = td[g0 / TP];
+        int32_t sidx;
+        int64_t sbeg;
+        if (d.ns >= 0) {
+            int t = 0;
+            for (int j = 1; j < d.ns; j++) t += (d.off[j] <= g0) ? 1 : 0;
+            sidx = d.s0 + t;
+            sbeg = d.off[t];
+        } else {
+            sidx = owner_of(off, n, g0);
+            sbeg = off[sidx];
         }
+        const int64_t L = g1 - g0;
+        uint64_t h = (uint64_t)L % P61;
+        int64_t g = g0;
+        if (aligned4) {
+            for (; g < g1 && (g & 3); g++) h = horner_step(h, B, chars[g]);
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(chars);
+            for (; g + 4 <= g1; g += 4) {
+                uint32_t v = w[g >> 2];
+                h = horner_step(h, B, v & 0xFFu);
+                h = horner_step(h, B, (v >> 8) & 0xFFu);
+                h = horner_step(h, B, (v >> 16) & 0xFFu);
+                h = horner_step(h, B, v >> 24);
+            }
+        }
+        for (; g < g1; g++) h = horner_step(h, B, chars[g]);
         key[k] = mix64(h ^ salt_f);
-        val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - off[sidx]);
+        val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
         if (len) len[k] = (uint32_t)L;
     }
 }
@@ -481,6 +543,10 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho
     uint64_t seed = p.seed + (uint64_t)rho;
     uint64_t salt = mix64(seed + GAMMA);
     if (ntiles > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many tiles");
+    // flagged positions are string starts plus strict minima of radius >= 1 (at most every
+    // other position); their ranks are 32-bit
+    if ((int64_t)d.n + d.total / 2 + 2 > 0xFFFFFFF0LL)
+        throw Error(MJ_ECAPACITY, "more than 2^32 partitions per repetition");
     int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
     TileDesc *ts = ws.get_n<TileDesc>(ntiles + 1);
     hipLaunchKernelGGL(k_tile_desc, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s,
@@ -512,8 +578,10 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho
     uint64_t salt_f = mix64(p.seed + GAMMA);
     if (R > 0) {
         int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
+        int aligned4 = ((uintptr_t)d.chars & 3) == 0 ? 1 : 0;
         hipLaunchKernelGGL(k_records, dim3(grid_for(R, 256, 65535)), dim3(256), 0, s, apos, R,
-                           d.offsets, d.n, d.chars, B, salt_f, out.key + base, out.val + base,
+                           d.offsets, d.n, d.chars, aligned4, ts, TP, B, salt_f, out.key + base,
+                           out.val + base,
                            out.with_len ? out.len + base : nullptr);
         MJ_LAUNCH_CHECK();
         if (kt) kt->end(tr, s);

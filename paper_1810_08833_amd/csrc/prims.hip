@@ -245,6 +245,8 @@ __global__ void k_compact_scatter(const uint8_t *flags, const uint32_t *pre, int
 int64_t compact_flags(const uint8_t *flags, int64_t n, int64_t *idx_out, Workspace &ws,
                       hipStream_t s, uint64_t *host_scratch) {
     if (n <= 0) return 0;
+    // 32-bit ranks: the count of kept elements must stay below 2^32
+    if (n > 0xFFFFFFF0LL) throw Error(MJ_ECAPACITY, "compaction of more than 2^32 elements");
     uint32_t *pre = ws.get_n<uint32_t>(n + 1);
     scan_impl<uint8_t, uint32_t>(flags, pre, n, ws, s);
     hipLaunchKernelGGL(k_compact_scatter, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, flags,

@@ -495,12 +495,16 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
             int nwl = nwl_for(nw, g);
             if (nwl == 0) continue;
             for (int mb : {512, 1024, 2048}) {
-                MJ_HIP(hipEventRecord(e0, s));
-                launch_persist(nwl, g, np, mb, pairs, order, n, va, vb, kmode, flags, cells, next, s);
-                MJ_HIP(hipEventRecord(e1, s));
-                MJ_HIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                MJ_HIP(hipEventElapsedTime(&ms, e0, e1));
+                float ms = 1e30f;
+                for (int rep = 0; rep < 2; rep++) {  // best of two: timing noise
+                    MJ_HIP(hipEventRecord(e0, s));
+                    launch_persist(nwl, g, np, mb, pairs, order, n, va, vb, kmode, flags, cells, next, s);
+                    MJ_HIP(hipEventRecord(e1, s));
+                    MJ_HIP(hipEventSynchronize(e1));
+                    float t = 0.f;
+                    MJ_HIP(hipEventElapsedTime(&t, e0, e1));
+                    ms = std::min(ms, t);
+                }
                 if (ms < best) {
                     best = ms;
                     best_g = g;
