@@ -32,27 +32,44 @@ METRIC = "strings joined/s + verified candidate pairs/s at exact recall; batched
 HBM_PEAK_GBS = 8000.0
 CUS, LANES, CLOCK_GHZ = 256, 64, 2.4
 INT_PEAK_TOPS = CUS * LANES * CLOCK_GHZ / 1e3  # 39.32 T int32 lane-ops/s
-# 32-bit operations of one word-column of the banded bit-vector recurrence (Myers'
-# update over 32 rows: 13) plus the match mask for a 2-plane alphabet (2 XNOR + 1 AND):
-# 16 operations per 32 band cells.
-OPS_PER_WORD_COLUMN = 16
+# 32-bit operations of one word-column of the banded bit-vector recurrence: Myers'
+# update over 32 rows (13) plus the match mask of a b-bit alphabet (one XOR per bit
+# plane against the broadcast query symbol, b - 1 ANDs): 13 + 2b - 1, 16 for DNA.
+def ops_per_word_column(bits):
+    return 13 + 2 * bits - 1
 
+
+# Each workload with the T rule (t_div, reps) that gives 100% recall against its ground
+# truth; cpu_sample is the bounded sample the CPU oracle is timed on.
 WORKLOADS = {
-    "dna_long": dict(q=5, k=150, t_div=2, sigma=4,
+    "dna_long": dict(q=5, k=150, t_div=2, reps=1, sigma=4, cpu_sample=dict(n_clusters=1000),
                      desc="dna_long: 50,000 DNA strings, lengths N(5000,800) clipped to "
                           "[2000,9000], 5,000 seeds x 10 copies, 1-6% edits "
                           "(ins .5/del .3/sub .2), K=150, q=5, T=ceil(K/2)"),
-    "dna_small": dict(q=4, k=60, t_div=1, sigma=4,
+    "dna_small": dict(q=4, k=60, t_div=1, reps=1, sigma=4, cpu_sample=dict(),
                       desc="dna_small: 1,000 DNA strings, 100 seeds x 10 copies, lengths "
                            "U[800,1200], 2-10% edits, K=60, q=4, T=K"),
+    "protein": dict(q=4, k_frac=(8, 100), t_div=1, reps=7, sigma=25, cpu_sample=dict(n=20000),
+                    desc="protein: 200,000 strings over 25 letters (Zipf 1.1), lengths "
+                         "lognormal(ln 400, 0.8) clipped to [50,5000], 20% in clusters of 10 "
+                         "at 3-12% edits, K_i=ceil(0.08 m_i), q=4, T=K_i, 7 repetitions"),
+    "text": dict(q=6, k=120, t_div=2, reps=4, sigma=37, cpu_sample=dict(n=30000),
+                 desc="text: 300,000 strings over 37 symbols (Zipf 1.0), lengths N(1200,300) "
+                      "clipped to [300,3000], 10% in clusters of 10 at 2-10% edits, K=120, "
+                      "q=6, T=ceil(K/2), 4 repetitions"),
 }
 
 
-def make(workload, n_clusters=None):
+def make(workload, **kw):
     from paper_1810_08833_amd import datagen as dg
-    if workload == "dna_long":
-        return dg.dna_long() if n_clusters is None else dg.dna_long(n_clusters=n_clusters)
-    return dg.dna_small() if n_clusters is None else dg.dna_small(n_clusters=n_clusters)
+    return getattr(dg, workload)(**kw)
+
+
+def k_of(cfg, lengths):
+    from paper_1810_08833_amd import datagen as dg
+    if "k_frac" in cfg:
+        return dict(k_per_string=dg.k_fraction(lengths, *cfg["k_frac"]))
+    return dict(k=cfg["k"])
 
 
 def intra_cluster_pairs(S):
@@ -91,18 +108,61 @@ def measured_traffic(kernel_src, config):
     return t.get("bytes_per_launch_by_config", {}).get(config)
 
 
-def cpu_baseline(workload, cfg, clusters):
+def roofline(kernel, stats, kms, kln, bits, q):
+    """Achieved algorithmic rate of `kernel` over the timed steps against its bound.
+    Integer ALU kernels count 32-bit operations of the plain algorithm per unit of work:
+      verify : 13 + 2b - 1 per 32 band cells (Myers' word update + b-plane match mask)
+      anchors: per position, 42 with the 64-bit hash (rolling code 5, SplitMix64 output
+               function 23, strict-minimum test on 64-bit values 14), 10 with the rank
+               table of small code spaces (code 3, lookup 1, test on 32-bit values 6)
+      records: per symbol 17 (one Horner step modulo 2^61 - 1), per record 23 (mixer)
+    Emission is memory bound: 32 bytes per pair test (two payloads, two lengths and two
+    thresholds)."""
+    secs = kms[kernel] * 1e-3
+    n_launch = max(1, kln[kernel])
+    tot = lambda f: float(np.sum([s[f] for s in stats]))
+    src = os.path.join(ROOT, "paper_1810_08833_amd", "csrc", "verify_lg.hip")
+    r = {"kernel": kernel, "avg_launch_ms": kms[kernel] / n_launch, "traffic": None}
+    if kernel == "verify":
+        cells = tot("band_cells")
+        ops = cells / 32.0 * ops_per_word_column(bits)
+        last = stats[-1]
+        planes = {1: 2, 2: 2, 3: 4, 4: 4, 5: 6, 6: 6}.get(bits, 8)
+        vcfg = "<%d, %d, %d>" % (last["verify_words"], last["verify_group"], planes)
+        r.update(kernel="k_verify_persist" + vcfg, bound="alu", unit="Tops/s",
+                 achieved=ops / secs / 1e12, peak=INT_PEAK_TOPS,
+                 traffic=measured_traffic(src, vcfg), band_cells_per_s=cells / secs)
+    elif kernel == "anchors":
+        per_pos = 10 if q * bits <= 12 else 42
+        r.update(kernel="k_anchor_tiles<%s>" % ("uint32_t" if per_pos == 10 else "uint64_t"),
+                 bound="alu", unit="Tops/s", achieved=tot("positions") * per_pos / secs / 1e12,
+                 peak=INT_PEAK_TOPS, ops_per_position=per_pos)
+    elif kernel == "records":
+        ops = tot("positions") * 17 + tot("records") * 23
+        r.update(kernel="k_records", bound="alu", unit="Tops/s", achieved=ops / secs / 1e12,
+                 peak=INT_PEAK_TOPS)
+    else:
+        byts = tot("pair_tests") * 32.0
+        r.update(kernel="k_emit", bound="hbm", unit="GB/s", achieved=byts / secs / 1e9,
+                 peak=HBM_PEAK_GBS)
+    r["frac"] = r["achieved"] / r["peak"]
+    return r
+
+
+def cpu_baseline(workload, cfg):
     import oracle
-    S = make(workload, n_clusters=clusters)
-    p = oracle.make_params(cfg["q"], cfg["sigma"], k=cfg["k"], t_div=cfg["t_div"])
+    S = make(workload, **cfg["cpu_sample"])
+    p = oracle.make_params(cfg["q"], cfg["sigma"], t_div=cfg["t_div"], reps=cfg["reps"],
+                           **k_of(cfg, S.lengths()))
     threads = oracle.max_threads()
     t0 = time.perf_counter()
     _, out, st = oracle.join(S.chars, S.offsets, p)
     dt = time.perf_counter() - t0
     return {"value": S.n / dt, "unit": "strings/s", "cores": threads, "kind": "oracle",
-            "sample": "%s with %d seed clusters (%d strings, %d symbols): full join incl. "
+            "sample": "%s generator with %s (%d strings, %d symbols): full join incl. "
                       "verification of %d candidates in %.1f s"
-                      % (workload, clusters, S.n, int(S.offsets[-1]), st["candidates"], dt)}
+                      % (workload, cfg["cpu_sample"] or "its full size", S.n,
+                         int(S.offsets[-1]), st["candidates"], dt)}
 
 
 def copy_calibration(gib):
@@ -208,7 +268,6 @@ def main():
     ap.add_argument("--workload", default="dna_long", choices=sorted(WORKLOADS))
     ap.add_argument("--t-div", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-clusters", type=int, default=1000)
     ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
     ap.add_argument("--serve-strings", type=int, default=1_000_000)
     ap.add_argument("--serve-queries", type=int, default=4096)
@@ -242,8 +301,19 @@ def main():
     print("[bench] workload %s: %d strings, %d symbols" % (args.workload, S.n, S.offsets[-1]),
           file=sys.stderr, flush=True)
     ds = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
-    params = mj.Params(q=cfg["q"], k=cfg["k"], t_div=cfg["t_div"])
+    kw = k_of(cfg, S.lengths())
+    if "k_per_string" in kw:
+        kw["k_per_string"] = torch.from_numpy(kw["k_per_string"]).cuda()
+    params = mj.Params(q=cfg["q"], t_div=cfg["t_div"], reps=cfg["reps"], **kw)
     ctx = mj.Context(0)
+    # the same join with the strings uploaded from pageable host memory inside the timing
+    torch.cuda.synchronize()
+    t_up = time.perf_counter()
+    for _ in range(3):
+        du = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
+        torch.cuda.synchronize()
+    upload_ms = (time.perf_counter() - t_up) * 1e3 / 3
+    del du
 
     # ground truth for recall (outside the timed region): every intra-cluster pair with
     # ED <= K, decided by the verifier; copies of different seeds are unrelated random
@@ -282,26 +352,8 @@ def main():
     dominant = max(kms, key=kms.get)
 
     # roofline of the dominant kernel
-    src = os.path.join(ROOT, "paper_1810_08833_amd", "csrc", "verify_lg.hip")
-    if dominant == "verify":
-        cells = float(np.sum([s["band_cells"] for s in stats]))
-        ops = cells / 32.0 * OPS_PER_WORD_COLUMN
-        achieved = ops / (kms["verify"] * 1e-3) / 1e12
-        vcfg = "<%d, %d, 2>" % (last["verify_words"], last["verify_group"])
-        traffic = measured_traffic(src, vcfg)
-        roof = {"kernel": "k_verify_persist" + vcfg, "bound": "alu", "achieved": achieved,
-                "peak": INT_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / INT_PEAK_TOPS,
-                "traffic": traffic,
-                "avg_launch_ms": kms["verify"] / max(1, kln["verify"]),
-                "band_cells_per_s": cells / (kms["verify"] * 1e-3)}
-    else:
-        pos = float(np.sum([s["positions"] for s in stats]))
-        # the anchor kernel reads each symbol once and writes one bit per position
-        byts = pos * (1.0 + 1.0 / 8)
-        achieved = byts / (kms[dominant] * 1e-3) / 1e9
-        roof = {"kernel": "k_anchor_tiles", "bound": "hbm", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": None, "avg_launch_ms": kms[dominant] / max(1, kln[dominant])}
+    bits = int(np.ceil(np.log2(S.sigma)))
+    roof = roofline(dominant, stats, kms, kln, bits, cfg["q"])
 
     line = {
         "metric": METRIC,
@@ -317,25 +369,29 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "strings": S.n, "symbols": int(S.offsets[-1]),
-                   "K": cfg["k"], "q": cfg["q"], "t_div": cfg["t_div"], "path": "batched",
+                   "K": cfg.get("k", "ceil(%d/%d m_i)" % tuple(cfg.get("k_frac", (0, 1)))),
+                   "q": cfg["q"], "t_div": cfg["t_div"], "reps": cfg["reps"], "path": "batched",
                    "verify_lanes_per_pair": last["verify_group"],
                    "verify_words_per_lane": last["verify_words"]},
         "plain": {"value": S.n / (plain_ms * 1e-3), "ms_per_step": plain_ms,
                   "verify_kernel_ms": float(np.mean([s["kernel_ms"]["verify"] for s in plain_stats]))},
         "batched_vs_plain": plain_ms / ms,
+        "with_upload": {"value": S.n / ((ms + upload_ms) * 1e-3), "upload_ms": upload_ms,
+                        "note": "strings uploaded from pageable host memory inside the timing"},
         "verified_pairs_per_s": last["candidates"] / (verify_ms * 1e-3),
         "candidates": last["candidates"],
         "output_pairs": int(len(out)),
         "recall": recall,
         "true_pairs": int(len(truth)),
         "records": last["records"],
+        "pair_tests": last["pair_tests"],
         "stage_ms": {k: float(np.mean([s["stage_ms"][k] for s in stats])) for k in mj.STAGES[:7]},
         "kernel_ms_per_step": {k: kms[k] / args.steps for k in kms},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.workload, cfg, args.cpu_clusters)
+        line["cpu_baseline"] = cpu_baseline(args.workload, cfg)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line))

@@ -193,9 +193,17 @@ int64_t orc_partition_all(const uint8_t *chars, const int64_t *offsets, int32_t 
                           const orc_params *p, orc_record **out) {
     int reps = p->reps > 0 ? p->reps : 1;
     int64_t *start = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
-    /* a string of length m has at most m partitions per repetition */
+    /* Room per string and repetition: two interior strict minima of radius r are more
+     * than r apart (each lies in the other's window), so there are at most
+     * (m-q+1)/(r+1) + 1 interior anchors and one partition more. */
     start[0] = 0;
-    for (int32_t i = 0; i < n; i++) start[i + 1] = start[i] + (offsets[i + 1] - offsets[i]) * reps;
+    for (int32_t i = 0; i < n; i++) {
+        int64_t m = offsets[i + 1] - offsets[i];
+        int64_t T = orc_target_partitions(string_k(p, i), p->t_div, p->t_fixed);
+        int64_t npos = m - p->q + 1 > 0 ? m - p->q + 1 : 0;
+        int64_t bound = npos / (orc_radius(m, p->q, T) + 1) + 2;
+        start[i + 1] = start[i] + bound * reps;
+    }
     orc_record *tmp = (orc_record *)malloc(sizeof(orc_record) * ((size_t)start[n] + 1));
     int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
     int nt = p->threads > 0 ? p->threads : 1;
@@ -215,17 +223,16 @@ int64_t orc_partition_all(const uint8_t *chars, const int64_t *offsets, int32_t 
         }
         free(anch);
     }
-    int64_t R = 0;
-    for (int32_t i = 0; i < n; i++) R += cnt[i];
-    orc_record *res = (orc_record *)malloc(sizeof(orc_record) * ((size_t)R + 1));
+    /* compact in place (the write position never passes the read position) */
     int64_t w = 0;
     for (int32_t i = 0; i < n; i++) {
-        memcpy(res + w, tmp + start[i], sizeof(orc_record) * (size_t)cnt[i]);
+        if (cnt[i]) memmove(tmp + w, tmp + start[i], sizeof(orc_record) * (size_t)cnt[i]);
         w += cnt[i];
     }
-    free(tmp); free(cnt); free(start);
-    *out = res;
-    return R;
+    orc_record *res = (orc_record *)realloc(tmp, sizeof(orc_record) * ((size_t)w + 1));
+    free(cnt); free(start);
+    *out = res ? res : tmp;
+    return w;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -479,6 +486,16 @@ int orc_join_candidates(const uint8_t *chars, const int64_t *offsets, int32_t n,
  * query is partitioned with the same q, seed and T rule, probes the index, applies the
  * filters with its own K, dedups and verifies with its own K.  Output: sorted
  * (query id << 32 | string id). */
+static int cmp_record_key(const void *a, const void *b) {
+    const orc_record *x = (const orc_record *)a, *y = (const orc_record *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    if (x->sid != y->sid) return x->sid < y->sid ? -1 : 1;
+    if (x->pos != y->pos) return x->pos < y->pos ? -1 : 1;
+    return x->rep < y->rep ? -1 : (x->rep > y->rep);
+}
+
+/* Search (the query side of Alg. 3 against a dictionary holding every index record):
+ * the dictionary is the index records sorted by key, probed by binary search. */
 int orc_search(const uint8_t *ichars, const int64_t *ioff, int32_t ni, const orc_params *ip,
                const uint8_t *qchars, const int64_t *qoff, int32_t nq, const orc_params *qp,
                uint64_t **cand_out, int64_t *ncand, uint64_t **pairs_out, int64_t *npairs) {
@@ -486,36 +503,26 @@ int orc_search(const uint8_t *ichars, const int64_t *ioff, int32_t ni, const orc
     orc_record *irec = NULL, *qrec = NULL;
     int64_t RI = orc_partition_all(ichars, ioff, ni, ip, &irec);
     int64_t RQ = orc_partition_all(qchars, qoff, nq, qp, &qrec);
-    uint64_t cap = 16;
-    while (cap < (uint64_t)(2 * RI + 16)) cap <<= 1;
-    orc_table tab;
-    tab.mask = cap - 1;
-    tab.keys = (uint64_t *)malloc(sizeof(uint64_t) * cap);
-    tab.b = (orc_bucket *)malloc(sizeof(orc_bucket) * cap);
-    tab.used = (uint8_t *)calloc(cap, 1);
-    for (int64_t r = 0; r < RI; r++) {
-        orc_entry ne = { irec[r].sid, irec[r].pos, irec[r].len };
-        bucket_push(table_get(&tab, irec[r].key, 1), ne);
-    }
+    qsort(irec, (size_t)RI, sizeof(orc_record), cmp_record_key);
     int64_t cc = 0, ccap = 1024;
     uint64_t *cand = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)ccap);
     for (int64_t r = 0; r < RQ; r++) {
         int32_t qi = qrec[r].sid;
         int64_t mq = qoff[qi + 1] - qoff[qi];
         int64_t Kq = string_k(qp, qi);
-        orc_bucket *bk = table_get(&tab, qrec[r].key, 0);
-        if (!bk) continue;
-        for (int64_t e = 0; e < bk->n; e++) {
-            orc_entry en = bk->e[e];
-            int64_t ms = ioff[en.j + 1] - ioff[en.j];
-            if (pass_length(mq, ms, Kq) && pass_position(qrec[r].pos, mq, en.pos, ms, Kq)) {
+        int64_t lo = 0, hi = RI;  /* first index record with key >= the query key */
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (irec[mid].key < qrec[r].key) lo = mid + 1; else hi = mid;
+        }
+        for (int64_t e = lo; e < RI && irec[e].key == qrec[r].key; e++) {
+            int64_t ms = ioff[irec[e].sid + 1] - ioff[irec[e].sid];
+            if (pass_length(mq, ms, Kq) && pass_position(qrec[r].pos, mq, irec[e].pos, ms, Kq)) {
                 if (cc == ccap) { ccap *= 2; cand = (uint64_t *)realloc(cand, sizeof(uint64_t) * (size_t)ccap); }
-                cand[cc++] = ((uint64_t)qi << 32) | (uint64_t)(uint32_t)en.j;
+                cand[cc++] = ((uint64_t)qi << 32) | (uint64_t)(uint32_t)irec[e].sid;
             }
         }
     }
-    for (uint64_t h = 0; h < cap; h++) if (tab.used[h]) free(tab.b[h].e);
-    free(tab.keys); free(tab.b); free(tab.used);
     cc = dedup_sorted(cand, cc);
     uint64_t *c2 = (uint64_t *)malloc(sizeof(uint64_t) * ((size_t)cc + 1));
     memcpy(c2, cand, sizeof(uint64_t) * (size_t)cc);

@@ -152,45 +152,49 @@ __device__ __forceinline__ uint32_t dpp_or(uint32_t old, uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, 0xF, 0xF, false);
 }
 
-// One step of an inclusive scan over a row of 16 lanes: combine with the lane D below
-// (prefix) or D above (suffix).  (v, arg, uniq): minimum, its index, and whether it is
-// attained once; the sentinel ~0 (never a stored hash of a tested position) is the
-// identity for lanes without a partner.
-template <int D>
-__device__ __forceinline__ void prefix_step(uint64_t &v, int &arg, int &uniq) {
-    constexpr int C = 0x110 + D;  // row_shr:D
-    uint32_t lo = dpp_or<C>(0xFFFFFFFFu, (uint32_t)v), hi = dpp_or<C>(0xFFFFFFFFu, (uint32_t)(v >> 32));
-    int oa = (int)dpp_or<C>(0xFFFFFFFFu, (uint32_t)arg);
-    int ou = (int)dpp_or<C>(1u, (uint32_t)uniq);
-    uint64_t ov = ((uint64_t)hi << 32) | lo;
-    if (ov < v) {
-        v = ov;
-        arg = oa;
-        uniq = ou;
-    } else if (ov == v) {
-        uniq = 0;
-    }
-}
-template <int D>
-__device__ __forceinline__ void prefix_min_step(uint64_t &v) {
-    constexpr int C = 0x110 + D;  // row_shr:D
-    uint32_t lo = dpp_or<C>(0xFFFFFFFFu, (uint32_t)v), hi = dpp_or<C>(0xFFFFFFFFu, (uint32_t)(v >> 32));
-    uint64_t ov = ((uint64_t)hi << 32) | lo;
-    v = ov < v ? ov : v;
-}
-// The value of the neighbouring lane in the row (CTRL = row_shr:1 or row_shl:1), ~0 at
-// the row's edge.
+// The value of the lane selected by CTRL within the row, ~0 where there is none.  The
+// sentinel ~0 is the identity of the minimum scans; a position holding ~0 (a 64-bit
+// hash can) is never strictly below anything, so it never becomes an anchor either way.
 template <int CTRL>
-__device__ __forceinline__ uint64_t shift_in(uint64_t v) {
+__device__ __forceinline__ uint32_t dpp_val(uint32_t v) {
+    return dpp_or<CTRL>(0xFFFFFFFFu, v);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_val(uint64_t v) {
     uint32_t lo = dpp_or<CTRL>(0xFFFFFFFFu, (uint32_t)v), hi = dpp_or<CTRL>(0xFFFFFFFFu, (uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
 }
-template <int D>
-__device__ __forceinline__ void suffix_step(uint64_t &v) {
-    constexpr int C = 0x100 + D;  // row_shl:D
-    uint32_t lo = dpp_or<C>(0xFFFFFFFFu, (uint32_t)v), hi = dpp_or<C>(0xFFFFFFFFu, (uint32_t)(v >> 32));
-    uint64_t ov = ((uint64_t)hi << 32) | lo;
-    v = ov < v ? ov : v;
+// Inclusive minimum scans over a row of 16 lanes: prefix (from the lane D below) and
+// suffix (from the lane D above).
+template <int D, typename V>
+__device__ __forceinline__ void prefix_min_step(V &v) {
+    V o = dpp_val<0x110 + D>(v);  // row_shr:D
+    v = o < v ? o : v;
+}
+template <int D, typename V>
+__device__ __forceinline__ void suffix_min_step(V &v) {
+    V o = dpp_val<0x100 + D>(v);  // row_shl:D
+    v = o < v ? o : v;
+}
+
+// Order-preserving ranks of the q-gram hash for small code spaces (q*b <= 12 bits):
+// rank(G) = number of codes whose hash is strictly smaller than Pi(G).  Pi(a) < Pi(b)
+// exactly when rank(a) < rank(b), and equal hashes get equal ranks, so every strict
+// window-minimum test gives the same answer on ranks as on the 64-bit hashes.
+constexpr int RANK_MAX_BITS = 12;
+__global__ __launch_bounds__(256) void k_rank_table(int ncodes, uint64_t salt,
+                                                    const uint64_t *__restrict__ table,
+                                                    uint16_t *__restrict__ rank) {
+    __shared__ uint64_t v[1 << RANK_MAX_BITS];
+    for (int c = threadIdx.x; c < ncodes; c += blockDim.x)
+        v[c] = table ? table[c] : mix64((uint64_t)c ^ salt);
+    __syncthreads();
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncodes) return;
+    const uint64_t x = v[c];
+    int below = 0;
+    for (int j = 0; j < ncodes; j++) below += v[j] < x ? 1 : 0;
+    rank[c] = (uint16_t)below;
 }
 
 // Per-tile descriptor: the strings overlapping the tile's region (first id, count), and
@@ -226,20 +230,25 @@ __global__ void k_tile_desc(const int64_t *__restrict__ off, const int32_t *__re
     td[t] = d;
 }
 
-template <int REGION>
+// V = uint64_t: the hash itself (Pi, or the injected table); V = uint32_t: its rank from
+// `rank` (code spaces of at most RANK_MAX_BITS bits), staged in LDS.
+template <int REGION, typename V>
 __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     const uint8_t *__restrict__ chars, const int64_t *__restrict__ off, int32_t n, int64_t total,
     int q, int bits, uint64_t salt, const uint64_t *__restrict__ table,
-    const int32_t *__restrict__ rr, int TP, int H, const TileDesc *__restrict__ tdesc,
-    uint64_t *__restrict__ bitmap) {
-    __shared__ uint64_t bufA[REGION];
-    __shared__ uint64_t bufB[REGION];
+    const uint16_t *__restrict__ rank, const int32_t *__restrict__ rr, int TP, int H,
+    const TileDesc *__restrict__ tdesc, uint64_t *__restrict__ bitmap) {
+    constexpr bool RANKED = sizeof(V) == 4;
+    constexpr int NRANK = RANKED ? (1 << RANK_MAX_BITS) : 1;
+    __shared__ V bufA[REGION];
+    __shared__ V bufB[REGION];
     __shared__ uint16_t pinfo[REGION];
     __shared__ uint8_t ch[REGION + 64];
     __shared__ uint32_t aflag[REGION / 32];
     __shared__ TileDesc td;
     __shared__ int16_t barg[REGION / AT_BLOCK];
-    __shared__ uint64_t bmin[REGION / AT_BLOCK];
+    __shared__ V bmin[REGION / AT_BLOCK];
+    __shared__ uint16_t rank_s[NRANK];
     __shared__ int32_t kmax_s, rmin_s;
     const int NR = TP + 2 * H;
     const int tid = threadIdx.x;
@@ -255,6 +264,10 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         ch[idx] = (g >= 0 && g < total) ? chars[g] : (uint8_t)0;
     }
     for (int w = tid; w < REGION / 32; w += AT_THREADS) aflag[w] = 0;
+    if constexpr (RANKED) {
+        const int nr = 1 << (q * bits);
+        for (int c = tid; c < nr; c += AT_THREADS) rank_s[c] = rank[c];
+    }
     __syncthreads();
     const int32_t s0 = td.s0, ns = td.ns;
     const uint64_t gmask = (q * bits >= 64) ? ~0ull : ((1ull << (q * bits)) - 1);
@@ -275,7 +288,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             const int idx = idx0 + j;
             if (idx >= NR) break;
             const int64_t g = base + idx;
-            uint64_t h = ~0ull;
+            V h = (V)~0ull;
             uint16_t info = 0;
             int32_t r = 0;
             int64_t sbeg = 0, send = 0;
@@ -303,7 +316,8 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                         G &= gmask;
                     }
                     have_end = send;
-                    h = table ? table[G] : mix64(G ^ salt);
+                    if constexpr (RANKED) h = rank_s[G];
+                    else h = table ? table[G] : mix64(G ^ salt);
                 } else {
                     have_end = -1;
                 }
@@ -331,18 +345,18 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         // before it and the suffix minimum after it (neighbouring lanes of the scans).
         for (int j0 = 0; j0 < NR; j0 += AT_THREADS) {  // uniform trip count for the DPP scans
             const int idx = j0 + tid;
-            const uint64_t hv = idx < NR ? bufA[idx] : ~0ull;
-            uint64_t pv = hv, sv = hv;
+            const V hv = idx < NR ? bufA[idx] : (V)~0ull;
+            V pv = hv, sv = hv;
             prefix_min_step<1>(pv);
             prefix_min_step<2>(pv);
             prefix_min_step<4>(pv);
             prefix_min_step<8>(pv);
-            suffix_step<1>(sv);
-            suffix_step<2>(sv);
-            suffix_step<4>(sv);
-            suffix_step<8>(sv);
-            const uint64_t before = shift_in<0x111>(pv);  // prefix minimum of the lane below
-            const uint64_t after = shift_in<0x101>(sv);   // suffix minimum of the lane above
+            suffix_min_step<1>(sv);
+            suffix_min_step<2>(sv);
+            suffix_min_step<4>(sv);
+            suffix_min_step<8>(sv);
+            const V before = dpp_val<0x111>(pv);  // prefix minimum of the lane below
+            const V after = dpp_val<0x101>(sv);   // suffix minimum of the lane above
             if (idx < NR) {
                 bufB[idx] = pv;
                 bufA[idx] = sv;
@@ -362,7 +376,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             if (p < H || p >= H + TP) continue;  // no unique minimum, or not a tile position
             const int r = pinfo[p] & 0x7FFF;
             if (r == 0) continue;  // not an interior position
-            const uint64_t hv = bmin[bk];
+            const V hv = bmin[bk];
             bool ok = true;
             const int L = p - r, lb = L / AT_BLOCK;
             if (lb < bk) {
@@ -380,7 +394,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     } else {
         // ---- sparse table
         const int kmax = kmax_s;
-        uint64_t hp[OWN];
+        V hp[OWN];
         uint16_t inf[OWN];
 #pragma unroll
         for (int c = 0; c < OWN; c++) {
@@ -388,7 +402,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             hp[c] = c < NC ? bufA[H + p] : 0;
             inf[c] = c < NC ? pinfo[H + p] : 0;
         }
-        uint64_t *cur = bufA, *nxt = bufB;
+        V *cur = bufA, *nxt = bufB;
         for (int k = 0; k <= kmax; k++) {
             const int w = 1 << k;
 #pragma unroll
@@ -396,8 +410,8 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 int r = inf[c] & 0x7FFF;
                 if (c < NC && r != 0 && (31 - __clz(r)) == k) {
                     int idx = H + tid + AT_THREADS * c;
-                    uint64_t L = min(cur[idx - r], cur[idx - w]);
-                    uint64_t R = min(cur[idx + 1], cur[idx + 1 + r - w]);
+                    V L = min(cur[idx - r], cur[idx - w]);
+                    V R = min(cur[idx + 1], cur[idx + 1 + r - w]);
                     if (hp[c] < L && hp[c] < R) {
                         int pp = tid + AT_THREADS * c;
                         atomicOr(&aflag[pp >> 5], 1u << (pp & 31));
@@ -406,12 +420,12 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             }
             if (k == kmax) break;
             for (int a = tid; a < NR; a += AT_THREADS) {
-                uint64_t v = cur[a];
+                V v = cur[a];
                 if (a + w < NR) v = min(v, cur[a + w]);
                 nxt[a] = v;
             }
             __syncthreads();
-            uint64_t *t = cur;
+            V *t = cur;
             cur = nxt;
             nxt = t;
         }
@@ -552,14 +566,26 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho
     hipLaunchKernelGGL(k_tile_desc, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s,
                        d.offsets, d.rr, d.n, d.total, ntiles, TP, H, ts);
     MJ_LAUNCH_CHECK();
-    if (region == 2048)
-        hipLaunchKernelGGL(k_anchor_tiles<2048>, dim3((unsigned)ntiles), dim3(AT_THREADS), 0, s,
-                           d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, d.rr, TP,
-                           H, ts, bitmap);
-    else
-        hipLaunchKernelGGL(k_anchor_tiles<4096>, dim3((unsigned)ntiles), dim3(AT_THREADS), 0, s,
-                           d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, d.rr, TP,
-                           H, ts, bitmap);
+    const int code_bits = p.q * d.bits;
+    const uint16_t *rank = nullptr;
+    if (code_bits <= RANK_MAX_BITS) {
+        const int nc = 1 << code_bits;
+        uint16_t *rk = ws.get_n<uint16_t>(nc);
+        hipLaunchKernelGGL(k_rank_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, salt,
+                           p.pi_table, rk);
+        MJ_LAUNCH_CHECK();
+        rank = rk;
+    }
+#define MJ_ANCHORS(R, V)                                                                        \
+    hipLaunchKernelGGL((k_anchor_tiles<R, V>), dim3((unsigned)ntiles), dim3(AT_THREADS), 0, s,  \
+                       d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, rank,    \
+                       d.rr, TP, H, ts, bitmap)
+    if (rank) {
+        if (region == 2048) MJ_ANCHORS(2048, uint32_t); else MJ_ANCHORS(4096, uint32_t);
+    } else {
+        if (region == 2048) MJ_ANCHORS(2048, uint64_t); else MJ_ANCHORS(4096, uint64_t);
+    }
+#undef MJ_ANCHORS
     MJ_LAUNCH_CHECK();
     if (kt) kt->end(th, s);
     uint32_t *cnt = ws.get_n<uint32_t>(nw + 1);

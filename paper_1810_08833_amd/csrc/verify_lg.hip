@@ -415,13 +415,38 @@ __global__ void k_lpt_hist(const uint64_t *pairs, int64_t n, VSet A, VSet B, uin
         if (h[t]) atomicAdd(&cnt[t], h[t]);
 }
 
-__global__ void k_lpt_scatter(const uint64_t *pairs, int64_t n, VSet A, VSet B,
-                              const uint32_t *off, uint32_t *fill, int64_t *order) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) {
-        int b = lpt_bin(pairs[i], A, B);
-        order[off[b] + atomicAdd(&fill[b], 1u)] = i;
+// Scatter into bin order.  Ranks inside a block come from LDS counters; each block then
+// reserves its range of every bin it touches with one global atomic (lengths cluster in
+// a few bins, so per-pair global atomics would serialise on them).
+constexpr int LPT_ITEMS = 16;
+__global__ __launch_bounds__(256) void k_lpt_scatter(const uint64_t *pairs, int64_t n, VSet A,
+                                                     VSet B, const uint32_t *off, uint32_t *fill,
+                                                     int64_t *order) {
+    __shared__ uint32_t cnt[LPT_BINS];
+    __shared__ uint32_t base[LPT_BINS];
+    for (int t = threadIdx.x; t < LPT_BINS; t += blockDim.x) cnt[t] = 0;
+    __syncthreads();
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x * LPT_ITEMS;
+    int bin[LPT_ITEMS];
+    uint32_t rank[LPT_ITEMS];
+#pragma unroll
+    for (int k = 0; k < LPT_ITEMS; k++) {
+        const int64_t i = first + (int64_t)k * blockDim.x + threadIdx.x;
+        bin[k] = 0;
+        rank[k] = 0;
+        if (i < n) {
+            bin[k] = lpt_bin(pairs[i], A, B);
+            rank[k] = atomicAdd(&cnt[bin[k]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < LPT_BINS; t += blockDim.x)
+        if (cnt[t]) base[t] = off[t] + atomicAdd(&fill[t], cnt[t]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < LPT_ITEMS; k++) {
+        const int64_t i = first + (int64_t)k * blockDim.x + threadIdx.x;
+        if (i < n) order[base[bin[k]] + rank[k]] = i;
     }
 }
 
@@ -474,8 +499,10 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     hipLaunchKernelGGL(k_lpt_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, pairs, n, va, vb, cnt);
     MJ_LAUNCH_CHECK();
     exclusive_scan_u32(cnt, off, LPT_BINS, ws, s);
-    hipLaunchKernelGGL(k_lpt_scatter, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, pairs, n, va,
-                       vb, off, fillc, order);
+    const int64_t sblocks = (n + 256 * LPT_ITEMS - 1) / (256 * LPT_ITEMS);
+    if (sblocks > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many pairs for one verification");
+    hipLaunchKernelGGL(k_lpt_scatter, dim3((unsigned)sblocks), dim3(256), 0, s, pairs, n, va, vb,
+                       off, fillc, order);
     MJ_LAUNCH_CHECK();
 
     const int nw = 2 * cmax + 1;

@@ -1,0 +1,98 @@
+"""GPU parity at full size: the five synthetic workloads at the sizes and in the launch
+configuration the benchmark uses, against the oracle's candidate and output pair sets.
+
+The oracle's results are stored as counts and SHA-256 digests of the sorted uint64
+pair arrays (tests/golden/full_size.json, written by tests/golden/make_full_size.py,
+which calls only the oracle).  Integer work: the bar is bit-exact equality."""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1810_08833_amd import datagen as dg
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "full_size.json")))
+JOINS = [n for n in ("dna_small", "dna_long", "protein", "text") if n in GOLDEN]
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def digest(a) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<u8").tobytes()).hexdigest()
+
+
+@pytest.fixture(scope="module")
+def mj():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1810_08833_amd as mj
+    mj.load_library()
+    return mj
+
+
+def params(mj, g, lengths, **kw):
+    import torch
+    if "k_frac" in g:
+        kp = torch.from_numpy(dg.k_fraction(lengths, *g["k_frac"])).cuda()
+        return mj.Params(q=g["q"], k_per_string=kp, t_div=g["t_div"], reps=g["reps"], **kw)
+    return mj.Params(q=g["q"], k=g["k"], t_div=g["t_div"], reps=g["reps"], **kw)
+
+
+@pytest.mark.parametrize("name", JOINS)
+def test_join_full_size_identical(mj, name):
+    g = GOLDEN[name]
+    say(name, "full size: %d strings, t_div=%d, reps=%d" % (g["strings"], g["t_div"], g["reps"]))
+    S = getattr(dg, name)()
+    assert S.n == g["strings"] and int(S.offsets[-1]) == g["symbols"]
+    ds = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
+    cand, _ = mj.candidates(ds, params(mj, g, S.lengths()))
+    assert cand.size == g["candidates"]
+    assert digest(cand) == g["candidates_sha256"]
+    for verifier in (mj.VERIFY_BATCHED, mj.VERIFY_PLAIN):
+        out, st = mj.join(ds, params(mj, g, S.lengths(), verifier=verifier))
+        assert st["candidates"] == g["candidates"]
+        assert out.size == g["output"], verifier
+        assert digest(out) == g["output_sha256"], verifier
+
+
+@pytest.mark.skipif("dna_index_search" not in GOLDEN, reason="no stored search result")
+def test_search_full_size_identical_direct_and_served(mj):
+    """1M-string index, 4096 queries: one mj_search call over all queries, and the same
+    queries through the continuous-batching server, both equal the oracle's pairs."""
+    import torch
+    g = GOLDEN["dna_index_search"]
+    say("dna_index search full size: %d index strings, %d queries" % (g["index_strings"], g["queries"]))
+    I = dg.dna_index(n=g["index_strings"])
+    Q, _, _ = dg.dna_queries(I, n=g["queries"], rate_per_s=g["rate_per_s"])
+    assert int(I.offsets[-1]) == g["index_symbols"] and int(Q.offsets[-1]) == g["query_symbols"]
+    ds = mj.DeviceStrings.from_host(I.chars, I.offsets, 4)
+    index = mj.Index(ds, params(mj, g, I.lengths()))
+    del ds
+    torch.cuda.empty_cache()
+    kq = dg.k_fraction(Q.lengths(), *g["k_frac"])
+    qd = mj.DeviceStrings.from_host(Q.chars, Q.offsets, 4)
+    out, st = index.search(qd, k_per_query=torch.from_numpy(kq).cuda())
+    assert st["candidates"] == g["candidates"]
+    assert out.size == g["output"] and digest(out) == g["output_sha256"]
+    say("served")
+    srv = mj.Server(index, workers=4, max_batch=512, memory_budget=8 << 30)
+    for t in range(Q.n):
+        srv.submit(Q.get(t), int(kq[t]), t)
+    replies = []
+    while len(replies) < Q.n:
+        replies += srv.poll(timeout_ms=60000)
+    srv.close()
+    assert all(r["status"] == 0 for r in replies)
+    served = np.sort(np.concatenate(
+        [(np.uint64(r["tag"]) << np.uint64(32)) | r["ids"].astype(np.uint64) for r in replies]))
+    assert served.size == g["output"] and digest(served) == g["output_sha256"]
+    assert max(r["batch_size"] for r in replies) > 1
