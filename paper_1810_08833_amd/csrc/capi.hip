@@ -44,7 +44,7 @@ extern "C" mj_status mj_ctx_create(int device, mj_ctx **out) {
     MJ_HIP(hipSetDevice(device));
     mj_ctx *c = new mj_ctx();
     c->device = device;
-    if (hipHostMalloc((void **)&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->pinned, HOST_SCRATCH_BYTES, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return fail(MJ_ENOMEM, "pinned host allocation failed");
     }
@@ -123,14 +123,13 @@ static DevStrings view(const mj_strings *s, hipStream_t st, uint64_t *pinned) {
     return d;
 }
 
-// All partitions of all repetitions, sorted by (key, payload).
+// All partitions of all repetitions, sorted by key (stable: equal keys keep partition order).
 static void sorted_records(const DevStrings &d, const PartitionParams &pp, int32_t halo, RecBuf &rb,
                            Workspace &ws, hipStream_t s, uint64_t *pinned) {
-    for (int rho = 0; rho < pp.reps; rho++) partition_records(d, pp, rho, halo, rb, ws, s, pinned);
+    partition_records(d, pp, halo, rb, ws, s, pinned);
     int64_t R = rb.count;
     if (R > 1) {
-        int bb = std::min(22, std::max(1, ceil_log2((uint64_t)(R / 128 + 1))));
-        sort_pairs(rb.key, rb.val, R, 64 - bb, bb, ws, s);
+        radix_sort(rb.key, rb.val, R, ~0ull, ws, s);
     }
 }
 
@@ -228,14 +227,12 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     if (upto >= 2) pack_planes(d, verify_planes(d.bits), ws, s);
     tm.mark();  // 0 setup
     RecBuf rb;
-    struct RbFree { RecBuf &r; ~RbFree() { r.release(); } } rbf{rb};
-    for (int rho = 0; rho < pp.reps; rho++)
-        partition_records(d, pp, rho, halo, rb, ws, s, ctx->pinned, &ctx->kt);
+    rb.ws = &ws;  // workspace memory: cached across calls, returned when the call ends
+    partition_records(d, pp, halo, rb, ws, s, ctx->pinned, &ctx->kt);
     tm.mark();  // 1 partition: anchors and records
     int64_t R = rb.count;
     if (R > 1) {
-        int bb = std::min(22, std::max(1, ceil_log2((uint64_t)(R / 128 + 1))));
-        sort_pairs(rb.key, rb.val, R, 64 - bb, bb, ws, s);
+        radix_sort(rb.key, rb.val, R, ~0ull, ws, s);
     }
     tm.mark();  // 2 sort
     GroupInfo g = find_groups(rb.key, R, ws, s, ctx->pinned);
@@ -246,7 +243,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     int64_t c0 = emit_candidates(rb.val, g, d, cand, cap, ws, s, ctx->pinned, &ctx->kt);
     tm.mark();  // 3 group + filter
     uint64_t *uniq = nullptr;
-    int64_t C = dedup_pairs(cand, c0, d.n, ws, s, ctx->pinned, &uniq);
+    int64_t C = dedup_pairs(cand, c0, d.n, d.n, ws, s, ctx->pinned, &uniq);
     tm.mark();  // 4 dedup
     if (stats) {
         memset(stats, 0, sizeof(*stats));
@@ -317,8 +314,7 @@ extern "C" mj_status mj_partition(mj_ctx *ctx, const mj_strings *strings, const 
     mj_records *r = new mj_records();
     r->rb.with_len = true;
     try {
-        for (int rho = 0; rho < pp.reps; rho++)
-            partition_records(d, pp, rho, halo, r->rb, ws, s, ctx->pinned);
+        partition_records(d, pp, halo, r->rb, ws, s, ctx->pinned);
         MJ_HIP(hipStreamSynchronize(s));
     } catch (...) {
         r->rb.release();
@@ -452,13 +448,11 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
     pack_planes(qd, ix->np, ws, s);
     tm.mark();  // 0 setup
     RecBuf rb;
-    struct RbFree { RecBuf &r; ~RbFree() { r.release(); } } rbf{rb};
-    for (int rho = 0; rho < qp.reps; rho++)
-        partition_records(qd, qp, rho, halo, rb, ws, s, ctx->pinned, &ctx->kt);
+    rb.ws = &ws;
+    partition_records(qd, qp, halo, rb, ws, s, ctx->pinned, &ctx->kt);
     tm.mark();  // 1 partition
     if (rb.count > 1) {
-        int bb = std::min(22, std::max(1, ceil_log2((uint64_t)(rb.count / 128 + 1))));
-        sort_pairs(rb.key, rb.val, rb.count, 64 - bb, bb, ws, s);
+        radix_sort(rb.key, rb.val, rb.count, ~0ull, ws, s);
     }
     tm.mark();  // 2 sort
     DevStrings id;
@@ -485,8 +479,7 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
                        : 0;
     tm.mark();  // 3 probe + filter
     uint64_t *uniq = nullptr;
-    int32_t maxid = std::max(qd.n, 1);
-    int64_t C = dedup_pairs(cand, c0, maxid, ws, s, ctx->pinned, &uniq);
+    int64_t C = dedup_pairs(cand, c0, qd.n, ix->n, ws, s, ctx->pinned, &uniq);
     struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
     tm.mark();  // 4 dedup
     uint8_t *flags = ws.get_n<uint8_t>(C + 1);

@@ -8,7 +8,7 @@ using namespace mj;
 struct mj_ctx {
     int device = 0;
     Workspace ws;
-    uint64_t *pinned = nullptr;  // host scratch for read-backs (4 KiB)
+    uint64_t *pinned = nullptr;  // host scratch for read-backs (HOST_SCRATCH_BYTES)
     hipEvent_t ev[9] = {};
     KTimer kt;
     VerifyTuning tune;

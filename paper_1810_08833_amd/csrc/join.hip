@@ -191,17 +191,18 @@ __global__ void k_unique_flags(const uint64_t *p, int64_t n, uint8_t *f) {
     for (; i < n; i += stride) f[i] = (i == 0 || p[i] != p[i - 1]) ? 1 : 0;
 }
 
-int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t max_id, Workspace &ws, hipStream_t s,
-                    uint64_t *host_scratch, uint64_t **result) {
+int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t n_first, int32_t n_second, Workspace &ws,
+                    hipStream_t s, uint64_t *host_scratch, uint64_t **result) {
     if (n == 0) {
         *result = (uint64_t *)dev_alloc(16);
         return 0;
     }
-    int bb = std::min(22, std::max(1, ceil_log2((uint64_t)(n / 128 + 1))));
-    int top = 32 + ceil_log2((uint64_t)max_id + 1);  // pairs < 2^top
-    if (top > 64) top = 64;
-    int shift = std::max(0, top - bb);
-    sort_pairs(pairs, nullptr, n, shift, bb, ws, s);
+    // pair = first << 32 | second with first < n_first and second < n_second
+    auto field_mask = [](int32_t count) -> uint64_t {
+        const int b = std::min(32, ceil_log2((uint64_t)std::max(count, 1)));
+        return b >= 32 ? 0xFFFFFFFFull : ((1ull << b) - 1);
+    };
+    radix_sort(pairs, nullptr, n, (field_mask(n_first) << 32) | field_mask(n_second), ws, s);
     uint8_t *f = ws.get_n<uint8_t>(n);
     hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, pairs, n, f);
     MJ_LAUNCH_CHECK();

@@ -100,10 +100,13 @@ void exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, Workspace 
 // Indices i (ascending) with flags[i] != 0; returns count (reads it back).
 int64_t compact_flags(const uint8_t *flags, int64_t n, int64_t *idx_out, Workspace &ws,
                       hipStream_t s, uint64_t *host_scratch);
-// Sort (key, val) pairs ascending by (key, val) in place.  Buckets are
-// (key >> shift); shift must make bucket ids < 2^bucket_bits.
-void sort_pairs(uint64_t *key, uint64_t *val, int64_t n, int shift, int bucket_bits,
-                Workspace &ws, hipStream_t s);
+// Size of the pinned host buffer each context keeps for small device-to-host reads.
+constexpr size_t HOST_SCRATCH_BYTES = 16384;
+
+// Stable sort of keys (and an optional payload) ascending, in place.  key_mask has a 1
+// at every bit that may be set in some key (the others must be zero in all keys).
+void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Workspace &ws,
+                hipStream_t s);
 // Gather: out_k[i] = key[idx[i]] (and val).
 void gather_u64(const uint64_t *src, const int64_t *idx, uint64_t *dst, int64_t n, hipStream_t s);
 
@@ -143,12 +146,15 @@ struct PartitionParams {
 
 // Growable, owned arrays of partition records: key f, payload (sid << 32 | pos), and
 // optionally the length.
+// Partition records.  With `ws` set the arrays come from that workspace (valid until
+// its release); otherwise they are owned allocations freed by release().
 struct RecBuf {
     uint64_t *key = nullptr;
     uint64_t *val = nullptr;
     uint32_t *len = nullptr;
     int64_t cap = 0, count = 0;
     bool with_len = false;
+    Workspace *ws = nullptr;
     void reserve(int64_t need, hipStream_t s);
     void release();
 };
@@ -157,9 +163,10 @@ struct RecBuf {
 int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
                         uint64_t *host_scratch);       // returns the halo radius needed
 void pack_planes(DevStrings &d, int planes, Workspace &ws, hipStream_t s);
-// Appends the records of every partition of repetition rho to `out`; returns how many.
-int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho, int32_t halo,
-                          RecBuf &out, Workspace &ws, hipStream_t s, uint64_t *host_scratch,
+// Appends the records of every partition of every repetition (repetition rho seeds Pi
+// with seed + rho) to `out`; returns how many.
+int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t halo, RecBuf &out,
+                          Workspace &ws, hipStream_t s, uint64_t *host_scratch,
                           KTimer *kt = nullptr);
 
 // join.hip
@@ -175,9 +182,10 @@ GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t
 int64_t emit_candidates(const uint64_t *val, const GroupInfo &g, const DevStrings &d,
                         uint64_t *out, int64_t cap, Workspace &ws, hipStream_t s,
                         uint64_t *host_scratch, KTimer *kt = nullptr);
-// Sort + unique in place; returns unique count.
-int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t max_id, Workspace &ws, hipStream_t s,
-                    uint64_t *host_scratch, uint64_t **result);
+// Sorted unique copy of pairs (first << 32 | second, first < n_first, second <
+// n_second) in *result (owned allocation); sorts `pairs` in place; returns the count.
+int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t n_first, int32_t n_second, Workspace &ws,
+                    hipStream_t s, uint64_t *host_scratch, uint64_t **result);
 // Search: probe sorted index keys with sorted query records.
 int64_t probe_candidates(const uint64_t *qkey, const uint64_t *qval, int64_t RQ,
                          const uint64_t *ikey, const uint64_t *ival, int64_t RI,

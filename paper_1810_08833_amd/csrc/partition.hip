@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "mj_common.h"
 
@@ -523,28 +524,33 @@ __global__ void k_records(const int64_t *__restrict__ apos, int64_t R,
 void RecBuf::reserve(int64_t need, hipStream_t s) {
     if (need <= cap) return;
     int64_t nc = std::max<int64_t>(need, cap + cap / 2);
-    uint64_t *k2 = (uint64_t *)dev_alloc((size_t)nc * 8);
-    uint64_t *v2 = (uint64_t *)dev_alloc((size_t)nc * 8);
-    uint32_t *l2 = with_len ? (uint32_t *)dev_alloc((size_t)nc * 4) : nullptr;
+    auto get = [&](size_t bytes) -> void * { return ws ? ws->get(bytes) : dev_alloc(bytes); };
+    uint64_t *k2 = (uint64_t *)get((size_t)nc * 8);
+    uint64_t *v2 = (uint64_t *)get((size_t)nc * 8);
+    uint32_t *l2 = with_len ? (uint32_t *)get((size_t)nc * 4) : nullptr;
     if (count > 0) {
         MJ_HIP(hipMemcpyAsync(k2, key, (size_t)count * 8, hipMemcpyDeviceToDevice, s));
         MJ_HIP(hipMemcpyAsync(v2, val, (size_t)count * 8, hipMemcpyDeviceToDevice, s));
         if (with_len) MJ_HIP(hipMemcpyAsync(l2, len, (size_t)count * 4, hipMemcpyDeviceToDevice, s));
         MJ_HIP(hipStreamSynchronize(s));
     }
-    dev_free(key); dev_free(val); dev_free(len);
+    if (!ws) {
+        dev_free(key); dev_free(val); dev_free(len);
+    }
     key = k2; val = v2; len = l2; cap = nc;
 }
 
 void RecBuf::release() {
-    dev_free(key); dev_free(val); dev_free(len);
+    if (!ws) {
+        dev_free(key); dev_free(val); dev_free(len);
+    }
     key = val = nullptr; len = nullptr; cap = count = 0;
 }
 
-int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho, int32_t halo,
-                          RecBuf &out, Workspace &ws, hipStream_t s, uint64_t *host_scratch,
-                          KTimer *kt) {
+int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t halo, RecBuf &out,
+                          Workspace &ws, hipStream_t s, uint64_t *host_scratch, KTimer *kt) {
     if (d.total == 0) return 0;
+    const int reps = std::max(1, p.reps);
     int H = std::max<int32_t>(halo, 1);
     if (H > 1920)
         throw Error(MJ_ECAPACITY, "radius " + std::to_string(H) + " exceeds the supported 1920");
@@ -553,67 +559,92 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int rho
     int TP = ((region - 2 * H) / AT_THREADS) * AT_THREADS;
     int64_t ntiles = (d.total + TP - 1) / TP;
     int64_t nw = (d.total + 63) / 64;
-    uint64_t *bitmap = ws.get_n<uint64_t>(nw + 1);
-    uint64_t seed = p.seed + (uint64_t)rho;
-    uint64_t salt = mix64(seed + GAMMA);
     if (ntiles > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many tiles");
     // flagged positions are string starts plus strict minima of radius >= 1 (at most every
     // other position); their ranks are 32-bit
     if ((int64_t)d.n + d.total / 2 + 2 > 0xFFFFFFF0LL)
         throw Error(MJ_ECAPACITY, "more than 2^32 partitions per repetition");
+    if ((size_t)reps * 8 > HOST_SCRATCH_BYTES) throw Error(MJ_EINVAL, "too many repetitions");
+    const int code_bits = p.q * d.bits;
+
+    // phase 1: anchors of every repetition (Pi seeded with seed + rho), their counts
     int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
     TileDesc *ts = ws.get_n<TileDesc>(ntiles + 1);
     hipLaunchKernelGGL(k_tile_desc, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s,
                        d.offsets, d.rr, d.n, d.total, ntiles, TP, H, ts);
     MJ_LAUNCH_CHECK();
-    const int code_bits = p.q * d.bits;
-    const uint16_t *rank = nullptr;
-    if (code_bits <= RANK_MAX_BITS) {
-        const int nc = 1 << code_bits;
-        uint16_t *rk = ws.get_n<uint16_t>(nc);
-        hipLaunchKernelGGL(k_rank_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, salt,
-                           p.pi_table, rk);
-        MJ_LAUNCH_CHECK();
-        rank = rk;
-    }
+    std::vector<uint64_t *> bitmap(reps);
+    std::vector<uint32_t *> pre(reps);
+    uint16_t *rank = code_bits <= RANK_MAX_BITS ? ws.get_n<uint16_t>((size_t)1 << code_bits) : nullptr;
+    for (int rho = 0; rho < reps; rho++) {
+        const uint64_t salt = mix64(p.seed + (uint64_t)rho + GAMMA);
+        bitmap[rho] = ws.get_n<uint64_t>(nw + 1);
+        if (rank) {
+            const int nc = 1 << code_bits;
+            hipLaunchKernelGGL(k_rank_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, salt,
+                               p.pi_table, rank);
+            MJ_LAUNCH_CHECK();
+        }
 #define MJ_ANCHORS(R, V)                                                                        \
-    hipLaunchKernelGGL((k_anchor_tiles<R, V>), dim3((unsigned)ntiles), dim3(AT_THREADS), 0, s,  \
-                       d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, rank,    \
-                       d.rr, TP, H, ts, bitmap)
-    if (rank) {
-        if (region == 2048) MJ_ANCHORS(2048, uint32_t); else MJ_ANCHORS(4096, uint32_t);
-    } else {
-        if (region == 2048) MJ_ANCHORS(2048, uint64_t); else MJ_ANCHORS(4096, uint64_t);
-    }
+        hipLaunchKernelGGL((k_anchor_tiles<R, V>), dim3((unsigned)ntiles), dim3(AT_THREADS), 0, s, \
+                           d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, rank, \
+                           d.rr, TP, H, ts, bitmap[rho])
+        if (rank) {
+            if (region == 2048) MJ_ANCHORS(2048, uint32_t); else MJ_ANCHORS(4096, uint32_t);
+        } else {
+            if (region == 2048) MJ_ANCHORS(2048, uint64_t); else MJ_ANCHORS(4096, uint64_t);
+        }
 #undef MJ_ANCHORS
-    MJ_LAUNCH_CHECK();
+        MJ_LAUNCH_CHECK();
+    }
     if (kt) kt->end(th, s);
     uint32_t *cnt = ws.get_n<uint32_t>(nw + 1);
-    uint32_t *pre = ws.get_n<uint32_t>(nw + 1);
-    hipLaunchKernelGGL(k_word_popc, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s, bitmap, nw, cnt);
-    MJ_LAUNCH_CHECK();
-    exclusive_scan_u32(cnt, pre, nw, ws, s);
-    int64_t R = (int64_t)read_back<uint32_t>(pre + nw, s, host_scratch);
-    int64_t base = out.count;
-    out.reserve(base + R + 1, s);
-    int64_t *apos = ws.get_n<int64_t>(R + 1);
-    hipLaunchKernelGGL(k_anchor_scatter, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s, bitmap,
-                       nw, pre, apos, d.total);
-    MJ_LAUNCH_CHECK();
-    uint64_t B = 2 + mix64(p.seed ^ GAMMA_B) % (P61 - 3);
-    uint64_t salt_f = mix64(p.seed + GAMMA);
-    if (R > 0) {
-        int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
-        int aligned4 = ((uintptr_t)d.chars & 3) == 0 ? 1 : 0;
-        hipLaunchKernelGGL(k_records, dim3(grid_for(R, 256, 65535)), dim3(256), 0, s, apos, R,
-                           d.offsets, d.n, d.chars, aligned4, ts, TP, B, salt_f, out.key + base,
-                           out.val + base,
-                           out.with_len ? out.len + base : nullptr);
+    for (int rho = 0; rho < reps; rho++) {
+        pre[rho] = ws.get_n<uint32_t>(nw + 1);
+        hipLaunchKernelGGL(k_word_popc, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s,
+                           bitmap[rho], nw, cnt);
         MJ_LAUNCH_CHECK();
-        if (kt) kt->end(tr, s);
+        exclusive_scan_u32(cnt, pre[rho], nw, ws, s);
+        MJ_HIP(hipMemcpyAsync((uint8_t *)host_scratch + 4 * rho, pre[rho] + nw, 4,
+                              hipMemcpyDeviceToHost, s));
     }
-    out.count = base + R;
-    return R;
+    MJ_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> R(reps);
+    int64_t total = 0;
+    for (int rho = 0; rho < reps; rho++) {
+        uint32_t v;
+        memcpy(&v, (const uint8_t *)host_scratch + 4 * rho, 4);
+        R[rho] = v;
+        total += v;
+    }
+
+    // phase 2: one reservation, then the records of each repetition
+    const int64_t base0 = out.count;
+    out.reserve(base0 + total + 1, s);
+    const uint64_t B = 2 + mix64(p.seed ^ GAMMA_B) % (P61 - 3);
+    const uint64_t salt_f = mix64(p.seed + GAMMA);
+    const int aligned4 = ((uintptr_t)d.chars & 3) == 0 ? 1 : 0;
+    int64_t maxR = 0;
+    for (int rho = 0; rho < reps; rho++) maxR = std::max(maxR, R[rho]);
+    int64_t *apos = ws.get_n<int64_t>(maxR + 1);
+    int64_t base = base0;
+    for (int rho = 0; rho < reps; rho++) {
+        hipLaunchKernelGGL(k_anchor_scatter, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s,
+                           bitmap[rho], nw, pre[rho], apos, d.total);
+        MJ_LAUNCH_CHECK();
+        if (R[rho] > 0) {
+            int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
+            hipLaunchKernelGGL(k_records, dim3(grid_for(R[rho], 256, 65535)), dim3(256), 0, s, apos,
+                               R[rho], d.offsets, d.n, d.chars, aligned4, ts, TP, B, salt_f,
+                               out.key + base, out.val + base,
+                               out.with_len ? out.len + base : nullptr);
+            MJ_LAUNCH_CHECK();
+            if (kt) kt->end(tr, s);
+        }
+        base += R[rho];
+    }
+    out.count = base;
+    return total;
 }
 
 }  // namespace mj

@@ -267,196 +267,183 @@ void gather_u64(const uint64_t *src, const int64_t *idx, uint64_t *dst, int64_t 
     MJ_LAUNCH_CHECK();
 }
 
-// ---------------------------------------------------------------- bucketed sort
-// Pass 1 histograms buckets (key >> shift), pass 2 scatters into bucket ranges of a
-// temporary array, pass 3 sorts each bucket in LDS (or, for buckets above LDS capacity,
-// in global memory by one workgroup) and writes it back in place.  The result is
-// ordered by (key, val) and does not depend on the scatter order.
-constexpr int LOCAL_MAX = 2048;
+// ---------------------------------------------------------------- radix sort
+// Least-significant-digit radix sort on 8-bit digits, stable, keys with an optional
+// 64-bit payload.  One pass: per-tile digit counts (k_rs_tile_counts), an exclusive
+// scan over (digit, tile), and a scatter (k_rs_scatter) in which every element's rank
+// among equal digits of its tile comes from LDS counters.  Inside a wave, the lanes that
+// share a digit find each other with one ballot per digit bit, so each group updates
+// its counter once (no serialisation on frequent digits).  Digit positions at which all
+// keys are known to be zero (the caller's bit mask) are skipped.
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_ITEMS = 16;                      // chunks of 64 per wave
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;    // 4096 elements per tile
+constexpr int RS_WAVE_SPAN = 64 * RS_ITEMS;       // a wave owns 1024 consecutive elements
 
-template <bool HASV>
-__global__ void k_bucket_hist(const uint64_t *key, int64_t n, int shift, uint32_t *cnt) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) atomicAdd(&cnt[key[i] >> shift], 1u);
+// Lanes of this wave (among `valid`) whose 8-bit digit equals this lane's.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t valid) {
+    uint64_t peers = valid;
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
 }
 
+__device__ __forceinline__ uint64_t lanes_below() {
+    const int lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Digit counts of one tile, written digit-major: cnt[d * ntiles + tile].
+__global__ __launch_bounds__(RS_THREADS) void k_rs_tile_counts(const uint64_t *__restrict__ key,
+                                                               int64_t n, int shift, int64_t ntiles,
+                                                               uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)wave * RS_WAVE_SPAN;
+    const uint64_t below = lanes_below();
+    for (int c = 0; c < RS_ITEMS; c++) {
+        const int64_t i = base + (int64_t)c * 64 + lane;
+        const bool ok = i < n;
+        const uint32_t d = ok ? (uint32_t)(key[i] >> shift) & 255u : 0u;
+        const uint64_t peers = digit_peers(d, __ballot(ok));
+        if (ok && (peers & below) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    cnt[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of one value per thread over a 256-thread block (v of thread t ->
+// sum of v over threads < t); `tmp` holds RS_WAVES words.
+__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t *tmp) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) tmp[wave] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; w++) before += tmp[w];
+    return before + x - v;
+}
+
+// Scatter of one tile: ranks among equal digits (wave peer groups and per-wave LDS
+// counters), the tile staged in LDS in digit order, then written out so that
+// consecutive lanes write consecutive addresses of a digit's run.
 template <bool HASV>
-__global__ void k_bucket_scatter(const uint64_t *key, const uint64_t *val, int64_t n, int shift,
-                                 const uint32_t *boff, uint32_t *fill, uint64_t *k2, uint64_t *v2) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) {
-        uint64_t k = key[i];
-        uint64_t b = k >> shift;
-        uint32_t p = boff[b] + atomicAdd(&fill[b], 1u);
-        k2[p] = k;
-        if (HASV) v2[p] = val[i];
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
+    const uint64_t *__restrict__ kin, const uint64_t *__restrict__ vin, uint64_t *__restrict__ kout,
+    uint64_t *__restrict__ vout, int64_t n, int shift, int64_t ntiles,
+    const uint32_t *__restrict__ off) {
+    __shared__ uint32_t wc[RS_WAVES][256];  // per-wave digit counts, then per-wave offsets
+    __shared__ uint32_t gbase[256];         // global position minus tile-local position
+    __shared__ uint32_t tmp[RS_WAVES];
+    __shared__ uint64_t sk[RS_TILE];
+    __shared__ uint64_t sv[HASV ? RS_TILE : 1];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int w = 0; w < RS_WAVES; w++) wc[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t base = tile0 + (int64_t)wave * RS_WAVE_SPAN;
+    const uint64_t below = lanes_below();
+    uint64_t k[RS_ITEMS];
+    uint64_t v[HASV ? RS_ITEMS : 1];
+    uint32_t dr[RS_ITEMS];  // digit << 16 | rank inside the wave's span
+#pragma unroll
+    for (int c = 0; c < RS_ITEMS; c++) {
+        const int64_t i = base + (int64_t)c * 64 + lane;
+        const bool ok = i < n;
+        k[c] = ok ? kin[i] : 0;
+        if (HASV) v[HASV ? c : 0] = ok ? vin[i] : 0;
+        const uint32_t d = (uint32_t)(k[c] >> shift) & 255u;
+        const uint64_t peers = digit_peers(d, __ballot(ok));
+        const uint32_t before = wc[wave][d];
+        __builtin_amdgcn_wave_barrier();
+        if (ok && (peers & below) == 0) wc[wave][d] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        dr[c] = (d << 16) | (before + (uint32_t)__popcll(peers & below));
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;  // one digit per thread
+        uint32_t cw[RS_WAVES], tot = 0;
+        for (int w = 0; w < RS_WAVES; w++) {
+            cw[w] = wc[w][d];
+            tot += cw[w];
+        }
+        const uint32_t tb = block_exclusive_scan_256(tot, tmp);  // tile-local start of digit d
+        gbase[d] = off[(int64_t)d * ntiles + blockIdx.x] - tb;  // modulo 2^32
+        uint32_t acc = tb;
+        for (int w = 0; w < RS_WAVES; w++) {
+            wc[w][d] = acc;
+            acc += cw[w];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < RS_ITEMS; c++) {
+        const int64_t i = base + (int64_t)c * 64 + lane;
+        if (i < n) {
+            const uint32_t li = wc[wave][dr[c] >> 16] + (dr[c] & 0xFFFFu);
+            sk[li] = k[c];
+            if (HASV) sv[li] = v[HASV ? c : 0];
+        }
+    }
+    __syncthreads();
+    const int cnt = (int)min<int64_t>(RS_TILE, n - tile0);
+    for (int li = threadIdx.x; li < cnt; li += RS_THREADS) {
+        const uint64_t key = sk[li];
+        const uint32_t pos = gbase[(uint32_t)(key >> shift) & 255u] + (uint32_t)li;
+        kout[pos] = key;
+        if (HASV) vout[pos] = sv[li];
     }
 }
 
-__device__ __forceinline__ bool greater_kv(uint64_t ka, uint64_t va, uint64_t kb, uint64_t vb) {
-    return ka > kb || (ka == kb && va > vb);
-}
-
-template <bool HASV>
-__global__ __launch_bounds__(256) void k_bucket_local_sort(const uint32_t *boff, int64_t nb,
-                                                           const uint64_t *k2, const uint64_t *v2,
-                                                           uint64_t *key, uint64_t *val,
-                                                           uint32_t *big, uint32_t *nbig) {
-    __shared__ uint64_t sk[LOCAL_MAX];
-    __shared__ uint64_t sv[HASV ? LOCAL_MAX : 1];
-    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        uint32_t start = boff[b], end = boff[b + 1];
-        uint32_t sz = end - start;
-        if (sz == 0) continue;
-        if (sz > (uint32_t)LOCAL_MAX) {
-            if (threadIdx.x == 0) {
-                uint32_t slot = atomicAdd(nbig, 1u);
-                big[slot] = (uint32_t)b;
-            }
-            continue;
-        }
-        for (uint32_t i = threadIdx.x; i < sz; i += blockDim.x) {
-            sk[i] = k2[start + i];
-            if (HASV) sv[i] = v2[start + i];
-        }
-        __syncthreads();
-        uint32_t p2 = 1;
-        while (p2 < sz) p2 <<= 1;
-        for (uint32_t k = 2; k <= p2; k <<= 1) {
-            // mirror step, then half-cleaners; the smaller element always goes low
-            for (uint32_t i = threadIdx.x; i < p2 / 2; i += blockDim.x) {
-                uint32_t half = k >> 1;
-                uint32_t lo = (i / half) * k + (i % half);
-                uint32_t hi = lo ^ (k - 1);
-                if (hi < sz) {
-                    uint64_t a = sk[lo], c = sk[hi];
-                    uint64_t av = HASV ? sv[lo] : 0, cv = HASV ? sv[hi] : 0;
-                    if (greater_kv(a, av, c, cv)) {
-                        sk[lo] = c; sk[hi] = a;
-                        if (HASV) { sv[lo] = cv; sv[hi] = av; }
-                    }
-                }
-            }
-            __syncthreads();
-            for (uint32_t j = k >> 2; j >= 1; j >>= 1) {
-                for (uint32_t i = threadIdx.x; i < p2 / 2; i += blockDim.x) {
-                    uint32_t lo = (i / j) * (2 * j) + (i % j);
-                    uint32_t hi = lo + j;
-                    if (hi < sz) {
-                        uint64_t a = sk[lo], c = sk[hi];
-                        uint64_t av = HASV ? sv[lo] : 0, cv = HASV ? sv[hi] : 0;
-                        if (greater_kv(a, av, c, cv)) {
-                            sk[lo] = c; sk[hi] = a;
-                            if (HASV) { sv[lo] = cv; sv[hi] = av; }
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (uint32_t i = threadIdx.x; i < sz; i += blockDim.x) {
-            key[start + i] = sk[i];
-            if (HASV) val[start + i] = sv[i];
-        }
-        __syncthreads();
-    }
-}
-
-// Buckets larger than LDS: the same network in global memory, one workgroup each.
-template <bool HASV>
-__global__ __launch_bounds__(1024) void k_bucket_big_sort(const uint32_t *boff, const uint32_t *big,
-                                                          const uint32_t *nbig, uint64_t *k2,
-                                                          uint64_t *v2, uint64_t *key,
-                                                          uint64_t *val) {
-    uint32_t count = *nbig;
-    for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
-        uint32_t b = big[t];
-        uint32_t start = boff[b], sz = boff[b + 1] - start;
-        uint64_t *sk = k2 + start;
-        uint64_t *sv = HASV ? v2 + start : nullptr;
-        uint32_t p2 = 1;
-        while (p2 < sz) p2 <<= 1;
-        for (uint32_t k = 2; k <= p2; k <<= 1) {
-            for (uint32_t i = threadIdx.x; i < p2 / 2; i += blockDim.x) {
-                uint32_t half = k >> 1;
-                uint32_t lo = (i / half) * k + (i % half);
-                uint32_t hi = lo ^ (k - 1);
-                if (hi < sz) {
-                    uint64_t a = sk[lo], c = sk[hi];
-                    uint64_t av = HASV ? sv[lo] : 0, cv = HASV ? sv[hi] : 0;
-                    if (greater_kv(a, av, c, cv)) {
-                        sk[lo] = c; sk[hi] = a;
-                        if (HASV) { sv[lo] = cv; sv[hi] = av; }
-                    }
-                }
-            }
-            __syncthreads();
-            for (uint32_t j = k >> 2; j >= 1; j >>= 1) {
-                for (uint32_t i = threadIdx.x; i < p2 / 2; i += blockDim.x) {
-                    uint32_t lo = (i / j) * (2 * j) + (i % j);
-                    uint32_t hi = lo + j;
-                    if (hi < sz) {
-                        uint64_t a = sk[lo], c = sk[hi];
-                        uint64_t av = HASV ? sv[lo] : 0, cv = HASV ? sv[hi] : 0;
-                        if (greater_kv(a, av, c, cv)) {
-                            sk[lo] = c; sk[hi] = a;
-                            if (HASV) { sv[lo] = cv; sv[hi] = av; }
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (uint32_t i = threadIdx.x; i < sz; i += blockDim.x) {
-            key[start + i] = sk[i];
-            if (HASV) val[start + i] = sv[i];
-        }
-        __syncthreads();
-    }
-}
-
-template <bool HASV>
-static void sort_impl(uint64_t *key, uint64_t *val, int64_t n, int shift, int bucket_bits,
-                      Workspace &ws, hipStream_t s) {
+void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Workspace &ws,
+                hipStream_t s) {
     if (n <= 1) return;
     if (n > 0xFFFFFFF0LL) throw Error(MJ_ECAPACITY, "sort of more than 2^32 elements");
-    int64_t nb = 1LL << bucket_bits;
-    uint32_t *cnt = ws.get_n<uint32_t>(nb + 1);
-    uint32_t *boff = ws.get_n<uint32_t>(nb + 1);
-    uint32_t *fillc = ws.get_n<uint32_t>(nb + 1);
-    uint32_t *big = ws.get_n<uint32_t>(nb + 1);
-    uint32_t *nbig = ws.get_n<uint32_t>(4);
+    int passes[8], np = 0;
+    for (int p = 0; p < 8; p++)
+        if ((key_mask >> (8 * p)) & 0xFFu) passes[np++] = p;
+    if (np == 0) return;
+    const int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+    if (ntiles > 0x7FFFFFFFLL || 256 * ntiles > 0xFFFFFFF0LL)
+        throw Error(MJ_ECAPACITY, "radix_sort: too many tiles");
+    uint32_t *cnt = ws.get_n<uint32_t>(256 * ntiles + 1);
+    uint32_t *off = ws.get_n<uint32_t>(256 * ntiles + 1);
     uint64_t *k2 = ws.get_n<uint64_t>(n);
-    uint64_t *v2 = HASV ? ws.get_n<uint64_t>(n) : nullptr;
-    fill_u32(cnt, 0, nb, s);
-    fill_u32(fillc, 0, nb, s);
-    fill_u32(nbig, 0, 1, s);
-    unsigned g = grid_for(n, 256, 16384);
-    hipLaunchKernelGGL(k_bucket_hist<HASV>, dim3(g), dim3(256), 0, s, key, n, shift, cnt);
-    MJ_LAUNCH_CHECK();
-    exclusive_scan_u32(cnt, boff, nb, ws, s);
-    hipLaunchKernelGGL(k_bucket_scatter<HASV>, dim3(g), dim3(256), 0, s, key, val, n, shift, boff,
-                       fillc, k2, v2);
-    MJ_LAUNCH_CHECK();
-    unsigned gl = (unsigned)std::min<int64_t>(nb, 1 << 16);
-    hipLaunchKernelGGL(k_bucket_local_sort<HASV>, dim3(gl), dim3(256), 0, s, boff, nb, k2, v2, key,
-                       val, big, nbig);
-    MJ_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_bucket_big_sort<HASV>, dim3(64), dim3(1024), 0, s, boff, big, nbig, k2, v2,
-                       key, val);
-    MJ_LAUNCH_CHECK();
-}
-
-void sort_pairs(uint64_t *key, uint64_t *val, int64_t n, int shift, int bucket_bits,
-                Workspace &ws, hipStream_t s) {
-    if (bucket_bits < 1 || bucket_bits > 24 || shift < 0 || shift > 63)
-        throw Error(MJ_EINVAL, "sort_pairs: bad bucket configuration");
-    if (val)
-        sort_impl<true>(key, val, n, shift, bucket_bits, ws, s);
-    else
-        sort_impl<false>(key, nullptr, n, shift, bucket_bits, ws, s);
+    uint64_t *v2 = val ? ws.get_n<uint64_t>(n) : nullptr;
+    uint64_t *ka = key, *va = val, *kb = k2, *vb = v2;
+    for (int t = 0; t < np; t++) {
+        const int shift = 8 * passes[t];
+        hipLaunchKernelGGL(k_rs_tile_counts, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, ka, n,
+                           shift, ntiles, cnt);
+        MJ_LAUNCH_CHECK();
+        exclusive_scan_u32(cnt, off, 256 * ntiles, ws, s);
+        if (val)
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s,
+                               ka, va, kb, vb, n, shift, ntiles, off);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s,
+                               ka, nullptr, kb, nullptr, n, shift, ntiles, off);
+        MJ_LAUNCH_CHECK();
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (ka != key) {
+        MJ_HIP(hipMemcpyAsync(key, ka, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+        if (val) MJ_HIP(hipMemcpyAsync(val, va, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+    }
 }
 
 }  // namespace mj

@@ -327,14 +327,63 @@ __global__ void k_bin_pairs(const uint64_t *pairs, int64_t n, VSet A, VSet B, in
     if (threadIdx.x < NBIN && local[threadIdx.x]) atomicAdd(&counts[threadIdx.x], local[threadIdx.x]);
 }
 
-__global__ void k_bin_scatter(const uint8_t *bin, int64_t n, const uint32_t *boff, uint32_t *fill,
-                              int64_t *sel) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) {
-        int b = bin[i];
-        uint32_t p = boff[b] + atomicAdd(&fill[b], 1u);
-        sel[p] = i;
+// Scatter pair indices into bin order.  Few bins, so most lanes of a wave share one:
+// lanes with equal bins find each other with one ballot per bin bit, each wave counts its
+// bins in LDS, and a block reserves its range of each bin with one global atomic.
+constexpr int BS_ITEMS = 16;
+constexpr int BS_BINS = 16;  // >= BP_MAX_C + 3, a power of two
+static_assert(BP_MAX_C + 3 <= BS_BINS, "bin count");
+
+__device__ __forceinline__ uint64_t bin_peers(uint32_t b, uint64_t valid) {
+    uint64_t peers = valid;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const bool bit = (b >> k) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+__global__ __launch_bounds__(256) void k_bin_scatter(const uint8_t *bin, int64_t n,
+                                                     const uint32_t *boff, uint32_t *fill,
+                                                     int64_t *sel) {
+    __shared__ uint32_t wcnt[4][BS_BINS];
+    __shared__ uint32_t wbase[4][BS_BINS];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane < BS_BINS) wcnt[wave][lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * 256 * BS_ITEMS + (int64_t)wave * 64 * BS_ITEMS;
+    uint32_t br[BS_ITEMS];  // bin << 16 | rank inside the wave's span
+#pragma unroll
+    for (int c = 0; c < BS_ITEMS; c++) {
+        const int64_t i = base + (int64_t)c * 64 + lane;
+        const bool ok = i < n;
+        const uint32_t b = ok ? (uint32_t)bin[i] & (BS_BINS - 1) : 0u;
+        const uint64_t peers = bin_peers(b, __ballot(ok));
+        const uint32_t before = wcnt[wave][b];
+        __builtin_amdgcn_wave_barrier();
+        if (ok && (peers & below) == 0) wcnt[wave][b] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        br[c] = (b << 16) | (before + (uint32_t)__popcll(peers & below));
+    }
+    __syncthreads();
+    if (threadIdx.x < BS_BINS) {
+        const int b = threadIdx.x;
+        uint32_t total = 0;
+        for (int w = 0; w < 4; w++) total += wcnt[w][b];
+        uint32_t acc = total ? boff[b] + atomicAdd(&fill[b], total) : 0u;
+        for (int w = 0; w < 4; w++) {
+            wbase[w][b] = acc;
+            acc += wcnt[w][b];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < BS_ITEMS; c++) {
+        const int64_t i = base + (int64_t)c * 64 + lane;
+        if (i < n) sel[wbase[wave][br[c] >> 16] + (br[c] & 0xFFFFu)] = i;
     }
 }
 
@@ -407,8 +456,10 @@ int64_t verify_pairs(const uint64_t *pairs, int64_t n, const DevStrings &A, cons
     uint32_t hoff[NB + 1];
     memcpy(hoff, host_scratch, sizeof(hoff));
     if (hoff[NB] != hoff[NB - 1]) throw Error(MJ_EINVAL, "pair names a string id out of range");
-    hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, bin, n, boff,
-                       fillc, sel);
+    const int64_t sblocks = (n + 256 * BS_ITEMS - 1) / (256 * BS_ITEMS);
+    if (sblocks > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many pairs for one verification");
+    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)sblocks), dim3(256), 0, s, bin, n, boff, fillc,
+                       sel);
     MJ_LAUNCH_CHECK();
     for (int b = 0; b < NB - 1; b++) {
         int64_t cnt = (int64_t)hoff[b + 1] - hoff[b];

@@ -223,6 +223,28 @@ def test_search_matches_oracle(mj):
     index.close()
 
 
+def test_search_few_queries_large_index(mj):
+    """Query ids span far fewer bits than index ids (3 queries, 6,000 index strings):
+    the candidate pairs must still be deduplicated over the full index id range."""
+    import torch
+    say("search: 3 queries against 6,000 strings")
+    S = dg.dna_small(seed=22, n_clusters=600, copies=10)
+    rng = np.random.default_rng(5)
+    qids = rng.choice(S.n, size=3, replace=False)
+    mask = np.ones(S.n, bool)
+    mask[qids] = False
+    I, Q = S.subset(np.nonzero(mask)[0]), S.subset(np.sort(qids))
+    kq = dg.k_fraction(Q.lengths(), 1, 10)
+    ki = dg.k_fraction(I.lengths(), 1, 10)
+    index = mj.Index(dev(mj, I), mj.Params(q=4, k_per_string=torch.from_numpy(ki).cuda(), t_div=1))
+    got, st = index.search(dev(mj, Q), k_per_query=torch.from_numpy(kq).cuda())
+    cand, want = oracle.search(I.chars, I.offsets, oracle.make_params(4, 4, k_per_string=ki, t_div=1),
+                               Q.chars, Q.offsets, oracle.make_params(4, 4, k_per_string=kq, t_div=1))
+    assert st["candidates"] == len(cand)
+    assert len(want) > 0 and np.array_equal(got, want)
+    index.close()
+
+
 # ---------------------------------------------------------------- full workloads
 def test_dna_small_workload_identical(mj):
     say("dna_small full (1,000 strings, K=60)")
