@@ -260,6 +260,64 @@ def serve(args):
     print(json.dumps(line))
 
 
+def characterise(args):
+    """Synthetic analogues of the paper's characterisation (Sec. 5): the distribution of
+    partitions per string around T (Fig. 2, T = 100 on long DNA, T = 25 on protein), the
+    T sweep of recall and time (Figs. 3-4, T = K/5 .. K) and the stage split as K grows
+    (Fig. 5), all on the GPU path.  One JSON line per measurement."""
+    import torch
+    import paper_1810_08833_amd as mj
+    from paper_1810_08833_amd import datagen as dg
+    torch.cuda.set_device(0)
+
+    def emit(kind, **kw):
+        print(json.dumps(dict(kind=kind, **kw)), flush=True)
+
+    # Fig. 2: partitions per string at a fixed T
+    for name, make_s, q, T in (("dna_long", dg.dna_long, 5, 100), ("protein", dg.protein, 4, 25)):
+        S = make_s()
+        ds = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
+        rec = mj.partition(ds, mj.Params(q=q, k=1, t_fixed=T))
+        per = np.bincount(rec["sid"], minlength=S.n)
+        # only strings whose radius formula gives r >= 1 (shorter ones are clamped)
+        long_enough = S.lengths() - q + 1 >= 3 * T + 2
+        c = per[long_enough]
+        emit("partitions_per_string", workload=name, T=T, strings=int(c.size),
+             excluded_short=int(S.n - c.size),
+             mean=float(c.mean()), std=float(c.std()),
+             quantiles={str(p): float(np.percentile(c, p)) for p in (1, 5, 25, 50, 75, 95, 99)},
+             within_20pct=float(np.mean(np.abs(c - T) <= 0.2 * T)),
+             cdf={str(f): float(np.mean(c <= f * T)) for f in (0.5, 0.75, 0.9, 1.0, 1.1, 1.25, 1.5)})
+        del ds
+
+    # Figs. 3-5: recall, time and stage split on long DNA for several K and T = K/t_div
+    S = dg.dna_long()
+    ds = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
+    tp = intra_cluster_pairs(S)
+    for K in (100, 150, 200, 250):
+        truth_ctx = mj.Context(0)
+        truth = tp[mj.verify(ds, mj.Params(q=5, k=K), tp, ctx=truth_ctx)]
+        for t_div in (5, 4, 3, 2, 1):
+            params = mj.Params(q=5, k=K, t_div=t_div)
+            ctx = mj.Context(0)
+            for _ in range(2):
+                out, st = mj.join(ds, params, ctx=ctx)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            stats = []
+            for _ in range(3):
+                out, st = mj.join(ds, params, ctx=ctx)
+                stats.append(st)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / 3
+            emit("t_sweep", workload="dna_long", K=K, t_div=t_div, T=int(-(-K // t_div)),
+                 recall=float(np.isin(truth, out).mean()) if len(truth) else 1.0,
+                 true_pairs=int(len(truth)), candidates=int(st["candidates"]),
+                 output=int(len(out)), ms_per_join=ms,
+                 stage_ms={k: float(np.mean([x["stage_ms"][k] for x in stats]))
+                           for k in mj.STAGES[:7]})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +333,8 @@ def main():
     ap.add_argument("--serve-t-div", type=int, default=2)
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=int, default=32)
+    ap.add_argument("--characterise", action="store_true",
+                    help="partition counts around T, T sweep and stage split (JSON lines)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain copy of this many GiB (rocprofv3 counter scale)")
     args = ap.parse_args()
@@ -288,6 +348,9 @@ def main():
         return
     if args.serve:
         serve(args)
+        return
+    if args.characterise:
+        characterise(args)
         return
 
     import torch

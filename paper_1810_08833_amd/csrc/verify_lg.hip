@@ -376,6 +376,9 @@ static int nwl_for(int nw, int g) {
 
 int persist_max_c() { return (11 * 8 - 1) / 2; }
 
+// Calls with fewer pairs use a fixed configuration instead of timing the choices.
+constexpr int64_t TUNE_MIN_PAIRS = 4096;
+
 // ---------------------------------------------------------------- longest-first order
 constexpr int LPT_BINS = 4096;
 
@@ -510,9 +513,16 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     const int ci = std::min(cmax, 63);
     int best_g = tune ? tune->best_g[ci][npi] : 0;
     int best_blocks = tune ? tune->best_blocks[ci][npi] : 0;
+    if (best_g == 0 && n < TUNE_MIN_PAIRS) {
+        // a small call leaves most of the chip idle: the most lanes per pair (shortest
+        // path per pair); timing the choices would cost more than the work
+        for (int g : G_CHOICES)
+            if (nwl_for(nw, g) != 0 && (g == 1 || nwl_for(nw, g / 2) > 1)) best_g = g;
+        best_blocks = 2048;
+    }
     if (best_g == 0) {
         // time each (lanes per pair, resident workgroups) once on this call's pairs and
-        // keep the fastest; small calls are not representative and are not cached
+        // keep the fastest
         hipEvent_t e0, e1;
         MJ_HIP(hipEventCreate(&e0));
         MJ_HIP(hipEventCreate(&e1));
@@ -541,7 +551,7 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        if (tune && n >= 4096) {
+        if (tune) {
             tune->best_g[ci][npi] = best_g;
             tune->best_blocks[ci][npi] = best_blocks;
         }
