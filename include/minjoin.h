@@ -100,7 +100,7 @@ typedef struct {
     int64_t pair_tests;  /* record pairs tested by the filters */
     int64_t candidates;  /* distinct candidate pairs */
     int64_t output;      /* pairs with ED <= K */
-    int64_t band_cells;  /* (columns processed) x (band width) summed over candidates */
+    int64_t band_cells;  /* (columns processed) x (K + 1 band diagonals), summed over candidates */
     float stage_ms[8];
     /* Device time of the hot kernels, summed over their launches in the call (HIP events
      * recorded on the call's stream immediately around each launch), and the launch

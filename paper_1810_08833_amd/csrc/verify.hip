@@ -1,9 +1,13 @@
 // Verification (Alg. 3; Sec. 3): decide ED(x, y) <= K for every candidate pair.
 //
-// Bit-parallel path (one pair per lane).  The longer string is the pattern (rows), the
-// shorter the text (columns).  Column j keeps the vertical deltas of a window of NW
-// 32-bit words of rows; the window starts at word floor((j-1)/32) - ceil(K/32), so it
-// covers every row i with |i - j| <= K when NW >= 2 ceil(K/32) + 1, and it moves by one
+// Bit-parallel path (one pair per lane).  The longer string is the pattern (rows, length
+// m), the shorter the text (columns, length n), d = m - n <= K.  A path of cost <= K that
+// visits diagonal k = i - j makes at least |k| + |d - k| edits, so it stays within the
+// K + 1 diagonals lo = ceil((d-K)/2) <= k <= hi = floor((d+K)/2) (Ukkonen's band, tightened
+// by the length difference).  Column j keeps the vertical deltas of a window of 32-bit
+// words of rows (word w holds rows 32w+1 .. 32w+32); in block b (columns 32b+1 .. 32b+32)
+// the window starts at word b + floor(lo/32), so it covers rows j+lo .. j+hi of every
+// column with ceil(hi/32) + 1 - floor(lo/32) <= ceil(K/32) + 2 words, and it moves by one
 // word every 32 columns for every lane at once.  Each column applies Myers' bit-vector
 // recurrence for global edit distance (hin = +1 at the top) to the whole window as one
 // multi-word integer.  Rows above the window are treated as one more than their left
@@ -42,7 +46,8 @@ int verify_planes(int bits) {
     return 8;
 }
 
-constexpr int BP_MAX_C = 8;  // ceil(K/32) handled by the bit-parallel kernels (K <= 256)
+// ceil(K/32) handled by the bit-parallel kernels (K <= 416); a window of c + 2 words
+constexpr int BP_MAX_C = 13;
 
 template <int NW, int NP>
 __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ pairs,
@@ -67,17 +72,19 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
         int64_t offy = a_is_x ? B.off[ib] : A.off[ia];
         int32_t mp = a_is_x ? ma : mb, nt = a_is_x ? mb : ma;
         uint8_t result;
-        const int c = (K + 31) >> 5;
+        const int dlen = mp - nt;
+        const int blo = -((K - dlen) >> 1), bhi = (K + dlen) >> 1;  // band diagonals
+        const int w0 = -((31 - blo) >> 5);                          // floor(blo / 32)
         if (mp - nt > K) {
             result = 0;
         } else if (nt == 0) {
             result = mp <= K;
-        } else if (2 * c + 1 > NW) {
+        } else if (((bhi + 31) >> 5) + 1 - w0 > NW) {
             result = 2;  // not handled by this instance (host bins pairs so this never happens)
         } else {
             uint32_t Pv[NW], Mv[NW], V[NW];
             uint32_t PL[NP][NW];
-            int wlo = -c;
+            int wlo = w0;
 #pragma unroll
             for (int s = 0; s < NW; s++) {
                 int w = wlo + s;
@@ -89,7 +96,7 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
                 for (int p = 0; p < NP; p++)
                     PL[p][s] = real ? load_word(PX + p * pwx, offx + 32 * (int64_t)w) : 0u;
             }
-            int S = c >= 1 ? 32 * (c - 1) : 32;  // value of the bottom row of word 0
+            int S = abs(32 * w0 + 32);  // column 0: row i holds |i| (rows <= 0 are made up)
             bool rejected = false;
             int jb = 0;
             for (; jb < nt; jb += 32) {
@@ -162,7 +169,7 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
                     S += dS;
                 }
             }
-            my_cells = (uint64_t)min(jb, nt) * (uint64_t)(2 * K + 1);
+            my_cells = (uint64_t)min(jb, nt) * (uint64_t)(bhi - blo + 1);
             if (rejected) {
                 result = 0;
             } else {
@@ -291,7 +298,10 @@ __global__ __launch_bounds__(64) void k_verify_dp(const uint64_t *__restrict__ p
         }
         if (lane == 0) {
             flags[pi] = result;
-            atomicAdd(cells, (unsigned long long)(rows_done * (uint64_t)W));
+            // algorithmic work: the K + 1 diagonals a path of cost <= K can visit
+            const int dd = ny - mx;
+            const uint64_t band = (uint64_t)(((K + dd) >> 1) + ((K - dd) >> 1) + 1);
+            atomicAdd(cells, (unsigned long long)(rows_done * band));
         }
     }
 }
@@ -395,13 +405,18 @@ static BpKernel bp_kernel_for(int c) {
     switch (c) {
         case 0: return k_verify_bp<1, NP>;
         case 1: return k_verify_bp<3, NP>;
-        case 2: return k_verify_bp<5, NP>;
-        case 3: return k_verify_bp<7, NP>;
-        case 4: return k_verify_bp<9, NP>;
-        case 5: return k_verify_bp<11, NP>;
-        case 6: return k_verify_bp<13, NP>;
-        case 7: return k_verify_bp<15, NP>;
-        default: return k_verify_bp<17, NP>;
+        case 2: return k_verify_bp<4, NP>;
+        case 3: return k_verify_bp<5, NP>;
+        case 4: return k_verify_bp<6, NP>;
+        case 5: return k_verify_bp<7, NP>;
+        case 6: return k_verify_bp<8, NP>;
+        case 7: return k_verify_bp<9, NP>;
+        case 8: return k_verify_bp<10, NP>;
+        case 9: return k_verify_bp<11, NP>;
+        case 10: return k_verify_bp<12, NP>;
+        case 11: return k_verify_bp<13, NP>;
+        case 12: return k_verify_bp<14, NP>;
+        default: return k_verify_bp<15, NP>;
     }
 }
 

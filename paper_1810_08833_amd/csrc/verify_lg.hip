@@ -1,7 +1,8 @@
 // Batched verification (Alg. 3; Sec. 3): one persistent launch for all candidates.
 //
-// A pair is owned by a lane group of G lanes; the band window of NW = NWL * G words is
-// split into G contiguous chunks, one per lane.  Per column each lane runs Myers'
+// A pair is owned by a lane group of G lanes; the band window (the K + 1 diagonals a path
+// of cost <= K can visit, as in the per-lane kernel) of NW = NWL * G words is split into
+// G contiguous chunks, one per lane.  Per column each lane runs Myers'
 // bit-vector recurrence on its chunk; the two cross-lane dependencies of a column are
 // resolved inside the group: the carry of the multi-word addition with a carry-lookahead
 // scan over the lanes (each lane adds with carry-in 0, reports carry-out and whether its
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
     const int leader_lane = lane - g;
     bool active = false, exhausted = false;
     int64_t pi = 0;
-    int32_t K = 0, mp = 0, nt = 0, wlo = 0, jb = 0, S = 0;
+    int32_t K = 0, mp = 0, nt = 0, wlo = 0, jb = 0, S = 0, band = 0;
     int64_t offx = 0, offy = 0, pwx = 0, pwy = 0;
     const uint32_t *PX = nullptr, *PY = nullptr;
     uint32_t Pv[NWL], Mv[NWL], V[NWL], PL[NP][NWL];
@@ -113,14 +114,16 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
                 offy = a_is_x ? B.off[ib] : A.off[ia];
                 mp = a_is_x ? ma : mb;
                 nt = a_is_x ? mb : ma;
-                const int c = (K + 31) >> 5;
+                const int dlen = mp - nt;
+                const int blo = -((K - dlen) >> 1), bhi = (K + dlen) >> 1;  // band diagonals
+                const int w0 = -((31 - blo) >> 5);                          // floor(blo / 32)
                 uint8_t result = 0;
                 bool trivial = true;
                 if (mp - nt > K) {
                     result = 0;
                 } else if (nt == 0) {
                     result = mp <= K;
-                } else if (2 * c + 1 > NW) {
+                } else if (((bhi + 31) >> 5) + 1 - w0 > NW) {
                     result = 2;
                 } else {
                     trivial = false;
@@ -129,9 +132,10 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
                     if (g == 0) flags[pi] = result;
                 } else {
                     active = true;
-                    wlo = -c;
+                    wlo = w0;
                     jb = 0;
-                    S = c >= 1 ? 32 * (c - 1) : 32;
+                    S = abs(32 * w0 + 32);  // column 0: row i holds |i| (rows <= 0 made up)
+                    band = bhi - blo + 1;
 #pragma unroll
                     for (int s = 0; s < NWL; s++) {
                         int w = wlo + g * NWL + s;
@@ -225,7 +229,7 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
             }
         }
         jb += cols;
-        if (g == 0) my_cells += (uint64_t)cols * (uint64_t)(2 * K + 1);
+        if (g == 0) my_cells += (uint64_t)cols * (uint64_t)band;
         const int S0 = __shfl(S, leader_lane, 64);
         int dl[NWL];
         int E = 0;
@@ -331,7 +335,7 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
 using PersistKernel = void (*)(const uint64_t *, const int64_t *, int64_t, VSet, VSet, int,
                                uint8_t *, unsigned long long *, unsigned long long *);
 
-constexpr int NWL_CHOICES[] = {1, 2, 3, 4, 5, 6, 9, 11};
+constexpr int NWL_CHOICES[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 11};
 constexpr int G_CHOICES[] = {1, 2, 4, 8};
 
 template <int NWL, int G>
@@ -353,6 +357,8 @@ static PersistKernel by_nwl(int nwl, int np) {
         case 4: return by_np<4, G>(np);
         case 5: return by_np<5, G>(np);
         case 6: return by_np<6, G>(np);
+        case 7: return by_np<7, G>(np);
+        case 8: return by_np<8, G>(np);
         case 9: return by_np<9, G>(np);
         default: return by_np<11, G>(np);
     }
@@ -374,7 +380,8 @@ static int nwl_for(int nw, int g) {
     return 0;
 }
 
-int persist_max_c() { return (11 * 8 - 1) / 2; }
+// The window needs ceil(K/32) + 2 words (at most 11 * 8); K <= 2047 keeps c <= 64.
+int persist_max_c() { return 64; }
 
 // Calls with fewer pairs use a fixed configuration instead of timing the choices.
 constexpr int64_t TUNE_MIN_PAIRS = 4096;
@@ -496,7 +503,7 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     if (hv[1]) throw Error(MJ_EINVAL, "pair names a string id out of range");
     const int cmax = (int)hv[0];
     if (cmax > persist_max_c())
-        throw Error(MJ_ECAPACITY, "threshold K above the batched verifier's band limit (K <= 1376)");
+        throw Error(MJ_ECAPACITY, "threshold K above the batched verifier's band limit (K <= 2047)");
     fill_u32(cnt, 0, LPT_BINS, s);
     fill_u32(fillc, 0, LPT_BINS, s);
     hipLaunchKernelGGL(k_lpt_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, pairs, n, va, vb, cnt);
@@ -508,7 +515,7 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
                        off, fillc, order);
     MJ_LAUNCH_CHECK();
 
-    const int nw = 2 * cmax + 1;
+    const int nw = cmax == 0 ? 1 : cmax + 2;
     const int npi = np / 2 - 1;
     const int ci = std::min(cmax, 63);
     int best_g = tune ? tune->best_g[ci][npi] : 0;

@@ -156,6 +156,21 @@ def near_threshold_pairs(rng, K, count, sigma=4):
         a, b = len(strs), len(strs) + 1
         strs += [x, y]
         pairs.append((a << 32) | b if t % 2 == 0 else (b << 32) | a)
+    # paths along the edges of the band: y drops a symbols at one end of x and gains b
+    # random symbols at the other, so the cheapest alignment runs along diagonal a (or
+    # -b) with a + b in {K-1, K, K+1} and length difference d = a - b
+    for d in sorted({0, 1, K // 3, max(0, K - 1), K}):
+        for total in (K - 1, K, K + 1):
+            if total < d or (total - d) % 2:
+                continue
+            a_, b_ = (total + d) // 2, (total - d) // 2
+            L = int(rng.integers(a_ + 8, a_ + 3 * K + 40))
+            x = rng.integers(0, sigma, L).astype(np.uint8)
+            extra = rng.integers(0, sigma, b_).astype(np.uint8)
+            for y in (np.concatenate([x[a_:], extra]), np.concatenate([extra, x[:L - a_]])):
+                i0 = len(strs)
+                strs += [x, y]
+                pairs.append((i0 << 32) | (i0 + 1))
     # a few degenerate ones: empty strings and length gaps at the limit
     e = len(strs)
     strs += [np.zeros(0, np.uint8), rng.integers(0, sigma, K).astype(np.uint8),
