@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "mj_common.h"
@@ -238,13 +239,14 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     const uint8_t *__restrict__ chars, const int64_t *__restrict__ off, int32_t n, int64_t total,
     int q, int bits, uint64_t salt, const uint64_t *__restrict__ table,
     const uint16_t *__restrict__ rank, const int32_t *__restrict__ rr, int TP, int H,
-    const TileDesc *__restrict__ tdesc, uint64_t *__restrict__ bitmap) {
+    const TileDesc *__restrict__ tdesc, int aligned4, uint64_t *__restrict__ bitmap) {
     constexpr bool RANKED = sizeof(V) == 4;
     constexpr int NRANK = RANKED ? (1 << RANK_MAX_BITS) : 1;
-    __shared__ V bufA[REGION];
-    __shared__ V bufB[REGION];
-    __shared__ uint16_t pinfo[REGION];
-    __shared__ uint8_t ch[REGION + 64];
+    __shared__ __align__(16) V bufA[REGION];
+    __shared__ __align__(16) V bufB[REGION];
+    __shared__ __align__(16) uint16_t pinfo[REGION];
+    __shared__ __align__(16) uint32_t ch32[(REGION + 64) / 4];  // symbols, word-aligned with the input
+    uint8_t *const ch = reinterpret_cast<uint8_t *>(ch32);
     __shared__ uint32_t aflag[REGION / 32];
     __shared__ TileDesc td;
     __shared__ int16_t barg[REGION / AT_BLOCK];
@@ -260,9 +262,21 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         rmin_s = 0x7FFFFFFF;
     }
     if (tid < 32) reinterpret_cast<uint32_t *>(&td)[tid] = reinterpret_cast<const uint32_t *>(tdesc + blockIdx.x)[tid];
-    for (int idx = tid; idx < NR + q; idx += AT_THREADS) {
-        int64_t g = base + idx;
-        ch[idx] = (g >= 0 && g < total) ? chars[g] : (uint8_t)0;
+    // symbols of the region: byte sh + idx of ch holds global position base + idx, with
+    // ch starting at a 4-byte boundary of the input so whole words are copied
+    const int sh = (int)(base & 3);
+    const int64_t chbase = base - sh;
+    for (int k = tid; k < (NR + q + sh + 3) / 4; k += AT_THREADS) {
+        const int64_t gp = chbase + 4 * (int64_t)k;
+        uint32_t w;
+        if (aligned4 && gp >= 0 && gp + 3 < total) {
+            w = reinterpret_cast<const uint32_t *>(chars)[gp >> 2];
+        } else {
+            w = 0;
+            for (int b = 0; b < 4; b++)
+                if (gp + b >= 0 && gp + b < total) w |= (uint32_t)chars[gp + b] << (8 * b);
+        }
+        ch32[k] = w;
     }
     for (int w = tid; w < REGION / 32; w += AT_THREADS) aflag[w] = 0;
     if constexpr (RANKED) {
@@ -275,64 +289,141 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     // hashes: each thread rolls the packed q-gram code over RUN consecutive positions
     {
         constexpr int RUN = REGION / AT_THREADS;
+        static_assert(RUN == 8 || RUN == 16, "positions per thread");
         int lmax = 0, lrmin = 0x7FFFFFFF;
-        uint64_t G = 0;
-        int64_t have_end = -1;  // G is valid for the previous position when it is in the same string
         const int idx0 = tid * RUN;
+        const int64_t g0 = base + idx0;
         int t = 0;
+        int64_t sb0 = 0, se0 = -1;
         if (ns >= 0) {
-            const int64_t g0 = base + idx0;
             for (int k = 1; k < ns; k++) t += (td.off[k] <= g0) ? 1 : 0;
+            sb0 = td.off[t];
+            se0 = td.off[t + 1];
         }
+        // fast path: all RUN positions of the thread hold full q-grams of one string
+        const bool fast = ns >= 0 && q <= 9 && g0 >= sb0 && g0 + RUN + q - 1 <= se0 &&
+                          idx0 + RUN <= NR;
+        if (fast) {
+            // bytes idx0 .. idx0 + RUN + 7 of the region (the first q-gram and the rest),
+            // and the RUN - 1 symbols entering the window, idx0 + q .. idx0 + q + RUN - 2
+            constexpr int NA = RUN / 4 + 3;
+            uint32_t A[NA], N[RUN / 4];
+            {
+                const int o = idx0 + sh;
+                uint32_t W[NA + 1];
 #pragma unroll
-        for (int j = 0; j < RUN; j++) {
-            const int idx = idx0 + j;
-            if (idx >= NR) break;
-            const int64_t g = base + idx;
-            V h = (V)~0ull;
-            uint16_t info = 0;
-            int32_t r = 0;
-            int64_t sbeg = 0, send = 0;
-            bool valid = g >= 0 && g < total;
-            if (ns >= 0) {
-                while (t + 1 < ns && td.off[t + 1] <= g) t++;
-                sbeg = td.off[t];
-                send = td.off[t + 1];
-                r = td.r[t];
-            } else if (valid) {
-                int32_t sidx = owner_of(off, n, g);
-                sbeg = off[sidx];
-                send = off[sidx + 1];
-                r = rr[sidx];
+                for (int i = 0; i <= NA; i++) W[i] = ch32[(o >> 2) + i];
+#pragma unroll
+                for (int i = 0; i < NA; i++)
+                    A[i] = __builtin_amdgcn_alignbit(W[i + 1], W[i], 8 * (o & 3));
+                const int o2 = o + q;
+                uint32_t W2[RUN / 4 + 1];
+#pragma unroll
+                for (int i = 0; i <= RUN / 4; i++) W2[i] = ch32[(o2 >> 2) + i];
+#pragma unroll
+                for (int i = 0; i < RUN / 4; i++)
+                    N[i] = __builtin_amdgcn_alignbit(W2[i + 1], W2[i], 8 * (o2 & 3));
             }
-            if (valid) {
-                const int64_t i = g - sbeg;
-                const int64_t npos = (send - sbeg) - q + 1;
-                if (i < npos) {
-                    if (have_end == send && i > 0 && j > 0) {
-                        G = ((G << bits) | ch[idx + q - 1]) & gmask;
+            using Code = typename std::conditional<RANKED, uint32_t, uint64_t>::type;
+            Code G = 0;
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                if (k < q) G = (G << bits) | ((A[k >> 2] >> (8 * (k & 3))) & 0xFFu);
+            const Code cmask = (Code)gmask;
+            const int64_t i0 = g0 - sb0;
+            const int64_t npos = (se0 - sb0) - q + 1;
+            const int32_t r = td.r[t];
+            V hv[RUN];
+            uint16_t inf[RUN];
+#pragma unroll
+            for (int j = 0; j < RUN; j++) {
+                if constexpr (RANKED) hv[j] = rank_s[G];
+                else hv[j] = table ? table[G] : mix64((uint64_t)G ^ salt);
+                const int64_t i = i0 + j;
+                const bool interior = (i >= r) && (i <= npos - 1 - r);
+                inf[j] = (uint16_t)((interior ? r : 0) | (i == 0 ? 0x8000 : 0));
+                const bool in_tile = interior && idx0 + j >= H && idx0 + j < H + TP;
+                lrmin = in_tile ? min(lrmin, r) : lrmin;
+                if (j + 1 < RUN) G = ((G << bits) | ((N[j >> 2] >> (8 * (j & 3))) & 0xFFu)) & cmask;
+            }
+            lmax = lrmin < 0x7FFFFFFF ? 31 - __clz(r) : 0;
+            // 16-byte stores of the thread's RUN hash slots and RUN info slots
+            {
+                uint32_t hw[RUN * sizeof(V) / 4];
+#pragma unroll
+                for (int j = 0; j < RUN; j++) {
+                    if constexpr (RANKED) {
+                        hw[j] = (uint32_t)hv[j];
                     } else {
-                        G = 0;
-                        for (int k = 0; k < q; k++) G = (G << bits) | ch[idx + k];
-                        G &= gmask;
+                        hw[2 * j] = (uint32_t)hv[j];
+                        hw[2 * j + 1] = (uint32_t)((uint64_t)hv[j] >> 32);
                     }
-                    have_end = send;
-                    if constexpr (RANKED) h = rank_s[G];
-                    else h = table ? table[G] : mix64(G ^ salt);
+                }
+                uint4 *dst = reinterpret_cast<uint4 *>(bufA + idx0);
+#pragma unroll
+                for (int i = 0; i < (int)(RUN * sizeof(V) / 16); i++)
+                    dst[i] = make_uint4(hw[4 * i], hw[4 * i + 1], hw[4 * i + 2], hw[4 * i + 3]);
+                uint32_t iw[RUN / 2];
+#pragma unroll
+                for (int j = 0; j < RUN / 2; j++) iw[j] = (uint32_t)inf[2 * j] | ((uint32_t)inf[2 * j + 1] << 16);
+                uint4 *di = reinterpret_cast<uint4 *>(pinfo + idx0);
+#pragma unroll
+                for (int i = 0; i < RUN / 8; i++)
+                    di[i] = make_uint4(iw[4 * i], iw[4 * i + 1], iw[4 * i + 2], iw[4 * i + 3]);
+            }
+        } else {
+            uint64_t G = 0;
+            int64_t have_end = -1;  // G is valid for the previous position in the same string
+#pragma unroll
+            for (int j = 0; j < RUN; j++) {
+                const int idx = idx0 + j;
+                if (idx >= NR) break;
+                const int64_t g = base + idx;
+                V h = (V)~0ull;
+                uint16_t info = 0;
+                int32_t r = 0;
+                int64_t sbeg = 0, send = 0;
+                bool valid = g >= 0 && g < total;
+                if (ns >= 0) {
+                    while (t + 1 < ns && td.off[t + 1] <= g) t++;
+                    sbeg = td.off[t];
+                    send = td.off[t + 1];
+                    r = td.r[t];
+                } else if (valid) {
+                    int32_t sidx = owner_of(off, n, g);
+                    sbeg = off[sidx];
+                    send = off[sidx + 1];
+                    r = rr[sidx];
+                }
+                if (valid) {
+                    const int64_t i = g - sbeg;
+                    const int64_t npos = (send - sbeg) - q + 1;
+                    if (i < npos) {
+                        if (have_end == send && i > 0 && j > 0) {
+                            G = ((G << bits) | ch[sh + idx + q - 1]) & gmask;
+                        } else {
+                            G = 0;
+                            for (int k = 0; k < q; k++) G = (G << bits) | ch[sh + idx + k];
+                            G &= gmask;
+                        }
+                        have_end = send;
+                        if constexpr (RANKED) h = rank_s[G];
+                        else h = table ? table[G] : mix64(G ^ salt);
+                    } else {
+                        have_end = -1;
+                    }
+                    const bool interior = (i >= r) && (i <= npos - 1 - r);
+                    info = (uint16_t)((interior ? r : 0) | (i == 0 ? 0x8000 : 0));
+                    if (interior && idx >= H && idx < H + TP) {
+                        lmax = max(lmax, 31 - __clz(r));
+                        lrmin = min(lrmin, r);
+                    }
                 } else {
                     have_end = -1;
                 }
-                const bool interior = (i >= r) && (i <= npos - 1 - r);
-                info = (uint16_t)((interior ? r : 0) | (i == 0 ? 0x8000 : 0));
-                if (interior && idx >= H && idx < H + TP) {
-                    lmax = max(lmax, 31 - __clz(r));
-                    lrmin = min(lrmin, r);
-                }
-            } else {
-                have_end = -1;
+                bufA[idx] = h;
+                pinfo[idx] = info;
             }
-            bufA[idx] = h;
-            pinfo[idx] = info;
         }
         if (lmax > 0) atomicMax(&kmax_s, lmax);
         if (lrmin < 0x7FFFFFFF) atomicMin(&rmin_s, lrmin);
@@ -362,13 +453,16 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 bufB[idx] = pv;
                 bufA[idx] = sv;
             }
-            if ((tid & (AT_BLOCK - 1)) == 0 && idx < NR) barg[idx / AT_BLOCK] = -1;
             if ((tid & (AT_BLOCK - 1)) == AT_BLOCK - 1 && idx - (AT_BLOCK - 1) < NR)
                 bmin[idx / AT_BLOCK] = pv;
-            // at most one lane per block satisfies this (a strict minimum of the block)
+            // at most one lane per block satisfies this (a strict minimum of the block);
+            // the block's first lane records it (the 16 lanes of a block share a wave)
             const bool uniq = idx < NR && hv < before && hv < after;
-            __syncthreads();
-            if (uniq) barg[idx / AT_BLOCK] = (int16_t)idx;
+            const uint64_t um = __ballot(uniq);
+            if ((tid & (AT_BLOCK - 1)) == 0 && idx < NR) {
+                const uint32_t row = (uint32_t)(um >> (tid & 63)) & 0xFFFFu;
+                barg[idx / AT_BLOCK] = row ? (int16_t)(idx + __ffs(row) - 1) : (int16_t)-1;
+            }
         }
         __syncthreads();
         const int NBK = (NR + AT_BLOCK - 1) / AT_BLOCK;
@@ -472,18 +566,42 @@ __global__ void k_anchor_scatter(const uint64_t *bm, int64_t nw, const uint32_t 
 // Partition records between consecutive flagged positions: key f = M(Phi xor S) with
 // Phi the Karp-Rabin polynomial of the content over GF(2^61-1), length folded in as the
 // leading coefficient; payload (string id << 32 | start position).  The owning string
-// comes from the descriptor of the tile holding the partition's first position; symbols
-// are read four at a time from aligned 32-bit words.
+// comes from the descriptor of the tile holding the partition's first position.
+// Horner's rule takes C symbols per step when the alphabet is small (C = 4 for b <= 2
+// bits, C = 2 for b <= 5): Phi <- Phi * B^C + T[x_0 .. x_{C-1}] with the table T of
+// sum_k (x_k + 1) B^(C-1-k) mod 2^61-1 over all 2^(C*b) chunks (in LDS).  Modular
+// arithmetic is exact, so this is the same Phi as one symbol per step.  Symbols come
+// four at a time from aligned 32-bit words; codes are taken modulo 2^b.
 __device__ __forceinline__ uint64_t horner_step(uint64_t h, uint64_t B, uint32_t c) {
     h = mulmod61(h, B) + (uint64_t)c + 1;
     return h >= P61 ? h - P61 : h;
+}
+
+__device__ __forceinline__ uint64_t horner_chunk(uint64_t h, uint64_t BC, uint64_t t) {
+    h = mulmod61(h, BC) + t;
+    return h >= P61 ? h - P61 : h;
+}
+
+__global__ void k_phi_table(int nc, int C, int bits, uint64_t B, uint64_t *__restrict__ T) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nc) return;
+    uint64_t h = 0;
+    for (int k = 0; k < C; k++)
+        h = horner_step(h, B, (uint32_t)(idx >> (bits * (C - 1 - k))) & ((1u << bits) - 1u));
+    T[idx] = h;
 }
 
 __global__ void k_records(const int64_t *__restrict__ apos, int64_t R,
                           const int64_t *__restrict__ off, int32_t n,
                           const uint8_t *__restrict__ chars, int aligned4,
                           const TileDesc *__restrict__ td, int TP, uint64_t B, uint64_t salt_f,
+                          const uint64_t *__restrict__ table, int C, int bits, uint64_t BC,
                           uint64_t *key, uint64_t *val, uint32_t *len) {
+    extern __shared__ uint64_t Ts[];
+    const int nc = C > 1 ? 1 << (C * bits) : 0;
+    for (int t = threadIdx.x; t < nc; t += blockDim.x) Ts[t] = table[t];
+    __syncthreads();
+    const uint32_t m = (1u << bits) - 1u;
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; k < R; k += stride) {
@@ -504,17 +622,32 @@ __global__ void k_records(const int64_t *__restrict__ apos, int64_t R,
         uint64_t h = (uint64_t)L % P61;
         int64_t g = g0;
         if (aligned4) {
-            for (; g < g1 && (g & 3); g++) h = horner_step(h, B, chars[g]);
+            for (; g < g1 && (g & 3); g++) h = horner_step(h, B, C > 1 ? (chars[g] & m) : chars[g]);
             const uint32_t *w = reinterpret_cast<const uint32_t *>(chars);
-            for (; g + 4 <= g1; g += 4) {
-                uint32_t v = w[g >> 2];
-                h = horner_step(h, B, v & 0xFFu);
-                h = horner_step(h, B, (v >> 8) & 0xFFu);
-                h = horner_step(h, B, (v >> 16) & 0xFFu);
-                h = horner_step(h, B, v >> 24);
+            if (C == 4) {
+                for (; g + 4 <= g1; g += 4) {
+                    const uint32_t v = w[g >> 2];
+                    const uint32_t x = ((v & m) << (3 * bits)) | (((v >> 8) & m) << (2 * bits)) |
+                                       (((v >> 16) & m) << bits) | ((v >> 24) & m);
+                    h = horner_chunk(h, BC, Ts[x]);
+                }
+            } else if (C == 2) {
+                for (; g + 4 <= g1; g += 4) {
+                    const uint32_t v = w[g >> 2];
+                    h = horner_chunk(h, BC, Ts[((v & m) << bits) | ((v >> 8) & m)]);
+                    h = horner_chunk(h, BC, Ts[(((v >> 16) & m) << bits) | ((v >> 24) & m)]);
+                }
+            } else {
+                for (; g + 4 <= g1; g += 4) {
+                    const uint32_t v = w[g >> 2];
+                    h = horner_step(h, B, v & 0xFFu);
+                    h = horner_step(h, B, (v >> 8) & 0xFFu);
+                    h = horner_step(h, B, (v >> 16) & 0xFFu);
+                    h = horner_step(h, B, v >> 24);
+                }
             }
         }
-        for (; g < g1; g++) h = horner_step(h, B, chars[g]);
+        for (; g < g1; g++) h = horner_step(h, B, C > 1 ? (chars[g] & m) : chars[g]);
         key[k] = mix64(h ^ salt_f);
         val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
         if (len) len[k] = (uint32_t)L;
@@ -566,6 +699,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
         throw Error(MJ_ECAPACITY, "more than 2^32 partitions per repetition");
     if ((size_t)reps * 8 > HOST_SCRATCH_BYTES) throw Error(MJ_EINVAL, "too many repetitions");
     const int code_bits = p.q * d.bits;
+    const int aligned4 = ((uintptr_t)d.chars & 3) == 0 ? 1 : 0;
 
     // phase 1: anchors of every repetition (Pi seeded with seed + rho), their counts
     int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
@@ -588,7 +722,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
 #define MJ_ANCHORS(R, V)                                                                        \
         hipLaunchKernelGGL((k_anchor_tiles<R, V>), dim3((unsigned)ntiles), dim3(AT_THREADS), 0, s, \
                            d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, rank, \
-                           d.rr, TP, H, ts, bitmap[rho])
+                           d.rr, TP, H, ts, aligned4, bitmap[rho])
         if (rank) {
             if (region == 2048) MJ_ANCHORS(2048, uint32_t); else MJ_ANCHORS(4096, uint32_t);
         } else {
@@ -623,7 +757,18 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     out.reserve(base0 + total + 1, s);
     const uint64_t B = 2 + mix64(p.seed ^ GAMMA_B) % (P61 - 3);
     const uint64_t salt_f = mix64(p.seed + GAMMA);
-    const int aligned4 = ((uintptr_t)d.chars & 3) == 0 ? 1 : 0;
+    // Horner chunk of C symbols and its table (see k_records)
+    const int C = d.bits <= 2 ? 4 : (d.bits <= 5 ? 2 : 1);  // tables of <= 1024 entries
+    uint64_t BC = 1;
+    for (int i = 0; i < C; i++) BC = (uint64_t)(((unsigned __int128)BC * B) % P61);
+    uint64_t *phi_table = nullptr;
+    const int nc = C > 1 ? 1 << (C * d.bits) : 0;
+    if (C > 1) {
+        phi_table = ws.get_n<uint64_t>(nc);
+        hipLaunchKernelGGL(k_phi_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, C, d.bits, B,
+                           phi_table);
+        MJ_LAUNCH_CHECK();
+    }
     int64_t maxR = 0;
     for (int rho = 0; rho < reps; rho++) maxR = std::max(maxR, R[rho]);
     int64_t *apos = ws.get_n<int64_t>(maxR + 1);
@@ -634,10 +779,10 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
         MJ_LAUNCH_CHECK();
         if (R[rho] > 0) {
             int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
-            hipLaunchKernelGGL(k_records, dim3(grid_for(R[rho], 256, 65535)), dim3(256), 0, s, apos,
-                               R[rho], d.offsets, d.n, d.chars, aligned4, ts, TP, B, salt_f,
-                               out.key + base, out.val + base,
-                               out.with_len ? out.len + base : nullptr);
+            hipLaunchKernelGGL(k_records, dim3(grid_for(R[rho], 256, 65535)), dim3(256),
+                               (size_t)nc * 8, s, apos, R[rho], d.offsets, d.n, d.chars, aligned4,
+                               ts, TP, B, salt_f, phi_table, C, d.bits, BC, out.key + base,
+                               out.val + base, out.with_len ? out.len + base : nullptr);
             MJ_LAUNCH_CHECK();
             if (kt) kt->end(tr, s);
         }

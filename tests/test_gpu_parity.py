@@ -87,6 +87,10 @@ CASES = {
     "protein_per_string_K": dict(make=lambda: dg.protein(seed=6, n=1500), q=4, k_frac=(8, 100),
                                  t_div=1),
     "text_q6": dict(make=lambda: dg.text(seed=7, n=1500), q=6, k=120, t_div=2),
+    "alphabet12_q4": dict(make=lambda: dg.from_list(
+        [dg.mutate(np.random.default_rng(900 + i), base, 0.02, 12)
+         for base in [np.random.default_rng(80 + c).integers(0, 12, 600 + 37 * c).astype(np.uint8)
+                      for c in range(40)] for i in range(5)], 12), q=4, k=50, t_div=2, reps=2),
 }
 
 
