@@ -153,9 +153,10 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
                         for (int p = 0; p < NP; p++) eq &= PL[p][s] ^ nt_[p];
                         uint32_t pv = Pv[s], mv = Mv[s];
                         uint32_t xv = eq | mv;
-                        uint64_t sum = (uint64_t)(eq & pv) + pv + carry;
-                        carry = (uint32_t)(sum >> 32);
-                        uint32_t xh = ((uint32_t)sum ^ pv) | eq;
+                        uint32_t co;
+                        const uint32_t sum = __builtin_addc(eq & pv, pv, carry, &co);
+                        carry = co;
+                        uint32_t xh = (sum ^ pv) | eq;
                         uint32_t ph = mv | ~(xh | pv);
                         uint32_t mh = pv & xh;
                         if (s == 0) dS = (int)(ph >> 31) - (int)(mh >> 31);

@@ -171,9 +171,9 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
 #pragma unroll
                 for (int p = 0; p < NP; p++) eq &= PL[p][s] ^ ntm[p];
                 eqv[s] = eq;
-                uint64_t x = (uint64_t)(eq & Pv[s]) + Pv[s] + carry;
-                sm[s] = (uint32_t)x;
-                carry = (uint32_t)(x >> 32);
+                uint32_t co;
+                sm[s] = __builtin_addc(eq & Pv[s], Pv[s], carry, &co);  // carry chain in a lane mask
+                carry = co;
                 all1 &= sm[s];
             }
             if constexpr (G > 1) {
@@ -195,9 +195,9 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
                 if (g == 0) cin = 0;
 #pragma unroll
                 for (int s = 0; s < NWL; s++) {
-                    uint64_t x = (uint64_t)sm[s] + cin;
-                    sm[s] = (uint32_t)x;
-                    cin = (uint32_t)(x >> 32);
+                    uint32_t co;
+                    sm[s] = __builtin_addc(sm[s], 0u, cin, &co);
+                    cin = co;
                 }
             }
             uint32_t ph[NWL], mh[NWL];
@@ -525,7 +525,7 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
         // path per pair); timing the choices would cost more than the work
         for (int g : G_CHOICES)
             if (nwl_for(nw, g) != 0 && (g == 1 || nwl_for(nw, g / 2) > 1)) best_g = g;
-        best_blocks = 2048;
+        best_blocks = 512;
     }
     if (best_g == 0) {
         // time each (lanes per pair, resident workgroups) once on this call's pairs and
@@ -538,7 +538,7 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
         for (int g : G_CHOICES) {
             int nwl = nwl_for(nw, g);
             if (nwl == 0) continue;
-            for (int mb : {512, 1024, 2048}) {
+            for (int mb : {256, 512, 768, 1024, 2048}) {
                 float ms = 1e30f;
                 for (int rep = 0; rep < 2; rep++) {  // best of two: timing noise
                     MJ_HIP(hipEventRecord(e0, s));
