@@ -19,7 +19,7 @@
 //
 // Pattern and text symbols come from bit planes (plane p holds bit p of each symbol),
 // so the match mask of 32 pattern rows against one text symbol is the AND over planes
-// of XNOR(plane word, text bit).
+// of XNOR(plane word, text bit), one v_bitop3 per plane.
 //
 // Wide path (K above the register-resident window): one wavefront per pair computes the
 // banded dynamic program row by row, saturated at K+1; the left-to-right dependency of
@@ -140,17 +140,17 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
                 for (int p = 0; p < NP; p++) TY[p] = load_word(PY + p * pwy, offy + jb);
                 const int cols = min(32, nt - jb);
                 for (int t = 0; t < cols; t++) {
-                    uint32_t nt_[NP];
+                    uint32_t tb[NP];  // the text symbol's plane bits, each broadcast to a word
 #pragma unroll
                     for (int p = 0; p < NP; p++)
-                        nt_[p] = ~(uint32_t)__builtin_amdgcn_sbfe((int)TY[p], (unsigned)t, 1u);
+                        tb[p] = (uint32_t)__builtin_amdgcn_sbfe((int)TY[p], (unsigned)t, 1u);
                     uint32_t carry = 0, phc = 1, mhc = 0;
                     int dS = 0;
 #pragma unroll
                     for (int s = 0; s < NW; s++) {
                         uint32_t eq = V[s];
 #pragma unroll
-                        for (int p = 0; p < NP; p++) eq &= PL[p][s] ^ nt_[p];
+                        for (int p = 0; p < NP; p++) eq = and_xnor(eq, PL[p][s], tb[p]);
                         uint32_t pv = Pv[s], mv = Mv[s];
                         uint32_t xv = eq | mv;
                         uint32_t co;

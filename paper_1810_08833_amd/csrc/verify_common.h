@@ -23,6 +23,14 @@ __device__ __forceinline__ uint32_t load_word(const uint32_t *plane, int64_t bit
     return __builtin_amdgcn_alignbit(hi, lo, sh);
 }
 
+// a & ~(b ^ c): the bits of a where b and c agree, in one v_bitop3 (truth table indexed
+// by a << 2 | b << 1 | c: set at 100b and 111b).  With b a plane word of the pattern and c
+// a text symbol's plane bit broadcast to all 32 lanes of the word, it narrows a match mask
+// to the rows whose plane bit equals the text's.
+__device__ __forceinline__ uint32_t and_xnor(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x90);
+}
+
 inline VSet vset(const DevStrings &d) {
     return VSet{d.n, d.chars, d.offsets, d.len, d.kk, d.planes, d.plane_words};
 }

@@ -159,17 +159,16 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
         for (int p = 0; p < NP; p++) TY[p] = load_word(PY + p * pwy, offy + jb);
         const int cols = min(32, nt - jb);
         for (int t = 0; t < cols; t++) {
-            uint32_t ntm[NP];
+            uint32_t tb[NP];  // the text symbol's plane bits, each broadcast to a word
 #pragma unroll
-            for (int p = 0; p < NP; p++)
-                ntm[p] = ~(uint32_t)__builtin_amdgcn_sbfe((int)TY[p], (unsigned)t, 1u);
+            for (int p = 0; p < NP; p++) tb[p] = (uint32_t)__builtin_amdgcn_sbfe((int)TY[p], (unsigned)t, 1u);
             uint32_t eqv[NWL], sm[NWL];
             uint32_t carry = 0, all1 = ~0u;
 #pragma unroll
             for (int s = 0; s < NWL; s++) {
                 uint32_t eq = V[s];
 #pragma unroll
-                for (int p = 0; p < NP; p++) eq &= PL[p][s] ^ ntm[p];
+                for (int p = 0; p < NP; p++) eq = and_xnor(eq, PL[p][s], tb[p]);
                 eqv[s] = eq;
                 uint32_t co;
                 sm[s] = __builtin_addc(eq & Pv[s], Pv[s], carry, &co);  // carry chain in a lane mask
