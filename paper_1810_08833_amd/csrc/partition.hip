@@ -330,23 +330,27 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             for (int k = 0; k < 9; k++)
                 if (k < q) G = (G << bits) | ((A[k >> 2] >> (8 * (k & 3))) & 0xFFu);
             const Code cmask = (Code)gmask;
-            const int64_t i0 = g0 - sb0;
-            const int64_t npos = (se0 - sb0) - q + 1;
+            // positions inside a string fit in 32 bits (m < 2^31)
+            const int32_t i0 = (int32_t)(g0 - sb0);
+            const int32_t npos = (int32_t)(se0 - sb0) - q + 1;
             const int32_t r = td.r[t];
+            // interior i in [r, npos-1-r]  <=>  (unsigned)(i - r) < ibound
+            const uint32_t ibound = (uint32_t)max(npos - 2 * r, 0);
             V hv[RUN];
             uint16_t inf[RUN];
 #pragma unroll
             for (int j = 0; j < RUN; j++) {
                 if constexpr (RANKED) hv[j] = rank_s[G];
                 else hv[j] = table ? table[G] : mix64((uint64_t)G ^ salt);
-                const int64_t i = i0 + j;
-                const bool interior = (i >= r) && (i <= npos - 1 - r);
-                inf[j] = (uint16_t)((interior ? r : 0) | (i == 0 ? 0x8000 : 0));
-                const bool in_tile = interior && idx0 + j >= H && idx0 + j < H + TP;
-                lrmin = in_tile ? min(lrmin, r) : lrmin;
+                inf[j] = (uint32_t)(i0 + j - r) < ibound ? (uint16_t)r : (uint16_t)0;
                 if (j + 1 < RUN) G = ((G << bits) | ((N[j >> 2] >> (8 * (j & 3))) & 0xFFu)) & cmask;
             }
-            lmax = lrmin < 0x7FFFFFFF ? 31 - __clz(r) : 0;
+            inf[0] |= i0 == 0 ? (uint16_t)0x8000 : (uint16_t)0;  // string start
+            // interior positions of the run that are tile positions: j in [jlo, jhi)
+            const int jlo = max(max(r - i0, H - idx0), 0);
+            const int jhi = min(min(npos - r - i0, H + TP - idx0), RUN);
+            lrmin = jlo < jhi ? r : lrmin;
+            lmax = jlo < jhi ? 31 - __clz(r) : 0;
             // 16-byte stores of the thread's RUN hash slots and RUN info slots
             {
                 uint32_t hw[RUN * sizeof(V) / 4];
@@ -377,7 +381,11 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
 #pragma unroll
             for (int j = 0; j < RUN; j++) {
                 const int idx = idx0 + j;
-                if (idx >= NR) break;
+                if (idx >= NR) {  // region padding: a sentinel that is never a strict minimum
+                    bufA[idx] = (V)~0ull;
+                    pinfo[idx] = 0;
+                    continue;
+                }
                 const int64_t g = base + idx;
                 V h = (V)~0ull;
                 uint16_t info = 0;
@@ -435,9 +443,11 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         // ---- block test: bufA <- suffix minima, bufB <- prefix minima (within blocks).
         // The block's unique minimum is the position strictly below the prefix minimum
         // before it and the suffix minimum after it (neighbouring lanes of the scans).
-        for (int j0 = 0; j0 < NR; j0 += AT_THREADS) {  // uniform trip count for the DPP scans
+        // the whole region (slots from NR on hold the sentinel): a fixed trip count
+#pragma unroll
+        for (int j0 = 0; j0 < REGION; j0 += AT_THREADS) {
             const int idx = j0 + tid;
-            const V hv = idx < NR ? bufA[idx] : (V)~0ull;
+            const V hv = bufA[idx];
             V pv = hv, sv = hv;
             prefix_min_step<1>(pv);
             prefix_min_step<2>(pv);
@@ -449,17 +459,14 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             suffix_min_step<8>(sv);
             const V before = dpp_val<0x111>(pv);  // prefix minimum of the lane below
             const V after = dpp_val<0x101>(sv);   // suffix minimum of the lane above
-            if (idx < NR) {
-                bufB[idx] = pv;
-                bufA[idx] = sv;
-            }
-            if ((tid & (AT_BLOCK - 1)) == AT_BLOCK - 1 && idx - (AT_BLOCK - 1) < NR)
-                bmin[idx / AT_BLOCK] = pv;
+            bufB[idx] = pv;
+            bufA[idx] = sv;
+            if ((tid & (AT_BLOCK - 1)) == AT_BLOCK - 1) bmin[idx / AT_BLOCK] = pv;
             // at most one lane per block satisfies this (a strict minimum of the block);
             // the block's first lane records it (the 16 lanes of a block share a wave)
-            const bool uniq = idx < NR && hv < before && hv < after;
+            const bool uniq = hv < before && hv < after;
             const uint64_t um = __ballot(uniq);
-            if ((tid & (AT_BLOCK - 1)) == 0 && idx < NR) {
+            if ((tid & (AT_BLOCK - 1)) == 0) {
                 const uint32_t row = (uint32_t)(um >> (tid & 63)) & 0xFFFFu;
                 barg[idx / AT_BLOCK] = row ? (int16_t)(idx + __ffs(row) - 1) : (int16_t)-1;
             }
@@ -528,15 +535,14 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     }
     // one bit per position: string start or anchor
     const int lane = tid & 63, wid = tid >> 6;
+    const int rem = (int)min<int64_t>(total - tile_start, (int64_t)TP);  // tile positions in the input
 #pragma unroll
     for (int c = 0; c < OWN; c++) {
         if (c < NC) {
-            int p = AT_THREADS * c + 64 * wid + lane;
-            int64_t chunk = tile_start + (int64_t)AT_THREADS * c + 64 * wid;
-            int64_t g = chunk + lane;
-            bool flag = g < total && (((pinfo[H + p] & 0x8000) != 0) || ((aflag[p >> 5] >> (p & 31)) & 1u));
-            uint64_t mask = __ballot(flag);
-            if (lane == 0 && chunk < total) bitmap[chunk >> 6] = mask;
+            const int p0 = AT_THREADS * c + 64 * wid, p = p0 + lane;
+            const uint32_t bit = ((uint32_t)pinfo[H + p] >> 15) | (aflag[p >> 5] >> (p & 31));
+            const uint64_t mask = __ballot(p < rem && (bit & 1u));
+            if (lane == 0 && p0 < rem) bitmap[(tile_start + p0) >> 6] = mask;
         }
     }
 }
