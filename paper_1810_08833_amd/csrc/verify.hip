@@ -5,10 +5,11 @@
 // visits diagonal k = i - j makes at least |k| + |d - k| edits, so it stays within the
 // K + 1 diagonals lo = ceil((d-K)/2) <= k <= hi = floor((d+K)/2) (Ukkonen's band, tightened
 // by the length difference).  Column j keeps the vertical deltas of a window of 32-bit
-// words of rows (word w holds rows 32w+1 .. 32w+32); in block b (columns 32b+1 .. 32b+32)
-// the window starts at word b + floor(lo/32), so it covers rows j+lo .. j+hi of every
-// column with ceil(hi/32) + 1 - floor(lo/32) <= ceil(K/32) + 2 words, and it moves by one
-// word every 32 columns for every lane at once.  Each column applies Myers' bit-vector
+// words of rows (word w holds rows 32w+1 .. 32w+32).  Columns come in blocks: a first
+// block of phi = ((-lo-1) mod 32) + 1 columns, then blocks of 32; the window moves down one
+// word between blocks, and phi puts the band's top row lo + (first column of the block)
+// on a word boundary at every move.  The window then covers rows j+lo .. j+hi of every
+// column j with 1 + ceil((hi-lo)/32) <= ceil(K/32) + 1 words.  Each column applies Myers' bit-vector
 // recurrence for global edit distance (hin = +1 at the top) to the whole window as one
 // multi-word integer.  Rows above the window are treated as one more than their left
 // neighbour, a word entering at the bottom as one more than the row above it, and rows
@@ -46,7 +47,7 @@ int verify_planes(int bits) {
     return 8;
 }
 
-// ceil(K/32) handled by the bit-parallel kernels (K <= 416); a window of c + 2 words
+// ceil(K/32) handled by the bit-parallel kernels (K <= 416); a window of c + 1 words
 constexpr int BP_MAX_C = 13;
 
 template <int NW, int NP>
@@ -74,12 +75,13 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
         uint8_t result;
         const int dlen = mp - nt;
         const int blo = -((K - dlen) >> 1), bhi = (K + dlen) >> 1;  // band diagonals
-        const int w0 = -((31 - blo) >> 5);                          // floor(blo / 32)
+        const int phi = ((-blo - 1) & 31) + 1;                      // columns of the first block
+        const int w0 = ((phi + blo) >> 5) - 1;                      // window word of that block
         if (mp - nt > K) {
             result = 0;
         } else if (nt == 0) {
             result = mp <= K;
-        } else if (((bhi + 31) >> 5) + 1 - w0 > NW) {
+        } else if (1 + ((bhi - blo + 31) >> 5) > NW) {
             result = 2;  // not handled by this instance (host bins pairs so this never happens)
         } else {
             uint32_t Pv[NW], Mv[NW], V[NW];
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
             int S = abs(32 * w0 + 32);  // column 0: row i holds |i| (rows <= 0 are made up)
             bool rejected = false;
             int jb = 0;
-            for (; jb < nt; jb += 32) {
+            for (int cols = min(phi, nt); jb < nt; jb += cols, cols = min(32, nt - jb)) {
                 if (jb > 0) {
                     // early exit: a lower bound of every window value, word by word
                     int Sw = S, lb = S - __popc(Pv[0]);
@@ -138,7 +140,6 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
                 uint32_t TY[NP];
 #pragma unroll
                 for (int p = 0; p < NP; p++) TY[p] = load_word(PY + p * pwy, offy + jb);
-                const int cols = min(32, nt - jb);
                 for (int t = 0; t < cols; t++) {
                     uint32_t tb[NP];  // the text symbol's plane bits, each broadcast to a word
 #pragma unroll
@@ -405,19 +406,19 @@ template <int NP>
 static BpKernel bp_kernel_for(int c) {
     switch (c) {
         case 0: return k_verify_bp<1, NP>;
-        case 1: return k_verify_bp<3, NP>;
-        case 2: return k_verify_bp<4, NP>;
-        case 3: return k_verify_bp<5, NP>;
-        case 4: return k_verify_bp<6, NP>;
-        case 5: return k_verify_bp<7, NP>;
-        case 6: return k_verify_bp<8, NP>;
-        case 7: return k_verify_bp<9, NP>;
-        case 8: return k_verify_bp<10, NP>;
-        case 9: return k_verify_bp<11, NP>;
-        case 10: return k_verify_bp<12, NP>;
-        case 11: return k_verify_bp<13, NP>;
-        case 12: return k_verify_bp<14, NP>;
-        default: return k_verify_bp<15, NP>;
+        case 1: return k_verify_bp<2, NP>;
+        case 2: return k_verify_bp<3, NP>;
+        case 3: return k_verify_bp<4, NP>;
+        case 4: return k_verify_bp<5, NP>;
+        case 5: return k_verify_bp<6, NP>;
+        case 6: return k_verify_bp<7, NP>;
+        case 7: return k_verify_bp<8, NP>;
+        case 8: return k_verify_bp<9, NP>;
+        case 9: return k_verify_bp<10, NP>;
+        case 10: return k_verify_bp<11, NP>;
+        case 11: return k_verify_bp<12, NP>;
+        case 12: return k_verify_bp<13, NP>;
+        default: return k_verify_bp<14, NP>;
     }
 }
 

@@ -7,8 +7,9 @@
 // resolved inside the group: the carry of the multi-word addition with a carry-lookahead
 // scan over the lanes (each lane adds with carry-in 0, reports carry-out and whether its
 // chunk would propagate a carry, then adds its resolved carry-in), and the bits shifted
-// from one chunk into the next.  The window and its one-word moves every 32 columns are
-// those of the per-lane kernel, so the decision ED <= K is the same.
+// from one chunk into the next.  The window, its column blocks (a first block of phi
+// columns, then 32) and its one-word moves between blocks are those of the per-lane
+// kernel, so the decision ED <= K is the same.
 //
 // Groups take pairs from a queue in order of decreasing length (longest first) and,
 // whenever their pair ends (accepted, rejected early, or out of columns), refill at the
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
     const int leader_lane = lane - g;
     bool active = false, exhausted = false;
     int64_t pi = 0;
-    int32_t K = 0, mp = 0, nt = 0, wlo = 0, jb = 0, S = 0, band = 0;
+    int32_t K = 0, mp = 0, nt = 0, wlo = 0, jb = 0, S = 0, band = 0, phi = 32;
     int64_t offx = 0, offy = 0, pwx = 0, pwy = 0;
     const uint32_t *PX = nullptr, *PY = nullptr;
     uint32_t Pv[NWL], Mv[NWL], V[NWL], PL[NP][NWL];
@@ -116,14 +117,15 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
                 nt = a_is_x ? mb : ma;
                 const int dlen = mp - nt;
                 const int blo = -((K - dlen) >> 1), bhi = (K + dlen) >> 1;  // band diagonals
-                const int w0 = -((31 - blo) >> 5);                          // floor(blo / 32)
+                phi = ((-blo - 1) & 31) + 1;                                // first block's columns
+                const int w0 = ((phi + blo) >> 5) - 1;                      // its window word
                 uint8_t result = 0;
                 bool trivial = true;
                 if (mp - nt > K) {
                     result = 0;
                 } else if (nt == 0) {
                     result = mp <= K;
-                } else if (((bhi + 31) >> 5) + 1 - w0 > NW) {
+                } else if (1 + ((bhi - blo + 31) >> 5) > NW) {
                     result = 2;
                 } else {
                     trivial = false;
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
         uint32_t TY[NP];
 #pragma unroll
         for (int p = 0; p < NP; p++) TY[p] = load_word(PY + p * pwy, offy + jb);
-        const int cols = min(32, nt - jb);
+        const int cols = min(jb == 0 ? phi : 32, nt - jb);
         for (int t = 0; t < cols; t++) {
             uint32_t tb[NP];  // the text symbol's plane bits, each broadcast to a word
 #pragma unroll
@@ -379,7 +381,7 @@ static int nwl_for(int nw, int g) {
     return 0;
 }
 
-// The window needs ceil(K/32) + 2 words (at most 11 * 8); K <= 2047 keeps c <= 64.
+// The window needs ceil(K/32) + 1 words (at most 11 * 8); K <= 2047 keeps c <= 64.
 int persist_max_c() { return 64; }
 
 // Calls with fewer pairs use a fixed configuration instead of timing the choices.
@@ -514,7 +516,7 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
                        off, fillc, order);
     MJ_LAUNCH_CHECK();
 
-    const int nw = cmax == 0 ? 1 : cmax + 2;
+    const int nw = cmax + 1;
     const int npi = np / 2 - 1;
     const int ci = std::min(cmax, 63);
     int best_g = tune ? tune->best_g[ci][npi] : 0;
