@@ -77,6 +77,9 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
     int64_t offx = 0, offy = 0, pwx = 0, pwy = 0;
     const uint32_t *PX = nullptr, *PY = nullptr;
     uint32_t Pv[NWL], Mv[NWL], V[NWL], PL[NP][NWL];
+    // software pipeline: text words of the current and the next block, and the plane words
+    // of the window's next bottom word, loaded one block ahead of their use
+    uint32_t TYc[NP], TYn[NP], PLn[NP];
     uint64_t my_cells = 0;
 #pragma unroll
     for (int s = 0; s < NWL; s++) {
@@ -149,6 +152,13 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
                         for (int p = 0; p < NP; p++)
                             PL[p][s] = real ? load_word(PX + p * pwx, offx + 32 * (int64_t)w) : 0u;
                     }
+#pragma unroll
+                    for (int p = 0; p < NP; p++) {
+                        TYc[p] = load_word(PY + p * pwy, offy);
+                        TYn[p] = load_word(PY + p * pwy, offy + phi);
+                        // bottom word after the first move: word w0 + NW (read by the last lane)
+                        PLn[p] = g == G - 1 ? load_word(PX + p * pwx, offx + 32 * (int64_t)(w0 + NW)) : 0u;
+                    }
                 }
             }
         }
@@ -158,7 +168,7 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
         // ---- one block of up to 32 columns
         uint32_t TY[NP];
 #pragma unroll
-        for (int p = 0; p < NP; p++) TY[p] = load_word(PY + p * pwy, offy + jb);
+        for (int p = 0; p < NP; p++) TY[p] = TYc[p];
         const int cols = min(jb == 0 ? phi : 32, nt - jb);
         for (int t = 0; t < cols; t++) {
             uint32_t tb[NP];  // the text symbol's plane bits, each broadcast to a word
@@ -307,14 +317,23 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
             for (int p = 0; p < NP; p++) PL[p][s] = PL[p][s + 1];
         }
         wlo++;
+        // next block's text words (prefetched) and the prefetch of the block after it; the
+        // bottom word after the following move (word wlo + NW).  Reads past a string's end
+        // stay within the padding of the plane arrays.
+#pragma unroll
+        for (int p = 0; p < NP; p++) {
+            TYc[p] = TYn[p];
+            TYn[p] = load_word(PY + p * pwy, offy + jb + 32);
+        }
         if (g == G - 1) {
-            int w = wlo + NW - 1;
             Pv[NWL - 1] = ~0u;
             Mv[NWL - 1] = 0u;
             V[NWL - 1] = ~0u;
 #pragma unroll
-            for (int p = 0; p < NP; p++)
-                PL[p][NWL - 1] = load_word(PX + p * pwx, offx + 32 * (int64_t)w);
+            for (int p = 0; p < NP; p++) {
+                PL[p][NWL - 1] = PLn[p];
+                PLn[p] = load_word(PX + p * pwx, offx + 32 * (int64_t)(wlo + NW));
+            }
         } else {
             Pv[NWL - 1] = inP;
             Mv[NWL - 1] = inM;
