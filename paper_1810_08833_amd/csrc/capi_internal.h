@@ -34,7 +34,7 @@ struct mj_index {
     uint32_t *planes = nullptr;
     int64_t plane_words = 0;
     int np = 0;
-    RecBuf rec;  // sorted by (key, val)
+    RecBuf rec;  // sorted by key
 };
 
 // Sets the thread-local error message and returns the status.
