@@ -129,7 +129,7 @@ static void sorted_records(const DevStrings &d, const PartitionParams &pp, int32
     partition_records(d, pp, halo, rb, ws, s, pinned);
     int64_t R = rb.count;
     if (R > 1) {
-        radix_sort(rb.key, rb.val, R, ~0ull, ws, s);
+        sort_records(rb.key, rb.val, R, ws, s, pinned);
     }
 }
 
@@ -232,7 +232,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     tm.mark();  // 1 partition: anchors and records
     int64_t R = rb.count;
     if (R > 1) {
-        radix_sort(rb.key, rb.val, R, ~0ull, ws, s);
+        sort_records(rb.key, rb.val, R, ws, s, ctx->pinned);
     }
     tm.mark();  // 2 sort
     GroupInfo g = find_groups(rb.key, R, ws, s, ctx->pinned);
@@ -452,7 +452,7 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
     partition_records(qd, qp, halo, rb, ws, s, ctx->pinned, &ctx->kt);
     tm.mark();  // 1 partition
     if (rb.count > 1) {
-        radix_sort(rb.key, rb.val, rb.count, ~0ull, ws, s);
+        sort_records(rb.key, rb.val, rb.count, ws, s, ctx->pinned);
     }
     tm.mark();  // 2 sort
     DevStrings id;

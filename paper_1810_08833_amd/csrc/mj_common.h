@@ -107,6 +107,10 @@ constexpr size_t HOST_SCRATCH_BYTES = 16384;
 // at every bit that may be set in some key (the others must be zero in all keys).
 void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Workspace &ws,
                 hipStream_t s);
+// Records (key, payload) sorted by the full 64-bit key, in place; equal keys keep their
+// order only up to the runs that the repair step reorders.
+void sort_records(uint64_t *key, uint64_t *val, int64_t n, Workspace &ws, hipStream_t s,
+                  uint64_t *host_scratch);
 // Gather: out_k[i] = key[idx[i]] (and val).
 void gather_u64(const uint64_t *src, const int64_t *idx, uint64_t *dst, int64_t n, hipStream_t s);
 

@@ -446,4 +446,121 @@ void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Work
     }
 }
 
+// ---------------------------------------------------------------- record sort
+// Records sorted by full 64-bit key with four radix passes: a stable sort by the top 32
+// bits, then a repair of the runs of equal top halves that hold more than one key.  Such
+// runs are rare (about n^2 / 2^33 pairs of keys share a top half).  k_run_bits marks, one
+// bit per record, where a run starts and where the key changes inside a run; k_mixed_runs
+// (read-only) lets the first change of each run record the run's bounds, found by
+// scanning those bitmaps 64 records per step; k_sort_runs then orders each listed run by
+// the full key (insertion sort: the runs are short, and a run that holds a frequent key
+// has few inversions).
+__global__ void k_run_bits(const uint64_t *__restrict__ key, int64_t n, uint64_t *__restrict__ rsb,
+                           uint64_t *__restrict__ brb) {
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;  // a multiple of 64
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - lane < n; i += stride) {
+        const bool ok = i < n;
+        const uint64_t b = ok ? key[i] : 0, a = (ok && i > 0) ? key[i - 1] : 0;
+        const bool same_top = i > 0 && (a >> 32) == (b >> 32);
+        const uint64_t ms = __ballot(ok && !same_top);
+        const uint64_t mb = __ballot(ok && same_top && a != b);
+        if (lane == 0) {
+            rsb[i >> 6] = ms;
+            brb[i >> 6] = mb;
+        }
+    }
+}
+
+__global__ void k_mixed_runs(const uint64_t *__restrict__ rsb, const uint64_t *__restrict__ brb,
+                             int64_t n, int64_t *runs, int64_t cap, unsigned long long *count) {
+    const int64_t nw = (n + 63) >> 6;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t bits = brb[w];
+        while (bits) {
+            const int b = __ffsll((unsigned long long)bits) - 1;
+            bits &= bits - 1;
+            const int64_t i = 64 * w + b;  // key[i-1] != key[i], same top half
+            // run start: the last run-start bit at or before i-1 (position 0 always is one)
+            int64_t pw = (i - 1) >> 6;
+            uint64_t m = rsb[pw] & (~0ull >> (63 - ((i - 1) & 63)));
+            while (m == 0) m = rsb[--pw];
+            const int64_t rs = 64 * pw + 63 - __clzll((long long)m);
+            // the run's first change owns it: no change bit in (rs, i)
+            bool first = true;
+            if (i - 1 > rs) {
+                int64_t qw = (i - 1) >> 6;
+                uint64_t mq = brb[qw] & (~0ull >> (63 - ((i - 1) & 63)));
+                for (;;) {
+                    const int64_t lo = 64 * qw;
+                    if (rs + 1 > lo) mq &= ~0ull << (rs + 1 - lo);
+                    if (mq) {
+                        first = false;
+                        break;
+                    }
+                    if (lo <= rs + 1) break;
+                    mq = brb[--qw];
+                }
+            }
+            if (!first) continue;
+            // run end: the next run-start bit after i, else n
+            int64_t ew = (i + 1) >> 6, re = n;
+            if (i + 1 < n) {
+                uint64_t me = rsb[ew] & (~0ull << ((i + 1) & 63));
+                while (me == 0 && ++ew < nw) me = rsb[ew];
+                if (me) re = min(n, 64 * ew + (__ffsll((unsigned long long)me) - 1));
+            }
+            const unsigned long long slot = atomicAdd(count, 1ull);
+            if ((int64_t)slot < cap) {
+                runs[2 * slot] = rs;
+                runs[2 * slot + 1] = re;
+            }
+        }
+    }
+}
+
+__global__ void k_sort_runs(uint64_t *__restrict__ key, uint64_t *__restrict__ val,
+                            const int64_t *__restrict__ runs, int64_t cap,
+                            const unsigned long long *count) {
+    const int64_t nr = min((int64_t)*count, cap);
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nr;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t rs = runs[2 * r], re = runs[2 * r + 1];
+        for (int64_t j = rs + 1; j < re; j++) {
+            const uint64_t k = key[j], v = val[j];
+            int64_t p = j;
+            while (p > rs && key[p - 1] > k) {
+                key[p] = key[p - 1];
+                val[p] = val[p - 1];
+                p--;
+            }
+            key[p] = k;
+            val[p] = v;
+        }
+    }
+}
+
+void sort_records(uint64_t *key, uint64_t *val, int64_t n, Workspace &ws, hipStream_t s,
+                  uint64_t *host_scratch) {
+    if (n <= 1) return;
+    radix_sort(key, val, n, 0xFFFFFFFF00000000ull, ws, s);
+    // at most one run per two records
+    const int64_t cap = n / 2 + 1;
+    const int64_t nw = (n + 63) / 64;
+    int64_t *runs = ws.get_n<int64_t>(2 * cap);
+    uint64_t *rsb = ws.get_n<uint64_t>(nw + 1);
+    uint64_t *brb = ws.get_n<uint64_t>(nw + 1);
+    unsigned long long *count = (unsigned long long *)ws.get_n<uint64_t>(2);
+    fill_u64((uint64_t *)count, 0, 1, s);
+    hipLaunchKernelGGL(k_run_bits, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, key, n, rsb, brb);
+    MJ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mixed_runs, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s, rsb, brb, n,
+                       runs, cap, count);
+    MJ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sort_runs, dim3(256), dim3(256), 0, s, key, val, runs, cap, count);
+    MJ_LAUNCH_CHECK();
+    (void)host_scratch;
+}
+
 }  // namespace mj
