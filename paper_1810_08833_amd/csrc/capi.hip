@@ -240,7 +240,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
         throw Error(MJ_ECAPACITY, "record-pair tests exceed 2^31 (" + std::to_string(g.tests) + ")");
     int64_t cap = (int64_t)g.tests;
     uint64_t *cand = ws.get_n<uint64_t>(cap + 1);
-    int64_t c0 = emit_candidates(rb.val, g, d, cand, cap, ws, s, ctx->pinned, &ctx->kt);
+    int64_t c0 = emit_candidates(rb.val, R, g, d, cand, cap, ws, s, ctx->pinned, &ctx->kt);
     tm.mark();  // 3 group + filter
     uint64_t *uniq = nullptr;
     int64_t C = dedup_pairs(cand, c0, d.n, d.n, ws, s, ctx->pinned, &uniq);

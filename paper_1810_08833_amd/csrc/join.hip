@@ -89,34 +89,70 @@ __device__ __forceinline__ bool pass_filter(int64_t mi, int64_t pi, int64_t mj, 
     return (d1 > d2 ? d1 : d2) <= K;
 }
 
-// Wave-aggregated append of `v` where `pass` holds.
-__device__ __forceinline__ void append(bool pass, uint64_t v, unsigned long long *counter,
-                                       uint64_t *out, int64_t cap) {
-    uint64_t mask = __ballot(pass);
+// Passing tests of one block's sweep are staged in LDS and written out with one
+// device-wide atomic per block and sweep: a single counter bumped by every wave of all
+// XCDs serialises (device-scope atomics are not served by an XCD's own L2).
+constexpr int EMIT_BLOCK = 256;
+struct EmitStage {
+    uint64_t buf[EMIT_BLOCK * EMIT_CHUNK];
+    uint32_t n;
+    unsigned long long base;
+};
+
+__device__ __forceinline__ void stage(bool pass, uint64_t v, EmitStage &st) {
+    const uint64_t mask = __ballot(pass);
     if (mask == 0) return;
     const int lane = threadIdx.x & 63;
-    int leader = __ffsll((unsigned long long)mask) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&st.n, (uint32_t)__popcll(mask));
     base = __shfl(base, leader, 64);
-    if (pass) {
-        unsigned long long idx = base + __popcll(mask & ((1ull << lane) - 1));
-        if ((int64_t)idx < cap) out[idx] = v;
+    if (pass) st.buf[base + __popcll(mask & ((1ull << lane) - 1))] = v;
+}
+
+// Block-uniform: every thread of the block calls it after the same sweep.
+__device__ __forceinline__ void flush(EmitStage &st, unsigned long long *counter, uint64_t *out,
+                                      int64_t cap) {
+    __syncthreads();
+    const uint32_t n = st.n;
+    if (threadIdx.x == 0 && n) st.base = atomicAdd(counter, (unsigned long long)n);
+    __syncthreads();
+    if (n) {
+        const unsigned long long base = st.base;
+        if (threadIdx.x == 0) st.n = 0;  // every thread has read n before the barrier above
+        for (uint32_t i = threadIdx.x; i < n; i += EMIT_BLOCK)
+            if ((int64_t)(base + i) < cap) out[base + i] = st.buf[i];
+        __syncthreads();  // buf and n are free for the next sweep
     }
 }
 
-__global__ __launch_bounds__(256) void k_emit(const uint64_t *__restrict__ val,
+// meta[i] = m << 32 | K of the string owning sorted record i, so that a pair test reads
+// four record-aligned words (two payloads, two metas) with no dependent gathers.
+__global__ void k_record_meta(const uint64_t *__restrict__ val, int64_t R,
+                              const int32_t *__restrict__ len, const int32_t *__restrict__ kk,
+                              uint64_t *__restrict__ meta) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < R; i += stride) {
+        const int32_t sid = (int32_t)(val[i] >> 32);
+        meta[i] = ((uint64_t)(uint32_t)len[sid] << 32) | (uint32_t)kk[sid];
+    }
+}
+
+__global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict__ val,
+                                              const uint64_t *__restrict__ meta,
                                               const int64_t *__restrict__ gs,
                                               const uint64_t *__restrict__ ts, int64_t G,
-                                              uint64_t P, const int32_t *__restrict__ len,
-                                              const int32_t *__restrict__ kk, uint64_t *out,
-                                              int64_t cap, unsigned long long *counter) {
-    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * EMIT_CHUNK; ;
+                                              uint64_t P, uint64_t *out, int64_t cap,
+                                              unsigned long long *counter) {
+    __shared__ EmitStage st;
+    if (threadIdx.x == 0) st.n = 0;
+    __syncthreads();
+    const uint64_t nthreads = (uint64_t)gridDim.x * EMIT_BLOCK;
+    for (uint64_t t0 = ((uint64_t)blockIdx.x * EMIT_BLOCK + threadIdx.x) * EMIT_CHUNK; ;
          t0 += nthreads * EMIT_CHUNK) {
-        // uniform loop exit: every lane of the wave leaves together
-        uint64_t wave_first = t0 - (uint64_t)(threadIdx.x & 63) * EMIT_CHUNK;
-        if (wave_first >= P) break;
+        // block-uniform loop exit (the flush has barriers)
+        if (t0 - (uint64_t)threadIdx.x * EMIT_CHUNK >= P) break;
         bool active = t0 < P;
         int64_t g = 0;
         uint64_t a = 0, b = 1;
@@ -140,11 +176,12 @@ __global__ __launch_bounds__(256) void k_emit(const uint64_t *__restrict__ val,
             uint64_t pairkey = 0;
             if (live) {
                 int64_t s0 = gs[g];
-                uint64_t va = val[s0 + (int64_t)a], vb = val[s0 + (int64_t)b];
+                const uint64_t va = val[s0 + (int64_t)a], vb = val[s0 + (int64_t)b];
+                const uint64_t xa = meta[s0 + (int64_t)a], xb = meta[s0 + (int64_t)b];
                 int32_t ia = (int32_t)(va >> 32), ib = (int32_t)(vb >> 32);
                 if (ia != ib) {
-                    int64_t ma = len[ia], mb = len[ib];
-                    int64_t K = max(kk[ia], kk[ib]);
+                    const int64_t ma = (int64_t)(xa >> 32), mb = (int64_t)(xb >> 32);
+                    const int64_t K = max((int64_t)(uint32_t)xa, (int64_t)(uint32_t)xb);
                     pass = pass_filter(ma, (int64_t)(uint32_t)va, mb, (int64_t)(uint32_t)vb, K);
                     uint64_t lo = (uint64_t)min(ia, ib), hi = (uint64_t)max(ia, ib);
                     pairkey = (lo << 32) | hi;
@@ -161,22 +198,27 @@ __global__ __launch_bounds__(256) void k_emit(const uint64_t *__restrict__ val,
                     }
                 }
             }
-            append(pass, pairkey, counter, out, cap);
+            stage(pass, pairkey, st);
         }
+        flush(st, counter, out, cap);
     }
 }
 
-int64_t emit_candidates(const uint64_t *val, const GroupInfo &g, const DevStrings &d,
+int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, const DevStrings &d,
                         uint64_t *out, int64_t cap, Workspace &ws, hipStream_t s,
                         uint64_t *host_scratch, KTimer *kt) {
     if (g.groups == 0 || g.tests == 0) return 0;
     unsigned long long *counter = (unsigned long long *)ws.get_n<uint64_t>(2);
     fill_u64((uint64_t *)counter, 0, 1, s);
-    uint64_t threads = (g.tests + EMIT_CHUNK - 1) / EMIT_CHUNK;
-    unsigned grid = (unsigned)std::min<uint64_t>((threads + 255) / 256, 1u << 16);
+    uint64_t *meta = ws.get_n<uint64_t>(R + 1);
     int th = kt ? kt->begin(KTimer::EMIT, s) : -1;
-    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(256), 0, s, val, g.gstart, g.tstart, g.groups,
-                       g.tests, d.len, d.kk, out, cap, counter);
+    hipLaunchKernelGGL(k_record_meta, dim3(grid_for(R, 256, 16384)), dim3(256), 0, s, val, R, d.len,
+                       d.kk, meta);
+    MJ_LAUNCH_CHECK();
+    uint64_t threads = (g.tests + EMIT_CHUNK - 1) / EMIT_CHUNK;
+    unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, 1u << 16);
+    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(EMIT_BLOCK), 0, s, val, meta, g.gstart, g.tstart,
+                       g.groups, g.tests, out, cap, counter);
     MJ_LAUNCH_CHECK();
     if (kt) kt->end(th, s);
     uint64_t c = read_back<uint64_t>((const uint64_t *)counter, s, host_scratch);
@@ -237,7 +279,7 @@ __global__ void k_probe_ranges(const uint64_t *qkey, int64_t RQ, const uint64_t 
     }
 }
 
-__global__ __launch_bounds__(256) void k_probe_emit(const uint64_t *__restrict__ qval,
+__global__ __launch_bounds__(EMIT_BLOCK) void k_probe_emit(const uint64_t *__restrict__ qval,
                                                     const int64_t *__restrict__ lo_arr,
                                                     const uint64_t *__restrict__ ts, int64_t RQ,
                                                     uint64_t P, const uint64_t *__restrict__ ival,
@@ -246,11 +288,13 @@ __global__ __launch_bounds__(256) void k_probe_emit(const uint64_t *__restrict__
                                                     const int32_t *__restrict__ ilen,
                                                     uint64_t *out, int64_t cap,
                                                     unsigned long long *counter) {
-    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * EMIT_CHUNK; ;
+    __shared__ EmitStage st;
+    if (threadIdx.x == 0) st.n = 0;
+    __syncthreads();
+    const uint64_t nthreads = (uint64_t)gridDim.x * EMIT_BLOCK;
+    for (uint64_t t0 = ((uint64_t)blockIdx.x * EMIT_BLOCK + threadIdx.x) * EMIT_CHUNK; ;
          t0 += nthreads * EMIT_CHUNK) {
-        uint64_t wave_first = t0 - (uint64_t)(threadIdx.x & 63) * EMIT_CHUNK;
-        if (wave_first >= P) break;
+        if (t0 - (uint64_t)threadIdx.x * EMIT_CHUNK >= P) break;
         bool active = t0 < P;
         int64_t r = 0;
         uint64_t j = 0;
@@ -282,8 +326,9 @@ __global__ __launch_bounds__(256) void k_probe_emit(const uint64_t *__restrict__
                 pairkey = ((uint64_t)(uint32_t)qi << 32) | (uint64_t)(uint32_t)si;
                 j++;
             }
-            append(pass, pairkey, counter, out, cap);
+            stage(pass, pairkey, st);
         }
+        flush(st, counter, out, cap);
     }
 }
 
@@ -307,8 +352,8 @@ int64_t probe_candidates(const uint64_t *qkey, const uint64_t *qval, int64_t RQ,
     unsigned long long *counter = (unsigned long long *)ws.get_n<uint64_t>(2);
     fill_u64((uint64_t *)counter, 0, 1, s);
     uint64_t threads = (P + EMIT_CHUNK - 1) / EMIT_CHUNK;
-    unsigned grid = (unsigned)std::min<uint64_t>((threads + 255) / 256, 1u << 16);
-    hipLaunchKernelGGL(k_probe_emit, dim3(grid), dim3(256), 0, s, qval, lo, ts, RQ, P, ival,
+    unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, 1u << 16);
+    hipLaunchKernelGGL(k_probe_emit, dim3(grid), dim3(EMIT_BLOCK), 0, s, qval, lo, ts, RQ, P, ival,
                        qd.len, qd.kk, id.len, out, cap, counter);
     MJ_LAUNCH_CHECK();
     uint64_t c = read_back<uint64_t>((const uint64_t *)counter, s, host_scratch);

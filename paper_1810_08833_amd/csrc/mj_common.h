@@ -183,7 +183,7 @@ struct GroupInfo {
 GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t s,
                       uint64_t *host_scratch);
 // Emit candidate pair keys for all pair tests; returns count emitted (<= cap).
-int64_t emit_candidates(const uint64_t *val, const GroupInfo &g, const DevStrings &d,
+int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, const DevStrings &d,
                         uint64_t *out, int64_t cap, Workspace &ws, hipStream_t s,
                         uint64_t *host_scratch, KTimer *kt = nullptr);
 // Sorted unique copy of pairs (first << 32 | second, first < n_first, second <
