@@ -36,25 +36,27 @@ __global__ void k_prepare(const int64_t *off, int32_t n, int q, int64_t kuni, co
                           int t_div, int t_fixed, int32_t *len, int32_t *kk, int32_t *rr,
                           uint32_t *halo, uint32_t *err) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int64_t m = off[i + 1] - off[i];
-    int64_t K = kuni >= 0 ? kuni : (int64_t)kps[i];
-    if (m < 0 || m > 0x7FFFFFFFLL) atomicOr(err, 1u);
-    if (K < 0) atomicOr(err, 2u);
-    if (K > 0x3FFFFFFFLL) K = 0x3FFFFFFFLL;
-    int64_t T = t_fixed > 0 ? (int64_t)t_fixed : (K + t_div - 1) / t_div;
-    if (T < 1) T = 1;
-    int64_t num = m - q + 1 - T;
-    int64_t r = num <= 0 ? 1 : num / (2 * T + 2);
-    if (r < 1) r = 1;
-    int64_t npos = m - q + 1;
-    if (npos - 1 - r >= r) {
-        if (r > 0x7FFFFFFFLL) r = 0x7FFFFFFFLL;
-        atomicMax(halo, (uint32_t)std::min<int64_t>(r, 0xFFFFFFFFLL));
+    uint32_t hr = 0;  // this string's contribution to the halo
+    if (i < n) {
+        int64_t m = off[i + 1] - off[i];
+        int64_t K = kuni >= 0 ? kuni : (int64_t)kps[i];
+        if (m < 0 || m > 0x7FFFFFFFLL) atomicOr(err, 1u);
+        if (K < 0) atomicOr(err, 2u);
+        if (K > 0x3FFFFFFFLL) K = 0x3FFFFFFFLL;
+        int64_t T = t_fixed > 0 ? (int64_t)t_fixed : (K + t_div - 1) / t_div;
+        if (T < 1) T = 1;
+        int64_t num = m - q + 1 - T;
+        int64_t r = num <= 0 ? 1 : num / (2 * T + 2);
+        if (r < 1) r = 1;
+        int64_t npos = m - q + 1;
+        if (npos - 1 - r >= r) hr = (uint32_t)std::min<int64_t>(r, 0x7FFFFFFFLL);
+        len[i] = (int32_t)m;
+        kk[i] = (int32_t)(K < 0 ? 0 : K);
+        rr[i] = (int32_t)std::min<int64_t>(r, 0x7FFFFFFFLL);
     }
-    len[i] = (int32_t)m;
-    kk[i] = (int32_t)(K < 0 ? 0 : K);
-    rr[i] = (int32_t)std::min<int64_t>(r, 0x7FFFFFFFLL);
+    // one atomic per wave: device-scope atomics on one address serialise
+    for (int d = 32; d >= 1; d >>= 1) hr = max(hr, (uint32_t)__shfl_xor((int)hr, d, 64));
+    if ((threadIdx.x & 63) == 0 && hr) atomicMax(halo, hr);
 }
 
 int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,

@@ -454,7 +454,13 @@ void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Work
 // (read-only) lets the first change of each run record the run's bounds, found by
 // scanning those bitmaps 64 records per step; k_sort_runs then orders each listed run by
 // the full key (insertion sort: the runs are short, and a run that holds a frequent key
-// has few inversions).
+// has few inversions).  The run list is split into RUN_SEGS segments, segment j taking
+// the runs whose first change lies in its share of bitmap words, each with a counter on
+// a line of its own (device-scope atomics on one address serialise).  Two runs are
+// disjoint and hold two records each around their first change, so W words of 64
+// positions hold at most 32 W + 1 first changes: a segment can never overflow.
+constexpr int RUN_SEGS = 64;
+constexpr int RUN_CSTRIDE = 64;  // uint64 words between two segment counters
 __global__ void k_run_bits(const uint64_t *__restrict__ key, int64_t n, uint64_t *__restrict__ rsb,
                            uint64_t *__restrict__ brb) {
     const int lane = threadIdx.x & 63;
@@ -473,11 +479,13 @@ __global__ void k_run_bits(const uint64_t *__restrict__ key, int64_t n, uint64_t
 }
 
 __global__ void k_mixed_runs(const uint64_t *__restrict__ rsb, const uint64_t *__restrict__ brb,
-                             int64_t n, int64_t *runs, int64_t cap, unsigned long long *count) {
+                             int64_t n, int64_t seg_words, int64_t *runs, int64_t seg_cap,
+                             unsigned long long *count) {
     const int64_t nw = (n + 63) >> 6;
     for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw;
          w += (int64_t)gridDim.x * blockDim.x) {
         uint64_t bits = brb[w];
+        const int64_t seg = w / seg_words;
         while (bits) {
             const int b = __ffsll((unsigned long long)bits) - 1;
             bits &= bits - 1;
@@ -511,22 +519,26 @@ __global__ void k_mixed_runs(const uint64_t *__restrict__ rsb, const uint64_t *_
                 while (me == 0 && ++ew < nw) me = rsb[ew];
                 if (me) re = min(n, 64 * ew + (__ffsll((unsigned long long)me) - 1));
             }
-            const unsigned long long slot = atomicAdd(count, 1ull);
-            if ((int64_t)slot < cap) {
-                runs[2 * slot] = rs;
-                runs[2 * slot + 1] = re;
+            const unsigned long long slot = atomicAdd(count + seg * RUN_CSTRIDE, 1ull);
+            if ((int64_t)slot < seg_cap) {
+                int64_t *r = runs + 2 * (seg * seg_cap + (int64_t)slot);
+                r[0] = rs;
+                r[1] = re;
             }
         }
     }
 }
 
+// grid.y = segment
 __global__ void k_sort_runs(uint64_t *__restrict__ key, uint64_t *__restrict__ val,
-                            const int64_t *__restrict__ runs, int64_t cap,
+                            const int64_t *__restrict__ runs, int64_t seg_cap,
                             const unsigned long long *count) {
-    const int64_t nr = min((int64_t)*count, cap);
+    const int64_t seg = blockIdx.y;
+    const int64_t nr = min((int64_t)count[seg * RUN_CSTRIDE], seg_cap);
+    const int64_t *sr = runs + 2 * seg * seg_cap;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nr;
          r += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t rs = runs[2 * r], re = runs[2 * r + 1];
+        const int64_t rs = sr[2 * r], re = sr[2 * r + 1];
         for (int64_t j = rs + 1; j < re; j++) {
             const uint64_t k = key[j], v = val[j];
             int64_t p = j;
@@ -545,20 +557,21 @@ void sort_records(uint64_t *key, uint64_t *val, int64_t n, Workspace &ws, hipStr
                   uint64_t *host_scratch) {
     if (n <= 1) return;
     radix_sort(key, val, n, 0xFFFFFFFF00000000ull, ws, s);
-    // at most one run per two records
-    const int64_t cap = n / 2 + 1;
     const int64_t nw = (n + 63) / 64;
-    int64_t *runs = ws.get_n<int64_t>(2 * cap);
+    const int64_t seg_words = (nw + RUN_SEGS - 1) / RUN_SEGS;
+    const int64_t seg_cap = 32 * seg_words + 1;  // first changes a segment can hold
+    int64_t *runs = ws.get_n<int64_t>(2 * RUN_SEGS * seg_cap);
     uint64_t *rsb = ws.get_n<uint64_t>(nw + 1);
     uint64_t *brb = ws.get_n<uint64_t>(nw + 1);
-    unsigned long long *count = (unsigned long long *)ws.get_n<uint64_t>(2);
-    fill_u64((uint64_t *)count, 0, 1, s);
+    unsigned long long *count = (unsigned long long *)ws.get_n<uint64_t>(RUN_SEGS * RUN_CSTRIDE);
+    fill_u64((uint64_t *)count, 0, RUN_SEGS * RUN_CSTRIDE, s);
     hipLaunchKernelGGL(k_run_bits, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, key, n, rsb, brb);
     MJ_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_mixed_runs, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s, rsb, brb, n,
-                       runs, cap, count);
+                       seg_words, runs, seg_cap, count);
     MJ_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sort_runs, dim3(256), dim3(256), 0, s, key, val, runs, cap, count);
+    hipLaunchKernelGGL(k_sort_runs, dim3(4, RUN_SEGS), dim3(256), 0, s, key, val, runs, seg_cap,
+                       count);
     MJ_LAUNCH_CHECK();
     (void)host_scratch;
 }

@@ -14,6 +14,11 @@
 // Groups take pairs from a queue in order of decreasing length (longest first) and,
 // whenever their pair ends (accepted, rejected early, or out of columns), refill at the
 // next 32-column block boundary, so lanes do not idle behind longer pairs of their wave.
+// The queue is split into QUEUES interleaved sub-queues, sub-queue j holding the pairs of
+// rank j, j + QUEUES, j + 2 QUEUES, ... in that order, each with a counter on a line of
+// its own: device-scope atomics on one address serialise across the chip, so a single
+// counter bumped at every refill would pace the whole launch.  A wave starts on the
+// sub-queue its number selects and moves to the next one when it finds its own dry.
 // The number of lanes per pair G is chosen per (band words, alphabet planes) by timing
 // the candidate configurations once per context.
 #include <string.h>
@@ -60,6 +65,9 @@ __device__ __forceinline__ int gshfl_xor(int v, int d) {
     return G > 1 ? __shfl_xor(v, d, G) : v;
 }
 
+constexpr int QUEUES = 32;
+constexpr int QSTRIDE = 64;  // uint64 words between two sub-queue counters (512 bytes)
+
 template <int NWL, int G, int NP>
 __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restrict__ pairs,
                                                         const int64_t *__restrict__ order,
@@ -72,6 +80,9 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
     const int g = lane & (G - 1);
     const int leader_lane = lane - g;
     bool active = false, exhausted = false;
+    // wave-uniform: current sub-queue and how many sub-queues were found dry
+    int qj = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % QUEUES);
+    int qdry = 0;
     int64_t pi = 0;
     int32_t K = 0, mp = 0, nt = 0, wlo = 0, jb = 0, S = 0, band = 0, phi = 32;
     int64_t offx = 0, offy = 0, pwx = 0, pwy = 0;
@@ -93,16 +104,23 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
         const uint64_t req = __ballot(need && g == 0);
         long long got = -1;
         if (req) {
-            int first = __ffsll((unsigned long long)req) - 1;
+            const int first = __ffsll((unsigned long long)req) - 1;
+            const long long qn = n > qj ? (n - qj + QUEUES - 1) / QUEUES : 0;  // sub-queue size
+            const long long want = __popcll(req);
             unsigned long long base = 0;
-            if (lane == first) base = atomicAdd(next, (unsigned long long)__popcll(req));
-            base = __shfl(base, first, 64);
-            if (need && g == 0) got = (long long)(base + __popcll(req & ((1ull << lane) - 1)));
+            if (lane == first) base = atomicAdd(next + qj * QSTRIDE, (unsigned long long)want);
+            const long long b0 = (long long)__shfl(base, first, 64);
+            const long long k = b0 + __popcll(req & ((1ull << lane) - 1));
+            if (need && g == 0 && k < qn) got = k * QUEUES + qj;
+            if (b0 + want > qn) {  // this sub-queue is dry from now on
+                qj = qj + 1 == QUEUES ? 0 : qj + 1;
+                if (++qdry == QUEUES) exhausted = true;  // every sub-queue is dry
+            }
         }
         got = __shfl(got, leader_lane, 64);
         if (need) {
             if (got < 0 || got >= n) {
-                exhausted = true;
+                // no pair this time: retried on the next sub-queue unless all are dry
             } else {
                 pi = order ? order[got] : got;
                 uint64_t pr = pairs[pi];
@@ -485,7 +503,7 @@ static void launch_persist(int nwl, int g, int np, int max_blocks, const uint64_
                            const int64_t *order, int64_t n, const VSet &va, const VSet &vb,
                            int kmode, uint8_t *flags, unsigned long long *cells,
                            unsigned long long *next, hipStream_t s) {
-    fill_u64((uint64_t *)next, 0, 1, s);
+    fill_u64((uint64_t *)next, 0, QUEUES * QSTRIDE, s);
     // at most max_blocks resident workgroups, and no more than the pairs need
     int64_t groups_per_block = 256 / g;
     int64_t blocks = (n + groups_per_block - 1) / groups_per_block;
@@ -504,7 +522,7 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     const int np = verify_planes(std::max(A.bits, B.bits));
     VSet va = vset(A), vb = vset(B);
     unsigned long long *cells = (unsigned long long *)ws.get_n<uint64_t>(2);
-    unsigned long long *next = (unsigned long long *)ws.get_n<uint64_t>(2);
+    unsigned long long *next = (unsigned long long *)ws.get_n<uint64_t>(QUEUES * QSTRIDE);
     uint32_t *cm = ws.get_n<uint32_t>(4);
     fill_u64((uint64_t *)cells, 0, 1, s);
     fill_u32(cm, 0, 2, s);
