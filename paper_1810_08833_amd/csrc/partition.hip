@@ -286,7 +286,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         for (int c = tid; c < nr; c += AT_THREADS) rank_s[c] = rank[c];
     }
     __syncthreads();
-    const int32_t s0 = td.s0, ns = td.ns;
+    const int32_t ns = td.ns;
     const uint64_t gmask = (q * bits >= 64) ? ~0ull : ((1ull << (q * bits)) - 1);
     // hashes: each thread rolls the packed q-gram code over RUN consecutive positions
     {
@@ -302,10 +302,15 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             sb0 = td.off[t];
             se0 = td.off[t + 1];
         }
-        // fast path: all RUN positions of the thread hold full q-grams of one string
-        const bool fast = ns >= 0 && q <= 9 && g0 >= sb0 && g0 + RUN + q - 1 <= se0 &&
-                          idx0 + RUN <= NR;
-        if (fast) {
+        // fast paths: the RUN positions lie in string t (fast1: all of them start full
+        // q-grams), or in strings t and t + 1 (fast2: positions from jb on belong to t + 1,
+        // and positions whose q-gram runs past their string's end hold the sentinel)
+        const bool in_t = ns >= 0 && q <= 9 && g0 >= sb0 && idx0 + RUN <= NR;
+        const bool fast1 = in_t && g0 + RUN + q - 1 <= se0;
+        const int64_t se1 = (in_t && t + 1 < ns) ? td.off[t + 2] : se0;
+        const bool fast2 = in_t && !fast1 && (se0 >= g0 + RUN || (t + 1 < ns && g0 + RUN <= se1));
+        auto hash_run = [&](auto two) {
+            constexpr bool TWO = decltype(two)::value;
             // bytes idx0 .. idx0 + RUN + 7 of the region (the first q-gram and the rest),
             // and the RUN - 1 symbols entering the window, idx0 + q .. idx0 + q + RUN - 2
             constexpr int NA = RUN / 4 + 3;
@@ -338,21 +343,44 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             const int32_t r = td.r[t];
             // interior i in [r, npos-1-r]  <=>  (unsigned)(i - r) < ibound
             const uint32_t ibound = (uint32_t)max(npos - 2 * r, 0);
+            // string t + 1 (fast2): its first run index jb, positions, radius
+            const int jb = TWO ? (int)min<int64_t>(se0 - g0, RUN) : RUN;
+            const int32_t npos1 = TWO ? (int32_t)(se1 - se0) - q + 1 : 0;
+            const int32_t r1 = (TWO && t + 1 < ns) ? td.r[t + 1] : r;
+            const uint32_t ibound1 = (uint32_t)max(npos1 - 2 * r1, 0);
             V hv[RUN];
             uint16_t inf[RUN];
 #pragma unroll
             for (int j = 0; j < RUN; j++) {
-                if constexpr (RANKED) hv[j] = rank_s[G];
-                else hv[j] = table ? table[G] : mix64((uint64_t)G ^ salt);
-                inf[j] = (uint32_t)(i0 + j - r) < ibound ? (uint16_t)r : (uint16_t)0;
+                V h;
+                if constexpr (RANKED) h = rank_s[G];
+                else h = table ? table[G] : mix64((uint64_t)G ^ salt);
+                if constexpr (TWO) {
+                    const bool in2 = j >= jb;
+                    const int32_t i = in2 ? j - jb : i0 + j;
+                    const int32_t rj = in2 ? r1 : r;
+                    const bool interior = (uint32_t)(i - rj) < (in2 ? ibound1 : ibound);
+                    hv[j] = i < (in2 ? npos1 : npos) ? h : (V)~0ull;
+                    inf[j] = (uint16_t)((interior ? rj : 0) | (i == 0 ? 0x8000 : 0));
+                    const int idx = idx0 + j;
+                    if (interior && idx >= H && idx < H + TP) {
+                        lmax = max(lmax, 31 - __clz(rj));
+                        lrmin = min(lrmin, rj);
+                    }
+                } else {
+                    hv[j] = h;
+                    inf[j] = (uint32_t)(i0 + j - r) < ibound ? (uint16_t)r : (uint16_t)0;
+                }
                 if (j + 1 < RUN) G = ((G << bits) | ((N[j >> 2] >> (8 * (j & 3))) & 0xFFu)) & cmask;
             }
-            inf[0] |= i0 == 0 ? (uint16_t)0x8000 : (uint16_t)0;  // string start
-            // interior positions of the run that are tile positions: j in [jlo, jhi)
-            const int jlo = max(max(r - i0, H - idx0), 0);
-            const int jhi = min(min(npos - r - i0, H + TP - idx0), RUN);
-            lrmin = jlo < jhi ? r : lrmin;
-            lmax = jlo < jhi ? 31 - __clz(r) : 0;
+            if constexpr (!TWO) {
+                inf[0] |= i0 == 0 ? (uint16_t)0x8000 : (uint16_t)0;  // string start
+                // interior positions of the run that are tile positions: j in [jlo, jhi)
+                const int jlo = max(max(r - i0, H - idx0), 0);
+                const int jhi = min(min(npos - r - i0, H + TP - idx0), RUN);
+                lrmin = jlo < jhi ? r : lrmin;
+                lmax = jlo < jhi ? 31 - __clz(r) : 0;
+            }
             // 16-byte stores of the thread's RUN hash slots and RUN info slots
             {
                 uint32_t hw[RUN * sizeof(V) / 4];
@@ -377,6 +405,14 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 for (int i = 0; i < RUN / 8; i++)
                     di[i] = make_uint4(iw[4 * i], iw[4 * i + 1], iw[4 * i + 2], iw[4 * i + 3]);
             }
+        };
+        // one body per wave: where a lane needs fast2, every fast lane of the wave takes it
+        // (it covers the fast1 case), so the wave does not run both
+        const bool wave_two = __any(fast2);
+        if (fast1 && !wave_two) {
+            hash_run(std::false_type{});
+        } else if (fast1 || fast2) {
+            hash_run(std::true_type{});
         } else {
             uint64_t G = 0;
             int64_t have_end = -1;  // G is valid for the previous position in the same string
