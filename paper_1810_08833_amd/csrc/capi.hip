@@ -110,16 +110,22 @@ static PartitionParams to_pp(const mj_params *p, int bits) {
     return pp;
 }
 
-static DevStrings view(const mj_strings *s, hipStream_t st, uint64_t *pinned) {
+// With read_total false the symbol count stays unknown (-1) until prepare_strings reads it
+// back together with its own results.
+static DevStrings view(const mj_strings *s, hipStream_t st, uint64_t *pinned,
+                       bool read_total = true) {
     DevStrings d;
     d.chars = s->chars;
     d.offsets = s->offsets;
     d.n = s->n;
     d.sigma = s->sigma;
     d.bits = symbol_bits(s->sigma);
+    if (!read_total && s->n > 0) {
+        d.total = -1;
+        return d;
+    }
     d.total = s->n > 0 ? read_back<int64_t>(s->offsets + s->n, st, pinned) : 0;
-    if (d.total < 0) throw Error(MJ_EINVAL, "offsets[n] < 0");
-    if (d.total > 0 && !s->chars) throw Error(MJ_EINVAL, "chars is NULL");
+    check_total(d);
     return d;
 }
 
@@ -168,23 +174,28 @@ static void check_flags(const uint8_t *f, int64_t n, Workspace &ws, hipStream_t 
 }
 
 // Verification of library-produced pairs with the chosen verifier.
-static int64_t run_verify(mj_ctx *ctx, const uint64_t *pairs, int64_t n, const DevStrings &A,
-                          const DevStrings &B, int kmode, int64_t uniform_k, int verifier,
-                          uint8_t *flags, hipStream_t s, mj_stats *stats) {
+// The band-cell count lands in *cells_h (pinned), valid after the stream's next
+// synchronisation.
+static void run_verify(mj_ctx *ctx, const uint64_t *pairs, int64_t n, const DevStrings &A,
+                       const DevStrings &B, int kmode, int64_t uniform_k, int verifier,
+                       uint8_t *flags, hipStream_t s, mj_stats *stats, uint64_t *cells_h) {
+    *cells_h = 0;
     if (verifier == MJ_VERIFY_BATCHED) {
-        int64_t cells = verify_pairs_batched(pairs, n, A, B, kmode, flags, ctx->ws, s, ctx->pinned,
-                                             &ctx->kt, &ctx->tune);
+        verify_pairs_batched(pairs, n, A, B, kmode, flags, ctx->ws, s, ctx->pinned, &ctx->kt,
+                             &ctx->tune, uniform_k, cells_h);
         if (stats) {
             stats->verify_group = ctx->tune.last_g;
             stats->verify_words = ctx->tune.last_nwl;
         }
-        return cells;
+        return;
     }
-    int64_t cells = verify_pairs(pairs, n, A, B, kmode, flags, ctx->ws, s, ctx->pinned, &ctx->kt,
-                                 uniform_k);
+    *cells_h = (uint64_t)verify_pairs(pairs, n, A, B, kmode, flags, ctx->ws, s, ctx->pinned,
+                                      &ctx->kt, uniform_k);
     if (uniform_k < 0) check_flags(flags, n, ctx->ws, s, ctx->pinned);
-    return cells;
 }
+
+// last word of the pinned scratch: the deferred band-cell count
+static uint64_t *cells_slot(mj_ctx *ctx) { return ctx->pinned + HOST_SCRATCH_BYTES / 8 - 1; }
 
 struct StageTimer {
     mj_ctx *ctx;
@@ -221,7 +232,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     Workspace &ws = ctx->ws;
     Released rel{ws};
     StageTimer tm(ctx, s);
-    DevStrings d = view(strings, s, ctx->pinned);
+    DevStrings d = view(strings, s, ctx->pinned, false);
     PartitionParams pp = to_pp(params, d.bits);
     int32_t halo = prepare_strings(d, pp, ws, s, ctx->pinned);
     if (upto >= 2) pack_planes(d, verify_planes(d.bits), ws, s);
@@ -262,9 +273,10 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     }
     struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
     uint8_t *flags = ws.get_n<uint8_t>(C + 1);
-    int64_t cells = run_verify(ctx, uniq, C, d, d, 0, params->k, params->verifier, flags, s, stats);
+    run_verify(ctx, uniq, C, d, d, 0, params->k, params->verifier, flags, s, stats, cells_slot(ctx));
     tm.mark();  // 5 verify
-    mj_pairs *out = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);
+    mj_pairs *out = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);  // synchronises when C > 0
+    const int64_t cells = (int64_t)*cells_slot(ctx);
     tm.mark();  // 6 output
     if (stats) {
         stats->output = out->n;
@@ -438,7 +450,7 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
     Released rel{ws};
     StageTimer tm(ctx, s);
     if (stats) memset(stats, 0, sizeof(*stats));
-    DevStrings qd = view(queries, s, ctx->pinned);
+    DevStrings qd = view(queries, s, ctx->pinned, false);
     qd.sigma = ix->sigma;
     qd.bits = ix->bits;
     PartitionParams qp = ix->pp;  // q, seed, T rule, reps of the index
@@ -483,9 +495,11 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
     struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
     tm.mark();  // 4 dedup
     uint8_t *flags = ws.get_n<uint8_t>(C + 1);
-    int64_t cells = run_verify(ctx, uniq, C, qd, id, 1, qparams->k, qparams->verifier, flags, s, stats);
+    run_verify(ctx, uniq, C, qd, id, 1, qparams->k, qparams->verifier, flags, s, stats,
+               cells_slot(ctx));
     tm.mark();  // 5 verify
-    mj_pairs *res = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);
+    mj_pairs *res = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);  // synchronises when C > 0
+    const int64_t cells = (int64_t)*cells_slot(ctx);
     tm.mark();  // 6 output
     if (stats) {
         stats->records = rb.count;

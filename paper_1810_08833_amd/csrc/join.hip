@@ -56,8 +56,14 @@ GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t
     MJ_LAUNCH_CHECK();
     int64_t *gs = ws.get_n<int64_t>(R / 2 + 2);
     int64_t *ge = ws.get_n<int64_t>(R / 2 + 2);
-    int64_t G1 = compact_flags(fs, R, gs, ws, s, host_scratch);
-    int64_t G2 = compact_flags(fe, R, ge, ws, s, host_scratch);
+    const uint32_t *c1 = compact_flags_async(fs, R, gs, ws, s);
+    const uint32_t *c2 = compact_flags_async(fe, R, ge, ws, s);
+    MJ_HIP(hipMemcpyAsync(host_scratch, c1, 4, hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipMemcpyAsync((uint8_t *)host_scratch + 4, c2, 4, hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipStreamSynchronize(s));
+    uint32_t hc[2];
+    memcpy(hc, host_scratch, 8);
+    const int64_t G1 = hc[0], G2 = hc[1];
     if (G1 != G2) throw Error(MJ_EDEVICE, "group boundary mismatch");
     gi.groups = G1;
     gi.gstart = gs;

@@ -100,6 +100,9 @@ void exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, Workspace 
 // Indices i (ascending) with flags[i] != 0; returns count (reads it back).
 int64_t compact_flags(const uint8_t *flags, int64_t n, int64_t *idx_out, Workspace &ws,
                       hipStream_t s, uint64_t *host_scratch);
+// The same without the read-back: returns the device address of the count (n >= 1).
+const uint32_t *compact_flags_async(const uint8_t *flags, int64_t n, int64_t *idx_out,
+                                    Workspace &ws, hipStream_t s);
 // Size of the pinned host buffer each context keeps for small device-to-host reads.
 constexpr size_t HOST_SCRATCH_BYTES = 16384;
 
@@ -139,6 +142,11 @@ struct DevStrings {
     uint32_t *planes = nullptr;  // bit planes: planes[p * plane_words + w]
     int64_t plane_words = 0;
 };
+
+inline void check_total(const DevStrings &d) {
+    if (d.total < 0) throw Error(MJ_EINVAL, "offsets[n] < 0");
+    if (d.total > 0 && !d.chars) throw Error(MJ_EINVAL, "chars is NULL");
+}
 
 struct PartitionParams {
     int q, bits, t_div, t_fixed, reps;
@@ -214,10 +222,15 @@ struct VerifyTuning {
     int best_blocks[64][4] = {};
     int last_g = 0, last_nwl = 0, last_blocks = 0;
 };
+// uniform_k >= 0 promises that every pair's K equals it and that all ids are valid (pairs
+// produced by the library): the pass that finds the largest K is skipped.  With
+// cells_defer set (pinned host memory) the band-cell count is copied there
+// asynchronously and the call returns 0 without synchronising.
 int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings &A,
                              const DevStrings &B, int kmode, uint8_t *flags, Workspace &ws,
                              hipStream_t s, uint64_t *host_scratch, KTimer *kt,
-                             VerifyTuning *tune);
+                             VerifyTuning *tune, int64_t uniform_k = -1,
+                             uint64_t *cells_defer = nullptr);
 int persist_max_c();
 
 }  // namespace mj

@@ -74,9 +74,16 @@ int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, 
         MJ_LAUNCH_CHECK();
     }
     MJ_HIP(hipMemcpyAsync(host_scratch, flags, 8, hipMemcpyDeviceToHost, s));
+    const bool want_total = d.total < 0;  // offsets[n] read back with the flags
+    if (want_total)
+        MJ_HIP(hipMemcpyAsync(host_scratch + 1, d.offsets + n, 8, hipMemcpyDeviceToHost, s));
     MJ_HIP(hipStreamSynchronize(s));
     uint32_t hv[2];
     memcpy(hv, host_scratch, 8);
+    if (want_total) {
+        d.total = (int64_t)host_scratch[1];
+        check_total(d);
+    }
     if (hv[1] & 1u) throw Error(MJ_EINVAL, "offsets must be non-decreasing with lengths < 2^31");
     if (hv[1] & 2u) throw Error(MJ_EINVAL, "K must be >= 0");
     return (int32_t)hv[0];
@@ -84,43 +91,74 @@ int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, 
 
 // ---------------------------------------------------------------- bit planes
 // planes[p][w] bit t = bit p of the symbol at global position 32w + t (0 past the end).
-// With 16-byte aligned symbols a thread reads its 32 symbols as two 16-byte loads.
-__device__ __forceinline__ void pack_bytes(uint32_t word, int t0, uint32_t acc[8]) {
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        uint32_t c = (word >> (8 * k)) & 0xFFu;
-#pragma unroll
-        for (int p = 0; p < 8; p++) acc[p] |= ((c >> p) & 1u) << (t0 + k);
-    }
+// With 16-byte aligned symbols a thread reads its 32 symbols as two 16-byte loads and
+// transposes each group of 8 as an 8x8 bit matrix (three delta swaps: Hacker's Delight,
+// sec. 7-3), after which byte p of the result holds plane p's bits of those 8 symbols.
+__device__ __forceinline__ uint64_t transpose8x8(uint64_t x) {
+    uint64_t t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+    x ^= t ^ (t << 7);
+    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+    x ^= t ^ (t << 14);
+    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+    x ^= t ^ (t << 28);
+    return x;
 }
 
+// byte p of each of y[0..3], in that order, as one word (v_perm: bytes 0-3 of the second
+// operand, 4-7 of the first; selector 0x0C gives a zero byte)
+template <int P>
+__device__ __forceinline__ uint32_t gather_byte(const uint64_t y[4]) {
+    constexpr int b = P & 3;
+    const uint32_t w0 = (uint32_t)(y[0] >> (P < 4 ? 0 : 32)), w1 = (uint32_t)(y[1] >> (P < 4 ? 0 : 32));
+    const uint32_t w2 = (uint32_t)(y[2] >> (P < 4 ? 0 : 32)), w3 = (uint32_t)(y[3] >> (P < 4 ? 0 : 32));
+    constexpr uint32_t sel = (uint32_t)b | ((uint32_t)(b + 4) << 8) | (0x0Cu << 16) | (0x0Cu << 24);
+    const uint32_t lo = __builtin_amdgcn_perm(w1, w0, sel);
+    const uint32_t hi = __builtin_amdgcn_perm(w3, w2, sel);
+    return lo | (hi << 16);
+}
+
+template <int NP>
 __global__ void k_pack_planes(const uint8_t *chars, int64_t total, uint32_t *planes,
-                              int64_t plane_words, int np, int aligned) {
+                              int64_t plane_words, int aligned) {
     int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; w < plane_words; w += stride) {
-        uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        uint32_t acc[NP];
         int64_t base = w * 32;
         if (aligned && base + 32 <= total) {
             const uint4 *v = reinterpret_cast<const uint4 *>(chars + base);
-            uint4 a = v[0], b = v[1];
-            pack_bytes(a.x, 0, acc);
-            pack_bytes(a.y, 4, acc);
-            pack_bytes(a.z, 8, acc);
-            pack_bytes(a.w, 12, acc);
-            pack_bytes(b.x, 16, acc);
-            pack_bytes(b.y, 20, acc);
-            pack_bytes(b.z, 24, acc);
-            pack_bytes(b.w, 28, acc);
+            const uint4 a = v[0], b = v[1];
+            uint64_t y[4];
+            y[0] = transpose8x8(((uint64_t)a.y << 32) | a.x);
+            y[1] = transpose8x8(((uint64_t)a.w << 32) | a.z);
+            y[2] = transpose8x8(((uint64_t)b.y << 32) | b.x);
+            y[3] = transpose8x8(((uint64_t)b.w << 32) | b.z);
+            acc[0] = gather_byte<0>(y);
+            acc[1] = gather_byte<1>(y);
+            if constexpr (NP > 2) {
+                acc[2] = gather_byte<2>(y);
+                acc[3] = gather_byte<3>(y);
+            }
+            if constexpr (NP > 4) {
+                acc[4] = gather_byte<4>(y);
+                acc[5] = gather_byte<5>(y);
+            }
+            if constexpr (NP > 6) {
+                acc[6] = gather_byte<6>(y);
+                acc[7] = gather_byte<7>(y);
+            }
         } else {
+#pragma unroll
+            for (int p = 0; p < NP; p++) acc[p] = 0;
             for (int t = 0; t < 32; t++) {
                 int64_t g = base + t;
                 uint32_t c = g < total ? chars[g] : 0u;
 #pragma unroll
-                for (int p = 0; p < 8; p++) acc[p] |= ((c >> p) & 1u) << t;
+                for (int p = 0; p < NP; p++) acc[p] |= ((c >> p) & 1u) << t;
             }
         }
-        for (int p = 0; p < np; p++) planes[(int64_t)p * plane_words + w] = acc[p];
+#pragma unroll
+        for (int p = 0; p < NP; p++) planes[(int64_t)p * plane_words + w] = acc[p];
     }
 }
 
@@ -128,8 +166,14 @@ void pack_planes(DevStrings &d, int np, Workspace &ws, hipStream_t s) {
     d.plane_words = (d.total + 31) / 32 + 96;  // padding: windows may read past the end
     d.planes = ws.get_n<uint32_t>((size_t)np * d.plane_words);
     int aligned = ((uintptr_t)d.chars & 15) == 0 ? 1 : 0;
-    hipLaunchKernelGGL(k_pack_planes, dim3(grid_for(d.plane_words, 256, 16384)), dim3(256), 0, s,
-                       d.chars, d.total, d.planes, d.plane_words, np, aligned);
+    const dim3 grid(grid_for(d.plane_words, 256, 16384));
+    switch (np) {
+        case 2: hipLaunchKernelGGL(k_pack_planes<2>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned); break;
+        case 4: hipLaunchKernelGGL(k_pack_planes<4>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned); break;
+        case 6: hipLaunchKernelGGL(k_pack_planes<6>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned); break;
+        case 8: hipLaunchKernelGGL(k_pack_planes<8>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned); break;
+        default: throw Error(MJ_EINVAL, "plane count must be 2, 4, 6 or 8");
+    }
     MJ_LAUNCH_CHECK();
 }
 
@@ -253,7 +297,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     __shared__ TileDesc td;
     __shared__ int16_t barg[REGION / AT_BLOCK];
     __shared__ V bmin[REGION / AT_BLOCK];
-    __shared__ uint16_t rank_s[NRANK];
+    __shared__ __align__(16) uint16_t rank_s[NRANK];
     __shared__ int32_t kmax_s, rmin_s;
     const int NR = TP + 2 * H;
     const int tid = threadIdx.x;
@@ -283,7 +327,10 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     for (int w = tid; w < REGION / 32; w += AT_THREADS) aflag[w] = 0;
     if constexpr (RANKED) {
         const int nr = 1 << (q * bits);
-        for (int c = tid; c < nr; c += AT_THREADS) rank_s[c] = rank[c];
+        // 16-byte copies (the table is a workspace block: 16-byte aligned, with 16 bytes of
+        // slack past its end)
+        for (int c = tid; c < (nr + 7) / 8; c += AT_THREADS)
+            reinterpret_cast<uint4 *>(rank_s)[c] = reinterpret_cast<const uint4 *>(rank)[c];
     }
     __syncthreads();
     const int32_t ns = td.ns;

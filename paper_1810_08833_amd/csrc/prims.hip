@@ -242,9 +242,8 @@ __global__ void k_compact_scatter(const uint8_t *flags, const uint32_t *pre, int
         if (flags[i]) idx[pre[i]] = i;
 }
 
-int64_t compact_flags(const uint8_t *flags, int64_t n, int64_t *idx_out, Workspace &ws,
-                      hipStream_t s, uint64_t *host_scratch) {
-    if (n <= 0) return 0;
+const uint32_t *compact_flags_async(const uint8_t *flags, int64_t n, int64_t *idx_out,
+                                    Workspace &ws, hipStream_t s) {
     // 32-bit ranks: the count of kept elements must stay below 2^32
     if (n > 0xFFFFFFF0LL) throw Error(MJ_ECAPACITY, "compaction of more than 2^32 elements");
     uint32_t *pre = ws.get_n<uint32_t>(n + 1);
@@ -252,7 +251,14 @@ int64_t compact_flags(const uint8_t *flags, int64_t n, int64_t *idx_out, Workspa
     hipLaunchKernelGGL(k_compact_scatter, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, flags,
                        pre, n, idx_out);
     MJ_LAUNCH_CHECK();
-    return (int64_t)read_back<uint32_t>(pre + n, s, host_scratch);
+    return pre + n;
+}
+
+int64_t compact_flags(const uint8_t *flags, int64_t n, int64_t *idx_out, Workspace &ws,
+                      hipStream_t s, uint64_t *host_scratch) {
+    if (n <= 0) return 0;
+    return (int64_t)read_back<uint32_t>(compact_flags_async(flags, n, idx_out, ws, s), s,
+                                        host_scratch);
 }
 
 __global__ void k_gather_u64(const uint64_t *src, const int64_t *idx, uint64_t *dst, int64_t n) {

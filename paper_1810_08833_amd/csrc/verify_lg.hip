@@ -516,7 +516,7 @@ static void launch_persist(int nwl, int g, int np, int max_blocks, const uint64_
 int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings &A,
                              const DevStrings &B, int kmode, uint8_t *flags, Workspace &ws,
                              hipStream_t s, uint64_t *host_scratch, KTimer *kt,
-                             VerifyTuning *tune) {
+                             VerifyTuning *tune, int64_t uniform_k, uint64_t *cells_defer) {
     if (n <= 0) return 0;
     if (A.planes == nullptr || B.planes == nullptr) throw Error(MJ_EINVAL, "strings not packed");
     const int np = verify_planes(std::max(A.bits, B.bits));
@@ -525,21 +525,27 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     unsigned long long *next = (unsigned long long *)ws.get_n<uint64_t>(QUEUES * QSTRIDE);
     uint32_t *cm = ws.get_n<uint32_t>(4);
     fill_u64((uint64_t *)cells, 0, 1, s);
-    fill_u32(cm, 0, 2, s);
-    hipLaunchKernelGGL(k_pair_cmax, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, pairs, n, va, vb,
-                       kmode, cm, cm + 1);
-    MJ_LAUNCH_CHECK();
     // longest pairs first
     uint32_t *cnt = ws.get_n<uint32_t>(LPT_BINS + 1);
     uint32_t *off = ws.get_n<uint32_t>(LPT_BINS + 1);
     uint32_t *fillc = ws.get_n<uint32_t>(LPT_BINS + 1);
     int64_t *order = ws.get_n<int64_t>(n);
-    MJ_HIP(hipMemcpyAsync(host_scratch, cm, 8, hipMemcpyDeviceToHost, s));
-    MJ_HIP(hipStreamSynchronize(s));
-    uint32_t hv[2];
-    memcpy(hv, host_scratch, 8);
-    if (hv[1]) throw Error(MJ_EINVAL, "pair names a string id out of range");
-    const int cmax = (int)hv[0];
+    int cmax;
+    if (uniform_k >= 0) {
+        // every pair's K is known (and its ids valid): no pass over the pairs
+        cmax = (int)((std::min<int64_t>(uniform_k, 0x3FFFFFFF) + 31) >> 5);
+    } else {
+        fill_u32(cm, 0, 2, s);
+        hipLaunchKernelGGL(k_pair_cmax, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, pairs, n, va,
+                           vb, kmode, cm, cm + 1);
+        MJ_LAUNCH_CHECK();
+        MJ_HIP(hipMemcpyAsync(host_scratch, cm, 8, hipMemcpyDeviceToHost, s));
+        MJ_HIP(hipStreamSynchronize(s));
+        uint32_t hv[2];
+        memcpy(hv, host_scratch, 8);
+        if (hv[1]) throw Error(MJ_EINVAL, "pair names a string id out of range");
+        cmax = (int)hv[0];
+    }
     if (cmax > persist_max_c())
         throw Error(MJ_ECAPACITY, "threshold K above the batched verifier's band limit (K <= 2047)");
     fill_u32(cnt, 0, LPT_BINS, s);
@@ -610,6 +616,11 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
         tune->last_g = best_g;
         tune->last_nwl = nwl_for(nw, best_g);
         tune->last_blocks = best_blocks;
+    }
+    if (cells_defer) {
+        // the caller reads it after its next synchronisation of the stream
+        MJ_HIP(hipMemcpyAsync(cells_defer, cells, 8, hipMemcpyDeviceToHost, s));
+        return 0;
     }
     return (int64_t)read_back<uint64_t>((const uint64_t *)cells, s, host_scratch);
 }
