@@ -128,8 +128,12 @@ def roofline(kernel, stats, kms, kln, bits, q):
         ops = cells / 32.0 * ops_per_word_column(bits)
         last = stats[-1]
         planes = {1: 2, 2: 2, 3: 4, 4: 4, 5: 6, 6: 6}.get(bits, 8)
-        vcfg = "<%d, %d, %d>" % (last["verify_words"], last["verify_group"], planes)
-        r.update(kernel="k_verify_persist" + vcfg, bound="alu", unit="Tops/s",
+        if last["verify_group"] == -2:  # two lanes per pair, split by text columns
+            kname, vcfg = "k_verify_bidir", "<%d, %d>" % (last["verify_words"], planes)
+        else:
+            kname = "k_verify_persist"
+            vcfg = "<%d, %d, %d>" % (last["verify_words"], last["verify_group"], planes)
+        r.update(kernel=kname + vcfg, bound="alu", unit="Tops/s",
                  achieved=ops / secs / 1e12, peak=INT_PEAK_TOPS,
                  traffic=measured_traffic(src, vcfg), band_cells_per_s=cells / secs)
     elif kernel == "anchors":

@@ -73,7 +73,12 @@ typedef struct {
  *   verifier MJ_VERIFY_BATCHED (0): all candidates in one persistent launch, a pair per
  *            lane group, longest pairs first, group width timed once per context;
  *            MJ_VERIFY_PLAIN (1): a pair per lane, one launch per band size.  Both give
- *            the same decisions. */
+ *            the same decisions.
+ *   verify_lanes  batched verifier only: 0 lets the context time the choices (the
+ *            default); 1, 2, 4 or 8 fixes the lanes per pair that split the band words;
+ *            -2 fixes two lanes per pair that split the text columns (one runs forward
+ *            over the first half, the other over the reversed second half).  A fixed
+ *            choice whose lanes cannot hold the band fails with MJ_ECAPACITY. */
 typedef struct {
     int32_t q;
     int32_t t_div;
@@ -84,7 +89,7 @@ typedef struct {
     const int32_t *k_per_string;
     const uint64_t *pi_table;
     int32_t verifier;
-    int32_t reserved;
+    int32_t verify_lanes;
 } mj_params;
 
 enum { MJ_VERIFY_BATCHED = 0, MJ_VERIFY_PLAIN = 1 };
@@ -108,7 +113,8 @@ typedef struct {
     float kernel_ms[4];
     int32_t kernel_launches[4];
     int64_t positions;   /* symbols scanned by the anchor kernel, over all repetitions */
-    int32_t verify_group;  /* lanes per pair of the batched verifier (0: plain) */
+    int32_t verify_group;  /* lanes per pair of the batched verifier (0: plain; -2: two
+                              lanes splitting the text columns, forward and reversed) */
     int32_t verify_words;  /* band words per lane of the batched verifier */
 } mj_stats;
 

@@ -36,7 +36,7 @@ class MjParams(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int32), ("t_div", ctypes.c_int32), ("t_fixed", ctypes.c_int32),
                 ("reps", ctypes.c_int32), ("seed", ctypes.c_uint64), ("k", ctypes.c_int64),
                 ("k_per_string", ctypes.c_void_p), ("pi_table", ctypes.c_void_p),
-                ("verifier", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("verifier", ctypes.c_int32), ("verify_lanes", ctypes.c_int32)]
 
 
 class MjStats(ctypes.Structure):
@@ -231,10 +231,12 @@ class Params:
     seed: int = 0
     pi_table: Optional[object] = None       # torch uint64/int64 tensor on the GPU
     verifier: int = VERIFY_BATCHED          # or VERIFY_PLAIN
+    verify_lanes: int = 0                   # batched: 0 timed; 1/2/4/8 word split; -2 column split
 
     def struct(self) -> MjParams:
         p = MjParams()
         p.verifier = self.verifier
+        p.verify_lanes = self.verify_lanes
         p.q, p.t_div, p.t_fixed, p.reps = self.q, self.t_div, self.t_fixed, self.reps
         p.seed = self.seed
         p.k = self.k if self.k_per_string is None else -1

@@ -88,6 +88,9 @@ static void check_params(const mj_params *p, int sigma, bool need_k) {
     if (p->pi_table && (int64_t)p->q * b > 24) throw Error(MJ_EINVAL, "pi_table needs q*b <= 24");
     if (p->verifier != MJ_VERIFY_BATCHED && p->verifier != MJ_VERIFY_PLAIN)
         throw Error(MJ_EINVAL, "verifier must be MJ_VERIFY_BATCHED or MJ_VERIFY_PLAIN");
+    if (p->verify_lanes != 0 && p->verify_lanes != 1 && p->verify_lanes != 2 &&
+        p->verify_lanes != 4 && p->verify_lanes != 8 && p->verify_lanes != -2)
+        throw Error(MJ_EINVAL, "verify_lanes must be 0, 1, 2, 4, 8 or -2");
 }
 
 static void check_strings(const mj_strings *s) {
@@ -177,14 +180,14 @@ static void check_flags(const uint8_t *f, int64_t n, Workspace &ws, hipStream_t 
 // The band-cell count lands in *cells_h (pinned), valid after the stream's next
 // synchronisation.
 static void run_verify(mj_ctx *ctx, const uint64_t *pairs, int64_t n, const DevStrings &A,
-                       const DevStrings &B, int kmode, int64_t uniform_k, int verifier,
+                       const DevStrings &B, int kmode, int64_t uniform_k, const mj_params *p,
                        uint8_t *flags, hipStream_t s, mj_stats *stats, uint64_t *cells_h) {
     *cells_h = 0;
-    if (verifier == MJ_VERIFY_BATCHED) {
+    if (p->verifier == MJ_VERIFY_BATCHED) {
         verify_pairs_batched(pairs, n, A, B, kmode, flags, ctx->ws, s, ctx->pinned, &ctx->kt,
-                             &ctx->tune, uniform_k, cells_h);
+                             &ctx->tune, uniform_k, cells_h, p->verify_lanes);
         if (stats) {
-            stats->verify_group = ctx->tune.last_g;
+            stats->verify_group = ctx->tune.last_g == VERIFY_BIDIR ? -2 : ctx->tune.last_g;
             stats->verify_words = ctx->tune.last_nwl;
         }
         return;
@@ -273,7 +276,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     }
     struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
     uint8_t *flags = ws.get_n<uint8_t>(C + 1);
-    run_verify(ctx, uniq, C, d, d, 0, params->k, params->verifier, flags, s, stats, cells_slot(ctx));
+    run_verify(ctx, uniq, C, d, d, 0, params->k, params, flags, s, stats, cells_slot(ctx));
     tm.mark();  // 5 verify
     mj_pairs *out = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);  // synchronises when C > 0
     const int64_t cells = (int64_t)*cells_slot(ctx);
@@ -354,7 +357,8 @@ extern "C" mj_status mj_verify(mj_ctx *ctx, const mj_strings *strings, const mj_
     (void)prepare_strings(d, pp, ws, s, ctx->pinned);
     pack_planes(d, verify_planes(d.bits), ws, s);
     if (params->verifier == MJ_VERIFY_BATCHED) {
-        verify_pairs_batched(pairs, n, d, d, 0, flags, ws, s, ctx->pinned, nullptr, &ctx->tune);
+        verify_pairs_batched(pairs, n, d, d, 0, flags, ws, s, ctx->pinned, nullptr, &ctx->tune, -1,
+                             nullptr, params->verify_lanes);
     } else {
         verify_pairs(pairs, n, d, d, 0, flags, ws, s, ctx->pinned);
         check_flags(flags, n, ws, s, ctx->pinned);
@@ -495,8 +499,7 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
     struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
     tm.mark();  // 4 dedup
     uint8_t *flags = ws.get_n<uint8_t>(C + 1);
-    run_verify(ctx, uniq, C, qd, id, 1, qparams->k, qparams->verifier, flags, s, stats,
-               cells_slot(ctx));
+    run_verify(ctx, uniq, C, qd, id, 1, qparams->k, qparams, flags, s, stats, cells_slot(ctx));
     tm.mark();  // 5 verify
     mj_pairs *res = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);  // synchronises when C > 0
     const int64_t cells = (int64_t)*cells_slot(ctx);

@@ -217,6 +217,9 @@ int verify_planes(int bits);   // planes the verifier needs for b bits per symbo
 
 // verify_lg.hip: one persistent launch for all pairs (lane groups, longest first).
 // The lane-group width is timed once per (ceil(Kmax/32), planes) and kept in `tune`.
+// VerifyTuning::last_g value of the kernel that splits each pair's text columns over two
+// lanes (forward and reversed halves)
+constexpr int VERIFY_BIDIR = 3;
 struct VerifyTuning {
     int best_g[64][4] = {};
     int best_blocks[64][4] = {};
@@ -225,12 +228,13 @@ struct VerifyTuning {
 // uniform_k >= 0 promises that every pair's K equals it and that all ids are valid (pairs
 // produced by the library): the pass that finds the largest K is skipped.  With
 // cells_defer set (pinned host memory) the band-cell count is copied there
-// asynchronously and the call returns 0 without synchronising.
+// asynchronously and the call returns 0 without synchronising.  force_lanes != 0 fixes
+// the configuration (mj_params.verify_lanes) instead of the timed choice.
 int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings &A,
                              const DevStrings &B, int kmode, uint8_t *flags, Workspace &ws,
                              hipStream_t s, uint64_t *host_scratch, KTimer *kt,
                              VerifyTuning *tune, int64_t uniform_k = -1,
-                             uint64_t *cells_defer = nullptr);
+                             uint64_t *cells_defer = nullptr, int force_lanes = 0);
 int persist_max_c();
 
 }  // namespace mj

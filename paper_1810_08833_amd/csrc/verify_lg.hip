@@ -369,12 +369,369 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
     if (lane == 0 && my_cells) atomicAdd(cells, (unsigned long long)my_cells);
 }
 
+// ---------------------------------------------------------------- split by columns
+// Lanes 2k and 2k + 1 share a pair.  Lane 2k runs the one-lane recurrence over the first
+// mid = nt / 2 text columns; lane 2k + 1 runs it over the reversed pattern and the
+// reversed remaining text (its cell (i', j') is the forward cell (mp - i', nt - j')).  The
+// reversed problem has the same length difference and hence the same band diagonals, so
+// each half is the one-lane loop with direction-dependent loads.  Splitting the text at
+// column mid (Hirschberg's middle-column decomposition),
+//   ED(X, Y) = min over rows i of D(X[0, i), Y[0, mid)) + D(X[i, mp), Y[mid, nt)),
+// and an alignment of cost <= K crosses column mid inside the band, where both halves hold
+// exact values whenever they are <= K: the decision ED <= K is that of the one-lane kernel.
+// A pair's latency halves; texts shorter than 64 columns stay with the first lane alone.
+__device__ __forceinline__ uint32_t load_dir(const uint32_t *plane, int64_t bitpos, bool rev) {
+    // forward: symbols bitpos .. bitpos + 31 at bits 0 .. 31; reversed: bit t holds symbol
+    // bitpos + 31 - t.  Positions before the start of the planes read as 0.
+    uint32_t w;
+    if (bitpos >= 0) w = load_word(plane, bitpos);
+    else if (bitpos > -32) w = load_word(plane, 0) << (uint32_t)(-bitpos);
+    else w = 0u;
+    return rev ? __builtin_bitreverse32(w) : w;
+}
+
+// 32 bits of a padded window (A[0] = 0, A[1 .. NW] = the words, A[NW + 1] = 0) starting
+// at bit e of the unpadded words, -32 < e < 32 NW
+template <int NW>
+__device__ __forceinline__ uint32_t window_bits(const uint32_t (*A)[128], int slot, int e) {
+    const int f = e + 32;
+    return __builtin_amdgcn_alignbit(A[(f >> 5) + 1][slot], A[f >> 5][slot], (uint32_t)(f & 31));
+}
+
+template <int NW, int NP>
+__global__ __launch_bounds__(256) void k_verify_bidir(const uint64_t *__restrict__ pairs,
+                                                      const int64_t *__restrict__ order,
+                                                      int64_t n, VSet A, VSet B, int kmode,
+                                                      uint8_t *__restrict__ flags,
+                                                      unsigned long long *cells,
+                                                      unsigned long long *next) {
+    // meeting of the two halves: the forward and backward windows of each pair's first lane
+    __shared__ uint32_t meet[4][NW + 2][128];
+    const int lane = threadIdx.x & 63;
+    const bool bwd = (lane & 1) != 0;
+    const int leader_lane = lane & ~1;
+    const int slot = threadIdx.x >> 1;
+    bool active = false, exhausted = false, done = false, rej = false, solo = false;
+    int lbv = 0;  // lower bound of this half's window values at its current column
+    uint8_t solo_res = 0;
+    int qj = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % QUEUES);
+    int qdry = 0;
+    int64_t pi = 0;
+    int32_t K = 0, mp = 0, nt = 0, ncols = 0, mid = 0, wlo = 0, jb = 0, S = 0, band = 0;
+    int32_t phi = 32, blo = 0, bhi = 0;
+    int64_t offx = 0, offy = 0, pwx = 0, pwy = 0;
+    const uint32_t *PX = nullptr, *PY = nullptr;
+    uint32_t Pv[NW], Mv[NW], V[NW], PL[NP][NW];
+    uint32_t TYc[NP], TYn[NP], PLn[NP];
+    uint64_t my_cells = 0;
+#pragma unroll
+    for (int s = 0; s < NW; s++) {
+        Pv[s] = Mv[s] = V[s] = 0;
+#pragma unroll
+        for (int p = 0; p < NP; p++) PL[p][s] = 0;
+    }
+    // the half's pattern word w and text word at column j (reversed for the second lane)
+    auto xword = [&](int p, int w) -> uint32_t {
+        const int64_t pos = bwd ? offx + mp - 32 - 32 * (int64_t)w : offx + 32 * (int64_t)w;
+        return load_dir(PX + p * pwx, pos, bwd);
+    };
+    auto yword = [&](int p, int j) -> uint32_t {
+        const int64_t pos = bwd ? offy + nt - 32 - (int64_t)j : offy + (int64_t)j;
+        return load_dir(PY + p * pwy, pos, bwd);
+    };
+    auto swap1 = [](uint32_t v) -> uint32_t {  // the partner lane's value (quad_perm 1,0,3,2)
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+    };
+    for (;;) {
+        // ---- resolution of pairs whose halves are both finished, or rejected.  An alignment
+        // within the band pays at least the forward bound before the forward lane's column
+        // and the backward bound after the backward lane's (disjoint parts of it), so the
+        // sum of the two bounds above K rejects the pair as early as one lane would.
+        const int plb = (int)swap1((uint32_t)lbv);
+        if (active && lbv + plb > K) rej = true;
+        const bool pdone = swap1(done ? 1u : 0u) != 0u, prej = swap1(rej ? 1u : 0u) != 0u;
+        const bool res_rej = active && (rej || prej);
+        const bool res_meet = active && !res_rej && done && pdone && !solo;
+        if (__any(res_meet)) {
+            uint32_t oP[NW], oM[NW];
+#pragma unroll
+            for (int s = 0; s < NW; s++) {
+                oP[s] = swap1(Pv[s]);
+                oM[s] = swap1(Mv[s]);
+            }
+            const int oS = (int)swap1((uint32_t)S), oW = (int)swap1((uint32_t)wlo);
+            if (res_meet && !bwd) {
+#pragma unroll
+                for (int s = 0; s < NW; s++) {
+                    meet[0][s + 1][slot] = Pv[s];
+                    meet[1][s + 1][slot] = Mv[s];
+                    meet[2][s + 1][slot] = oP[s];
+                    meet[3][s + 1][slot] = oM[s];
+                }
+#pragma unroll
+                for (int a = 0; a < 4; a++) {
+                    meet[a][0][slot] = 0u;
+                    meet[a][NW + 1][slot] = 0u;
+                }
+                // band rows at column mid, inside the pattern
+                const int ilo = max(0, mid + blo), ihi = min(mp, mid + bhi);
+                // value of a window at row i from its reference row 32 w + 32 (value Sr)
+                auto value_at = [&](int a, int w, int Sr, int i) -> int {
+                    const int rel = i - (32 * w + 32);
+                    int v = Sr;
+                    if (rel >= 0) {
+                        for (int e = 32; e < 32 + rel; e += 32) {  // rows 32w + 33 .. i
+                            const int cnt = min(32, 32 + rel - e);
+                            const uint32_t mk = cnt >= 32 ? ~0u : ((1u << cnt) - 1u);
+                            v += __popc(window_bits<NW>(meet[a], slot, e) & mk) -
+                                 __popc(window_bits<NW>(meet[a + 1], slot, e) & mk);
+                        }
+                    } else {  // rows i + 1 .. 32w + 32, all in slot 0
+                        const uint32_t mk = ~0u << (32 + rel);
+                        v -= __popc(window_bits<NW>(meet[a], slot, 0) & mk) -
+                             __popc(window_bits<NW>(meet[a + 1], slot, 0) & mk);
+                    }
+                    return v;
+                };
+                int Df = value_at(0, wlo, S, ilo);
+                int Db = value_at(2, oW, oS, mp - ilo);
+                int best = Df + Db;
+                // walk down the band: row i -> i + 1 adds the forward delta of row i + 1
+                // (bit i - 32 wlo) and removes the backward delta of row mp - i (bit
+                // mp - i - 1 - 32 oW)
+                for (int i0 = ilo; i0 < ihi && best > K; i0 += 32) {
+                    const int ef = i0 - 32 * wlo;
+                    const int eb = mp - i0 - 1 - 32 * oW;  // bit of step 0; later steps go down
+                    const uint32_t fP = window_bits<NW>(meet[0], slot, ef);
+                    const uint32_t fM = window_bits<NW>(meet[1], slot, ef);
+                    const uint32_t bP = __builtin_bitreverse32(window_bits<NW>(meet[2], slot, eb - 31));
+                    const uint32_t bM = __builtin_bitreverse32(window_bits<NW>(meet[3], slot, eb - 31));
+                    const int steps = min(32, ihi - i0);
+                    for (int t = 0; t < steps; t++) {
+                        Df += (int)((fP >> t) & 1u) - (int)((fM >> t) & 1u);
+                        Db -= (int)((bP >> t) & 1u) - (int)((bM >> t) & 1u);
+                        best = min(best, Df + Db);
+                    }
+                }
+                flags[pi] = best <= K ? 1 : 0;
+            }
+        }
+        if (res_rej && !bwd) flags[pi] = 0;
+        if (active && !res_rej && done && pdone && solo && !bwd) flags[pi] = solo_res;
+        if (res_rej || (active && done && pdone)) {
+            active = false;
+            done = rej = false;
+        }
+
+        // ---- refill: each lane pair without a pair takes the next one
+        const bool need = !active && !exhausted;
+        const uint64_t req = __ballot(need && !bwd);
+        long long got = -1;
+        if (req) {
+            const int first = __ffsll((unsigned long long)req) - 1;
+            const long long qn = n > qj ? (n - qj + QUEUES - 1) / QUEUES : 0;
+            const long long want = __popcll(req);
+            unsigned long long base = 0;
+            if (lane == first) base = atomicAdd(next + qj * QSTRIDE, (unsigned long long)want);
+            const long long b0 = (long long)__shfl(base, first, 64);
+            const long long k = b0 + __popcll(req & ((1ull << lane) - 1));
+            if (need && !bwd && k < qn) got = k * QUEUES + qj;
+            if (b0 + want > qn) {
+                qj = qj + 1 == QUEUES ? 0 : qj + 1;
+                if (++qdry == QUEUES) exhausted = true;
+            }
+        }
+        got = __shfl(got, leader_lane, 64);
+        if (need && got >= 0 && got < n) {
+            pi = order ? order[got] : got;
+            const uint64_t pr = pairs[pi];
+            const int32_t ia = (int32_t)(pr >> 32), ib = (int32_t)(uint32_t)pr;
+            const int32_t ma = A.len[ia], mb = B.len[ib];
+            K = kmode == 0 ? max(A.kk[ia], B.kk[ib]) : A.kk[ia];
+            const bool a_is_x = ma >= mb;
+            PX = a_is_x ? A.planes : B.planes;
+            PY = a_is_x ? B.planes : A.planes;
+            pwx = a_is_x ? A.pw : B.pw;
+            pwy = a_is_x ? B.pw : A.pw;
+            offx = a_is_x ? A.off[ia] : B.off[ib];
+            offy = a_is_x ? B.off[ib] : A.off[ia];
+            mp = a_is_x ? ma : mb;
+            nt = a_is_x ? mb : ma;
+            const int dlen = mp - nt;
+            blo = -((K - dlen) >> 1);
+            bhi = (K + dlen) >> 1;
+            phi = ((-blo - 1) & 31) + 1;
+            const int w0 = ((phi + blo) >> 5) - 1;
+            uint8_t result = 0;
+            bool trivial = true;
+            if (mp - nt > K) {
+                result = 0;
+            } else if (nt == 0) {
+                result = mp <= K;
+            } else if (1 + ((bhi - blo + 31) >> 5) > NW) {
+                result = 2;
+            } else {
+                trivial = false;
+            }
+            if (trivial) {
+                if (!bwd) flags[pi] = result;
+            } else {
+                active = true;
+                solo = nt < 64;
+                mid = solo ? nt : nt >> 1;
+                ncols = bwd ? nt - mid : mid;
+                done = ncols == 0;
+                rej = false;
+                lbv = 0;
+                wlo = w0;
+                jb = 0;
+                S = abs(32 * w0 + 32);
+                band = bhi - blo + 1;
+#pragma unroll
+                for (int s = 0; s < NW; s++) {
+                    const int w = wlo + s;
+                    const bool real = w >= 0;
+                    Pv[s] = real ? ~0u : 0u;
+                    Mv[s] = real ? 0u : ~0u;
+                    V[s] = real ? ~0u : 0u;
+#pragma unroll
+                    for (int p = 0; p < NP; p++) PL[p][s] = real ? xword(p, w) : 0u;
+                }
+#pragma unroll
+                for (int p = 0; p < NP; p++) {
+                    TYc[p] = yword(p, 0);
+                    TYn[p] = yword(p, phi);
+                    PLn[p] = xword(p, w0 + NW);
+                }
+            }
+        }
+        if (__all(!active && exhausted)) break;
+        if (!active || done || rej) continue;
+
+        // ---- one block of up to 32 columns of this lane's half
+        uint32_t TY[NP];
+#pragma unroll
+        for (int p = 0; p < NP; p++) TY[p] = TYc[p];
+        const int cols = min(jb == 0 ? phi : 32, ncols - jb);
+        for (int t = 0; t < cols; t++) {
+            uint32_t tb[NP];
+#pragma unroll
+            for (int p = 0; p < NP; p++) tb[p] = (uint32_t)__builtin_amdgcn_sbfe((int)TY[p], (unsigned)t, 1u);
+            uint32_t eqv[NW], sm[NW];
+            uint32_t carry = 0;
+#pragma unroll
+            for (int s = 0; s < NW; s++) {
+                uint32_t eq = V[s];
+#pragma unroll
+                for (int p = 0; p < NP; p++) eq = and_xnor(eq, PL[p][s], tb[p]);
+                eqv[s] = eq;
+                uint32_t co;
+                sm[s] = __builtin_addc(eq & Pv[s], Pv[s], carry, &co);
+                carry = co;
+            }
+            uint32_t ph[NW], mh[NW];
+#pragma unroll
+            for (int s = 0; s < NW; s++) {
+                const uint32_t xh = (sm[s] ^ Pv[s]) | eqv[s];
+                ph[s] = Mv[s] | ~(xh | Pv[s]);
+                mh[s] = Pv[s] & xh;
+            }
+            S += (int)(ph[0] >> 31) - (int)(mh[0] >> 31);
+            uint32_t phc = 1, mhc = 0;
+#pragma unroll
+            for (int s = 0; s < NW; s++) {
+                const uint32_t xv = eqv[s] | Mv[s];
+                const uint32_t phs = (ph[s] << 1) | phc;
+                phc = ph[s] >> 31;
+                const uint32_t mhs = (mh[s] << 1) | mhc;
+                mhc = mh[s] >> 31;
+                Pv[s] = mhs | ~(xv | phs);
+                Mv[s] = phs & xv;
+            }
+        }
+        jb += cols;
+        my_cells += (uint64_t)cols * (uint64_t)band;
+        int dl[NW];
+#pragma unroll
+        for (int s = 0; s < NW; s++) dl[s] = __popc(Pv[s]) - __popc(Mv[s]);
+        // a lower bound of every window value
+        {
+            int Sw = S, lb = 0x3FFFFFFF;
+#pragma unroll
+            for (int s = 0; s < NW; s++) {
+                if (s > 0) Sw += dl[s];
+                lb = min(lb, Sw - __popc(Pv[s]));
+            }
+            lbv = lb;
+        }
+        if (jb >= ncols) {
+            if (solo) {
+                // the whole text: the value at row mp decides, as in the one-lane kernel
+                const int rel = mp - (32 * wlo + 32);
+                int part = 0;
+                if (rel >= 0) {
+#pragma unroll
+                    for (int s = 1; s < NW; s++) {
+                        const int cnt = min(32, max(0, 32 + rel - 32 * s));
+                        const uint32_t mk = cnt >= 32 ? ~0u : ((1u << cnt) - 1u);
+                        part += __popc(Pv[s] & mk) - __popc(Mv[s] & mk);
+                    }
+                } else {
+                    const uint32_t mk = ~0u << (32 + rel);
+                    part = -(__popc(Pv[0] & mk) - __popc(Mv[0] & mk));
+                }
+                solo_res = (S + part) <= K ? 1 : 0;
+            }
+            done = true;
+            continue;
+        }
+        if (lbv > K) {
+            rej = true;
+            continue;
+        }
+        // move the window down one word
+        if constexpr (NW == 1) S += 32;
+        else S += dl[1];
+#pragma unroll
+        for (int s = 0; s + 1 < NW; s++) {
+            Pv[s] = Pv[s + 1];
+            Mv[s] = Mv[s + 1];
+            V[s] = V[s + 1];
+#pragma unroll
+            for (int p = 0; p < NP; p++) PL[p][s] = PL[p][s + 1];
+        }
+        wlo++;
+#pragma unroll
+        for (int p = 0; p < NP; p++) {
+            TYc[p] = TYn[p];
+            TYn[p] = yword(p, jb + 32);
+        }
+        Pv[NW - 1] = ~0u;
+        Mv[NW - 1] = 0u;
+        V[NW - 1] = ~0u;
+#pragma unroll
+        for (int p = 0; p < NP; p++) {
+            PL[p][NW - 1] = PLn[p];
+            PLn[p] = xword(p, wlo + NW);
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint32_t lo = (uint32_t)my_cells, hi = (uint32_t)(my_cells >> 32);
+        lo = __shfl_down(lo, d, 64);
+        hi = __shfl_down(hi, d, 64);
+        my_cells += ((uint64_t)hi << 32) | lo;
+    }
+    if (lane == 0 && my_cells) atomicAdd(cells, (unsigned long long)my_cells);
+}
+
 // ---------------------------------------------------------------- configurations
 using PersistKernel = void (*)(const uint64_t *, const int64_t *, int64_t, VSet, VSet, int,
                                uint8_t *, unsigned long long *, unsigned long long *);
 
 constexpr int NWL_CHOICES[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 11};
-constexpr int G_CHOICES[] = {1, 2, 4, 8};
+// g == BIDIR: two lanes per pair, split by columns (each lane holds the whole window)
+constexpr int BIDIR = VERIFY_BIDIR;
+constexpr int G_CHOICES[] = {1, 2, BIDIR, 4, 8};
 
 template <int NWL, int G>
 static PersistKernel by_np(int np) {
@@ -402,19 +759,46 @@ static PersistKernel by_nwl(int nwl, int np) {
     }
 }
 
+template <int NW>
+static PersistKernel bidir_by_np(int np) {
+    switch (np) {
+        case 2: return k_verify_bidir<NW, 2>;
+        case 4: return k_verify_bidir<NW, 4>;
+        case 6: return k_verify_bidir<NW, 6>;
+        default: return k_verify_bidir<NW, 8>;
+    }
+}
+
+static PersistKernel bidir_kernel(int nwl, int np) {
+    switch (nwl) {
+        case 1: return bidir_by_np<1>(np);
+        case 2: return bidir_by_np<2>(np);
+        case 3: return bidir_by_np<3>(np);
+        case 4: return bidir_by_np<4>(np);
+        case 5: return bidir_by_np<5>(np);
+        case 6: return bidir_by_np<6>(np);
+        case 7: return bidir_by_np<7>(np);
+        case 8: return bidir_by_np<8>(np);
+        case 9: return bidir_by_np<9>(np);
+        default: return bidir_by_np<11>(np);
+    }
+}
+
 static PersistKernel persist_kernel(int nwl, int g, int np) {
     switch (g) {
         case 1: return by_nwl<1>(nwl, np);
         case 2: return by_nwl<2>(nwl, np);
+        case BIDIR: return bidir_kernel(nwl, np);
         case 4: return by_nwl<4>(nwl, np);
         default: return by_nwl<8>(nwl, np);
     }
 }
 
-// smallest supported NWL with NWL * G >= nw, or 0
+// smallest supported NWL with NWL * G >= nw (the whole window per lane for BIDIR), or 0
 static int nwl_for(int nw, int g) {
+    const int lanes = g == BIDIR ? 1 : g;
     for (int v : NWL_CHOICES)
-        if (v * g >= nw) return v;
+        if (v * lanes >= nw) return v;
     return 0;
 }
 
@@ -505,7 +889,7 @@ static void launch_persist(int nwl, int g, int np, int max_blocks, const uint64_
                            unsigned long long *next, hipStream_t s) {
     fill_u64((uint64_t *)next, 0, QUEUES * QSTRIDE, s);
     // at most max_blocks resident workgroups, and no more than the pairs need
-    int64_t groups_per_block = 256 / g;
+    int64_t groups_per_block = 256 / (g == BIDIR ? 2 : g);
     int64_t blocks = (n + groups_per_block - 1) / groups_per_block;
     blocks = std::min<int64_t>(blocks, max_blocks);
     hipLaunchKernelGGL(persist_kernel(nwl, g, np), dim3((unsigned)std::max<int64_t>(blocks, 1)),
@@ -516,7 +900,8 @@ static void launch_persist(int nwl, int g, int np, int max_blocks, const uint64_
 int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings &A,
                              const DevStrings &B, int kmode, uint8_t *flags, Workspace &ws,
                              hipStream_t s, uint64_t *host_scratch, KTimer *kt,
-                             VerifyTuning *tune, int64_t uniform_k, uint64_t *cells_defer) {
+                             VerifyTuning *tune, int64_t uniform_k, uint64_t *cells_defer,
+                             int force_lanes) {
     if (n <= 0) return 0;
     if (A.planes == nullptr || B.planes == nullptr) throw Error(MJ_EINVAL, "strings not packed");
     const int np = verify_planes(std::max(A.bits, B.bits));
@@ -564,11 +949,17 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     const int ci = std::min(cmax, 63);
     int best_g = tune ? tune->best_g[ci][npi] : 0;
     int best_blocks = tune ? tune->best_blocks[ci][npi] : 0;
+    if (force_lanes != 0) {
+        best_g = force_lanes == -2 ? BIDIR : force_lanes;
+        best_blocks = 512;
+        if (nwl_for(nw, best_g) == 0)
+            throw Error(MJ_ECAPACITY, "verify_lanes: the lanes of a pair cannot hold this band");
+    }
     if (best_g == 0 && n < TUNE_MIN_PAIRS) {
         // a small call leaves most of the chip idle: the most lanes per pair (shortest
         // path per pair); timing the choices would cost more than the work
         for (int g : G_CHOICES)
-            if (nwl_for(nw, g) != 0 && (g == 1 || nwl_for(nw, g / 2) > 1)) best_g = g;
+            if (g != BIDIR && nwl_for(nw, g) != 0 && (g == 1 || nwl_for(nw, g / 2) > 1)) best_g = g;
         best_blocks = 512;
     }
     if (best_g == 0) {

@@ -196,6 +196,21 @@ def test_verify_matches_banded_oracle(mj, K, verifier):
     assert 0 < want.sum() < len(want)
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, -2])
+@pytest.mark.parametrize("K", [0, 1, 31, 33, 60, 150, 257])
+def test_verify_each_lane_layout_matches_banded_oracle(mj, K, lanes):
+    """Every fixed layout of the batched verifier (1-8 lanes splitting the band words, or
+    two lanes splitting the text columns) decides like the oracle; texts under 64 columns
+    exercise the column split's one-lane fallback, longer ones its meeting step."""
+    say("verify K=%d lanes=%d" % (K, lanes))
+    rng = np.random.default_rng(2000 + K)
+    S, pairs = near_threshold_pairs(rng, K, 120)
+    got = mj.verify(dev(mj, S), mj.Params(q=4, k=K, t_div=1, verify_lanes=lanes), pairs)
+    want = oracle.verify_list(S.chars, S.offsets, oracle.make_params(4, 4, k=K), pairs)
+    assert np.array_equal(got, want)
+    assert 0 < want.sum() < len(want)
+
+
 @pytest.mark.parametrize("verifier", ["batched", "plain"])
 def test_verify_per_pair_thresholds_across_bins(mj, verifier):
     import torch
