@@ -119,6 +119,29 @@ def test_partition_records_identical(mj, name):
     assert_records_equal(got, want)
 
 
+@pytest.mark.parametrize("t_div", [1, 4])
+def test_partition_hashed_path_with_top_half_collisions(mj, t_div):
+    """q * b = 14 bits: the anchor test runs on 64-bit hashes, not ranks.  A table whose
+    values share only 8 distinct top halves (distinct low halves) makes nearly every window
+    minimum tie on the top half, so every comparison must use the full values; lengths from
+    40 to 2500 give radii on both sides of the block test's limit."""
+    import torch
+    say("partition hashed path, top-half ties, t_div=%d" % t_div)
+    rng = np.random.default_rng(4242 + t_div)
+    q, ncodes = 7, 1 << 14
+    low = rng.permutation(ncodes).astype(np.uint64) * np.uint64(2654435761) + np.uint64(12345)
+    table = (rng.integers(0, 8, ncodes).astype(np.uint64) << np.uint64(32)) | (low & np.uint64(0xFFFFFFFF))
+    assert len(np.unique(table)) == ncodes
+    strs = [rng.integers(0, 4, int(rng.integers(40, 2500))).astype(np.uint8) for _ in range(160)]
+    S = dg.from_list(strs, 4)
+    tab = torch.from_numpy(table.view(np.int64)).cuda()
+    got = mj.partition(dev(mj, S), mj.Params(q=q, k=30, t_div=t_div, pi_table=tab))
+    want = oracle.partition_all(S.chars, S.offsets,
+                                oracle.make_params(q, 4, k=30, t_div=t_div, pi_table=table))
+    assert len(got) > S.n
+    assert_records_equal(got, want)
+
+
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_candidates_and_output_identical(mj, name):
     say("join", name)
