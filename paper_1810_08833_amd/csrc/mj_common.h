@@ -139,7 +139,7 @@ struct DevStrings {
     int32_t *len = nullptr;  // m_i
     int32_t *kk = nullptr;   // K_i
     int32_t *rr = nullptr;   // r_i (repetition-independent)
-    uint32_t *planes = nullptr;  // bit planes: planes[p * plane_words + w]
+    uint32_t *planes = nullptr;  // bit planes, interleaved: planes[w * np + p]
     int64_t plane_words = 0;
 };
 

@@ -90,7 +90,9 @@ int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, 
 }
 
 // ---------------------------------------------------------------- bit planes
-// planes[p][w] bit t = bit p of the symbol at global position 32w + t (0 past the end).
+// planes[w * NP + p] bit t = bit p of the symbol at global position 32w + t (0 past the
+// end): the NP planes interleaved word by word, so that a verifier lane reading the planes
+// of 32 symbols touches one cache line, not NP.
 // With 16-byte aligned symbols a thread reads its 32 symbols as two 16-byte loads and
 // transposes each group of 8 as an 8x8 bit matrix (three delta swaps: Hacker's Delight,
 // sec. 7-3), after which byte p of the result holds plane p's bits of those 8 symbols.
@@ -158,7 +160,7 @@ __global__ void k_pack_planes(const uint8_t *chars, int64_t total, uint32_t *pla
             }
         }
 #pragma unroll
-        for (int p = 0; p < NP; p++) planes[(int64_t)p * plane_words + w] = acc[p];
+        for (int p = 0; p < NP; p++) planes[w * NP + p] = acc[p];
     }
 }
 

@@ -68,7 +68,6 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
         bool a_is_x = ma >= mb;
         const uint32_t *PX = a_is_x ? A.planes : B.planes;
         const uint32_t *PY = a_is_x ? B.planes : A.planes;
-        int64_t pwx = a_is_x ? A.pw : B.pw, pwy = a_is_x ? B.pw : A.pw;
         int64_t offx = a_is_x ? A.off[ia] : B.off[ib];
         int64_t offy = a_is_x ? B.off[ib] : A.off[ia];
         int32_t mp = a_is_x ? ma : mb, nt = a_is_x ? mb : ma;
@@ -96,7 +95,7 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
                 V[s] = real ? ~0u : 0u;
 #pragma unroll
                 for (int p = 0; p < NP; p++)
-                    PL[p][s] = real ? load_word(PX + p * pwx, offx + 32 * (int64_t)w) : 0u;
+                    PL[p][s] = real ? load_word<NP>(PX + p, offx + 32 * (int64_t)w) : 0u;
             }
             int S = abs(32 * w0 + 32);  // column 0: row i holds |i| (rows <= 0 are made up)
             bool rejected = false;
@@ -135,11 +134,11 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
                     V[NW - 1] = ~0u;
 #pragma unroll
                     for (int p = 0; p < NP; p++)
-                        PL[p][NW - 1] = load_word(PX + p * pwx, offx + 32 * (int64_t)w);
+                        PL[p][NW - 1] = load_word<NP>(PX + p, offx + 32 * (int64_t)w);
                 }
                 uint32_t TY[NP];
 #pragma unroll
-                for (int p = 0; p < NP; p++) TY[p] = load_word(PY + p * pwy, offy + jb);
+                for (int p = 0; p < NP; p++) TY[p] = load_word<NP>(PY + p, offy + jb);
                 for (int t = 0; t < cols; t++) {
                     uint32_t tb[NP];  // the text symbol's plane bits, each broadcast to a word
 #pragma unroll

@@ -12,14 +12,16 @@ struct VSet {
     const int32_t *len;
     const int32_t *kk;
     const uint32_t *planes;
-    int64_t pw;
 };
 
+// The NP bit planes are interleaved: word w of plane p is planes[w * NP + p], so the planes
+// of 32 consecutive symbols share a cache line.  `plane` points at plane p's first word
+// (planes + p); returns 32 symbols' bits starting at global bit position bitpos (>= 0).
+template <int NP>
 __device__ __forceinline__ uint32_t load_word(const uint32_t *plane, int64_t bitpos) {
-    // 32 symbols' bits starting at global bit position bitpos (>= 0)
     int64_t w = bitpos >> 5;
     uint32_t sh = (uint32_t)(bitpos & 31);
-    uint32_t lo = plane[w], hi = plane[w + 1];
+    uint32_t lo = plane[w * NP], hi = plane[(w + 1) * NP];
     return __builtin_amdgcn_alignbit(hi, lo, sh);
 }
 
@@ -32,7 +34,7 @@ __device__ __forceinline__ uint32_t and_xnor(uint32_t a, uint32_t b, uint32_t c)
 }
 
 inline VSet vset(const DevStrings &d) {
-    return VSet{d.n, d.chars, d.offsets, d.len, d.kk, d.planes, d.plane_words};
+    return VSet{d.n, d.chars, d.offsets, d.len, d.kk, d.planes};
 }
 
 }  // namespace mj

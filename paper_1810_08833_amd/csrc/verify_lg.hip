@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
     int qdry = 0;
     int64_t pi = 0;
     int32_t K = 0, mp = 0, nt = 0, wlo = 0, jb = 0, S = 0, band = 0, phi = 32;
-    int64_t offx = 0, offy = 0, pwx = 0, pwy = 0;
+    int64_t offx = 0, offy = 0;
     const uint32_t *PX = nullptr, *PY = nullptr;
     uint32_t Pv[NWL], Mv[NWL], V[NWL], PL[NP][NWL];
     // software pipeline: text words of the current and the next block, and the plane words
@@ -130,8 +130,6 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
                 bool a_is_x = ma >= mb;
                 PX = a_is_x ? A.planes : B.planes;
                 PY = a_is_x ? B.planes : A.planes;
-                pwx = a_is_x ? A.pw : B.pw;
-                pwy = a_is_x ? B.pw : A.pw;
                 offx = a_is_x ? A.off[ia] : B.off[ib];
                 offy = a_is_x ? B.off[ib] : A.off[ia];
                 mp = a_is_x ? ma : mb;
@@ -168,14 +166,14 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
                         V[s] = real ? ~0u : 0u;
 #pragma unroll
                         for (int p = 0; p < NP; p++)
-                            PL[p][s] = real ? load_word(PX + p * pwx, offx + 32 * (int64_t)w) : 0u;
+                            PL[p][s] = real ? load_word<NP>(PX + p, offx + 32 * (int64_t)w) : 0u;
                     }
 #pragma unroll
                     for (int p = 0; p < NP; p++) {
-                        TYc[p] = load_word(PY + p * pwy, offy);
-                        TYn[p] = load_word(PY + p * pwy, offy + phi);
+                        TYc[p] = load_word<NP>(PY + p, offy);
+                        TYn[p] = load_word<NP>(PY + p, offy + phi);
                         // bottom word after the first move: word w0 + NW (read by the last lane)
-                        PLn[p] = g == G - 1 ? load_word(PX + p * pwx, offx + 32 * (int64_t)(w0 + NW)) : 0u;
+                        PLn[p] = g == G - 1 ? load_word<NP>(PX + p, offx + 32 * (int64_t)(w0 + NW)) : 0u;
                     }
                 }
             }
@@ -341,7 +339,7 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
 #pragma unroll
         for (int p = 0; p < NP; p++) {
             TYc[p] = TYn[p];
-            TYn[p] = load_word(PY + p * pwy, offy + jb + 32);
+            TYn[p] = load_word<NP>(PY + p, offy + jb + 32);
         }
         if (g == G - 1) {
             Pv[NWL - 1] = ~0u;
@@ -350,7 +348,7 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
 #pragma unroll
             for (int p = 0; p < NP; p++) {
                 PL[p][NWL - 1] = PLn[p];
-                PLn[p] = load_word(PX + p * pwx, offx + 32 * (int64_t)(wlo + NW));
+                PLn[p] = load_word<NP>(PX + p, offx + 32 * (int64_t)(wlo + NW));
             }
         } else {
             Pv[NWL - 1] = inP;
@@ -380,12 +378,13 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
 // and an alignment of cost <= K crosses column mid inside the band, where both halves hold
 // exact values whenever they are <= K: the decision ED <= K is that of the one-lane kernel.
 // A pair's latency halves; texts shorter than 64 columns stay with the first lane alone.
+template <int NP>
 __device__ __forceinline__ uint32_t load_dir(const uint32_t *plane, int64_t bitpos, bool rev) {
     // forward: symbols bitpos .. bitpos + 31 at bits 0 .. 31; reversed: bit t holds symbol
     // bitpos + 31 - t.  Positions before the start of the planes read as 0.
     uint32_t w;
-    if (bitpos >= 0) w = load_word(plane, bitpos);
-    else if (bitpos > -32) w = load_word(plane, 0) << (uint32_t)(-bitpos);
+    if (bitpos >= 0) w = load_word<NP>(plane, bitpos);
+    else if (bitpos > -32) w = load_word<NP>(plane, 0) << (uint32_t)(-bitpos);
     else w = 0u;
     return rev ? __builtin_bitreverse32(w) : w;
 }
@@ -419,7 +418,7 @@ __global__ __launch_bounds__(256) void k_verify_bidir(const uint64_t *__restrict
     int64_t pi = 0;
     int32_t K = 0, mp = 0, nt = 0, ncols = 0, mid = 0, wlo = 0, jb = 0, S = 0, band = 0;
     int32_t phi = 32, blo = 0, bhi = 0;
-    int64_t offx = 0, offy = 0, pwx = 0, pwy = 0;
+    int64_t offx = 0, offy = 0;
     const uint32_t *PX = nullptr, *PY = nullptr;
     uint32_t Pv[NW], Mv[NW], V[NW], PL[NP][NW];
     uint32_t TYc[NP], TYn[NP], PLn[NP];
@@ -433,11 +432,11 @@ __global__ __launch_bounds__(256) void k_verify_bidir(const uint64_t *__restrict
     // the half's pattern word w and text word at column j (reversed for the second lane)
     auto xword = [&](int p, int w) -> uint32_t {
         const int64_t pos = bwd ? offx + mp - 32 - 32 * (int64_t)w : offx + 32 * (int64_t)w;
-        return load_dir(PX + p * pwx, pos, bwd);
+        return load_dir<NP>(PX + p, pos, bwd);
     };
     auto yword = [&](int p, int j) -> uint32_t {
         const int64_t pos = bwd ? offy + nt - 32 - (int64_t)j : offy + (int64_t)j;
-        return load_dir(PY + p * pwy, pos, bwd);
+        return load_dir<NP>(PY + p, pos, bwd);
     };
     auto swap1 = [](uint32_t v) -> uint32_t {  // the partner lane's value (quad_perm 1,0,3,2)
         return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
@@ -551,8 +550,6 @@ __global__ __launch_bounds__(256) void k_verify_bidir(const uint64_t *__restrict
             const bool a_is_x = ma >= mb;
             PX = a_is_x ? A.planes : B.planes;
             PY = a_is_x ? B.planes : A.planes;
-            pwx = a_is_x ? A.pw : B.pw;
-            pwy = a_is_x ? B.pw : A.pw;
             offx = a_is_x ? A.off[ia] : B.off[ib];
             offy = a_is_x ? B.off[ib] : A.off[ia];
             mp = a_is_x ? ma : mb;
