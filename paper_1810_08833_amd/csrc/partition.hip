@@ -289,7 +289,6 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     const uint16_t *__restrict__ rank, const int32_t *__restrict__ rr, int TP, int H,
     const TileDesc *__restrict__ tdesc, int aligned4, uint64_t *__restrict__ bitmap) {
     constexpr bool RANKED = sizeof(V) == 4;
-    constexpr int NRANK = RANKED ? (1 << RANK_MAX_BITS) : 1;
     __shared__ __align__(16) V bufA[REGION];
     __shared__ __align__(16) V bufB[REGION];
     __shared__ __align__(16) uint16_t pinfo[REGION];
@@ -299,7 +298,9 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     __shared__ TileDesc td;
     __shared__ int16_t barg[REGION / AT_BLOCK];
     __shared__ V bmin[REGION / AT_BLOCK];
-    __shared__ __align__(16) uint16_t rank_s[NRANK];
+    // rank table: 2^(q b) entries in dynamic shared memory (sized at launch; none for
+    // hashes), so that small code spaces leave room for more resident workgroups
+    extern __shared__ __align__(16) uint16_t rank_s[];
     __shared__ int32_t kmax_s, rmin_s;
     const int NR = TP + 2 * H;
     const int tid = threadIdx.x;
@@ -813,9 +814,10 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
             MJ_LAUNCH_CHECK();
         }
 #define MJ_ANCHORS(R, V)                                                                        \
-        hipLaunchKernelGGL((k_anchor_tiles<R, V>), dim3((unsigned)ntiles), dim3(AT_THREADS), 0, s, \
+        hipLaunchKernelGGL((k_anchor_tiles<R, V>), dim3((unsigned)ntiles), dim3(AT_THREADS), rank_lds, s, \
                            d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, rank, \
                            d.rr, TP, H, ts, aligned4, bitmap[rho])
+        const size_t rank_lds = rank ? ((size_t)2 << code_bits) + 16 : 0;
         if (rank) {
             if (region == 2048) MJ_ANCHORS(2048, uint32_t); else MJ_ANCHORS(4096, uint32_t);
         } else {
