@@ -289,15 +289,18 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     const uint16_t *__restrict__ rank, const int32_t *__restrict__ rr, int TP, int H,
     const TileDesc *__restrict__ tdesc, int aligned4, uint64_t *__restrict__ bitmap) {
     constexpr bool RANKED = sizeof(V) == 4;
-    __shared__ __align__(16) V bufA[REGION];
-    __shared__ __align__(16) V bufB[REGION];
+    // LDS slots hold ranks as 16 bits (ranks < 2^12; the sentinel 0xFFFF is above them
+    // all) and hashes as 64: half the LDS of 32-bit ranks, more resident workgroups
+    using S = typename std::conditional<RANKED, uint16_t, uint64_t>::type;
+    __shared__ __align__(16) S bufA[REGION];
+    __shared__ __align__(16) S bufB[REGION];
     __shared__ __align__(16) uint16_t pinfo[REGION];
     __shared__ __align__(16) uint32_t ch32[(REGION + 64) / 4];  // symbols, word-aligned with the input
     uint8_t *const ch = reinterpret_cast<uint8_t *>(ch32);
     __shared__ uint32_t aflag[REGION / 32];
     __shared__ TileDesc td;
     __shared__ int16_t barg[REGION / AT_BLOCK];
-    __shared__ V bmin[REGION / AT_BLOCK];
+    __shared__ S bmin[REGION / AT_BLOCK];
     // rank table: 2^(q b) entries in dynamic shared memory (sized at launch; none for
     // hashes), so that small code spaces leave room for more resident workgroups
     extern __shared__ __align__(16) uint16_t rank_s[];
@@ -433,11 +436,12 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             }
             // 16-byte stores of the thread's RUN hash slots and RUN info slots
             {
-                uint32_t hw[RUN * sizeof(V) / 4];
+                uint32_t hw[RUN * sizeof(S) / 4];
 #pragma unroll
                 for (int j = 0; j < RUN; j++) {
                     if constexpr (RANKED) {
-                        hw[j] = (uint32_t)hv[j];
+                        if (j & 1) hw[j >> 1] |= (uint32_t)hv[j] << 16;
+                        else hw[j >> 1] = (uint32_t)hv[j] & 0xFFFFu;
                     } else {
                         hw[2 * j] = (uint32_t)hv[j];
                         hw[2 * j + 1] = (uint32_t)((uint64_t)hv[j] >> 32);
@@ -445,7 +449,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 }
                 uint4 *dst = reinterpret_cast<uint4 *>(bufA + idx0);
 #pragma unroll
-                for (int i = 0; i < (int)(RUN * sizeof(V) / 16); i++)
+                for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++)
                     dst[i] = make_uint4(hw[4 * i], hw[4 * i + 1], hw[4 * i + 2], hw[4 * i + 3]);
                 uint32_t iw[RUN / 2];
 #pragma unroll
@@ -470,7 +474,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             for (int j = 0; j < RUN; j++) {
                 const int idx = idx0 + j;
                 if (idx >= NR) {  // region padding: a sentinel that is never a strict minimum
-                    bufA[idx] = (V)~0ull;
+                    bufA[idx] = (S)~0ull;
                     pinfo[idx] = 0;
                     continue;
                 }
@@ -517,7 +521,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 } else {
                     have_end = -1;
                 }
-                bufA[idx] = h;
+                bufA[idx] = (S)h;
                 pinfo[idx] = info;
             }
         }
@@ -547,9 +551,9 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             suffix_min_step<8>(sv);
             const V before = dpp_val<0x111>(pv);  // prefix minimum of the lane below
             const V after = dpp_val<0x101>(sv);   // suffix minimum of the lane above
-            bufB[idx] = pv;
-            bufA[idx] = sv;
-            if ((tid & (AT_BLOCK - 1)) == AT_BLOCK - 1) bmin[idx / AT_BLOCK] = pv;
+            bufB[idx] = (S)pv;
+            bufA[idx] = (S)sv;
+            if ((tid & (AT_BLOCK - 1)) == AT_BLOCK - 1) bmin[idx / AT_BLOCK] = (S)pv;
             // at most one lane per block satisfies this (a strict minimum of the block);
             // the block's first lane records it (the 16 lanes of a block share a wave)
             const bool uniq = hv < before && hv < after;
@@ -592,7 +596,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             hp[c] = c < NC ? bufA[H + p] : 0;
             inf[c] = c < NC ? pinfo[H + p] : 0;
         }
-        V *cur = bufA, *nxt = bufB;
+        S *cur = bufA, *nxt = bufB;
         for (int k = 0; k <= kmax; k++) {
             const int w = 1 << k;
 #pragma unroll
@@ -600,8 +604,8 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 int r = inf[c] & 0x7FFF;
                 if (c < NC && r != 0 && (31 - __clz(r)) == k) {
                     int idx = H + tid + AT_THREADS * c;
-                    V L = min(cur[idx - r], cur[idx - w]);
-                    V R = min(cur[idx + 1], cur[idx + 1 + r - w]);
+                    const V L = min<V>(cur[idx - r], cur[idx - w]);
+                    const V R = min<V>(cur[idx + 1], cur[idx + 1 + r - w]);
                     if (hp[c] < L && hp[c] < R) {
                         int pp = tid + AT_THREADS * c;
                         atomicOr(&aflag[pp >> 5], 1u << (pp & 31));
@@ -610,12 +614,12 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             }
             if (k == kmax) break;
             for (int a = tid; a < NR; a += AT_THREADS) {
-                V v = cur[a];
+                S v = cur[a];
                 if (a + w < NR) v = min(v, cur[a + w]);
                 nxt[a] = v;
             }
             __syncthreads();
-            V *t = cur;
+            S *t = cur;
             cur = nxt;
             nxt = t;
         }
