@@ -529,7 +529,8 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         if (lrmin < 0x7FFFFFFF) atomicMin(&rmin_s, lrmin);
     }
     __syncthreads();
-    const int NC = TP / AT_THREADS;
+    // tile positions p < TP (TP a multiple of 64, so a wave's 64 positions are all in or
+    // all out)
     constexpr int OWN = REGION / AT_THREADS;
     if (rmin_s >= AT_BLOCK - 1) {
         // ---- block test: bufA <- suffix minima, bufB <- prefix minima (within blocks).
@@ -593,8 +594,8 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
 #pragma unroll
         for (int c = 0; c < OWN; c++) {
             int p = tid + AT_THREADS * c;
-            hp[c] = c < NC ? bufA[H + p] : 0;
-            inf[c] = c < NC ? pinfo[H + p] : 0;
+            hp[c] = p < TP ? bufA[H + p] : 0;
+            inf[c] = p < TP ? pinfo[H + p] : 0;
         }
         S *cur = bufA, *nxt = bufB;
         for (int k = 0; k <= kmax; k++) {
@@ -602,7 +603,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
 #pragma unroll
             for (int c = 0; c < OWN; c++) {
                 int r = inf[c] & 0x7FFF;
-                if (c < NC && r != 0 && (31 - __clz(r)) == k) {
+                if (tid + AT_THREADS * c < TP && r != 0 && (31 - __clz(r)) == k) {
                     int idx = H + tid + AT_THREADS * c;
                     const V L = min<V>(cur[idx - r], cur[idx - w]);
                     const V R = min<V>(cur[idx + 1], cur[idx + 1 + r - w]);
@@ -630,8 +631,8 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     const int rem = (int)min<int64_t>(total - tile_start, (int64_t)TP);  // tile positions in the input
 #pragma unroll
     for (int c = 0; c < OWN; c++) {
-        if (c < NC) {
-            const int p0 = AT_THREADS * c + 64 * wid, p = p0 + lane;
+        const int p0 = AT_THREADS * c + 64 * wid, p = p0 + lane;
+        if (p0 < TP) {
             const uint32_t bit = ((uint32_t)pinfo[H + p] >> 15) | (aflag[p >> 5] >> (p & 31));
             const uint64_t mask = __ballot(p < rem && (bit & 1u));
             if (lane == 0 && p0 < rem) bitmap[(tile_start + p0) >> 6] = mask;
@@ -787,7 +788,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
         throw Error(MJ_ECAPACITY, "radius " + std::to_string(H) + " exceeds the supported 1920");
     // the smaller region (more workgroups per CU) when the halo leaves room for 1024+ positions
     const int region = (2048 - 2 * H >= 1024) ? 2048 : 4096;
-    int TP = ((region - 2 * H) / AT_THREADS) * AT_THREADS;
+    int TP = ((region - 2 * H) / 64) * 64;  // whole bitmap words per tile
     int64_t ntiles = (d.total + TP - 1) / TP;
     int64_t nw = (d.total + 63) / 64;
     if (ntiles > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many tiles");
