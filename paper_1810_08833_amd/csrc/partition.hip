@@ -289,9 +289,13 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     const uint16_t *__restrict__ rank, const int32_t *__restrict__ rr, int TP, int H,
     const TileDesc *__restrict__ tdesc, int aligned4, uint64_t *__restrict__ bitmap) {
     constexpr bool RANKED = sizeof(V) == 4;
-    // LDS slots hold ranks as 16 bits (ranks < 2^12; the sentinel 0xFFFF is above them
-    // all) and hashes as 64: half the LDS of 32-bit ranks, more resident workgroups
-    using S = typename std::conditional<RANKED, uint16_t, uint64_t>::type;
+    // LDS slots hold keys: ranks as 16 bits (ranks < 2^12; the sentinel 0xFFFF is above
+    // them all), hashes by their top 32 bits (sentinel 0xFFFFFFFF).  Compact slots leave
+    // room for more resident workgroups.  Ranks order positions exactly; top halves only
+    // decide where they differ: where the key of a candidate equals a competitor's, the
+    // full hashes, recomputed from the staged symbols, decide (exact64 below).
+    using S = typename std::conditional<RANKED, uint16_t, uint32_t>::type;
+    using KT = uint32_t;  // keys in registers
     __shared__ __align__(16) S bufA[REGION];
     __shared__ __align__(16) S bufB[REGION];
     __shared__ __align__(16) uint16_t pinfo[REGION];
@@ -413,8 +417,9 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                     const int32_t i = in2 ? j - jb : i0 + j;
                     const int32_t rj = in2 ? r1 : r;
                     const bool interior = (uint32_t)(i - rj) < (in2 ? ibound1 : ibound);
-                    hv[j] = i < (in2 ? npos1 : npos) ? h : (V)~0ull;
-                    inf[j] = (uint16_t)((interior ? rj : 0) | (i == 0 ? 0x8000 : 0));
+                    const bool vq = i < (in2 ? npos1 : npos);
+                    hv[j] = vq ? h : (V)~0ull;
+                    inf[j] = (uint16_t)((interior ? rj : 0) | (i == 0 ? 0x8000 : 0) | (vq ? 0x4000 : 0));
                     const int idx = idx0 + j;
                     if (interior && idx >= H && idx < H + TP) {
                         lmax = max(lmax, 31 - __clz(rj));
@@ -422,7 +427,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                     }
                 } else {
                     hv[j] = h;
-                    inf[j] = (uint32_t)(i0 + j - r) < ibound ? (uint16_t)r : (uint16_t)0;
+                    inf[j] = (uint16_t)(((uint32_t)(i0 + j - r) < ibound ? r : 0) | 0x4000);
                 }
                 if (j + 1 < RUN) G = ((G << bits) | ((N[j >> 2] >> (8 * (j & 3))) & 0xFFu)) & cmask;
             }
@@ -443,8 +448,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                         if (j & 1) hw[j >> 1] |= (uint32_t)hv[j] << 16;
                         else hw[j >> 1] = (uint32_t)hv[j] & 0xFFFFu;
                     } else {
-                        hw[2 * j] = (uint32_t)hv[j];
-                        hw[2 * j + 1] = (uint32_t)((uint64_t)hv[j] >> 32);
+                        hw[j] = (uint32_t)((uint64_t)hv[j] >> 32);
                     }
                 }
                 uint4 *dst = reinterpret_cast<uint4 *>(bufA + idx0);
@@ -513,7 +517,8 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                         have_end = -1;
                     }
                     const bool interior = (i >= r) && (i <= npos - 1 - r);
-                    info = (uint16_t)((interior ? r : 0) | (i == 0 ? 0x8000 : 0));
+                    info = (uint16_t)((interior ? r : 0) | (i == 0 ? 0x8000 : 0) |
+                                      (i < npos ? 0x4000 : 0));
                     if (interior && idx >= H && idx < H + TP) {
                         lmax = max(lmax, 31 - __clz(r));
                         lrmin = min(lrmin, r);
@@ -521,7 +526,8 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 } else {
                     have_end = -1;
                 }
-                bufA[idx] = (S)h;
+                if constexpr (RANKED) bufA[idx] = (S)h;
+                else bufA[idx] = (S)((uint64_t)h >> 32);
                 pinfo[idx] = info;
             }
         }
@@ -529,6 +535,16 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         if (lrmin < 0x7FFFFFFF) atomicMin(&rmin_s, lrmin);
     }
     __syncthreads();
+    // the full hash of region slot idx (~0 where no full q-gram starts): the tie-break of
+    // equal top halves
+    auto exact64 = [&](int idx) -> uint64_t {
+        if (((pinfo[idx] >> 14) & 1u) == 0) return ~0ull;
+        uint64_t G = 0;
+        for (int k = 0; k < q; k++) G = (G << bits) | ch[sh + idx + k];
+        G &= gmask;
+        return table ? table[G] : mix64(G ^ salt);
+    };
+    (void)exact64;
     // tile positions p < TP (TP a multiple of 64, so a wave's 64 positions are all in or
     // all out)
     constexpr int OWN = REGION / AT_THREADS;
@@ -540,8 +556,8 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
 #pragma unroll
         for (int j0 = 0; j0 < REGION; j0 += AT_THREADS) {
             const int idx = j0 + tid;
-            const V hv = bufA[idx];
-            V pv = hv, sv = hv;
+            const KT hv = bufA[idx];
+            KT pv = hv, sv = hv;
             prefix_min_step<1>(pv);
             prefix_min_step<2>(pv);
             prefix_min_step<4>(pv);
@@ -550,14 +566,38 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             suffix_min_step<2>(sv);
             suffix_min_step<4>(sv);
             suffix_min_step<8>(sv);
-            const V before = dpp_val<0x111>(pv);  // prefix minimum of the lane below
-            const V after = dpp_val<0x101>(sv);   // suffix minimum of the lane above
+            const KT before = dpp_val<0x111>(pv);  // prefix minimum of the lane below
+            const KT after = dpp_val<0x101>(sv);   // suffix minimum of the lane above
             bufB[idx] = (S)pv;
             bufA[idx] = (S)sv;
             if ((tid & (AT_BLOCK - 1)) == AT_BLOCK - 1) bmin[idx / AT_BLOCK] = (S)pv;
             // at most one lane per block satisfies this (a strict minimum of the block);
             // the block's first lane records it (the 16 lanes of a block share a wave)
-            const bool uniq = hv < before && hv < after;
+            bool uniq = hv < before && hv < after;
+            if constexpr (!RANKED) {
+                // a block whose minimum top half is held by several lanes: its unique
+                // minimum, if any, by the full hashes of those lanes
+                const KT m = pv < sv ? pv : sv;
+                const int rb0 = (tid & 63) & ~(AT_BLOCK - 1);
+                const uint32_t rowm = (uint32_t)(__ballot(hv == m) >> rb0) & 0xFFFFu;
+                const bool tie_block = __popc(rowm) >= 2;
+                if (__any(tie_block)) {
+                    const uint64_t e = (tie_block && hv == m) ? exact64(idx) : ~0ull;
+                    uint64_t pe = e, se = e;
+                    prefix_min_step<1>(pe);
+                    prefix_min_step<2>(pe);
+                    prefix_min_step<4>(pe);
+                    prefix_min_step<8>(pe);
+                    suffix_min_step<1>(se);
+                    suffix_min_step<2>(se);
+                    suffix_min_step<4>(se);
+                    suffix_min_step<8>(se);
+                    const uint64_t emin = pe < se ? pe : se;
+                    const bool at_min = tie_block && e == emin && e != ~0ull;
+                    const uint32_t rowu = (uint32_t)(__ballot(at_min) >> rb0) & 0xFFFFu;
+                    if (at_min && __popc(rowu) == 1) uniq = true;
+                }
+            }
             const uint64_t um = __ballot(uniq);
             if ((tid & (AT_BLOCK - 1)) == 0) {
                 const uint32_t row = (uint32_t)(um >> (tid & 63)) & 0xFFFFu;
@@ -569,19 +609,33 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         for (int bk = tid; bk < NBK; bk += AT_THREADS) {
             const int p = barg[bk];
             if (p < H || p >= H + TP) continue;  // no unique minimum, or not a tile position
-            const int r = pinfo[p] & 0x7FFF;
+            const int r = pinfo[p] & 0x3FFF;
             if (r == 0) continue;  // not an interior position
-            const V hv = bmin[bk];
-            bool ok = true;
+            const KT hv = bmin[bk];
+            // strictly below every other key of the window: an anchor; above one: not;
+            // equal to one (ranks: equal hashes, not strict): hashes decide by full value
+            bool below = false, tie = false;
+            auto see = [&](KT x) {
+                below |= x < hv;
+                tie |= x == hv;
+            };
             const int L = p - r, lb = L / AT_BLOCK;
             if (lb < bk) {
-                ok = hv < bufA[L];
-                for (int b2 = lb + 1; ok && b2 < bk; b2++) ok = hv < bmin[b2];
+                see(bufA[L]);
+                for (int b2 = lb + 1; !below && b2 < bk; b2++) see(bmin[b2]);
             }
             const int R = p + r, rb = R / AT_BLOCK;
-            if (ok && rb > bk) {
-                for (int b2 = bk + 1; ok && b2 < rb; b2++) ok = hv < bmin[b2];
-                if (ok) ok = hv < bufB[R];
+            if (!below && rb > bk) {
+                for (int b2 = bk + 1; !below && b2 < rb; b2++) see(bmin[b2]);
+                if (!below) see(bufB[R]);
+            }
+            bool ok = !below && !tie;
+            if constexpr (!RANKED) {
+                if (!below && tie) {
+                    const uint64_t ep = exact64(p);
+                    ok = true;
+                    for (int dd = 1; ok && dd <= r; dd++) ok = exact64(p - dd) > ep && exact64(p + dd) > ep;
+                }
             }
             if (ok) atomicOr(&aflag[(p - H) >> 5], 1u << ((p - H) & 31));
         }
@@ -589,7 +643,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     } else {
         // ---- sparse table
         const int kmax = kmax_s;
-        V hp[OWN];
+        KT hp[OWN];
         uint16_t inf[OWN];
 #pragma unroll
         for (int c = 0; c < OWN; c++) {
@@ -602,12 +656,21 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             const int w = 1 << k;
 #pragma unroll
             for (int c = 0; c < OWN; c++) {
-                int r = inf[c] & 0x7FFF;
+                int r = inf[c] & 0x3FFF;
                 if (tid + AT_THREADS * c < TP && r != 0 && (31 - __clz(r)) == k) {
                     int idx = H + tid + AT_THREADS * c;
-                    const V L = min<V>(cur[idx - r], cur[idx - w]);
-                    const V R = min<V>(cur[idx + 1], cur[idx + 1 + r - w]);
-                    if (hp[c] < L && hp[c] < R) {
+                    const KT L = min<KT>(cur[idx - r], cur[idx - w]);
+                    const KT R = min<KT>(cur[idx + 1], cur[idx + 1 + r - w]);
+                    bool anchor = hp[c] < L && hp[c] < R;
+                    if constexpr (!RANKED) {
+                        if (!anchor && hp[c] <= L && hp[c] <= R) {  // equal top halves
+                            const uint64_t ep = exact64(idx);
+                            anchor = true;
+                            for (int dd = 1; anchor && dd <= r; dd++)
+                                anchor = exact64(idx - dd) > ep && exact64(idx + dd) > ep;
+                        }
+                    }
+                    if (anchor) {
                         int pp = tid + AT_THREADS * c;
                         atomicOr(&aflag[pp >> 5], 1u << (pp & 31));
                     }
