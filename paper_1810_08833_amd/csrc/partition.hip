@@ -744,12 +744,20 @@ __device__ __forceinline__ uint64_t horner_chunk(uint64_t h, uint64_t BC, uint64
     return h >= P61 ? h - P61 : h;
 }
 
-__global__ void k_phi_table(int nc, int C, int bits, uint64_t B, uint64_t *__restrict__ T) {
+// Chunk tables of Horner's rule over 4 symbols.  pt == 0: T[x] for every packed chunk x
+// (2^(4b) entries, b <= 2).  pt == 1: four power tables, T[j 2^b + c] = (c + 1) B^j, so a
+// chunk's value is the sum of one entry of each (4 * 2^b entries).
+__global__ void k_phi_table(int nc, int bits, uint64_t B, int pt, uint64_t *__restrict__ T) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nc) return;
     uint64_t h = 0;
-    for (int k = 0; k < C; k++)
-        h = horner_step(h, B, (uint32_t)(idx >> (bits * (C - 1 - k))) & ((1u << bits) - 1u));
+    if (pt) {
+        h = (uint64_t)(idx & ((1 << bits) - 1)) + 1;
+        for (int j = 0; j < (idx >> bits); j++) h = mulmod61(h, B);
+    } else {
+        for (int k = 0; k < 4; k++)
+            h = horner_step(h, B, (uint32_t)(idx >> (bits * (3 - k))) & ((1u << bits) - 1u));
+    }
     T[idx] = h;
 }
 
@@ -757,10 +765,11 @@ __global__ void k_records(const int64_t *__restrict__ apos, int64_t R,
                           const int64_t *__restrict__ off, int32_t n,
                           const uint8_t *__restrict__ chars, int aligned4,
                           const TileDesc *__restrict__ td, int TP, uint64_t B, uint64_t salt_f,
-                          const uint64_t *__restrict__ table, int C, int bits, uint64_t BC,
+                          const uint64_t *__restrict__ table, int pt, int bits, uint64_t BC,
                           uint64_t *key, uint64_t *val, uint32_t *len) {
     extern __shared__ uint64_t Ts[];
-    const int nc = C > 1 ? 1 << (C * bits) : 0;
+    const int nsym = 1 << bits;
+    const int nc = pt ? 4 * nsym : 1 << (4 * bits);
     for (int t = threadIdx.x; t < nc; t += blockDim.x) Ts[t] = table[t];
     __syncthreads();
     const uint32_t m = (1u << bits) - 1u;
@@ -784,32 +793,29 @@ __global__ void k_records(const int64_t *__restrict__ apos, int64_t R,
         uint64_t h = (uint64_t)L % P61;
         int64_t g = g0;
         if (aligned4) {
-            for (; g < g1 && (g & 3); g++) h = horner_step(h, B, C > 1 ? (chars[g] & m) : chars[g]);
+            for (; g < g1 && (g & 3); g++) h = horner_step(h, B, chars[g] & m);
             const uint32_t *w = reinterpret_cast<const uint32_t *>(chars);
-            if (C == 4) {
+            if (!pt) {
                 for (; g + 4 <= g1; g += 4) {
                     const uint32_t v = w[g >> 2];
                     const uint32_t x = ((v & m) << (3 * bits)) | (((v >> 8) & m) << (2 * bits)) |
                                        (((v >> 16) & m) << bits) | ((v >> 24) & m);
                     h = horner_chunk(h, BC, Ts[x]);
                 }
-            } else if (C == 2) {
-                for (; g + 4 <= g1; g += 4) {
-                    const uint32_t v = w[g >> 2];
-                    h = horner_chunk(h, BC, Ts[((v & m) << bits) | ((v >> 8) & m)]);
-                    h = horner_chunk(h, BC, Ts[(((v >> 16) & m) << bits) | ((v >> 24) & m)]);
-                }
             } else {
+                // h B^4 + (x0+1) B^3 + (x1+1) B^2 + (x2+1) B + (x3+1): five terms below
+                // 2^61 - 1 sum below 2^64; one fold and one subtraction reduce them
                 for (; g + 4 <= g1; g += 4) {
                     const uint32_t v = w[g >> 2];
-                    h = horner_step(h, B, v & 0xFFu);
-                    h = horner_step(h, B, (v >> 8) & 0xFFu);
-                    h = horner_step(h, B, (v >> 16) & 0xFFu);
-                    h = horner_step(h, B, v >> 24);
+                    const uint64_t sum = mulmod61(h, BC) + Ts[3 * nsym + (v & m)] +
+                                         Ts[2 * nsym + ((v >> 8) & m)] + Ts[nsym + ((v >> 16) & m)] +
+                                         Ts[(v >> 24) & m];
+                    h = (sum & P61) + (sum >> 61);
+                    h = h >= P61 ? h - P61 : h;
                 }
             }
         }
-        for (; g < g1; g++) h = horner_step(h, B, C > 1 ? (chars[g] & m) : chars[g]);
+        for (; g < g1; g++) h = horner_step(h, B, chars[g] & m);
         key[k] = mix64(h ^ salt_f);
         val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
         if (len) len[k] = (uint32_t)L;
@@ -920,18 +926,16 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     out.reserve(base0 + total + 1, s);
     const uint64_t B = 2 + mix64(p.seed ^ GAMMA_B) % (P61 - 3);
     const uint64_t salt_f = mix64(p.seed + GAMMA);
-    // Horner chunk of C symbols and its table (see k_records)
-    const int C = d.bits <= 2 ? 4 : (d.bits <= 5 ? 2 : 1);  // tables of <= 1024 entries
+    // Horner chunks of 4 symbols (see k_phi_table): one table of all chunks for b <= 2,
+    // power tables above (at most 1,024 entries either way)
+    const int pt = d.bits > 2 ? 1 : 0;
     uint64_t BC = 1;
-    for (int i = 0; i < C; i++) BC = (uint64_t)(((unsigned __int128)BC * B) % P61);
-    uint64_t *phi_table = nullptr;
-    const int nc = C > 1 ? 1 << (C * d.bits) : 0;
-    if (C > 1) {
-        phi_table = ws.get_n<uint64_t>(nc);
-        hipLaunchKernelGGL(k_phi_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, C, d.bits, B,
-                           phi_table);
-        MJ_LAUNCH_CHECK();
-    }
+    for (int i = 0; i < 4; i++) BC = (uint64_t)(((unsigned __int128)BC * B) % P61);
+    const int nc = pt ? 4 << d.bits : 1 << (4 * d.bits);
+    uint64_t *phi_table = ws.get_n<uint64_t>(nc);
+    hipLaunchKernelGGL(k_phi_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, d.bits, B, pt,
+                       phi_table);
+    MJ_LAUNCH_CHECK();
     int64_t maxR = 0;
     for (int rho = 0; rho < reps; rho++) maxR = std::max(maxR, R[rho]);
     int64_t *apos = ws.get_n<int64_t>(maxR + 1);
@@ -944,7 +948,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
             int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
             hipLaunchKernelGGL(k_records, dim3(grid_for(R[rho], 256, 65535)), dim3(256),
                                (size_t)nc * 8, s, apos, R[rho], d.offsets, d.n, d.chars, aligned4,
-                               ts, TP, B, salt_f, phi_table, C, d.bits, BC, out.key + base,
+                               ts, TP, B, salt_f, phi_table, pt, d.bits, BC, out.key + base,
                                out.val + base, out.with_len ? out.len + base : nullptr);
             MJ_LAUNCH_CHECK();
             if (kt) kt->end(tr, s);
