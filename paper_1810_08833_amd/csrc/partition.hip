@@ -761,25 +761,58 @@ __global__ void k_phi_table(int nc, int bits, uint64_t B, int pt, uint64_t *__re
     T[idx] = h;
 }
 
-__global__ void k_records(const int64_t *__restrict__ apos, int64_t R,
-                          const int64_t *__restrict__ off, int32_t n,
-                          const uint8_t *__restrict__ chars, int aligned4,
-                          const TileDesc *__restrict__ td, int TP, uint64_t B, uint64_t salt_f,
-                          const uint64_t *__restrict__ table, int pt, int bits, uint64_t BC,
-                          uint64_t *key, uint64_t *val, uint32_t *len) {
+constexpr int REC_THREADS = 256;
+constexpr int REC_STAGE_WORDS = 6144;  // 24 KB: the symbols of a block's records
+
+// One thread per record; a block takes 256 consecutive records per sweep.  STAGED (long
+// partitions): their symbols form one contiguous range, which the block first copies to
+// LDS with coalesced word loads (a lane reading its own partition directly touches a line
+// per lane and load); a range longer than the stage is read from global memory instead.
+// Short partitions are read directly: the copy and its barriers would cost more.
+template <bool STAGED>
+__global__ __launch_bounds__(REC_THREADS) void k_records(
+    const int64_t *__restrict__ apos, int64_t R, const int64_t *__restrict__ off, int32_t n,
+    const uint8_t *__restrict__ chars, int64_t total, int aligned4,
+    const TileDesc *__restrict__ td, int TP, uint64_t B, uint64_t salt_f,
+    const uint64_t *__restrict__ table, int pt, int bits, uint64_t BC, uint64_t *key,
+    uint64_t *val, uint32_t *len) {
     extern __shared__ uint64_t Ts[];
+    __shared__ uint32_t stage[STAGED ? REC_STAGE_WORDS : 1];
     const int nsym = 1 << bits;
     const int nc = pt ? 4 * nsym : 1 << (4 * bits);
     for (int t = threadIdx.x; t < nc; t += blockDim.x) Ts[t] = table[t];
-    __syncthreads();
     const uint32_t m = (1u << bits) - 1u;
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; k < R; k += stride) {
-        const int64_t g0 = apos[k], g1 = apos[k + 1];
+    // Horner's rule over [g, g1) from symbol bytes sym(i) and aligned words word(i)
+    auto hash = [&](uint64_t h, int64_t g, int64_t g1, auto sym, auto word) -> uint64_t {
+        if (aligned4) {
+            for (; g < g1 && (g & 3); g++) h = horner_step(h, B, sym(g) & m);
+            if (!pt) {
+                for (; g + 4 <= g1; g += 4) {
+                    const uint32_t v = word(g);
+                    const uint32_t x = ((v & m) << (3 * bits)) | (((v >> 8) & m) << (2 * bits)) |
+                                       (((v >> 16) & m) << bits) | ((v >> 24) & m);
+                    h = horner_chunk(h, BC, Ts[x]);
+                }
+            } else {
+                // h B^4 + (x0+1) B^3 + (x1+1) B^2 + (x2+1) B + (x3+1): five terms below
+                // 2^61 - 1 sum below 2^64; one fold and one subtraction reduce them
+                for (; g + 4 <= g1; g += 4) {
+                    const uint32_t v = word(g);
+                    const uint64_t sum = mulmod61(h, BC) + Ts[3 * nsym + (v & m)] +
+                                         Ts[2 * nsym + ((v >> 8) & m)] + Ts[nsym + ((v >> 16) & m)] +
+                                         Ts[(v >> 24) & m];
+                    h = (sum & P61) + (sum >> 61);
+                    h = h >= P61 ? h - P61 : h;
+                }
+            }
+        }
+        for (; g < g1; g++) h = horner_step(h, B, sym(g) & m);
+        return h;
+    };
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(chars);
+    // the string of the partition starting at g0 and its first position
+    auto owner = [&](int64_t g0, int32_t &sidx, int64_t &sbeg) {
         const TileDesc &d = td[g0 / TP];
-        int32_t sidx;
-        int64_t sbeg;
         if (d.ns >= 0) {
             int t = 0;
             for (int j = 1; j < d.ns; j++) t += (d.off[j] <= g0) ? 1 : 0;
@@ -789,33 +822,83 @@ __global__ void k_records(const int64_t *__restrict__ apos, int64_t R,
             sidx = owner_of(off, n, g0);
             sbeg = off[sidx];
         }
-        const int64_t L = g1 - g0;
-        uint64_t h = (uint64_t)L % P61;
-        int64_t g = g0;
-        if (aligned4) {
-            for (; g < g1 && (g & 3); g++) h = horner_step(h, B, chars[g] & m);
-            const uint32_t *w = reinterpret_cast<const uint32_t *>(chars);
-            if (!pt) {
-                for (; g + 4 <= g1; g += 4) {
-                    const uint32_t v = w[g >> 2];
-                    const uint32_t x = ((v & m) << (3 * bits)) | (((v >> 8) & m) << (2 * bits)) |
-                                       (((v >> 16) & m) << bits) | ((v >> 24) & m);
-                    h = horner_chunk(h, BC, Ts[x]);
-                }
-            } else {
-                // h B^4 + (x0+1) B^3 + (x1+1) B^2 + (x2+1) B + (x3+1): five terms below
-                // 2^61 - 1 sum below 2^64; one fold and one subtraction reduce them
-                for (; g + 4 <= g1; g += 4) {
-                    const uint32_t v = w[g >> 2];
-                    const uint64_t sum = mulmod61(h, BC) + Ts[3 * nsym + (v & m)] +
-                                         Ts[2 * nsym + ((v >> 8) & m)] + Ts[nsym + ((v >> 16) & m)] +
-                                         Ts[(v >> 24) & m];
-                    h = (sum & P61) + (sum >> 61);
-                    h = h >= P61 ? h - P61 : h;
+    };
+    if constexpr (!STAGED) {
+        __syncthreads();  // the table is in place
+        for (int64_t k = (int64_t)blockIdx.x * REC_THREADS + threadIdx.x; k < R;
+             k += (int64_t)gridDim.x * REC_THREADS) {
+            const int64_t g0 = apos[k], g1 = apos[k + 1];
+            int32_t sidx;
+            int64_t sbeg;
+            owner(g0, sidx, sbeg);
+            const int64_t L = g1 - g0;
+            uint64_t h = (uint64_t)L % P61;
+            int64_t g = g0;
+            if (aligned4) {
+                for (; g < g1 && (g & 3); g++) h = horner_step(h, B, chars[g] & m);
+                if (!pt) {
+                    for (; g + 4 <= g1; g += 4) {
+                        const uint32_t v = w[g >> 2];
+                        const uint32_t x = ((v & m) << (3 * bits)) | (((v >> 8) & m) << (2 * bits)) |
+                                           (((v >> 16) & m) << bits) | ((v >> 24) & m);
+                        h = horner_chunk(h, BC, Ts[x]);
+                    }
+                } else {
+                    for (; g + 4 <= g1; g += 4) {
+                        const uint32_t v = w[g >> 2];
+                        const uint64_t sum = mulmod61(h, BC) + Ts[3 * nsym + (v & m)] +
+                                             Ts[2 * nsym + ((v >> 8) & m)] +
+                                             Ts[nsym + ((v >> 16) & m)] + Ts[(v >> 24) & m];
+                        h = (sum & P61) + (sum >> 61);
+                        h = h >= P61 ? h - P61 : h;
+                    }
                 }
             }
+            for (; g < g1; g++) h = horner_step(h, B, chars[g] & m);
+            key[k] = mix64(h ^ salt_f);
+            val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
+            if (len) len[k] = (uint32_t)L;
         }
-        for (; g < g1; g++) h = horner_step(h, B, chars[g] & m);
+        return;
+    }
+    for (int64_t kb = (int64_t)blockIdx.x * REC_THREADS; kb < R;
+         kb += (int64_t)gridDim.x * REC_THREADS) {
+        const int64_t kend = min<int64_t>(kb + REC_THREADS, R);
+        const int64_t sb = apos[kb] & ~(int64_t)3;  // word-aligned start of the range
+        const int64_t nwords = (apos[kend] - sb + 3) >> 2;
+        const bool staged = aligned4 && nwords <= REC_STAGE_WORDS;
+        __syncthreads();  // the table is in place; the previous sweep is done with the stage
+        if (staged) {
+            for (int64_t i = threadIdx.x; i < nwords; i += REC_THREADS) {
+                const int64_t gp = sb + 4 * i;
+                uint32_t v;
+                if (gp + 4 <= total) {
+                    v = w[gp >> 2];
+                } else {
+                    v = 0;
+                    for (int bb = 0; bb < 4; bb++)
+                        if (gp + bb < total) v |= (uint32_t)chars[gp + bb] << (8 * bb);
+                }
+                stage[i] = v;
+            }
+        }
+        __syncthreads();
+        const int64_t k = kb + threadIdx.x;
+        if (k >= kend) continue;
+        const int64_t g0 = apos[k], g1 = apos[k + 1];
+        int32_t sidx;
+        int64_t sbeg;
+        owner(g0, sidx, sbeg);
+        const int64_t L = g1 - g0;
+        uint64_t h = (uint64_t)L % P61;
+        if (staged) {
+            const uint8_t *sbytes = reinterpret_cast<const uint8_t *>(stage);
+            h = hash(h, g0, g1, [&](int64_t g) -> uint32_t { return sbytes[g - sb]; },
+                     [&](int64_t g) -> uint32_t { return stage[(g - sb) >> 2]; });
+        } else {
+            h = hash(h, g0, g1, [&](int64_t g) -> uint32_t { return chars[g]; },
+                     [&](int64_t g) -> uint32_t { return w[g >> 2]; });
+        }
         key[k] = mix64(h ^ salt_f);
         val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
         if (len) len[k] = (uint32_t)L;
@@ -946,10 +1029,14 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
         MJ_LAUNCH_CHECK();
         if (R[rho] > 0) {
             int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
-            hipLaunchKernelGGL(k_records, dim3(grid_for(R[rho], 256, 65535)), dim3(256),
-                               (size_t)nc * 8, s, apos, R[rho], d.offsets, d.n, d.chars, aligned4,
-                               ts, TP, B, salt_f, phi_table, pt, d.bits, BC, out.key + base,
-                               out.val + base, out.with_len ? out.len + base : nullptr);
+            // stage the symbols when partitions average 24 symbols or more
+            const bool stg = d.total >= 24 * R[rho];
+            hipLaunchKernelGGL(stg ? k_records<true> : k_records<false>,
+                               dim3(grid_for(R[rho], REC_THREADS, 65535)), dim3(REC_THREADS),
+                               (size_t)nc * 8, s, apos, R[rho], d.offsets, d.n, d.chars, d.total,
+                               aligned4, ts, TP, B, salt_f, phi_table, pt, d.bits, BC,
+                               out.key + base, out.val + base,
+                               out.with_len ? out.len + base : nullptr);
             MJ_LAUNCH_CHECK();
             if (kt) kt->end(tr, s);
         }
