@@ -180,8 +180,9 @@ void pack_planes(DevStrings &d, int np, Workspace &ws, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- anchors
-// One workgroup handles a tile of TP positions of the concatenated strings plus a halo
-// of H positions on each side (H >= every radius used).  It hashes every q-gram of the
+// One workgroup handles a tile of TP positions of the concatenated strings within a
+// region of REGION positions: H before the tile (H >= every radius used) and the rest,
+// at least H, after it.  It hashes every q-gram of the
 // region into LDS; string boundaries come from an LDS copy of the offsets of the strings
 // the region overlaps.  A position p is an anchor when h[p] is strictly smaller than
 // every other value in [p-r, p+r].  Two exact tests:
@@ -192,7 +193,7 @@ void pack_planes(DevStrings &d, int np, Workspace &ws, hipStream_t s) {
 //  * sparse table (otherwise): doubling in two LDS buffers, after level k the current
 //    buffer holds min h[a .. a + 2^k - 1] at a; p is tested at level k = floor(log2 r):
 //    left window min(cur[p-r], cur[p-2^k]), right window min(cur[p+1], cur[p+1+r-2^k]).
-// Anchors and string starts are written as one bit per position.
+// Anchors and string starts are flagged in LDS and written as one bit per position.
 constexpr int AT_THREADS = 256;
 constexpr int AT_BLOCK = 16;
 
@@ -261,11 +262,10 @@ struct TileDesc {
 static_assert(sizeof(TileDesc) == 128, "tile descriptor size");
 
 __global__ void k_tile_desc(const int64_t *__restrict__ off, const int32_t *__restrict__ rr,
-                            int32_t n, int64_t total, int64_t ntiles, int TP, int H,
+                            int32_t n, int64_t total, int64_t ntiles, int TP, int H, int NR,
                             TileDesc *__restrict__ td) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
-    const int NR = TP + 2 * H;
     int64_t base = t * TP - H;
     int64_t g0 = base < 0 ? 0 : base;
     int64_t g1 = min(base + NR, total) - 1;
@@ -299,7 +299,11 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     __shared__ __align__(16) S bufA[REGION];
     __shared__ __align__(16) S bufB[REGION];
     __shared__ __align__(16) uint16_t pinfo[REGION];
-    __shared__ __align__(16) uint32_t ch32[(REGION + 64) / 4];  // symbols, word-aligned with the input
+    // symbols, word-aligned with the input: NR + q - 1 bytes from offset sh < 4, read as
+    // whole words (and up to 16 bytes past the last q-gram by the hashing loop)
+    constexpr int CH_WORDS = (REGION + 64 + 8) / 4 + 4;
+    constexpr int CW = (CH_WORDS + AT_THREADS - 1) / AT_THREADS;  // words per thread
+    __shared__ __align__(16) uint32_t ch32[CH_WORDS];
     uint8_t *const ch = reinterpret_cast<uint8_t *>(ch32);
     __shared__ uint32_t aflag[REGION / 32];
     __shared__ TileDesc td;
@@ -309,41 +313,70 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     // hashes), so that small code spaces leave room for more resident workgroups
     extern __shared__ __align__(16) uint16_t rank_s[];
     __shared__ int32_t kmax_s, rmin_s;
-    const int NR = TP + 2 * H;
+    const int NR = REGION;
     const int tid = threadIdx.x;
     const int64_t tile_start = (int64_t)blockIdx.x * TP;
     const int64_t base = tile_start - H;
-    if (tid == 0) {
-        kmax_s = 0;
-        rmin_s = 0x7FFFFFFF;
+    // Every global load of the set-up is issued before the first of them is used, so a
+    // workgroup waits for one memory round trip rather than one per copy loop trip.
+    uint32_t tdw = 0;
+    if (tid < 32) tdw = reinterpret_cast<const uint32_t *>(tdesc + blockIdx.x)[tid];
+    // rank table: 16-byte copies (the table is a workspace block: 16-byte aligned, with 16
+    // bytes of slack past its end)
+    constexpr int RK = RANKED ? ((1 << RANK_MAX_BITS) / 8 + AT_THREADS - 1) / AT_THREADS : 1;
+    uint4 rk[RK];
+    const int nr8 = RANKED ? ((1 << (q * bits)) + 7) / 8 : 0;
+    if constexpr (RANKED) {
+#pragma unroll
+        for (int i = 0; i < RK; i++) {
+            const int c = tid + AT_THREADS * i;
+            rk[i] = c < nr8 ? reinterpret_cast<const uint4 *>(rank)[c] : make_uint4(0, 0, 0, 0);
+        }
     }
-    if (tid < 32) reinterpret_cast<uint32_t *>(&td)[tid] = reinterpret_cast<const uint32_t *>(tdesc + blockIdx.x)[tid];
     // symbols of the region: byte sh + idx of ch holds global position base + idx, with
     // ch starting at a 4-byte boundary of the input so whole words are copied
     const int sh = (int)(base & 3);
     const int64_t chbase = base - sh;
-    for (int k = tid; k < (NR + q + sh + 3) / 4; k += AT_THREADS) {
-        const int64_t gp = chbase + 4 * (int64_t)k;
-        uint32_t w;
-        if (aligned4 && gp >= 0 && gp + 3 < total) {
-            w = reinterpret_cast<const uint32_t *>(chars)[gp >> 2];
-        } else {
-            w = 0;
-            for (int b = 0; b < 4; b++)
-                if (gp + b >= 0 && gp + b < total) w |= (uint32_t)chars[gp + b] << (8 * b);
+    const int nwords = (NR + q + sh + 3) / 4;  // <= CH_WORDS (q <= 64)
+    uint32_t cw[CW];
+    if (aligned4 && chbase >= 0 && chbase + 4 * (int64_t)nwords <= total) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(chars) + (chbase >> 2);
+#pragma unroll
+        for (int i = 0; i < CW; i++) {
+            const int k = tid + AT_THREADS * i;
+            cw[i] = k < nwords ? src[k] : 0u;
         }
-        ch32[k] = w;
+    } else {  // the first and last tiles, or unaligned symbols: byte by byte, 0 outside
+#pragma unroll
+        for (int i = 0; i < CW; i++) {
+            const int64_t gp = chbase + 4 * (int64_t)(tid + AT_THREADS * i);
+            uint32_t w = 0;
+            if (tid + AT_THREADS * i < nwords)
+                for (int b = 0; b < 4; b++)
+                    if (gp + b >= 0 && gp + b < total) w |= (uint32_t)chars[gp + b] << (8 * b);
+            cw[i] = w;
+        }
+    }
+    if (tid == 0) {
+        kmax_s = 0;
+        rmin_s = 0x7FFFFFFF;
     }
     for (int w = tid; w < REGION / 32; w += AT_THREADS) aflag[w] = 0;
+    if (tid < 32) reinterpret_cast<uint32_t *>(&td)[tid] = tdw;
+#pragma unroll
+    for (int i = 0; i < CW; i++)
+        if (tid + AT_THREADS * i < nwords) ch32[tid + AT_THREADS * i] = cw[i];
     if constexpr (RANKED) {
-        const int nr = 1 << (q * bits);
-        // 16-byte copies (the table is a workspace block: 16-byte aligned, with 16 bytes of
-        // slack past its end)
-        for (int c = tid; c < (nr + 7) / 8; c += AT_THREADS)
-            reinterpret_cast<uint4 *>(rank_s)[c] = reinterpret_cast<const uint4 *>(rank)[c];
+#pragma unroll
+        for (int i = 0; i < RK; i++)
+            if (tid + AT_THREADS * i < nr8) reinterpret_cast<uint4 *>(rank_s)[tid + AT_THREADS * i] = rk[i];
     }
     __syncthreads();
     const int32_t ns = td.ns;
+    // string starts inside the tile are flagged like anchors (a few per tile)
+    auto flag_start = [&](int idx) {
+        if (idx >= H && idx < H + TP) atomicOr(&aflag[(idx - H) >> 5], 1u << ((idx - H) & 31));
+    };
     const uint64_t gmask = (q * bits >= 64) ? ~0ull : ((1ull << (q * bits)) - 1);
     // hashes: each thread rolls the packed q-gram code over RUN consecutive positions
     {
@@ -419,25 +452,30 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                     const bool interior = (uint32_t)(i - rj) < (in2 ? ibound1 : ibound);
                     const bool vq = i < (in2 ? npos1 : npos);
                     hv[j] = vq ? h : (V)~0ull;
-                    inf[j] = (uint16_t)((interior ? rj : 0) | (i == 0 ? 0x8000 : 0) | (vq ? 0x4000 : 0));
-                    const int idx = idx0 + j;
-                    if (interior && idx >= H && idx < H + TP) {
-                        lmax = max(lmax, 31 - __clz(rj));
-                        lrmin = min(lrmin, rj);
-                    }
+                    inf[j] = (uint16_t)((interior ? rj : 0) | (vq ? 0x4000 : 0));
                 } else {
                     hv[j] = h;
                     inf[j] = (uint16_t)(((uint32_t)(i0 + j - r) < ibound ? r : 0) | 0x4000);
                 }
                 if (j + 1 < RUN) G = ((G << bits) | ((N[j >> 2] >> (8 * (j & 3))) & 0xFFu)) & cmask;
             }
-            if constexpr (!TWO) {
-                inf[0] |= i0 == 0 ? (uint16_t)0x8000 : (uint16_t)0;  // string start
-                // interior positions of the run that are tile positions: j in [jlo, jhi)
-                const int jlo = max(max(r - i0, H - idx0), 0);
-                const int jhi = min(min(npos - r - i0, H + TP - idx0), RUN);
-                lrmin = jlo < jhi ? r : lrmin;
-                lmax = jlo < jhi ? 31 - __clz(r) : 0;
+            // radii of the interior tile positions of the run: run indices [lo, hi) of a
+            // string with radius rr
+            auto radii = [&](int lo, int hi, int32_t rr) {
+                lo = max(lo, H - idx0);
+                hi = min(hi, H + TP - idx0);
+                if (lo < hi) {
+                    lrmin = min(lrmin, rr);
+                    lmax = max(lmax, 31 - __clz(rr));
+                }
+            };
+            radii(max(r - i0, 0), min(npos - r - i0, jb), r);  // string t: i = i0 + j
+            if (i0 == 0) flag_start(idx0);
+            if constexpr (TWO) {
+                if (jb < RUN) {  // string t + 1 from run index jb: i = j - jb
+                    radii(jb + r1, min(jb + npos1 - r1, RUN), r1);
+                    flag_start(idx0 + jb);
+                }
             }
             // 16-byte stores of the thread's RUN hash slots and RUN info slots
             {
@@ -517,8 +555,8 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                         have_end = -1;
                     }
                     const bool interior = (i >= r) && (i <= npos - 1 - r);
-                    info = (uint16_t)((interior ? r : 0) | (i == 0 ? 0x8000 : 0) |
-                                      (i < npos ? 0x4000 : 0));
+                    info = (uint16_t)((interior ? r : 0) | (i < npos ? 0x4000 : 0));
+                    if (i == 0) flag_start(idx);
                     if (interior && idx >= H && idx < H + TP) {
                         lmax = max(lmax, 31 - __clz(r));
                         lrmin = min(lrmin, r);
@@ -689,17 +727,12 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         }
         __syncthreads();
     }
-    // one bit per position: string start or anchor
-    const int lane = tid & 63, wid = tid >> 6;
+    // one bit per position: string start or anchor (TP is a multiple of 64)
     const int rem = (int)min<int64_t>(total - tile_start, (int64_t)TP);  // tile positions in the input
-#pragma unroll
-    for (int c = 0; c < OWN; c++) {
-        const int p0 = AT_THREADS * c + 64 * wid, p = p0 + lane;
-        if (p0 < TP) {
-            const uint32_t bit = ((uint32_t)pinfo[H + p] >> 15) | (aflag[p >> 5] >> (p & 31));
-            const uint64_t mask = __ballot(p < rem && (bit & 1u));
-            if (lane == 0 && p0 < rem) bitmap[(tile_start + p0) >> 6] = mask;
-        }
+    for (int w = tid; 64 * w < rem; w += AT_THREADS) {
+        uint64_t v = (uint64_t)aflag[2 * w] | ((uint64_t)aflag[2 * w + 1] << 32);
+        if (rem - 64 * w < 64) v &= (1ull << (rem - 64 * w)) - 1ull;
+        bitmap[(tile_start >> 6) + w] = v;
     }
 }
 
@@ -956,7 +989,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
     TileDesc *ts = ws.get_n<TileDesc>(ntiles + 1);
     hipLaunchKernelGGL(k_tile_desc, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s,
-                       d.offsets, d.rr, d.n, d.total, ntiles, TP, H, ts);
+                       d.offsets, d.rr, d.n, d.total, ntiles, TP, H, region, ts);
     MJ_LAUNCH_CHECK();
     std::vector<uint64_t *> bitmap(reps);
     std::vector<uint32_t *> pre(reps);
