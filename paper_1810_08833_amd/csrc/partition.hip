@@ -182,51 +182,12 @@ void pack_planes(DevStrings &d, int np, Workspace &ws, hipStream_t s) {
 // ---------------------------------------------------------------- anchors
 // One workgroup handles a tile of TP positions of the concatenated strings within a
 // region of REGION positions: H before the tile (H >= every radius used) and the rest,
-// at least H, after it.  It hashes every q-gram of the
-// region into LDS; string boundaries come from an LDS copy of the offsets of the strings
-// the region overlaps.  A position p is an anchor when h[p] is strictly smaller than
-// every other value in [p-r, p+r].  Two exact tests:
-//  * block test (every interior radius of the tile >= 15): a 16-position aligned block
-//    lies inside the window of each of its positions, so an anchor is the unique minimum
-//    of its block; only those candidates are checked against the rest of their window,
-//    whole blocks through their minima and the two partial blocks element by element;
-//  * sparse table (otherwise): doubling in two LDS buffers, after level k the current
-//    buffer holds min h[a .. a + 2^k - 1] at a; p is tested at level k = floor(log2 r):
-//    left window min(cur[p-r], cur[p-2^k]), right window min(cur[p+1], cur[p+1+r-2^k]).
-// Anchors and string starts are flagged in LDS and written as one bit per position.
+// at least H, after it.  Each thread hashes the q-grams of RUN consecutive positions of
+// the region into LDS; string boundaries come from an LDS copy of the offsets of the
+// strings the region overlaps.  A position p is an anchor when h[p] is strictly smaller
+// than every other value in [p-r, p+r] (the window test below).  Anchors and string
+// starts are flagged in LDS and written as one bit per position.
 constexpr int AT_THREADS = 256;
-constexpr int AT_BLOCK = 16;
-
-// DPP moves inside rows of 16 lanes; a lane whose source is outside its row keeps `old`.
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_or(uint32_t old, uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, 0xF, 0xF, false);
-}
-
-// The value of the lane selected by CTRL within the row, ~0 where there is none.  The
-// sentinel ~0 is the identity of the minimum scans; a position holding ~0 (a 64-bit
-// hash can) is never strictly below anything, so it never becomes an anchor either way.
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_val(uint32_t v) {
-    return dpp_or<CTRL>(0xFFFFFFFFu, v);
-}
-template <int CTRL>
-__device__ __forceinline__ uint64_t dpp_val(uint64_t v) {
-    uint32_t lo = dpp_or<CTRL>(0xFFFFFFFFu, (uint32_t)v), hi = dpp_or<CTRL>(0xFFFFFFFFu, (uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-// Inclusive minimum scans over a row of 16 lanes: prefix (from the lane D below) and
-// suffix (from the lane D above).
-template <int D, typename V>
-__device__ __forceinline__ void prefix_min_step(V &v) {
-    V o = dpp_val<0x110 + D>(v);  // row_shr:D
-    v = o < v ? o : v;
-}
-template <int D, typename V>
-__device__ __forceinline__ void suffix_min_step(V &v) {
-    V o = dpp_val<0x100 + D>(v);  // row_shl:D
-    v = o < v ? o : v;
-}
 
 // Order-preserving ranks of the q-gram hash for small code spaces (q*b <= 12 bits):
 // rank(G) = number of codes whose hash is strictly smaller than Pi(G).  Pi(a) < Pi(b)
@@ -307,12 +268,10 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     uint8_t *const ch = reinterpret_cast<uint8_t *>(ch32);
     __shared__ uint32_t aflag[REGION / 32];
     __shared__ TileDesc td;
-    __shared__ int16_t barg[REGION / AT_BLOCK];
-    __shared__ S bmin[REGION / AT_BLOCK];
     // rank table: 2^(q b) entries in dynamic shared memory (sized at launch; none for
     // hashes), so that small code spaces leave room for more resident workgroups
     extern __shared__ __align__(16) uint16_t rank_s[];
-    __shared__ int32_t kmax_s, rmin_s;
+    __shared__ int32_t rmin_s;
     const int NR = REGION;
     const int tid = threadIdx.x;
     const int64_t tile_start = (int64_t)blockIdx.x * TP;
@@ -358,7 +317,6 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         }
     }
     if (tid == 0) {
-        kmax_s = 0;
         rmin_s = 0x7FFFFFFF;
     }
     for (int w = tid; w < REGION / 32; w += AT_THREADS) aflag[w] = 0;
@@ -382,7 +340,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     {
         constexpr int RUN = REGION / AT_THREADS;
         static_assert(RUN == 8 || RUN == 16, "positions per thread");
-        int lmax = 0, lrmin = 0x7FFFFFFF;
+        int lrmin = 0x7FFFFFFF;
         const int idx0 = tid * RUN;
         const int64_t g0 = base + idx0;
         int t = 0;
@@ -466,7 +424,6 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 hi = min(hi, H + TP - idx0);
                 if (lo < hi) {
                     lrmin = min(lrmin, rr);
-                    lmax = max(lmax, 31 - __clz(rr));
                 }
             };
             radii(max(r - i0, 0), min(npos - r - i0, jb), r);  // string t: i = i0 + j
@@ -558,7 +515,6 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                     info = (uint16_t)((interior ? r : 0) | (i < npos ? 0x4000 : 0));
                     if (i == 0) flag_start(idx);
                     if (interior && idx >= H && idx < H + TP) {
-                        lmax = max(lmax, 31 - __clz(r));
                         lrmin = min(lrmin, r);
                     }
                 } else {
@@ -569,7 +525,6 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 pinfo[idx] = info;
             }
         }
-        if (lmax > 0) atomicMax(&kmax_s, lmax);
         if (lrmin < 0x7FFFFFFF) atomicMin(&rmin_s, lrmin);
     }
     __syncthreads();
@@ -583,73 +538,103 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         return table ? table[G] : mix64(G ^ salt);
     };
     (void)exact64;
-    // tile positions p < TP (TP a multiple of 64, so a wave's 64 positions are all in or
-    // all out)
-    constexpr int OWN = REGION / AT_THREADS;
-    if (rmin_s >= AT_BLOCK - 1) {
-        // ---- block test: bufA <- suffix minima, bufB <- prefix minima (within blocks).
-        // The block's unique minimum is the position strictly below the prefix minimum
-        // before it and the suffix minimum after it (neighbouring lanes of the scans).
-        // the whole region (slots from NR on hold the sentinel): a fixed trip count
+    // ---- window test.  Blocks of B = 2^k positions with B - 1 <= every interior radius of
+    // the tile and B <= RUN (so a block is a part of one thread's run): a block lies inside
+    // the window of each of its positions, so an anchor is the unique minimum of its block.
+    // Each thread finds the unique minima of its blocks and stores the prefix minima (bufB)
+    // and suffix minima (bufA) within blocks; each such candidate is then checked against
+    // the rest of its window: whole blocks through their minima (the prefix minimum at the
+    // block's end), the two partial blocks through one suffix and one prefix minimum.
+    if (rmin_s != 0x7FFFFFFF) {  // some tile position is interior
+        constexpr int RUN = REGION / AT_THREADS;
+        const int B = min(RUN, 1 << (31 - __clz(rmin_s + 1)));
+        const int bm = B - 1;
+        const int idx0 = tid * RUN;
+        KT v[RUN];
+        {
+            uint4 raw[RUN * sizeof(S) / 16];
 #pragma unroll
-        for (int j0 = 0; j0 < REGION; j0 += AT_THREADS) {
-            const int idx = j0 + tid;
-            const KT hv = bufA[idx];
-            KT pv = hv, sv = hv;
-            prefix_min_step<1>(pv);
-            prefix_min_step<2>(pv);
-            prefix_min_step<4>(pv);
-            prefix_min_step<8>(pv);
-            suffix_min_step<1>(sv);
-            suffix_min_step<2>(sv);
-            suffix_min_step<4>(sv);
-            suffix_min_step<8>(sv);
-            const KT before = dpp_val<0x111>(pv);  // prefix minimum of the lane below
-            const KT after = dpp_val<0x101>(sv);   // suffix minimum of the lane above
-            bufB[idx] = (S)pv;
-            bufA[idx] = (S)sv;
-            if ((tid & (AT_BLOCK - 1)) == AT_BLOCK - 1) bmin[idx / AT_BLOCK] = (S)pv;
-            // at most one lane per block satisfies this (a strict minimum of the block);
-            // the block's first lane records it (the 16 lanes of a block share a wave)
-            bool uniq = hv < before && hv < after;
-            if constexpr (!RANKED) {
-                // a block whose minimum top half is held by several lanes: its unique
-                // minimum, if any, by the full hashes of those lanes
-                const KT m = pv < sv ? pv : sv;
-                const int rb0 = (tid & 63) & ~(AT_BLOCK - 1);
-                const uint32_t rowm = (uint32_t)(__ballot(hv == m) >> rb0) & 0xFFFFu;
-                const bool tie_block = __popc(rowm) >= 2;
-                if (__any(tie_block)) {
-                    const uint64_t e = (tie_block && hv == m) ? exact64(idx) : ~0ull;
-                    uint64_t pe = e, se = e;
-                    prefix_min_step<1>(pe);
-                    prefix_min_step<2>(pe);
-                    prefix_min_step<4>(pe);
-                    prefix_min_step<8>(pe);
-                    suffix_min_step<1>(se);
-                    suffix_min_step<2>(se);
-                    suffix_min_step<4>(se);
-                    suffix_min_step<8>(se);
-                    const uint64_t emin = pe < se ? pe : se;
-                    const bool at_min = tie_block && e == emin && e != ~0ull;
-                    const uint32_t rowu = (uint32_t)(__ballot(at_min) >> rb0) & 0xFFFFu;
-                    if (at_min && __popc(rowu) == 1) uniq = true;
+            for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++) raw[i] = reinterpret_cast<const uint4 *>(bufA + idx0)[i];
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(raw);
+#pragma unroll
+            for (int j = 0; j < RUN; j++) {
+                if constexpr (RANKED) v[j] = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+                else v[j] = w[j];
+            }
+        }
+        KT pre[RUN], suf[RUN];
+#pragma unroll
+        for (int j = 0; j < RUN; j++) pre[j] = (j & bm) == 0 ? v[j] : min(pre[j > 0 ? j - 1 : 0], v[j]);
+#pragma unroll
+        for (int j = RUN - 1; j >= 0; j--)
+            suf[j] = ((j + 1) & bm) == 0 ? v[j] : min(suf[j + 1 < RUN ? j + 1 : j], v[j]);
+        // bit j: v[j] is strictly below every other key of its block
+        uint32_t cand = 0;
+#pragma unroll
+        for (int j = 0; j < RUN; j++) {
+            const KT before = (j & bm) == 0 ? (KT)~0u : pre[j > 0 ? j - 1 : 0];
+            const KT after = ((j + 1) & bm) == 0 ? (KT)~0u : suf[j + 1 < RUN ? j + 1 : j];
+            cand |= (v[j] < before && v[j] < after) ? 1u << j : 0u;
+        }
+        if constexpr (!RANKED) {
+            // blocks whose minimum top half several positions hold: their unique minimum,
+            // if any, by the full hashes of those positions
+            uint32_t tied = 0;
+#pragma unroll
+            for (int j = 0; j < RUN; j++) tied |= v[j] == min(pre[j], suf[j]) ? 1u << j : 0u;
+            const uint32_t bbits = B >= 32 ? ~0u : (1u << B) - 1u;
+            for (int b0 = 0; b0 < RUN; b0 += B) {
+                uint32_t tb = tied & (bbits << b0);
+                if (__popc(tb) < 2) continue;
+                uint64_t e = ~0ull;
+                int je = -1;
+                bool dup = false;
+                for (; tb; tb &= tb - 1) {
+                    const int j = __ffs(tb) - 1;
+                    const uint64_t x = exact64(idx0 + j);
+                    if (x < e) {
+                        e = x;
+                        je = j;
+                        dup = false;
+                    } else if (x == e) {
+                        dup = true;
+                    }
+                }
+                if (!dup && e != ~0ull) cand |= 1u << je;
+            }
+        }
+        {
+            uint32_t pw[RUN * sizeof(S) / 4], sw[RUN * sizeof(S) / 4];
+#pragma unroll
+            for (int j = 0; j < RUN; j++) {
+                if constexpr (RANKED) {
+                    if (j & 1) {
+                        pw[j >> 1] |= (uint32_t)pre[j] << 16;
+                        sw[j >> 1] |= (uint32_t)suf[j] << 16;
+                    } else {
+                        pw[j >> 1] = (uint32_t)pre[j];
+                        sw[j >> 1] = (uint32_t)suf[j];
+                    }
+                } else {
+                    pw[j] = pre[j];
+                    sw[j] = suf[j];
                 }
             }
-            const uint64_t um = __ballot(uniq);
-            if ((tid & (AT_BLOCK - 1)) == 0) {
-                const uint32_t row = (uint32_t)(um >> (tid & 63)) & 0xFFFFu;
-                barg[idx / AT_BLOCK] = row ? (int16_t)(idx + __ffs(row) - 1) : (int16_t)-1;
+#pragma unroll
+            for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++) {
+                reinterpret_cast<uint4 *>(bufB + idx0)[i] = make_uint4(pw[4 * i], pw[4 * i + 1], pw[4 * i + 2], pw[4 * i + 3]);
+                reinterpret_cast<uint4 *>(bufA + idx0)[i] = make_uint4(sw[4 * i], sw[4 * i + 1], sw[4 * i + 2], sw[4 * i + 3]);
             }
         }
         __syncthreads();
-        const int NBK = (NR + AT_BLOCK - 1) / AT_BLOCK;
-        for (int bk = tid; bk < NBK; bk += AT_THREADS) {
-            const int p = barg[bk];
-            if (p < H || p >= H + TP) continue;  // no unique minimum, or not a tile position
+        const int lb2 = 31 - __clz(B);  // log2 B
+        for (; cand; cand &= cand - 1) {
+            const int p = idx0 + __ffs(cand) - 1;
+            if (p < H || p >= H + TP) continue;  // not a tile position
             const int r = pinfo[p] & 0x3FFF;
             if (r == 0) continue;  // not an interior position
-            const KT hv = bmin[bk];
+            const KT hv = bufA[p];  // its key: the suffix minimum from a block's minimum
+            const int bk = p >> lb2;
             // strictly below every other key of the window: an anchor; above one: not;
             // equal to one (ranks: equal hashes, not strict): hashes decide by full value
             bool below = false, tie = false;
@@ -657,14 +642,14 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 below |= x < hv;
                 tie |= x == hv;
             };
-            const int L = p - r, lb = L / AT_BLOCK;
+            const int L = p - r, lb = L >> lb2;
             if (lb < bk) {
                 see(bufA[L]);
-                for (int b2 = lb + 1; !below && b2 < bk; b2++) see(bmin[b2]);
+                for (int b2 = lb + 1; !below && b2 < bk; b2++) see(bufB[(b2 << lb2) + bm]);
             }
-            const int R = p + r, rb = R / AT_BLOCK;
+            const int R = p + r, rb = R >> lb2;
             if (!below && rb > bk) {
-                for (int b2 = bk + 1; !below && b2 < rb; b2++) see(bmin[b2]);
+                for (int b2 = bk + 1; !below && b2 < rb; b2++) see(bufB[(b2 << lb2) + bm]);
                 if (!below) see(bufB[R]);
             }
             bool ok = !below && !tie;
@@ -676,54 +661,6 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 }
             }
             if (ok) atomicOr(&aflag[(p - H) >> 5], 1u << ((p - H) & 31));
-        }
-        __syncthreads();
-    } else {
-        // ---- sparse table
-        const int kmax = kmax_s;
-        KT hp[OWN];
-        uint16_t inf[OWN];
-#pragma unroll
-        for (int c = 0; c < OWN; c++) {
-            int p = tid + AT_THREADS * c;
-            hp[c] = p < TP ? bufA[H + p] : 0;
-            inf[c] = p < TP ? pinfo[H + p] : 0;
-        }
-        S *cur = bufA, *nxt = bufB;
-        for (int k = 0; k <= kmax; k++) {
-            const int w = 1 << k;
-#pragma unroll
-            for (int c = 0; c < OWN; c++) {
-                int r = inf[c] & 0x3FFF;
-                if (tid + AT_THREADS * c < TP && r != 0 && (31 - __clz(r)) == k) {
-                    int idx = H + tid + AT_THREADS * c;
-                    const KT L = min<KT>(cur[idx - r], cur[idx - w]);
-                    const KT R = min<KT>(cur[idx + 1], cur[idx + 1 + r - w]);
-                    bool anchor = hp[c] < L && hp[c] < R;
-                    if constexpr (!RANKED) {
-                        if (!anchor && hp[c] <= L && hp[c] <= R) {  // equal top halves
-                            const uint64_t ep = exact64(idx);
-                            anchor = true;
-                            for (int dd = 1; anchor && dd <= r; dd++)
-                                anchor = exact64(idx - dd) > ep && exact64(idx + dd) > ep;
-                        }
-                    }
-                    if (anchor) {
-                        int pp = tid + AT_THREADS * c;
-                        atomicOr(&aflag[pp >> 5], 1u << (pp & 31));
-                    }
-                }
-            }
-            if (k == kmax) break;
-            for (int a = tid; a < NR; a += AT_THREADS) {
-                S v = cur[a];
-                if (a + w < NR) v = min(v, cur[a + w]);
-                nxt[a] = v;
-            }
-            __syncthreads();
-            S *t = cur;
-            cur = nxt;
-            nxt = t;
         }
         __syncthreads();
     }

@@ -57,6 +57,15 @@ def mixed_collection(seed):
     return dg.from_list([strs[i] for i in order], 4)
 
 
+def wide_radius_collection(seed, sigma, n=60):
+    """Lengths 50..6000 at T = 2: radii from 7 to ~1000 (regions of 4096 positions, window
+    blocks of 8 and 16), plus a homopolymer run (equal q-grams across whole windows)."""
+    rng = np.random.default_rng(seed)
+    strs = [rng.integers(0, sigma, int(rng.integers(50, 6000))).astype(np.uint8) for _ in range(n)]
+    strs.insert(n // 2, np.full(3000, 1, np.uint8))
+    return dg.from_list(strs, sigma)
+
+
 # ---------------------------------------------------------------- worked example
 def test_worked_example_end_to_end(mj):
     import torch
@@ -87,6 +96,9 @@ CASES = {
     "protein_per_string_K": dict(make=lambda: dg.protein(seed=6, n=1500), q=4, k_frac=(8, 100),
                                  t_div=1),
     "text_q6": dict(make=lambda: dg.text(seed=7, n=1500), q=6, k=120, t_div=2),
+    "dna_wide_radius": dict(make=lambda: wide_radius_collection(31, 4), q=4, k=60, t_fixed=2),
+    "text_wide_radius_hashed": dict(make=lambda: wide_radius_collection(32, 37), q=6, k=60,
+                                    t_fixed=2),
     "alphabet12_q4": dict(make=lambda: dg.from_list(
         [dg.mutate(np.random.default_rng(900 + i), base, 0.02, 12)
          for base in [np.random.default_rng(80 + c).integers(0, 12, 600 + 37 * c).astype(np.uint8)
