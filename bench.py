@@ -439,7 +439,8 @@ def main():
                    "K": cfg.get("k", "ceil(%d/%d m_i)" % tuple(cfg.get("k_frac", (0, 1)))),
                    "q": cfg["q"], "t_div": cfg["t_div"], "reps": cfg["reps"], "path": "batched",
                    "verify_lanes_per_pair": last["verify_group"],
-                   "verify_words_per_lane": last["verify_words"]},
+                   "verify_words_per_lane": last["verify_words"],
+                   "verify_workgroups": last["verify_blocks"]},
         "plain": {"value": S.n / (plain_ms * 1e-3), "ms_per_step": plain_ms,
                   "verify_kernel_ms": float(np.mean([s["kernel_ms"]["verify"] for s in plain_stats]))},
         "batched_vs_plain": plain_ms / ms,

@@ -116,6 +116,8 @@ typedef struct {
     int32_t verify_group;  /* lanes per pair of the batched verifier (0: plain; -2: two
                               lanes splitting the text columns, forward and reversed) */
     int32_t verify_words;  /* band words per lane of the batched verifier */
+    int32_t verify_blocks; /* most workgroups the batched verifier's persistent launch may
+                              have (fewer when the pairs need fewer) */
 } mj_stats;
 
 /* ---- context ---------------------------------------------------------------- */

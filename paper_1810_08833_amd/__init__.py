@@ -45,12 +45,13 @@ class MjStats(ctypes.Structure):
                 ("output", ctypes.c_int64), ("band_cells", ctypes.c_int64),
                 ("stage_ms", ctypes.c_float * 8), ("kernel_ms", ctypes.c_float * 4),
                 ("kernel_launches", ctypes.c_int32 * 4), ("positions", ctypes.c_int64),
-                ("verify_group", ctypes.c_int32), ("verify_words", ctypes.c_int32)]
+                ("verify_group", ctypes.c_int32), ("verify_words", ctypes.c_int32),
+                ("verify_blocks", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k in ("records", "groups", "pair_tests", "candidates",
                                            "output", "band_cells", "positions", "verify_group",
-                                           "verify_words")}
+                                           "verify_words", "verify_blocks")}
         d["stage_ms"] = {STAGES[i]: float(self.stage_ms[i]) for i in range(7)}
         d["kernel_ms"] = {KERNELS[i]: float(self.kernel_ms[i]) for i in range(4)}
         d["kernel_launches"] = {KERNELS[i]: int(self.kernel_launches[i]) for i in range(4)}

@@ -189,6 +189,7 @@ static void run_verify(mj_ctx *ctx, const uint64_t *pairs, int64_t n, const DevS
         if (stats) {
             stats->verify_group = ctx->tune.last_g == VERIFY_BIDIR ? -2 : ctx->tune.last_g;
             stats->verify_words = ctx->tune.last_nwl;
+            stats->verify_blocks = ctx->tune.last_blocks;
         }
         return;
     }
