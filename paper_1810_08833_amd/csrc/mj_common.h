@@ -63,6 +63,15 @@ class Workspace {
     template <class T> T *get_n(size_t n) { return static_cast<T *>(get(n * sizeof(T) + 16)); }
     void release_all();
     size_t bytes_held() const { return held_; }
+    // State of the single-pass scans (prims.hip), kept across calls: one word per tile
+    // tagged with the call's epoch (so it never needs clearing) and a tile ticket counter
+    // that only grows (`base` = its value before the next scan).
+    struct ScanState {
+        uint64_t *state = nullptr;
+        unsigned long long *ticket = nullptr;
+        uint64_t base = 0;
+        uint32_t epoch = 0;
+    } scan;
 
   private:
     struct Block { void *p; size_t n; bool used; };

@@ -699,24 +699,22 @@ __global__ void k_anchor_scatter(const uint64_t *bm, int64_t nw, const uint32_t 
 // Phi the Karp-Rabin polynomial of the content over GF(2^61-1), length folded in as the
 // leading coefficient; payload (string id << 32 | start position).  The owning string
 // comes from the descriptor of the tile holding the partition's first position.
-// Horner's rule takes C symbols per step when the alphabet is small (C = 4 for b <= 2
-// bits, C = 2 for b <= 5): Phi <- Phi * B^C + T[x_0 .. x_{C-1}] with the table T of
-// sum_k (x_k + 1) B^(C-1-k) mod 2^61-1 over all 2^(C*b) chunks (in LDS).  Modular
-// arithmetic is exact, so this is the same Phi as one symbol per step.  Symbols come
-// four at a time from aligned 32-bit words; codes are taken modulo 2^b.
+// Horner's rule takes 8 symbols per step: Phi <- Phi * B^8 + sum_k (x_k + 1) B^(7-k), the
+// sum read from tables in LDS, and a shorter tail 4 symbols and then 1 symbol at a time.
+// Modular arithmetic is exact, so this is the same Phi as one symbol per step.  Symbols
+// come four at a time from aligned 32-bit words; codes are taken modulo 2^b.
 __device__ __forceinline__ uint64_t horner_step(uint64_t h, uint64_t B, uint32_t c) {
     h = mulmod61(h, B) + (uint64_t)c + 1;
     return h >= P61 ? h - P61 : h;
 }
 
-__device__ __forceinline__ uint64_t horner_chunk(uint64_t h, uint64_t BC, uint64_t t) {
-    h = mulmod61(h, BC) + t;
-    return h >= P61 ? h - P61 : h;
-}
+// s < 2^64 reduced to [0, 2^61 + 8): 2^61 = 1 modulo 2^61 - 1
+__device__ __forceinline__ uint64_t fold61(uint64_t s) { return (s & P61) + (s >> 61); }
 
-// Chunk tables of Horner's rule over 4 symbols.  pt == 0: T[x] for every packed chunk x
-// (2^(4b) entries, b <= 2).  pt == 1: four power tables, T[j 2^b + c] = (c + 1) B^j, so a
-// chunk's value is the sum of one entry of each (4 * 2^b entries).
+// Chunk tables.  pt == 0 (b <= 2): T[x] = sum_k (x_k + 1) B^(3-k) for every packed chunk x
+// of 4 symbols, then the same values times B^4 (2 * 2^(4b) entries).  pt == 1: eight power
+// tables T[j 2^b + c] = (c + 1) B^j, j < 8, a chunk's value being the sum of one entry of
+// each (8 * 2^b entries).
 __global__ void k_phi_table(int nc, int bits, uint64_t B, int pt, uint64_t *__restrict__ T) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nc) return;
@@ -725,8 +723,11 @@ __global__ void k_phi_table(int nc, int bits, uint64_t B, int pt, uint64_t *__re
         h = (uint64_t)(idx & ((1 << bits) - 1)) + 1;
         for (int j = 0; j < (idx >> bits); j++) h = mulmod61(h, B);
     } else {
+        const int x = idx & ((1 << (4 * bits)) - 1);
         for (int k = 0; k < 4; k++)
-            h = horner_step(h, B, (uint32_t)(idx >> (bits * (3 - k))) & ((1u << bits) - 1u));
+            h = horner_step(h, B, (uint32_t)(x >> (bits * (3 - k))) & ((1u << bits) - 1u));
+        if (idx >> (4 * bits))
+            for (int k = 0; k < 4; k++) h = mulmod61(h, B);
     }
     T[idx] = h;
 }
@@ -744,36 +745,47 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
     const int64_t *__restrict__ apos, int64_t R, const int64_t *__restrict__ off, int32_t n,
     const uint8_t *__restrict__ chars, int64_t total, int aligned4,
     const TileDesc *__restrict__ td, int TP, uint64_t B, uint64_t salt_f,
-    const uint64_t *__restrict__ table, int pt, int bits, uint64_t BC, uint64_t *key,
+    const uint64_t *__restrict__ table, int pt, int bits, uint64_t B4, uint64_t B8, uint64_t *key,
     uint64_t *val, uint32_t *len) {
     extern __shared__ uint64_t Ts[];
     __shared__ uint32_t stage[STAGED ? REC_STAGE_WORDS : 1];
     const int nsym = 1 << bits;
-    const int nc = pt ? 4 * nsym : 1 << (4 * bits);
+    const int n4 = 1 << (4 * bits);  // pt == 0: chunks of 4 symbols
+    const int nc = pt ? 8 * nsym : 2 * n4;
     for (int t = threadIdx.x; t < nc; t += blockDim.x) Ts[t] = table[t];
     const uint32_t m = (1u << bits) - 1u;
-    // Horner's rule over [g, g1) from symbol bytes sym(i) and aligned words word(i)
+    // the packed chunk of the 4 symbol bytes of v (pt == 0)
+    auto pack4 = [&](uint32_t v) -> uint32_t {
+        return ((v & m) << (3 * bits)) | (((v >> 8) & m) << (2 * bits)) | (((v >> 16) & m) << bits) |
+               ((v >> 24) & m);
+    };
+    // sum over the 4 symbols x_k of v of (x_k + 1) B^(j0 + 3 - k) (pt == 1): four terms
+    auto pw4 = [&](uint32_t v, int j0) -> uint64_t {
+        return Ts[(j0 + 3) * nsym + (v & m)] + Ts[(j0 + 2) * nsym + ((v >> 8) & m)] +
+               Ts[(j0 + 1) * nsym + ((v >> 16) & m)] + Ts[j0 * nsym + ((v >> 24) & m)];
+    };
+    // Horner's rule over [g, g1) from symbol bytes sym(i) and aligned words word(i).  Every
+    // table entry and h are below p = 2^61 - 1, so a sum of at most five of them stays below
+    // 2^64 and one fold brings it below 2^61 + 5 < 2p.
     auto hash = [&](uint64_t h, int64_t g, int64_t g1, auto sym, auto word) -> uint64_t {
         if (aligned4) {
             for (; g < g1 && (g & 3); g++) h = horner_step(h, B, sym(g) & m);
-            if (!pt) {
-                for (; g + 4 <= g1; g += 4) {
-                    const uint32_t v = word(g);
-                    const uint32_t x = ((v & m) << (3 * bits)) | (((v >> 8) & m) << (2 * bits)) |
-                                       (((v >> 16) & m) << bits) | ((v >> 24) & m);
-                    h = horner_chunk(h, BC, Ts[x]);
+            for (; g + 8 <= g1; g += 8) {  // h B^8 + (x0..x3) B^4 + (x4..x7)
+                const uint32_t v0 = word(g), v1 = word(g + 4);
+                uint64_t x;
+                if (!pt) {
+                    x = fold61(mulmod61(h, B8) + Ts[n4 + pack4(v0)] + Ts[pack4(v1)]);
+                } else {
+                    x = fold61(mulmod61(h, B8) + pw4(v0, 4));
+                    x = fold61(x + pw4(v1, 0));
                 }
-            } else {
-                // h B^4 + (x0+1) B^3 + (x1+1) B^2 + (x2+1) B + (x3+1): five terms below
-                // 2^61 - 1 sum below 2^64; one fold and one subtraction reduce them
-                for (; g + 4 <= g1; g += 4) {
-                    const uint32_t v = word(g);
-                    const uint64_t sum = mulmod61(h, BC) + Ts[3 * nsym + (v & m)] +
-                                         Ts[2 * nsym + ((v >> 8) & m)] + Ts[nsym + ((v >> 16) & m)] +
-                                         Ts[(v >> 24) & m];
-                    h = (sum & P61) + (sum >> 61);
-                    h = h >= P61 ? h - P61 : h;
-                }
+                h = x >= P61 ? x - P61 : x;
+            }
+            if (g + 4 <= g1) {
+                const uint32_t v = word(g);
+                const uint64_t x = fold61(mulmod61(h, B4) + (pt ? pw4(v, 0) : Ts[pack4(v)]));
+                h = x >= P61 ? x - P61 : x;
+                g += 4;
             }
         }
         for (; g < g1; g++) h = horner_step(h, B, sym(g) & m);
@@ -802,29 +814,8 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
             int64_t sbeg;
             owner(g0, sidx, sbeg);
             const int64_t L = g1 - g0;
-            uint64_t h = (uint64_t)L % P61;
-            int64_t g = g0;
-            if (aligned4) {
-                for (; g < g1 && (g & 3); g++) h = horner_step(h, B, chars[g] & m);
-                if (!pt) {
-                    for (; g + 4 <= g1; g += 4) {
-                        const uint32_t v = w[g >> 2];
-                        const uint32_t x = ((v & m) << (3 * bits)) | (((v >> 8) & m) << (2 * bits)) |
-                                           (((v >> 16) & m) << bits) | ((v >> 24) & m);
-                        h = horner_chunk(h, BC, Ts[x]);
-                    }
-                } else {
-                    for (; g + 4 <= g1; g += 4) {
-                        const uint32_t v = w[g >> 2];
-                        const uint64_t sum = mulmod61(h, BC) + Ts[3 * nsym + (v & m)] +
-                                             Ts[2 * nsym + ((v >> 8) & m)] +
-                                             Ts[nsym + ((v >> 16) & m)] + Ts[(v >> 24) & m];
-                        h = (sum & P61) + (sum >> 61);
-                        h = h >= P61 ? h - P61 : h;
-                    }
-                }
-            }
-            for (; g < g1; g++) h = horner_step(h, B, chars[g] & m);
+            const uint64_t h = hash((uint64_t)L % P61, g0, g1, [&](int64_t g) -> uint32_t { return chars[g]; },
+                                    [&](int64_t g) -> uint32_t { return w[g >> 2]; });
             key[k] = mix64(h ^ salt_f);
             val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
             if (len) len[k] = (uint32_t)L;
@@ -979,12 +970,13 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     out.reserve(base0 + total + 1, s);
     const uint64_t B = 2 + mix64(p.seed ^ GAMMA_B) % (P61 - 3);
     const uint64_t salt_f = mix64(p.seed + GAMMA);
-    // Horner chunks of 4 symbols (see k_phi_table): one table of all chunks for b <= 2,
-    // power tables above (at most 1,024 entries either way)
+    // Horner steps of 8 symbols (see k_phi_table): tables of all 4-symbol chunks for
+    // b <= 2, power tables above (at most 2,048 entries either way)
     const int pt = d.bits > 2 ? 1 : 0;
-    uint64_t BC = 1;
-    for (int i = 0; i < 4; i++) BC = (uint64_t)(((unsigned __int128)BC * B) % P61);
-    const int nc = pt ? 4 << d.bits : 1 << (4 * d.bits);
+    uint64_t B4 = 1;
+    for (int i = 0; i < 4; i++) B4 = (uint64_t)(((unsigned __int128)B4 * B) % P61);
+    const uint64_t B8 = (uint64_t)(((unsigned __int128)B4 * B4) % P61);
+    const int nc = pt ? 8 << d.bits : 2 << (4 * d.bits);
     uint64_t *phi_table = ws.get_n<uint64_t>(nc);
     hipLaunchKernelGGL(k_phi_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, d.bits, B, pt,
                        phi_table);
@@ -1004,7 +996,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
             hipLaunchKernelGGL(stg ? k_records<true> : k_records<false>,
                                dim3(grid_for(R[rho], REC_THREADS, 65535)), dim3(REC_THREADS),
                                (size_t)nc * 8, s, apos, R[rho], d.offsets, d.n, d.chars, d.total,
-                               aligned4, ts, TP, B, salt_f, phi_table, pt, d.bits, BC,
+                               aligned4, ts, TP, B, salt_f, phi_table, pt, d.bits, B4, B8,
                                out.key + base, out.val + base,
                                out.with_len ? out.len + base : nullptr);
             MJ_LAUNCH_CHECK();
