@@ -37,7 +37,15 @@ __global__ void k_group_flags(const uint64_t *key, int64_t R, uint8_t *fs, uint8
     }
 }
 
-__global__ void k_group_tests(const int64_t *gs, const int64_t *ge, int64_t G, uint64_t *cnt) {
+// Pair tests of each group.  The group counts c1 (starts) and c2 (ends) are device
+// values: slot[0] = c1 | c2 << 32 and slot[1] = min(c1, c2), the groups scanned.
+__global__ void k_group_tests(const int64_t *gs, const int64_t *ge, const uint32_t *c1,
+                              const uint32_t *c2, uint64_t *cnt, uint64_t *slot) {
+    const int64_t G = min(*c1, *c2);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        slot[0] = (uint64_t)*c1 | ((uint64_t)*c2 << 32);
+        slot[1] = (uint64_t)G;
+    }
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; g < G; g += stride) {
@@ -58,22 +66,27 @@ GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t
     int64_t *ge = ws.get_n<int64_t>(R / 2 + 2);
     const uint32_t *c1 = compact_flags_async(fs, R, gs, ws, s);
     const uint32_t *c2 = compact_flags_async(fe, R, ge, ws, s);
-    MJ_HIP(hipMemcpyAsync(host_scratch, c1, 4, hipMemcpyDeviceToHost, s));
-    MJ_HIP(hipMemcpyAsync((uint8_t *)host_scratch + 4, c2, 4, hipMemcpyDeviceToHost, s));
+    // the group counts stay on the device: test counts and their scan are sized by the
+    // bound R / 2 (a group holds >= 2 records), and one read brings back both counts and
+    // the total
+    const int64_t gmax = R / 2;
+    uint64_t *cnt = ws.get_n<uint64_t>(gmax + 1);
+    gi.tstart = ws.get_n<uint64_t>(gmax + 1);
+    uint64_t *slot = ws.get_n<uint64_t>(3);
+    hipLaunchKernelGGL(k_group_tests, dim3(grid_for(gmax, 256, 16384)), dim3(256), 0, s, gs, ge, c1,
+                       c2, cnt, slot);
+    MJ_LAUNCH_CHECK();
+    exclusive_scan_u64_dev(cnt, gi.tstart, gmax, reinterpret_cast<const uint32_t *>(slot + 1),
+                           slot + 2, ws, s);
+    MJ_HIP(hipMemcpyAsync(host_scratch, slot, 24, hipMemcpyDeviceToHost, s));
     MJ_HIP(hipStreamSynchronize(s));
-    uint32_t hc[2];
-    memcpy(hc, host_scratch, 8);
-    const int64_t G1 = hc[0], G2 = hc[1];
+    uint64_t hs[3];
+    memcpy(hs, host_scratch, 24);
+    const int64_t G1 = (int64_t)(hs[0] & 0xFFFFFFFFu), G2 = (int64_t)(hs[0] >> 32);
     if (G1 != G2) throw Error(MJ_EDEVICE, "group boundary mismatch");
     gi.groups = G1;
     gi.gstart = gs;
-    if (G1 == 0) return gi;
-    uint64_t *cnt = ws.get_n<uint64_t>(G1 + 1);
-    gi.tstart = ws.get_n<uint64_t>(G1 + 1);
-    hipLaunchKernelGGL(k_group_tests, dim3(grid_for(G1, 256, 16384)), dim3(256), 0, s, gs, ge, G1, cnt);
-    MJ_LAUNCH_CHECK();
-    exclusive_scan_u64(cnt, gi.tstart, G1, ws, s);
-    gi.tests = read_back<uint64_t>(gi.tstart + G1, s, host_scratch);
+    gi.tests = G1 > 0 ? hs[2] : 0;
     return gi;
 }
 

@@ -106,6 +106,10 @@ void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 // out[0..n] = exclusive prefix sums of in[0..n), out[n] = total.
 void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, Workspace &ws, hipStream_t s);
 void exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, Workspace &ws, hipStream_t s);
+// The same over the first min(n, *count) elements, count a device value (launch sizes
+// from the bound n); the grand total also goes to *total_out.
+void exclusive_scan_u64_dev(const uint64_t *in, uint64_t *out, int64_t n, const uint32_t *count,
+                            uint64_t *total_out, Workspace &ws, hipStream_t s);
 // Indices i (ascending) with flags[i] != 0; returns count (reads it back).
 int64_t compact_flags(const uint8_t *flags, int64_t n, int64_t *idx_out, Workspace &ws,
                       hipStream_t s, uint64_t *host_scratch);

@@ -163,9 +163,16 @@ __device__ T block_exclusive_scan(T v, T *smem /* >= 4 entries */, T *total) {
     return wpre + inc - v;
 }
 
+// ndev (optional): the element count is min(n, *ndev), a device value; tiles past it
+// contribute 0 and write nothing.
 template <class In, class T>
-__global__ void k_scan_reduce(const In *in, int64_t n, T *partial) {
+__global__ void k_scan_reduce(const In *in, int64_t n, T *partial, const uint32_t *ndev) {
     __shared__ T smem[8];
+    if (ndev) n = min<int64_t>(n, *ndev);
+    if ((int64_t)blockIdx.x * SCAN_TILE >= n) {  // block-uniform
+        if (threadIdx.x == 0) partial[blockIdx.x] = 0;
+        return;
+    }
     int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
     T s = 0;
 #pragma unroll
@@ -176,9 +183,19 @@ __global__ void k_scan_reduce(const In *in, int64_t n, T *partial) {
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
+// ndev as for k_scan_reduce; total_out (optional) receives the grand total as well.
 template <class In, class T>
-__global__ void k_scan_apply(const In *in, int64_t n, const T *partial_scan, T *out) {
+__global__ void k_scan_apply(const In *in, int64_t n, const T *partial_scan, T *out,
+                             const uint32_t *ndev, T *total_out) {
     __shared__ T smem[8];
+    if (ndev) n = min<int64_t>(n, *ndev);
+    if ((int64_t)blockIdx.x * SCAN_TILE >= n) {  // block-uniform
+        if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+            out[0] = 0;
+            if (total_out) *total_out = 0;
+        }
+        return;
+    }
     int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
     T v[SCAN_ITEMS];
     T s = 0;
@@ -198,7 +215,10 @@ __global__ void k_scan_apply(const In *in, int64_t n, const T *partial_scan, T *
     }
     // the block holding element n-1 writes the grand total at out[n]
     int64_t last = n - 1;
-    if (last >= base && last < base + SCAN_ITEMS) out[n] = run;
+    if (last >= base && last < base + SCAN_ITEMS) {
+        out[n] = run;
+        if (total_out) *total_out = run;
+    }
 }
 
 // Single-pass scan of 32-bit sums (decoupled look-back).  A workgroup takes the next tile
@@ -285,7 +305,8 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_lookback(const In *in, int6
 }
 
 template <class In, class T>
-static void scan_impl(const In *in, T *out, int64_t n, Workspace &ws, hipStream_t s);
+static void scan_impl(const In *in, T *out, int64_t n, Workspace &ws, hipStream_t s,
+                      const uint32_t *ndev = nullptr, T *total_out = nullptr);
 
 template <class In>
 static void scan_u32_single_pass(const In *in, uint32_t *out, int64_t n, int64_t nb, Workspace &ws,
@@ -311,7 +332,8 @@ static void scan_u32_single_pass(const In *in, uint32_t *out, int64_t n, int64_t
 }
 
 template <class In, class T>
-static void scan_impl(const In *in, T *out, int64_t n, Workspace &ws, hipStream_t s) {
+static void scan_impl(const In *in, T *out, int64_t n, Workspace &ws, hipStream_t s,
+                      const uint32_t *ndev, T *total_out) {
     if (n <= 0) {
         hipLaunchKernelGGL(k_fill<T>, dim3(1), dim3(64), 0, s, out, (T)0, (int64_t)1);
         MJ_LAUNCH_CHECK();
@@ -320,13 +342,13 @@ static void scan_impl(const In *in, T *out, int64_t n, Workspace &ws, hipStream_
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 1) {
         hipLaunchKernelGGL((k_scan_apply<In, T>), dim3(1), dim3(SCAN_BLOCK), 0, s, in, n,
-                           (const T *)nullptr, out);
+                           (const T *)nullptr, out, ndev, total_out);
         MJ_LAUNCH_CHECK();
         return;
     }
     if (nb > 2147483647LL) throw Error(MJ_ECAPACITY, "scan too large");
     if constexpr (sizeof(T) == 4) {
-        if (nb <= SCAN_LOOKBACK_MAX_TILES) {
+        if (nb <= SCAN_LOOKBACK_MAX_TILES && !ndev && !total_out) {
             scan_u32_single_pass<In>(in, out, n, nb, ws, s);
             return;
         }
@@ -334,11 +356,11 @@ static void scan_impl(const In *in, T *out, int64_t n, Workspace &ws, hipStream_
     T *partial = ws.get_n<T>(nb + 1);
     T *pscan = ws.get_n<T>(nb + 1);
     hipLaunchKernelGGL((k_scan_reduce<In, T>), dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n,
-                       partial);
+                       partial, ndev);
     MJ_LAUNCH_CHECK();
     scan_impl<T, T>(partial, pscan, nb, ws, s);
     hipLaunchKernelGGL((k_scan_apply<In, T>), dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n,
-                       (const T *)pscan, out);
+                       (const T *)pscan, out, ndev, total_out);
     MJ_LAUNCH_CHECK();
 }
 
@@ -347,6 +369,10 @@ void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, Workspace 
 }
 void exclusive_scan_u64(const uint64_t *in, uint64_t *out, int64_t n, Workspace &ws, hipStream_t s) {
     scan_impl<uint64_t, uint64_t>(in, out, n, ws, s);
+}
+void exclusive_scan_u64_dev(const uint64_t *in, uint64_t *out, int64_t n, const uint32_t *count,
+                            uint64_t *total_out, Workspace &ws, hipStream_t s) {
+    scan_impl<uint64_t, uint64_t>(in, out, std::max<int64_t>(n, 1), ws, s, count, total_out);
 }
 
 // ---------------------------------------------------------------- compaction

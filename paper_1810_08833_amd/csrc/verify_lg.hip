@@ -883,8 +883,8 @@ __global__ __launch_bounds__(256) void k_lpt_scatter(const uint64_t *pairs, int6
 static void launch_persist(int nwl, int g, int np, int max_blocks, const uint64_t *pairs,
                            const int64_t *order, int64_t n, const VSet &va, const VSet &vb,
                            int kmode, uint8_t *flags, unsigned long long *cells,
-                           unsigned long long *next, hipStream_t s) {
-    fill_u64((uint64_t *)next, 0, QUEUES * QSTRIDE, s);
+                           unsigned long long *next, hipStream_t s, bool next_zero = false) {
+    if (!next_zero) fill_u64((uint64_t *)next, 0, QUEUES * QSTRIDE, s);
     // at most max_blocks resident workgroups, and no more than the pairs need
     int64_t groups_per_block = 256 / (g == BIDIR ? 2 : g);
     int64_t blocks = (n + groups_per_block - 1) / groups_per_block;
@@ -903,21 +903,25 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     if (A.planes == nullptr || B.planes == nullptr) throw Error(MJ_EINVAL, "strings not packed");
     const int np = verify_planes(std::max(A.bits, B.bits));
     VSet va = vset(A), vb = vset(B);
-    unsigned long long *cells = (unsigned long long *)ws.get_n<uint64_t>(2);
-    unsigned long long *next = (unsigned long long *)ws.get_n<uint64_t>(QUEUES * QSTRIDE);
-    uint32_t *cm = ws.get_n<uint32_t>(4);
-    fill_u64((uint64_t *)cells, 0, 1, s);
+    // one block cleared by one launch: the sub-queue counters, the band-cell counter, the
+    // K pass's two words and the two length-bin counter arrays
+    constexpr int64_t ZNEXT = 2 * QUEUES * QSTRIDE, ZCNT = LPT_BINS + 4;
+    uint32_t *zb = ws.get_n<uint32_t>(ZNEXT + 4 + 4 + 2 * ZCNT);
+    unsigned long long *next = (unsigned long long *)zb;
+    unsigned long long *cells = (unsigned long long *)(zb + ZNEXT);
+    uint32_t *cm = zb + ZNEXT + 4;
     // longest pairs first
-    uint32_t *cnt = ws.get_n<uint32_t>(LPT_BINS + 1);
+    uint32_t *cnt = zb + ZNEXT + 8;
+    uint32_t *fillc = cnt + ZCNT;
+    fill_u32(zb, 0, ZNEXT + 8 + 2 * ZCNT, s);
+    bool next_zero = true;
     uint32_t *off = ws.get_n<uint32_t>(LPT_BINS + 1);
-    uint32_t *fillc = ws.get_n<uint32_t>(LPT_BINS + 1);
     int64_t *order = ws.get_n<int64_t>(n);
     int cmax;
     if (uniform_k >= 0) {
         // every pair's K is known (and its ids valid): no pass over the pairs
         cmax = (int)((std::min<int64_t>(uniform_k, 0x3FFFFFFF) + 31) >> 5);
     } else {
-        fill_u32(cm, 0, 2, s);
         hipLaunchKernelGGL(k_pair_cmax, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, pairs, n, va,
                            vb, kmode, cm, cm + 1);
         MJ_LAUNCH_CHECK();
@@ -930,8 +934,6 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     }
     if (cmax > persist_max_c())
         throw Error(MJ_ECAPACITY, "threshold K above the batched verifier's band limit (K <= 2047)");
-    fill_u32(cnt, 0, LPT_BINS, s);
-    fill_u32(fillc, 0, LPT_BINS, s);
     hipLaunchKernelGGL(k_lpt_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, pairs, n, va, vb, cnt);
     MJ_LAUNCH_CHECK();
     exclusive_scan_u32(cnt, off, LPT_BINS, ws, s);
@@ -979,7 +981,9 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
                 float ms = 1e30f;
                 for (int rep = 0; rep < 2; rep++) {  // best of two: timing noise
                     MJ_HIP(hipEventRecord(e0, s));
-                    launch_persist(nwl, g, np, mb, pairs, order, n, va, vb, kmode, flags, cells, next, s);
+                    launch_persist(nwl, g, np, mb, pairs, order, n, va, vb, kmode, flags, cells, next, s,
+                                   next_zero);
+                    next_zero = false;
                     MJ_HIP(hipEventRecord(e1, s));
                     MJ_HIP(hipEventSynchronize(e1));
                     float t = 0.f;
@@ -1003,7 +1007,7 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     }
     int th = kt ? kt->begin(KTimer::VERIFY, s) : -1;
     launch_persist(nwl_for(nw, best_g), best_g, np, best_blocks, pairs, order, n, va, vb, kmode,
-                   flags, cells, next, s);
+                   flags, cells, next, s, next_zero);
     if (kt) kt->end(th, s);
     if (tune) {
         tune->last_g = best_g;
