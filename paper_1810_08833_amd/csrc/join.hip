@@ -188,15 +188,27 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
             while ((b + 1) * b / 2 <= u) b++;
             a = u - b * (b - 1) / 2;
         }
+        // the group start and record b's words change only when b or the group does:
+        // loaded then, not at every test
+        int64_t s0 = 0, cached_g = -1, cached_b = -1;
+        uint64_t vb = 0, xb = 0;
         for (int c = 0; c < EMIT_CHUNK; c++) {
             uint64_t t = t0 + c;
             bool live = active && t < P;
             bool pass = false;
             uint64_t pairkey = 0;
             if (live) {
-                int64_t s0 = gs[g];
-                const uint64_t va = val[s0 + (int64_t)a], vb = val[s0 + (int64_t)b];
-                const uint64_t xa = meta[s0 + (int64_t)a], xb = meta[s0 + (int64_t)b];
+                if (g != cached_g) {
+                    s0 = gs[g];
+                    cached_g = g;
+                    cached_b = -1;
+                }
+                if ((int64_t)b != cached_b) {
+                    vb = val[s0 + (int64_t)b];
+                    xb = meta[s0 + (int64_t)b];
+                    cached_b = (int64_t)b;
+                }
+                const uint64_t va = val[s0 + (int64_t)a], xa = meta[s0 + (int64_t)a];
                 int32_t ia = (int32_t)(va >> 32), ib = (int32_t)(vb >> 32);
                 if (ia != ib) {
                     const int64_t ma = (int64_t)(xa >> 32), mb = (int64_t)(xb >> 32);
