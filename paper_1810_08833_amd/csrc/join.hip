@@ -91,8 +91,9 @@ GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t
 }
 
 // ---------------------------------------------------------------- candidate emission
-// Pair tests are numbered consecutively across groups; each thread takes EMIT_CHUNK
-// consecutive tests, so a huge group is spread over many threads.  Inside a group of
+// Pair tests are numbered consecutively across groups; each thread takes a run of
+// consecutive tests (EMIT_CHUNK, or a multiple of it in k_emit), so a huge group is
+// spread over many threads.  Inside a group of
 // size z, test u is the pair (a, b), a < b, with u = b(b-1)/2 + a.
 // Filter (Alg. 3): |m_i - m_j| <= K and |pos_i - pos_j| + |(m_i-pos_i) - (m_j-pos_j)| <= K,
 // evaluated as max(|m_i - m_j|, |(2pos_i - m_i) - (2pos_j - m_j)|) <= K (the same test,
@@ -163,15 +164,15 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
                                               const int64_t *__restrict__ gs,
                                               const uint64_t *__restrict__ ts, int64_t G,
                                               uint64_t P, uint64_t *out, int64_t cap,
-                                              unsigned long long *counter) {
+                                              unsigned long long *counter, int chunk) {
     __shared__ EmitStage st;
     if (threadIdx.x == 0) st.n = 0;
     __syncthreads();
     const uint64_t nthreads = (uint64_t)gridDim.x * EMIT_BLOCK;
-    for (uint64_t t0 = ((uint64_t)blockIdx.x * EMIT_BLOCK + threadIdx.x) * EMIT_CHUNK; ;
-         t0 += nthreads * EMIT_CHUNK) {
+    for (uint64_t t0 = ((uint64_t)blockIdx.x * EMIT_BLOCK + threadIdx.x) * chunk; ;
+         t0 += nthreads * chunk) {
         // block-uniform loop exit (the flush has barriers)
-        if (t0 - (uint64_t)threadIdx.x * EMIT_CHUNK >= P) break;
+        if (t0 - (uint64_t)threadIdx.x * chunk >= P) break;
         bool active = t0 < P;
         int64_t g = 0;
         uint64_t a = 0, b = 1;
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
         // loaded then, not at every test
         int64_t s0 = 0, cached_g = -1, cached_b = -1;
         uint64_t vb = 0, xb = 0;
-        for (int c = 0; c < EMIT_CHUNK; c++) {
+        for (int c = 0; c < chunk; c++) {
             uint64_t t = t0 + c;
             bool live = active && t < P;
             bool pass = false;
@@ -230,8 +231,9 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
                 }
             }
             stage(pass, pairkey, st);
+            // the stage holds EMIT_CHUNK tests per thread (chunk is a multiple of it)
+            if ((c & (EMIT_CHUNK - 1)) == EMIT_CHUNK - 1) flush(st, counter, out, cap);
         }
-        flush(st, counter, out, cap);
     }
 }
 
@@ -246,10 +248,14 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
     hipLaunchKernelGGL(k_record_meta, dim3(grid_for(R, 256, 16384)), dim3(256), 0, s, val, R, d.len,
                        d.kk, meta);
     MJ_LAUNCH_CHECK();
-    uint64_t threads = (g.tests + EMIT_CHUNK - 1) / EMIT_CHUNK;
+    // a thread locates its first test by a binary search over the groups; with tests
+    // enough for 2^20 threads it takes longer runs (up to 4 x EMIT_CHUNK) per search
+    int chunk = EMIT_CHUNK;
+    while (chunk < 4 * EMIT_CHUNK && g.tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
+    uint64_t threads = (g.tests + chunk - 1) / chunk;
     unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, 1u << 16);
     hipLaunchKernelGGL(k_emit, dim3(grid), dim3(EMIT_BLOCK), 0, s, val, meta, g.gstart, g.tstart,
-                       g.groups, g.tests, out, cap, counter);
+                       g.groups, g.tests, out, cap, counter, chunk);
     MJ_LAUNCH_CHECK();
     if (kt) kt->end(th, s);
     uint64_t c = read_back<uint64_t>((const uint64_t *)counter, s, host_scratch);
