@@ -194,6 +194,8 @@ constexpr int AT_THREADS = 256;
 // exactly when rank(a) < rank(b), and equal hashes get equal ranks, so every strict
 // window-minimum test gives the same answer on ranks as on the 64-bit hashes.
 constexpr int RANK_MAX_BITS = 12;
+// One wave per code (four per block): the block hashes every code into LDS, each lane
+// counts the smaller hashes among every 64th code, and the wave adds the counts.
 __global__ __launch_bounds__(256) void k_rank_table(int ncodes, uint64_t salt,
                                                     const uint64_t *__restrict__ table,
                                                     uint16_t *__restrict__ rank) {
@@ -201,12 +203,13 @@ __global__ __launch_bounds__(256) void k_rank_table(int ncodes, uint64_t salt,
     for (int c = threadIdx.x; c < ncodes; c += blockDim.x)
         v[c] = table ? table[c] : mix64((uint64_t)c ^ salt);
     __syncthreads();
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncodes) return;
+    const int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (c >= ncodes) return;  // wave-uniform
     const uint64_t x = v[c];
     int below = 0;
-    for (int j = 0; j < ncodes; j++) below += v[j] < x ? 1 : 0;
-    rank[c] = (uint16_t)below;
+    for (int j = lane; j < ncodes; j += 64) below += v[j] < x ? 1 : 0;
+    for (int d = 32; d >= 1; d >>= 1) below += __shfl_xor(below, d, 64);
+    if (lane == 0) rank[c] = (uint16_t)below;
 }
 
 // Per-tile descriptor: the strings overlapping the tile's region (first id, count), and
@@ -248,7 +251,8 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     const uint8_t *__restrict__ chars, const int64_t *__restrict__ off, int32_t n, int64_t total,
     int q, int bits, uint64_t salt, const uint64_t *__restrict__ table,
     const uint16_t *__restrict__ rank, const int32_t *__restrict__ rr, int TP, int H,
-    const TileDesc *__restrict__ tdesc, int aligned4, uint64_t *__restrict__ bitmap) {
+    const TileDesc *__restrict__ tdesc, int aligned4, uint64_t *__restrict__ bitmap,
+    uint32_t *__restrict__ tile_count) {
     constexpr bool RANKED = sizeof(V) == 4;
     // LDS slots hold keys: ranks as 16 bits (ranks < 2^12; the sentinel 0xFFFF is above
     // them all), hashes by their top 32 bits (sentinel 0xFFFFFFFF).  Compact slots leave
@@ -666,33 +670,45 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     }
     // one bit per position: string start or anchor (TP is a multiple of 64)
     const int rem = (int)min<int64_t>(total - tile_start, (int64_t)TP);  // tile positions in the input
-    for (int w = tid; 64 * w < rem; w += AT_THREADS) {
-        uint64_t v = (uint64_t)aflag[2 * w] | ((uint64_t)aflag[2 * w + 1] << 32);
-        if (rem - 64 * w < 64) v &= (1ull << (rem - 64 * w)) - 1ull;
-        bitmap[(tile_start >> 6) + w] = v;
-    }
-}
-
-__global__ void k_word_popc(const uint64_t *bm, int64_t nw, uint32_t *cnt) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < nw; i += stride) cnt[i] = (uint32_t)__popcll(bm[i]);
-}
-
-__global__ void k_anchor_scatter(const uint64_t *bm, int64_t nw, const uint32_t *pre,
-                                 int64_t *apos, int64_t total) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < nw; i += stride) {
-        uint64_t w = bm[i];
-        uint32_t rank = pre[i];
-        while (w) {
-            int b = __ffsll((unsigned long long)w) - 1;
-            apos[rank++] = i * 64 + b;
-            w &= w - 1;
+    // TP / 64 < 64 words: the first wave writes them all and adds up their bits
+    if (tid < 64) {
+        uint32_t mine = 0;
+        if (64 * tid < rem) {
+            uint64_t v = (uint64_t)aflag[2 * tid] | ((uint64_t)aflag[2 * tid + 1] << 32);
+            if (rem - 64 * tid < 64) v &= (1ull << (rem - 64 * tid)) - 1ull;
+            bitmap[(tile_start >> 6) + tid] = v;
+            mine = (uint32_t)__popcll(v);
         }
+        for (int d = 32; d >= 1; d >>= 1) mine += (uint32_t)__shfl_xor((int)mine, d, 64);
+        if (tid == 0) tile_count[blockIdx.x] = mine;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) apos[pre[nw]] = total;
+}
+
+// Positions of the flagged bits, in order: one wave per anchor tile (its TP / 64 <= 64
+// bitmap words), the tile's first rank from the scan of the tiles' counts, each word's
+// from a prefix over the wave.  apos[R] = total closes the last partition.
+__global__ __launch_bounds__(64) void k_anchor_scatter(const uint64_t *__restrict__ bm, int64_t nw,
+                                                       int words_per_tile,
+                                                       const uint32_t *__restrict__ tile_pre,
+                                                       int64_t ntiles, int64_t *__restrict__ apos,
+                                                       int64_t total) {
+    const int lane = threadIdx.x;
+    const int64_t t = blockIdx.x;
+    const int64_t w = t * words_per_tile + lane;
+    uint64_t bits = (lane < words_per_tile && w < nw) ? bm[w] : 0ull;
+    const uint32_t c = (uint32_t)__popcll(bits);
+    uint32_t incl = c;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    uint32_t rank = tile_pre[t] + incl - c;
+    while (bits) {
+        const int b = __ffsll((unsigned long long)bits) - 1;
+        apos[rank++] = w * 64 + b;
+        bits &= bits - 1;
+    }
+    if (t == ntiles - 1 && lane == 63) apos[tile_pre[ntiles]] = total;
 }
 
 // Partition records between consecutive flagged positions: key f = M(Phi xor S) with
@@ -920,21 +936,22 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
                        d.offsets, d.rr, d.n, d.total, ntiles, TP, H, region, ts);
     MJ_LAUNCH_CHECK();
     std::vector<uint64_t *> bitmap(reps);
-    std::vector<uint32_t *> pre(reps);
+    std::vector<uint32_t *> tcount(reps), pre(reps);  // per tile: flagged positions, their scan
     uint16_t *rank = code_bits <= RANK_MAX_BITS ? ws.get_n<uint16_t>((size_t)1 << code_bits) : nullptr;
     for (int rho = 0; rho < reps; rho++) {
         const uint64_t salt = mix64(p.seed + (uint64_t)rho + GAMMA);
         bitmap[rho] = ws.get_n<uint64_t>(nw + 1);
+        tcount[rho] = ws.get_n<uint32_t>(ntiles + 1);
         if (rank) {
             const int nc = 1 << code_bits;
-            hipLaunchKernelGGL(k_rank_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, salt,
+            hipLaunchKernelGGL(k_rank_table, dim3((nc + 3) / 4), dim3(256), 0, s, nc, salt,
                                p.pi_table, rank);
             MJ_LAUNCH_CHECK();
         }
 #define MJ_ANCHORS(R, V)                                                                        \
         hipLaunchKernelGGL((k_anchor_tiles<R, V>), dim3((unsigned)ntiles), dim3(AT_THREADS), rank_lds, s, \
                            d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, rank, \
-                           d.rr, TP, H, ts, aligned4, bitmap[rho])
+                           d.rr, TP, H, ts, aligned4, bitmap[rho], tcount[rho])
         const size_t rank_lds = rank ? ((size_t)2 << code_bits) + 16 : 0;
         if (rank) {
             if (region == 2048) MJ_ANCHORS(2048, uint32_t); else MJ_ANCHORS(4096, uint32_t);
@@ -945,14 +962,10 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
         MJ_LAUNCH_CHECK();
     }
     if (kt) kt->end(th, s);
-    uint32_t *cnt = ws.get_n<uint32_t>(nw + 1);
     for (int rho = 0; rho < reps; rho++) {
-        pre[rho] = ws.get_n<uint32_t>(nw + 1);
-        hipLaunchKernelGGL(k_word_popc, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s,
-                           bitmap[rho], nw, cnt);
-        MJ_LAUNCH_CHECK();
-        exclusive_scan_u32(cnt, pre[rho], nw, ws, s);
-        MJ_HIP(hipMemcpyAsync((uint8_t *)host_scratch + 4 * rho, pre[rho] + nw, 4,
+        pre[rho] = ws.get_n<uint32_t>(ntiles + 1);
+        exclusive_scan_u32(tcount[rho], pre[rho], ntiles, ws, s);
+        MJ_HIP(hipMemcpyAsync((uint8_t *)host_scratch + 4 * rho, pre[rho] + ntiles, 4,
                               hipMemcpyDeviceToHost, s));
     }
     MJ_HIP(hipStreamSynchronize(s));
@@ -986,8 +999,8 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     int64_t *apos = ws.get_n<int64_t>(maxR + 1);
     int64_t base = base0;
     for (int rho = 0; rho < reps; rho++) {
-        hipLaunchKernelGGL(k_anchor_scatter, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s,
-                           bitmap[rho], nw, pre[rho], apos, d.total);
+        hipLaunchKernelGGL(k_anchor_scatter, dim3((unsigned)ntiles), dim3(64), 0, s, bitmap[rho], nw,
+                           TP / 64, pre[rho], ntiles, apos, d.total);
         MJ_LAUNCH_CHECK();
         if (R[rho] > 0) {
             int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
