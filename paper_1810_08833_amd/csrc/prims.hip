@@ -376,24 +376,64 @@ void exclusive_scan_u64_dev(const uint64_t *in, uint64_t *out, int64_t n, const 
 }
 
 // ---------------------------------------------------------------- compaction
-__global__ void k_compact_scatter(const uint8_t *flags, const uint32_t *pre, int64_t n,
-                                  int64_t *idx) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride)
-        if (flags[i]) idx[pre[i]] = i;
+// Indices of the nonzero flags, in order, in three launches and two passes over the
+// flags: per-tile counts, a scan of the tile counts, and a compaction in which each tile
+// ranks its flags with one block-wide prefix (no per-element prefix array).
+constexpr int CT_ITEMS = 16;                      // flags per thread (one 16-byte load)
+constexpr int CT_TILE = SCAN_BLOCK * CT_ITEMS;    // 4,096 flags per tile
+
+// the CT_ITEMS flags of this thread as bits (bit k: element base + k is flagged)
+__device__ __forceinline__ uint32_t flag_bits(const uint8_t *flags, int64_t n, int64_t base) {
+    uint32_t m = 0;
+    if (base + CT_ITEMS <= n && ((uintptr_t)(flags + base) & 15) == 0) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(flags + base);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < CT_ITEMS; k++) m |= ((w[k >> 2] >> (8 * (k & 3))) & 0xFFu) ? 1u << k : 0u;
+    } else {
+        for (int k = 0; k < CT_ITEMS; k++)
+            if (base + k < n && flags[base + k]) m |= 1u << k;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_flag_counts(const uint8_t *flags, int64_t n,
+                                                            uint32_t *tile_count) {
+    __shared__ uint32_t smem[8];
+    const int64_t base = (int64_t)blockIdx.x * CT_TILE + (int64_t)threadIdx.x * CT_ITEMS;
+    uint32_t tot;
+    (void)block_exclusive_scan<uint32_t>((uint32_t)__popc(flag_bits(flags, n, base)), smem, &tot);
+    if (threadIdx.x == 0) tile_count[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_compact_tiles(const uint8_t *flags, int64_t n,
+                                                              const uint32_t *tile_pre,
+                                                              int64_t *idx) {
+    __shared__ uint32_t smem[8];
+    const int64_t base = (int64_t)blockIdx.x * CT_TILE + (int64_t)threadIdx.x * CT_ITEMS;
+    uint32_t m = flag_bits(flags, n, base);
+    uint32_t tot;
+    uint32_t r = tile_pre[blockIdx.x] + block_exclusive_scan<uint32_t>((uint32_t)__popc(m), smem, &tot);
+    while (m) {
+        idx[r++] = base + __ffs(m) - 1;
+        m &= m - 1;
+    }
 }
 
 const uint32_t *compact_flags_async(const uint8_t *flags, int64_t n, int64_t *idx_out,
                                     Workspace &ws, hipStream_t s) {
     // 32-bit ranks: the count of kept elements must stay below 2^32
     if (n > 0xFFFFFFF0LL) throw Error(MJ_ECAPACITY, "compaction of more than 2^32 elements");
-    uint32_t *pre = ws.get_n<uint32_t>(n + 1);
-    scan_impl<uint8_t, uint32_t>(flags, pre, n, ws, s);
-    hipLaunchKernelGGL(k_compact_scatter, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, flags,
-                       pre, n, idx_out);
+    const int64_t nb = std::max<int64_t>((n + CT_TILE - 1) / CT_TILE, 1);
+    uint32_t *cnt = ws.get_n<uint32_t>(nb + 1);
+    uint32_t *pre = ws.get_n<uint32_t>(nb + 1);
+    hipLaunchKernelGGL(k_flag_counts, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, flags, n, cnt);
     MJ_LAUNCH_CHECK();
-    return pre + n;
+    scan_impl<uint32_t, uint32_t>(cnt, pre, nb, ws, s);
+    hipLaunchKernelGGL(k_compact_tiles, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, flags, n, pre,
+                       idx_out);
+    MJ_LAUNCH_CHECK();
+    return pre + nb;
 }
 
 int64_t compact_flags(const uint8_t *flags, int64_t n, int64_t *idx_out, Workspace &ws,
