@@ -644,10 +644,11 @@ void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Work
 // the full key (insertion sort: the runs are short, and a run that holds a frequent key
 // has few inversions).  The run list is split into RUN_SEGS segments, segment j taking
 // the runs whose first change lies in its share of bitmap words, each with a counter on
-// a line of its own (device-scope atomics on one address serialise).  Two runs are
+// a line of its own (device-scope atomics on one address serialise: 64 segments left the
+// repair at 0.9 ms on 78 M text records, 1,024 took 0.4 ms off the sort).  Two runs are
 // disjoint and hold two records each around their first change, so W words of 64
 // positions hold at most 32 W + 1 first changes: a segment can never overflow.
-constexpr int RUN_SEGS = 64;
+constexpr int RUN_SEGS = 1024;
 constexpr int RUN_CSTRIDE = 64;  // uint64 words between two segment counters
 __global__ void k_run_bits(const uint64_t *__restrict__ key, int64_t n, uint64_t *__restrict__ rsb,
                            uint64_t *__restrict__ brb) {
