@@ -159,8 +159,13 @@ __global__ void k_record_meta(const uint64_t *__restrict__ val, int64_t R,
     }
 }
 
+// LAZY: no meta array; a record's (m, K) word is gathered by its string id at each use
+// (fewer pair tests than records, as on text and DNA).
+template <bool LAZY>
 __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict__ val,
                                               const uint64_t *__restrict__ meta,
+                                              const int32_t *__restrict__ len,
+                                              const int32_t *__restrict__ kk,
                                               const int64_t *__restrict__ gs,
                                               const uint64_t *__restrict__ ts, int64_t G,
                                               uint64_t P, uint64_t *out, int64_t cap,
@@ -204,12 +209,20 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
                     cached_g = g;
                     cached_b = -1;
                 }
+                auto meta_of = [&](int64_t i, uint64_t v) -> uint64_t {
+                    if constexpr (LAZY) {
+                        const int32_t sid = (int32_t)(v >> 32);
+                        return ((uint64_t)(uint32_t)len[sid] << 32) | (uint32_t)kk[sid];
+                    } else {
+                        return meta[i];
+                    }
+                };
                 if ((int64_t)b != cached_b) {
                     vb = val[s0 + (int64_t)b];
-                    xb = meta[s0 + (int64_t)b];
+                    xb = meta_of(s0 + (int64_t)b, vb);
                     cached_b = (int64_t)b;
                 }
-                const uint64_t va = val[s0 + (int64_t)a], xa = meta[s0 + (int64_t)a];
+                const uint64_t va = val[s0 + (int64_t)a], xa = meta_of(s0 + (int64_t)a, va);
                 int32_t ia = (int32_t)(va >> 32), ib = (int32_t)(vb >> 32);
                 if (ia != ib) {
                     const int64_t ma = (int64_t)(xa >> 32), mb = (int64_t)(xb >> 32);
@@ -243,19 +256,25 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
     if (g.groups == 0 || g.tests == 0) return 0;
     unsigned long long *counter = (unsigned long long *)ws.get_n<uint64_t>(2);
     fill_u64((uint64_t *)counter, 0, 1, s);
-    uint64_t *meta = ws.get_n<uint64_t>(R + 1);
+    // the (m, K) words of all records in one pass when the pair tests outnumber the
+    // records; gathered at each use otherwise
+    const bool lazy = g.tests < (uint64_t)R;
+    uint64_t *meta = lazy ? nullptr : ws.get_n<uint64_t>(R + 1);
     int th = kt ? kt->begin(KTimer::EMIT, s) : -1;
-    hipLaunchKernelGGL(k_record_meta, dim3(grid_for(R, 256, 16384)), dim3(256), 0, s, val, R, d.len,
-                       d.kk, meta);
-    MJ_LAUNCH_CHECK();
+    if (!lazy) {
+        hipLaunchKernelGGL(k_record_meta, dim3(grid_for(R, 256, 16384)), dim3(256), 0, s, val, R,
+                           d.len, d.kk, meta);
+        MJ_LAUNCH_CHECK();
+    }
     // a thread locates its first test by a binary search over the groups; with tests
     // enough for 2^20 threads it takes longer runs (up to 4 x EMIT_CHUNK) per search
     int chunk = EMIT_CHUNK;
     while (chunk < 4 * EMIT_CHUNK && g.tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
     uint64_t threads = (g.tests + chunk - 1) / chunk;
     unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, 1u << 16);
-    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(EMIT_BLOCK), 0, s, val, meta, g.gstart, g.tstart,
-                       g.groups, g.tests, out, cap, counter, chunk);
+    hipLaunchKernelGGL(lazy ? k_emit<true> : k_emit<false>, dim3(grid), dim3(EMIT_BLOCK), 0, s, val,
+                       meta, d.len, d.kk, g.gstart, g.tstart, g.groups, g.tests, out, cap, counter,
+                       chunk);
     MJ_LAUNCH_CHECK();
     if (kt) kt->end(th, s);
     uint64_t c = read_back<uint64_t>((const uint64_t *)counter, s, host_scratch);
