@@ -257,7 +257,8 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
     unsigned long long *counter = (unsigned long long *)ws.get_n<uint64_t>(2);
     fill_u64((uint64_t *)counter, 0, 1, s);
     // the (m, K) words of all records in one pass when the pair tests outnumber the
-    // records; gathered at each use otherwise
+    // records; gathered at each use otherwise (measured: text with 0.46 tests per record
+    // gains 0.7 ms, protein with 3.7 loses 0.2 ms gathering)
     const bool lazy = g.tests < (uint64_t)R;
     uint64_t *meta = lazy ? nullptr : ws.get_n<uint64_t>(R + 1);
     int th = kt ? kt->begin(KTimer::EMIT, s) : -1;
