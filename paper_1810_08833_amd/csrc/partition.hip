@@ -727,17 +727,19 @@ __device__ __forceinline__ uint64_t horner_step(uint64_t h, uint64_t B, uint32_t
 // s < 2^64 reduced to [0, 2^61 + 8): 2^61 = 1 modulo 2^61 - 1
 __device__ __forceinline__ uint64_t fold61(uint64_t s) { return (s & P61) + (s >> 61); }
 
-// Chunk tables.  pt == 0 (b <= 2): T[x] = sum_k (x_k + 1) B^(3-k) for every packed chunk x
-// of 4 symbols, then the same values times B^4 (2 * 2^(4b) entries).  pt == 1: eight power
-// tables T[j 2^b + c] = (c + 1) B^j, j < 8, a chunk's value being the sum of one entry of
-// each (8 * 2^b entries).
+// Chunk tables.  Eight power tables P[j 2^b + c] = (c + 1) B^j, j < 8 (8 * 2^b entries):
+// a chunk's value is the sum of one entry of each, and P[j 2^b] = B^j.  pt == 0 (b <= 2)
+// puts before them T[x] = sum_k (x_k + 1) B^(3-k) for every packed chunk x of 4 symbols
+// and the same values times B^4 (2 * 2^(4b) entries).
 __global__ void k_phi_table(int nc, int bits, uint64_t B, int pt, uint64_t *__restrict__ T) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nc) return;
     uint64_t h = 0;
-    if (pt) {
-        h = (uint64_t)(idx & ((1 << bits) - 1)) + 1;
-        for (int j = 0; j < (idx >> bits); j++) h = mulmod61(h, B);
+    const int pbase = pt ? 0 : 2 << (4 * bits);  // first power-table entry
+    if (idx >= pbase) {
+        const int e = idx - pbase;
+        h = (uint64_t)(e & ((1 << bits) - 1)) + 1;
+        for (int j = 0; j < (e >> bits); j++) h = mulmod61(h, B);
     } else {
         const int x = idx & ((1 << (4 * bits)) - 1);
         for (int k = 0; k < 4; k++)
@@ -767,7 +769,8 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
     __shared__ uint32_t stage[STAGED ? REC_STAGE_WORDS : 1];
     const int nsym = 1 << bits;
     const int n4 = 1 << (4 * bits);  // pt == 0: chunks of 4 symbols
-    const int nc = pt ? 8 * nsym : 2 * n4;
+    const int pbase = pt ? 0 : 2 * n4;  // the power tables
+    const int nc = pbase + 8 * nsym;
     for (int t = threadIdx.x; t < nc; t += blockDim.x) Ts[t] = table[t];
     const uint32_t m = (1u << bits) - 1u;
     // the packed chunk of the 4 symbol bytes of v (pt == 0)
@@ -780,11 +783,25 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
         return Ts[(j0 + 3) * nsym + (v & m)] + Ts[(j0 + 2) * nsym + ((v >> 8) & m)] +
                Ts[(j0 + 1) * nsym + ((v >> 16) & m)] + Ts[j0 * nsym + ((v >> 24) & m)];
     };
-    // Horner's rule over [g, g1) from symbol bytes sym(i) and aligned words word(i).  Every
-    // table entry and h are below p = 2^61 - 1, so a sum of at most five of them stays below
-    // 2^64 and one fold brings it below 2^61 + 5 < 2p.
-    auto hash = [&](uint64_t h, int64_t g, int64_t g1, auto sym, auto word) -> uint64_t {
+    // h B^k + sum over the k < 4 symbols x_i at bytes 0 .. k-1 of v of (x_i + 1) B^(k-1-i)
+    auto partial = [&](uint64_t h, uint32_t v, int k) -> uint64_t {
+        uint64_t sum = mulmod61(h, Ts[pbase + k * nsym]);  // P[k 2^b] = B^k
+        for (int i = 0; i < k; i++) sum += Ts[pbase + (k - 1 - i) * nsym + ((v >> (8 * i)) & m)];
+        const uint64_t x = fold61(sum);
+        return x >= P61 ? x - P61 : x;
+    };
+    // Horner's rule over [g, g1) from symbol bytes sym(i) and aligned words word(i), a word
+    // being readable when it ends at or before wend.  Every table entry and h are below
+    // p = 2^61 - 1, so a sum of at most five of them stays below 2^64 and one fold brings
+    // it below 2^61 + 5 < 2p.  The symbols before the first word boundary and after the
+    // last whole chunk go in one step each.
+    auto hash = [&](uint64_t h, int64_t g, int64_t g1, int64_t wend, auto sym, auto word) -> uint64_t {
         if (aligned4) {
+            if ((g & 3) && g < g1 && (g | 3) < wend) {
+                const int k = (int)min<int64_t>(4 - (g & 3), g1 - g);
+                h = partial(h, word(g & ~(int64_t)3) >> (8 * (g & 3)), k);
+                g += k;
+            }
             for (; g < g1 && (g & 3); g++) h = horner_step(h, B, sym(g) & m);
             for (; g + 8 <= g1; g += 8) {  // h B^8 + (x0..x3) B^4 + (x4..x7)
                 const uint32_t v0 = word(g), v1 = word(g + 4);
@@ -802,6 +819,10 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
                 const uint64_t x = fold61(mulmod61(h, B4) + (pt ? pw4(v, 0) : Ts[pack4(v)]));
                 h = x >= P61 ? x - P61 : x;
                 g += 4;
+            }
+            if (g < g1 && g + 4 <= wend) {
+                h = partial(h, word(g), (int)(g1 - g));
+                g = g1;
             }
         }
         for (; g < g1; g++) h = horner_step(h, B, sym(g) & m);
@@ -830,7 +851,8 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
             int64_t sbeg;
             owner(g0, sidx, sbeg);
             const int64_t L = g1 - g0;
-            const uint64_t h = hash((uint64_t)L % P61, g0, g1, [&](int64_t g) -> uint32_t { return chars[g]; },
+            const uint64_t h = hash((uint64_t)L % P61, g0, g1, total,
+                                    [&](int64_t g) -> uint32_t { return chars[g]; },
                                     [&](int64_t g) -> uint32_t { return w[g >> 2]; });
             key[k] = mix64(h ^ salt_f);
             val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
@@ -870,10 +892,10 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
         uint64_t h = (uint64_t)L % P61;
         if (staged) {
             const uint8_t *sbytes = reinterpret_cast<const uint8_t *>(stage);
-            h = hash(h, g0, g1, [&](int64_t g) -> uint32_t { return sbytes[g - sb]; },
+            h = hash(h, g0, g1, sb + 4 * nwords, [&](int64_t g) -> uint32_t { return sbytes[g - sb]; },
                      [&](int64_t g) -> uint32_t { return stage[(g - sb) >> 2]; });
         } else {
-            h = hash(h, g0, g1, [&](int64_t g) -> uint32_t { return chars[g]; },
+            h = hash(h, g0, g1, total, [&](int64_t g) -> uint32_t { return chars[g]; },
                      [&](int64_t g) -> uint32_t { return w[g >> 2]; });
         }
         key[k] = mix64(h ^ salt_f);
@@ -983,13 +1005,13 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     out.reserve(base0 + total + 1, s);
     const uint64_t B = 2 + mix64(p.seed ^ GAMMA_B) % (P61 - 3);
     const uint64_t salt_f = mix64(p.seed + GAMMA);
-    // Horner steps of 8 symbols (see k_phi_table): tables of all 4-symbol chunks for
-    // b <= 2, power tables above (at most 2,048 entries either way)
+    // Horner steps of 8 symbols (see k_phi_table): power tables, and for b <= 2 tables of
+    // all 4-symbol chunks before them (at most 2,048 entries)
     const int pt = d.bits > 2 ? 1 : 0;
     uint64_t B4 = 1;
     for (int i = 0; i < 4; i++) B4 = (uint64_t)(((unsigned __int128)B4 * B) % P61);
     const uint64_t B8 = (uint64_t)(((unsigned __int128)B4 * B4) % P61);
-    const int nc = pt ? 8 << d.bits : 2 << (4 * d.bits);
+    const int nc = (pt ? 0 : 2 << (4 * d.bits)) + (8 << d.bits);
     uint64_t *phi_table = ws.get_n<uint64_t>(nc);
     hipLaunchKernelGGL(k_phi_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, d.bits, B, pt,
                        phi_table);
