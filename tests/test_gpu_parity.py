@@ -57,6 +57,19 @@ def mixed_collection(seed):
     return dg.from_list([strs[i] for i in order], 4)
 
 
+def heavy_cluster_collection(seed):
+    """Two bases with 60 near-copies each (1% edits): groups of ~60 records, so the pair
+    tests outnumber the records many times over (the emission path that builds the (m, K)
+    words of every record first)."""
+    rng = np.random.default_rng(seed)
+    strs = []
+    for c in range(2):
+        base = rng.integers(0, 4, 500).astype(np.uint8)
+        strs += [dg.mutate(np.random.default_rng(seed * 1000 + c * 100 + i), base, 0.01, 4)
+                 for i in range(60)]
+    return dg.from_list(strs, 4)
+
+
 def wide_radius_collection(seed, sigma, n=60):
     """Lengths 50..6000 at T = 2: radii from 7 to ~1000 (regions of 4096 positions, window
     blocks of 8 and 16), plus a homopolymer run (equal q-grams across whole windows)."""
@@ -96,6 +109,7 @@ CASES = {
     "protein_per_string_K": dict(make=lambda: dg.protein(seed=6, n=1500), q=4, k_frac=(8, 100),
                                  t_div=1),
     "text_q6": dict(make=lambda: dg.text(seed=7, n=1500), q=6, k=120, t_div=2),
+    "dna_heavy_clusters": dict(make=lambda: heavy_cluster_collection(77), q=4, k=20, t_div=1),
     "dna_wide_radius": dict(make=lambda: wide_radius_collection(31, 4), q=4, k=60, t_fixed=2),
     "text_wide_radius_hashed": dict(make=lambda: wide_radius_collection(32, 37), q=6, k=60,
                                     t_fixed=2),
