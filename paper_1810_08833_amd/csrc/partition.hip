@@ -261,8 +261,11 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     // full hashes, recomputed from the staged symbols, decide (exact64 below).
     using S = typename std::conditional<RANKED, uint16_t, uint32_t>::type;
     using KT = uint32_t;  // keys in registers
+    // keys, then the suffix (bufA) and prefix (bufB) minima within window-test blocks
     __shared__ __align__(16) S bufA[REGION];
     __shared__ __align__(16) S bufB[REGION];
+    // per region slot: bits 0-13 the radius if the position is interior (else 0), bit 14
+    // set where a full q-gram starts
     __shared__ __align__(16) uint16_t pinfo[REGION];
     // symbols, word-aligned with the input: NR + q - 1 bytes from offset sh < 4, read as
     // whole words (and up to 16 bytes past the last q-gram by the hashing loop)
@@ -270,6 +273,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     constexpr int CW = (CH_WORDS + AT_THREADS - 1) / AT_THREADS;  // words per thread
     __shared__ __align__(16) uint32_t ch32[CH_WORDS];
     uint8_t *const ch = reinterpret_cast<uint8_t *>(ch32);
+    // anchor and string-start flags of the tile positions, one bit each
     __shared__ uint32_t aflag[REGION / 32];
     __shared__ TileDesc td;
     // rank table: 2^(q b) entries in dynamic shared memory (sized at launch; none for
