@@ -533,7 +533,9 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 pinfo[idx] = info;
             }
         }
-        if (lrmin < 0x7FFFFFFF) atomicMin(&rmin_s, lrmin);
+        // one LDS atomic per wave: the lanes' atomics on one address would serialise
+        for (int d = 32; d >= 1; d >>= 1) lrmin = min(lrmin, __shfl_xor(lrmin, d, 64));
+        if ((tid & 63) == 0 && lrmin < 0x7FFFFFFF) atomicMin(&rmin_s, lrmin);
     }
     __syncthreads();
     // the full hash of region slot idx (~0 where no full q-gram starts): the tie-break of
