@@ -146,24 +146,30 @@ __device__ __forceinline__ void flush(EmitStage &st, unsigned long long *counter
     }
 }
 
-// meta[i] = m << 32 | K of the string owning sorted record i, so that a pair test reads
-// four record-aligned words (two payloads, two metas) with no dependent gathers.
+// lk[s] = m << 32 | K of string s: one gather where a record's string is looked up
+__global__ void k_string_meta(const int32_t *__restrict__ len, const int32_t *__restrict__ kk,
+                              int32_t n, uint64_t *__restrict__ lk) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        lk[i] = ((uint64_t)(uint32_t)len[i] << 32) | (uint32_t)kk[i];
+}
+
+// meta[i] = the (m, K) word of the string owning sorted record i, so that a pair test
+// reads four record-aligned words (two payloads, two metas) with no dependent gathers.
 __global__ void k_record_meta(const uint64_t *__restrict__ val, int64_t R,
-                              const int32_t *__restrict__ len, const int32_t *__restrict__ kk,
-                              uint64_t *__restrict__ meta) {
+                              const uint64_t *__restrict__ lk, uint64_t *__restrict__ meta) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < R; i += stride) {
-        const int32_t sid = (int32_t)(val[i] >> 32);
-        meta[i] = ((uint64_t)(uint32_t)len[sid] << 32) | (uint32_t)kk[sid];
-    }
+    for (; i < R; i += stride) meta[i] = lk[(int32_t)(val[i] >> 32)];
 }
 
 // LAZY: no meta array; a record's (m, K) word is gathered by its string id at each use
-// (fewer pair tests than records, as on text and DNA).
+// (fewer pair tests than records, as on text and DNA), from lk if given, else from the
+// length and K arrays.
 template <bool LAZY>
 __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict__ val,
                                               const uint64_t *__restrict__ meta,
+                                              const uint64_t *__restrict__ lk,
                                               const int32_t *__restrict__ len,
                                               const int32_t *__restrict__ kk,
                                               const int64_t *__restrict__ gs,
@@ -212,6 +218,7 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
                 auto meta_of = [&](int64_t i, uint64_t v) -> uint64_t {
                     if constexpr (LAZY) {
                         const int32_t sid = (int32_t)(v >> 32);
+                        if (lk) return lk[sid];
                         return ((uint64_t)(uint32_t)len[sid] << 32) | (uint32_t)kk[sid];
                     } else {
                         return meta[i];
@@ -261,10 +268,19 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
     // gains 0.7 ms, protein with 3.7 loses 0.2 ms gathering)
     const bool lazy = g.tests < (uint64_t)R;
     uint64_t *meta = lazy ? nullptr : ws.get_n<uint64_t>(R + 1);
+    // one (m, K) word per string, one gather per look-up, when look-ups are many enough
+    // (16 per string) to repay its pass
+    const bool packed = !lazy || g.tests >= 16 * (uint64_t)std::max(d.n, 1);
+    uint64_t *lk = packed ? ws.get_n<uint64_t>((size_t)d.n + 1) : nullptr;
     int th = kt ? kt->begin(KTimer::EMIT, s) : -1;
+    if (packed) {
+        hipLaunchKernelGGL(k_string_meta, dim3(grid_for(d.n, 256, 65535)), dim3(256), 0, s, d.len,
+                           d.kk, d.n, lk);
+        MJ_LAUNCH_CHECK();
+    }
     if (!lazy) {
         hipLaunchKernelGGL(k_record_meta, dim3(grid_for(R, 256, 16384)), dim3(256), 0, s, val, R,
-                           d.len, d.kk, meta);
+                           lk, meta);
         MJ_LAUNCH_CHECK();
     }
     // a thread locates its first test by a binary search over the groups; with tests
@@ -274,7 +290,7 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
     uint64_t threads = (g.tests + chunk - 1) / chunk;
     unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, 1u << 16);
     hipLaunchKernelGGL(lazy ? k_emit<true> : k_emit<false>, dim3(grid), dim3(EMIT_BLOCK), 0, s, val,
-                       meta, d.len, d.kk, g.gstart, g.tstart, g.groups, g.tests, out, cap, counter,
+                       meta, lk, d.len, d.kk, g.gstart, g.tstart, g.groups, g.tests, out, cap, counter,
                        chunk);
     MJ_LAUNCH_CHECK();
     if (kt) kt->end(th, s);
