@@ -185,7 +185,8 @@ static void run_verify(mj_ctx *ctx, const uint64_t *pairs, int64_t n, const DevS
     *cells_h = 0;
     if (p->verifier == MJ_VERIFY_BATCHED) {
         verify_pairs_batched(pairs, n, A, B, kmode, flags, ctx->ws, s, ctx->pinned, &ctx->kt,
-                             &ctx->tune, uniform_k, cells_h, p->verify_lanes);
+                             ctx->no_tuning ? nullptr : &ctx->tune, uniform_k, cells_h,
+                             p->verify_lanes);
         if (stats) {
             stats->verify_group = ctx->tune.last_g == VERIFY_BIDIR ? -2 : ctx->tune.last_g;
             stats->verify_words = ctx->tune.last_nwl;

@@ -12,6 +12,9 @@ struct mj_ctx {
     hipEvent_t ev[9] = {};
     KTimer kt;
     VerifyTuning tune;
+    // latency first (server workers): the batched verifier takes its fixed small-call
+    // configuration instead of timing the choices on a live call
+    bool no_tuning = false;
 };
 
 struct mj_pairs {

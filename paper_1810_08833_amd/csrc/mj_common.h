@@ -242,7 +242,8 @@ struct VerifyTuning {
 // produced by the library): the pass that finds the largest K is skipped.  With
 // cells_defer set (pinned host memory) the band-cell count is copied there
 // asynchronously and the call returns 0 without synchronising.  force_lanes != 0 fixes
-// the configuration (mj_params.verify_lanes) instead of the timed choice.
+// the configuration (mj_params.verify_lanes) instead of the timed choice; tune == nullptr
+// takes the fixed small-call configuration (no timing runs on the call).
 int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings &A,
                              const DevStrings &B, int kmode, uint8_t *flags, Workspace &ws,
                              hipStream_t s, uint64_t *host_scratch, KTimer *kt,

@@ -68,6 +68,7 @@ void mj_server::worker(int w) {
         (void)hipStreamDestroy(st);
         return;
     }
+    ctx->no_tuning = true;  // a timing pass inside a request would set the tail latency
     uint8_t *hchars = nullptr, *dchars = nullptr;
     int64_t *hoff = nullptr, *doff = nullptr;
     int32_t *hk = nullptr, *dk = nullptr;

@@ -954,9 +954,10 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
         if (nwl_for(nw, best_g) == 0)
             throw Error(MJ_ECAPACITY, "verify_lanes: the lanes of a pair cannot hold this band");
     }
-    if (best_g == 0 && n < TUNE_MIN_PAIRS) {
+    if (best_g == 0 && (n < TUNE_MIN_PAIRS || !tune)) {
         // a small call leaves most of the chip idle: the most lanes per pair (shortest
-        // path per pair); timing the choices would cost more than the work
+        // path per pair); timing the choices would cost more than the work.  Without a
+        // tuning table (latency-first callers) the same fixed choice.
         for (int g : G_CHOICES)
             if (g != BIDIR && nwl_for(nw, g) != 0 && (g == 1 || nwl_for(nw, g / 2) > 1)) best_g = g;
         best_blocks = 512;
