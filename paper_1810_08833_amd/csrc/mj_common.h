@@ -91,12 +91,15 @@ struct KTimer {
     hipEvent_t ev[POOL] = {};
     int used = 0;
     int slot_of[POOL / 2] = {};
+    int count_of[POOL / 2] = {};  // launches of the hot kernel inside each bracket
     void create();
     void destroy();
     void reset() { used = 0; }
     // returns a handle for end(); -1 when the pool is exhausted (launch not timed)
     int begin(int slot, hipStream_t s);
-    void end(int h, hipStream_t s);
+    // closes the bracket opened by begin(); `launches` is how many launches of the slot's
+    // kernel it holds (the anchor kernel runs once per repetition inside one bracket)
+    void end(int h, hipStream_t s, int launches = 1);
     void collect(float *ms, int32_t *launches);  // stream must be synchronised
 };
 

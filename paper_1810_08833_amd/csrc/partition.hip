@@ -989,7 +989,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
 #undef MJ_ANCHORS
         MJ_LAUNCH_CHECK();
     }
-    if (kt) kt->end(th, s);
+    if (kt) kt->end(th, s, reps);
     for (int rho = 0; rho < reps; rho++) {
         pre[rho] = ws.get_n<uint32_t>(ntiles + 1);
         exclusive_scan_u32(tcount[rho], pre[rho], ntiles, ws, s);

@@ -78,8 +78,10 @@ int KTimer::begin(int slot, hipStream_t s) {
     return h;
 }
 
-void KTimer::end(int h, hipStream_t s) {
-    if (h >= 0) MJ_HIP(hipEventRecord(ev[h + 1], s));
+void KTimer::end(int h, hipStream_t s, int launches) {
+    if (h < 0) return;
+    count_of[h / 2] = launches;
+    MJ_HIP(hipEventRecord(ev[h + 1], s));
 }
 
 void KTimer::collect(float *ms, int32_t *launches) {
@@ -91,7 +93,7 @@ void KTimer::collect(float *ms, int32_t *launches) {
         float t = 0.f;
         MJ_HIP(hipEventElapsedTime(&t, ev[h], ev[h + 1]));
         ms[slot_of[h / 2]] += t;
-        launches[slot_of[h / 2]] += 1;
+        launches[slot_of[h / 2]] += count_of[h / 2];
     }
 }
 
