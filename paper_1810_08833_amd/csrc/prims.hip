@@ -528,7 +528,9 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
 
 // Scatter of one tile: ranks among equal digits (wave peer groups and per-wave LDS
 // counters), the tile staged in LDS in digit order, then written out so that
-// consecutive lanes write consecutive addresses of a digit's run.
+// consecutive lanes write consecutive addresses of a digit's run.  Keys and payloads
+// take turns in one LDS buffer (38 KB per workgroup instead of 70 KB), so three
+// workgroups fit a CU where two did.
 template <bool HASV>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const uint64_t *__restrict__ vin, uint64_t *__restrict__ kout,
@@ -537,8 +539,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     __shared__ uint32_t wc[RS_WAVES][256];  // per-wave digit counts, then per-wave offsets
     __shared__ uint32_t gbase[256];         // global position minus tile-local position
     __shared__ uint32_t tmp[RS_WAVES];
-    __shared__ uint64_t sk[RS_TILE];
-    __shared__ uint64_t sv[HASV ? RS_TILE : 1];
+    __shared__ uint64_t sk[RS_TILE];  // the tile's keys in digit order, then its payloads
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int w = 0; w < RS_WAVES; w++) wc[w][threadIdx.x] = 0;
     __syncthreads();
@@ -579,22 +580,37 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
         }
     }
     __syncthreads();
+    uint32_t li_of[RS_ITEMS];
 #pragma unroll
     for (int c = 0; c < RS_ITEMS; c++) {
         const int64_t i = base + (int64_t)c * 64 + lane;
-        if (i < n) {
-            const uint32_t li = wc[wave][dr[c] >> 16] + (dr[c] & 0xFFFFu);
-            sk[li] = k[c];
-            if (HASV) sv[li] = v[HASV ? c : 0];
-        }
+        li_of[c] = wc[wave][dr[c] >> 16] + (dr[c] & 0xFFFFu);
+        if (i < n) sk[li_of[c]] = k[c];
     }
     __syncthreads();
     const int cnt = (int)min<int64_t>(RS_TILE, n - tile0);
-    for (int li = threadIdx.x; li < cnt; li += RS_THREADS) {
-        const uint64_t key = sk[li];
-        const uint32_t pos = gbase[(uint32_t)(key >> shift) & 255u] + (uint32_t)li;
-        kout[pos] = key;
-        if (HASV) vout[pos] = sv[li];
+    uint32_t pos[RS_ITEMS];
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; j++) {
+        const int li = threadIdx.x + j * RS_THREADS;
+        if (li < cnt) {
+            const uint64_t key = sk[li];
+            pos[j] = gbase[(uint32_t)(key >> shift) & 255u] + (uint32_t)li;
+            kout[pos[j]] = key;
+        }
+    }
+    if (!HASV) return;
+    __syncthreads();  // every key read from the buffer before payloads overwrite it
+#pragma unroll
+    for (int c = 0; c < RS_ITEMS; c++) {
+        const int64_t i = base + (int64_t)c * 64 + lane;
+        if (i < n) sk[li_of[c]] = v[HASV ? c : 0];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; j++) {
+        const int li = threadIdx.x + j * RS_THREADS;
+        if (li < cnt) vout[pos[j]] = sk[li];
     }
 }
 
