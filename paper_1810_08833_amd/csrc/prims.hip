@@ -529,10 +529,11 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
 // Scatter of one tile: ranks among equal digits (wave peer groups and per-wave LDS
 // counters), the tile staged in LDS in digit order, then written out so that
 // consecutive lanes write consecutive addresses of a digit's run.  Keys and payloads
-// take turns in one LDS buffer (38 KB per workgroup instead of 70 KB), so three
-// workgroups fit a CU where two did.
+// take turns in one LDS buffer (38 KB per workgroup instead of 70 KB), and the payloads
+// are loaded only once the keys are ranked, which keeps the kernel within 128 registers:
+// four workgroups fit a CU where two did.
 template <bool HASV>
-__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
+__global__ __launch_bounds__(RS_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const uint64_t *__restrict__ vin, uint64_t *__restrict__ kout,
     uint64_t *__restrict__ vout, int64_t n, int shift, int64_t ntiles,
     const uint32_t *__restrict__ off) {
@@ -554,7 +555,6 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
         const int64_t i = base + (int64_t)c * 64 + lane;
         const bool ok = i < n;
         k[c] = ok ? kin[i] : 0;
-        if (HASV) v[HASV ? c : 0] = ok ? vin[i] : 0;
         const uint32_t d = (uint32_t)(k[c] >> shift) & 255u;
         const uint64_t peers = digit_peers(d, __ballot(ok));
         const uint32_t before = wc[wave][d];
@@ -586,6 +586,13 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
         const int64_t i = base + (int64_t)c * 64 + lane;
         li_of[c] = wc[wave][dr[c] >> 16] + (dr[c] & 0xFFFFu);
         if (i < n) sk[li_of[c]] = k[c];
+    }
+    if (HASV) {  // payload loads in flight while the keys are written
+#pragma unroll
+        for (int c = 0; c < RS_ITEMS; c++) {
+            const int64_t i = base + (int64_t)c * 64 + lane;
+            v[HASV ? c : 0] = i < n ? vin[i] : 0;
+        }
     }
     __syncthreads();
     const int cnt = (int)min<int64_t>(RS_TILE, n - tile0);
