@@ -94,21 +94,22 @@ def file_sha(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel_src, config):
-    """HBM bytes per launch of the verifier configuration `config` ("<words, lanes,
-    planes>") from the committed rocprofv3 counter summary, if the counters were taken on
-    the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "verify_traffic_dna_long.json")
+def measured_traffic(workload, kernel, kernel_src):
+    """HBM bytes per launch of `kernel` (the label the roofline reports) on `workload`, from
+    the committed rocprofv3 counter summary, if the counters were taken on the current
+    source of that kernel; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_sha256") != file_sha(kernel_src):
+    name = os.path.basename(kernel_src)
+    if t.get("source_sha256", {}).get(name) != file_sha(kernel_src):
         return None
-    return t.get("bytes_per_launch_by_config", {}).get(config)
+    return t.get("bytes_per_launch", {}).get(kernel)
 
 
-def roofline(kernel, stats, kms, kln, bits, q):
+def roofline(kernel, stats, kms, kln, bits, q, workload):
     """Achieved algorithmic rate of `kernel` over the timed steps against its bound.
     Integer ALU kernels count 32-bit operations of the plain algorithm per unit of work:
       verify : 13 + 2b - 1 per 32 band cells (Myers' word update + b-plane match mask)
@@ -121,7 +122,7 @@ def roofline(kernel, stats, kms, kln, bits, q):
     secs = kms[kernel] * 1e-3
     n_launch = max(1, kln[kernel])
     tot = lambda f: float(np.sum([s[f] for s in stats]))
-    src = os.path.join(ROOT, "paper_1810_08833_amd", "csrc", "verify_lg.hip")
+    csrc = os.path.join(ROOT, "paper_1810_08833_amd", "csrc")
     r = {"kernel": kernel, "avg_launch_ms": kms[kernel] / n_launch, "traffic": None}
     if kernel == "verify":
         cells = tot("band_cells")
@@ -135,12 +136,14 @@ def roofline(kernel, stats, kms, kln, bits, q):
             vcfg = "<%d, %d, %d>" % (last["verify_words"], last["verify_group"], planes)
         r.update(kernel=kname + vcfg, bound="alu", unit="Tops/s",
                  achieved=ops / secs / 1e12, peak=INT_PEAK_TOPS,
-                 traffic=measured_traffic(src, vcfg), band_cells_per_s=cells / secs)
+                 band_cells_per_s=cells / secs)
+        r["traffic"] = measured_traffic(workload, r["kernel"], os.path.join(csrc, "verify_lg.hip"))
     elif kernel == "anchors":
         per_pos = 10 if q * bits <= 12 else 42
         r.update(kernel="k_anchor_tiles<%s>" % ("uint32_t" if per_pos == 10 else "uint64_t"),
                  bound="alu", unit="Tops/s", achieved=tot("positions") * per_pos / secs / 1e12,
                  peak=INT_PEAK_TOPS, ops_per_position=per_pos)
+        r["traffic"] = measured_traffic(workload, r["kernel"], os.path.join(csrc, "partition.hip"))
     elif kernel == "records":
         ops = tot("positions") * 17 + tot("records") * 23
         r.update(kernel="k_records", bound="alu", unit="Tops/s", achieved=ops / secs / 1e12,
@@ -420,7 +423,7 @@ def main():
 
     # roofline of the dominant kernel
     bits = int(np.ceil(np.log2(S.sigma)))
-    roof = roofline(dominant, stats, kms, kln, bits, cfg["q"])
+    roof = roofline(dominant, stats, kms, kln, bits, cfg["q"], args.workload)
 
     line = {
         "metric": METRIC,
