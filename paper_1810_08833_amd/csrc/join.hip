@@ -306,25 +306,52 @@ __global__ void k_unique_flags(const uint64_t *p, int64_t n, uint8_t *f) {
     for (; i < n; i += stride) f[i] = (i == 0 || p[i] != p[i - 1]) ? 1 : 0;
 }
 
+// (first << 32 | second) <-> (first << b | second), second < 2^b: the same order
+__global__ void k_pack_pairs(uint64_t *p, int64_t n, int b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = ((p[i] >> 32) << b) | (p[i] & 0xFFFFFFFFull);
+}
+
+__global__ void k_unpack_pairs(uint64_t *p, int64_t n, int b) {
+    const uint64_t lo = b >= 64 ? ~0ull : ((1ull << b) - 1);
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = ((p[i] >> b) << 32) | (p[i] & lo);
+}
+
 int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t n_first, int32_t n_second, Workspace &ws,
                     hipStream_t s, uint64_t *host_scratch, uint64_t **result) {
     if (n == 0) {
         *result = (uint64_t *)dev_alloc(16);
         return 0;
     }
-    // pair = first << 32 | second with first < n_first and second < n_second
-    auto field_mask = [](int32_t count) -> uint64_t {
-        const int b = std::min(32, ceil_log2((uint64_t)std::max(count, 1)));
-        return b >= 32 ? 0xFFFFFFFFull : ((1ull << b) - 1);
+    // pair = first << 32 | second with first < 2^bf and second < 2^bs.  The radix sort
+    // takes 8-bit digits; when the two fields waste digit bits (19 + 19 bits: 3 + 3
+    // passes) they are packed next to each other first (38 bits: 5 passes).
+    auto field_bits = [](int32_t count) {
+        return std::min(32, ceil_log2((uint64_t)std::max(count, 1)));
     };
-    radix_sort(pairs, nullptr, n, (field_mask(n_first) << 32) | field_mask(n_second), ws, s);
+    const int bf = field_bits(n_first), bs = field_bits(n_second);
+    const bool pack = (bf + bs + 7) / 8 < (bf + 7) / 8 + (bs + 7) / 8;
+    const unsigned pgrid = grid_for(n, 256, 16384);
+    if (pack) {
+        hipLaunchKernelGGL(k_pack_pairs, dim3(pgrid), dim3(256), 0, s, pairs, n, bs);
+        MJ_LAUNCH_CHECK();
+    }
+    auto ones = [](int b) { return b >= 64 ? ~0ull : ((1ull << b) - 1); };
+    radix_sort(pairs, nullptr, n, pack ? ones(bf + bs) : (ones(bf) << 32) | ones(bs), ws, s);
     uint8_t *f = ws.get_n<uint8_t>(n);
-    hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, pairs, n, f);
+    hipLaunchKernelGGL(k_unique_flags, dim3(pgrid), dim3(256), 0, s, pairs, n, f);
     MJ_LAUNCH_CHECK();
     int64_t *idx = ws.get_n<int64_t>(n + 1);
     int64_t u = compact_flags(f, n, idx, ws, s, host_scratch);
     uint64_t *res = (uint64_t *)dev_alloc((size_t)(u + 1) * 8);
     gather_u64(pairs, idx, res, u, s);
+    if (pack && u > 0) {
+        hipLaunchKernelGGL(k_unpack_pairs, dim3(grid_for(u, 256, 16384)), dim3(256), 0, s, res, u, bs);
+        MJ_LAUNCH_CHECK();
+    }
     *result = res;
     return u;
 }
