@@ -483,6 +483,15 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t valid) {
     return peers;
 }
 
+// The tile a workgroup takes.  Workgroups are dispatched round-robin over the 8 XCDs, each
+// with its own L2; giving XCD x the contiguous tiles [start(x), start(x) + count(x)) keeps
+// the digit-major counts and offsets of neighbouring tiles (one cache line holds 32) and
+// the seams between their output runs within one L2.  A bijection of [0, ntiles).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t ntiles) {
+    const int64_t per = ntiles >> 3, rem = ntiles & 7, x = b & 7;
+    return x * per + min(x, rem) + (b >> 3);
+}
+
 __device__ __forceinline__ uint64_t lanes_below() {
     const int lane = threadIdx.x & 63;
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -496,7 +505,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_tile_counts(const uint64_t *_
     h[threadIdx.x] = 0;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)wave * RS_WAVE_SPAN;
+    const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+    const int64_t base = tile * RS_TILE + (int64_t)wave * RS_WAVE_SPAN;
     const uint64_t below = lanes_below();
     for (int c = 0; c < RS_ITEMS; c++) {
         const int64_t i = base + (int64_t)c * 64 + lane;
@@ -506,7 +516,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_tile_counts(const uint64_t *_
         if (ok && (peers & below) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
-    cnt[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+    cnt[(int64_t)threadIdx.x * ntiles + tile] = h[threadIdx.x];
 }
 
 // Exclusive scan of one value per thread over a 256-thread block (v of thread t ->
@@ -544,7 +554,8 @@ __global__ __launch_bounds__(RS_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int w = 0; w < RS_WAVES; w++) wc[w][threadIdx.x] = 0;
     __syncthreads();
-    const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+    const int64_t tile0 = tile * RS_TILE;
     const int64_t base = tile0 + (int64_t)wave * RS_WAVE_SPAN;
     const uint64_t below = lanes_below();
     uint64_t k[RS_ITEMS];
@@ -572,7 +583,7 @@ __global__ __launch_bounds__(RS_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             tot += cw[w];
         }
         const uint32_t tb = block_exclusive_scan_256(tot, tmp);  // tile-local start of digit d
-        gbase[d] = off[(int64_t)d * ntiles + blockIdx.x] - tb;  // modulo 2^32
+        gbase[d] = off[(int64_t)d * ntiles + tile] - tb;  // modulo 2^32
         uint32_t acc = tb;
         for (int w = 0; w < RS_WAVES; w++) {
             wc[w][d] = acc;
