@@ -764,16 +764,36 @@ __global__ void k_sort_runs(uint64_t *__restrict__ key, uint64_t *__restrict__ v
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nr;
          r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t rs = sr[2 * r], re = sr[2 * r + 1];
-        for (int64_t j = rs + 1; j < re; j++) {
-            const uint64_t k = key[j], v = val[j];
-            int64_t p = j;
-            while (p > rs && key[p - 1] > k) {
-                key[p] = key[p - 1];
-                val[p] = val[p - 1];
-                p--;
+        // Mixed runs are mostly one frequent key and a rare colliding one, so nearly every
+        // record is already in place.  The largest key of the sorted prefix stays in a
+        // register and keys are loaded RS_FIX at a time (all in flight together): an
+        // insertion at position j writes only positions <= j, so the keys loaded beyond j
+        // are still current.
+        constexpr int RS_FIX = 16;
+        uint64_t top = key[rs];
+        for (int64_t j0 = rs + 1; j0 < re; j0 += RS_FIX) {
+            const int cnt = (int)min<int64_t>(RS_FIX, re - j0);
+            uint64_t kc[RS_FIX];
+#pragma unroll
+            for (int c = 0; c < RS_FIX; c++) kc[c] = c < cnt ? key[j0 + c] : 0;
+#pragma unroll
+            for (int c = 0; c < RS_FIX; c++) {
+                if (c >= cnt) break;
+                const uint64_t k = kc[c];
+                if (k >= top) {  // in place (equal keys keep their order)
+                    top = k;
+                    continue;
+                }
+                int64_t p = j0 + c;
+                const uint64_t v = val[p];
+                while (p > rs && key[p - 1] > k) {
+                    key[p] = key[p - 1];
+                    val[p] = val[p - 1];
+                    p--;
+                }
+                key[p] = k;
+                val[p] = v;
             }
-            key[p] = k;
-            val[p] = v;
         }
     }
 }
