@@ -79,10 +79,18 @@ int64_t orc_radius(int64_t m, int q, int64_t T) {
     return r < 1 ? 1 : r;
 }
 
-/* Find-Anchor (Alg. 2).  Anchors are the first position, every q-gram start p in
- * [r, npos-1-r] whose hash is strictly smaller than every other hash within distance
- * r, and the end sentinel m (so that partitions tile the whole string, Table 4).
- * Writes the anchors in increasing order; returns their count. */
+/* Find-Anchor (Alg. 2), from the definition of an anchor: a q-gram start p is an
+ * anchor when its hash is strictly smaller than each of the other 2r hashes within
+ * distance r (Sec. 2.1: the strict local minimum; equal q-grams suppress each other),
+ * among the p whose window [p-r, p+r] lies inside the hash array.  The first position
+ * and the end sentinel m are anchors too, so that the partitions tile the string
+ * (Table 4).  Writes the anchors in increasing order; returns their count. */
+static uint64_t min_hash(const uint64_t *h, int64_t lo, int64_t hi) {
+    uint64_t v = UINT64_MAX;
+    for (int64_t j = lo; j <= hi; j++) v = h[j] < v ? h[j] : v;
+    return v;
+}
+
 int64_t orc_find_anchors(const uint8_t *s, int64_t m, int q, int b, int64_t T,
                          uint64_t seed, const uint64_t *table, int64_t *out) {
     int64_t na = 0;
@@ -93,13 +101,10 @@ int64_t orc_find_anchors(const uint8_t *s, int64_t m, int q, int b, int64_t T,
         uint64_t *h = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)npos);
         orc_qgram_hashes(s, m, q, b, seed, table, h);
         int64_t r = orc_radius(m, q, T);
-        for (int64_t i = r; i <= npos - 1 - r; i++) {
-            int label = 1;
-            for (int64_t j = i - r; j <= i + r; j++) {
-                if (j == i) continue;
-                if (h[i] >= h[j]) { label = 0; break; }
-            }
-            if (label) out[na++] = i;
+        for (int64_t p = r; p + r < npos; p++) {
+            /* strictly below the smallest hash on each side of p */
+            if (h[p] < min_hash(h, p - r, p - 1) && h[p] < min_hash(h, p + 1, p + r))
+                out[na++] = p;
         }
         free(h);
     }
@@ -305,46 +310,14 @@ int orc_ed_within(const uint8_t *x, int64_t m, const uint8_t *y, int64_t n, int6
 }
 
 /* ------------------------------------------------------------------------- */
-/* MinJoin (Alg. 3), literally: strings in (length, lexicographic) order; for each
- * partition, probe the bucket of its key, apply the length filter and the position
- * filter, evict entries that fail the length filter (only when that is safe, see
- * below), then insert; dedup the candidates; verify each with the banded test. */
-
-typedef struct { int32_t j, pos, len; } orc_entry;
-typedef struct { orc_entry *e; int64_t n, cap; } orc_bucket;
-typedef struct { uint64_t *keys; orc_bucket *b; uint8_t *used; uint64_t mask; } orc_table;
-
-static orc_bucket *table_get(orc_table *t, uint64_t key, int create) {
-    uint64_t h = orc_mix64(key) & t->mask;
-    while (t->used[h]) {
-        if (t->keys[h] == key) return &t->b[h];
-        h = (h + 1) & t->mask;
-    }
-    if (!create) return NULL;
-    t->used[h] = 1;
-    t->keys[h] = key;
-    t->b[h].e = NULL; t->b[h].n = 0; t->b[h].cap = 0;
-    return &t->b[h];
-}
-
-static void bucket_push(orc_bucket *b, orc_entry e) {
-    if (b->n == b->cap) {
-        b->cap = b->cap ? 2 * b->cap : 4;
-        b->e = (orc_entry *)realloc(b->e, sizeof(orc_entry) * (size_t)b->cap);
-    }
-    b->e[b->n++] = e;
-}
-
-static const uint8_t *g_sort_chars;
-static const int64_t *g_sort_off;
-static int cmp_len_lex(const void *a, const void *b) {
-    int32_t i = *(const int32_t *)a, j = *(const int32_t *)b;
-    int64_t mi = g_sort_off[i + 1] - g_sort_off[i], mj = g_sort_off[j + 1] - g_sort_off[j];
-    if (mi != mj) return mi < mj ? -1 : 1;
-    int c = memcmp(g_sort_chars + g_sort_off[i], g_sort_chars + g_sort_off[j], (size_t)mi);
-    if (c) return c;
-    return i < j ? -1 : (i > j);
-}
+/* MinJoin (Alg. 3) from the definition of its candidate set: two strings are a
+ * candidate when they hold partitions in the same bucket (equal key f: a common
+ * partition, Sec. 2.1) whose pair passes the length filter and the position filter
+ * (Alg. 3; Sec. 3) under the pair's threshold.  Alg. 3 walks the strings by length and
+ * evicts bucket entries failing the length filter; eviction drops only entries that
+ * the filter would reject for every later string, so testing every pair of records of
+ * a bucket gives the same set.  The candidates are deduplicated and each is verified
+ * with the banded test. */
 
 static int cmp_u64(const void *a, const void *b) {
     uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
@@ -371,8 +344,17 @@ static int64_t dedup_sorted(uint64_t *a, int64_t n) {
     return w;
 }
 
-/* Verification of a deduplicated, sorted candidate list; keeps accepted pairs in
- * order.  kfun: 0 -> pair threshold max(K_i, K_j); used by join.  Returns count. */
+/* Records ordered by bucket key (ties by string, position, repetition). */
+static int cmp_record_key(const void *a, const void *b) {
+    const orc_record *x = (const orc_record *)a, *y = (const orc_record *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    if (x->sid != y->sid) return x->sid < y->sid ? -1 : 1;
+    if (x->pos != y->pos) return x->pos < y->pos ? -1 : 1;
+    return x->rep < y->rep ? -1 : (x->rep > y->rep);
+}
+
+/* Verification of a deduplicated, sorted candidate list with pair threshold
+ * max(K_i, K_j); keeps accepted pairs in order.  Returns their count. */
 static int64_t verify_pairs(const uint8_t *chars, const int64_t *off, const int64_t *kq,
                             uint64_t *pairs, int64_t np, int nt) {
     uint8_t *ok = (uint8_t *)malloc((size_t)np + 1);
@@ -395,77 +377,42 @@ static int join_impl(const uint8_t *chars, const int64_t *offsets, int32_t n, co
                      uint64_t **cand_out, int64_t *ncand, uint64_t **pairs_out, int64_t *npairs,
                      orc_stats *stats, int do_verify) {
     int nt = p->threads > 0 ? p->threads : 1;
-    /* S0: per-string K and the sorted order */
     int64_t *K = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
     for (int32_t i = 0; i < n; i++) K[i] = string_k(p, i);
-    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
-    for (int32_t i = 0; i < n; i++) order[i] = i;
-    g_sort_chars = chars; g_sort_off = offsets;
-    qsort(order, (size_t)n, sizeof(int32_t), cmp_len_lex);
-    /* Eviction is safe when a later (longer) string can never pass the length filter
-     * against an entry that an earlier one evicted: with pair threshold max(K_i,K_j)
-     * this holds when K and m-K are both non-decreasing along the sorted order. */
-    int evict = 1;
-    for (int32_t t = 1; t < n; t++) {
-        int32_t a = order[t - 1], c = order[t];
-        int64_t ma = offsets[a + 1] - offsets[a], mc = offsets[c + 1] - offsets[c];
-        if (K[c] < K[a] || (mc - K[c]) < (ma - K[a])) { evict = 0; break; }
-    }
-    /* S1: partitions of every string */
+    /* the partitions of every string (and repetition), grouped into buckets by key */
     orc_record *rec = NULL;
     int64_t R = orc_partition_all(chars, offsets, n, p, &rec);
-    int64_t *rstart = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
-    for (int64_t t = 0; t < R; t++) rstart[rec[t].sid + 1]++;
-    for (int32_t i = 0; i < n; i++) rstart[i + 1] += rstart[i];
-    /* S2: hash join with filters */
-    uint64_t cap = 16;
-    while (cap < (uint64_t)(2 * R + 16)) cap <<= 1;
-    orc_table tab;
-    tab.mask = cap - 1;
-    tab.keys = (uint64_t *)malloc(sizeof(uint64_t) * cap);
-    tab.b = (orc_bucket *)malloc(sizeof(orc_bucket) * cap);
-    tab.used = (uint8_t *)calloc(cap, 1);
+    qsort(rec, (size_t)R, sizeof(orc_record), cmp_record_key);
+    /* every pair of records of a bucket: distinct strings passing both filters */
     int64_t cc = 0, ccap = 1024, tests = 0;
     uint64_t *cand = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)ccap);
-    for (int32_t t = 0; t < n; t++) {
-        int32_t i = order[t];
-        int64_t mi = offsets[i + 1] - offsets[i];
-        for (int64_t r = rstart[i]; r < rstart[i + 1]; r++) {
-            orc_bucket *bk = table_get(&tab, rec[r].key, 1);
-            int64_t keep = 0;
-            for (int64_t e = 0; e < bk->n; e++) {
-                orc_entry en = bk->e[e];
-                int64_t mj = offsets[en.j + 1] - offsets[en.j];
-                int64_t Kij = K[i] > K[en.j] ? K[i] : K[en.j];
+    for (int64_t g0 = 0, g1; g0 < R; g0 = g1) {
+        for (g1 = g0 + 1; g1 < R && rec[g1].key == rec[g0].key; g1++) {}
+        for (int64_t a = g0; a < g1; a++) {
+            for (int64_t b = a + 1; b < g1; b++) {
+                int32_t i = rec[a].sid, j = rec[b].sid;
+                int64_t mi = offsets[i + 1] - offsets[i], mj = offsets[j + 1] - offsets[j];
+                int64_t Kij = K[i] > K[j] ? K[i] : K[j];
                 tests++;
-                if (pass_length(mi, mj, Kij)) {
-                    if (pass_position(rec[r].pos, mi, en.pos, mj, Kij) && en.j != i) {
-                        if (cc == ccap) { ccap *= 2; cand = (uint64_t *)realloc(cand, sizeof(uint64_t) * (size_t)ccap); }
-                        uint64_t lo = (uint64_t)(en.j < i ? en.j : i), hi = (uint64_t)(en.j < i ? i : en.j);
-                        cand[cc++] = (lo << 32) | hi;
-                    }
-                    bk->e[keep++] = en;
-                } else if (!evict) {
-                    bk->e[keep++] = en;
-                }
+                if (i == j) continue;  /* a string repeating a partition meets itself */
+                if (!pass_length(mi, mj, Kij)) continue;
+                if (!pass_position(rec[a].pos, mi, rec[b].pos, mj, Kij)) continue;
+                if (cc == ccap) { ccap *= 2; cand = (uint64_t *)realloc(cand, sizeof(uint64_t) * (size_t)ccap); }
+                uint64_t lo = (uint64_t)(i < j ? i : j), hi = (uint64_t)(i < j ? j : i);
+                cand[cc++] = (lo << 32) | hi;
             }
-            bk->n = keep;
-            orc_entry ne = { i, rec[r].pos, rec[r].len };
-            bucket_push(bk, ne);
         }
     }
-    for (uint64_t h = 0; h < cap; h++) if (tab.used[h]) free(tab.b[h].e);
-    free(tab.keys); free(tab.b); free(tab.used);
-    /* dedup (the line removing duplicate pairs) */
+    /* dedup (Alg. 3 removes duplicate pairs) */
     cc = dedup_sorted(cand, cc);
     uint64_t *c2 = (uint64_t *)malloc(sizeof(uint64_t) * ((size_t)cc + 1));
     memcpy(c2, cand, sizeof(uint64_t) * (size_t)cc);
-    /* S3: verification */
+    /* verification */
     int64_t no = do_verify ? verify_pairs(chars, offsets, K, cand, cc, nt) : 0;
     if (stats) { stats->records = R; stats->candidates = cc; stats->output = no; stats->pair_tests = tests; }
     *cand_out = c2; *ncand = cc;
     *pairs_out = cand; *npairs = no;
-    free(rec); free(rstart); free(order); free(K);
+    free(rec); free(K);
     return 0;
 }
 
@@ -486,13 +433,6 @@ int orc_join_candidates(const uint8_t *chars, const int64_t *offsets, int32_t n,
  * query is partitioned with the same q, seed and T rule, probes the index, applies the
  * filters with its own K, dedups and verifies with its own K.  Output: sorted
  * (query id << 32 | string id). */
-static int cmp_record_key(const void *a, const void *b) {
-    const orc_record *x = (const orc_record *)a, *y = (const orc_record *)b;
-    if (x->key != y->key) return x->key < y->key ? -1 : 1;
-    if (x->sid != y->sid) return x->sid < y->sid ? -1 : 1;
-    if (x->pos != y->pos) return x->pos < y->pos ? -1 : 1;
-    return x->rep < y->rep ? -1 : (x->rep > y->rep);
-}
 
 /* Search (the query side of Alg. 3 against a dictionary holding every index record):
  * the dictionary is the index records sorted by key, probed by binary search. */

@@ -359,3 +359,155 @@ def test_deterministic_for_a_fixed_seed():
     a = oracle.join(S.chars, S.offsets, oracle.make_params(4, 4, k=60, t_div=2, seed=1))
     b = oracle.join(S.chars, S.offsets, oracle.make_params(4, 4, k=60, t_div=2, seed=1, threads=1))
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ---------------------------------------------------------------- pins added for the
+# repetition schedule, per-query thresholds and larger alphabets
+@pytest.mark.parametrize("sigma", [25, 37])
+def test_pi_is_injective_for_larger_alphabets(sigma):
+    # b = ceil(log2 sigma) = 5 or 6 bits per symbol: every one of the sigma^3 3-grams gets
+    # its own hash (a too-narrow packing would make codes >= 2^(b-1) collide)
+    grams = np.array(list(itertools.product(range(sigma), repeat=3)), dtype=np.uint8)
+    h = oracle.qgram_hashes(grams.reshape(-1), 3, sigma, seed=0)[::3]
+    assert len(h) == sigma ** 3
+    assert len(np.unique(h)) == sigma ** 3
+
+
+def _content_partitions(S, q, T_of, reps, seed=0):
+    """Each repetition rho cuts every string at the anchors that Find-Anchor gives with
+    seed + rho (Sec. 3, parallel repetition); a partition is (content bytes, sid, pos)."""
+    parts = []
+    for i in range(S.n):
+        s = S.get(i)
+        for rho in range(reps):
+            a = oracle.find_anchors(s, q, S.sigma, T_of(i), seed=seed + rho)
+            parts += [(s[a[k]:a[k + 1]].tobytes(), i, int(a[k])) for k in range(len(a) - 1)]
+    return parts
+
+
+def _content_candidates(S, parts, K_of):
+    """Candidates by brute force on partition content (not on the bucket key): distinct
+    strings holding a partition with the same symbols that pass both filters."""
+    lens = S.lengths()
+    by = {}
+    for c, i, p in parts:
+        by.setdefault(c, []).append((i, p))
+    out = set()
+    for group in by.values():
+        for a in range(len(group)):
+            for b in range(a + 1, len(group)):
+                (i, pi), (j, pj) = group[a], group[b]
+                if i == j:
+                    continue
+                mi, mj = int(lens[i]), int(lens[j])
+                K = max(K_of(i), K_of(j))
+                if abs(mi - mj) <= K and abs(pi - pj) + abs((mi - pi) - (mj - pj)) <= K:
+                    out.add((min(i, j) << 32) | max(i, j))
+    return out
+
+
+def test_repetition_rho_uses_seed_plus_rho():
+    # the records of repetition rho are exactly the partitions at Find-Anchor's anchors
+    # for seed + rho, with the bucket key of the base seed
+    S = dg.dna_small(seed=61, n_clusters=5, copies=4)
+    K, t_div, reps, seed = 60, 3, 3, 11
+    p = oracle.make_params(4, 4, k=K, t_div=t_div, reps=reps, seed=seed)
+    rec = oracle.partition_all(S.chars, S.offsets, p)
+    T = oracle.target_partitions(K, t_div)
+    for i in range(S.n):
+        s = S.get(i)
+        for rho in range(reps):
+            mine = np.sort(rec[(rec["sid"] == i) & (rec["rep"] == rho)], order="pos")
+            a = oracle.find_anchors(s, 4, 4, T, seed=seed + rho)
+            assert mine["pos"].tolist() == a[:-1].tolist()
+            assert mine["len"].tolist() == np.diff(a).tolist()
+            keys = [oracle.partition_key(s[a[k]:a[k + 1]], seed) for k in range(len(a) - 1)]
+            assert mine["key"].tolist() == keys
+        # the repetitions really cut differently
+        a0 = oracle.find_anchors(s, 4, 4, T, seed=seed)
+        a1 = oracle.find_anchors(s, 4, 4, T, seed=seed + 1)
+        assert not np.array_equal(a0, a1)
+
+
+@pytest.mark.parametrize("reps", [1, 2, 3])
+def test_join_with_repetitions_equals_content_brute_force(reps):
+    # the union of all repetitions' partitions is joined: partitions of different
+    # repetitions with the same content share a bucket
+    S = dg.dna_small(seed=62, n_clusters=6, copies=4)
+    K, t_div = 60, 3
+    p = oracle.make_params(4, 4, k=K, t_div=t_div, reps=reps)
+    cand, _, _ = oracle.join(S.chars, S.offsets, p, verify=False)
+    T = oracle.target_partitions(K, t_div)
+    want = _content_candidates(S, _content_partitions(S, 4, lambda i: T, reps), lambda i: K)
+    assert set(cand.tolist()) == want
+
+
+def test_second_repetition_finds_a_pair_the_first_misses():
+    # at T = K/4 on these copies one repetition misses a true pair that a second finds
+    S = dg.dna_small(seed=57, n_clusters=10, copies=4)
+    c1, o1, _ = oracle.join(S.chars, S.offsets, oracle.make_params(4, 4, k=60, t_div=4, reps=1))
+    c2, o2, _ = oracle.join(S.chars, S.offsets, oracle.make_params(4, 4, k=60, t_div=4, reps=2))
+    new = set(o2.tolist()) - set(o1.tolist())
+    assert new and set(o1.tolist()) < set(o2.tolist())
+    for v in new:
+        assert oracle.edit_distance(S.get(v >> 32), S.get(v & 0xFFFFFFFF)) <= 60
+
+
+def _split_search_fixture(seed=43):
+    S = dg.dna_small(seed=seed, n_clusters=8, copies=4)
+    ids = np.arange(S.n)
+    return S.subset(ids[ids % 4 != 0]), S.subset(ids[ids % 4 == 0])
+
+
+def test_search_per_query_threshold_matches_definition():
+    # search(index, queries, K): query q partitions with the T rule at its own K_q, and
+    # both the filters and the verification use K_q (not max(K_q, K_s)).  The index
+    # strings hold K = 140 for their T rule, above every query's K, so a threshold of
+    # max(K_q, K_s) would accept more pairs.
+    I, Q = _split_search_fixture(47)
+    rng = np.random.default_rng(3)
+    kq = rng.integers(40, 100, Q.n).astype(np.int32)
+    KI, t_div = 140, 1
+    ip = oracle.make_params(4, 4, k=KI, t_div=t_div)
+    qp = oracle.make_params(4, 4, k_per_string=kq, t_div=t_div)
+    cand, got = oracle.search(I.chars, I.offsets, ip, Q.chars, Q.offsets, qp)
+    TI = oracle.target_partitions(KI, t_div)
+    iparts = _content_partitions(I, 4, lambda i: TI, 1)
+    by = {}
+    for c, s, p in iparts:
+        by.setdefault(c, []).append((s, p))
+    want_c, want_o, wider = set(), set(), 0
+    for qi in range(Q.n):
+        x, mq, K = Q.get(qi), Q.lengths()[qi], int(kq[qi])
+        a = oracle.find_anchors(x, 4, 4, oracle.target_partitions(K, t_div))
+        for k in range(len(a) - 1):
+            pq = int(a[k])
+            for s, ps in by.get(x[a[k]:a[k + 1]].tobytes(), []):
+                ms = int(I.lengths()[s])
+                if abs(mq - ms) <= K and abs(pq - ps) + abs((mq - pq) - (ms - ps)) <= K:
+                    want_c.add((qi << 32) | s)
+    for v in want_c:
+        d = oracle.edit_distance(Q.get(v >> 32), I.get(v & 0xFFFFFFFF))
+        if d <= int(kq[v >> 32]):
+            want_o.add(v)
+        elif d <= KI:
+            wider += 1
+    assert set(cand.tolist()) == want_c
+    assert set(got.tolist()) == want_o
+    assert want_o and wider > 0  # the case distinguishes K_q from max(K_q, K_s)
+
+
+def test_search_per_query_threshold_is_the_union_of_single_query_searches():
+    I, Q = _split_search_fixture(44)
+    rng = np.random.default_rng(4)
+    kq = rng.integers(30, 80, Q.n).astype(np.int32)
+    ip = oracle.make_params(4, 4, k=70, t_div=1)
+    _, got = oracle.search(I.chars, I.offsets, ip, Q.chars, Q.offsets,
+                           oracle.make_params(4, 4, k_per_string=kq, t_div=1))
+    want = set()
+    for qi in range(Q.n):
+        one = dg.from_list([Q.get(qi)], 4)
+        _, o = oracle.search(I.chars, I.offsets, ip, one.chars, one.offsets,
+                             oracle.make_params(4, 4, k=int(kq[qi]), t_div=1))
+        want |= {(qi << 32) | (int(v) & 0xFFFFFFFF) for v in o.tolist()}
+    assert set(got.tolist()) == want and want
