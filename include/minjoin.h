@@ -139,7 +139,8 @@ const char *mj_version(void);
 
 /* Stream-ordered; returns once the pair count is known.  *out is library-owned until
  * mj_pairs_free.  stats may be NULL.  EINVAL on bad arguments (q < 1, q*b > 64,
- * t_div < 1, K < -1, sigma outside 2..256, offsets decreasing); ECAPACITY when a
+ * t_div < 1, K < -1, sigma outside 2..256, offsets decreasing, a symbol code >= sigma,
+ * verifier or verify_lanes not one of the listed values); ECAPACITY when a
  * documented limit is exceeded: record-pair tests of one call above 2^31, a radius r
  * above 1920 on a string long enough to have interior positions, or a candidate whose
  * threshold K is above 2047; ENOMEM when device memory runs out. */
@@ -172,8 +173,10 @@ mj_status mj_index_build(mj_ctx *ctx, const mj_strings *strings, const mj_params
 void mj_index_free(mj_index *index);
 int64_t mj_index_records(const mj_index *index);
 
-/* queries: borrowed; qparams->k / k_per_string give each query's K (q, seed, T rule
- * and reps are taken from the index). */
+/* queries: borrowed; qparams->k / k_per_string give each query's K, qparams->verifier and
+ * verify_lanes choose the verifier as for mj_join (EINVAL on other values); q, seed, the
+ * T rule and reps are taken from the index, which keeps its own copy of an injected Pi
+ * table. */
 mj_status mj_search(mj_ctx *ctx, const mj_index *index, const mj_strings *queries,
                     const mj_params *qparams, void *stream, mj_pairs **out,
                     mj_stats *stats);
@@ -211,7 +214,8 @@ typedef struct {
 mj_status mj_server_create(int device, const mj_index *index, const mj_server_config *cfg,
                            mj_server **out);
 /* Copies the query (host symbol codes, length len >= 0) and queues it with threshold k
- * (0 <= k <= 2047).  EINVAL if the request alone exceeds the memory budget. */
+ * (0 <= k <= 2047).  EINVAL if a code is not below the index's sigma or if the request
+ * alone exceeds the memory budget. */
 mj_status mj_server_submit(mj_server *srv, const uint8_t *codes, int32_t len, int32_t k,
                            uint64_t tag);
 /* Waits up to timeout_ms (0: no wait; < 0: until one reply) for completed requests and

@@ -338,10 +338,11 @@ class Index:
         return load_library().mj_index_records(self.handle)
 
     def search(self, queries: DeviceStrings, k: int = -1, k_per_query=None, stream=None,
-               verifier: int = VERIFY_BATCHED):
+               verifier: int = VERIFY_BATCHED, verify_lanes: int = 0):
         """(query id << 32 | string id) pairs with ED <= K_query; returns (pairs, stats)."""
         L = load_library()
-        qp = Params(q=1, k=k, k_per_string=k_per_query, verifier=verifier)
+        qp = Params(q=1, k=k, k_per_string=k_per_query, verifier=verifier,
+                    verify_lanes=verify_lanes)
         s, p, st, h = queries.struct(), qp.struct(), MjStats(), ctypes.c_void_p()
         _check(L.mj_search(self.ctx.handle, self.handle, ctypes.byref(s), ctypes.byref(p),
                            _stream_ptr(stream), ctypes.byref(h), ctypes.byref(st)))

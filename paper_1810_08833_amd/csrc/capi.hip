@@ -72,6 +72,14 @@ static int ceil_log2(uint64_t v) {
     return b;
 }
 
+static void check_verifier(const mj_params *p) {
+    if (p->verifier != MJ_VERIFY_BATCHED && p->verifier != MJ_VERIFY_PLAIN)
+        throw Error(MJ_EINVAL, "verifier must be MJ_VERIFY_BATCHED or MJ_VERIFY_PLAIN");
+    if (p->verify_lanes != 0 && p->verify_lanes != 1 && p->verify_lanes != 2 &&
+        p->verify_lanes != 4 && p->verify_lanes != 8 && p->verify_lanes != -2)
+        throw Error(MJ_EINVAL, "verify_lanes must be 0, 1, 2, 4, 8 or -2");
+}
+
 static void check_params(const mj_params *p, int sigma, bool need_k) {
     if (!p) throw Error(MJ_EINVAL, "params is NULL");
     if (sigma < 2 || sigma > 256) throw Error(MJ_EINVAL, "sigma must be in 2..256");
@@ -86,11 +94,7 @@ static void check_params(const mj_params *p, int sigma, bool need_k) {
         if (p->k > 0x3FFFFFFF) throw Error(MJ_EINVAL, "k too large");
     }
     if (p->pi_table && (int64_t)p->q * b > 24) throw Error(MJ_EINVAL, "pi_table needs q*b <= 24");
-    if (p->verifier != MJ_VERIFY_BATCHED && p->verifier != MJ_VERIFY_PLAIN)
-        throw Error(MJ_EINVAL, "verifier must be MJ_VERIFY_BATCHED or MJ_VERIFY_PLAIN");
-    if (p->verify_lanes != 0 && p->verify_lanes != 1 && p->verify_lanes != 2 &&
-        p->verify_lanes != 4 && p->verify_lanes != 8 && p->verify_lanes != -2)
-        throw Error(MJ_EINVAL, "verify_lanes must be 0, 1, 2, 4, 8 or -2");
+    check_verifier(p);
 }
 
 static void check_strings(const mj_strings *s) {
@@ -182,7 +186,7 @@ static void check_flags(const uint8_t *f, int64_t n, Workspace &ws, hipStream_t 
 static void run_verify(mj_ctx *ctx, const uint64_t *pairs, int64_t n, const DevStrings &A,
                        const DevStrings &B, int kmode, int64_t uniform_k, const mj_params *p,
                        uint8_t *flags, hipStream_t s, mj_stats *stats, uint64_t *cells_h) {
-    *cells_h = 0;
+    cells_h[0] = cells_h[1] = 0;
     if (p->verifier == MJ_VERIFY_BATCHED) {
         verify_pairs_batched(pairs, n, A, B, kmode, flags, ctx->ws, s, ctx->pinned, &ctx->kt,
                              ctx->no_tuning ? nullptr : &ctx->tune, uniform_k, cells_h,
@@ -199,8 +203,20 @@ static void run_verify(mj_ctx *ctx, const uint64_t *pairs, int64_t n, const DevS
     if (uniform_k < 0) check_flags(flags, n, ctx->ws, s, ctx->pinned);
 }
 
-// last word of the pinned scratch: the deferred band-cell count
-static uint64_t *cells_slot(mj_ctx *ctx) { return ctx->pinned + HOST_SCRATCH_BYTES / 8 - 1; }
+// last two words of the pinned scratch: the deferred band-cell count and the batched
+// verifier's undersized-window error word
+static uint64_t *cells_slot(mj_ctx *ctx) { return ctx->pinned + HOST_SCRATCH_BYTES / 8 - 2; }
+
+// After the stream has synchronised: the deferred band-cell count; fails (freeing `out`)
+// when some pair's band did not fit the verifier's window.
+static int64_t take_cells(mj_ctx *ctx, mj_pairs *out) {
+    const uint64_t *c = cells_slot(ctx);
+    if (c[1]) {
+        mj_pairs_free(out);
+        throw Error(MJ_ECAPACITY, "a pair's band exceeds the verifier window");
+    }
+    return (int64_t)c[0];
+}
 
 struct StageTimer {
     mj_ctx *ctx;
@@ -240,7 +256,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     DevStrings d = view(strings, s, ctx->pinned, false);
     PartitionParams pp = to_pp(params, d.bits);
     int32_t halo = prepare_strings(d, pp, ws, s, ctx->pinned);
-    if (upto >= 2) pack_planes(d, verify_planes(d.bits), ws, s);
+    pack_planes(d, verify_planes(d.bits), ws, s);  // also checks the symbol codes
     tm.mark();  // 0 setup
     RecBuf rb;
     rb.ws = &ws;  // workspace memory: cached across calls, returned when the call ends
@@ -281,7 +297,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     run_verify(ctx, uniq, C, d, d, 0, params->k, params, flags, s, stats, cells_slot(ctx));
     tm.mark();  // 5 verify
     mj_pairs *out = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);  // synchronises when C > 0
-    const int64_t cells = (int64_t)*cells_slot(ctx);
+    const int64_t cells = take_cells(ctx, out);
     tm.mark();  // 6 output
     if (stats) {
         stats->output = out->n;
@@ -328,6 +344,7 @@ extern "C" mj_status mj_partition(mj_ctx *ctx, const mj_strings *strings, const 
     DevStrings d = view(strings, s, ctx->pinned);
     PartitionParams pp = to_pp(params, d.bits);
     int32_t halo = prepare_strings(d, pp, ws, s, ctx->pinned);
+    pack_planes(d, verify_planes(d.bits), ws, s);  // checks the symbol codes
     mj_records *r = new mj_records();
     r->rb.with_len = true;
     try {
@@ -358,6 +375,7 @@ extern "C" mj_status mj_verify(mj_ctx *ctx, const mj_strings *strings, const mj_
     PartitionParams pp = to_pp(params, d.bits);
     (void)prepare_strings(d, pp, ws, s, ctx->pinned);
     pack_planes(d, verify_planes(d.bits), ws, s);
+    check_symbols(d, s, ctx->pinned);
     if (params->verifier == MJ_VERIFY_BATCHED) {
         verify_pairs_batched(pairs, n, d, d, 0, flags, ws, s, ctx->pinned, nullptr, &ctx->tune, -1,
                              nullptr, params->verify_lanes);
@@ -413,6 +431,14 @@ extern "C" mj_status mj_index_build(mj_ctx *ctx, const mj_strings *strings, cons
         MJ_HIP(hipMemcpyAsync(ix->planes, di.planes, (size_t)ix->np * di.plane_words * 4,
                               hipMemcpyDeviceToDevice, s));
         sorted_records(di, pk, halo, ix->rec, ws, s, ctx->pinned);
+        if (pp.pi_table) {
+            // searches partition their queries with this table long after the caller's
+            // copy may be gone: the index keeps its own
+            const size_t tb = (size_t)8 << (pp.q * d.bits);
+            ix->pi_table = (uint64_t *)dev_alloc(tb);
+            MJ_HIP(hipMemcpyAsync(ix->pi_table, pp.pi_table, tb, hipMemcpyDeviceToDevice, s));
+            pp.pi_table = ix->pi_table;
+        }
         MJ_HIP(hipStreamSynchronize(s));
         ix->pp = pp;
     } catch (...) {
@@ -432,6 +458,7 @@ extern "C" void mj_index_free(mj_index *ix) {
     dev_free(ix->len);
     dev_free(ix->kk);
     dev_free(ix->planes);
+    dev_free(ix->pi_table);
     ix->rec.release();
     delete ix;
 }
@@ -450,6 +477,7 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
     if (qparams->k < -1 || (qparams->k == -1 && !qparams->k_per_string))
         throw Error(MJ_EINVAL, "bad query threshold");
     if (qparams->k > 2047) throw Error(MJ_ECAPACITY, "threshold K exceeds the verifier's band limit (K <= 2047)");
+    check_verifier(qparams);
     MJ_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     Workspace &ws = ctx->ws;
@@ -504,7 +532,7 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
     run_verify(ctx, uniq, C, qd, id, 1, qparams->k, qparams, flags, s, stats, cells_slot(ctx));
     tm.mark();  // 5 verify
     mj_pairs *res = compact_pairs(uniq, flags, C, ws, s, ctx->pinned);  // synchronises when C > 0
-    const int64_t cells = (int64_t)*cells_slot(ctx);
+    const int64_t cells = take_cells(ctx, res);
     tm.mark();  // 6 output
     if (stats) {
         stats->records = rb.count;

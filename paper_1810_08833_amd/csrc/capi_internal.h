@@ -37,6 +37,7 @@ struct mj_index {
     uint32_t *planes = nullptr;
     int64_t plane_words = 0;
     int np = 0;
+    uint64_t *pi_table = nullptr;  // the index's own copy of an injected Pi table
     RecBuf rec;  // sorted by key
 };
 

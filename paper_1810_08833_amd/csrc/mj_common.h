@@ -157,6 +157,9 @@ struct DevStrings {
     int32_t *rr = nullptr;   // r_i (repetition-independent)
     uint32_t *planes = nullptr;  // bit planes, interleaved: planes[w * np + p]
     int64_t plane_words = 0;
+    // device word set by the plane packing when a symbol code is >= sigma (nullptr: the
+    // symbols were not checked)
+    uint32_t *symbol_err = nullptr;
 };
 
 inline void check_total(const DevStrings &d) {
@@ -190,7 +193,11 @@ struct RecBuf {
 // partition.hip
 int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
                         uint64_t *host_scratch);       // returns the halo radius needed
+// Builds the verifier's bit planes and checks every symbol against sigma (the result in
+// d.symbol_err, read with the partition stage's counts or by check_symbols).
 void pack_planes(DevStrings &d, int planes, Workspace &ws, hipStream_t s);
+// Reads d.symbol_err back (synchronises); MJ_EINVAL when a symbol code is >= sigma.
+void check_symbols(const DevStrings &d, hipStream_t s, uint64_t *host_scratch);
 // Appends the records of every partition of every repetition (repetition rho seeds Pi
 // with seed + rho) to `out`; returns how many.
 int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t halo, RecBuf &out,
@@ -243,8 +250,10 @@ struct VerifyTuning {
 };
 // uniform_k >= 0 promises that every pair's K equals it and that all ids are valid (pairs
 // produced by the library): the pass that finds the largest K is skipped.  With
-// cells_defer set (pinned host memory) the band-cell count is copied there
-// asynchronously and the call returns 0 without synchronising.  force_lanes != 0 fixes
+// cells_defer set (two words of pinned host memory) the band-cell count and an error word
+// (nonzero when some pair's band did not fit the launched window) are copied there
+// asynchronously and the call returns 0 without synchronising; otherwise the call reads
+// both and fails with MJ_ECAPACITY on the error word.  force_lanes != 0 fixes
 // the configuration (mj_params.verify_lanes) instead of the timed choice; tune == nullptr
 // takes the fixed small-call configuration (no timing runs on the call).
 int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings &A,

@@ -119,17 +119,29 @@ __device__ __forceinline__ uint32_t gather_byte(const uint64_t y[4]) {
     return lo | (hi << 16);
 }
 
+// nonzero when some byte of x is >= sigma
+__device__ __forceinline__ uint32_t any_byte_ge(uint32_t x, uint32_t sigma) {
+    return (uint32_t)((x & 0xFFu) >= sigma) | (uint32_t)(((x >> 8) & 0xFFu) >= sigma) |
+           (uint32_t)(((x >> 16) & 0xFFu) >= sigma) | (uint32_t)((x >> 24) >= sigma);
+}
+
+// Also checks every symbol against the alphabet: *err |= 1 when a code is >= sigma (the
+// entry points fail with MJ_EINVAL at their next read-back).
 template <int NP>
 __global__ void k_pack_planes(const uint8_t *chars, int64_t total, uint32_t *planes,
-                              int64_t plane_words, int aligned) {
+                              int64_t plane_words, int aligned, uint32_t sigma, uint32_t *err) {
     int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t over = 0;
     for (; w < plane_words; w += stride) {
         uint32_t acc[NP];
         int64_t base = w * 32;
         if (aligned && base + 32 <= total) {
             const uint4 *v = reinterpret_cast<const uint4 *>(chars + base);
             const uint4 a = v[0], b = v[1];
+            over |= any_byte_ge(a.x, sigma) | any_byte_ge(a.y, sigma) | any_byte_ge(a.z, sigma) |
+                    any_byte_ge(a.w, sigma) | any_byte_ge(b.x, sigma) | any_byte_ge(b.y, sigma) |
+                    any_byte_ge(b.z, sigma) | any_byte_ge(b.w, sigma);
             uint64_t y[4];
             y[0] = transpose8x8(((uint64_t)a.y << 32) | a.x);
             y[1] = transpose8x8(((uint64_t)a.w << 32) | a.z);
@@ -155,6 +167,7 @@ __global__ void k_pack_planes(const uint8_t *chars, int64_t total, uint32_t *pla
             for (int t = 0; t < 32; t++) {
                 int64_t g = base + t;
                 uint32_t c = g < total ? chars[g] : 0u;
+                over |= (uint32_t)(c >= sigma);
 #pragma unroll
                 for (int p = 0; p < NP; p++) acc[p] |= ((c >> p) & 1u) << t;
             }
@@ -162,21 +175,32 @@ __global__ void k_pack_planes(const uint8_t *chars, int64_t total, uint32_t *pla
 #pragma unroll
         for (int p = 0; p < NP; p++) planes[w * NP + p] = acc[p];
     }
+    if (over) atomicOr(err, 1u);
 }
 
 void pack_planes(DevStrings &d, int np, Workspace &ws, hipStream_t s) {
     d.plane_words = (d.total + 31) / 32 + 96;  // padding: windows may read past the end
     d.planes = ws.get_n<uint32_t>((size_t)np * d.plane_words);
+    uint32_t *err = ws.get_n<uint32_t>(2);
+    fill_u32(err, 0, 1, s);
+    d.symbol_err = err;
     int aligned = ((uintptr_t)d.chars & 15) == 0 ? 1 : 0;
+    const uint32_t sg = (uint32_t)d.sigma;
     const dim3 grid(grid_for(d.plane_words, 256, 16384));
     switch (np) {
-        case 2: hipLaunchKernelGGL(k_pack_planes<2>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned); break;
-        case 4: hipLaunchKernelGGL(k_pack_planes<4>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned); break;
-        case 6: hipLaunchKernelGGL(k_pack_planes<6>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned); break;
-        case 8: hipLaunchKernelGGL(k_pack_planes<8>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned); break;
+        case 2: hipLaunchKernelGGL(k_pack_planes<2>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned, sg, err); break;
+        case 4: hipLaunchKernelGGL(k_pack_planes<4>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned, sg, err); break;
+        case 6: hipLaunchKernelGGL(k_pack_planes<6>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned, sg, err); break;
+        case 8: hipLaunchKernelGGL(k_pack_planes<8>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned, sg, err); break;
         default: throw Error(MJ_EINVAL, "plane count must be 2, 4, 6 or 8");
     }
     MJ_LAUNCH_CHECK();
+}
+
+void check_symbols(const DevStrings &d, hipStream_t s, uint64_t *host_scratch) {
+    if (!d.symbol_err) return;
+    if (read_back<uint32_t>(d.symbol_err, s, host_scratch))
+        throw Error(MJ_EINVAL, "a symbol code is not below sigma");
 }
 
 // ---------------------------------------------------------------- anchors
@@ -388,11 +412,12 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                     N[i] = __builtin_amdgcn_alignbit(W2[i + 1], W2[i], 8 * (o2 & 3));
             }
             using Code = typename std::conditional<RANKED, uint32_t, uint64_t>::type;
+            const Code cmask = (Code)gmask;
             Code G = 0;
 #pragma unroll
             for (int k = 0; k < 9; k++)
                 if (k < q) G = (G << bits) | ((A[k >> 2] >> (8 * (k & 3))) & 0xFFu);
-            const Code cmask = (Code)gmask;
+            G &= cmask;  // the code indexes the rank table: never past its 2^(q b) entries
             // positions inside a string fit in 32 bits (m < 2^31)
             const int32_t i0 = (int32_t)(g0 - sb0);
             const int32_t npos = (int32_t)(se0 - sb0) - q + 1;
@@ -953,7 +978,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     // other position); their ranks are 32-bit
     if ((int64_t)d.n + d.total / 2 + 2 > 0xFFFFFFF0LL)
         throw Error(MJ_ECAPACITY, "more than 2^32 partitions per repetition");
-    if ((size_t)reps * 8 > HOST_SCRATCH_BYTES) throw Error(MJ_EINVAL, "too many repetitions");
+    if ((size_t)reps * 4 + 4 > HOST_SCRATCH_BYTES / 2) throw Error(MJ_EINVAL, "too many repetitions");
     const int code_bits = p.q * d.bits;
     const int aligned4 = ((uintptr_t)d.chars & 3) == 0 ? 1 : 0;
 
@@ -996,7 +1021,13 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
         MJ_HIP(hipMemcpyAsync((uint8_t *)host_scratch + 4 * rho, pre[rho] + ntiles, 4,
                               hipMemcpyDeviceToHost, s));
     }
+    // the symbol check of the plane packing comes back with the counts
+    uint32_t *sym_err_h = (uint32_t *)host_scratch + reps;
+    *sym_err_h = 0;
+    if (d.symbol_err)
+        MJ_HIP(hipMemcpyAsync(sym_err_h, d.symbol_err, 4, hipMemcpyDeviceToHost, s));
     MJ_HIP(hipStreamSynchronize(s));
+    if (*sym_err_h) throw Error(MJ_EINVAL, "a symbol code is not below sigma");
     std::vector<int64_t> R(reps);
     int64_t total = 0;
     for (int rho = 0; rho < reps; rho++) {

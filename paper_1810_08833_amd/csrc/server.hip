@@ -211,6 +211,9 @@ extern "C" mj_status mj_server_submit(mj_server *srv, const uint8_t *codes, int3
     if (!srv) return mj_fail(MJ_EINVAL, "server is NULL");
     if (len < 0 || (len > 0 && !codes)) return mj_fail(MJ_EINVAL, "bad query");
     if (k < 0 || k > 2047) return mj_fail(MJ_EINVAL, "k must be in 0..2047");
+    for (int32_t i = 0; i < len; i++)
+        if ((int32_t)codes[i] >= srv->ix->sigma)
+            return mj_fail(MJ_EINVAL, "query symbol code is not below the index alphabet");
     int64_t est = request_bytes(len);
     if (est > srv->cfg.memory_budget) return mj_fail(MJ_EINVAL, "query exceeds the memory budget");
     Request r;

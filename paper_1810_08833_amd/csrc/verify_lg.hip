@@ -151,6 +151,8 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
                 }
                 if (trivial) {
                     if (g == 0) flags[pi] = result;
+                    // a window too small for the band: the call fails (never a silent flag)
+                    if (g == 0 && result == 2) atomicOr(cells + 1, 1ull);
                 } else {
                     active = true;
                     wlo = w0;
@@ -572,6 +574,7 @@ __global__ __launch_bounds__(256) void k_verify_bidir(const uint64_t *__restrict
             }
             if (trivial) {
                 if (!bwd) flags[pi] = result;
+                if (!bwd && result == 2) atomicOr(cells + 1, 1ull);
             } else {
                 active = true;
                 solo = nt < 64;
@@ -787,7 +790,8 @@ static PersistKernel persist_kernel(int nwl, int g, int np) {
         case 2: return by_nwl<2>(nwl, np);
         case BIDIR: return bidir_kernel(nwl, np);
         case 4: return by_nwl<4>(nwl, np);
-        default: return by_nwl<8>(nwl, np);
+        case 8: return by_nwl<8>(nwl, np);
+        default: throw Error(MJ_EINVAL, "lanes per pair must be 1, 2, 4, 8 or the column split");
     }
 }
 
@@ -1016,11 +1020,17 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
         tune->last_blocks = best_blocks;
     }
     if (cells_defer) {
-        // the caller reads it after its next synchronisation of the stream
-        MJ_HIP(hipMemcpyAsync(cells_defer, cells, 8, hipMemcpyDeviceToHost, s));
+        // the caller reads both words after its next synchronisation of the stream:
+        // the band-cell count and the undersized-window error word
+        MJ_HIP(hipMemcpyAsync(cells_defer, cells, 16, hipMemcpyDeviceToHost, s));
         return 0;
     }
-    return (int64_t)read_back<uint64_t>((const uint64_t *)cells, s, host_scratch);
+    MJ_HIP(hipMemcpyAsync(host_scratch, cells, 16, hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipStreamSynchronize(s));
+    uint64_t hv[2];
+    memcpy(hv, host_scratch, 16);
+    if (hv[1]) throw Error(MJ_ECAPACITY, "a pair's band exceeds the verifier window");
+    return (int64_t)hv[0];
 }
 
 }  // namespace mj

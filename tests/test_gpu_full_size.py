@@ -80,9 +80,10 @@ def test_search_full_size_identical_direct_and_served(mj):
     torch.cuda.empty_cache()
     kq = dg.k_fraction(Q.lengths(), *g["k_frac"])
     qd = mj.DeviceStrings.from_host(Q.chars, Q.offsets, 4)
-    out, st = index.search(qd, k_per_query=torch.from_numpy(kq).cuda())
-    assert st["candidates"] == g["candidates"]
-    assert out.size == g["output"] and digest(out) == g["output_sha256"]
+    for verifier in (mj.VERIFY_BATCHED, mj.VERIFY_PLAIN):
+        out, st = index.search(qd, k_per_query=torch.from_numpy(kq).cuda(), verifier=verifier)
+        assert st["candidates"] == g["candidates"]
+        assert out.size == g["output"] and digest(out) == g["output_sha256"], verifier
     say("served")
     srv = mj.Server(index, workers=4, max_batch=512, memory_budget=8 << 30)
     for t in range(Q.n):

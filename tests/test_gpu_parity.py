@@ -315,6 +315,10 @@ def test_search_matches_oracle(mj):
     # a second batch on the same resident index gives the same answer
     got2, _ = index.search(dev(mj, Q), k_per_query=torch.from_numpy(kq).cuda())
     assert np.array_equal(got2, want)
+    # and so does the plain verifier (a pair per lane, one launch per band size)
+    got3, st3 = index.search(dev(mj, Q), k_per_query=torch.from_numpy(kq).cuda(),
+                             verifier=mj.VERIFY_PLAIN)
+    assert np.array_equal(got3, want) and st3["verify_group"] == 0
     index.close()
 
 
