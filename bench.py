@@ -2,16 +2,19 @@
 
 One step = one full join (every stage of the hot path: per-string setup, anchors,
 partition records, sort, group and filter, dedup, banded verification, output) over
-the long-read DNA workload: 50,000 strings, lengths N(5000, 800) clipped to
-[2000, 9000], 5,000 hidden seeds x 10 copies with 1-6% edits (insertions .5,
-deletions .3, substitutions .2), K = 150, q = 5, T = ceil(K / 2).  The strings are
-resident in HBM before the timed region; the timed region ends when the sorted output
-pairs are on the host.
+the text-shaped workload, the largest join that fits one GPU: 300,000 strings over 37
+symbols with Zipf(1.0) frequencies, lengths N(1200, 300) clipped to [300, 3000], 10% in
+clusters of 10 near-duplicates at 2-10% edits, K = 120, q = 6, T = ceil(K / 2), four
+parallel repetitions.  The strings are resident in HBM before the timed region; the
+timed region ends when the sorted output pairs are on the host.  The long-read DNA and
+protein joins are measured the same way after it and reported under "workloads".
 
 Prints one JSON line: strings joined/s (value), verified candidate pairs/s, recall
-against the intra-cluster ground truth, the roofline of the dominant kernel (timed with
-HIP events inside the library, on the launching stream) and the CPU oracle timed on a
-bounded sample of the same workload.
+against the intra-cluster ground truth, the plain GPU path beside the batched one, the
+roofline of the dominant kernel (timed with HIP events inside the library, on the
+launching stream), the HBM rates of the partition and sort stages, and the CPU oracle
+timed on a bounded sample of the same workload (all host threads and one thread, with
+its stage split).
 """
 import argparse
 import hashlib
@@ -156,20 +159,34 @@ def roofline(kernel, stats, kms, kln, bits, q, workload):
     return r
 
 
-def cpu_baseline(workload, cfg):
+def cpu_baseline(workload, cfg, one_thread=True):
+    """The oracle as it stands on the host cores: all threads (partition and verification
+    run over strings and pairs in parallel, the bucket join on one thread), then one
+    thread, on the same bounded sample; with the stage split of the paper's Fig. 5 (the
+    input is already in memory, so there is no read stage)."""
     import oracle
     S = make(workload, **cfg["cpu_sample"])
-    p = oracle.make_params(cfg["q"], cfg["sigma"], t_div=cfg["t_div"], reps=cfg["reps"],
-                           **k_of(cfg, S.lengths()))
-    threads = oracle.max_threads()
-    t0 = time.perf_counter()
-    _, out, st = oracle.join(S.chars, S.offsets, p)
-    dt = time.perf_counter() - t0
-    return {"value": S.n / dt, "unit": "strings/s", "cores": threads, "kind": "oracle",
+    res = {}
+    for threads in ([oracle.max_threads(), 1] if one_thread else [oracle.max_threads()]):
+        p = oracle.make_params(cfg["q"], cfg["sigma"], t_div=cfg["t_div"], reps=cfg["reps"],
+                               threads=threads, **k_of(cfg, S.lengths()))
+        t0 = time.perf_counter()
+        _, out, st = oracle.join(S.chars, S.offsets, p)
+        dt = time.perf_counter() - t0
+        res[threads] = (dt, st)
+    threads = max(res)
+    dt, st = res[threads]
+    line = {"value": S.n / dt, "unit": "strings/s", "cores": threads, "kind": "oracle",
             "sample": "%s generator with %s (%d strings, %d symbols): full join incl. "
-                      "verification of %d candidates in %.1f s"
+                      "verification of %d candidates in %.1f s on %d threads"
                       % (workload, cfg["cpu_sample"] or "its full size", S.n,
-                         int(S.offsets[-1]), st["candidates"], dt)}
+                         int(S.offsets[-1]), st["candidates"], dt, threads),
+            "stage_s": st["stage_s"]}
+    if 1 in res and threads != 1:
+        dt1, st1 = res[1]
+        line["one_thread"] = {"value": S.n / dt1, "unit": "strings/s", "seconds": dt1,
+                              "stage_s": st1["stage_s"]}
+    return line
 
 
 def copy_calibration(gib):
@@ -325,12 +342,139 @@ def characterise(args):
                            for k in mj.STAGES[:7]})
 
 
+def stage_hbm(workload, stats, reps, sym_bytes):
+    """HBM rates of the partition and sort stages over their stage times (HIP events on the
+    call's stream).  Algorithmic bytes are the least traffic the stage needs: partitioning
+    reads the symbols once per repetition and writes a 16-byte record (key, string id and
+    position) per partition; the sort reads and writes every record once.  Measured bytes
+    are FETCH_SIZE + WRITE_SIZE of the stage's kernels in one join (rocprofv3, calibrated),
+    used only when the counters were taken on the current sources."""
+    total = float(np.mean([s["positions"] for s in stats])) / reps
+    R = float(np.mean([s["records"] for s in stats]))
+    alg = {"partition": reps * total * sym_bytes + 16.0 * R, "sort": 32.0 * R}
+    meas = {}
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if os.path.exists(path):
+        with open(path) as f:
+            t = json.load(f)
+        csrc = os.path.join(ROOT, "paper_1810_08833_amd", "csrc")
+        fresh = all(t.get("source_sha256", {}).get(n) == file_sha(os.path.join(csrc, n))
+                    for n in os.listdir(csrc) if n.endswith(".hip") or n.endswith(".h"))
+        if fresh:
+            meas = t.get("bytes_per_join_by_stage", {})
+    out = {}
+    for st in ("partition", "sort"):
+        secs = float(np.mean([s["stage_ms"][st] for s in stats])) * 1e-3
+        m = meas.get(st)
+        out[st] = {"ms": secs * 1e3, "algorithmic_bytes": alg[st],
+                   "algorithmic_GBps": alg[st] / secs / 1e9,
+                   "measured_bytes": m, "measured_GBps": (m / secs / 1e9) if m else None,
+                   "frac_of_hbm_peak": ((m or alg[st]) / secs / 1e9) / HBM_PEAK_GBS}
+    return out
+
+
+def measure_join(workload, args, steps, warmup):
+    """Times `steps` joins of `workload` (after `warmup`) on the plain and the batched path
+    and returns the measurement as a dict (no CPU baseline)."""
+    import torch
+    import paper_1810_08833_amd as mj
+
+    cfg = dict(WORKLOADS[workload])
+    if args.t_div is not None:
+        cfg["t_div"] = args.t_div
+    S = make(workload)
+    print("[bench] workload %s: %d strings, %d symbols" % (workload, S.n, S.offsets[-1]),
+          file=sys.stderr, flush=True)
+    ds = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
+    kw = k_of(cfg, S.lengths())
+    if "k_per_string" in kw:
+        kw["k_per_string"] = torch.from_numpy(kw["k_per_string"]).cuda()
+    params = mj.Params(q=cfg["q"], t_div=cfg["t_div"], reps=cfg["reps"], **kw)
+    ctx = mj.Context(0)
+    # the same join with the strings uploaded from pageable host memory inside the timing
+    torch.cuda.synchronize()
+    t_up = time.perf_counter()
+    for _ in range(3):
+        du = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
+        torch.cuda.synchronize()
+    upload_ms = (time.perf_counter() - t_up) * 1e3 / 3
+    del du
+
+    # ground truth for recall (outside the timed region): every intra-cluster pair with
+    # ED <= K, decided by the verifier; copies of different seeds are unrelated random
+    # strings, far beyond K
+    # (its own context: the verifier's one-time configuration timing belongs to the join)
+    truth_pairs = intra_cluster_pairs(S)
+    flags = mj.verify(ds, params, truth_pairs, ctx=mj.Context(0))
+    truth = truth_pairs[flags]
+
+    def timed(verifier):
+        params.verifier = verifier
+        out = None
+        for _ in range(warmup):
+            out, st = mj.join(ds, params, ctx=ctx)
+        torch.cuda.synchronize()
+        stats = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out, st = mj.join(ds, params, ctx=ctx)
+            stats.append(st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return out, stats, dt * 1e3 / steps
+
+    plain_out, plain_stats, plain_ms = timed(mj.VERIFY_PLAIN)
+    print("[bench] %s plain: %.3f ms/step" % (workload, plain_ms), file=sys.stderr, flush=True)
+    out, stats, ms = timed(mj.VERIFY_BATCHED)
+    print("[bench] %s batched: %.3f ms/step" % (workload, ms), file=sys.stderr, flush=True)
+    assert np.array_equal(out, plain_out), "batched and plain verifiers disagree"
+
+    recall = float(np.isin(truth, out).mean()) if len(truth) else 1.0
+    last = stats[-1]
+    verify_ms = np.mean([s["stage_ms"]["verify"] for s in stats])
+    kms = {k: float(np.sum([s["kernel_ms"][k] for s in stats])) for k in mj.KERNELS}
+    kln = {k: int(np.sum([s["kernel_launches"][k] for s in stats])) for k in mj.KERNELS}
+    dominant = max(kms, key=kms.get)
+    bits = int(np.ceil(np.log2(S.sigma)))
+    roof = roofline(dominant, stats, kms, kln, bits, cfg["q"], workload)
+    return {
+        "cfg": cfg,
+        "value": S.n / (ms * 1e-3),
+        "ms_per_step": ms,
+        "config": {"workload": cfg["desc"], "strings": S.n, "symbols": int(S.offsets[-1]),
+                   "K": cfg.get("k", "ceil(%d/%d m_i)" % tuple(cfg.get("k_frac", (0, 1)))),
+                   "q": cfg["q"], "t_div": cfg["t_div"], "reps": cfg["reps"], "path": "batched",
+                   "verify_lanes_per_pair": last["verify_group"],
+                   "verify_words_per_lane": last["verify_words"],
+                   "verify_workgroups": last["verify_blocks"]},
+        "plain": {"value": S.n / (plain_ms * 1e-3), "ms_per_step": plain_ms,
+                  "verify_kernel_ms": float(np.mean([s["kernel_ms"]["verify"] for s in plain_stats]))},
+        "batched_vs_plain": plain_ms / ms,
+        "with_upload": {"value": S.n / ((ms + upload_ms) * 1e-3), "upload_ms": upload_ms,
+                        "note": "strings uploaded from pageable host memory inside the timing"},
+        "verified_pairs_per_s": last["candidates"] / (verify_ms * 1e-3),
+        "candidates": last["candidates"],
+        "output_pairs": int(len(out)),
+        "recall": recall,
+        "true_pairs": int(len(truth)),
+        "records": last["records"],
+        "pair_tests": last["pair_tests"],
+        "stage_ms": {k: float(np.mean([s["stage_ms"][k] for s in stats])) for k in mj.STAGES[:7]},
+        "stage_hbm": stage_hbm(workload, stats, cfg["reps"], 1.0),
+        "kernel_ms_per_step": {k: kms[k] / steps for k in kms},
+        "roofline": roof,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="dna_long", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="text", choices=sorted(WORKLOADS))
+    ap.add_argument("--also", default=None,
+                    help="comma-separated workloads measured after the main one (default: "
+                         "dna_long,protein when the main workload is text, else none)")
     ap.add_argument("--t-div", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
@@ -361,105 +505,36 @@ def main():
         return
 
     import torch
-    import paper_1810_08833_amd as mj
-
-    cfg = dict(WORKLOADS[args.workload])
-    if args.t_div is not None:
-        cfg["t_div"] = args.t_div
     torch.cuda.set_device(0)
-    S = make(args.workload)
-    print("[bench] workload %s: %d strings, %d symbols" % (args.workload, S.n, S.offsets[-1]),
-          file=sys.stderr, flush=True)
-    ds = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
-    kw = k_of(cfg, S.lengths())
-    if "k_per_string" in kw:
-        kw["k_per_string"] = torch.from_numpy(kw["k_per_string"]).cuda()
-    params = mj.Params(q=cfg["q"], t_div=cfg["t_div"], reps=cfg["reps"], **kw)
-    ctx = mj.Context(0)
-    # the same join with the strings uploaded from pageable host memory inside the timing
-    torch.cuda.synchronize()
-    t_up = time.perf_counter()
-    for _ in range(3):
-        du = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
-        torch.cuda.synchronize()
-    upload_ms = (time.perf_counter() - t_up) * 1e3 / 3
-    del du
+    also = args.also
+    if also is None:
+        also = "dna_long,protein" if args.workload == "text" else ""
+    also = [w for w in also.split(",") if w and w != args.workload]
 
-    # ground truth for recall (outside the timed region): every intra-cluster pair with
-    # ED <= K, decided by the verifier; copies of different seeds are unrelated random
-    # strings, far beyond K
-    # (its own context: the verifier's one-time configuration timing belongs to the join)
-    truth_pairs = intra_cluster_pairs(S)
-    flags = mj.verify(ds, params, truth_pairs, ctx=mj.Context(0))
-    truth = truth_pairs[flags]
-
-    def timed(verifier):
-        params.verifier = verifier
-        out = None
-        for _ in range(args.warmup):
-            out, st = mj.join(ds, params, ctx=ctx)
-        torch.cuda.synchronize()
-        stats = []
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            out, st = mj.join(ds, params, ctx=ctx)
-            stats.append(st)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        return out, stats, dt * 1e3 / args.steps
-
-    plain_out, plain_stats, plain_ms = timed(mj.VERIFY_PLAIN)
-    print("[bench] plain: %.3f ms/step" % plain_ms, file=sys.stderr, flush=True)
-    out, stats, ms = timed(mj.VERIFY_BATCHED)
-    print("[bench] batched: %.3f ms/step" % ms, file=sys.stderr, flush=True)
-    assert np.array_equal(out, plain_out), "batched and plain verifiers disagree"
-
-    recall = float(np.isin(truth, out).mean()) if len(truth) else 1.0
-    last = stats[-1]
-    verify_ms = np.mean([s["stage_ms"]["verify"] for s in stats])
-    kms = {k: float(np.sum([s["kernel_ms"][k] for s in stats])) for k in mj.KERNELS}
-    kln = {k: int(np.sum([s["kernel_launches"][k] for s in stats])) for k in mj.KERNELS}
-    dominant = max(kms, key=kms.get)
-
-    # roofline of the dominant kernel
-    bits = int(np.ceil(np.log2(S.sigma)))
-    roof = roofline(dominant, stats, kms, kln, bits, cfg["q"], args.workload)
-
+    m = measure_join(args.workload, args, args.steps, args.warmup)
+    cfg = m.pop("cfg")
     line = {
         "metric": METRIC,
-        "value": S.n / (ms * 1e-3),
+        "value": m.pop("value"),
         "unit": "strings/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": m.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": cfg["desc"], "strings": S.n, "symbols": int(S.offsets[-1]),
-                   "K": cfg.get("k", "ceil(%d/%d m_i)" % tuple(cfg.get("k_frac", (0, 1)))),
-                   "q": cfg["q"], "t_div": cfg["t_div"], "reps": cfg["reps"], "path": "batched",
-                   "verify_lanes_per_pair": last["verify_group"],
-                   "verify_words_per_lane": last["verify_words"],
-                   "verify_workgroups": last["verify_blocks"]},
-        "plain": {"value": S.n / (plain_ms * 1e-3), "ms_per_step": plain_ms,
-                  "verify_kernel_ms": float(np.mean([s["kernel_ms"]["verify"] for s in plain_stats]))},
-        "batched_vs_plain": plain_ms / ms,
-        "with_upload": {"value": S.n / ((ms + upload_ms) * 1e-3), "upload_ms": upload_ms,
-                        "note": "strings uploaded from pageable host memory inside the timing"},
-        "verified_pairs_per_s": last["candidates"] / (verify_ms * 1e-3),
-        "candidates": last["candidates"],
-        "output_pairs": int(len(out)),
-        "recall": recall,
-        "true_pairs": int(len(truth)),
-        "records": last["records"],
-        "pair_tests": last["pair_tests"],
-        "stage_ms": {k: float(np.mean([s["stage_ms"][k] for s in stats])) for k in mj.STAGES[:7]},
-        "kernel_ms_per_step": {k: kms[k] / args.steps for k in kms},
-        "roofline": roof,
+        "config": m.pop("config"),
     }
+    line.update(m)
+    if also:
+        line["workloads"] = {}
+        for w in also:
+            mw = measure_join(w, args, min(args.steps, 10), min(args.warmup, 3))
+            mw.pop("cfg")
+            line["workloads"][w] = mw
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.workload, cfg)

@@ -45,7 +45,9 @@ class Record(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("records", ctypes.c_int64), ("candidates", ctypes.c_int64),
-                ("output", ctypes.c_int64), ("pair_tests", ctypes.c_int64)]
+                ("output", ctypes.c_int64), ("pair_tests", ctypes.c_int64),
+                ("partition_s", ctypes.c_double), ("join_s", ctypes.c_double),
+                ("dedup_s", ctypes.c_double), ("verify_s", ctypes.c_double)]
 
 
 RECORD_DTYPE = np.dtype([("key", "<u8"), ("sid", "<i4"), ("pos", "<i4"), ("len", "<i4"),
@@ -220,7 +222,9 @@ def join(chars, offsets, params, verify=True):
     cand = _take_u64(cp, nc.value)
     pairs = _take_u64(pp, npairs.value)
     return cand, pairs, {"records": st.records, "candidates": st.candidates,
-                         "output": st.output, "pair_tests": st.pair_tests}
+                         "output": st.output, "pair_tests": st.pair_tests,
+                         "stage_s": {"partition": st.partition_s, "join": st.join_s,
+                                     "dedup": st.dedup_s, "verify": st.verify_s}}
 
 
 def search(ichars, ioffsets, iparams, qchars, qoffsets, qparams):

@@ -334,6 +334,8 @@ static int pass_position(int64_t pi, int64_t mi, int64_t pj, int64_t mj, int64_t
 
 typedef struct {
     int64_t records, candidates, output, pair_tests;
+    /* wall-clock seconds of the stages (the split of the paper's Fig. 5) */
+    double partition_s, join_s, dedup_s, verify_s;
 } orc_stats;
 
 static int64_t dedup_sorted(uint64_t *a, int64_t n) {
@@ -380,8 +382,10 @@ static int join_impl(const uint8_t *chars, const int64_t *offsets, int32_t n, co
     int64_t *K = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
     for (int32_t i = 0; i < n; i++) K[i] = string_k(p, i);
     /* the partitions of every string (and repetition), grouped into buckets by key */
+    double t0 = omp_get_wtime();
     orc_record *rec = NULL;
     int64_t R = orc_partition_all(chars, offsets, n, p, &rec);
+    double t1 = omp_get_wtime();
     qsort(rec, (size_t)R, sizeof(orc_record), cmp_record_key);
     /* every pair of records of a bucket: distinct strings passing both filters */
     int64_t cc = 0, ccap = 1024, tests = 0;
@@ -403,13 +407,20 @@ static int join_impl(const uint8_t *chars, const int64_t *offsets, int32_t n, co
             }
         }
     }
+    double t2 = omp_get_wtime();
     /* dedup (Alg. 3 removes duplicate pairs) */
     cc = dedup_sorted(cand, cc);
     uint64_t *c2 = (uint64_t *)malloc(sizeof(uint64_t) * ((size_t)cc + 1));
     memcpy(c2, cand, sizeof(uint64_t) * (size_t)cc);
+    double t3 = omp_get_wtime();
     /* verification */
     int64_t no = do_verify ? verify_pairs(chars, offsets, K, cand, cc, nt) : 0;
-    if (stats) { stats->records = R; stats->candidates = cc; stats->output = no; stats->pair_tests = tests; }
+    double t4 = omp_get_wtime();
+    if (stats) {
+        stats->records = R; stats->candidates = cc; stats->output = no; stats->pair_tests = tests;
+        stats->partition_s = t1 - t0; stats->join_s = t2 - t1; stats->dedup_s = t3 - t2;
+        stats->verify_s = t4 - t3;
+    }
     *cand_out = c2; *ncand = cc;
     *pairs_out = cand; *npairs = no;
     free(rec); free(K);
