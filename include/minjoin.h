@@ -162,6 +162,22 @@ mj_status mj_candidates(mj_ctx *ctx, const mj_strings *strings, const mj_params 
 mj_status mj_verify(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
                     const uint64_t *pairs, int64_t n, uint8_t *flags, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): mj_verify's batched verification with
+ * no context and no allocation of any kind.  Every scratch buffer comes from one fixed
+ * array of 64 MiB in device memory that each GPU holds from the library's first such call
+ * until the process ends (the call's device is the current HIP device).  Arguments, layout
+ * and result are mj_verify's (params->verifier must be MJ_VERIFY_BATCHED; the lanes per
+ * pair are the fixed small-call choice unless verify_lanes fixes them).  A call whose
+ * strings, planes and pairs need more scratch than the array holds fails with
+ * MJ_ECAPACITY before writing flags (about 12 bytes per string, 2-8 bits per symbol
+ * (2 for 4 letters, 6 for 37), 8 bytes per pair, plus ~70 KB).  Calls on one GPU share
+ * its array, which keeps the last call's contents: the library serialises them with a
+ * lock and each returns only after its work on `stream` is complete, so calls from this
+ * process never overlap on the device; calls that overlapped would race. */
+mj_status mj_verify_noalloc(const mj_strings *strings, const mj_params *params,
+                            const uint64_t *pairs, int64_t n, uint8_t *flags, void *stream);
+
 /* ---- search: index the strings once, then find (query, string) pairs with
  * ED <= K_query.  Queries use the index's q, seed, t_div/t_fixed and reps. ------- */
 

@@ -75,7 +75,7 @@ EXPORTS = ["mj_ctx_create", "mj_ctx_destroy", "mj_last_error", "mj_version", "mj
            "mj_index_records", "mj_search", "mj_pairs_count", "mj_pairs_device",
            "mj_pairs_copy_to_host", "mj_pairs_free", "mj_records_count",
            "mj_records_copy_to_host", "mj_records_free", "mj_server_create", "mj_server_submit",
-           "mj_server_poll", "mj_server_pending", "mj_server_destroy"]
+           "mj_server_poll", "mj_server_pending", "mj_server_destroy", "mj_verify_noalloc"]
 
 _lib = None
 
@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH):
     L.mj_candidates.argtypes = [VP, P(MjStrings), P(MjParams), VP, P(VP), P(MjStats)]
     L.mj_partition.argtypes = [VP, P(MjStrings), P(MjParams), VP, P(VP)]
     L.mj_verify.argtypes = [VP, P(MjStrings), P(MjParams), VP, I64, VP, VP]
+    L.mj_verify_noalloc.argtypes = [P(MjStrings), P(MjParams), VP, I64, VP, VP]
     L.mj_index_build.argtypes = [VP, P(MjStrings), P(MjParams), VP, P(VP)]
     L.mj_index_free.argtypes = [VP]
     L.mj_index_free.restype = None
@@ -134,6 +135,7 @@ def load_library(path: str = LIB_PATH):
     for fn in ("mj_server_create", "mj_server_submit", "mj_server_poll"):
         getattr(L, fn).restype = ctypes.c_int
     for fn in ("mj_ctx_create", "mj_join", "mj_candidates", "mj_partition", "mj_verify",
+               "mj_verify_noalloc",
                "mj_index_build", "mj_search", "mj_pairs_copy_to_host", "mj_records_copy_to_host"):
         getattr(L, fn).restype = ctypes.c_int
     _lib = L

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libminjoin.so")
-SOURCES = ["prims.hip", "partition.hip", "join.hip", "verify.hip", "verify_lg.hip", "capi.hip", "server.hip"]
+SOURCES = ["prims.hip", "partition.hip", "join.hip", "verify.hip", "verify_lg.hip", "capi.hip", "server.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -63,6 +63,14 @@ class Workspace {
     template <class T> T *get_n(size_t n) { return static_cast<T *>(get(n * sizeof(T) + 16)); }
     void release_all();
     size_t bytes_held() const { return held_; }
+    // Arena mode: every block comes from the fixed device region [base, base + bytes)
+    // (bump allocation, reset by release_all; MJ_ECAPACITY when it is exhausted) and the
+    // workspace never allocates or frees device memory.  The region's first
+    // ARENA_SCAN_BYTES hold the single-pass scans' state, which must be zero before the
+    // first scan (the caller clears it once).
+    static constexpr size_t ARENA_SCAN_BYTES = 4096;
+    void bind_arena(void *base, size_t bytes);
+    bool arena() const { return arena_base_ != nullptr; }
     // State of the single-pass scans (prims.hip), kept across calls: one word per tile
     // tagged with the call's epoch (so it never needs clearing) and a tile ticket counter
     // that only grows (`base` = its value before the next scan).
@@ -77,6 +85,8 @@ class Workspace {
     struct Block { void *p; size_t n; bool used; };
     std::vector<Block> blocks_;
     size_t held_ = 0;
+    uint8_t *arena_base_ = nullptr;
+    size_t arena_bytes_ = 0, arena_used_ = 0;
 };
 
 // Owned device allocation (results).

@@ -1,5 +1,6 @@
-// Device primitives: fills, exclusive scans, stream compaction and a bucketed
-// (key, value) sort.  All loops are bounds-checked; grids come from host-known sizes.
+// Device primitives: workspace, fills, exclusive scans, stream compaction and an LSD radix
+// sort of (key, value) records.  All loops are bounds-checked; grids come from host-known
+// sizes.
 #include <string.h>
 
 #include <algorithm>
@@ -11,11 +12,31 @@ namespace mj {
 // ---------------------------------------------------------------- workspace / alloc
 Workspace::~Workspace() {
     for (auto &b : blocks_) (void)hipFree(b.p);
-    if (scan.state) (void)hipFree(scan.state);
+    if (scan.state && !arena()) (void)hipFree(scan.state);
+}
+
+void Workspace::bind_arena(void *base, size_t bytes) {
+    arena_base_ = static_cast<uint8_t *>(base);
+    arena_bytes_ = bytes;
+    arena_used_ = ARENA_SCAN_BYTES;
+    // the ticket on a line of its own after the tile words (as in scan_u32_single_pass)
+    scan.state = reinterpret_cast<uint64_t *>(arena_base_);
+    scan.ticket = reinterpret_cast<unsigned long long *>(scan.state + ARENA_SCAN_BYTES / 8 - 32);
+    scan.base = 0;
+    scan.epoch = 0;
 }
 
 void *Workspace::get(size_t bytes) {
     bytes = (bytes + 255) & ~size_t(255);
+    if (arena()) {
+        if (bytes > arena_bytes_ - arena_used_)
+            throw Error(MJ_ECAPACITY, "the call needs more than the " +
+                                          std::to_string(arena_bytes_ >> 20) +
+                                          " MiB of fixed scratch memory");
+        void *p = arena_base_ + arena_used_;
+        arena_used_ += bytes;
+        return p;
+    }
     Block *best = nullptr;
     for (auto &b : blocks_)
         if (!b.used && b.n >= bytes && (!best || b.n < best->n)) best = &b;
@@ -43,6 +64,7 @@ void *Workspace::get(size_t bytes) {
 
 void Workspace::release_all() {
     for (auto &b : blocks_) b.used = false;
+    if (arena()) arena_used_ = ARENA_SCAN_BYTES;
 }
 
 void *dev_alloc(size_t bytes) {
@@ -315,6 +337,7 @@ static void scan_u32_single_pass(const In *in, uint32_t *out, int64_t n, int64_t
                                  hipStream_t s) {
     if (nb > SCAN_MAX_TILES) throw Error(MJ_ECAPACITY, "scan too large");
     auto &sc = ws.scan;
+    static_assert((SCAN_MAX_TILES + 64) * 8 <= Workspace::ARENA_SCAN_BYTES, "arena scan state");
     if (!sc.state) {
         // the ticket on a line of its own after the tile words; all zero (epoch 0 unused)
         sc.state = (uint64_t *)dev_alloc((size_t)(SCAN_MAX_TILES + 64) * 8);
