@@ -112,6 +112,29 @@ def measured_traffic(workload, kernel, kernel_src):
     return t.get("bytes_per_launch", {}).get(kernel)
 
 
+def measured_valu(workload, kernel):
+    """VALU counters of the dominant kernel on `workload` (rocprofv3 SQ_INSTS_VALU,
+    SQ_ACTIVE_INST_VALU, SQ_THREAD_CYCLES_VALU, GRBM_GUI_ACTIVE; profiles/valu_<workload>.md
+    gives the commands and definitions), if they were taken on the current sources and
+    for this kernel; else None."""
+    path = os.path.join(ROOT, "profiles", "valu_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    csrc = os.path.join(ROOT, "paper_1810_08833_amd", "csrc")
+    for name, sha in t.get("source_sha256", {}).items():
+        p = os.path.join(csrc, name)
+        if not os.path.exists(p) or file_sha(p) != sha:
+            return None
+    d = t.get("dominant")
+    if not d or d.get("kernel") != kernel:
+        return None
+    return {"valu_busy": d["valu_busy"], "lane_ops_frac_of_peak": d["frac_of_int32_peak"],
+            "lane_instr_per_%s" % d["unit"].replace(" ", "_"): d["lane_instr_per_unit"],
+            "source": "profiles/valu_%s.md" % workload}
+
+
 def roofline(kernel, stats, kms, kln, bits, q, workload):
     """Achieved algorithmic rate of `kernel` over the timed steps against its bound.
     Integer ALU kernels count 32-bit operations of the plain algorithm per unit of work:
@@ -156,6 +179,7 @@ def roofline(kernel, stats, kms, kln, bits, q, workload):
         r.update(kernel="k_emit", bound="hbm", unit="GB/s", achieved=byts / secs / 1e9,
                  peak=HBM_PEAK_GBS)
     r["frac"] = r["achieved"] / r["peak"]
+    r["counters"] = measured_valu(workload, r["kernel"])
     return r
 
 
