@@ -46,9 +46,11 @@ def ops_per_word_column(bits):
 # truth; cpu_sample is the bounded sample the CPU oracle is timed on.
 WORKLOADS = {
     "dna_long": dict(q=5, k=150, t_div=2, reps=1, sigma=4, cpu_sample=dict(n_clusters=1000),
+                     packed=True,
                      desc="dna_long: 50,000 DNA strings, lengths N(5000,800) clipped to "
                           "[2000,9000], 5,000 seeds x 10 copies, 1-6% edits "
-                          "(ins .5/del .3/sub .2), K=150, q=5, T=ceil(K/2)"),
+                          "(ins .5/del .3/sub .2), K=150, q=5, T=ceil(K/2), 2-bit packed "
+                          "storage on device"),
     "dna_small": dict(q=4, k=60, t_div=1, reps=1, sigma=4, cpu_sample=dict(),
                       desc="dna_small: 1,000 DNA strings, 100 seeds x 10 copies, lengths "
                            "U[800,1200], 2-10% edits, K=60, q=4, T=K"),
@@ -239,7 +241,7 @@ def serve(args):
     Q, src, arrivals = dg.dna_queries(S, n=args.serve_queries, rate_per_s=args.serve_rate)
     print("[serve] index %d strings (%d symbols), %d queries, generated in %.1f s"
           % (S.n, S.offsets[-1], Q.n, time.perf_counter() - t_gen), file=sys.stderr, flush=True)
-    ds = mj.DeviceStrings.from_host(S.chars, S.offsets, 4)
+    ds = mj.DeviceStrings.from_host(S.chars, S.offsets, 4, packing=mj.PACK_2BIT)
     ki = torch.from_numpy(dg.k_fraction(S.lengths(), 1, 10)).cuda()
     torch.cuda.synchronize()
     t_b = time.perf_counter()
@@ -303,6 +305,7 @@ def serve(args):
         "recall": found / max(1, len(truth)),
         "true_pairs": len(truth),
         "index_records": index.records,
+        "index_device_bytes": index.device_bytes,
         "index_build_s": build_s,
     }
     print(json.dumps(line))
@@ -409,17 +412,23 @@ def measure_join(workload, args, steps, warmup):
     S = make(workload)
     print("[bench] workload %s: %d strings, %d symbols" % (workload, S.n, S.offsets[-1]),
           file=sys.stderr, flush=True)
-    ds = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
+    packing = mj.PACK_2BIT if cfg.get("packed") else mj.PACK_U8
+    ds = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma, packing=packing)
     kw = k_of(cfg, S.lengths())
     if "k_per_string" in kw:
         kw["k_per_string"] = torch.from_numpy(kw["k_per_string"]).cuda()
     params = mj.Params(q=cfg["q"], t_div=cfg["t_div"], reps=cfg["reps"], **kw)
     ctx = mj.Context(0)
     # the same join with the strings uploaded from pageable host memory inside the timing
+    # (held on the host 2 bits per symbol when the device stores them so)
+    host_words = mj.pack_2bit(S.chars) if packing == mj.PACK_2BIT else None
     torch.cuda.synchronize()
     t_up = time.perf_counter()
     for _ in range(3):
-        du = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
+        if host_words is not None:
+            du = mj.DeviceStrings.from_packed_host(host_words, S.offsets, S.sigma)
+        else:
+            du = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma)
         torch.cuda.synchronize()
     upload_ms = (time.perf_counter() - t_up) * 1e3 / 3
     del du
@@ -468,6 +477,7 @@ def measure_join(workload, args, steps, warmup):
         "config": {"workload": cfg["desc"], "strings": S.n, "symbols": int(S.offsets[-1]),
                    "K": cfg.get("k", "ceil(%d/%d m_i)" % tuple(cfg.get("k_frac", (0, 1)))),
                    "q": cfg["q"], "t_div": cfg["t_div"], "reps": cfg["reps"], "path": "batched",
+                   "storage": "2-bit packed" if cfg.get("packed") else "uint8",
                    "verify_lanes_per_pair": last["verify_group"],
                    "verify_words_per_lane": last["verify_words"],
                    "verify_workgroups": last["verify_blocks"]},
@@ -484,7 +494,7 @@ def measure_join(workload, args, steps, warmup):
         "records": last["records"],
         "pair_tests": last["pair_tests"],
         "stage_ms": {k: float(np.mean([s["stage_ms"][k] for s in stats])) for k in mj.STAGES[:7]},
-        "stage_hbm": stage_hbm(workload, stats, cfg["reps"], 1.0),
+        "stage_hbm": stage_hbm(workload, stats, cfg["reps"], 0.25 if cfg.get("packed") else 1.0),
         "kernel_ms_per_step": {k: kms[k] / steps for k in kms},
         "roofline": roof,
     }

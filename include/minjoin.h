@@ -44,12 +44,22 @@ typedef struct mj_pairs mj_pairs;
 typedef struct mj_records mj_records;
 typedef struct mj_index mj_index;
 
-/* Borrowed description of a string collection (all pointers device). */
+/* Borrowed description of a string collection (all pointers device).
+ *   packing MJ_PACK_U8: chars holds one byte per symbol, symbol g of the collection at
+ *           chars[g].
+ *   packing MJ_PACK_2BIT (sigma <= 4; the packed storage of DNA-shaped inputs): four
+ *           symbols per byte, symbol g in bits 2(g mod 4) .. 2(g mod 4)+1 of byte g/4
+ *           (the first symbol in the low bits).  The buffer holds whole 32-bit words,
+ *           ceil(offsets[n] / 16) of them, 4-byte aligned; bits past the last symbol are
+ *           ignored.  Positions and offsets still count symbols. */
+enum { MJ_PACK_U8 = 0, MJ_PACK_2BIT = 1 };
 typedef struct {
-    const uint8_t *chars;    /* symbol codes, one byte each, in [0, sigma) */
+    const uint8_t *chars;    /* symbol codes in [0, sigma), stored as `packing` says */
     const int64_t *offsets;  /* n + 1 non-decreasing offsets, offsets[0] = 0 */
     int32_t n;               /* number of strings, >= 0 */
     int32_t sigma;           /* alphabet size, 2 .. 256 */
+    int32_t packing;         /* MJ_PACK_U8 or MJ_PACK_2BIT */
+    int32_t reserved;        /* 0 */
 } mj_strings;
 
 /* Method parameters (Alg. 2, Alg. 3, Remark 1).
@@ -123,9 +133,25 @@ typedef struct {
 
 /* ---- context ---------------------------------------------------------------- */
 
+/* Device memory from the caller's pool (e.g. a framework's caching allocator).  alloc
+ * returns `bytes` of device memory on the context's device, 256-byte aligned, or NULL;
+ * free returns a block alloc gave.  The library calls them from the
+ * thread of the entry point that needs the memory (a server's worker threads use their
+ * own contexts, without an allocator), only after the stream work using a block has
+ * completed when freeing it. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} mj_allocator;
+
 /* Create a context on HIP device `device` (made current for the calls).  The context
- * owns a growable device workspace.  EINVAL for a bad device, EDEVICE on HIP errors. */
-mj_status mj_ctx_create(int device, mj_ctx **out);
+ * owns a growable device workspace.  alloc (nullable, copied) backs every device buffer
+ * the context's calls obtain -- the workspace, result pair lists, record lists and
+ * indexes built with it (each result keeps the allocator to free itself); with NULL the
+ * library uses hipMalloc.  EINVAL for a bad device or an allocator without alloc/free,
+ * EDEVICE on HIP errors. */
+mj_status mj_ctx_create(int device, const mj_allocator *alloc, mj_ctx **out);
 void mj_ctx_destroy(mj_ctx *ctx);
 
 /* Thread-local description of the last error (never NULL). */
@@ -182,12 +208,15 @@ mj_status mj_verify_noalloc(const mj_strings *strings, const mj_params *params,
  * ED <= K_query.  Queries use the index's q, seed, t_div/t_fixed and reps. ------- */
 
 /* Builds partitions of `strings` (Alg. 1-2) and keeps them sorted by key in device
- * memory together with a packed copy of the strings; inputs are borrowed only during
- * the call.  *out is library-owned until mj_index_free. */
+ * memory, with the strings' bit planes for verification (2 bits per symbol for 4
+ * letters) and their lengths and thresholds -- not the input symbols; inputs are
+ * borrowed only during the call.  *out is library-owned until mj_index_free. */
 mj_status mj_index_build(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
                          void *stream, mj_index **out);
 void mj_index_free(mj_index *index);
 int64_t mj_index_records(const mj_index *index);
+/* Device memory the index holds, in bytes (records, planes, lengths, thresholds, offsets). */
+int64_t mj_index_bytes(const mj_index *index);
 
 /* queries: borrowed; qparams->k / k_per_string give each query's K, qparams->verifier and
  * verify_lanes choose the verifier as for mj_join (EINVAL on other values); q, seed, the

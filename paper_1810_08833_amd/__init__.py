@@ -27,9 +27,20 @@ KERNELS = ["anchors", "records", "emit", "verify"]
 STAGES = ["setup", "partition", "sort", "group_filter", "dedup", "verify", "output", "unused"]
 
 
+PACK_U8, PACK_2BIT = 0, 1
+
+
 class MjStrings(ctypes.Structure):
     _fields_ = [("chars", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n", ctypes.c_int32),
-                ("sigma", ctypes.c_int32)]
+                ("sigma", ctypes.c_int32), ("packing", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class MjAllocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
 
 
 class MjParams(ctypes.Structure):
@@ -72,7 +83,7 @@ class MjReply(ctypes.Structure):
 
 EXPORTS = ["mj_ctx_create", "mj_ctx_destroy", "mj_last_error", "mj_version", "mj_join",
            "mj_partition", "mj_candidates", "mj_verify", "mj_index_build", "mj_index_free",
-           "mj_index_records", "mj_search", "mj_pairs_count", "mj_pairs_device",
+           "mj_index_records", "mj_index_bytes", "mj_search", "mj_pairs_count", "mj_pairs_device",
            "mj_pairs_copy_to_host", "mj_pairs_free", "mj_records_count",
            "mj_records_copy_to_host", "mj_records_free", "mj_server_create", "mj_server_submit",
            "mj_server_poll", "mj_server_pending", "mj_server_destroy", "mj_verify_noalloc"]
@@ -96,7 +107,7 @@ def load_library(path: str = LIB_PATH):
                            "`python -m paper_1810_08833_amd.build`" % path)
     L = ctypes.CDLL(path)
     P, VP, I64 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int64
-    L.mj_ctx_create.argtypes = [ctypes.c_int, P(VP)]
+    L.mj_ctx_create.argtypes = [ctypes.c_int, P(MjAllocator), P(VP)]
     L.mj_ctx_destroy.argtypes = [VP]
     L.mj_ctx_destroy.restype = None
     L.mj_last_error.restype = ctypes.c_char_p
@@ -111,6 +122,8 @@ def load_library(path: str = LIB_PATH):
     L.mj_index_free.restype = None
     L.mj_index_records.argtypes = [VP]
     L.mj_index_records.restype = I64
+    L.mj_index_bytes.argtypes = [VP]
+    L.mj_index_bytes.restype = I64
     L.mj_search.argtypes = [VP, VP, P(MjStrings), P(MjParams), VP, P(VP), P(MjStats)]
     L.mj_pairs_count.argtypes = [VP]
     L.mj_pairs_count.restype = I64
@@ -158,15 +171,50 @@ def _stream_ptr(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-class Context:
-    """Owns an mj_ctx (device workspace) on one GPU."""
+class TorchAllocator:
+    """An mj_allocator backed by torch's caching allocator (torch.cuda.caching_allocator_alloc
+    and _delete on the context's device), so that the library's device buffers come from the
+    same pool as the framework's tensors.  Counts the blocks it hands out and takes back."""
 
-    def __init__(self, device: Optional[int] = None):
+    def __init__(self, device: int):
+        self.device = device
+        self.allocs = 0
+        self.frees = 0
+        self.live = {}
+
+        def _alloc(nbytes, user):
+            torch = _torch()
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device)
+            except Exception:
+                return None
+            self.allocs += 1
+            self.live[p] = int(nbytes)
+            return p
+
+        def _free(ptr, user):
+            torch = _torch()
+            self.frees += 1
+            self.live.pop(ptr, None)
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        self.struct = MjAllocator(self._alloc_cb, self._free_cb, None)
+
+
+class Context:
+    """Owns an mj_ctx (device workspace) on one GPU.  allocator: None (the library's own
+    hipMalloc) or a TorchAllocator whose pool backs every device buffer of the context."""
+
+    def __init__(self, device: Optional[int] = None, allocator: Optional[TorchAllocator] = None):
         torch = _torch()
         L = load_library()
         self.device = torch.cuda.current_device() if device is None else int(device)
+        self.allocator = allocator  # kept alive as long as the context
         h = ctypes.c_void_p()
-        _check(L.mj_ctx_create(self.device, ctypes.byref(h)))
+        _check(L.mj_ctx_create(self.device, ctypes.byref(allocator.struct) if allocator else None,
+                               ctypes.byref(h)))
         self.handle = h
 
     def close(self):
@@ -192,26 +240,56 @@ def default_context(device: Optional[int] = None) -> Context:
     return _default_ctx[dev]
 
 
+def pack_2bit(codes) -> np.ndarray:
+    """Symbol codes < 4 packed four to a byte, the first in the low bits, as whole
+    little-endian 32-bit words (ceil(len / 16) of them): the layout of MJ_PACK_2BIT."""
+    c = np.ascontiguousarray(codes, dtype=np.uint8)
+    if c.size and int(c.max()) > 3:
+        raise ValueError("2-bit packing needs codes < 4")
+    n16 = -(-c.size // 16) * 16
+    pad = np.zeros(n16, dtype=np.uint8)
+    pad[:c.size] = c
+    q = pad.reshape(-1, 4)
+    b = (q[:, 0] | (q[:, 1] << 2) | (q[:, 2] << 4) | (q[:, 3] << 6)).astype(np.uint8)
+    return b.view("<u4").copy() if b.size else np.zeros(0, dtype="<u4")
+
+
 @dataclass
 class DeviceStrings:
-    """Strings resident on the GPU: uint8 codes + int64 offsets (torch tensors)."""
+    """Strings resident on the GPU: symbol codes (uint8, one per byte, or 2-bit packed) +
+    int64 offsets (torch tensors)."""
     chars: "object"
     offsets: "object"
     sigma: int
+    packing: int = PACK_U8
 
     @property
     def n(self) -> int:
         return int(self.offsets.numel()) - 1
 
     @classmethod
-    def from_host(cls, chars, offsets, sigma, device=None):
+    def from_host(cls, chars, offsets, sigma, device=None, packing=PACK_U8):
         torch = _torch()
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        c = torch.from_numpy(np.ascontiguousarray(chars, dtype=np.uint8))
-        if c.numel() == 0:
-            c = torch.zeros(1, dtype=torch.uint8)
+        if packing == PACK_2BIT:
+            words = pack_2bit(chars)
+            c = torch.from_numpy(words.view(np.int32) if words.size else np.zeros(1, np.int32))
+        else:
+            c = torch.from_numpy(np.ascontiguousarray(chars, dtype=np.uint8))
+            if c.numel() == 0:
+                c = torch.zeros(1, dtype=torch.uint8)
         return cls(c.to(dev), torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).to(dev),
-                   int(sigma))
+                   int(sigma), int(packing))
+
+    @classmethod
+    def from_packed_host(cls, words, offsets, sigma, device=None):
+        """Strings already packed 2 bits per symbol on the host (pack_2bit's layout)."""
+        torch = _torch()
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        w = np.ascontiguousarray(words, dtype="<u4")
+        c = torch.from_numpy(w.view(np.int32) if w.size else np.zeros(1, np.int32))
+        return cls(c.to(dev), torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).to(dev),
+                   int(sigma), PACK_2BIT)
 
     def struct(self) -> MjStrings:
         s = MjStrings()
@@ -219,6 +297,8 @@ class DeviceStrings:
         s.offsets = self.offsets.data_ptr()
         s.n = self.n
         s.sigma = self.sigma
+        s.packing = self.packing
+        s.reserved = 0
         return s
 
 
@@ -338,6 +418,10 @@ class Index:
     @property
     def records(self) -> int:
         return load_library().mj_index_records(self.handle)
+
+    @property
+    def device_bytes(self) -> int:
+        return load_library().mj_index_bytes(self.handle)
 
     def search(self, queries: DeviceStrings, k: int = -1, k_per_query=None, stream=None,
                verifier: int = VERIFY_BATCHED, verify_lanes: int = 0):

@@ -35,8 +35,9 @@ extern "C" const char *mj_last_error(void) { return g_err.c_str(); }
 
 extern "C" const char *mj_version(void) { return "minjoin-mi355x 0.1 (gfx950)"; }
 
-extern "C" mj_status mj_ctx_create(int device, mj_ctx **out) {
+extern "C" mj_status mj_ctx_create(int device, const mj_allocator *alloc, mj_ctx **out) {
     if (!out) return fail(MJ_EINVAL, "out is NULL");
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(MJ_EINVAL, "allocator needs alloc and free");
     MJ_API_BEGIN
     int count = 0;
     MJ_HIP(hipGetDeviceCount(&count));
@@ -44,6 +45,7 @@ extern "C" mj_status mj_ctx_create(int device, mj_ctx **out) {
     MJ_HIP(hipSetDevice(device));
     mj_ctx *c = new mj_ctx();
     c->device = device;
+    if (alloc) c->ws.alloc = *alloc;
     if (hipHostMalloc((void **)&c->pinned, HOST_SCRATCH_BYTES, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return fail(MJ_ENOMEM, "pinned host allocation failed");
@@ -58,6 +60,7 @@ extern "C" mj_status mj_ctx_create(int device, mj_ctx **out) {
 extern "C" void mj_ctx_destroy(mj_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
+    AllocScope as(ctx->ws.alloc);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     ctx->kt.destroy();
@@ -101,6 +104,10 @@ static void check_strings(const mj_strings *s) {
     if (!s) throw Error(MJ_EINVAL, "strings is NULL");
     if (s->n < 0) throw Error(MJ_EINVAL, "n must be >= 0");
     if (s->n > 0 && (!s->offsets)) throw Error(MJ_EINVAL, "offsets is NULL");
+    if (s->packing != MJ_PACK_U8 && s->packing != MJ_PACK_2BIT)
+        throw Error(MJ_EINVAL, "packing must be MJ_PACK_U8 or MJ_PACK_2BIT");
+    if (s->packing == MJ_PACK_2BIT && (s->sigma > 4 || ((uintptr_t)s->chars & 3)))
+        throw Error(MJ_EINVAL, "2-bit packing needs sigma <= 4 and 4-byte aligned words");
 }
 
 static PartitionParams to_pp(const mj_params *p, int bits) {
@@ -123,6 +130,7 @@ static DevStrings view(const mj_strings *s, hipStream_t st, uint64_t *pinned,
                        bool read_total = true) {
     DevStrings d;
     d.chars = s->chars;
+    d.packing = s->packing;
     d.offsets = s->offsets;
     d.n = s->n;
     d.sigma = s->sigma;
@@ -149,6 +157,7 @@ static void sorted_records(const DevStrings &d, const PartitionParams &pp, int32
 static mj_pairs *compact_pairs(const uint64_t *pairs, const uint8_t *flags, int64_t n, Workspace &ws,
                                hipStream_t s, uint64_t *pinned) {
     mj_pairs *out = new mj_pairs();
+    out->alloc = t_dev_alloc;
     if (n == 0) {
         out->d = (uint64_t *)dev_alloc(16);
         out->n = 0;
@@ -287,6 +296,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     }
     if (upto == 1) {
         mj_pairs *out = new mj_pairs();
+        out->alloc = t_dev_alloc;
         out->d = uniq;
         out->n = C;
         tm.fill(stats);
@@ -314,6 +324,7 @@ extern "C" mj_status mj_join(mj_ctx *ctx, const mj_strings *strings, const mj_pa
     check_strings(strings);
     check_params(params, strings->sigma, true);
     MJ_HIP(hipSetDevice(ctx->device));
+    AllocScope as(ctx->ws.alloc);
     *out = run_join(ctx, strings, params, (hipStream_t)stream, 2, stats);
     return MJ_OK;
     MJ_API_END
@@ -326,6 +337,7 @@ extern "C" mj_status mj_candidates(mj_ctx *ctx, const mj_strings *strings, const
     check_strings(strings);
     check_params(params, strings->sigma, true);
     MJ_HIP(hipSetDevice(ctx->device));
+    AllocScope as(ctx->ws.alloc);
     *out = run_join(ctx, strings, params, (hipStream_t)stream, 1, stats);
     return MJ_OK;
     MJ_API_END
@@ -338,6 +350,7 @@ extern "C" mj_status mj_partition(mj_ctx *ctx, const mj_strings *strings, const 
     check_strings(strings);
     check_params(params, strings->sigma, true);
     MJ_HIP(hipSetDevice(ctx->device));
+    AllocScope as(ctx->ws.alloc);
     hipStream_t s = (hipStream_t)stream;
     Workspace &ws = ctx->ws;
     Released rel{ws};
@@ -347,6 +360,7 @@ extern "C" mj_status mj_partition(mj_ctx *ctx, const mj_strings *strings, const 
     pack_planes(d, verify_planes(d.bits), ws, s);  // checks the symbol codes
     mj_records *r = new mj_records();
     r->rb.with_len = true;
+    r->rb.alloc = ctx->ws.alloc;
     try {
         partition_records(d, pp, halo, r->rb, ws, s, ctx->pinned);
         MJ_HIP(hipStreamSynchronize(s));
@@ -368,6 +382,7 @@ extern "C" mj_status mj_verify(mj_ctx *ctx, const mj_strings *strings, const mj_
     check_strings(strings);
     check_params(params, strings->sigma, true);
     MJ_HIP(hipSetDevice(ctx->device));
+    AllocScope as(ctx->ws.alloc);
     hipStream_t s = (hipStream_t)stream;
     Workspace &ws = ctx->ws;
     Released rel{ws};
@@ -396,6 +411,7 @@ extern "C" mj_status mj_index_build(mj_ctx *ctx, const mj_strings *strings, cons
     check_strings(strings);
     check_params(params, strings->sigma, true);
     MJ_HIP(hipSetDevice(ctx->device));
+    AllocScope as(ctx->ws.alloc);
     hipStream_t s = (hipStream_t)stream;
     Workspace &ws = ctx->ws;
     Released rel{ws};
@@ -403,6 +419,8 @@ extern "C" mj_status mj_index_build(mj_ctx *ctx, const mj_strings *strings, cons
     PartitionParams pp = to_pp(params, d.bits);
     pp.k_per_string = nullptr;  // not kept: the index stores per-string K below
     mj_index *ix = new mj_index();
+    ix->alloc = ctx->ws.alloc;
+    ix->rec.alloc = ctx->ws.alloc;
     try {
         ix->device = ctx->device;
         ix->n = d.n;
@@ -410,14 +428,13 @@ extern "C" mj_status mj_index_build(mj_ctx *ctx, const mj_strings *strings, cons
         ix->bits = d.bits;
         ix->total = d.total;
         ix->np = verify_planes(d.bits);
-        ix->chars = (uint8_t *)dev_alloc((size_t)d.total + 16);
         ix->offsets = (int64_t *)dev_alloc(((size_t)d.n + 1) * 8);
         ix->len = (int32_t *)dev_alloc(((size_t)d.n + 1) * 4);
         ix->kk = (int32_t *)dev_alloc(((size_t)d.n + 1) * 4);
-        if (d.total) MJ_HIP(hipMemcpyAsync(ix->chars, d.chars, (size_t)d.total, hipMemcpyDeviceToDevice, s));
         MJ_HIP(hipMemcpyAsync(ix->offsets, d.offsets, ((size_t)d.n + 1) * 8, hipMemcpyDeviceToDevice, s));
+        // the symbols are read from the caller's buffer during the build only: the index
+        // keeps the verifier's bit planes, not the input
         DevStrings di = d;
-        di.chars = ix->chars;
         di.offsets = ix->offsets;
         PartitionParams pk = to_pp(params, d.bits);
         int32_t halo = prepare_strings(di, pk, ws, s, ctx->pinned);
@@ -425,11 +442,9 @@ extern "C" mj_status mj_index_build(mj_ctx *ctx, const mj_strings *strings, cons
             MJ_HIP(hipMemcpyAsync(ix->len, di.len, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s));
             MJ_HIP(hipMemcpyAsync(ix->kk, di.kk, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s));
         }
-        pack_planes(di, ix->np, ws, s);
-        ix->plane_words = di.plane_words;
-        ix->planes = (uint32_t *)dev_alloc((size_t)ix->np * di.plane_words * 4);
-        MJ_HIP(hipMemcpyAsync(ix->planes, di.planes, (size_t)ix->np * di.plane_words * 4,
-                              hipMemcpyDeviceToDevice, s));
+        ix->plane_words = plane_words_for(di.total);
+        ix->planes = (uint32_t *)dev_alloc((size_t)ix->np * ix->plane_words * 4);
+        pack_planes(di, ix->np, ws, s, ix->planes);
         sorted_records(di, pk, halo, ix->rec, ws, s, ctx->pinned);
         if (pp.pi_table) {
             // searches partition their queries with this table long after the caller's
@@ -453,17 +468,25 @@ extern "C" mj_status mj_index_build(mj_ctx *ctx, const mj_strings *strings, cons
 extern "C" void mj_index_free(mj_index *ix) {
     if (!ix) return;
     (void)hipSetDevice(ix->device);
-    dev_free(ix->chars);
-    dev_free(ix->offsets);
-    dev_free(ix->len);
-    dev_free(ix->kk);
-    dev_free(ix->planes);
-    dev_free(ix->pi_table);
+    dev_free(ix->offsets, ix->alloc);
+    dev_free(ix->len, ix->alloc);
+    dev_free(ix->kk, ix->alloc);
+    dev_free(ix->planes, ix->alloc);
+    dev_free(ix->pi_table, ix->alloc);
     ix->rec.release();
     delete ix;
 }
 
 extern "C" int64_t mj_index_records(const mj_index *ix) { return ix ? ix->rec.count : 0; }
+
+extern "C" int64_t mj_index_bytes(const mj_index *ix) {
+    if (!ix) return 0;
+    int64_t b = ((int64_t)ix->n + 1) * (8 + 4 + 4);  // offsets, lengths, thresholds
+    b += (int64_t)ix->np * ix->plane_words * 4;
+    b += ix->rec.cap * (8 + 8 + (ix->rec.with_len ? 4 : 0));
+    if (ix->pi_table) b += (int64_t)8 << (ix->pp.q * ix->bits);
+    return b;
+}
 
 extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings *queries,
                                const mj_params *qparams, void *stream, mj_pairs **out,
@@ -474,11 +497,14 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
     if (!qparams) throw Error(MJ_EINVAL, "qparams is NULL");
     if (queries->sigma > ix->sigma || queries->sigma < 2)
         throw Error(MJ_EINVAL, "query alphabet must not exceed the index alphabet");
+    if (queries->packing == MJ_PACK_2BIT && ix->bits > 2)
+        throw Error(MJ_EINVAL, "2-bit packed queries need an index over at most 4 symbols");
     if (qparams->k < -1 || (qparams->k == -1 && !qparams->k_per_string))
         throw Error(MJ_EINVAL, "bad query threshold");
     if (qparams->k > 2047) throw Error(MJ_ECAPACITY, "threshold K exceeds the verifier's band limit (K <= 2047)");
     check_verifier(qparams);
     MJ_HIP(hipSetDevice(ctx->device));
+    AllocScope as(ctx->ws.alloc);
     hipStream_t s = (hipStream_t)stream;
     Workspace &ws = ctx->ws;
     Released rel{ws};
@@ -501,8 +527,8 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
         sort_records(rb.key, rb.val, rb.count, ws, s, ctx->pinned);
     }
     tm.mark();  // 2 sort
-    DevStrings id;
-    id.chars = ix->chars;
+    DevStrings id;  // the index keeps no symbols: planes, lengths and thresholds only
+    id.chars = nullptr;
     id.offsets = ix->offsets;
     id.n = ix->n;
     id.sigma = ix->sigma;
@@ -563,7 +589,7 @@ extern "C" mj_status mj_pairs_copy_to_host(const mj_pairs *p, uint64_t *dst, int
 
 extern "C" void mj_pairs_free(mj_pairs *p) {
     if (!p) return;
-    dev_free(p->d);
+    dev_free(p->d, p->alloc);
     delete p;
 }
 
@@ -588,6 +614,7 @@ extern "C" mj_status mj_records_copy_to_host(const mj_records *r, uint64_t *key,
     if (key) MJ_HIP(hipMemcpy(key, r->rb.key, (size_t)n * 8, hipMemcpyDeviceToHost));
     if (len && r->rb.len) MJ_HIP(hipMemcpy(len, r->rb.len, (size_t)n * 4, hipMemcpyDeviceToHost));
     if (sid || pos) {
+        AllocScope as(r->rb.alloc);
         int32_t *ds = (int32_t *)dev_alloc((size_t)n * 4), *dp = (int32_t *)dev_alloc((size_t)n * 4);
         unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 16384);
         hipLaunchKernelGGL(k_split_records, dim3(g), dim3(256), 0, 0, r->rb.val, n, ds, dp);

@@ -20,6 +20,7 @@ struct mj_ctx {
 struct mj_pairs {
     uint64_t *d = nullptr;
     int64_t n = 0;
+    mj_allocator alloc{};  // the allocator that made d
 };
 
 struct mj_records {
@@ -31,7 +32,6 @@ struct mj_index {
     PartitionParams pp{};
     int32_t n = 0, sigma = 0, bits = 0;
     int64_t total = 0;
-    uint8_t *chars = nullptr;
     int64_t *offsets = nullptr;
     int32_t *len = nullptr, *kk = nullptr;
     uint32_t *planes = nullptr;
@@ -39,6 +39,7 @@ struct mj_index {
     int np = 0;
     uint64_t *pi_table = nullptr;  // the index's own copy of an injected Pi table
     RecBuf rec;  // sorted by key
+    mj_allocator alloc{};  // the allocator that made the index's arrays
 };
 
 // Sets the thread-local error message and returns the status.

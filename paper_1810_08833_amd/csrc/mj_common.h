@@ -53,11 +53,30 @@ inline int symbol_bits(int sigma) {
     return b;
 }
 
+// ---------------------------------------------------------------- device memory
+// Device allocations come from the caller's mj_allocator when the context has one, else
+// from hipMalloc (alloc == nullptr).  Entry points install their context's allocator for
+// their thread with AllocScope; objects that outlive the call (results, indexes) keep a
+// copy of the allocator that made their memory and free with it.
+extern thread_local mj_allocator t_dev_alloc;
+struct AllocScope {
+    mj_allocator prev;
+    explicit AllocScope(const mj_allocator &a) : prev(t_dev_alloc) { t_dev_alloc = a; }
+    ~AllocScope() { t_dev_alloc = prev; }
+};
+void *dev_alloc(size_t bytes, const mj_allocator &a);
+void dev_free(void *p, const mj_allocator &a);
+// From / to the current thread's allocator.
+void *dev_alloc(size_t bytes);
+void dev_free(void *p);
+
 // ---------------------------------------------------------------- workspace
 // Grow-only cache of device blocks; blocks handed out during one call are released
-// together at its end and reused by the next call.
+// together at its end and reused by the next call.  Blocks come from `alloc` (the
+// context's allocator; hipMalloc when its alloc is null).
 class Workspace {
   public:
+    mj_allocator alloc{};
     ~Workspace();
     void *get(size_t bytes);
     template <class T> T *get_n(size_t n) { return static_cast<T *>(get(n * sizeof(T) + 16)); }
@@ -89,9 +108,6 @@ class Workspace {
     size_t arena_bytes_ = 0, arena_used_ = 0;
 };
 
-// Owned device allocation (results).
-void *dev_alloc(size_t bytes);
-void dev_free(void *p);
 
 // ---------------------------------------------------------------- kernel timers
 // HIP events recorded on the launching stream around each launch of a hot kernel;
@@ -157,6 +173,7 @@ T read_back(const T *dev, hipStream_t s, void *pinned) {
 // A string collection prepared on the device.
 struct DevStrings {
     const uint8_t *chars = nullptr;
+    int packing = MJ_PACK_U8;  // MJ_PACK_2BIT: four 2-bit symbols per byte, first in the low bits
     const int64_t *offsets = nullptr;
     int32_t n = 0;
     int32_t sigma = 0;
@@ -196,6 +213,7 @@ struct RecBuf {
     int64_t cap = 0, count = 0;
     bool with_len = false;
     Workspace *ws = nullptr;
+    mj_allocator alloc{};  // owned arrays (ws == nullptr): the allocator that made them
     void reserve(int64_t need, hipStream_t s);
     void release();
 };
@@ -205,7 +223,11 @@ int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, 
                         uint64_t *host_scratch);       // returns the halo radius needed
 // Builds the verifier's bit planes and checks every symbol against sigma (the result in
 // d.symbol_err, read with the partition stage's counts or by check_symbols).
-void pack_planes(DevStrings &d, int planes, Workspace &ws, hipStream_t s);
+void pack_planes(DevStrings &d, int planes, Workspace &ws, hipStream_t s,
+                 uint32_t *dest = nullptr);  // dest: plane_words_for(total) * planes words
+// Plane words per plane for `total` symbols (with padding: verifier windows read past the
+// end).
+inline int64_t plane_words_for(int64_t total) { return (total + 31) / 32 + 96; }
 // Reads d.symbol_err back (synchronises); MJ_EINVAL when a symbol code is >= sigma.
 void check_symbols(const DevStrings &d, hipStream_t s, uint64_t *host_scratch);
 // Appends the records of every partition of every repetition (repetition rho seeds Pi

@@ -63,6 +63,10 @@ extern "C" mj_status mj_verify_noalloc(const mj_strings *strings, const mj_param
         if (strings->n < 0 || (strings->n > 0 && !strings->offsets))
             throw Error(MJ_EINVAL, "bad strings");
         if (strings->sigma < 2 || strings->sigma > 256) throw Error(MJ_EINVAL, "sigma must be in 2..256");
+        if (strings->packing != MJ_PACK_U8 && strings->packing != MJ_PACK_2BIT)
+            throw Error(MJ_EINVAL, "packing must be MJ_PACK_U8 or MJ_PACK_2BIT");
+        if (strings->packing == MJ_PACK_2BIT && (strings->sigma > 4 || ((uintptr_t)strings->chars & 3)))
+            throw Error(MJ_EINVAL, "2-bit packing needs sigma <= 4 and 4-byte aligned words");
         if (params->k > 2047) throw Error(MJ_ECAPACITY, "threshold K exceeds the verifier's band limit (K <= 2047)");
         if (params->k < -1 || (params->k == -1 && !params->k_per_string))
             throw Error(MJ_EINVAL, "bad threshold");
@@ -75,6 +79,7 @@ extern "C" mj_status mj_verify_noalloc(const mj_strings *strings, const mj_param
         struct Release { Workspace &w; ~Release() { w.release_all(); } } rel{ws};
         DevStrings d;
         d.chars = static_cast<const uint8_t *>(strings->chars);
+        d.packing = strings->packing;
         d.offsets = strings->offsets;
         d.n = strings->n;
         d.sigma = strings->sigma;

@@ -178,15 +178,61 @@ __global__ void k_pack_planes(const uint8_t *chars, int64_t total, uint32_t *pla
     if (over) atomicOr(err, 1u);
 }
 
-void pack_planes(DevStrings &d, int np, Workspace &ws, hipStream_t s) {
-    d.plane_words = (d.total + 31) / 32 + 96;  // padding: windows may read past the end
-    d.planes = ws.get_n<uint32_t>((size_t)np * d.plane_words);
+// Planes of 2-bit packed symbols (four per byte, the first in the low bits): the 32
+// symbols of plane word w are the 64 bits of packed words 2w and 2w + 1, plane 0 their
+// even bits and plane 1 their odd bits, gathered by halving shift-and-mask steps.  Bits
+// past the last symbol are cleared; with sigma < 4 a code >= sigma sets *err.
+__device__ __forceinline__ uint32_t even_bits64(uint64_t x) {
+    x &= 0x5555555555555555ull;
+    x = (x | (x >> 1)) & 0x3333333333333333ull;
+    x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+    return (uint32_t)(x | (x >> 16));
+}
+
+__global__ void k_pack_planes_2bit(const uint32_t *packed, int64_t total, uint32_t *planes,
+                                   int64_t plane_words, uint32_t sigma, uint32_t *err) {
+    int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t nin = (total + 15) / 16;  // packed words the caller holds
+    uint32_t over = 0;
+    for (; w < plane_words; w += stride) {
+        const uint32_t lo = 2 * w < nin ? packed[2 * w] : 0u;
+        const uint32_t hi = 2 * w + 1 < nin ? packed[2 * w + 1] : 0u;
+        const uint64_t x = ((uint64_t)hi << 32) | lo;
+        uint32_t p0 = even_bits64(x), p1 = even_bits64(x >> 1);
+        const int64_t valid = total - 32 * w;  // symbols of this word inside the input
+        if (valid < 32) {
+            const uint32_t keep = valid <= 0 ? 0u : (1u << valid) - 1u;
+            p0 &= keep;
+            p1 &= keep;
+        }
+        if (sigma == 3) over |= p0 & p1;  // code 3
+        if (sigma == 2) over |= p1;       // codes 2 and 3
+        planes[2 * w] = p0;
+        planes[2 * w + 1] = p1;
+    }
+    if (over) atomicOr(err, 1u);
+}
+
+void pack_planes(DevStrings &d, int np, Workspace &ws, hipStream_t s, uint32_t *dest) {
+    d.plane_words = plane_words_for(d.total);
+    d.planes = dest ? dest : ws.get_n<uint32_t>((size_t)np * d.plane_words);
     uint32_t *err = ws.get_n<uint32_t>(2);
     fill_u32(err, 0, 1, s);
     d.symbol_err = err;
     int aligned = ((uintptr_t)d.chars & 15) == 0 ? 1 : 0;
     const uint32_t sg = (uint32_t)d.sigma;
     const dim3 grid(grid_for(d.plane_words, 256, 16384));
+    if (d.packing == MJ_PACK_2BIT) {
+        if (np != 2) throw Error(MJ_EINVAL, "2-bit packing has two planes");
+        hipLaunchKernelGGL(k_pack_planes_2bit, grid, dim3(256), 0, s,
+                           reinterpret_cast<const uint32_t *>(d.chars), d.total, d.planes,
+                           d.plane_words, sg, err);
+        MJ_LAUNCH_CHECK();
+        return;
+    }
     switch (np) {
         case 2: hipLaunchKernelGGL(k_pack_planes<2>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned, sg, err); break;
         case 4: hipLaunchKernelGGL(k_pack_planes<4>, grid, dim3(256), 0, s, d.chars, d.total, d.planes, d.plane_words, aligned, sg, err); break;
@@ -275,7 +321,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     const uint8_t *__restrict__ chars, const int64_t *__restrict__ off, int32_t n, int64_t total,
     int q, int bits, uint64_t salt, const uint64_t *__restrict__ table,
     const uint16_t *__restrict__ rank, const int32_t *__restrict__ rr, int TP, int H,
-    const TileDesc *__restrict__ tdesc, int aligned4, uint64_t *__restrict__ bitmap,
+    const TileDesc *__restrict__ tdesc, int aligned4, int packed, uint64_t *__restrict__ bitmap,
     uint32_t *__restrict__ tile_count) {
     constexpr bool RANKED = sizeof(V) == 4;
     // LDS slots hold keys: ranks as 16 bits (ranks < 2^12; the sentinel 0xFFFF is above
@@ -291,10 +337,12 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     // per region slot: bits 0-13 the radius if the position is interior (else 0), bit 14
     // set where a full q-gram starts
     __shared__ __align__(16) uint16_t pinfo[REGION];
-    // symbols, word-aligned with the input: NR + q - 1 bytes from offset sh < 4, read as
-    // whole words (and up to 16 bytes past the last q-gram by the hashing loop)
+    // symbols, one byte each, word-aligned with the input: NR + q - 1 bytes from offset
+    // sh (< 4; < 16 for 2-bit packed input, where q <= 32), read as whole words (and up to
+    // 16 bytes past the last q-gram by the hashing loop)
     constexpr int CH_WORDS = (REGION + 64 + 8) / 4 + 4;
     constexpr int CW = (CH_WORDS + AT_THREADS - 1) / AT_THREADS;  // words per thread
+    constexpr int CWP = (CH_WORDS / 4 + 1 + AT_THREADS - 1) / AT_THREADS;  // packed words
     __shared__ __align__(16) uint32_t ch32[CH_WORDS];
     uint8_t *const ch = reinterpret_cast<uint8_t *>(ch32);
     // anchor and string-start flags of the tile positions, one bit each
@@ -325,12 +373,24 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         }
     }
     // symbols of the region: byte sh + idx of ch holds global position base + idx, with
-    // ch starting at a 4-byte boundary of the input so whole words are copied
-    const int sh = (int)(base & 3);
+    // ch starting at a 4-byte boundary of the input (16 symbols: a 32-bit word of 2-bit
+    // packed input) so whole words are copied
+    const int sh = (int)(base & (packed ? 15 : 3));
     const int64_t chbase = base - sh;
-    const int nwords = (NR + q + sh + 3) / 4;  // <= CH_WORDS (q <= 64)
+    const int nwords = (NR + q + sh + 3) / 4;  // <= CH_WORDS (q <= 64; q <= 32 packed)
     uint32_t cw[CW];
-    if (aligned4 && chbase >= 0 && chbase + 4 * (int64_t)nwords <= total) {
+    if (packed) {
+        // 2-bit input: a thread loads whole packed words (16 symbols) and spreads them to
+        // bytes when it stores them (0 outside the input)
+        const int64_t pw0 = chbase >> 4, nin = (total + 15) >> 4;
+        const int npw = (nwords + 3) / 4;
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(chars);
+#pragma unroll
+        for (int i = 0; i < CWP; i++) {
+            const int k = tid + AT_THREADS * i;
+            cw[i] = (k < npw && pw0 + k >= 0 && pw0 + k < nin) ? src[pw0 + k] : 0u;
+        }
+    } else if (aligned4 && chbase >= 0 && chbase + 4 * (int64_t)nwords <= total) {
         const uint32_t *src = reinterpret_cast<const uint32_t *>(chars) + (chbase >> 2);
 #pragma unroll
         for (int i = 0; i < CW; i++) {
@@ -353,9 +413,26 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     }
     for (int w = tid; w < REGION / 32; w += AT_THREADS) aflag[w] = 0;
     if (tid < 32) reinterpret_cast<uint32_t *>(&td)[tid] = tdw;
+    if (packed) {
 #pragma unroll
-    for (int i = 0; i < CW; i++)
-        if (tid + AT_THREADS * i < nwords) ch32[tid + AT_THREADS * i] = cw[i];
+        for (int i = 0; i < CWP; i++) {
+            const int k = tid + AT_THREADS * i;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (4 * k + j < nwords) {
+                    // four 2-bit symbols (first in the low bits) to four bytes
+                    uint32_t x = (cw[i] >> (8 * j)) & 0xFFu;
+                    x = (x | (x << 12)) & 0x000F000Fu;
+                    x = (x | (x << 6)) & 0x03030303u;
+                    ch32[4 * k + j] = x;
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < CW; i++)
+            if (tid + AT_THREADS * i < nwords) ch32[tid + AT_THREADS * i] = cw[i];
+    }
     if constexpr (RANKED) {
 #pragma unroll
         for (int i = 0; i < RK; i++)
@@ -762,7 +839,9 @@ __device__ __forceinline__ uint64_t fold61(uint64_t s) { return (s & P61) + (s >
 // a chunk's value is the sum of one entry of each, and P[j 2^b] = B^j.  pt == 0 (b <= 2)
 // puts before them T[x] = sum_k (x_k + 1) B^(3-k) for every packed chunk x of 4 symbols
 // and the same values times B^4 (2 * 2^(4b) entries).
-__global__ void k_phi_table(int nc, int bits, uint64_t B, int pt, uint64_t *__restrict__ T) {
+// lsb != 0 (2-bit packed input): a chunk x holds its first symbol in the low bits, so a
+// packed byte is its own table index.
+__global__ void k_phi_table(int nc, int bits, uint64_t B, int pt, int lsb, uint64_t *__restrict__ T) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nc) return;
     uint64_t h = 0;
@@ -774,7 +853,7 @@ __global__ void k_phi_table(int nc, int bits, uint64_t B, int pt, uint64_t *__re
     } else {
         const int x = idx & ((1 << (4 * bits)) - 1);
         for (int k = 0; k < 4; k++)
-            h = horner_step(h, B, (uint32_t)(x >> (bits * (3 - k))) & ((1u << bits) - 1u));
+            h = horner_step(h, B, (uint32_t)(x >> (bits * (lsb ? k : 3 - k))) & ((1u << bits) - 1u));
         if (idx >> (4 * bits))
             for (int k = 0; k < 4; k++) h = mulmod61(h, B);
     }
@@ -789,7 +868,9 @@ constexpr int REC_STAGE_WORDS = 6144;  // 24 KB: the symbols of a block's record
 // LDS with coalesced word loads (a lane reading its own partition directly touches a line
 // per lane and load); a range longer than the stage is read from global memory instead.
 // Short partitions are read directly: the copy and its barriers would cost more.
-template <bool STAGED>
+// PACKED: 2-bit input (four symbols per byte, the first in the low bits); a packed byte is
+// a 4-symbol chunk and, with the chunk tables built in that order, its own table index.
+template <bool STAGED, bool PACKED>
 __global__ __launch_bounds__(REC_THREADS) void k_records(
     const int64_t *__restrict__ apos, int64_t R, const int64_t *__restrict__ off, int32_t n,
     const uint8_t *__restrict__ chars, int64_t total, int aligned4,
@@ -804,33 +885,36 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
     const int nc = pbase + 8 * nsym;
     for (int t = threadIdx.x; t < nc; t += blockDim.x) Ts[t] = table[t];
     const uint32_t m = (1u << bits) - 1u;
-    // the packed chunk of the 4 symbol bytes of v (pt == 0)
-    auto pack4 = [&](uint32_t v) -> uint32_t {
+    // a chunk word holds 4 symbols, SU bits apart (bytes; 2-bit fields when packed)
+    constexpr int SU = PACKED ? 2 : 8;
+    // the table index of a chunk word (pt == 0)
+    auto cidx = [&](uint32_t v) -> uint32_t {
+        if constexpr (PACKED) return v & 0xFFu;
         return ((v & m) << (3 * bits)) | (((v >> 8) & m) << (2 * bits)) | (((v >> 16) & m) << bits) |
                ((v >> 24) & m);
     };
     // sum over the 4 symbols x_k of v of (x_k + 1) B^(j0 + 3 - k) (pt == 1): four terms
     auto pw4 = [&](uint32_t v, int j0) -> uint64_t {
-        return Ts[(j0 + 3) * nsym + (v & m)] + Ts[(j0 + 2) * nsym + ((v >> 8) & m)] +
-               Ts[(j0 + 1) * nsym + ((v >> 16) & m)] + Ts[j0 * nsym + ((v >> 24) & m)];
+        return Ts[(j0 + 3) * nsym + (v & m)] + Ts[(j0 + 2) * nsym + ((v >> SU) & m)] +
+               Ts[(j0 + 1) * nsym + ((v >> (2 * SU)) & m)] + Ts[j0 * nsym + ((v >> (3 * SU)) & m)];
     };
-    // h B^k + sum over the k < 4 symbols x_i at bytes 0 .. k-1 of v of (x_i + 1) B^(k-1-i)
+    // h B^k + sum over the k < 4 symbols x_i in slots 0 .. k-1 of v of (x_i + 1) B^(k-1-i)
     auto partial = [&](uint64_t h, uint32_t v, int k) -> uint64_t {
         uint64_t sum = mulmod61(h, Ts[pbase + k * nsym]);  // P[k 2^b] = B^k
-        for (int i = 0; i < k; i++) sum += Ts[pbase + (k - 1 - i) * nsym + ((v >> (8 * i)) & m)];
+        for (int i = 0; i < k; i++) sum += Ts[pbase + (k - 1 - i) * nsym + ((v >> (SU * i)) & m)];
         const uint64_t x = fold61(sum);
         return x >= P61 ? x - P61 : x;
     };
-    // Horner's rule over [g, g1) from symbol bytes sym(i) and aligned words word(i), a word
-    // being readable when it ends at or before wend.  Every table entry and h are below
-    // p = 2^61 - 1, so a sum of at most five of them stays below 2^64 and one fold brings
-    // it below 2^61 + 5 < 2p.  The symbols before the first word boundary and after the
-    // last whole chunk go in one step each.
+    // Horner's rule over [g, g1) from symbols sym(i) and chunk words word(i) (i a multiple
+    // of 4), a chunk being readable when it ends at or before wend.  Every table entry and
+    // h are below p = 2^61 - 1, so a sum of at most five of them stays below 2^64 and one
+    // fold brings it below 2^61 + 5 < 2p.  The symbols before the first chunk boundary
+    // and after the last whole chunk go in one step each.
     auto hash = [&](uint64_t h, int64_t g, int64_t g1, int64_t wend, auto sym, auto word) -> uint64_t {
-        if (aligned4) {
+        if (PACKED || aligned4) {
             if ((g & 3) && g < g1 && (g | 3) < wend) {
                 const int k = (int)min<int64_t>(4 - (g & 3), g1 - g);
-                h = partial(h, word(g & ~(int64_t)3) >> (8 * (g & 3)), k);
+                h = partial(h, word(g & ~(int64_t)3) >> (SU * (g & 3)), k);
                 g += k;
             }
             for (; g < g1 && (g & 3); g++) h = horner_step(h, B, sym(g) & m);
@@ -838,7 +922,7 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
                 const uint32_t v0 = word(g), v1 = word(g + 4);
                 uint64_t x;
                 if (!pt) {
-                    x = fold61(mulmod61(h, B8) + Ts[n4 + pack4(v0)] + Ts[pack4(v1)]);
+                    x = fold61(mulmod61(h, B8) + Ts[n4 + cidx(v0)] + Ts[cidx(v1)]);
                 } else {
                     x = fold61(mulmod61(h, B8) + pw4(v0, 4));
                     x = fold61(x + pw4(v1, 0));
@@ -847,7 +931,7 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
             }
             if (g + 4 <= g1) {
                 const uint32_t v = word(g);
-                const uint64_t x = fold61(mulmod61(h, B4) + (pt ? pw4(v, 0) : Ts[pack4(v)]));
+                const uint64_t x = fold61(mulmod61(h, B4) + (pt ? pw4(v, 0) : Ts[cidx(v)]));
                 h = x >= P61 ? x - P61 : x;
                 g += 4;
             }
@@ -860,6 +944,17 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
         return h;
     };
     const uint32_t *w = reinterpret_cast<const uint32_t *>(chars);
+    // global accessors: a symbol, and the chunk word at a multiple of 4
+    auto gsym = [&](int64_t g) -> uint32_t {
+        if constexpr (PACKED) return (uint32_t)(chars[g >> 2] >> (2 * (g & 3))) & 3u;
+        return chars[g];
+    };
+    auto gword = [&](int64_t g) -> uint32_t {
+        if constexpr (PACKED) return chars[g >> 2];
+        return w[g >> 2];
+    };
+    // packed input: the whole words (16 symbols) the caller holds; unpacked: whole symbols
+    const int64_t gend = PACKED ? ((total + 15) & ~(int64_t)15) : total;
     // the string of the partition starting at g0 and its first position
     auto owner = [&](int64_t g0, int32_t &sidx, int64_t &sbeg) {
         const TileDesc &d = td[g0 / TP];
@@ -882,32 +977,33 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
             int64_t sbeg;
             owner(g0, sidx, sbeg);
             const int64_t L = g1 - g0;
-            const uint64_t h = hash((uint64_t)L % P61, g0, g1, total,
-                                    [&](int64_t g) -> uint32_t { return chars[g]; },
-                                    [&](int64_t g) -> uint32_t { return w[g >> 2]; });
+            const uint64_t h = hash((uint64_t)L % P61, g0, g1, gend, gsym, gword);
             key[k] = mix64(h ^ salt_f);
             val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
             if (len) len[k] = (uint32_t)L;
         }
         return;
     }
+    // symbols per staged word, and the alignment of the staged range
+    constexpr int SPW = PACKED ? 16 : 4;
     for (int64_t kb = (int64_t)blockIdx.x * REC_THREADS; kb < R;
          kb += (int64_t)gridDim.x * REC_THREADS) {
         const int64_t kend = min<int64_t>(kb + REC_THREADS, R);
-        const int64_t sb = apos[kb] & ~(int64_t)3;  // word-aligned start of the range
-        const int64_t nwords = (apos[kend] - sb + 3) >> 2;
-        const bool staged = aligned4 && nwords <= REC_STAGE_WORDS;
+        const int64_t sb = apos[kb] & ~(int64_t)(SPW - 1);  // word-aligned start of the range
+        const int64_t nwords = (apos[kend] - sb + SPW - 1) / SPW;
+        const bool staged = (PACKED || aligned4) && nwords <= REC_STAGE_WORDS;
         __syncthreads();  // the table is in place; the previous sweep is done with the stage
         if (staged) {
             for (int64_t i = threadIdx.x; i < nwords; i += REC_THREADS) {
-                const int64_t gp = sb + 4 * i;
+                const int64_t gp = sb + SPW * i;
                 uint32_t v;
-                if (gp + 4 <= total) {
-                    v = w[gp >> 2];
+                if (gp + SPW <= gend) {
+                    v = w[gp / SPW];
                 } else {
                     v = 0;
-                    for (int bb = 0; bb < 4; bb++)
-                        if (gp + bb < total) v |= (uint32_t)chars[gp + bb] << (8 * bb);
+                    if constexpr (!PACKED)
+                        for (int bb = 0; bb < 4; bb++)
+                            if (gp + bb < total) v |= (uint32_t)chars[gp + bb] << (8 * bb);
                 }
                 stage[i] = v;
             }
@@ -923,11 +1019,17 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
         uint64_t h = (uint64_t)L % P61;
         if (staged) {
             const uint8_t *sbytes = reinterpret_cast<const uint8_t *>(stage);
-            h = hash(h, g0, g1, sb + 4 * nwords, [&](int64_t g) -> uint32_t { return sbytes[g - sb]; },
-                     [&](int64_t g) -> uint32_t { return stage[(g - sb) >> 2]; });
+            auto ssym = [&](int64_t g) -> uint32_t {
+                if constexpr (PACKED) return (uint32_t)(sbytes[(g - sb) >> 2] >> (2 * (g & 3))) & 3u;
+                return sbytes[g - sb];
+            };
+            auto sword = [&](int64_t g) -> uint32_t {
+                if constexpr (PACKED) return sbytes[(g - sb) >> 2];
+                return stage[(g - sb) >> 2];
+            };
+            h = hash(h, g0, g1, sb + SPW * nwords, ssym, sword);
         } else {
-            h = hash(h, g0, g1, total, [&](int64_t g) -> uint32_t { return chars[g]; },
-                     [&](int64_t g) -> uint32_t { return w[g >> 2]; });
+            h = hash(h, g0, g1, gend, gsym, gword);
         }
         key[k] = mix64(h ^ salt_f);
         val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
@@ -938,7 +1040,7 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
 void RecBuf::reserve(int64_t need, hipStream_t s) {
     if (need <= cap) return;
     int64_t nc = std::max<int64_t>(need, cap + cap / 2);
-    auto get = [&](size_t bytes) -> void * { return ws ? ws->get(bytes) : dev_alloc(bytes); };
+    auto get = [&](size_t bytes) -> void * { return ws ? ws->get(bytes) : dev_alloc(bytes, alloc); };
     uint64_t *k2 = (uint64_t *)get((size_t)nc * 8);
     uint64_t *v2 = (uint64_t *)get((size_t)nc * 8);
     uint32_t *l2 = with_len ? (uint32_t *)get((size_t)nc * 4) : nullptr;
@@ -949,14 +1051,14 @@ void RecBuf::reserve(int64_t need, hipStream_t s) {
         MJ_HIP(hipStreamSynchronize(s));
     }
     if (!ws) {
-        dev_free(key); dev_free(val); dev_free(len);
+        dev_free(key, alloc); dev_free(val, alloc); dev_free(len, alloc);
     }
     key = k2; val = v2; len = l2; cap = nc;
 }
 
 void RecBuf::release() {
     if (!ws) {
-        dev_free(key); dev_free(val); dev_free(len);
+        dev_free(key, alloc); dev_free(val, alloc); dev_free(len, alloc);
     }
     key = val = nullptr; len = nullptr; cap = count = 0;
 }
@@ -981,6 +1083,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     if ((size_t)reps * 4 + 4 > HOST_SCRATCH_BYTES / 2) throw Error(MJ_EINVAL, "too many repetitions");
     const int code_bits = p.q * d.bits;
     const int aligned4 = ((uintptr_t)d.chars & 3) == 0 ? 1 : 0;
+    const int packed = d.packing == MJ_PACK_2BIT ? 1 : 0;
 
     // phase 1: anchors of every repetition (Pi seeded with seed + rho), their counts
     int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
@@ -1004,7 +1107,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
 #define MJ_ANCHORS(R, V)                                                                        \
         hipLaunchKernelGGL((k_anchor_tiles<R, V>), dim3((unsigned)ntiles), dim3(AT_THREADS), rank_lds, s, \
                            d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, rank, \
-                           d.rr, TP, H, ts, aligned4, bitmap[rho], tcount[rho])
+                           d.rr, TP, H, ts, aligned4, packed, bitmap[rho], tcount[rho])
         const size_t rank_lds = rank ? ((size_t)2 << code_bits) + 16 : 0;
         if (rank) {
             if (region == 2048) MJ_ANCHORS(2048, uint32_t); else MJ_ANCHORS(4096, uint32_t);
@@ -1044,14 +1147,16 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     const uint64_t salt_f = mix64(p.seed + GAMMA);
     // Horner steps of 8 symbols (see k_phi_table): power tables, and for b <= 2 tables of
     // all 4-symbol chunks before them (at most 2,048 entries)
-    const int pt = d.bits > 2 ? 1 : 0;
+    // (2-bit packed input with b = 1 has chunks of 2-bit fields, not 4-bit codes: the
+    // power tables serve it)
+    const int pt = (d.bits > 2 || (packed && d.bits != 2)) ? 1 : 0;
     uint64_t B4 = 1;
     for (int i = 0; i < 4; i++) B4 = (uint64_t)(((unsigned __int128)B4 * B) % P61);
     const uint64_t B8 = (uint64_t)(((unsigned __int128)B4 * B4) % P61);
     const int nc = (pt ? 0 : 2 << (4 * d.bits)) + (8 << d.bits);
     uint64_t *phi_table = ws.get_n<uint64_t>(nc);
     hipLaunchKernelGGL(k_phi_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, d.bits, B, pt,
-                       phi_table);
+                       packed, phi_table);
     MJ_LAUNCH_CHECK();
     int64_t maxR = 0;
     for (int rho = 0; rho < reps; rho++) maxR = std::max(maxR, R[rho]);
@@ -1065,7 +1170,9 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
             int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
             // stage the symbols when partitions average 24 symbols or more
             const bool stg = d.total >= 24 * R[rho];
-            hipLaunchKernelGGL(stg ? k_records<true> : k_records<false>,
+            auto kern = packed ? (stg ? k_records<true, true> : k_records<false, true>)
+                               : (stg ? k_records<true, false> : k_records<false, false>);
+            hipLaunchKernelGGL(kern,
                                dim3(grid_for(R[rho], REC_THREADS, 65535)), dim3(REC_THREADS),
                                (size_t)nc * 8, s, apos, R[rho], d.offsets, d.n, d.chars, d.total,
                                aligned4, ts, TP, B, salt_f, phi_table, pt, d.bits, B4, B8,

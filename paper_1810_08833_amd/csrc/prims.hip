@@ -10,9 +10,35 @@
 namespace mj {
 
 // ---------------------------------------------------------------- workspace / alloc
+thread_local mj_allocator t_dev_alloc{};
+
+void *dev_alloc(size_t bytes, const mj_allocator &a) {
+    void *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (a.alloc) {
+        p = a.alloc(bytes, a.user);
+        if (!p) throw Error(MJ_ENOMEM, "the caller's allocator refused " + std::to_string(bytes) + " bytes");
+        return p;
+    }
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(MJ_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+}
+
+void dev_free(void *p, const mj_allocator &a) {
+    if (!p) return;
+    if (a.alloc) a.free(p, a.user);
+    else (void)hipFree(p);
+}
+
+void *dev_alloc(size_t bytes) { return dev_alloc(bytes, t_dev_alloc); }
+void dev_free(void *p) { dev_free(p, t_dev_alloc); }
+
 Workspace::~Workspace() {
-    for (auto &b : blocks_) (void)hipFree(b.p);
-    if (scan.state && !arena()) (void)hipFree(scan.state);
+    for (auto &b : blocks_) dev_free(b.p, alloc);
+    if (scan.state && !arena()) dev_free(scan.state, alloc);
 }
 
 void Workspace::bind_arena(void *base, size_t bytes) {
@@ -45,17 +71,16 @@ void *Workspace::get(size_t bytes) {
         return best->p;
     }
     void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        // free idle blocks and retry once
+    try {
+        p = dev_alloc(bytes, alloc);
+    } catch (const Error &) {
+        // free idle blocks and retry once (the stream work of earlier calls is complete:
+        // every entry point synchronises before it returns)
         for (auto it = blocks_.begin(); it != blocks_.end();) {
-            if (!it->used) { (void)hipFree(it->p); held_ -= it->n; it = blocks_.erase(it); }
+            if (!it->used) { dev_free(it->p, alloc); held_ -= it->n; it = blocks_.erase(it); }
             else ++it;
         }
-        if (hipMalloc(&p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            throw Error(MJ_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-        }
+        p = dev_alloc(bytes, alloc);
     }
     blocks_.push_back({p, bytes, true});
     held_ += bytes;
@@ -67,19 +92,6 @@ void Workspace::release_all() {
     if (arena()) arena_used_ = ARENA_SCAN_BYTES;
 }
 
-void *dev_alloc(size_t bytes) {
-    void *p = nullptr;
-    if (bytes == 0) bytes = 16;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        throw Error(MJ_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-    }
-    return p;
-}
-
-void dev_free(void *p) {
-    if (p) (void)hipFree(p);
-}
 
 // ---------------------------------------------------------------- kernel timers
 void KTimer::create() {
@@ -340,7 +352,7 @@ static void scan_u32_single_pass(const In *in, uint32_t *out, int64_t n, int64_t
     static_assert((SCAN_MAX_TILES + 64) * 8 <= Workspace::ARENA_SCAN_BYTES, "arena scan state");
     if (!sc.state) {
         // the ticket on a line of its own after the tile words; all zero (epoch 0 unused)
-        sc.state = (uint64_t *)dev_alloc((size_t)(SCAN_MAX_TILES + 64) * 8);
+        sc.state = (uint64_t *)dev_alloc((size_t)(SCAN_MAX_TILES + 64) * 8, ws.alloc);
         sc.ticket = (unsigned long long *)(sc.state + SCAN_MAX_TILES + 32);
         fill_u64(sc.state, 0, SCAN_MAX_TILES + 64, s);
         sc.base = 0;

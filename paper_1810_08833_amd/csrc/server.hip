@@ -64,7 +64,7 @@ void mj_server::worker(int w) {
     hipStream_t st = nullptr;
     mj_ctx *ctx = nullptr;
     if (hipStreamCreate(&st) != hipSuccess) return;
-    if (mj_ctx_create(device, &ctx) != MJ_OK) {
+    if (mj_ctx_create(device, nullptr, &ctx) != MJ_OK) {
         (void)hipStreamDestroy(st);
         return;
     }
@@ -137,7 +137,7 @@ void mj_server::worker(int w) {
             }
         }
         if (status == MJ_OK) {
-            mj_strings qs{dchars, doff, n, ix->sigma};
+            mj_strings qs{dchars, doff, n, ix->sigma, MJ_PACK_U8, 0};
             mj_params qp{};
             qp.q = ix->pp.q;
             qp.k = -1;

@@ -206,9 +206,20 @@ __global__ __launch_bounds__(256) void k_verify_bp(const uint64_t *__restrict__ 
 // ---------------------------------------------------------------- wide path
 constexpr int DP_MAX_NT = 64;  // cells per lane: band up to 64 * 64 = 4096 (K <= 2047)
 
+// The symbol at global position g, gathered from its bit in each of the np interleaved
+// planes (the only copy of the strings the library is sure to hold: the input may be
+// 2-bit packed, and an index keeps no symbols).
+__device__ __forceinline__ int plane_symbol(const uint32_t *__restrict__ planes, int np, int64_t g) {
+    const uint32_t *w = planes + (g >> 5) * np;
+    const int b = (int)(g & 31);
+    int c = 0;
+    for (int p = 0; p < np; p++) c |= (int)((w[p] >> b) & 1u) << p;
+    return c;
+}
+
 __global__ __launch_bounds__(64) void k_verify_dp(const uint64_t *__restrict__ pairs,
                                                   const int64_t *__restrict__ sel, int64_t n,
-                                                  VSet A, VSet B, int kmode,
+                                                  VSet A, VSet B, int kmode, int np,
                                                   uint8_t *__restrict__ flags,
                                                   unsigned long long *cells) {
     const int lane = threadIdx.x;
@@ -220,8 +231,8 @@ __global__ __launch_bounds__(64) void k_verify_dp(const uint64_t *__restrict__ p
         int32_t K = kmode == 0 ? max(A.kk[ia], B.kk[ib]) : A.kk[ia];
         // rows over the shorter string x, columns over the longer y
         bool a_short = ma <= mb;
-        const uint8_t *X = a_short ? A.chars + A.off[ia] : B.chars + B.off[ib];
-        const uint8_t *Y = a_short ? B.chars + B.off[ib] : A.chars + A.off[ia];
+        const uint32_t *XP = a_short ? A.planes : B.planes, *YP = a_short ? B.planes : A.planes;
+        const int64_t xo = a_short ? A.off[ia] : B.off[ib], yo = a_short ? B.off[ib] : A.off[ia];
         int32_t mx = a_short ? ma : mb, ny = a_short ? mb : ma;
         uint8_t result = 0;
         const int W = 2 * K + 1;
@@ -241,7 +252,7 @@ __global__ __launch_bounds__(64) void k_verify_dp(const uint64_t *__restrict__ p
             }
             bool ok = true;
             for (int i = 1; i <= mx && ok; i++) {
-                int xc = X[i - 1];
+                int xc = plane_symbol(XP, np, xo + i - 1);
                 int up_next = __shfl_down(prev[0], 1, 64);  // first cell of the next lane
                 if (lane == 63) up_next = CAP;
                 int run = 0x3FFFFFFF;  // lane-local prefix min of U[d] - d
@@ -257,7 +268,7 @@ __global__ __launch_bounds__(64) void k_verify_dp(const uint64_t *__restrict__ p
                     } else {
                         int up = (t + 1 < NT) ? prev[t + 1] : up_next;
                         if (d + 1 >= W) up = CAP;
-                        int diag = prev[t] + (xc != Y[j - 1] ? 1 : 0);
+                        int diag = prev[t] + (xc != plane_symbol(YP, np, yo + j - 1) ? 1 : 0);
                         U = min(up + 1, diag);
                     }
                     run = min(run, U - d);
@@ -449,7 +460,7 @@ int64_t verify_pairs(const uint64_t *pairs, int64_t n, const DevStrings &A, cons
                                pairs, (const int64_t *)nullptr, n, va, vb, kmode, flags, cells);
         } else {
             hipLaunchKernelGGL(k_verify_dp, dim3(grid_for(n, 1, 1u << 20)), dim3(64), 0, s, pairs,
-                               (const int64_t *)nullptr, n, va, vb, kmode, flags, cells);
+                               (const int64_t *)nullptr, n, va, vb, kmode, np, flags, cells);
         }
         MJ_LAUNCH_CHECK();
         if (kt) kt->end(th, s);
@@ -488,7 +499,7 @@ int64_t verify_pairs(const uint64_t *pairs, int64_t n, const DevStrings &A, cons
                                cnt, va, vb, kmode, flags, cells);
         } else {
             hipLaunchKernelGGL(k_verify_dp, dim3(grid_for(cnt, 1, 1u << 20)), dim3(64), 0, s, pairs,
-                               bsel, cnt, va, vb, kmode, flags, cells);
+                               bsel, cnt, va, vb, kmode, np, flags, cells);
         }
         MJ_LAUNCH_CHECK();
         if (kt) kt->end(th, s);

@@ -5,9 +5,9 @@
 
 namespace mj {
 
+// The verifiers read strings through their bit planes only (never the input symbols).
 struct VSet {
     int32_t n;
-    const uint8_t *chars;
     const int64_t *off;
     const int32_t *len;
     const int32_t *kk;
@@ -34,7 +34,7 @@ __device__ __forceinline__ uint32_t and_xnor(uint32_t a, uint32_t b, uint32_t c)
 }
 
 inline VSet vset(const DevStrings &d) {
-    return VSet{d.n, d.chars, d.offsets, d.len, d.kk, d.planes};
+    return VSet{d.n, d.offsets, d.len, d.kk, d.planes};
 }
 
 }  // namespace mj

@@ -39,7 +39,9 @@ def test_null_arguments_are_rejected_before_any_device_work():
     lib = mj.load_library()
     out = ctypes.c_void_p()
     assert lib.mj_join(None, None, None, None, ctypes.byref(out), None) == mj.MJ_EINVAL
-    assert lib.mj_ctx_create(0, None) == mj.MJ_EINVAL
+    assert lib.mj_ctx_create(0, None, None) == mj.MJ_EINVAL
+    bad = mj.MjAllocator()  # an allocator without alloc/free
+    assert lib.mj_ctx_create(0, ctypes.byref(bad), ctypes.byref(out)) == mj.MJ_EINVAL
     assert lib.mj_pairs_copy_to_host(None, None, 0) == mj.MJ_EINVAL
     assert lib.mj_pairs_count(None) == 0
     assert lib.mj_records_count(None) == 0
@@ -47,3 +49,16 @@ def test_null_arguments_are_rejected_before_any_device_work():
     lib.mj_records_free(None)
     lib.mj_index_free(None)
     lib.mj_ctx_destroy(None)
+
+
+def test_two_bit_packing_layout():
+    """MJ_PACK_2BIT: four symbols per byte, the first in the low bits, whole 32-bit words."""
+    import numpy as np
+    rng = np.random.default_rng(1)
+    for n in (0, 1, 15, 16, 17, 1000):
+        c = rng.integers(0, 4, n).astype(np.uint8)
+        w = mj.pack_2bit(c)
+        assert w.dtype == np.dtype("<u4") and len(w) == -(-n // 16)
+        bits = np.unpackbits(w.view(np.uint8), bitorder="little").reshape(-1, 2)
+        back = (bits[:, 0] | (bits[:, 1] << 1)).astype(np.uint8)
+        assert np.array_equal(back[:n], c) and not back[n:].any()

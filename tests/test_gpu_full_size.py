@@ -64,6 +64,20 @@ def test_join_full_size_identical(mj, name):
         assert digest(out) == g["output_sha256"], verifier
 
 
+@pytest.mark.parametrize("name", [n for n in JOINS if GOLDEN[n]["sigma"] <= 4])
+def test_join_full_size_identical_from_packed_input(mj, name):
+    """The DNA joins with the strings stored 2 bits per symbol on the device (the layout the
+    benchmark times for them)."""
+    g = GOLDEN[name]
+    say(name, "full size, 2-bit packed input")
+    S = getattr(dg, name)()
+    ds = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma, packing=mj.PACK_2BIT)
+    cand, _ = mj.candidates(ds, params(mj, g, S.lengths()))
+    assert cand.size == g["candidates"] and digest(cand) == g["candidates_sha256"]
+    out, st = mj.join(ds, params(mj, g, S.lengths()))
+    assert out.size == g["output"] and digest(out) == g["output_sha256"]
+
+
 @pytest.mark.skipif("dna_index_search" not in GOLDEN, reason="no stored search result")
 def test_search_full_size_identical_direct_and_served(mj):
     """1M-string index, 4096 queries: one mj_search call over all queries, and the same
@@ -74,12 +88,16 @@ def test_search_full_size_identical_direct_and_served(mj):
     I = dg.dna_index(n=g["index_strings"])
     Q, _, _ = dg.dna_queries(I, n=g["queries"], rate_per_s=g["rate_per_s"])
     assert int(I.offsets[-1]) == g["index_symbols"] and int(Q.offsets[-1]) == g["query_symbols"]
-    ds = mj.DeviceStrings.from_host(I.chars, I.offsets, 4)
+    # the index is built from the strings stored 2 bits per symbol (1.4 GB) and keeps no
+    # copy of them, only the verifier's planes, lengths, thresholds and sorted records
+    ds = mj.DeviceStrings.from_host(I.chars, I.offsets, 4, packing=mj.PACK_2BIT)
     index = mj.Index(ds, params(mj, g, I.lengths()))
+    say("index holds %.2f GB of device memory" % (index.device_bytes / 1e9))
+    assert index.device_bytes <= 6.1e9  # 1.4 GB of planes + 16 B per record, no symbols
     del ds
     torch.cuda.empty_cache()
     kq = dg.k_fraction(Q.lengths(), *g["k_frac"])
-    qd = mj.DeviceStrings.from_host(Q.chars, Q.offsets, 4)
+    qd = mj.DeviceStrings.from_host(Q.chars, Q.offsets, 4, packing=mj.PACK_2BIT)
     for verifier in (mj.VERIFY_BATCHED, mj.VERIFY_PLAIN):
         out, st = index.search(qd, k_per_query=torch.from_numpy(kq).cuda(), verifier=verifier)
         assert st["candidates"] == g["candidates"]
