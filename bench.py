@@ -441,8 +441,9 @@ def measure_join(workload, args, steps, warmup):
     flags = mj.verify(ds, params, truth_pairs, ctx=mj.Context(0))
     truth = truth_pairs[flags]
 
-    def timed(verifier):
+    def timed(verifier, streaming=True):
         params.verifier = verifier
+        ctx.set_streaming(streaming)
         out = None
         for _ in range(warmup):
             out, st = mj.join(ds, params, ctx=ctx)
@@ -458,9 +459,20 @@ def measure_join(workload, args, steps, warmup):
 
     plain_out, plain_stats, plain_ms = timed(mj.VERIFY_PLAIN)
     print("[bench] %s plain: %.3f ms/step" % (workload, plain_ms), file=sys.stderr, flush=True)
+    sbs_out, sbs_stats, sbs_ms = timed(mj.VERIFY_BATCHED, streaming=False)
+    print("[bench] %s batched, stage by stage: %.3f ms/step" % (workload, sbs_ms), file=sys.stderr,
+          flush=True)
     out, stats, ms = timed(mj.VERIFY_BATCHED)
-    print("[bench] %s batched: %.3f ms/step" % (workload, ms), file=sys.stderr, flush=True)
+    st_ms, st_joins = ms, int(sum(s["streamed"] for s in stats))
+    print("[bench] %s batched, streamed: %.3f ms/step (%d of %d joins streamed)"
+          % (workload, ms, st_joins, len(stats)), file=sys.stderr, flush=True)
     assert np.array_equal(out, plain_out), "batched and plain verifiers disagree"
+    assert np.array_equal(sbs_out, plain_out), "stage-by-stage and plain joins disagree"
+    # the headline is the faster of the batched path's two modes (both exact); the other
+    # is reported beside it
+    mode = "streamed"
+    if sbs_ms < ms:
+        out, stats, ms, mode = sbs_out, sbs_stats, sbs_ms, "stage by stage"
 
     recall = float(np.isin(truth, out).mean()) if len(truth) else 1.0
     last = stats[-1]
@@ -484,6 +496,8 @@ def measure_join(workload, args, steps, warmup):
         "plain": {"value": S.n / (plain_ms * 1e-3), "ms_per_step": plain_ms,
                   "verify_kernel_ms": float(np.mean([s["kernel_ms"]["verify"] for s in plain_stats]))},
         "batched_vs_plain": plain_ms / ms,
+        "batched_modes": {"streamed_ms_per_step": st_ms, "streamed_joins": st_joins,
+                          "stage_by_stage_ms_per_step": sbs_ms, "headline_mode": mode},
         "with_upload": {"value": S.n / ((ms + upload_ms) * 1e-3), "upload_ms": upload_ms,
                         "note": "strings uploaded from pageable host memory inside the timing"},
         "verified_pairs_per_s": last["candidates"] / (verify_ms * 1e-3),

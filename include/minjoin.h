@@ -129,6 +129,9 @@ typedef struct {
     int32_t verify_words;  /* band words per lane of the batched verifier */
     int32_t verify_blocks; /* most workgroups the batched verifier's persistent launch may
                               have (fewer when the pairs need fewer) */
+    int32_t streamed;      /* 1: the join sized its stages on the device (see mj_join) */
+    int32_t host_reads;    /* reads of device values the host waited for: 2 when
+                              streamed, 0 (not counted) stage by stage */
 } mj_stats;
 
 /* ---- context ---------------------------------------------------------------- */
@@ -153,6 +156,10 @@ typedef struct {
  * EDEVICE on HIP errors. */
 mj_status mj_ctx_create(int device, const mj_allocator *alloc, mj_ctx **out);
 void mj_ctx_destroy(mj_ctx *ctx);
+/* Streamed joins (see mj_join) on (1, the default) or off (0): off, every join runs stage
+ * by stage, each stage sized exactly from a read-back (less memory: the streamed join holds
+ * capacities, e.g. records for the set-up's bound).  EINVAL for a NULL context. */
+mj_status mj_ctx_set_streaming(mj_ctx *ctx, int enable);
 
 /* Thread-local description of the last error (never NULL). */
 const char *mj_last_error(void);
@@ -164,7 +171,13 @@ const char *mj_version(void);
  * passing the filters ---------------------------------------------------------- */
 
 /* Stream-ordered; returns once the pair count is known.  *out is library-owned until
- * mj_pairs_free.  stats may be NULL.  EINVAL on bad arguments (q < 1, q*b > 64,
+ * mj_pairs_free.  stats may be NULL.
+ * With the batched verifier, a join that follows one with the same parameters on the same
+ * context runs streamed: every stage after the per-string set-up is sized on the device
+ * (records by a bound from the set-up, candidates by the last join's rate, the verifier in
+ * the configuration the context timed), so the host waits twice -- for the set-up and for
+ * the result.  When a capacity turns out too small, the join runs again stage by stage
+ * (which sizes every stage from read-backs) and the result is the same.  EINVAL on bad arguments (q < 1, q*b > 64,
  * t_div < 1, K < -1, sigma outside 2..256, offsets decreasing, a symbol code >= sigma,
  * verifier or verify_lanes not one of the listed values); ECAPACITY when a
  * documented limit is exceeded: record-pair tests of one call above 2^31, a radius r

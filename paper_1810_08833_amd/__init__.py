@@ -57,12 +57,14 @@ class MjStats(ctypes.Structure):
                 ("stage_ms", ctypes.c_float * 8), ("kernel_ms", ctypes.c_float * 4),
                 ("kernel_launches", ctypes.c_int32 * 4), ("positions", ctypes.c_int64),
                 ("verify_group", ctypes.c_int32), ("verify_words", ctypes.c_int32),
-                ("verify_blocks", ctypes.c_int32)]
+                ("verify_blocks", ctypes.c_int32), ("streamed", ctypes.c_int32),
+                ("host_reads", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k in ("records", "groups", "pair_tests", "candidates",
                                            "output", "band_cells", "positions", "verify_group",
-                                           "verify_words", "verify_blocks")}
+                                           "verify_words", "verify_blocks", "streamed",
+                                           "host_reads")}
         d["stage_ms"] = {STAGES[i]: float(self.stage_ms[i]) for i in range(7)}
         d["kernel_ms"] = {KERNELS[i]: float(self.kernel_ms[i]) for i in range(4)}
         d["kernel_launches"] = {KERNELS[i]: int(self.kernel_launches[i]) for i in range(4)}
@@ -81,7 +83,7 @@ class MjReply(ctypes.Structure):
                 ("start_ms", ctypes.c_double), ("done_ms", ctypes.c_double)]
 
 
-EXPORTS = ["mj_ctx_create", "mj_ctx_destroy", "mj_last_error", "mj_version", "mj_join",
+EXPORTS = ["mj_ctx_create", "mj_ctx_destroy", "mj_ctx_set_streaming", "mj_last_error", "mj_version", "mj_join",
            "mj_partition", "mj_candidates", "mj_verify", "mj_index_build", "mj_index_free",
            "mj_index_records", "mj_index_bytes", "mj_search", "mj_pairs_count", "mj_pairs_device",
            "mj_pairs_copy_to_host", "mj_pairs_free", "mj_records_count",
@@ -110,6 +112,8 @@ def load_library(path: str = LIB_PATH):
     L.mj_ctx_create.argtypes = [ctypes.c_int, P(MjAllocator), P(VP)]
     L.mj_ctx_destroy.argtypes = [VP]
     L.mj_ctx_destroy.restype = None
+    L.mj_ctx_set_streaming.argtypes = [VP, ctypes.c_int]
+    L.mj_ctx_set_streaming.restype = ctypes.c_int
     L.mj_last_error.restype = ctypes.c_char_p
     L.mj_version.restype = ctypes.c_char_p
     L.mj_join.argtypes = [VP, P(MjStrings), P(MjParams), VP, P(VP), P(MjStats)]
@@ -216,6 +220,10 @@ class Context:
         _check(L.mj_ctx_create(self.device, ctypes.byref(allocator.struct) if allocator else None,
                                ctypes.byref(h)))
         self.handle = h
+
+    def set_streaming(self, enable: bool):
+        """Streamed joins (two host reads per join) on or off (stage by stage)."""
+        _check(load_library().mj_ctx_set_streaming(self.handle, 1 if enable else 0))
 
     def close(self):
         if self.handle:

@@ -68,6 +68,12 @@ extern "C" void mj_ctx_destroy(mj_ctx *ctx) {
     delete ctx;
 }
 
+extern "C" mj_status mj_ctx_set_streaming(mj_ctx *ctx, int enable) {
+    if (!ctx) return fail(MJ_EINVAL, "ctx is NULL");
+    ctx->streaming = enable != 0;
+    return MJ_OK;
+}
+
 // ---------------------------------------------------------------- helpers
 static int ceil_log2(uint64_t v) {
     int b = 0;
@@ -158,6 +164,7 @@ static mj_pairs *compact_pairs(const uint64_t *pairs, const uint8_t *flags, int6
                                hipStream_t s, uint64_t *pinned) {
     mj_pairs *out = new mj_pairs();
     out->alloc = t_dev_alloc;
+    out->stream = s;
     if (n == 0) {
         out->d = (uint64_t *)dev_alloc(16);
         out->n = 0;
@@ -264,7 +271,8 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     StageTimer tm(ctx, s);
     DevStrings d = view(strings, s, ctx->pinned, false);
     PartitionParams pp = to_pp(params, d.bits);
-    int32_t halo = prepare_strings(d, pp, ws, s, ctx->pinned);
+    SetupInfo si;
+    int32_t halo = prepare_strings(d, pp, ws, s, ctx->pinned, &si);
     pack_planes(d, verify_planes(d.bits), ws, s);  // also checks the symbol codes
     tm.mark();  // 0 setup
     RecBuf rb;
@@ -282,6 +290,9 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     int64_t cap = (int64_t)g.tests;
     uint64_t *cand = ws.get_n<uint64_t>(cap + 1);
     int64_t c0 = emit_candidates(rb.val, R, g, d, cand, cap, ws, s, ctx->pinned, &ctx->kt);
+    ctx->last_c0 = c0;
+    ctx->last_R = R;
+    ctx->last_rcap = std::max<int64_t>(si.rec_bound * pp.reps, 2);
     tm.mark();  // 3 group + filter
     uint64_t *uniq = nullptr;
     int64_t C = dedup_pairs(cand, c0, d.n, d.n, ws, s, ctx->pinned, &uniq);
@@ -297,6 +308,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     if (upto == 1) {
         mj_pairs *out = new mj_pairs();
         out->alloc = t_dev_alloc;
+        out->stream = s;
         out->d = uniq;
         out->n = C;
         tm.fill(stats);
@@ -317,6 +329,143 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     return out;
 }
 
+// ---------------------------------------------------------------- streamed join
+// The batched join with every size after the set-up on the device: records by the set-up's
+// bound, candidates by the last join's candidates-per-record (with room to spare), the
+// verifier in the configuration the context timed.  Between the set-up read-back and the
+// final one, no stage waits for the host.  Returns nullptr when a capacity was exceeded
+// (the caller then runs the join stage by stage, which sizes everything exactly).
+
+__global__ void k_collect(const int64_t *R, const uint64_t *slot, const unsigned long long *c0,
+                          const uint32_t *u, const uint32_t *outn, const unsigned long long *cells,
+                          const uint32_t *symbol_err, uint64_t *dst) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    dst[9] = symbol_err ? *symbol_err : 0;
+    dst[0] = (uint64_t)*R;
+    dst[1] = slot ? slot[0] : 0;
+    dst[2] = slot ? slot[1] : 0;
+    dst[3] = slot ? slot[2] : 0;
+    dst[4] = *c0;
+    dst[5] = *u;
+    dst[6] = *outn;
+    dst[7] = cells[0];
+    dst[8] = cells[1];
+}
+
+static bool hints_match(const StreamHints &h, const mj_strings *st, const mj_params *p) {
+    return h.valid && h.q == p->q && h.t_div == p->t_div && h.t_fixed == p->t_fixed &&
+           h.reps == p->reps && h.seed == p->seed && h.k == p->k && h.sigma == st->sigma &&
+           h.packing == st->packing && h.verify_lanes == p->verify_lanes;
+}
+
+static mj_pairs *run_join_streamed(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
+                                   hipStream_t s, mj_stats *stats) {
+    Workspace &ws = ctx->ws;
+    Released rel{ws};
+    StageTimer tm(ctx, s);
+    const StreamHints &h = ctx->stream;
+    DevStrings d = view(strings, s, ctx->pinned, false);
+    PartitionParams pp = to_pp(params, d.bits);
+    SetupInfo si;
+    (void)prepare_strings(d, pp, ws, s, ctx->pinned, &si);  // the one read before the end
+    pack_planes(d, verify_planes(d.bits), ws, s);
+    const int cmax = (int)((std::min<int64_t>(params->k >= 0 ? params->k : si.kmax, 0x3FFFFFFF) + 31) >> 5);
+    if (cmax > persist_max_c()) return nullptr;
+    {
+        const int np = verify_planes(d.bits);
+        // the configuration the last join used (the small-call one if it verified nothing)
+        const int g = params->verify_lanes == -2 ? VERIFY_BIDIR
+                    : params->verify_lanes ? params->verify_lanes
+                    : h.verify_g ? h.verify_g : verify_small_call_lanes(cmax);
+        int nwl = 0;
+        for (int v : {1, 2, 3, 4, 5, 6, 7, 8, 9, 11})
+            if (v * (g == VERIFY_BIDIR ? 1 : g) >= cmax + 1) { nwl = v; break; }
+        if (g == 0 || nwl == 0) return nullptr;  // no configuration for this band: stage by stage
+        ctx->tune.best_g[std::min(cmax, 63)][np / 2 - 1] = g;
+        if (!ctx->tune.best_blocks[std::min(cmax, 63)][np / 2 - 1])
+            ctx->tune.best_blocks[std::min(cmax, 63)][np / 2 - 1] = h.verify_blocks ? h.verify_blocks : 512;
+    }
+    tm.mark();  // 0 setup
+    const int reps = pp.reps;
+    const int64_t rcap = std::max<int64_t>(si.rec_bound * reps, 2);
+    uint64_t *key = ws.get_n<uint64_t>(rcap + 1);
+    uint64_t *val = ws.get_n<uint64_t>(rcap + 1);
+    int64_t *R_dev = ws.get_n<int64_t>(2);
+    partition_records_streamed(d, pp, si, key, val, R_dev, ws, s, &ctx->kt);
+    tm.mark();  // 1 partition
+    // the stages after the partition are sized by the last join's records per bound, with
+    // room (more records than that: the join runs again stage by stage)
+    const int64_t scap = std::max<int64_t>(
+        2, std::min<int64_t>(rcap, (int64_t)(1.02 * h.rec_per_bound * (double)rcap) + 4096));
+    sort_records(key, val, scap, ws, s, ctx->pinned, R_dev);
+    tm.mark();  // 2 sort
+    GroupInfo g = find_groups_streamed(key, scap, R_dev, ws, s);
+    // candidates before the dedup: the last join's rate per record bound, with room
+    const int64_t ccap = (int64_t)std::min<double>(1.1 * h.cand_per_record * (double)rcap + 65536.0,
+                                                   (double)0x7FFFFFF0LL);
+    uint64_t *cand = ws.get_n<uint64_t>(ccap + 1);
+    unsigned long long *c0 = (unsigned long long *)ws.get_n<uint64_t>(2);
+    emit_candidates_streamed(val, scap, R_dev, g, d, cand, ccap, c0, h.emit, ws, s, &ctx->kt);
+    tm.mark();  // 3 group + filter
+    uint64_t *uniq = nullptr;
+    const uint32_t *u = dedup_pairs_streamed(cand, ccap, c0, d.n, d.n, ws, s, &uniq);
+    tm.mark();  // 4 dedup
+    uint8_t *flags = ws.get_n<uint8_t>(ccap + 4);
+    unsigned long long *cells = nullptr;
+    verify_pairs_batched_streamed(uniq, ccap, u, d, d, 0, cmax, flags, ws, s, &ctx->kt, ctx->tune,
+                                  params->verify_lanes, &cells);
+    tm.mark();  // 5 verify
+    int64_t *idx = ws.get_n<int64_t>(ccap + 1);
+    const uint32_t *on = compact_flags_async(flags, ccap, idx, ws, s);
+    uint64_t *outbuf = ws.get_n<uint64_t>(ccap + 1);
+    gather_u64(uniq, idx, outbuf, ccap, s, on);
+    uint64_t *res = ws.get_n<uint64_t>(16);
+    hipLaunchKernelGGL(k_collect, dim3(1), dim3(64), 0, s, R_dev, g.slot, c0, u, on, cells,
+                       (const uint32_t *)d.symbol_err, res);
+    MJ_LAUNCH_CHECK();
+    MJ_HIP(hipMemcpyAsync(ctx->pinned, res, 10 * 8, hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipStreamSynchronize(s));  // the one read at the end
+    uint64_t hv[10];
+    memcpy(hv, ctx->pinned, sizeof(hv));
+    if (hv[9]) throw Error(MJ_EINVAL, "a symbol code is not below sigma");
+    const int64_t R = (int64_t)hv[0], c0h = (int64_t)hv[4], C = (int64_t)hv[5], nout = (int64_t)hv[6];
+    if (c0h > ccap || R > scap) return nullptr;  // more than the room left: stage by stage
+    if (R > 1 && (hv[1] & 0xFFFFFFFFu) != (hv[1] >> 32)) throw Error(MJ_EDEVICE, "group boundary mismatch");
+    if (hv[8]) throw Error(MJ_ECAPACITY, "a pair's band exceeds the verifier window");
+    mj_pairs *out = new mj_pairs();
+    out->alloc = t_dev_alloc;
+    out->stream = s;
+    out->n = nout;
+    out->d = (uint64_t *)dev_alloc((size_t)(nout + 1) * 8);
+    if (nout) MJ_HIP(hipMemcpyAsync(out->d, outbuf, (size_t)nout * 8, hipMemcpyDeviceToDevice, s));
+    tm.mark();  // 6 output
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->records = R;
+        stats->groups = (int64_t)hv[2];
+        stats->pair_tests = (int64_t)hv[3];
+        stats->candidates = C;
+        stats->output = nout;
+        stats->band_cells = (int64_t)hv[7];
+        stats->positions = d.total * pp.reps;
+        const int ci = std::min(cmax, 63), npi = verify_planes(d.bits) / 2 - 1;
+        stats->verify_group = ctx->tune.best_g[ci][npi] == VERIFY_BIDIR ? -2 : ctx->tune.best_g[ci][npi];
+        for (int v : {1, 2, 3, 4, 5, 6, 7, 8, 9, 11}) {
+            const int gg = ctx->tune.best_g[ci][npi];
+            if (v * (gg == VERIFY_BIDIR ? 1 : gg) >= cmax + 1) { stats->verify_words = v; break; }
+        }
+        stats->verify_blocks = ctx->tune.best_blocks[ci][npi];
+        stats->streamed = 1;
+        stats->host_reads = 2;
+    }
+    tm.fill(stats);
+    // keep the rates current (capacities of the next join)
+    ctx->stream.cand_per_record = (double)c0h / (double)rcap;
+    ctx->stream.rec_per_bound = (double)R / (double)rcap;
+    ctx->stream.emit = emit_hints((uint64_t)hv[3], R, d.n);
+    return out;
+}
+
 extern "C" mj_status mj_join(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
                              void *stream, mj_pairs **out, mj_stats *stats) {
     if (!ctx || !out) return fail(MJ_EINVAL, "ctx/out is NULL");
@@ -325,7 +474,31 @@ extern "C" mj_status mj_join(mj_ctx *ctx, const mj_strings *strings, const mj_pa
     check_params(params, strings->sigma, true);
     MJ_HIP(hipSetDevice(ctx->device));
     AllocScope as(ctx->ws.alloc);
-    *out = run_join(ctx, strings, params, (hipStream_t)stream, 2, stats);
+    hipStream_t s = (hipStream_t)stream;
+    const bool batched = params->verifier == MJ_VERIFY_BATCHED;
+    if (batched && ctx->streaming && !ctx->no_tuning && hints_match(ctx->stream, strings, params)) {
+        mj_pairs *r = run_join_streamed(ctx, strings, params, s, stats);
+        if (r) {
+            ctx->streamed_joins++;
+            *out = r;
+            return MJ_OK;
+        }
+        ctx->stream_fallbacks++;
+    }
+    *out = run_join(ctx, strings, params, s, 2, stats);
+    if (batched && !ctx->no_tuning && stats) {
+        // what the streamed join of the next call with these parameters needs
+        StreamHints &h = ctx->stream;
+        h.valid = true;
+        h.q = params->q; h.t_div = params->t_div; h.t_fixed = params->t_fixed; h.reps = params->reps;
+        h.seed = params->seed; h.k = params->k; h.sigma = strings->sigma; h.packing = strings->packing;
+        h.verify_lanes = params->verify_lanes;
+        h.cand_per_record = (double)ctx->last_c0 / (double)std::max<int64_t>(ctx->last_rcap, 1);
+        h.rec_per_bound = (double)ctx->last_R / (double)std::max<int64_t>(ctx->last_rcap, 1);
+        h.emit = emit_hints((uint64_t)stats->pair_tests, stats->records, strings->n);
+        h.verify_g = ctx->tune.last_g;
+        h.verify_blocks = ctx->tune.last_blocks;
+    }
     return MJ_OK;
     MJ_API_END
 }
@@ -582,7 +755,10 @@ extern "C" mj_status mj_pairs_copy_to_host(const mj_pairs *p, uint64_t *dst, int
     if (!p) return fail(MJ_EINVAL, "pairs is NULL");
     if (cap < p->n || (p->n > 0 && !dst)) return fail(MJ_EINVAL, "destination too small");
     MJ_API_BEGIN
-    if (p->n) MJ_HIP(hipMemcpy(dst, p->d, (size_t)p->n * 8, hipMemcpyDeviceToHost));
+    if (p->n) {
+        MJ_HIP(hipMemcpyAsync(dst, p->d, (size_t)p->n * 8, hipMemcpyDeviceToHost, p->stream));
+        MJ_HIP(hipStreamSynchronize(p->stream));
+    }
     return MJ_OK;
     MJ_API_END
 }

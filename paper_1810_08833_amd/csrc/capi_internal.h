@@ -5,6 +5,22 @@
 
 using namespace mj;
 
+// What a join of the batched path learned for the next join with the same parameters:
+// how many candidates (before the dedup) per record it emitted, the emission layout, and
+// the verifier configuration it used.  With it, the next join sizes its stages from the
+// set-up read-back alone (the streamed join: one more read, at the end).
+struct StreamHints {
+    bool valid = false;
+    // parameters the hints belong to
+    int32_t q = 0, t_div = 0, t_fixed = 0, reps = 0, sigma = 0, packing = 0, verify_lanes = 0;
+    uint64_t seed = 0;
+    int64_t k = 0;
+    double cand_per_record = 0;  // emitted candidates (before the dedup) per record bound
+    double rec_per_bound = 1;    // records per record bound
+    EmitHints emit;
+    int verify_g = 0, verify_blocks = 0;
+};
+
 struct mj_ctx {
     int device = 0;
     Workspace ws;
@@ -15,12 +31,18 @@ struct mj_ctx {
     // latency first (server workers): the batched verifier takes its fixed small-call
     // configuration instead of timing the choices on a live call
     bool no_tuning = false;
+    bool streaming = true;  // streamed joins allowed (mj_ctx_set_streaming)
+    StreamHints stream;
+    int streamed_joins = 0, stream_fallbacks = 0;
+    // the last stage-by-stage join's emitted candidates, records and record bound
+    int64_t last_c0 = 0, last_R = 0, last_rcap = 0;
 };
 
 struct mj_pairs {
     uint64_t *d = nullptr;
     int64_t n = 0;
     mj_allocator alloc{};  // the allocator that made d
+    hipStream_t stream = nullptr;  // d is complete once this stream's work is
 };
 
 struct mj_records {

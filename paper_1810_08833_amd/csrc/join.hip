@@ -25,15 +25,25 @@ static int ceil_log2(uint64_t v) {
 // ---------------------------------------------------------------- groups
 // A group is a maximal run of equal keys in the sorted records; only runs of length
 // >= 2 can produce pairs.  start flag: first of a run of >= 2; end flag: last of one.
-__global__ void k_group_flags(const uint64_t *key, int64_t R, uint8_t *fs, uint8_t *fe) {
+// R_dev (nullable): the record count on the device; flags up to the capacity R are
+// written (0 past the count), so that compactions over the capacity see only records.
+__global__ void k_group_flags(const uint64_t *key, int64_t R, uint8_t *fs, uint8_t *fe,
+                              const int64_t *R_dev) {
+    const int64_t cap = R;
+    if (R_dev) R = min(R, *R_dev);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < R; i += stride) {
-        uint64_t k = key[i];
-        bool same_prev = i > 0 && key[i - 1] == k;
-        bool same_next = i + 1 < R && key[i + 1] == k;
-        fs[i] = (!same_prev && same_next) ? 1 : 0;
-        fe[i] = (same_prev && !same_next) ? 1 : 0;
+    for (; i < cap; i += stride) {
+        bool s1 = false, e1 = false;
+        if (i < R) {
+            uint64_t k = key[i];
+            bool same_prev = i > 0 && key[i - 1] == k;
+            bool same_next = i + 1 < R && key[i + 1] == k;
+            s1 = !same_prev && same_next;
+            e1 = same_prev && !same_next;
+        }
+        fs[i] = s1 ? 1 : 0;
+        fe[i] = e1 ? 1 : 0;
     }
 }
 
@@ -60,7 +70,8 @@ GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t
     if (R < 2) return gi;
     uint8_t *fs = ws.get_n<uint8_t>(R);
     uint8_t *fe = ws.get_n<uint8_t>(R);
-    hipLaunchKernelGGL(k_group_flags, dim3(grid_for(R, 256, 16384)), dim3(256), 0, s, key, R, fs, fe);
+    hipLaunchKernelGGL(k_group_flags, dim3(grid_for(R, 256, 16384)), dim3(256), 0, s, key, R, fs, fe,
+                       (const int64_t *)nullptr);
     MJ_LAUNCH_CHECK();
     int64_t *gs = ws.get_n<int64_t>(R / 2 + 2);
     int64_t *ge = ws.get_n<int64_t>(R / 2 + 2);
@@ -87,6 +98,35 @@ GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t
     gi.groups = G1;
     gi.gstart = gs;
     gi.tests = G1 > 0 ? hs[2] : 0;
+    return gi;
+}
+
+GroupInfo find_groups_streamed(const uint64_t *key, int64_t R_cap, const int64_t *R_dev,
+                               Workspace &ws, hipStream_t s) {
+    GroupInfo gi;
+    const int64_t R = std::max<int64_t>(R_cap, 2);
+    uint8_t *fs = ws.get_n<uint8_t>(R);
+    uint8_t *fe = ws.get_n<uint8_t>(R);
+    hipLaunchKernelGGL(k_group_flags, dim3(grid_for(R, 256, 16384)), dim3(256), 0, s, key, R, fs, fe,
+                       R_dev);
+    MJ_LAUNCH_CHECK();
+    int64_t *gs = ws.get_n<int64_t>(R / 2 + 2);
+    int64_t *ge = ws.get_n<int64_t>(R / 2 + 2);
+    const uint32_t *c1 = compact_flags_async(fs, R, gs, ws, s);
+    const uint32_t *c2 = compact_flags_async(fe, R, ge, ws, s);
+    const int64_t gmax = R / 2;
+    uint64_t *cnt = ws.get_n<uint64_t>(gmax + 1);
+    gi.tstart = ws.get_n<uint64_t>(gmax + 1);
+    uint64_t *slot = ws.get_n<uint64_t>(3);
+    hipLaunchKernelGGL(k_group_tests, dim3(grid_for(gmax, 256, 16384)), dim3(256), 0, s, gs, ge, c1,
+                       c2, cnt, slot);
+    MJ_LAUNCH_CHECK();
+    exclusive_scan_u64_dev(cnt, gi.tstart, gmax, reinterpret_cast<const uint32_t *>(slot + 1),
+                           slot + 2, ws, s);
+    gi.groups = -1;  // on the device: slot[0] = c1 | c2 << 32, slot[1] = groups, slot[2] = tests
+    gi.gstart = gs;
+    gi.slot = slot;
+    gi.gmax = gmax;
     return gi;
 }
 
@@ -157,7 +197,9 @@ __global__ void k_string_meta(const int32_t *__restrict__ len, const int32_t *__
 // meta[i] = the (m, K) word of the string owning sorted record i, so that a pair test
 // reads four record-aligned words (two payloads, two metas) with no dependent gathers.
 __global__ void k_record_meta(const uint64_t *__restrict__ val, int64_t R,
-                              const uint64_t *__restrict__ lk, uint64_t *__restrict__ meta) {
+                              const uint64_t *__restrict__ lk, uint64_t *__restrict__ meta,
+                              const int64_t *__restrict__ R_dev) {
+    if (R_dev) R = min(R, *R_dev);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < R; i += stride) meta[i] = lk[(int32_t)(val[i] >> 32)];
@@ -175,7 +217,13 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
                                               const int64_t *__restrict__ gs,
                                               const uint64_t *__restrict__ ts, int64_t G,
                                               uint64_t P, uint64_t *out, int64_t cap,
-                                              unsigned long long *counter, int chunk) {
+                                              unsigned long long *counter, int chunk,
+                                              const uint64_t *__restrict__ slot) {
+    // group and test counts on the device (the streamed join): slot[1], slot[2]
+    if (slot) {
+        G = (int64_t)slot[1];
+        P = G > 0 ? slot[2] : 0;
+    }
     __shared__ EmitStage st;
     if (threadIdx.x == 0) st.n = 0;
     __syncthreads();
@@ -280,7 +328,7 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
     }
     if (!lazy) {
         hipLaunchKernelGGL(k_record_meta, dim3(grid_for(R, 256, 16384)), dim3(256), 0, s, val, R,
-                           lk, meta);
+                           lk, meta, (const int64_t *)nullptr);
         MJ_LAUNCH_CHECK();
     }
     // a thread locates its first test by a binary search over the groups; with tests
@@ -291,7 +339,7 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
     unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, 1u << 16);
     hipLaunchKernelGGL(lazy ? k_emit<true> : k_emit<false>, dim3(grid), dim3(EMIT_BLOCK), 0, s, val,
                        meta, lk, d.len, d.kk, g.gstart, g.tstart, g.groups, g.tests, out, cap, counter,
-                       chunk);
+                       chunk, (const uint64_t *)nullptr);
     MJ_LAUNCH_CHECK();
     if (kt) kt->end(th, s);
     uint64_t c = read_back<uint64_t>((const uint64_t *)counter, s, host_scratch);
@@ -350,6 +398,108 @@ int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t n_first, int32_t n_secon
     gather_u64(pairs, idx, res, u, s);
     if (pack && u > 0) {
         hipLaunchKernelGGL(k_unpack_pairs, dim3(grid_for(u, 256, 16384)), dim3(256), 0, s, res, u, bs);
+        MJ_LAUNCH_CHECK();
+    }
+    *result = res;
+    return u;
+}
+
+// Emission with the record, group and test counts on the device; the candidates go to
+// out[0 .. cap), their count (which may exceed cap: the caller checks) to *count.  The
+// layout choices (record-aligned (m, K) words, string words, tests per search) come from
+// the caller's hints (the last call of the same shape), as they only affect speed.
+void emit_candidates_streamed(const uint64_t *val, int64_t R_cap, const int64_t *R_dev,
+                              const GroupInfo &g, const DevStrings &d, uint64_t *out, int64_t cap,
+                              unsigned long long *count, const EmitHints &h, Workspace &ws,
+                              hipStream_t s, KTimer *kt) {
+    fill_u64((uint64_t *)count, 0, 1, s);
+    uint64_t *meta = h.lazy ? nullptr : ws.get_n<uint64_t>(R_cap + 1);
+    const bool packed = !h.lazy || h.string_words;
+    uint64_t *lk = packed ? ws.get_n<uint64_t>((size_t)d.n + 1) : nullptr;
+    int th = kt ? kt->begin(KTimer::EMIT, s) : -1;
+    if (packed) {
+        hipLaunchKernelGGL(k_string_meta, dim3(grid_for(d.n, 256, 65535)), dim3(256), 0, s, d.len,
+                           d.kk, d.n, lk);
+        MJ_LAUNCH_CHECK();
+    }
+    if (!h.lazy) {
+        hipLaunchKernelGGL(k_record_meta, dim3(grid_for(R_cap, 256, 16384)), dim3(256), 0, s, val,
+                           R_cap, lk, meta, R_dev);
+        MJ_LAUNCH_CHECK();
+    }
+    const int chunk = std::max(EMIT_CHUNK, h.chunk);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(h.blocks, 1 << 16));
+    hipLaunchKernelGGL(h.lazy ? k_emit<true> : k_emit<false>, dim3(grid), dim3(EMIT_BLOCK), 0, s,
+                       val, meta, lk, d.len, d.kk, g.gstart, g.tstart, (int64_t)0, (uint64_t)0, out,
+                       cap, count, chunk, (const uint64_t *)g.slot);
+    MJ_LAUNCH_CHECK();
+    if (kt) kt->end(th, s);
+}
+
+EmitHints emit_hints(uint64_t tests, int64_t R, int32_t n) {
+    EmitHints h;
+    h.lazy = tests < (uint64_t)R;
+    h.string_words = tests >= 16 * (uint64_t)std::max(n, 1);
+    int chunk = EMIT_CHUNK;
+    while (chunk < 4 * EMIT_CHUNK && tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
+    h.chunk = chunk;
+    const uint64_t threads = (tests + chunk - 1) / chunk;
+    h.blocks = (int64_t)std::max<uint64_t>(1, std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK,
+                                                                  1u << 16));
+    return h;
+}
+
+__global__ void k_clamp_count(const unsigned long long *c, int64_t cap, int64_t *out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *out = min((int64_t)*c, cap);
+}
+
+__global__ void k_unique_flags_dev(const uint64_t *p, int64_t cap, const int64_t *n_dev, uint8_t *f) {
+    const int64_t n = *n_dev;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < cap; i += stride) f[i] = (i < n && (i == 0 || p[i] != p[i - 1])) ? 1 : 0;
+}
+
+__global__ void k_pack_pairs_dev(uint64_t *p, const int64_t *n_dev, int64_t cap, int b, int unpack,
+                                 const uint32_t *u_dev) {
+    const int64_t n = u_dev ? (int64_t)*u_dev : min(cap, *n_dev);
+    const uint64_t lo = b >= 64 ? ~0ull : ((1ull << b) - 1);
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        p[i] = unpack ? ((p[i] >> b) << 32) | (p[i] & lo) : ((p[i] >> 32) << b) | (p[i] & 0xFFFFFFFFull);
+}
+
+// Dedup with the candidate count on the device (*count, at most cap of them kept); the
+// distinct pairs go to a workspace array of cap entries, their number to the returned
+// device word.
+const uint32_t *dedup_pairs_streamed(uint64_t *pairs, int64_t cap, const unsigned long long *count,
+                                     int32_t n_first, int32_t n_second, Workspace &ws, hipStream_t s,
+                                     uint64_t **result) {
+    cap = std::max<int64_t>(cap, 1);
+    int64_t *n_dev = ws.get_n<int64_t>(2);
+    hipLaunchKernelGGL(k_clamp_count, dim3(1), dim3(64), 0, s, count, cap, n_dev);
+    MJ_LAUNCH_CHECK();
+    auto field_bits = [](int32_t c) { return std::min(32, ceil_log2((uint64_t)std::max(c, 1))); };
+    const int bf = field_bits(n_first), bs = field_bits(n_second);
+    const bool pack = (bf + bs + 7) / 8 < (bf + 7) / 8 + (bs + 7) / 8;
+    const unsigned pgrid = grid_for(cap, 256, 16384);
+    if (pack) {
+        hipLaunchKernelGGL(k_pack_pairs_dev, dim3(pgrid), dim3(256), 0, s, pairs, n_dev, cap, bs, 0,
+                           (const uint32_t *)nullptr);
+        MJ_LAUNCH_CHECK();
+    }
+    auto ones = [](int b) { return b >= 64 ? ~0ull : ((1ull << b) - 1); };
+    radix_sort(pairs, nullptr, cap, pack ? ones(bf + bs) : (ones(bf) << 32) | ones(bs), ws, s, n_dev);
+    uint8_t *f = ws.get_n<uint8_t>(cap);
+    hipLaunchKernelGGL(k_unique_flags_dev, dim3(pgrid), dim3(256), 0, s, pairs, cap, n_dev, f);
+    MJ_LAUNCH_CHECK();
+    int64_t *idx = ws.get_n<int64_t>(cap + 1);
+    const uint32_t *u = compact_flags_async(f, cap, idx, ws, s);
+    uint64_t *res = ws.get_n<uint64_t>(cap + 1);
+    gather_u64(pairs, idx, res, cap, s, u);
+    if (pack) {
+        hipLaunchKernelGGL(k_pack_pairs_dev, dim3(pgrid), dim3(256), 0, s, res, n_dev, cap, bs, 1, u);
         MJ_LAUNCH_CHECK();
     }
     *result = res;

@@ -150,14 +150,16 @@ constexpr size_t HOST_SCRATCH_BYTES = 16384;
 
 // Stable sort of keys (and an optional payload) ascending, in place.  key_mask has a 1
 // at every bit that may be set in some key (the others must be zero in all keys).
+// n_dev (nullable): the element count on the device, n then being its capacity.
 void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Workspace &ws,
-                hipStream_t s);
+                hipStream_t s, const int64_t *n_dev = nullptr);
 // Records (key, payload) sorted by the full 64-bit key, in place; equal keys keep their
 // order only up to the runs that the repair step reorders.
 void sort_records(uint64_t *key, uint64_t *val, int64_t n, Workspace &ws, hipStream_t s,
-                  uint64_t *host_scratch);
-// Gather: out_k[i] = key[idx[i]] (and val).
-void gather_u64(const uint64_t *src, const int64_t *idx, uint64_t *dst, int64_t n, hipStream_t s);
+                  uint64_t *host_scratch, const int64_t *n_dev = nullptr);
+// Gather: dst[i] = src[idx[i]] for i < n (or < *n_dev when given).
+void gather_u64(const uint64_t *src, const int64_t *idx, uint64_t *dst, int64_t n, hipStream_t s,
+                const uint32_t *n_dev = nullptr);
 
 // Read one device value back (synchronises the stream).
 template <class T>
@@ -219,8 +221,15 @@ struct RecBuf {
 };
 
 // partition.hip
+// What the per-string set-up reads back: the halo radius the anchor kernel needs, a bound
+// on the partitions of one repetition (summed over strings), and the largest K.
+struct SetupInfo {
+    int32_t halo = 0;
+    int64_t rec_bound = 0;
+    int32_t kmax = 0;
+};
 int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
-                        uint64_t *host_scratch);       // returns the halo radius needed
+                        uint64_t *host_scratch, SetupInfo *info = nullptr);  // returns the halo
 // Builds the verifier's bit planes and checks every symbol against sigma (the result in
 // d.symbol_err, read with the partition stage's counts or by check_symbols).
 void pack_planes(DevStrings &d, int planes, Workspace &ws, hipStream_t s,
@@ -236,15 +245,43 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
                           Workspace &ws, hipStream_t s, uint64_t *host_scratch,
                           KTimer *kt = nullptr);
 
+// The same with every size after the set-up on the device: the records of all
+// repetitions go to key/val (room for reps * si.rec_bound), their count to *R_dev; no
+// host read.  Returns the record capacity used (reps * si.rec_bound).
+int64_t partition_records_streamed(const DevStrings &d, const PartitionParams &p, const SetupInfo &si,
+                                   uint64_t *key, uint64_t *val, int64_t *R_dev, Workspace &ws,
+                                   hipStream_t s, KTimer *kt = nullptr);
+
 // join.hip
 struct GroupInfo {
-    int64_t groups = 0;
+    int64_t groups = 0;          // -1: on the device (slot)
     uint64_t tests = 0;
     int64_t *gstart = nullptr;   // group start index in the sorted records
     uint64_t *tstart = nullptr;  // exclusive prefix of pair tests, groups + 1 entries
+    uint64_t *slot = nullptr;    // streamed: [0] c1 | c2 << 32, [1] groups, [2] tests
+    int64_t gmax = 0;            // streamed: capacity of the group arrays
 };
+// Speed-only choices of the emission kernel (see emit_candidates): gather (m, K) by string
+// id at each use (lazy), one packed (m, K) word per string, tests per thread, workgroups.
+struct EmitHints {
+    bool lazy = true;
+    bool string_words = false;
+    int chunk = 16;
+    int64_t blocks = 4096;
+};
+EmitHints emit_hints(uint64_t tests, int64_t R, int32_t n);
 GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t s,
                       uint64_t *host_scratch);
+// The same with the record count on the device (*R_dev <= R_cap); no host read.
+GroupInfo find_groups_streamed(const uint64_t *key, int64_t R_cap, const int64_t *R_dev,
+                               Workspace &ws, hipStream_t s);
+void emit_candidates_streamed(const uint64_t *val, int64_t R_cap, const int64_t *R_dev,
+                              const GroupInfo &g, const DevStrings &d, uint64_t *out, int64_t cap,
+                              unsigned long long *count, const EmitHints &h, Workspace &ws,
+                              hipStream_t s, KTimer *kt = nullptr);
+const uint32_t *dedup_pairs_streamed(uint64_t *pairs, int64_t cap, const unsigned long long *count,
+                                     int32_t n_first, int32_t n_second, Workspace &ws, hipStream_t s,
+                                     uint64_t **result);
 // Emit candidate pair keys for all pair tests; returns count emitted (<= cap).
 int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, const DevStrings &d,
                         uint64_t *out, int64_t cap, Workspace &ws, hipStream_t s,
@@ -294,5 +331,11 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
                              VerifyTuning *tune, int64_t uniform_k = -1,
                              uint64_t *cells_defer = nullptr, int force_lanes = 0);
 int persist_max_c();
+int verify_small_call_lanes(int cmax);
+void verify_pairs_batched_streamed(const uint64_t *pairs, int64_t cap, const uint32_t *n_dev,
+                                   const DevStrings &A, const DevStrings &B, int kmode, int cmax,
+                                   uint8_t *flags, Workspace &ws, hipStream_t s, KTimer *kt,
+                                   const VerifyTuning &tune, int force_lanes,
+                                   unsigned long long **cells_out);
 
 }  // namespace mj

@@ -34,9 +34,15 @@ __device__ __forceinline__ int32_t owner_of(const int64_t *off, int32_t n, int64
 // of a string that has interior positions.
 __global__ void k_prepare(const int64_t *off, int32_t n, int q, int64_t kuni, const int32_t *kps,
                           int t_div, int t_fixed, int32_t *len, int32_t *kk, int32_t *rr,
-                          uint32_t *halo, uint32_t *err) {
+                          uint32_t *halo, uint32_t *err, unsigned long long *rec_bound,
+                          uint32_t *kmax) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t hr = 0;  // this string's contribution to the halo
+    // and to the bound on the partitions of one repetition: interior anchors are strict
+    // minima of radius r, so two of them are more than r apart, and a string of npos q-gram
+    // starts has at most npos / (r + 1) + 2 partitions (one for m < q, none for m = 0)
+    unsigned long long bnd = 0;
+    uint32_t km = 0;
     if (i < n) {
         int64_t m = off[i + 1] - off[i];
         int64_t K = kuni >= 0 ? kuni : (int64_t)kps[i];
@@ -53,39 +59,57 @@ __global__ void k_prepare(const int64_t *off, int32_t n, int q, int64_t kuni, co
         len[i] = (int32_t)m;
         kk[i] = (int32_t)(K < 0 ? 0 : K);
         rr[i] = (int32_t)std::min<int64_t>(r, 0x7FFFFFFFLL);
+        if (m > 0) bnd = npos <= 0 ? 1ull : (unsigned long long)(npos / (r + 1) + 2);
+        km = (uint32_t)(K < 0 ? 0 : K);
     }
     // one atomic per wave: device-scope atomics on one address serialise
-    for (int d = 32; d >= 1; d >>= 1) hr = max(hr, (uint32_t)__shfl_xor((int)hr, d, 64));
-    if ((threadIdx.x & 63) == 0 && hr) atomicMax(halo, hr);
+    for (int d = 32; d >= 1; d >>= 1) {
+        hr = max(hr, (uint32_t)__shfl_xor((int)hr, d, 64));
+        km = max(km, (uint32_t)__shfl_xor((int)km, d, 64));
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)bnd, d, 64);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(bnd >> 32), d, 64);
+        bnd += ((unsigned long long)hi << 32) | lo;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (hr) atomicMax(halo, hr);
+        if (km) atomicMax(kmax, km);
+        if (bnd) atomicAdd(rec_bound, bnd);
+    }
 }
 
 int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
-                        uint64_t *host_scratch) {
+                        uint64_t *host_scratch, SetupInfo *info) {
     int32_t n = d.n;
     d.len = ws.get_n<int32_t>(n + 1);
     d.kk = ws.get_n<int32_t>(n + 1);
     d.rr = ws.get_n<int32_t>(n + 1);
-    uint32_t *flags = ws.get_n<uint32_t>(4);
-    fill_u32(flags, 0, 2, s);
+    // [0] halo, [1] error bits, [2..3] partition bound (u64), [4] largest K
+    uint32_t *flags = ws.get_n<uint32_t>(8);
+    fill_u32(flags, 0, 6, s);
     if (n > 0) {
         hipLaunchKernelGGL(k_prepare, dim3((n + 255) / 256), dim3(256), 0, s, d.offsets, n, p.q,
                            p.k, p.k_per_string, p.t_div, p.t_fixed, d.len, d.kk, d.rr, flags,
-                           flags + 1);
+                           flags + 1, reinterpret_cast<unsigned long long *>(flags + 2), flags + 4);
         MJ_LAUNCH_CHECK();
     }
-    MJ_HIP(hipMemcpyAsync(host_scratch, flags, 8, hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipMemcpyAsync(host_scratch, flags, 24, hipMemcpyDeviceToHost, s));
     const bool want_total = d.total < 0;  // offsets[n] read back with the flags
     if (want_total)
-        MJ_HIP(hipMemcpyAsync(host_scratch + 1, d.offsets + n, 8, hipMemcpyDeviceToHost, s));
+        MJ_HIP(hipMemcpyAsync(host_scratch + 3, d.offsets + n, 8, hipMemcpyDeviceToHost, s));
     MJ_HIP(hipStreamSynchronize(s));
-    uint32_t hv[2];
-    memcpy(hv, host_scratch, 8);
+    uint32_t hv[6];
+    memcpy(hv, host_scratch, 24);
     if (want_total) {
-        d.total = (int64_t)host_scratch[1];
+        d.total = (int64_t)host_scratch[3];
         check_total(d);
     }
     if (hv[1] & 1u) throw Error(MJ_EINVAL, "offsets must be non-decreasing with lengths < 2^31");
     if (hv[1] & 2u) throw Error(MJ_EINVAL, "K must be >= 0");
+    if (info) {
+        info->halo = (int32_t)hv[0];
+        info->rec_bound = (int64_t)(((uint64_t)hv[3] << 32) | hv[2]);
+        info->kmax = (int32_t)hv[4];
+    }
     return (int32_t)hv[0];
 }
 
@@ -876,9 +900,19 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
     const uint8_t *__restrict__ chars, int64_t total, int aligned4,
     const TileDesc *__restrict__ td, int TP, uint64_t B, uint64_t salt_f,
     const uint64_t *__restrict__ table, int pt, int bits, uint64_t B4, uint64_t B8, uint64_t *key,
-    uint64_t *val, uint32_t *len) {
+    uint64_t *val, uint32_t *len, const uint32_t *__restrict__ Rdev,
+    const int64_t *__restrict__ base_dev) {
     extern __shared__ uint64_t Ts[];
     __shared__ uint32_t stage[STAGED ? REC_STAGE_WORDS : 1];
+    // sizes known on the device only: this repetition's record count and where its records
+    // go (R is then the bound the grid was sized by)
+    if (Rdev) R = min<int64_t>(R, (int64_t)*Rdev);
+    if (base_dev) {
+        const int64_t b = *base_dev;
+        key += b;
+        val += b;
+        if (len) len += b;
+    }
     const int nsym = 1 << bits;
     const int n4 = 1 << (4 * bits);  // pt == 0: chunks of 4 symbols
     const int pbase = pt ? 0 : 2 * n4;  // the power tables
@@ -1177,7 +1211,8 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
                                (size_t)nc * 8, s, apos, R[rho], d.offsets, d.n, d.chars, d.total,
                                aligned4, ts, TP, B, salt_f, phi_table, pt, d.bits, B4, B8,
                                out.key + base, out.val + base,
-                               out.with_len ? out.len + base : nullptr);
+                               out.with_len ? out.len + base : nullptr, (const uint32_t *)nullptr,
+                               (const int64_t *)nullptr);
             MJ_LAUNCH_CHECK();
             if (kt) kt->end(tr, s);
         }
@@ -1185,6 +1220,115 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     }
     out.count = base;
     return total;
+}
+
+// Record bases of the repetitions and the record total, from the repetitions' scanned
+// anchor-tile counts (pre_all holds reps arrays of ntiles + 1 words, the last one each
+// repetition's count).
+__global__ void k_rep_bases(const uint32_t *pre_all, int reps, int64_t ntiles, int64_t *base,
+                            int64_t *total) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int64_t acc = 0;
+    for (int r = 0; r < reps; r++) {
+        base[r] = acc;
+        acc += pre_all[(int64_t)r * (ntiles + 1) + ntiles];
+    }
+    *total = acc;
+}
+
+int64_t partition_records_streamed(const DevStrings &d, const PartitionParams &p, const SetupInfo &si,
+                                   uint64_t *key, uint64_t *val, int64_t *R_dev, Workspace &ws,
+                                   hipStream_t s, KTimer *kt) {
+    const int reps = std::max(1, p.reps);
+    const int64_t bound = si.rec_bound;  // partitions of one repetition, at most
+    if (d.total == 0 || bound == 0) {
+        fill_u64(reinterpret_cast<uint64_t *>(R_dev), 0, 1, s);
+        return 0;
+    }
+    int H = std::max<int32_t>(si.halo, 1);
+    if (H > 1920)
+        throw Error(MJ_ECAPACITY, "radius " + std::to_string(H) + " exceeds the supported 1920");
+    const int region = (2048 - 2 * H >= 1024) ? 2048 : 4096;
+    int TP = ((region - 2 * H) / 64) * 64;
+    int64_t ntiles = (d.total + TP - 1) / TP;
+    int64_t nw = (d.total + 63) / 64;
+    if (ntiles > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many tiles");
+    if ((int64_t)d.n + d.total / 2 + 2 > 0xFFFFFFF0LL)
+        throw Error(MJ_ECAPACITY, "more than 2^32 partitions per repetition");
+    const int code_bits = p.q * d.bits;
+    const int aligned4 = ((uintptr_t)d.chars & 3) == 0 ? 1 : 0;
+    const int packed = d.packing == MJ_PACK_2BIT ? 1 : 0;
+
+    int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
+    TileDesc *ts = ws.get_n<TileDesc>(ntiles + 1);
+    hipLaunchKernelGGL(k_tile_desc, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s,
+                       d.offsets, d.rr, d.n, d.total, ntiles, TP, H, region, ts);
+    MJ_LAUNCH_CHECK();
+    std::vector<uint64_t *> bitmap(reps);
+    std::vector<uint32_t *> tcount(reps);
+    uint32_t *pre_all = ws.get_n<uint32_t>((size_t)reps * (ntiles + 1));
+    uint16_t *rank = code_bits <= RANK_MAX_BITS ? ws.get_n<uint16_t>((size_t)1 << code_bits) : nullptr;
+    for (int rho = 0; rho < reps; rho++) {
+        const uint64_t salt = mix64(p.seed + (uint64_t)rho + GAMMA);
+        bitmap[rho] = ws.get_n<uint64_t>(nw + 1);
+        tcount[rho] = ws.get_n<uint32_t>(ntiles + 1);
+        if (rank) {
+            const int nc = 1 << code_bits;
+            hipLaunchKernelGGL(k_rank_table, dim3((nc + 3) / 4), dim3(256), 0, s, nc, salt,
+                               p.pi_table, rank);
+            MJ_LAUNCH_CHECK();
+        }
+        const size_t rank_lds = rank ? ((size_t)2 << code_bits) + 16 : 0;
+#define MJ_ANCHORS(R, V)                                                                        \
+        hipLaunchKernelGGL((k_anchor_tiles<R, V>), dim3((unsigned)ntiles), dim3(AT_THREADS), rank_lds, s, \
+                           d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, rank, \
+                           d.rr, TP, H, ts, aligned4, packed, bitmap[rho], tcount[rho])
+        if (rank) {
+            if (region == 2048) MJ_ANCHORS(2048, uint32_t); else MJ_ANCHORS(4096, uint32_t);
+        } else {
+            if (region == 2048) MJ_ANCHORS(2048, uint64_t); else MJ_ANCHORS(4096, uint64_t);
+        }
+#undef MJ_ANCHORS
+        MJ_LAUNCH_CHECK();
+    }
+    if (kt) kt->end(th, s, reps);
+    for (int rho = 0; rho < reps; rho++)
+        exclusive_scan_u32(tcount[rho], pre_all + (int64_t)rho * (ntiles + 1), ntiles, ws, s);
+    int64_t *base_dev = ws.get_n<int64_t>(reps + 1);
+    hipLaunchKernelGGL(k_rep_bases, dim3(1), dim3(64), 0, s, pre_all, reps, ntiles, base_dev, R_dev);
+    MJ_LAUNCH_CHECK();
+
+    const uint64_t B = 2 + mix64(p.seed ^ GAMMA_B) % (P61 - 3);
+    const uint64_t salt_f = mix64(p.seed + GAMMA);
+    const int pt = (d.bits > 2 || (packed && d.bits != 2)) ? 1 : 0;
+    uint64_t B4 = 1;
+    for (int i = 0; i < 4; i++) B4 = (uint64_t)(((unsigned __int128)B4 * B) % P61);
+    const uint64_t B8 = (uint64_t)(((unsigned __int128)B4 * B4) % P61);
+    const int nc = (pt ? 0 : 2 << (4 * d.bits)) + (8 << d.bits);
+    uint64_t *phi_table = ws.get_n<uint64_t>(nc);
+    hipLaunchKernelGGL(k_phi_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, d.bits, B, pt,
+                       packed, phi_table);
+    MJ_LAUNCH_CHECK();
+    int64_t *apos = ws.get_n<int64_t>(bound + 1);
+    // partitions average about half the bound's length (the bound counts anchors r + 1
+    // apart, Lemma 1 expects them 2r + 1 apart): stage the symbols when that is 24 or more
+    const bool stg = d.total >= 12 * bound;
+    auto kern = packed ? (stg ? k_records<true, true> : k_records<false, true>)
+                       : (stg ? k_records<true, false> : k_records<false, false>);
+    for (int rho = 0; rho < reps; rho++) {
+        const uint32_t *pre = pre_all + (int64_t)rho * (ntiles + 1);
+        hipLaunchKernelGGL(k_anchor_scatter, dim3((unsigned)ntiles), dim3(64), 0, s, bitmap[rho], nw,
+                           TP / 64, pre, ntiles, apos, d.total);
+        MJ_LAUNCH_CHECK();
+        int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
+        hipLaunchKernelGGL(kern, dim3(grid_for(bound, REC_THREADS, 65535)), dim3(REC_THREADS),
+                           (size_t)nc * 8, s, apos, bound, d.offsets, d.n, d.chars, d.total,
+                           aligned4, ts, TP, B, salt_f, phi_table, pt, d.bits, B4, B8, key, val,
+                           (uint32_t *)nullptr, pre + ntiles, base_dev + rho);
+        MJ_LAUNCH_CHECK();
+        if (kt) kt->end(tr, s);
+    }
+    return bound * reps;
 }
 
 }  // namespace mj

@@ -480,15 +480,19 @@ int64_t compact_flags(const uint8_t *flags, int64_t n, int64_t *idx_out, Workspa
                                         host_scratch);
 }
 
-__global__ void k_gather_u64(const uint64_t *src, const int64_t *idx, uint64_t *dst, int64_t n) {
+__global__ void k_gather_u64(const uint64_t *src, const int64_t *idx, uint64_t *dst, int64_t n,
+                             const uint32_t *n_dev) {
+    if (n_dev) n = min(n, (int64_t)*n_dev);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) dst[i] = src[idx[i]];
 }
 
-void gather_u64(const uint64_t *src, const int64_t *idx, uint64_t *dst, int64_t n, hipStream_t s) {
+void gather_u64(const uint64_t *src, const int64_t *idx, uint64_t *dst, int64_t n, hipStream_t s,
+                const uint32_t *n_dev) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_gather_u64, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, src, idx, dst, n);
+    hipLaunchKernelGGL(k_gather_u64, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, src, idx, dst, n,
+                       n_dev);
     MJ_LAUNCH_CHECK();
 }
 
@@ -527,20 +531,36 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t ntiles) {
     return x * per + min(x, rem) + (b >> 3);
 }
 
+// The tile of workgroup b when only the first nt_act of ntiles tiles hold elements (a
+// count known on the device): those are spread over the XCDs as above, and workgroups
+// b >= nt_act take the empty tiles b (whose counts are zero).
+__device__ __forceinline__ int64_t xcd_tile_act(int64_t b, int64_t n) {
+    const int64_t nt_act = (n + RS_TILE - 1) / RS_TILE;
+    return b < nt_act ? xcd_tile(b, nt_act) : b;
+}
+
 __device__ __forceinline__ uint64_t lanes_below() {
     const int lane = threadIdx.x & 63;
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
 // Digit counts of one tile, written digit-major: cnt[d * ntiles + tile].
+// n_dev (nullable): the element count on the device (n is then the capacity the tiles
+// cover; tiles past the count write zero counts).
 __global__ __launch_bounds__(RS_THREADS) void k_rs_tile_counts(const uint64_t *__restrict__ key,
                                                                int64_t n, int shift, int64_t ntiles,
-                                                               uint32_t *__restrict__ cnt) {
+                                                               uint32_t *__restrict__ cnt,
+                                                               const int64_t *__restrict__ n_dev) {
+    if (n_dev) n = min(n, *n_dev);
+    const int64_t tile = xcd_tile_act(blockIdx.x, n);
+    if (tile * RS_TILE >= n) {  // an empty tile: zero counts (the whole workgroup)
+        cnt[(int64_t)threadIdx.x * ntiles + tile] = 0;
+        return;
+    }
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t tile = xcd_tile(blockIdx.x, ntiles);
     const int64_t base = tile * RS_TILE + (int64_t)wave * RS_WAVE_SPAN;
     const uint64_t below = lanes_below();
     for (int c = 0; c < RS_ITEMS; c++) {
@@ -581,7 +601,9 @@ template <bool HASV>
 __global__ __launch_bounds__(RS_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const uint64_t *__restrict__ vin, uint64_t *__restrict__ kout,
     uint64_t *__restrict__ vout, int64_t n, int shift, int64_t ntiles,
-    const uint32_t *__restrict__ off) {
+    const uint32_t *__restrict__ off, const int64_t *__restrict__ n_dev) {
+    if (n_dev) n = min(n, *n_dev);
+    if ((int64_t)blockIdx.x * RS_TILE >= n) return;  // an empty tile (whole workgroup)
     __shared__ uint32_t wc[RS_WAVES][256];  // per-wave digit counts, then per-wave offsets
     __shared__ uint32_t gbase[256];         // global position minus tile-local position
     __shared__ uint32_t tmp[RS_WAVES];
@@ -589,7 +611,7 @@ __global__ __launch_bounds__(RS_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int w = 0; w < RS_WAVES; w++) wc[w][threadIdx.x] = 0;
     __syncthreads();
-    const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+    const int64_t tile = xcd_tile_act(blockIdx.x, n);
     const int64_t tile0 = tile * RS_TILE;
     const int64_t base = tile0 + (int64_t)wave * RS_WAVE_SPAN;
     const uint64_t below = lanes_below();
@@ -668,7 +690,7 @@ __global__ __launch_bounds__(RS_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
 }
 
 void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Workspace &ws,
-                hipStream_t s) {
+                hipStream_t s, const int64_t *n_dev) {
     if (n <= 1) return;
     if (n > 0xFFFFFFF0LL) throw Error(MJ_ECAPACITY, "sort of more than 2^32 elements");
     int passes[8], np = 0;
@@ -686,15 +708,15 @@ void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Work
     for (int t = 0; t < np; t++) {
         const int shift = 8 * passes[t];
         hipLaunchKernelGGL(k_rs_tile_counts, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, ka, n,
-                           shift, ntiles, cnt);
+                           shift, ntiles, cnt, n_dev);
         MJ_LAUNCH_CHECK();
         exclusive_scan_u32(cnt, off, 256 * ntiles, ws, s);
         if (val)
             hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s,
-                               ka, va, kb, vb, n, shift, ntiles, off);
+                               ka, va, kb, vb, n, shift, ntiles, off, n_dev);
         else
             hipLaunchKernelGGL(k_rs_scatter<false>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s,
-                               ka, nullptr, kb, nullptr, n, shift, ntiles, off);
+                               ka, nullptr, kb, nullptr, n, shift, ntiles, off, n_dev);
         MJ_LAUNCH_CHECK();
         std::swap(ka, kb);
         std::swap(va, vb);
@@ -722,7 +744,8 @@ void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Work
 constexpr int RUN_SEGS = 1024;
 constexpr int RUN_CSTRIDE = 64;  // uint64 words between two segment counters
 __global__ void k_run_bits(const uint64_t *__restrict__ key, int64_t n, uint64_t *__restrict__ rsb,
-                           uint64_t *__restrict__ brb) {
+                           uint64_t *__restrict__ brb, const int64_t *__restrict__ n_dev) {
+    if (n_dev) n = min(n, *n_dev);
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;  // a multiple of 64
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - lane < n; i += stride) {
@@ -740,7 +763,8 @@ __global__ void k_run_bits(const uint64_t *__restrict__ key, int64_t n, uint64_t
 
 __global__ void k_mixed_runs(const uint64_t *__restrict__ rsb, const uint64_t *__restrict__ brb,
                              int64_t n, int64_t seg_words, int64_t *runs, int64_t seg_cap,
-                             unsigned long long *count) {
+                             unsigned long long *count, const int64_t *__restrict__ n_dev) {
+    if (n_dev) n = min(n, *n_dev);
     const int64_t nw = (n + 63) >> 6;
     for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw;
          w += (int64_t)gridDim.x * blockDim.x) {
@@ -834,9 +858,9 @@ __global__ void k_sort_runs(uint64_t *__restrict__ key, uint64_t *__restrict__ v
 }
 
 void sort_records(uint64_t *key, uint64_t *val, int64_t n, Workspace &ws, hipStream_t s,
-                  uint64_t *host_scratch) {
+                  uint64_t *host_scratch, const int64_t *n_dev) {
     if (n <= 1) return;
-    radix_sort(key, val, n, 0xFFFFFFFF00000000ull, ws, s);
+    radix_sort(key, val, n, 0xFFFFFFFF00000000ull, ws, s, n_dev);
     const int64_t nw = (n + 63) / 64;
     const int64_t seg_words = (nw + RUN_SEGS - 1) / RUN_SEGS;
     const int64_t seg_cap = 32 * seg_words + 1;  // first changes a segment can hold
@@ -845,10 +869,11 @@ void sort_records(uint64_t *key, uint64_t *val, int64_t n, Workspace &ws, hipStr
     uint64_t *brb = ws.get_n<uint64_t>(nw + 1);
     unsigned long long *count = (unsigned long long *)ws.get_n<uint64_t>(RUN_SEGS * RUN_CSTRIDE);
     fill_u64((uint64_t *)count, 0, RUN_SEGS * RUN_CSTRIDE, s);
-    hipLaunchKernelGGL(k_run_bits, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, key, n, rsb, brb);
+    hipLaunchKernelGGL(k_run_bits, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, key, n, rsb, brb,
+                       n_dev);
     MJ_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_mixed_runs, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s, rsb, brb, n,
-                       seg_words, runs, seg_cap, count);
+                       seg_words, runs, seg_cap, count, n_dev);
     MJ_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sort_runs, dim3(4, RUN_SEGS), dim3(256), 0, s, key, val, runs, seg_cap,
                        count);

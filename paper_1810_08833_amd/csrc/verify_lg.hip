@@ -74,7 +74,9 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
                                                         int64_t n, VSet A, VSet B, int kmode,
                                                         uint8_t *__restrict__ flags,
                                                         unsigned long long *cells,
-                                                        unsigned long long *next) {
+                                                        unsigned long long *next,
+                                                        const uint32_t *__restrict__ ndev) {
+    if (ndev) n = min(n, (int64_t)*ndev);  // the pair count on the device (n: its capacity)
     constexpr int NW = NWL * G;
     const int lane = threadIdx.x & 63;
     const int g = lane & (G - 1);
@@ -405,7 +407,9 @@ __global__ __launch_bounds__(256) void k_verify_bidir(const uint64_t *__restrict
                                                       int64_t n, VSet A, VSet B, int kmode,
                                                       uint8_t *__restrict__ flags,
                                                       unsigned long long *cells,
-                                                      unsigned long long *next) {
+                                                      unsigned long long *next,
+                                                      const uint32_t *__restrict__ ndev) {
+    if (ndev) n = min(n, (int64_t)*ndev);  // the pair count on the device (n: its capacity)
     // meeting of the two halves: the forward and backward windows of each pair's first lane
     __shared__ uint32_t meet[4][NW + 2][128];
     const int lane = threadIdx.x & 63;
@@ -726,7 +730,8 @@ __global__ __launch_bounds__(256) void k_verify_bidir(const uint64_t *__restrict
 
 // ---------------------------------------------------------------- configurations
 using PersistKernel = void (*)(const uint64_t *, const int64_t *, int64_t, VSet, VSet, int,
-                               uint8_t *, unsigned long long *, unsigned long long *);
+                               uint8_t *, unsigned long long *, unsigned long long *,
+                               const uint32_t *);
 
 constexpr int NWL_CHOICES[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 11};
 // g == BIDIR: two lanes per pair, split by columns (each lane holds the whole window)
@@ -806,6 +811,16 @@ static int nwl_for(int nw, int g) {
 // The window needs ceil(K/32) + 1 words (at most 11 * 8); K <= 2047 keeps c <= 64.
 int persist_max_c() { return 64; }
 
+// The configuration of calls too small to time: the most lanes per pair that still gives
+// each lane more than one word (one lane when the band fits one word).
+int verify_small_call_lanes(int cmax) {
+    const int nw = cmax + 1;
+    int best = 0;
+    for (int g : G_CHOICES)
+        if (g != BIDIR && nwl_for(nw, g) != 0 && (g == 1 || nwl_for(nw, g / 2) > 1)) best = g;
+    return best;
+}
+
 // Calls with fewer pairs use a fixed configuration instead of timing the choices.
 constexpr int64_t TUNE_MIN_PAIRS = 4096;
 
@@ -836,7 +851,9 @@ __device__ __forceinline__ int lpt_bin(const uint64_t pr, const VSet &A, const V
     return LPT_BINS - 1 - min(nt >> 4, LPT_BINS - 1);  // longest first
 }
 
-__global__ void k_lpt_hist(const uint64_t *pairs, int64_t n, VSet A, VSet B, uint32_t *cnt) {
+__global__ void k_lpt_hist(const uint64_t *pairs, int64_t n, VSet A, VSet B, uint32_t *cnt,
+                           const uint32_t *ndev) {
+    if (ndev) n = min(n, (int64_t)*ndev);
     __shared__ uint32_t h[LPT_BINS];
     for (int t = threadIdx.x; t < LPT_BINS; t += blockDim.x) h[t] = 0;
     __syncthreads();
@@ -854,7 +871,8 @@ __global__ void k_lpt_hist(const uint64_t *pairs, int64_t n, VSet A, VSet B, uin
 constexpr int LPT_ITEMS = 16;
 __global__ __launch_bounds__(256) void k_lpt_scatter(const uint64_t *pairs, int64_t n, VSet A,
                                                      VSet B, const uint32_t *off, uint32_t *fill,
-                                                     int64_t *order) {
+                                                     int64_t *order, const uint32_t *ndev) {
+    if (ndev) n = min(n, (int64_t)*ndev);
     __shared__ uint32_t cnt[LPT_BINS];
     __shared__ uint32_t base[LPT_BINS];
     for (int t = threadIdx.x; t < LPT_BINS; t += blockDim.x) cnt[t] = 0;
@@ -887,14 +905,15 @@ __global__ __launch_bounds__(256) void k_lpt_scatter(const uint64_t *pairs, int6
 static void launch_persist(int nwl, int g, int np, int max_blocks, const uint64_t *pairs,
                            const int64_t *order, int64_t n, const VSet &va, const VSet &vb,
                            int kmode, uint8_t *flags, unsigned long long *cells,
-                           unsigned long long *next, hipStream_t s, bool next_zero = false) {
+                           unsigned long long *next, hipStream_t s, bool next_zero = false,
+                           const uint32_t *ndev = nullptr) {
     if (!next_zero) fill_u64((uint64_t *)next, 0, QUEUES * QSTRIDE, s);
     // at most max_blocks resident workgroups, and no more than the pairs need
     int64_t groups_per_block = 256 / (g == BIDIR ? 2 : g);
     int64_t blocks = (n + groups_per_block - 1) / groups_per_block;
     blocks = std::min<int64_t>(blocks, max_blocks);
     hipLaunchKernelGGL(persist_kernel(nwl, g, np), dim3((unsigned)std::max<int64_t>(blocks, 1)),
-                       dim3(256), 0, s, pairs, order, n, va, vb, kmode, flags, cells, next);
+                       dim3(256), 0, s, pairs, order, n, va, vb, kmode, flags, cells, next, ndev);
     MJ_LAUNCH_CHECK();
 }
 
@@ -938,13 +957,14 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     }
     if (cmax > persist_max_c())
         throw Error(MJ_ECAPACITY, "threshold K above the batched verifier's band limit (K <= 2047)");
-    hipLaunchKernelGGL(k_lpt_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, pairs, n, va, vb, cnt);
+    hipLaunchKernelGGL(k_lpt_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, pairs, n, va, vb, cnt,
+                       (const uint32_t *)nullptr);
     MJ_LAUNCH_CHECK();
     exclusive_scan_u32(cnt, off, LPT_BINS, ws, s);
     const int64_t sblocks = (n + 256 * LPT_ITEMS - 1) / (256 * LPT_ITEMS);
     if (sblocks > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many pairs for one verification");
     hipLaunchKernelGGL(k_lpt_scatter, dim3((unsigned)sblocks), dim3(256), 0, s, pairs, n, va, vb,
-                       off, fillc, order);
+                       off, fillc, order, (const uint32_t *)nullptr);
     MJ_LAUNCH_CHECK();
 
     const int nw = cmax + 1;
@@ -962,8 +982,7 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
         // a small call leaves most of the chip idle: the most lanes per pair (shortest
         // path per pair); timing the choices would cost more than the work.  Without a
         // tuning table (latency-first callers) the same fixed choice.
-        for (int g : G_CHOICES)
-            if (g != BIDIR && nwl_for(nw, g) != 0 && (g == 1 || nwl_for(nw, g / 2) > 1)) best_g = g;
+        best_g = verify_small_call_lanes(cmax);
         best_blocks = 512;
     }
     if (best_g == 0) {
@@ -1031,6 +1050,57 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     memcpy(hv, host_scratch, 16);
     if (hv[1]) throw Error(MJ_ECAPACITY, "a pair's band exceeds the verifier window");
     return (int64_t)hv[0];
+}
+
+// The batched verification with the pair count on the device (*n_dev <= cap): pairs
+// longest first, then the persistent launch in the configuration the context timed for this
+// band size (the caller makes sure one is known: `cmax` words of band from the largest K),
+// no host read.  flags[n .. cap) are written 0; the band-cell count and the window error
+// word go to cells_out[0..1] (device).
+void verify_pairs_batched_streamed(const uint64_t *pairs, int64_t cap, const uint32_t *n_dev,
+                                   const DevStrings &A, const DevStrings &B, int kmode, int cmax,
+                                   uint8_t *flags, Workspace &ws, hipStream_t s, KTimer *kt,
+                                   const VerifyTuning &tune, int force_lanes,
+                                   unsigned long long **cells_out) {
+    const int np = verify_planes(std::max(A.bits, B.bits));
+    VSet va = vset(A), vb = vset(B);
+    cap = std::max<int64_t>(cap, 1);
+    constexpr int64_t ZNEXT = 2 * QUEUES * QSTRIDE, ZCNT = LPT_BINS + 4;
+    uint32_t *zb = ws.get_n<uint32_t>(ZNEXT + 4 + 4 + 2 * ZCNT);
+    unsigned long long *next = (unsigned long long *)zb;
+    unsigned long long *cells = (unsigned long long *)(zb + ZNEXT);
+    uint32_t *cnt = zb + ZNEXT + 8;
+    uint32_t *fillc = cnt + ZCNT;
+    fill_u32(zb, 0, ZNEXT + 8 + 2 * ZCNT, s);
+    *cells_out = cells;
+    fill_u32(reinterpret_cast<uint32_t *>(flags), 0, (cap + 3) / 4, s);
+    uint32_t *off = ws.get_n<uint32_t>(LPT_BINS + 1);
+    int64_t *order = ws.get_n<int64_t>(cap);
+    if (cmax > persist_max_c())
+        throw Error(MJ_ECAPACITY, "threshold K above the batched verifier's band limit (K <= 2047)");
+    hipLaunchKernelGGL(k_lpt_hist, dim3(grid_for(cap, 256, 1024)), dim3(256), 0, s, pairs, cap, va, vb,
+                       cnt, n_dev);
+    MJ_LAUNCH_CHECK();
+    exclusive_scan_u32(cnt, off, LPT_BINS, ws, s);
+    const int64_t sblocks = (cap + 256 * LPT_ITEMS - 1) / (256 * LPT_ITEMS);
+    if (sblocks > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many pairs for one verification");
+    hipLaunchKernelGGL(k_lpt_scatter, dim3((unsigned)sblocks), dim3(256), 0, s, pairs, cap, va, vb,
+                       off, fillc, order, n_dev);
+    MJ_LAUNCH_CHECK();
+    const int nw = cmax + 1;
+    const int npi = np / 2 - 1;
+    const int ci = std::min(cmax, 63);
+    int g = tune.best_g[ci][npi], blocks = tune.best_blocks[ci][npi];
+    if (force_lanes != 0) {
+        g = force_lanes == -2 ? BIDIR : force_lanes;
+        blocks = 512;
+    }
+    if (g == 0 || nwl_for(nw, g) == 0)
+        throw Error(MJ_EINVAL, "no verifier configuration for this band size");
+    int th = kt ? kt->begin(KTimer::VERIFY, s) : -1;
+    launch_persist(nwl_for(nw, g), g, np, blocks, pairs, order, cap, va, vb, kmode, flags, cells, next,
+                   s, true, n_dev);
+    if (kt) kt->end(th, s);
 }
 
 }  // namespace mj

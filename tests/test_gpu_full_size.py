@@ -57,11 +57,15 @@ def test_join_full_size_identical(mj, name):
     cand, _ = mj.candidates(ds, params(mj, g, S.lengths()))
     assert cand.size == g["candidates"]
     assert digest(cand) == g["candidates_sha256"]
-    for verifier in (mj.VERIFY_BATCHED, mj.VERIFY_PLAIN):
-        out, st = mj.join(ds, params(mj, g, S.lengths(), verifier=verifier))
+    ctx = mj.Context()
+    for verifier in (mj.VERIFY_BATCHED, mj.VERIFY_PLAIN, mj.VERIFY_BATCHED):
+        # the second batched join is streamed (stages sized on the device)
+        out, st = mj.join(ds, params(mj, g, S.lengths(), verifier=verifier), ctx=ctx)
         assert st["candidates"] == g["candidates"]
         assert out.size == g["output"], verifier
         assert digest(out) == g["output_sha256"], verifier
+    assert st["streamed"] == 1
+    ctx.close()
 
 
 @pytest.mark.parametrize("name", [n for n in JOINS if GOLDEN[n]["sigma"] <= 4])
@@ -74,8 +78,12 @@ def test_join_full_size_identical_from_packed_input(mj, name):
     ds = mj.DeviceStrings.from_host(S.chars, S.offsets, S.sigma, packing=mj.PACK_2BIT)
     cand, _ = mj.candidates(ds, params(mj, g, S.lengths()))
     assert cand.size == g["candidates"] and digest(cand) == g["candidates_sha256"]
-    out, st = mj.join(ds, params(mj, g, S.lengths()))
-    assert out.size == g["output"] and digest(out) == g["output_sha256"]
+    ctx = mj.Context()
+    for _ in range(2):
+        out, st = mj.join(ds, params(mj, g, S.lengths()), ctx=ctx)
+        assert out.size == g["output"] and digest(out) == g["output_sha256"]
+    assert st["streamed"] == 1
+    ctx.close()
 
 
 @pytest.mark.skipif("dna_index_search" not in GOLDEN, reason="no stored search result")

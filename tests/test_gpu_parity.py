@@ -121,9 +121,11 @@ CASES = {
 
 
 def run_case(mj, name):
+    return params_for(mj, CASES[name], CASES[name]["make"]())
+
+
+def params_for(mj, c, S):
     import torch
-    c = CASES[name]
-    S = c["make"]()
     kw = dict(t_div=c.get("t_div", 1), t_fixed=c.get("t_fixed", 0), reps=c.get("reps", 1))
     if "k_frac" in c:
         kq = dg.k_fraction(S.lengths(), *c["k_frac"])
@@ -431,3 +433,45 @@ def test_server_answers_equal_alone_and_in_the_mix(mj):
     assert max(r["batch_size"] for r in replies) > 1
     assert sum(len(a) for a in alone) > 0
     index.close()
+
+
+# ---------------------------------------------------------------- streamed join
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_streamed_join_identical(mj, name):
+    """A second batched join with the same parameters on a context sizes its stages on the
+    device (two host reads); its output equals the oracle's, and so does a join of another
+    collection through the same context (streamed, or stage by stage when the candidates
+    outgrow the room the first join left)."""
+    say("streamed", name)
+    S, op, gp = run_case(mj, name)
+    _, out_w, _ = oracle.join(S.chars, S.offsets, op)
+    ctx = mj.Context()
+    ds = dev(mj, S)
+    out1, st1 = mj.join(ds, gp, ctx=ctx)
+    out2, st2 = mj.join(ds, gp, ctx=ctx)
+    assert st1["streamed"] == 0 and st2["streamed"] == 1 and st2["host_reads"] == 2
+    assert np.array_equal(out1, out_w) and np.array_equal(out2, out_w)
+    assert st2["candidates"] == st1["candidates"] and st2["records"] == st1["records"]
+    assert st2["pair_tests"] == st1["pair_tests"] and st2["groups"] == st1["groups"]
+    # another collection (every other string) through the same context
+    T = S.subset(np.arange(0, S.n, 2))
+    _, op_t, gp_t = params_for(mj, CASES[name], T)
+    _, out_t, _ = oracle.join(T.chars, T.offsets, op_t)
+    out3, _ = mj.join(dev(mj, T), gp_t, ctx=ctx)
+    assert np.array_equal(out3, out_t)
+    ctx.close()
+
+
+def test_streamed_join_falls_back_when_candidates_outgrow_the_room(mj):
+    """Hints from a join with few candidates per record leave too little room for a
+    collection of near-copies: the streamed join notices and the result is still exact."""
+    say("streamed fallback")
+    sparse = dg.dna_small(seed=81, n_clusters=40, copies=2)
+    dense = heavy_cluster_collection(82)
+    p = mj.Params(q=4, k=20, t_div=1)
+    ctx = mj.Context()
+    mj.join(dev(mj, sparse), p, ctx=ctx)
+    _, want, _ = oracle.join(dense.chars, dense.offsets, oracle.make_params(4, 4, k=20, t_div=1))
+    out, st = mj.join(dev(mj, dense), p, ctx=ctx)
+    assert np.array_equal(out, want) and len(want) > 0
+    ctx.close()
