@@ -462,6 +462,11 @@ def measure_join(workload, args, steps, warmup):
     sbs_out, sbs_stats, sbs_ms = timed(mj.VERIFY_BATCHED, streaming=False)
     print("[bench] %s batched, stage by stage: %.3f ms/step" % (workload, sbs_ms), file=sys.stderr,
           flush=True)
+    cap_out, cap_stats, cap_ms = timed(mj.VERIFY_BATCHED, streaming=2)
+    cap_joins = int(sum(1 for s in cap_stats if s["streamed"] == 2))
+    print("[bench] %s batched, captured in HIP graphs: %.3f ms/step (%d of %d joins replayed)"
+          % (workload, cap_ms, cap_joins, len(cap_stats)), file=sys.stderr, flush=True)
+    assert np.array_equal(cap_out, plain_out), "captured and plain joins disagree"
     out, stats, ms = timed(mj.VERIFY_BATCHED)
     st_ms, st_joins = ms, int(sum(s["streamed"] for s in stats))
     print("[bench] %s batched, streamed: %.3f ms/step (%d of %d joins streamed)"
@@ -497,7 +502,11 @@ def measure_join(workload, args, steps, warmup):
                   "verify_kernel_ms": float(np.mean([s["kernel_ms"]["verify"] for s in plain_stats]))},
         "batched_vs_plain": plain_ms / ms,
         "batched_modes": {"streamed_ms_per_step": st_ms, "streamed_joins": st_joins,
-                          "stage_by_stage_ms_per_step": sbs_ms, "headline_mode": mode},
+                          "stage_by_stage_ms_per_step": sbs_ms,
+                          "captured_ms_per_step": cap_ms, "captured_replays": cap_joins,
+                          "headline_mode": mode,
+                          "note": "the headline is the faster mode whose kernels the library "
+                                  "times (captured graphs carry no kernel timers)"},
         "with_upload": {"value": S.n / ((ms + upload_ms) * 1e-3), "upload_ms": upload_ms,
                         "note": "strings uploaded from pageable host memory inside the timing"},
         "verified_pairs_per_s": last["candidates"] / (verify_ms * 1e-3),

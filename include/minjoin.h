@@ -129,7 +129,8 @@ typedef struct {
     int32_t verify_words;  /* band words per lane of the batched verifier */
     int32_t verify_blocks; /* most workgroups the batched verifier's persistent launch may
                               have (fewer when the pairs need fewer) */
-    int32_t streamed;      /* 1: the join sized its stages on the device (see mj_join) */
+    int32_t streamed;      /* 1: the join sized its stages on the device (see mj_join);
+                              2: the same, replayed from captured graphs */
     int32_t host_reads;    /* reads of device values the host waited for: 2 when
                               streamed, 0 (not counted) stage by stage */
 } mj_stats;
@@ -156,10 +157,14 @@ typedef struct {
  * EDEVICE on HIP errors. */
 mj_status mj_ctx_create(int device, const mj_allocator *alloc, mj_ctx **out);
 void mj_ctx_destroy(mj_ctx *ctx);
-/* Streamed joins (see mj_join) on (1, the default) or off (0): off, every join runs stage
- * by stage, each stage sized exactly from a read-back (less memory: the streamed join holds
- * capacities, e.g. records for the set-up's bound).  EINVAL for a NULL context. */
-mj_status mj_ctx_set_streaming(mj_ctx *ctx, int enable);
+/* How joins after the first (see mj_join) run: 0 stage by stage, each stage sized exactly
+ * from a read-back (the least memory); 1 streamed (the default: stages sized on the device
+ * from capacities, two host reads); 2 streamed and captured into two HIP graphs (the
+ * set-up and everything after it), replayed while the strings' pointers and sizes, the
+ * parameters and the set-up's results stay the same.  Captured joins give no kernel times
+ * in mj_stats (stage_ms[0] is the set-up graph, stage_ms[7] the main graph).  EINVAL for a
+ * NULL context or another mode. */
+mj_status mj_ctx_set_streaming(mj_ctx *ctx, int mode);
 
 /* Thread-local description of the last error (never NULL). */
 const char *mj_last_error(void);

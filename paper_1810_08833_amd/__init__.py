@@ -221,9 +221,10 @@ class Context:
                                ctypes.byref(h)))
         self.handle = h
 
-    def set_streaming(self, enable: bool):
-        """Streamed joins (two host reads per join) on or off (stage by stage)."""
-        _check(load_library().mj_ctx_set_streaming(self.handle, 1 if enable else 0))
+    def set_streaming(self, mode):
+        """0 (or False): stage by stage; 1 (or True): streamed, two host reads per join;
+        2: streamed and captured into HIP graphs, replayed while inputs repeat."""
+        _check(load_library().mj_ctx_set_streaming(self.handle, int(mode)))
 
     def close(self):
         if self.handle:

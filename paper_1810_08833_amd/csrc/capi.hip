@@ -61,6 +61,9 @@ extern "C" void mj_ctx_destroy(mj_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     AllocScope as(ctx->ws.alloc);
+    if (ctx->graph.setup) (void)hipGraphExecDestroy(ctx->graph.setup);
+    if (ctx->graph.main) (void)hipGraphExecDestroy(ctx->graph.main);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     ctx->kt.destroy();
@@ -68,10 +71,17 @@ extern "C" void mj_ctx_destroy(mj_ctx *ctx) {
     delete ctx;
 }
 
-extern "C" mj_status mj_ctx_set_streaming(mj_ctx *ctx, int enable) {
+static void graph_drop(mj_ctx *ctx);
+
+extern "C" mj_status mj_ctx_set_streaming(mj_ctx *ctx, int mode) {
     if (!ctx) return fail(MJ_EINVAL, "ctx is NULL");
-    ctx->streaming = enable != 0;
+    if (mode < 0 || mode > 2) return fail(MJ_EINVAL, "streaming mode must be 0, 1 or 2");
+    MJ_API_BEGIN
+    MJ_HIP(hipSetDevice(ctx->device));
+    if (mode != 2) graph_drop(ctx);
+    ctx->streaming = mode;
     return MJ_OK;
+    MJ_API_END
 }
 
 // ---------------------------------------------------------------- helpers
@@ -358,78 +368,88 @@ static bool hints_match(const StreamHints &h, const mj_strings *st, const mj_par
            h.packing == st->packing && h.verify_lanes == p->verify_lanes;
 }
 
-static mj_pairs *run_join_streamed(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
-                                   hipStream_t s, mj_stats *stats) {
-    Workspace &ws = ctx->ws;
-    Released rel{ws};
-    StageTimer tm(ctx, s);
+static bool plan_streamed(mj_ctx *ctx, const mj_params *params, const DevStrings &d,
+                          const PartitionParams &pp, const SetupInfo &si, StreamedPlan &pl) {
     const StreamHints &h = ctx->stream;
-    DevStrings d = view(strings, s, ctx->pinned, false);
-    PartitionParams pp = to_pp(params, d.bits);
-    SetupInfo si;
-    (void)prepare_strings(d, pp, ws, s, ctx->pinned, &si);  // the one read before the end
-    pack_planes(d, verify_planes(d.bits), ws, s);
-    const int cmax = (int)((std::min<int64_t>(params->k >= 0 ? params->k : si.kmax, 0x3FFFFFFF) + 31) >> 5);
-    if (cmax > persist_max_c()) return nullptr;
-    {
-        const int np = verify_planes(d.bits);
-        // the configuration the last join used (the small-call one if it verified nothing)
-        const int g = params->verify_lanes == -2 ? VERIFY_BIDIR
-                    : params->verify_lanes ? params->verify_lanes
-                    : h.verify_g ? h.verify_g : verify_small_call_lanes(cmax);
-        int nwl = 0;
-        for (int v : {1, 2, 3, 4, 5, 6, 7, 8, 9, 11})
-            if (v * (g == VERIFY_BIDIR ? 1 : g) >= cmax + 1) { nwl = v; break; }
-        if (g == 0 || nwl == 0) return nullptr;  // no configuration for this band: stage by stage
-        ctx->tune.best_g[std::min(cmax, 63)][np / 2 - 1] = g;
-        if (!ctx->tune.best_blocks[std::min(cmax, 63)][np / 2 - 1])
-            ctx->tune.best_blocks[std::min(cmax, 63)][np / 2 - 1] = h.verify_blocks ? h.verify_blocks : 512;
-    }
-    tm.mark();  // 0 setup
-    const int reps = pp.reps;
-    const int64_t rcap = std::max<int64_t>(si.rec_bound * reps, 2);
-    uint64_t *key = ws.get_n<uint64_t>(rcap + 1);
-    uint64_t *val = ws.get_n<uint64_t>(rcap + 1);
-    int64_t *R_dev = ws.get_n<int64_t>(2);
-    partition_records_streamed(d, pp, si, key, val, R_dev, ws, s, &ctx->kt);
-    tm.mark();  // 1 partition
+    pl.si = si;
+    pl.cmax = (int)((std::min<int64_t>(params->k >= 0 ? params->k : si.kmax, 0x3FFFFFFF) + 31) >> 5);
+    if (pl.cmax > persist_max_c()) return false;
+    const int np = verify_planes(d.bits);
+    // the configuration the last join used (the small-call one if it verified nothing)
+    const int g = params->verify_lanes == -2 ? VERIFY_BIDIR
+                : params->verify_lanes ? params->verify_lanes
+                : h.verify_g ? h.verify_g : verify_small_call_lanes(pl.cmax);
+    int nwl = 0;
+    for (int v : {1, 2, 3, 4, 5, 6, 7, 8, 9, 11})
+        if (v * (g == VERIFY_BIDIR ? 1 : g) >= pl.cmax + 1) { nwl = v; break; }
+    if (g == 0 || nwl == 0) return false;  // no configuration for this band: stage by stage
+    const int ci = std::min(pl.cmax, 63);
+    ctx->tune.best_g[ci][np / 2 - 1] = g;
+    if (!ctx->tune.best_blocks[ci][np / 2 - 1])
+        ctx->tune.best_blocks[ci][np / 2 - 1] = h.verify_blocks ? h.verify_blocks : 512;
+    pl.rcap = std::max<int64_t>(si.rec_bound * pp.reps, 2);
     // the stages after the partition are sized by the last join's records per bound, with
     // room (more records than that: the join runs again stage by stage)
-    const int64_t scap = std::max<int64_t>(
-        2, std::min<int64_t>(rcap, (int64_t)(1.02 * h.rec_per_bound * (double)rcap) + 4096));
-    sort_records(key, val, scap, ws, s, ctx->pinned, R_dev);
-    tm.mark();  // 2 sort
-    GroupInfo g = find_groups_streamed(key, scap, R_dev, ws, s);
+    pl.scap = std::max<int64_t>(
+        2, std::min<int64_t>(pl.rcap, (int64_t)(1.02 * h.rec_per_bound * (double)pl.rcap) + 4096));
     // candidates before the dedup: the last join's rate per record bound, with room
-    const int64_t ccap = (int64_t)std::min<double>(1.1 * h.cand_per_record * (double)rcap + 65536.0,
-                                                   (double)0x7FFFFFF0LL);
-    uint64_t *cand = ws.get_n<uint64_t>(ccap + 1);
+    pl.ccap = (int64_t)std::min<double>(1.1 * h.cand_per_record * (double)pl.rcap + 65536.0,
+                                        (double)0x7FFFFFF0LL);
+    pl.emit = h.emit;
+    return true;
+}
+
+// Everything from the plane packing to the copy of the result counts into ctx->pinned,
+// with no host read.  tm and kt are null while the launches are captured into a graph.
+static StreamedDev launch_streamed_main(mj_ctx *ctx, DevStrings &d, const PartitionParams &pp,
+                                        const StreamedPlan &pl, const mj_params *params,
+                                        hipStream_t s, StageTimer *tm, KTimer *kt) {
+    Workspace &ws = ctx->ws;
+    StreamedDev dv;
+    pack_planes(d, verify_planes(d.bits), ws, s);
+    if (tm) tm->mark();  // 0 setup
+    uint64_t *key = ws.get_n<uint64_t>(pl.rcap + 1);
+    uint64_t *val = ws.get_n<uint64_t>(pl.rcap + 1);
+    int64_t *R_dev = ws.get_n<int64_t>(2);
+    partition_records_streamed(d, pp, pl.si, key, val, R_dev, ws, s, kt);
+    if (tm) tm->mark();  // 1 partition
+    sort_records(key, val, pl.scap, ws, s, ctx->pinned, R_dev);
+    if (tm) tm->mark();  // 2 sort
+    GroupInfo g = find_groups_streamed(key, pl.scap, R_dev, ws, s);
+    uint64_t *cand = ws.get_n<uint64_t>(pl.ccap + 1);
     unsigned long long *c0 = (unsigned long long *)ws.get_n<uint64_t>(2);
-    emit_candidates_streamed(val, scap, R_dev, g, d, cand, ccap, c0, h.emit, ws, s, &ctx->kt);
-    tm.mark();  // 3 group + filter
+    emit_candidates_streamed(val, pl.scap, R_dev, g, d, cand, pl.ccap, c0, pl.emit, ws, s, kt);
+    if (tm) tm->mark();  // 3 group + filter
     uint64_t *uniq = nullptr;
-    const uint32_t *u = dedup_pairs_streamed(cand, ccap, c0, d.n, d.n, ws, s, &uniq);
-    tm.mark();  // 4 dedup
-    uint8_t *flags = ws.get_n<uint8_t>(ccap + 4);
+    const uint32_t *u = dedup_pairs_streamed(cand, pl.ccap, c0, d.n, d.n, ws, s, &uniq);
+    if (tm) tm->mark();  // 4 dedup
+    uint8_t *flags = ws.get_n<uint8_t>(pl.ccap + 4);
     unsigned long long *cells = nullptr;
-    verify_pairs_batched_streamed(uniq, ccap, u, d, d, 0, cmax, flags, ws, s, &ctx->kt, ctx->tune,
+    verify_pairs_batched_streamed(uniq, pl.ccap, u, d, d, 0, pl.cmax, flags, ws, s, kt, ctx->tune,
                                   params->verify_lanes, &cells);
-    tm.mark();  // 5 verify
-    int64_t *idx = ws.get_n<int64_t>(ccap + 1);
-    const uint32_t *on = compact_flags_async(flags, ccap, idx, ws, s);
-    uint64_t *outbuf = ws.get_n<uint64_t>(ccap + 1);
-    gather_u64(uniq, idx, outbuf, ccap, s, on);
+    if (tm) tm->mark();  // 5 verify
+    int64_t *idx = ws.get_n<int64_t>(pl.ccap + 1);
+    const uint32_t *on = compact_flags_async(flags, pl.ccap, idx, ws, s);
+    dv.outbuf = ws.get_n<uint64_t>(pl.ccap + 1);
+    gather_u64(uniq, idx, dv.outbuf, pl.ccap, s, on);
     uint64_t *res = ws.get_n<uint64_t>(16);
     hipLaunchKernelGGL(k_collect, dim3(1), dim3(64), 0, s, R_dev, g.slot, c0, u, on, cells,
                        (const uint32_t *)d.symbol_err, res);
     MJ_LAUNCH_CHECK();
     MJ_HIP(hipMemcpyAsync(ctx->pinned, res, 10 * 8, hipMemcpyDeviceToHost, s));
-    MJ_HIP(hipStreamSynchronize(s));  // the one read at the end
+    return dv;
+}
+
+// After the final synchronisation: the counts, the result pairs, the stats and the hints
+// of the next join.  nullptr when a capacity was exceeded.
+static mj_pairs *finish_streamed(mj_ctx *ctx, const StreamedPlan &pl, const StreamedDev &dv,
+                                 const DevStrings &d, const PartitionParams &pp, hipStream_t s,
+                                 mj_stats *stats) {
     uint64_t hv[10];
     memcpy(hv, ctx->pinned, sizeof(hv));
-    if (hv[9]) throw Error(MJ_EINVAL, "a symbol code is not below sigma");
     const int64_t R = (int64_t)hv[0], c0h = (int64_t)hv[4], C = (int64_t)hv[5], nout = (int64_t)hv[6];
-    if (c0h > ccap || R > scap) return nullptr;  // more than the room left: stage by stage
+    if (hv[9]) throw Error(MJ_EINVAL, "a symbol code is not below sigma");
+    if (c0h > pl.ccap || R > pl.scap) return nullptr;  // more than the room left: stage by stage
     if (R > 1 && (hv[1] & 0xFFFFFFFFu) != (hv[1] >> 32)) throw Error(MJ_EDEVICE, "group boundary mismatch");
     if (hv[8]) throw Error(MJ_ECAPACITY, "a pair's band exceeds the verifier window");
     mj_pairs *out = new mj_pairs();
@@ -437,8 +457,7 @@ static mj_pairs *run_join_streamed(mj_ctx *ctx, const mj_strings *strings, const
     out->stream = s;
     out->n = nout;
     out->d = (uint64_t *)dev_alloc((size_t)(nout + 1) * 8);
-    if (nout) MJ_HIP(hipMemcpyAsync(out->d, outbuf, (size_t)nout * 8, hipMemcpyDeviceToDevice, s));
-    tm.mark();  // 6 output
+    if (nout) MJ_HIP(hipMemcpyAsync(out->d, dv.outbuf, (size_t)nout * 8, hipMemcpyDeviceToDevice, s));
     if (stats) {
         memset(stats, 0, sizeof(*stats));
         stats->records = R;
@@ -448,21 +467,149 @@ static mj_pairs *run_join_streamed(mj_ctx *ctx, const mj_strings *strings, const
         stats->output = nout;
         stats->band_cells = (int64_t)hv[7];
         stats->positions = d.total * pp.reps;
-        const int ci = std::min(cmax, 63), npi = verify_planes(d.bits) / 2 - 1;
-        stats->verify_group = ctx->tune.best_g[ci][npi] == VERIFY_BIDIR ? -2 : ctx->tune.best_g[ci][npi];
-        for (int v : {1, 2, 3, 4, 5, 6, 7, 8, 9, 11}) {
-            const int gg = ctx->tune.best_g[ci][npi];
-            if (v * (gg == VERIFY_BIDIR ? 1 : gg) >= cmax + 1) { stats->verify_words = v; break; }
-        }
+        const int ci = std::min(pl.cmax, 63), npi = verify_planes(d.bits) / 2 - 1;
+        const int gg = ctx->tune.best_g[ci][npi];
+        stats->verify_group = gg == VERIFY_BIDIR ? -2 : gg;
+        for (int v : {1, 2, 3, 4, 5, 6, 7, 8, 9, 11})
+            if (v * (gg == VERIFY_BIDIR ? 1 : gg) >= pl.cmax + 1) { stats->verify_words = v; break; }
         stats->verify_blocks = ctx->tune.best_blocks[ci][npi];
         stats->streamed = 1;
         stats->host_reads = 2;
     }
-    tm.fill(stats);
     // keep the rates current (capacities of the next join)
-    ctx->stream.cand_per_record = (double)c0h / (double)rcap;
-    ctx->stream.rec_per_bound = (double)R / (double)rcap;
+    ctx->stream.cand_per_record = (double)c0h / (double)pl.rcap;
+    ctx->stream.rec_per_bound = (double)R / (double)pl.rcap;
     ctx->stream.emit = emit_hints((uint64_t)hv[3], R, d.n);
+    return out;
+}
+
+static mj_pairs *run_join_streamed(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
+                                   hipStream_t s, mj_stats *stats) {
+    Workspace &ws = ctx->ws;
+    Released rel{ws};
+    StageTimer tm(ctx, s);
+    DevStrings d = view(strings, s, ctx->pinned, false);
+    PartitionParams pp = to_pp(params, d.bits);
+    SetupInfo si;
+    (void)prepare_strings(d, pp, ws, s, ctx->pinned, &si);  // the one read before the end
+    StreamedPlan pl;
+    if (!plan_streamed(ctx, params, d, pp, si, pl)) return nullptr;
+    StreamedDev dv = launch_streamed_main(ctx, d, pp, pl, params, s, &tm, &ctx->kt);
+    MJ_HIP(hipStreamSynchronize(s));  // the one read at the end
+    mj_pairs *out = finish_streamed(ctx, pl, dv, d, pp, s, stats);
+    if (out) {
+        tm.mark();  // 6 output
+        tm.fill(stats);
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------- captured join
+// The streamed join captured into two HIP graphs and replayed while the strings, the
+// parameters and the set-up results stay the same: the set-up graph (per-string
+// parameters and their read-back), then, once the host has checked those, the main graph
+// (planes to the result counts).  Workspace blocks used by the graphs are held for them;
+// scans take their multi-pass form (no state carried between calls).  Kernel timers cannot
+// sit inside a graph: the stats give the two graphs' times only (stage 0 and stage 7).
+
+static void graph_drop(mj_ctx *ctx) {
+    JoinGraph &gr = ctx->graph;
+    if (gr.setup) (void)hipGraphExecDestroy(gr.setup);
+    if (gr.main) (void)hipGraphExecDestroy(gr.main);
+    gr = JoinGraph();
+    ctx->ws.drop_holds();
+}
+
+static bool graph_key_matches(const JoinGraph &gr, const mj_strings *st, const mj_params *p) {
+    return gr.setup && gr.chars == st->chars && gr.offsets == st->offsets && gr.n == st->n &&
+           gr.sigma == st->sigma && gr.packing == st->packing &&
+           memcmp(&gr.params, p, sizeof(mj_params)) == 0;
+}
+
+// Captures fn's launches on the context's capture stream into an executable graph.
+template <class F>
+static hipGraphExec_t capture(mj_ctx *ctx, F fn) {
+    if (!ctx->cap_stream) MJ_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = ctx->cap_stream;
+    MJ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));  // workspace blocks may be allocated
+    ctx->ws.hold(true);
+    ctx->ws.no_lookback = true;
+    try {
+        fn(cs);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        ctx->ws.hold(false);
+        ctx->ws.no_lookback = false;
+        throw;
+    }
+    ctx->ws.hold(false);
+    ctx->ws.no_lookback = false;
+    hipGraph_t g = nullptr;
+    MJ_HIP(hipStreamEndCapture(cs, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    MJ_HIP(e);
+    return ex;
+}
+
+static mj_pairs *run_join_graph(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
+                                hipStream_t s, mj_stats *stats) {
+    JoinGraph &gr = ctx->graph;
+    Workspace &ws = ctx->ws;
+    Released rel{ws};
+    if (!graph_key_matches(gr, strings, params)) {
+        graph_drop(ctx);
+        gr.chars = strings->chars;
+        gr.offsets = strings->offsets;
+        gr.n = strings->n;
+        gr.sigma = strings->sigma;
+        gr.packing = strings->packing;
+        gr.params = *params;
+        gr.d = view(strings, s, ctx->pinned, false);
+        gr.pp = to_pp(params, gr.d.bits);
+        gr.setup = capture(ctx, [&](hipStream_t cs) { prepare_launch(gr.d, gr.pp, ws, cs, ctx->pinned); });
+    }
+    MJ_HIP(hipEventRecord(ctx->ev[0], s));
+    MJ_HIP(hipGraphLaunch(gr.setup, s));
+    MJ_HIP(hipStreamSynchronize(s));  // the one read before the end
+    DevStrings d = gr.d;  // the set-up graph's arrays; total comes with its read-back
+    SetupInfo si;
+    (void)prepare_finish(d, ctx->pinned, &si);
+    if (!gr.main || si.halo != gr.si.halo || si.rec_bound != gr.si.rec_bound ||
+        si.kmax != gr.si.kmax || d.total != gr.total) {
+        if (gr.main) (void)hipGraphExecDestroy(gr.main);
+        gr.main = nullptr;
+        StreamedPlan pl;
+        if (!plan_streamed(ctx, params, d, gr.pp, si, pl)) return nullptr;
+        gr.plan = pl;
+        gr.si = si;
+        gr.total = d.total;
+        gr.md = d;
+        gr.main = capture(ctx, [&](hipStream_t cs) {
+            gr.dv = launch_streamed_main(ctx, gr.md, gr.pp, gr.plan, params, cs, nullptr, nullptr);
+        });
+    }
+    MJ_HIP(hipEventRecord(ctx->ev[1], s));
+    MJ_HIP(hipGraphLaunch(gr.main, s));
+    MJ_HIP(hipEventRecord(ctx->ev[2], s));
+    MJ_HIP(hipStreamSynchronize(s));  // the one read at the end
+    mj_pairs *out = finish_streamed(ctx, gr.plan, gr.dv, gr.md, gr.pp, s, stats);
+    if (!out) {
+        graph_drop(ctx);  // recaptured with the new capacities next time
+        return nullptr;
+    }
+    if (stats) {
+        MJ_HIP(hipStreamSynchronize(s));
+        float a = 0.f, b = 0.f;
+        MJ_HIP(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
+        MJ_HIP(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
+        stats->stage_ms[0] = a;
+        stats->stage_ms[7] = b;
+        stats->streamed = 2;
+    }
     return out;
 }
 
@@ -477,7 +624,8 @@ extern "C" mj_status mj_join(mj_ctx *ctx, const mj_strings *strings, const mj_pa
     hipStream_t s = (hipStream_t)stream;
     const bool batched = params->verifier == MJ_VERIFY_BATCHED;
     if (batched && ctx->streaming && !ctx->no_tuning && hints_match(ctx->stream, strings, params)) {
-        mj_pairs *r = run_join_streamed(ctx, strings, params, s, stats);
+        mj_pairs *r = ctx->streaming == 2 ? run_join_graph(ctx, strings, params, s, stats)
+                                          : run_join_streamed(ctx, strings, params, s, stats);
         if (r) {
             ctx->streamed_joins++;
             *out = r;

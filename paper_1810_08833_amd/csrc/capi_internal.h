@@ -21,6 +21,34 @@ struct StreamHints {
     int verify_g = 0, verify_blocks = 0;
 };
 
+// Sizes of a streamed join, fixed by the set-up read-back and the hints of the last join,
+// and the device buffer the host copies the result from after the final read.
+struct StreamedPlan {
+    SetupInfo si;
+    int cmax = 0;
+    int64_t rcap = 0, scap = 0, ccap = 0;
+    EmitHints emit;
+};
+struct StreamedDev {
+    uint64_t *outbuf = nullptr;
+};
+
+// A captured join (see run_join_graph in capi.hip): the strings and parameters it was
+// captured for, its two executable graphs, and what the host needs around them.
+struct JoinGraph {
+    const void *chars = nullptr;
+    const int64_t *offsets = nullptr;
+    int32_t n = 0, sigma = 0, packing = 0;
+    mj_params params{};
+    hipGraphExec_t setup = nullptr, main = nullptr;
+    DevStrings d, md;      // after the set-up graph; with the planes of the main graph
+    PartitionParams pp{};
+    SetupInfo si;          // the set-up results the main graph was captured for
+    int64_t total = -1;
+    StreamedPlan plan;     // sizes and buffers of the main graph
+    StreamedDev dv;
+};
+
 struct mj_ctx {
     int device = 0;
     Workspace ws;
@@ -31,8 +59,10 @@ struct mj_ctx {
     // latency first (server workers): the batched verifier takes its fixed small-call
     // configuration instead of timing the choices on a live call
     bool no_tuning = false;
-    bool streaming = true;  // streamed joins allowed (mj_ctx_set_streaming)
+    int streaming = 1;  // 0 stage by stage, 1 streamed, 2 streamed and captured (mj_ctx_set_streaming)
     StreamHints stream;
+    JoinGraph graph;
+    hipStream_t cap_stream = nullptr;  // the stream graphs are captured on
     int streamed_joins = 0, stream_fallbacks = 0;
     // the last stage-by-stage join's emitted candidates, records and record bound
     int64_t last_c0 = 0, last_R = 0, last_rcap = 0;

@@ -90,6 +90,13 @@ class Workspace {
     static constexpr size_t ARENA_SCAN_BYTES = 4096;
     void bind_arena(void *base, size_t bytes);
     bool arena() const { return arena_base_ != nullptr; }
+    // Holding: blocks handed out while holding stay reserved across release_all (their
+    // addresses are baked into a captured graph) until drop_holds.
+    void hold(bool on) { holding_ = on; }
+    void drop_holds();
+    // Scans launch their multi-pass form (no state kept across calls: a captured graph
+    // replays its launch arguments unchanged).
+    bool no_lookback = false;
     // State of the single-pass scans (prims.hip), kept across calls: one word per tile
     // tagged with the call's epoch (so it never needs clearing) and a tile ticket counter
     // that only grows (`base` = its value before the next scan).
@@ -101,7 +108,8 @@ class Workspace {
     } scan;
 
   private:
-    struct Block { void *p; size_t n; bool used; };
+    struct Block { void *p; size_t n; bool used; bool held; };
+    bool holding_ = false;
     std::vector<Block> blocks_;
     size_t held_ = 0;
     uint8_t *arena_base_ = nullptr;
@@ -230,6 +238,11 @@ struct SetupInfo {
 };
 int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
                         uint64_t *host_scratch, SetupInfo *info = nullptr);  // returns the halo
+// The same in two halves: the launches and the copies to host_dst (pinned, 4 words), and,
+// once the stream has synchronised, the checks and results.
+void prepare_launch(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
+                    uint64_t *host_dst);
+int32_t prepare_finish(DevStrings &d, const uint64_t *host_src, SetupInfo *info);
 // Builds the verifier's bit planes and checks every symbol against sigma (the result in
 // d.symbol_err, read with the partition stage's counts or by check_symbols).
 void pack_planes(DevStrings &d, int planes, Workspace &ws, hipStream_t s,

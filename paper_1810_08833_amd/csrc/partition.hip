@@ -77,8 +77,8 @@ __global__ void k_prepare(const int64_t *off, int32_t n, int q, int64_t kuni, co
     }
 }
 
-int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
-                        uint64_t *host_scratch, SetupInfo *info) {
+void prepare_launch(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
+                    uint64_t *host_dst) {
     int32_t n = d.n;
     d.len = ws.get_n<int32_t>(n + 1);
     d.kk = ws.get_n<int32_t>(n + 1);
@@ -92,15 +92,16 @@ int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, 
                            flags + 1, reinterpret_cast<unsigned long long *>(flags + 2), flags + 4);
         MJ_LAUNCH_CHECK();
     }
-    MJ_HIP(hipMemcpyAsync(host_scratch, flags, 24, hipMemcpyDeviceToHost, s));
-    const bool want_total = d.total < 0;  // offsets[n] read back with the flags
-    if (want_total)
-        MJ_HIP(hipMemcpyAsync(host_scratch + 3, d.offsets + n, 8, hipMemcpyDeviceToHost, s));
-    MJ_HIP(hipStreamSynchronize(s));
+    MJ_HIP(hipMemcpyAsync(host_dst, flags, 24, hipMemcpyDeviceToHost, s));
+    if (d.total < 0)  // offsets[n] read back with the flags
+        MJ_HIP(hipMemcpyAsync(host_dst + 3, d.offsets + n, 8, hipMemcpyDeviceToHost, s));
+}
+
+int32_t prepare_finish(DevStrings &d, const uint64_t *host_src, SetupInfo *info) {
     uint32_t hv[6];
-    memcpy(hv, host_scratch, 24);
-    if (want_total) {
-        d.total = (int64_t)host_scratch[3];
+    memcpy(hv, host_src, 24);
+    if (d.total < 0) {
+        d.total = (int64_t)host_src[3];
         check_total(d);
     }
     if (hv[1] & 1u) throw Error(MJ_EINVAL, "offsets must be non-decreasing with lengths < 2^31");
@@ -111,6 +112,13 @@ int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, 
         info->kmax = (int32_t)hv[4];
     }
     return (int32_t)hv[0];
+}
+
+int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
+                        uint64_t *host_scratch, SetupInfo *info) {
+    prepare_launch(d, p, ws, s, host_scratch);
+    MJ_HIP(hipStreamSynchronize(s));
+    return prepare_finish(d, host_scratch, info);
 }
 
 // ---------------------------------------------------------------- bit planes

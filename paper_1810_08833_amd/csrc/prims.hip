@@ -68,6 +68,7 @@ void *Workspace::get(size_t bytes) {
         if (!b.used && b.n >= bytes && (!best || b.n < best->n)) best = &b;
     if (best && best->n <= 4 * bytes + (1 << 20)) {
         best->used = true;
+        best->held = holding_;
         return best->p;
     }
     void *p = nullptr;
@@ -82,14 +83,23 @@ void *Workspace::get(size_t bytes) {
         }
         p = dev_alloc(bytes, alloc);
     }
-    blocks_.push_back({p, bytes, true});
+    blocks_.push_back({p, bytes, true, holding_});
     held_ += bytes;
     return p;
 }
 
 void Workspace::release_all() {
-    for (auto &b : blocks_) b.used = false;
+    for (auto &b : blocks_)
+        if (!b.held) b.used = false;
     if (arena()) arena_used_ = ARENA_SCAN_BYTES;
+}
+
+void Workspace::drop_holds() {
+    for (auto &b : blocks_)
+        if (b.held) {
+            b.held = false;
+            b.used = false;
+        }
 }
 
 
@@ -385,7 +395,7 @@ static void scan_impl(const In *in, T *out, int64_t n, Workspace &ws, hipStream_
     }
     if (nb > 2147483647LL) throw Error(MJ_ECAPACITY, "scan too large");
     if constexpr (sizeof(T) == 4) {
-        if (nb <= SCAN_LOOKBACK_MAX_TILES && !ndev && !total_out) {
+        if (nb <= SCAN_LOOKBACK_MAX_TILES && !ndev && !total_out && !ws.no_lookback) {
             scan_u32_single_pass<In>(in, out, n, nb, ws, s);
             return;
         }

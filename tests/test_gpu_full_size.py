@@ -83,6 +83,11 @@ def test_join_full_size_identical_from_packed_input(mj, name):
         out, st = mj.join(ds, params(mj, g, S.lengths()), ctx=ctx)
         assert out.size == g["output"] and digest(out) == g["output_sha256"]
     assert st["streamed"] == 1
+    ctx.set_streaming(2)  # captured into HIP graphs, then replayed
+    for _ in range(2):
+        out, st = mj.join(ds, params(mj, g, S.lengths()), ctx=ctx)
+        assert out.size == g["output"] and digest(out) == g["output_sha256"]
+    assert st["streamed"] == 2
     ctx.close()
 
 

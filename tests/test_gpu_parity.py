@@ -475,3 +475,36 @@ def test_streamed_join_falls_back_when_candidates_outgrow_the_room(mj):
     out, st = mj.join(dev(mj, dense), p, ctx=ctx)
     assert np.array_equal(out, want) and len(want) > 0
     ctx.close()
+
+
+@pytest.mark.parametrize("name", ["dna_mixed_T_from_K", "protein_per_string_K", "text_q6", "dna_reps3"])
+def test_captured_join_identical(mj, name):
+    """Streamed joins captured into HIP graphs (mj_ctx_set_streaming 2) and replayed: each
+    replay equals the oracle, also after the strings' content changes in place (same
+    pointers and lengths: the graphs replay, or the join runs again stage by stage)."""
+    import torch
+    say("captured", name)
+    S, op, gp = run_case(mj, name)
+    _, out_w, _ = oracle.join(S.chars, S.offsets, op)
+    ctx = mj.Context()
+    ctx.set_streaming(2)
+    ds = dev(mj, S)
+    modes = []
+    for _ in range(3):
+        out, st = mj.join(ds, gp, ctx=ctx)
+        assert np.array_equal(out, out_w)
+        modes.append(st["streamed"])
+    assert modes == [0, 2, 2]
+    # new content, same lengths, same device buffers: every string reversed
+    rev = np.concatenate([S.get(i)[::-1] for i in range(S.n)]) if S.n else S.chars
+    T = dg.from_list([S.get(i)[::-1] for i in range(S.n)], S.sigma)
+    assert np.array_equal(T.offsets, S.offsets)
+    ds.chars.copy_(torch.from_numpy(np.ascontiguousarray(rev, dtype=np.uint8)).cuda()[:ds.chars.numel()])
+    torch.cuda.synchronize()
+    _, out_t, _ = oracle.join(T.chars, T.offsets, op)
+    out, st = mj.join(ds, gp, ctx=ctx)
+    assert np.array_equal(out, out_t)
+    ctx.set_streaming(1)
+    out, st = mj.join(ds, gp, ctx=ctx)
+    assert np.array_equal(out, out_t) and st["streamed"] == 1
+    ctx.close()
