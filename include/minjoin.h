@@ -157,6 +157,12 @@ typedef struct {
  * EDEVICE on HIP errors. */
 mj_status mj_ctx_create(int device, const mj_allocator *alloc, mj_ctx **out);
 void mj_ctx_destroy(mj_ctx *ctx);
+/* Record-pair tests per candidate-emission pass (default 2^28, at least 1024): a join
+ * whose groups hold more tests emits and deduplicates them in passes of this many, then
+ * deduplicates the union, which bounds the candidate buffer (8 bytes per test of a pass)
+ * however skewed the groups are.  EINVAL for a NULL context or a smaller value. */
+mj_status mj_ctx_set_pair_test_pass(mj_ctx *ctx, int64_t tests);
+
 /* How joins after the first (see mj_join) run: 0 stage by stage, each stage sized exactly
  * from a read-back (the least memory); 1 streamed (the default: stages sized on the device
  * from capacities, two host reads); 2 streamed and captured into two HIP graphs (the
@@ -185,9 +191,9 @@ const char *mj_version(void);
  * (which sizes every stage from read-backs) and the result is the same.  EINVAL on bad arguments (q < 1, q*b > 64,
  * t_div < 1, K < -1, sigma outside 2..256, offsets decreasing, a symbol code >= sigma,
  * verifier or verify_lanes not one of the listed values); ECAPACITY when a
- * documented limit is exceeded: record-pair tests of one call above 2^31, a radius r
- * above 1920 on a string long enough to have interior positions, or a candidate whose
- * threshold K is above 2047; ENOMEM when device memory runs out. */
+ * documented limit is exceeded: a candidate whose threshold K is above 2047; ENOMEM when
+ * device memory runs out.  Any radius r is taken: strings with r above 1920 are anchored
+ * by a separate pass over their hashes in device memory (24 bytes per q-gram start). */
 mj_status mj_join(mj_ctx *ctx, const mj_strings *strings, const mj_params *params,
                   void *stream, mj_pairs **out, mj_stats *stats);
 

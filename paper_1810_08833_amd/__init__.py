@@ -83,7 +83,8 @@ class MjReply(ctypes.Structure):
                 ("start_ms", ctypes.c_double), ("done_ms", ctypes.c_double)]
 
 
-EXPORTS = ["mj_ctx_create", "mj_ctx_destroy", "mj_ctx_set_streaming", "mj_last_error", "mj_version", "mj_join",
+EXPORTS = ["mj_ctx_create", "mj_ctx_destroy", "mj_ctx_set_streaming", "mj_ctx_set_pair_test_pass",
+           "mj_last_error", "mj_version", "mj_join",
            "mj_partition", "mj_candidates", "mj_verify", "mj_index_build", "mj_index_free",
            "mj_index_records", "mj_index_bytes", "mj_search", "mj_pairs_count", "mj_pairs_device",
            "mj_pairs_copy_to_host", "mj_pairs_free", "mj_records_count",
@@ -114,6 +115,8 @@ def load_library(path: str = LIB_PATH):
     L.mj_ctx_destroy.restype = None
     L.mj_ctx_set_streaming.argtypes = [VP, ctypes.c_int]
     L.mj_ctx_set_streaming.restype = ctypes.c_int
+    L.mj_ctx_set_pair_test_pass.argtypes = [VP, ctypes.c_int64]
+    L.mj_ctx_set_pair_test_pass.restype = ctypes.c_int
     L.mj_last_error.restype = ctypes.c_char_p
     L.mj_version.restype = ctypes.c_char_p
     L.mj_join.argtypes = [VP, P(MjStrings), P(MjParams), VP, P(VP), P(MjStats)]
@@ -225,6 +228,10 @@ class Context:
         """0 (or False): stage by stage; 1 (or True): streamed, two host reads per join;
         2: streamed and captured into HIP graphs, replayed while inputs repeat."""
         _check(load_library().mj_ctx_set_streaming(self.handle, int(mode)))
+
+    def set_pair_test_pass(self, tests: int):
+        """Record-pair tests per emission pass (joins with more run in passes)."""
+        _check(load_library().mj_ctx_set_pair_test_pass(self.handle, int(tests)))
 
     def close(self):
         if self.handle:

@@ -73,6 +73,13 @@ extern "C" void mj_ctx_destroy(mj_ctx *ctx) {
 
 static void graph_drop(mj_ctx *ctx);
 
+extern "C" mj_status mj_ctx_set_pair_test_pass(mj_ctx *ctx, int64_t tests) {
+    if (!ctx) return fail(MJ_EINVAL, "ctx is NULL");
+    if (tests < 1024) return fail(MJ_EINVAL, "a pass must hold at least 1024 pair tests");
+    ctx->pair_test_pass = tests;
+    return MJ_OK;
+}
+
 extern "C" mj_status mj_ctx_set_streaming(mj_ctx *ctx, int mode) {
     if (!ctx) return fail(MJ_EINVAL, "ctx is NULL");
     if (mode < 0 || mode > 2) return fail(MJ_EINVAL, "streaming mode must be 0, 1 or 2");
@@ -295,17 +302,51 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     }
     tm.mark();  // 2 sort
     GroupInfo g = find_groups(rb.key, R, ws, s, ctx->pinned);
-    if (g.tests > (uint64_t)0x7FFFFFFF)
-        throw Error(MJ_ECAPACITY, "record-pair tests exceed 2^31 (" + std::to_string(g.tests) + ")");
-    int64_t cap = (int64_t)g.tests;
-    uint64_t *cand = ws.get_n<uint64_t>(cap + 1);
-    int64_t c0 = emit_candidates(rb.val, R, g, d, cand, cap, ws, s, ctx->pinned, &ctx->kt);
-    ctx->last_c0 = c0;
+    uint64_t *uniq = nullptr;
+    int64_t C = 0;
+    const uint64_t pass_tests = (uint64_t)ctx->pair_test_pass;
+    if (g.tests <= pass_tests) {
+        int64_t cap = (int64_t)g.tests;
+        uint64_t *cand = ws.get_n<uint64_t>(cap + 1);
+        int64_t c0 = emit_candidates(rb.val, R, g, d, cand, cap, ws, s, ctx->pinned, &ctx->kt);
+        ctx->last_c0 = c0;
+        tm.mark();  // 3 group + filter
+        C = dedup_pairs(cand, c0, d.n, d.n, ws, s, ctx->pinned, &uniq);
+    } else {
+        // more record-pair tests than one pass holds (huge groups): emit and dedup them in
+        // passes, then dedup the union of the passes' distinct pairs
+        std::vector<std::pair<uint64_t *, int64_t>> parts;
+        int64_t total_u = 0;
+        uint64_t *cand = ws.get_n<uint64_t>(pass_tests + 1);
+        try {
+            for (uint64_t t0 = 0; t0 < g.tests; t0 += pass_tests) {
+                const uint64_t t1 = std::min(g.tests, t0 + pass_tests);
+                int64_t c0 = emit_candidates(rb.val, R, g, d, cand, (int64_t)pass_tests, ws, s,
+                                             ctx->pinned, &ctx->kt, t0, t1);
+                uint64_t *u = nullptr;
+                const int64_t nu = dedup_pairs(cand, c0, d.n, d.n, ws, s, ctx->pinned, &u);
+                parts.push_back({u, nu});
+                total_u += nu;
+            }
+            uint64_t *all = ws.get_n<uint64_t>(total_u + 1);
+            int64_t at = 0;
+            for (auto &pr : parts) {
+                if (pr.second)
+                    MJ_HIP(hipMemcpyAsync(all + at, pr.first, (size_t)pr.second * 8,
+                                          hipMemcpyDeviceToDevice, s));
+                at += pr.second;
+            }
+            ctx->last_c0 = total_u;
+            tm.mark();  // 3 group + filter
+            C = dedup_pairs(all, total_u, d.n, d.n, ws, s, ctx->pinned, &uniq);
+        } catch (...) {
+            for (auto &pr : parts) dev_free(pr.first);
+            throw;
+        }
+        for (auto &pr : parts) dev_free(pr.first);
+    }
     ctx->last_R = R;
     ctx->last_rcap = std::max<int64_t>(si.rec_bound * pp.reps, 2);
-    tm.mark();  // 3 group + filter
-    uint64_t *uniq = nullptr;
-    int64_t C = dedup_pairs(cand, c0, d.n, d.n, ws, s, ctx->pinned, &uniq);
     tm.mark();  // 4 dedup
     if (stats) {
         memset(stats, 0, sizeof(*stats));
@@ -393,8 +434,10 @@ static bool plan_streamed(mj_ctx *ctx, const mj_params *params, const DevStrings
     pl.scap = std::max<int64_t>(
         2, std::min<int64_t>(pl.rcap, (int64_t)(1.02 * h.rec_per_bound * (double)pl.rcap) + 4096));
     // candidates before the dedup: the last join's rate per record bound, with room
-    pl.ccap = (int64_t)std::min<double>(1.1 * h.cand_per_record * (double)pl.rcap + 65536.0,
-                                        (double)0x7FFFFFF0LL);
+    const double ccap = 1.1 * h.cand_per_record * (double)pl.rcap + 65536.0;
+    if (ccap > (double)std::min<int64_t>(ctx->pair_test_pass, 0x7FFFFFF0LL))
+        return false;  // candidates beyond one emission pass: stage by stage, in passes
+    pl.ccap = (int64_t)ccap;
     pl.emit = h.emit;
     return true;
 }
@@ -579,7 +622,8 @@ static mj_pairs *run_join_graph(mj_ctx *ctx, const mj_strings *strings, const mj
     SetupInfo si;
     (void)prepare_finish(d, ctx->pinned, &si);
     if (!gr.main || si.halo != gr.si.halo || si.rec_bound != gr.si.rec_bound ||
-        si.kmax != gr.si.kmax || d.total != gr.total) {
+        si.kmax != gr.si.kmax || d.total != gr.total || d.wide_count != gr.md.wide_count ||
+        d.wide_pos != gr.md.wide_pos) {
         if (gr.main) (void)hipGraphExecDestroy(gr.main);
         gr.main = nullptr;
         StreamedPlan pl;

@@ -59,6 +59,7 @@ struct mj_ctx {
     // latency first (server workers): the batched verifier takes its fixed small-call
     // configuration instead of timing the choices on a live call
     bool no_tuning = false;
+    int64_t pair_test_pass = (int64_t)1 << 28;  // record-pair tests per emission pass
     int streaming = 1;  // 0 stage by stage, 1 streamed, 2 streamed and captured (mj_ctx_set_streaming)
     StreamHints stream;
     JoinGraph graph;

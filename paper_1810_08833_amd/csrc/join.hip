@@ -218,17 +218,18 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
                                               const uint64_t *__restrict__ ts, int64_t G,
                                               uint64_t P, uint64_t *out, int64_t cap,
                                               unsigned long long *counter, int chunk,
-                                              const uint64_t *__restrict__ slot) {
+                                              const uint64_t *__restrict__ slot, uint64_t tb) {
     // group and test counts on the device (the streamed join): slot[1], slot[2]
     if (slot) {
         G = (int64_t)slot[1];
         P = G > 0 ? slot[2] : 0;
     }
+    // tests [tb, P): the whole range, or one pass of a join emitted in passes
     __shared__ EmitStage st;
     if (threadIdx.x == 0) st.n = 0;
     __syncthreads();
     const uint64_t nthreads = (uint64_t)gridDim.x * EMIT_BLOCK;
-    for (uint64_t t0 = ((uint64_t)blockIdx.x * EMIT_BLOCK + threadIdx.x) * chunk; ;
+    for (uint64_t t0 = tb + ((uint64_t)blockIdx.x * EMIT_BLOCK + threadIdx.x) * chunk; ;
          t0 += nthreads * chunk) {
         // block-uniform loop exit (the flush has barriers)
         if (t0 - (uint64_t)threadIdx.x * chunk >= P) break;
@@ -307,8 +308,11 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
 
 int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, const DevStrings &d,
                         uint64_t *out, int64_t cap, Workspace &ws, hipStream_t s,
-                        uint64_t *host_scratch, KTimer *kt) {
+                        uint64_t *host_scratch, KTimer *kt, uint64_t t_begin, uint64_t t_end) {
     if (g.groups == 0 || g.tests == 0) return 0;
+    if (t_end == 0 || t_end > g.tests) t_end = g.tests;
+    if (t_begin >= t_end) return 0;
+    const uint64_t tests = t_end - t_begin;  // this pass
     unsigned long long *counter = (unsigned long long *)ws.get_n<uint64_t>(2);
     fill_u64((uint64_t *)counter, 0, 1, s);
     // the (m, K) words of all records in one pass when the pair tests outnumber the
@@ -334,12 +338,12 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
     // a thread locates its first test by a binary search over the groups; with tests
     // enough for 2^20 threads it takes longer runs (up to 4 x EMIT_CHUNK) per search
     int chunk = EMIT_CHUNK;
-    while (chunk < 4 * EMIT_CHUNK && g.tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
-    uint64_t threads = (g.tests + chunk - 1) / chunk;
+    while (chunk < 4 * EMIT_CHUNK && tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
+    uint64_t threads = (tests + chunk - 1) / chunk;
     unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, 1u << 16);
     hipLaunchKernelGGL(lazy ? k_emit<true> : k_emit<false>, dim3(grid), dim3(EMIT_BLOCK), 0, s, val,
-                       meta, lk, d.len, d.kk, g.gstart, g.tstart, g.groups, g.tests, out, cap, counter,
-                       chunk, (const uint64_t *)nullptr);
+                       meta, lk, d.len, d.kk, g.gstart, g.tstart, g.groups, t_end, out, cap, counter,
+                       chunk, (const uint64_t *)nullptr, t_begin);
     MJ_LAUNCH_CHECK();
     if (kt) kt->end(th, s);
     uint64_t c = read_back<uint64_t>((const uint64_t *)counter, s, host_scratch);
@@ -431,7 +435,7 @@ void emit_candidates_streamed(const uint64_t *val, int64_t R_cap, const int64_t 
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(h.blocks, 1 << 16));
     hipLaunchKernelGGL(h.lazy ? k_emit<true> : k_emit<false>, dim3(grid), dim3(EMIT_BLOCK), 0, s,
                        val, meta, lk, d.len, d.kk, g.gstart, g.tstart, (int64_t)0, (uint64_t)0, out,
-                       cap, count, chunk, (const uint64_t *)g.slot);
+                       cap, count, chunk, (const uint64_t *)g.slot, (uint64_t)0);
     MJ_LAUNCH_CHECK();
     if (kt) kt->end(th, s);
 }

@@ -197,6 +197,11 @@ struct DevStrings {
     // device word set by the plane packing when a symbol code is >= sigma (nullptr: the
     // symbols were not checked)
     uint32_t *symbol_err = nullptr;
+    // strings whose radius exceeds the tile kernel's halo: their ids and radii (device),
+    // their number and their q-gram starts in all (host, from the set-up read-back)
+    int32_t *wide_ids = nullptr, *wide_r = nullptr;
+    int32_t wide_count = 0;
+    int64_t wide_pos = 0;
 };
 
 inline void check_total(const DevStrings &d) {
@@ -238,7 +243,7 @@ struct SetupInfo {
 };
 int32_t prepare_strings(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
                         uint64_t *host_scratch, SetupInfo *info = nullptr);  // returns the halo
-// The same in two halves: the launches and the copies to host_dst (pinned, 4 words), and,
+// The same in two halves: the launches and the copies to host_dst (pinned, 5 words), and,
 // once the stream has synchronised, the checks and results.
 void prepare_launch(DevStrings &d, const PartitionParams &p, Workspace &ws, hipStream_t s,
                     uint64_t *host_dst);
@@ -296,9 +301,11 @@ const uint32_t *dedup_pairs_streamed(uint64_t *pairs, int64_t cap, const unsigne
                                      int32_t n_first, int32_t n_second, Workspace &ws, hipStream_t s,
                                      uint64_t **result);
 // Emit candidate pair keys for all pair tests; returns count emitted (<= cap).
+// Tests [t_begin, t_end) only when t_end > 0 (a join emitted in passes).
 int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, const DevStrings &d,
                         uint64_t *out, int64_t cap, Workspace &ws, hipStream_t s,
-                        uint64_t *host_scratch, KTimer *kt = nullptr);
+                        uint64_t *host_scratch, KTimer *kt = nullptr, uint64_t t_begin = 0,
+                        uint64_t t_end = 0);
 // Sorted unique copy of pairs (first << 32 | second, first < n_first, second <
 // n_second) in *result (owned allocation); sorts `pairs` in place; returns the count.
 int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t n_first, int32_t n_second, Workspace &ws,

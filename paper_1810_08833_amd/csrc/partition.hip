@@ -32,10 +32,15 @@ __device__ __forceinline__ int32_t owner_of(const int64_t *off, int32_t n, int64
 // m_i, K_i, and r_i = max(1, floor((m - q + 1 - T) / (2T + 2))) with T from the rule of
 // Remark 1 (Alg. 2 defines r).  The halo needed by the anchor kernel is the largest r
 // of a string that has interior positions.
+constexpr int32_t WIDE_R = 1920, WIDE_SENTINEL = 0x3FFFFFFF;
+// Radii above WIDE_R take the wide path (a tile region holds at most 1,920 positions of
+// halo on each side): such a string's radius in rr is WIDE_SENTINEL, which gives it no
+// interior position in the tile kernel, and it is listed in wide_ids with its radius.
 __global__ void k_prepare(const int64_t *off, int32_t n, int q, int64_t kuni, const int32_t *kps,
                           int t_div, int t_fixed, int32_t *len, int32_t *kk, int32_t *rr,
                           uint32_t *halo, uint32_t *err, unsigned long long *rec_bound,
-                          uint32_t *kmax) {
+                          uint32_t *kmax, int32_t *wide_ids, int32_t *wide_r, uint32_t *wide_count,
+                          unsigned long long *wide_pos) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t hr = 0;  // this string's contribution to the halo
     // and to the bound on the partitions of one repetition: interior anchors are strict
@@ -55,10 +60,21 @@ __global__ void k_prepare(const int64_t *off, int32_t n, int q, int64_t kuni, co
         int64_t r = num <= 0 ? 1 : num / (2 * T + 2);
         if (r < 1) r = 1;
         int64_t npos = m - q + 1;
-        if (npos - 1 - r >= r) hr = (uint32_t)std::min<int64_t>(r, 0x7FFFFFFFLL);
+        bool wide = false;
+        if (npos - 1 - r >= r) {  // the string has interior positions
+            if (r > WIDE_R) {
+                wide = true;
+                const uint32_t w = atomicAdd(wide_count, 1u);
+                wide_ids[w] = i;
+                wide_r[w] = (int32_t)r;
+                atomicAdd(wide_pos, (unsigned long long)npos);
+            } else {
+                hr = (uint32_t)r;
+            }
+        }
         len[i] = (int32_t)m;
         kk[i] = (int32_t)(K < 0 ? 0 : K);
-        rr[i] = (int32_t)std::min<int64_t>(r, 0x7FFFFFFFLL);
+        rr[i] = wide ? WIDE_SENTINEL : (int32_t)std::min<int64_t>(r, 0x7FFFFFFFLL);
         if (m > 0) bnd = npos <= 0 ? 1ull : (unsigned long long)(npos / (r + 1) + 2);
         km = (uint32_t)(K < 0 ? 0 : K);
     }
@@ -83,27 +99,34 @@ void prepare_launch(DevStrings &d, const PartitionParams &p, Workspace &ws, hipS
     d.len = ws.get_n<int32_t>(n + 1);
     d.kk = ws.get_n<int32_t>(n + 1);
     d.rr = ws.get_n<int32_t>(n + 1);
-    // [0] halo, [1] error bits, [2..3] partition bound (u64), [4] largest K
+    d.wide_ids = ws.get_n<int32_t>(n + 1);
+    d.wide_r = ws.get_n<int32_t>(n + 1);
+    // [0] halo, [1] error bits, [2..3] partition bound (u64), [4] largest K, [5] wide
+    // strings, [6..7] their q-gram starts (u64)
     uint32_t *flags = ws.get_n<uint32_t>(8);
-    fill_u32(flags, 0, 6, s);
+    fill_u32(flags, 0, 8, s);
     if (n > 0) {
         hipLaunchKernelGGL(k_prepare, dim3((n + 255) / 256), dim3(256), 0, s, d.offsets, n, p.q,
                            p.k, p.k_per_string, p.t_div, p.t_fixed, d.len, d.kk, d.rr, flags,
-                           flags + 1, reinterpret_cast<unsigned long long *>(flags + 2), flags + 4);
+                           flags + 1, reinterpret_cast<unsigned long long *>(flags + 2), flags + 4,
+                           d.wide_ids, d.wide_r, flags + 5,
+                           reinterpret_cast<unsigned long long *>(flags + 6));
         MJ_LAUNCH_CHECK();
     }
-    MJ_HIP(hipMemcpyAsync(host_dst, flags, 24, hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipMemcpyAsync(host_dst, flags, 32, hipMemcpyDeviceToHost, s));
     if (d.total < 0)  // offsets[n] read back with the flags
-        MJ_HIP(hipMemcpyAsync(host_dst + 3, d.offsets + n, 8, hipMemcpyDeviceToHost, s));
+        MJ_HIP(hipMemcpyAsync(host_dst + 4, d.offsets + n, 8, hipMemcpyDeviceToHost, s));
 }
 
 int32_t prepare_finish(DevStrings &d, const uint64_t *host_src, SetupInfo *info) {
-    uint32_t hv[6];
-    memcpy(hv, host_src, 24);
+    uint32_t hv[8];
+    memcpy(hv, host_src, 32);
     if (d.total < 0) {
-        d.total = (int64_t)host_src[3];
+        d.total = (int64_t)host_src[4];
         check_total(d);
     }
+    d.wide_count = (int32_t)hv[5];
+    d.wide_pos = (int64_t)(((uint64_t)hv[7] << 32) | hv[6]);
     if (hv[1] & 1u) throw Error(MJ_EINVAL, "offsets must be non-decreasing with lengths < 2^31");
     if (hv[1] & 2u) throw Error(MJ_EINVAL, "K must be >= 0");
     if (info) {
@@ -531,13 +554,14 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             const int32_t i0 = (int32_t)(g0 - sb0);
             const int32_t npos = (int32_t)(se0 - sb0) - q + 1;
             const int32_t r = td.r[t];
-            // interior i in [r, npos-1-r]  <=>  (unsigned)(i - r) < ibound
-            const uint32_t ibound = (uint32_t)max(npos - 2 * r, 0);
+            // interior i in [r, npos-1-r]  <=>  (unsigned)(i - r) < ibound; none for a
+            // string on the wide path
+            const uint32_t ibound = r >= WIDE_SENTINEL ? 0u : (uint32_t)max(npos - 2 * r, 0);
             // string t + 1 (fast2): its first run index jb, positions, radius
             const int jb = TWO ? (int)min<int64_t>(se0 - g0, RUN) : RUN;
             const int32_t npos1 = TWO ? (int32_t)(se1 - se0) - q + 1 : 0;
             const int32_t r1 = (TWO && t + 1 < ns) ? td.r[t + 1] : r;
-            const uint32_t ibound1 = (uint32_t)max(npos1 - 2 * r1, 0);
+            const uint32_t ibound1 = r1 >= WIDE_SENTINEL ? 0u : (uint32_t)max(npos1 - 2 * r1, 0);
             V hv[RUN];
             uint16_t inf[RUN];
 #pragma unroll
@@ -653,7 +677,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                     } else {
                         have_end = -1;
                     }
-                    const bool interior = (i >= r) && (i <= npos - 1 - r);
+                    const bool interior = r < WIDE_SENTINEL && (i >= r) && (i <= npos - 1 - r);
                     info = (uint16_t)((interior ? r : 0) | (i < npos ? 0x4000 : 0));
                     if (i == 0) flag_start(idx);
                     if (interior && idx >= H && idx < H + TP) {
@@ -822,6 +846,125 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         for (int d = 32; d >= 1; d >>= 1) mine += (uint32_t)__shfl_xor((int)mine, d, 64);
         if (tid == 0) tile_count[blockIdx.x] = mine;
     }
+}
+
+// ---------------------------------------------------------------- wide radii
+// Strings whose radius exceeds what a tile region's halo holds.  Their hashes go to global
+// memory; so do prefix and suffix minima within blocks of r positions.  Each side of an
+// interior position's window, [p - r, p - 1] and [p + 1, p + r], is r positions long, so it
+// meets at most two blocks and its minimum is one block suffix minimum and one block prefix
+// minimum.  Anchors are ORed into the tile kernel's bitmap and counted into its tile counts
+// (the tile kernel sets no bit of these strings but their starts, which are not interior).
+__device__ __forceinline__ uint32_t symbol_at(const uint8_t *chars, int packed, int64_t g) {
+    return packed ? (uint32_t)(chars[g >> 2] >> (2 * (g & 3))) & 3u : (uint32_t)chars[g];
+}
+
+__global__ void k_wide_npos(const int64_t *__restrict__ off, const int32_t *__restrict__ ids,
+                            int32_t nw, int q, uint64_t *__restrict__ npos) {
+    const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < nw) npos[w] = (uint64_t)(off[ids[w] + 1] - off[ids[w]] - q + 1);
+}
+
+__global__ void k_wide_hashes(const uint8_t *__restrict__ chars, int packed,
+                              const int64_t *__restrict__ off, const int32_t *__restrict__ ids,
+                              int32_t nw, const uint64_t *__restrict__ hoff, int q, int bits,
+                              uint64_t salt, const uint64_t *__restrict__ table,
+                              uint64_t *__restrict__ h) {
+    const uint64_t gmask = (q * bits >= 64) ? ~0ull : ((1ull << (q * bits)) - 1);
+    for (int32_t w = blockIdx.x; w < nw; w += gridDim.x) {
+        const int64_t s0 = off[ids[w]];
+        const int64_t npos = (int64_t)(hoff[w + 1] - hoff[w]);
+        uint64_t *hw = h + hoff[w];
+        for (int64_t p = threadIdx.x; p < npos; p += blockDim.x) {
+            uint64_t G = 0;
+            for (int k = 0; k < q; k++) G = (G << bits) | symbol_at(chars, packed, s0 + p + k);
+            G &= gmask;
+            hw[p] = table ? table[G] : mix64(G ^ salt);
+        }
+    }
+}
+
+__global__ void k_wide_blockmin(const int32_t *__restrict__ wr, int32_t nw,
+                                const uint64_t *__restrict__ hoff, const uint64_t *__restrict__ h,
+                                uint64_t *__restrict__ P, uint64_t *__restrict__ S) {
+    for (int32_t w = blockIdx.x; w < nw; w += gridDim.x) {
+        const int64_t o = (int64_t)hoff[w], npos = (int64_t)(hoff[w + 1] - hoff[w]), r = wr[w];
+        const int64_t nb = (npos + r - 1) / r;
+        for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+            const int64_t lo = o + b * r, hi = o + min(npos, (b + 1) * r);
+            uint64_t m = ~0ull;
+            for (int64_t p = lo; p < hi; p++) {
+                m = min(m, h[p]);
+                P[p] = m;
+            }
+            m = ~0ull;
+            for (int64_t p = hi - 1; p >= lo; p--) {
+                m = min(m, h[p]);
+                S[p] = m;
+            }
+        }
+    }
+}
+
+__global__ void k_wide_anchors(const int64_t *__restrict__ off, const int32_t *__restrict__ ids,
+                               const int32_t *__restrict__ wr, int32_t nw,
+                               const uint64_t *__restrict__ hoff, const uint64_t *__restrict__ h,
+                               const uint64_t *__restrict__ P, const uint64_t *__restrict__ S,
+                               int TP, unsigned long long *bitmap, uint32_t *tcount) {
+    for (int32_t w = blockIdx.x; w < nw; w += gridDim.x) {
+        const int64_t s0 = off[ids[w]], o = (int64_t)hoff[w];
+        const int64_t npos = (int64_t)(hoff[w + 1] - hoff[w]), r = wr[w];
+        for (int64_t p = r + threadIdx.x; p <= npos - 1 - r; p += blockDim.x) {
+            const uint64_t x = h[o + p];
+            const uint64_t left = min(S[o + p - r], P[o + p - 1]);
+            const uint64_t right = min(S[o + p + 1], P[o + p + r]);
+            if (x < left && x < right) {
+                const int64_t g = s0 + p;
+                atomicOr(bitmap + (g >> 6), 1ull << (g & 63));
+                atomicAdd(tcount + g / TP, 1u);
+            }
+        }
+    }
+}
+
+// Buffers of the wide path: each wide string's first slot (hoff, nw + 1 entries), and the
+// hashes and block minima of all their q-gram starts.
+struct WideBufs {
+    uint64_t *hoff = nullptr, *h = nullptr, *P = nullptr, *S = nullptr;
+};
+
+static WideBufs wide_setup(const DevStrings &d, int q, Workspace &ws, hipStream_t s) {
+    WideBufs wb;
+    if (d.wide_count <= 0) return wb;
+    const int32_t nw = d.wide_count;
+    uint64_t *np = ws.get_n<uint64_t>((size_t)nw + 1);
+    wb.hoff = ws.get_n<uint64_t>((size_t)nw + 1);
+    hipLaunchKernelGGL(k_wide_npos, dim3((nw + 255) / 256), dim3(256), 0, s, d.offsets, d.wide_ids,
+                       nw, q, np);
+    MJ_LAUNCH_CHECK();
+    exclusive_scan_u64(np, wb.hoff, nw, ws, s);
+    wb.h = ws.get_n<uint64_t>((size_t)d.wide_pos + 1);
+    wb.P = ws.get_n<uint64_t>((size_t)d.wide_pos + 1);
+    wb.S = ws.get_n<uint64_t>((size_t)d.wide_pos + 1);
+    return wb;
+}
+
+static void wide_anchors(const DevStrings &d, const WideBufs &wb, const PartitionParams &p,
+                         uint64_t salt, int TP, uint64_t *bitmap, uint32_t *tcount, hipStream_t s) {
+    if (d.wide_count <= 0) return;
+    const int32_t nw = d.wide_count;
+    const dim3 grid((unsigned)std::min<int32_t>(nw, 65535));
+    const int packed = d.packing == MJ_PACK_2BIT ? 1 : 0;
+    hipLaunchKernelGGL(k_wide_hashes, grid, dim3(256), 0, s, d.chars, packed, d.offsets,
+                       d.wide_ids, nw, wb.hoff, p.q, d.bits, salt, p.pi_table, wb.h);
+    MJ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_wide_blockmin, grid, dim3(256), 0, s, d.wide_r, nw, wb.hoff, wb.h, wb.P,
+                       wb.S);
+    MJ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_wide_anchors, grid, dim3(256), 0, s, d.offsets, d.wide_ids, d.wide_r, nw,
+                       wb.hoff, wb.h, wb.P, wb.S, TP,
+                       reinterpret_cast<unsigned long long *>(bitmap), tcount);
+    MJ_LAUNCH_CHECK();
 }
 
 // Positions of the flagged bits, in order: one wave per anchor tile (its TP / 64 <= 64
@@ -1109,9 +1252,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
                           Workspace &ws, hipStream_t s, uint64_t *host_scratch, KTimer *kt) {
     if (d.total == 0) return 0;
     const int reps = std::max(1, p.reps);
-    int H = std::max<int32_t>(halo, 1);
-    if (H > 1920)
-        throw Error(MJ_ECAPACITY, "radius " + std::to_string(H) + " exceeds the supported 1920");
+    int H = std::max<int32_t>(halo, 1);  // radii above WIDE_R take the wide path
     // the smaller region (more workgroups per CU) when the halo leaves room for 1024+ positions
     const int region = (2048 - 2 * H >= 1024) ? 2048 : 4096;
     int TP = ((region - 2 * H) / 64) * 64;  // whole bitmap words per tile
@@ -1136,6 +1277,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     std::vector<uint64_t *> bitmap(reps);
     std::vector<uint32_t *> tcount(reps), pre(reps);  // per tile: flagged positions, their scan
     uint16_t *rank = code_bits <= RANK_MAX_BITS ? ws.get_n<uint16_t>((size_t)1 << code_bits) : nullptr;
+    const WideBufs wb = wide_setup(d, p.q, ws, s);
     for (int rho = 0; rho < reps; rho++) {
         const uint64_t salt = mix64(p.seed + (uint64_t)rho + GAMMA);
         bitmap[rho] = ws.get_n<uint64_t>(nw + 1);
@@ -1158,6 +1300,7 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
         }
 #undef MJ_ANCHORS
         MJ_LAUNCH_CHECK();
+        wide_anchors(d, wb, p, salt, TP, bitmap[rho], tcount[rho], s);
     }
     if (kt) kt->end(th, s, reps);
     for (int rho = 0; rho < reps; rho++) {
@@ -1253,9 +1396,7 @@ int64_t partition_records_streamed(const DevStrings &d, const PartitionParams &p
         fill_u64(reinterpret_cast<uint64_t *>(R_dev), 0, 1, s);
         return 0;
     }
-    int H = std::max<int32_t>(si.halo, 1);
-    if (H > 1920)
-        throw Error(MJ_ECAPACITY, "radius " + std::to_string(H) + " exceeds the supported 1920");
+    int H = std::max<int32_t>(si.halo, 1);  // radii above WIDE_R take the wide path
     const int region = (2048 - 2 * H >= 1024) ? 2048 : 4096;
     int TP = ((region - 2 * H) / 64) * 64;
     int64_t ntiles = (d.total + TP - 1) / TP;
@@ -1276,6 +1417,7 @@ int64_t partition_records_streamed(const DevStrings &d, const PartitionParams &p
     std::vector<uint32_t *> tcount(reps);
     uint32_t *pre_all = ws.get_n<uint32_t>((size_t)reps * (ntiles + 1));
     uint16_t *rank = code_bits <= RANK_MAX_BITS ? ws.get_n<uint16_t>((size_t)1 << code_bits) : nullptr;
+    const WideBufs wb = wide_setup(d, p.q, ws, s);
     for (int rho = 0; rho < reps; rho++) {
         const uint64_t salt = mix64(p.seed + (uint64_t)rho + GAMMA);
         bitmap[rho] = ws.get_n<uint64_t>(nw + 1);
@@ -1298,6 +1440,7 @@ int64_t partition_records_streamed(const DevStrings &d, const PartitionParams &p
         }
 #undef MJ_ANCHORS
         MJ_LAUNCH_CHECK();
+        wide_anchors(d, wb, p, salt, TP, bitmap[rho], tcount[rho], s);
     }
     if (kt) kt->end(th, s, reps);
     for (int rho = 0; rho < reps; rho++)

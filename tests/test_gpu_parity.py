@@ -79,6 +79,24 @@ def wide_radius_collection(seed, sigma, n=60):
     return dg.from_list(strs, sigma)
 
 
+def long_T1_collection(seed, sigma, n_bases=6, copies=3):
+    """Strings of 8,000-11,000 symbols at T = 1: radii of 2,000-2,750, past what a tile
+    region's halo holds (the wide anchor path), in clusters of near-copies (0.02% edits:
+    with about three partitions per string, a candidate needs an unedited one), a
+    homopolymer of 9,000 (no strict minimum anywhere) and shorter strings whose radii the
+    tile kernel takes, in the same collection."""
+    rng = np.random.default_rng(seed)
+    strs = []
+    for c in range(n_bases):
+        base = rng.integers(0, sigma, int(rng.integers(8000, 11000))).astype(np.uint8)
+        strs += [base] + [dg.mutate(np.random.default_rng(seed * 100 + 10 * c + i), base, 0.0002,
+                                    sigma) for i in range(copies - 1)]
+    strs.append(np.full(9000, 2, np.uint8))
+    strs += [rng.integers(0, sigma, L).astype(np.uint8) for L in (0, 3, 40, 500, 3000, 7700)]
+    order = rng.permutation(len(strs))
+    return dg.from_list([strs[i] for i in order], sigma)
+
+
 # ---------------------------------------------------------------- worked example
 def test_worked_example_end_to_end(mj):
     import torch
@@ -113,6 +131,9 @@ CASES = {
     "dna_wide_radius": dict(make=lambda: wide_radius_collection(31, 4), q=4, k=60, t_fixed=2),
     "text_wide_radius_hashed": dict(make=lambda: wide_radius_collection(32, 37), q=6, k=60,
                                     t_fixed=2),
+    "dna_T1_long_reps2": dict(make=lambda: long_T1_collection(41, 4), q=6, k=60, t_fixed=1,
+                              reps=2),
+    "text_T1_long_hashed": dict(make=lambda: long_T1_collection(42, 37), q=6, k=40, t_div=40),
     "alphabet12_q4": dict(make=lambda: dg.from_list(
         [dg.mutate(np.random.default_rng(900 + i), base, 0.02, 12)
          for base in [np.random.default_rng(80 + c).integers(0, 12, 600 + 37 * c).astype(np.uint8)
@@ -324,6 +345,25 @@ def test_search_matches_oracle(mj):
     index.close()
 
 
+def test_search_with_wide_radii(mj):
+    """An index and queries of 8,000-11,000 symbols at T = 1 (radii above the tile halo, on
+    both sides of the search) against the oracle, with both verifiers."""
+    import torch
+    say("search, wide radii")
+    S = long_T1_collection(43, 4, n_bases=5, copies=3)
+    ids = np.arange(S.n)
+    I, Q = S.subset(ids[ids % 3 != 0]), S.subset(ids[ids % 3 == 0])
+    op = oracle.make_params(6, 4, k=60, t_fixed=1)
+    _, want = oracle.search(I.chars, I.offsets, op, Q.chars, Q.offsets, op)
+    assert len(want) > 0
+    index = mj.Index(dev(mj, I), mj.Params(q=6, k=60, t_fixed=1))
+    kq = torch.full((Q.n,), 60, dtype=torch.int32).cuda()
+    for verifier in (mj.VERIFY_BATCHED, mj.VERIFY_PLAIN):
+        got, _ = index.search(dev(mj, Q), k_per_query=kq, verifier=verifier)
+        assert np.array_equal(got, want)
+    index.close()
+
+
 def test_search_few_queries_large_index(mj):
     """Query ids span far fewer bits than index ids (3 queries, 6,000 index strings):
     the candidate pairs must still be deduplicated over the full index id range."""
@@ -477,7 +517,8 @@ def test_streamed_join_falls_back_when_candidates_outgrow_the_room(mj):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["dna_mixed_T_from_K", "protein_per_string_K", "text_q6", "dna_reps3"])
+@pytest.mark.parametrize("name", ["dna_mixed_T_from_K", "protein_per_string_K", "text_q6", "dna_reps3",
+                                  "dna_T1_long_reps2"])
 def test_captured_join_identical(mj, name):
     """Streamed joins captured into HIP graphs (mj_ctx_set_streaming 2) and replayed: each
     replay equals the oracle, also after the strings' content changes in place (same
@@ -507,4 +548,24 @@ def test_captured_join_identical(mj, name):
     ctx.set_streaming(1)
     out, st = mj.join(ds, gp, ctx=ctx)
     assert np.array_equal(out, out_t) and st["streamed"] == 1
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["dna_heavy_clusters", "protein_per_string_K"])
+def test_join_in_emission_passes(mj, name):
+    """A join whose record-pair tests exceed one emission pass (here forced down to 1,024
+    tests per pass) emits and deduplicates them in passes: candidates and output equal the
+    oracle's, for the stage-by-stage and the streamed path."""
+    say("emission passes", name)
+    S, op, gp = run_case(mj, name)
+    cand_w, out_w, st_w = oracle.join(S.chars, S.offsets, op)
+    assert st_w["pair_tests"] > 8 * 1024
+    ctx = mj.Context()
+    ctx.set_pair_test_pass(1024)
+    ds = dev(mj, S)
+    cand, st = mj.candidates(ds, gp, ctx=ctx)
+    assert np.array_equal(cand, cand_w) and st["pair_tests"] > 8 * 1024
+    for _ in range(2):
+        out, st = mj.join(ds, gp, ctx=ctx)
+        assert np.array_equal(out, out_w)
     ctx.close()
