@@ -515,6 +515,8 @@ def measure_join(workload, args, steps, warmup):
         "recall": recall,
         "true_pairs": int(len(truth)),
         "records": last["records"],
+        "members": last["members"],
+        "member_filter": last["member_filter"],
         "pair_tests": last["pair_tests"],
         "stage_ms": {k: float(np.mean([s["stage_ms"][k] for s in stats])) for k in mj.STAGES[:7]},
         "stage_hbm": stage_hbm(workload, stats, cfg["reps"], 0.25 if cfg.get("packed") else 1.0),

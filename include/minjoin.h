@@ -133,6 +133,9 @@ typedef struct {
                               2: the same, replayed from captured graphs */
     int32_t host_reads;    /* reads of device values the host waited for: 2 when
                               streamed, 0 (not counted) stage by stage */
+    int32_t member_filter; /* 1: only the records that may share their key went through
+                              the record sort (see mj_ctx_set_member_filter) */
+    int64_t members;       /* records sorted and grouped (records when member_filter is 0) */
 } mj_stats;
 
 /* ---- context ---------------------------------------------------------------- */
@@ -162,6 +165,15 @@ void mj_ctx_destroy(mj_ctx *ctx);
  * deduplicates the union, which bounds the candidate buffer (8 bytes per test of a pass)
  * however skewed the groups are.  EINVAL for a NULL context or a smaller value. */
 mj_status mj_ctx_set_pair_test_pass(mj_ctx *ctx, int64_t tests);
+/* Joins with at least min_records records (default 2^23; 0: every join; -1: none) first
+ * keep only the records that may share their key with another one -- those whose key's top
+ * 32 bits occur twice, found with two radix passes over 8-byte elements (ordering them by
+ * the key's top 16 bits into buckets) and a per-bucket LDS bitmap -- and sort and group
+ * those alone.  A bucket of more than bucket_limit records (0: the default, 65,536) is
+ * kept whole.  Results are the same either way (a record whose key occurs once forms no
+ * group); the filter saves time when most records are unique.  EINVAL for a NULL context,
+ * min_records < -1 or bucket_limit < 0. */
+mj_status mj_ctx_set_member_filter(mj_ctx *ctx, int64_t min_records, int32_t bucket_limit);
 
 /* How joins after the first (see mj_join) run: 0 stage by stage, each stage sized exactly
  * from a read-back (the least memory); 1 streamed (the default: stages sized on the device
@@ -305,6 +317,10 @@ int64_t mj_pairs_count(const mj_pairs *p);
 const uint64_t *mj_pairs_device(const mj_pairs *p);     /* count entries, sorted */
 /* Copies count packed pairs to host memory; EINVAL if cap < count. */
 mj_status mj_pairs_copy_to_host(const mj_pairs *p, uint64_t *dst, int64_t cap);
+/* Returns the pairs' device memory: to the context's allocator when it has one, else to a
+ * per-device stream-ordered pool (hipFreeAsync on the stream the pairs were made on, which
+ * must still exist; work on other streams that reads the pairs must be complete).  Neither
+ * the join's allocation of the result nor this free waits for the device. */
 void mj_pairs_free(mj_pairs *p);
 
 int64_t mj_records_count(const mj_records *r);

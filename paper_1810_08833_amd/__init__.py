@@ -58,13 +58,14 @@ class MjStats(ctypes.Structure):
                 ("kernel_launches", ctypes.c_int32 * 4), ("positions", ctypes.c_int64),
                 ("verify_group", ctypes.c_int32), ("verify_words", ctypes.c_int32),
                 ("verify_blocks", ctypes.c_int32), ("streamed", ctypes.c_int32),
-                ("host_reads", ctypes.c_int32)]
+                ("host_reads", ctypes.c_int32), ("member_filter", ctypes.c_int32),
+                ("members", ctypes.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k in ("records", "groups", "pair_tests", "candidates",
                                            "output", "band_cells", "positions", "verify_group",
                                            "verify_words", "verify_blocks", "streamed",
-                                           "host_reads")}
+                                           "host_reads", "member_filter", "members")}
         d["stage_ms"] = {STAGES[i]: float(self.stage_ms[i]) for i in range(7)}
         d["kernel_ms"] = {KERNELS[i]: float(self.kernel_ms[i]) for i in range(4)}
         d["kernel_launches"] = {KERNELS[i]: int(self.kernel_launches[i]) for i in range(4)}
@@ -84,6 +85,7 @@ class MjReply(ctypes.Structure):
 
 
 EXPORTS = ["mj_ctx_create", "mj_ctx_destroy", "mj_ctx_set_streaming", "mj_ctx_set_pair_test_pass",
+           "mj_ctx_set_member_filter",
            "mj_last_error", "mj_version", "mj_join",
            "mj_partition", "mj_candidates", "mj_verify", "mj_index_build", "mj_index_free",
            "mj_index_records", "mj_index_bytes", "mj_search", "mj_pairs_count", "mj_pairs_device",
@@ -117,6 +119,8 @@ def load_library(path: str = LIB_PATH):
     L.mj_ctx_set_streaming.restype = ctypes.c_int
     L.mj_ctx_set_pair_test_pass.argtypes = [VP, ctypes.c_int64]
     L.mj_ctx_set_pair_test_pass.restype = ctypes.c_int
+    L.mj_ctx_set_member_filter.argtypes = [VP, ctypes.c_int64, ctypes.c_int32]
+    L.mj_ctx_set_member_filter.restype = ctypes.c_int
     L.mj_last_error.restype = ctypes.c_char_p
     L.mj_version.restype = ctypes.c_char_p
     L.mj_join.argtypes = [VP, P(MjStrings), P(MjParams), VP, P(VP), P(MjStats)]
@@ -232,6 +236,13 @@ class Context:
     def set_pair_test_pass(self, tests: int):
         """Record-pair tests per emission pass (joins with more run in passes)."""
         _check(load_library().mj_ctx_set_pair_test_pass(self.handle, int(tests)))
+
+    def set_member_filter(self, min_records: int, bucket_limit: int = 0):
+        """Joins with at least min_records records sort only the records that may share
+        their key (0: every join, -1: none); buckets above bucket_limit records (0: the
+        default) are kept whole."""
+        _check(load_library().mj_ctx_set_member_filter(self.handle, int(min_records),
+                                                       int(bucket_limit)))
 
     def close(self):
         if self.handle:

@@ -80,6 +80,20 @@ extern "C" mj_status mj_ctx_set_pair_test_pass(mj_ctx *ctx, int64_t tests) {
     return MJ_OK;
 }
 
+extern "C" mj_status mj_ctx_set_member_filter(mj_ctx *ctx, int64_t min_records,
+                                              int32_t bucket_limit) {
+    if (!ctx) return fail(MJ_EINVAL, "ctx is NULL");
+    if (min_records < -1) return fail(MJ_EINVAL, "min_records must be >= -1");
+    if (bucket_limit < 0) return fail(MJ_EINVAL, "bucket_limit must be >= 0");
+    ctx->member_min = min_records;
+    ctx->member_big = bucket_limit ? (uint32_t)bucket_limit : 1u << 16;
+    return MJ_OK;
+}
+
+static bool use_members(const mj_ctx *ctx, int64_t records) {
+    return ctx->member_min >= 0 && records >= std::max<int64_t>(ctx->member_min, 2);
+}
+
 extern "C" mj_status mj_ctx_set_streaming(mj_ctx *ctx, int mode) {
     if (!ctx) return fail(MJ_EINVAL, "ctx is NULL");
     if (mode < 0 || mode > 2) return fail(MJ_EINVAL, "streaming mode must be 0, 1 or 2");
@@ -183,14 +197,14 @@ static mj_pairs *compact_pairs(const uint64_t *pairs, const uint8_t *flags, int6
     out->alloc = t_dev_alloc;
     out->stream = s;
     if (n == 0) {
-        out->d = (uint64_t *)dev_alloc(16);
+        out->d = (uint64_t *)result_alloc(16, out->alloc, s);
         out->n = 0;
         return out;
     }
     // flags are 0/1 here (2 would mean an unhandled band, rejected earlier)
     int64_t *idx = ws.get_n<int64_t>(n + 1);
     int64_t c = compact_flags(flags, n, idx, ws, s, pinned);
-    out->d = (uint64_t *)dev_alloc((size_t)(c + 1) * 8);
+    out->d = (uint64_t *)result_alloc((size_t)(c + 1) * 8, out->alloc, s);
     gather_u64(pairs, idx, out->d, c, s);
     out->n = c;
     return out;
@@ -297,55 +311,61 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     partition_records(d, pp, halo, rb, ws, s, ctx->pinned, &ctx->kt);
     tm.mark();  // 1 partition: anchors and records
     int64_t R = rb.count;
-    if (R > 1) {
-        sort_records(rb.key, rb.val, R, ws, s, ctx->pinned);
+    // the records that are sorted and grouped: all of them, or those the member filter keeps
+    uint64_t *gkey = rb.key, *gval = rb.val;
+    int64_t M = R;
+    const bool members = use_members(ctx, R);
+    if (members) {
+        gkey = ws.get_n<uint64_t>(R + 1);
+        gval = ws.get_n<uint64_t>(R + 1);
+        int64_t *m_dev = ws.get_n<int64_t>(2);
+        group_members(rb.key, rb.val, R, nullptr, gkey, gval, R, m_dev, ctx->member_big, ws, s);
+        M = read_back<int64_t>(m_dev, s, ctx->pinned);
+    }
+    if (M > 1) {
+        sort_records(gkey, gval, M, ws, s, ctx->pinned);
     }
     tm.mark();  // 2 sort
-    GroupInfo g = find_groups(rb.key, R, ws, s, ctx->pinned);
+    GroupInfo g = find_groups(gkey, M, ws, s, ctx->pinned);
     uint64_t *uniq = nullptr;
     int64_t C = 0;
     const uint64_t pass_tests = (uint64_t)ctx->pair_test_pass;
     if (g.tests <= pass_tests) {
         int64_t cap = (int64_t)g.tests;
         uint64_t *cand = ws.get_n<uint64_t>(cap + 1);
-        int64_t c0 = emit_candidates(rb.val, R, g, d, cand, cap, ws, s, ctx->pinned, &ctx->kt);
+        int64_t c0 = emit_candidates(gval, M, g, d, cand, cap, ws, s, ctx->pinned, &ctx->kt);
         ctx->last_c0 = c0;
         tm.mark();  // 3 group + filter
-        C = dedup_pairs(cand, c0, d.n, d.n, ws, s, ctx->pinned, &uniq);
+        C = dedup_pairs(cand, c0, d.n, d.n, ws, s, ctx->pinned, &uniq, upto != 1);
     } else {
         // more record-pair tests than one pass holds (huge groups): emit and dedup them in
         // passes, then dedup the union of the passes' distinct pairs
-        std::vector<std::pair<uint64_t *, int64_t>> parts;
+        std::vector<std::pair<uint64_t *, int64_t>> parts;  // workspace blocks
         int64_t total_u = 0;
         uint64_t *cand = ws.get_n<uint64_t>(pass_tests + 1);
-        try {
-            for (uint64_t t0 = 0; t0 < g.tests; t0 += pass_tests) {
-                const uint64_t t1 = std::min(g.tests, t0 + pass_tests);
-                int64_t c0 = emit_candidates(rb.val, R, g, d, cand, (int64_t)pass_tests, ws, s,
-                                             ctx->pinned, &ctx->kt, t0, t1);
-                uint64_t *u = nullptr;
-                const int64_t nu = dedup_pairs(cand, c0, d.n, d.n, ws, s, ctx->pinned, &u);
-                parts.push_back({u, nu});
-                total_u += nu;
-            }
-            uint64_t *all = ws.get_n<uint64_t>(total_u + 1);
-            int64_t at = 0;
-            for (auto &pr : parts) {
-                if (pr.second)
-                    MJ_HIP(hipMemcpyAsync(all + at, pr.first, (size_t)pr.second * 8,
-                                          hipMemcpyDeviceToDevice, s));
-                at += pr.second;
-            }
-            ctx->last_c0 = total_u;
-            tm.mark();  // 3 group + filter
-            C = dedup_pairs(all, total_u, d.n, d.n, ws, s, ctx->pinned, &uniq);
-        } catch (...) {
-            for (auto &pr : parts) dev_free(pr.first);
-            throw;
+        for (uint64_t t0 = 0; t0 < g.tests; t0 += pass_tests) {
+            const uint64_t t1 = std::min(g.tests, t0 + pass_tests);
+            int64_t c0 = emit_candidates(gval, M, g, d, cand, (int64_t)pass_tests, ws, s,
+                                         ctx->pinned, &ctx->kt, t0, t1);
+            uint64_t *u = nullptr;
+            const int64_t nu = dedup_pairs(cand, c0, d.n, d.n, ws, s, ctx->pinned, &u, true);
+            parts.push_back({u, nu});
+            total_u += nu;
         }
-        for (auto &pr : parts) dev_free(pr.first);
+        uint64_t *all = ws.get_n<uint64_t>(total_u + 1);
+        int64_t at = 0;
+        for (auto &pr : parts) {
+            if (pr.second)
+                MJ_HIP(hipMemcpyAsync(all + at, pr.first, (size_t)pr.second * 8,
+                                      hipMemcpyDeviceToDevice, s));
+            at += pr.second;
+        }
+        ctx->last_c0 = total_u;
+        tm.mark();  // 3 group + filter
+        C = dedup_pairs(all, total_u, d.n, d.n, ws, s, ctx->pinned, &uniq, upto != 1);
     }
     ctx->last_R = R;
+    ctx->last_M = M;
     ctx->last_rcap = std::max<int64_t>(si.rec_bound * pp.reps, 2);
     tm.mark();  // 4 dedup
     if (stats) {
@@ -355,6 +375,8 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
         stats->pair_tests = (int64_t)g.tests;
         stats->candidates = C;
         stats->positions = d.total * pp.reps;
+        stats->member_filter = members ? 1 : 0;
+        stats->members = M;
     }
     if (upto == 1) {
         mj_pairs *out = new mj_pairs();
@@ -365,7 +387,6 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
         tm.fill(stats);
         return out;
     }
-    struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
     uint8_t *flags = ws.get_n<uint8_t>(C + 1);
     run_verify(ctx, uniq, C, d, d, 0, params->k, params, flags, s, stats, cells_slot(ctx));
     tm.mark();  // 5 verify
@@ -389,8 +410,9 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
 
 __global__ void k_collect(const int64_t *R, const uint64_t *slot, const unsigned long long *c0,
                           const uint32_t *u, const uint32_t *outn, const unsigned long long *cells,
-                          const uint32_t *symbol_err, uint64_t *dst) {
+                          const uint32_t *symbol_err, const int64_t *M, uint64_t *dst) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    dst[10] = (uint64_t)*M;
     dst[9] = symbol_err ? *symbol_err : 0;
     dst[0] = (uint64_t)*R;
     dst[1] = slot ? slot[0] : 0;
@@ -438,6 +460,11 @@ static bool plan_streamed(mj_ctx *ctx, const mj_params *params, const DevStrings
     if (ccap > (double)std::min<int64_t>(ctx->pair_test_pass, 0x7FFFFFF0LL))
         return false;  // candidates beyond one emission pass: stage by stage, in passes
     pl.ccap = (int64_t)ccap;
+    // the member filter's records: the last join's rate per record bound, with room
+    pl.members = use_members(ctx, pl.scap);
+    pl.mcap = pl.members ? std::max<int64_t>(2, std::min<int64_t>(
+                               pl.scap, (int64_t)(1.1 * h.mem_per_bound * (double)pl.rcap) + 65536))
+                         : pl.scap;
     pl.emit = h.emit;
     return true;
 }
@@ -456,12 +483,20 @@ static StreamedDev launch_streamed_main(mj_ctx *ctx, DevStrings &d, const Partit
     int64_t *R_dev = ws.get_n<int64_t>(2);
     partition_records_streamed(d, pp, pl.si, key, val, R_dev, ws, s, kt);
     if (tm) tm->mark();  // 1 partition
-    sort_records(key, val, pl.scap, ws, s, ctx->pinned, R_dev);
+    uint64_t *gkey = key, *gval = val;
+    int64_t *M_dev = R_dev;
+    if (pl.members) {
+        gkey = ws.get_n<uint64_t>(pl.mcap + 1);
+        gval = ws.get_n<uint64_t>(pl.mcap + 1);
+        M_dev = ws.get_n<int64_t>(2);
+        group_members(key, val, pl.scap, R_dev, gkey, gval, pl.mcap, M_dev, ctx->member_big, ws, s);
+    }
+    sort_records(gkey, gval, pl.mcap, ws, s, ctx->pinned, M_dev);
     if (tm) tm->mark();  // 2 sort
-    GroupInfo g = find_groups_streamed(key, pl.scap, R_dev, ws, s);
+    GroupInfo g = find_groups_streamed(gkey, pl.mcap, M_dev, ws, s);
     uint64_t *cand = ws.get_n<uint64_t>(pl.ccap + 1);
     unsigned long long *c0 = (unsigned long long *)ws.get_n<uint64_t>(2);
-    emit_candidates_streamed(val, pl.scap, R_dev, g, d, cand, pl.ccap, c0, pl.emit, ws, s, kt);
+    emit_candidates_streamed(gval, pl.mcap, M_dev, g, d, cand, pl.ccap, c0, pl.emit, ws, s, kt);
     if (tm) tm->mark();  // 3 group + filter
     uint64_t *uniq = nullptr;
     const uint32_t *u = dedup_pairs_streamed(cand, pl.ccap, c0, d.n, d.n, ws, s, &uniq);
@@ -477,9 +512,9 @@ static StreamedDev launch_streamed_main(mj_ctx *ctx, DevStrings &d, const Partit
     gather_u64(uniq, idx, dv.outbuf, pl.ccap, s, on);
     uint64_t *res = ws.get_n<uint64_t>(16);
     hipLaunchKernelGGL(k_collect, dim3(1), dim3(64), 0, s, R_dev, g.slot, c0, u, on, cells,
-                       (const uint32_t *)d.symbol_err, res);
+                       (const uint32_t *)d.symbol_err, M_dev, res);
     MJ_LAUNCH_CHECK();
-    MJ_HIP(hipMemcpyAsync(ctx->pinned, res, 10 * 8, hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipMemcpyAsync(ctx->pinned, res, 11 * 8, hipMemcpyDeviceToHost, s));
     return dv;
 }
 
@@ -488,18 +523,20 @@ static StreamedDev launch_streamed_main(mj_ctx *ctx, DevStrings &d, const Partit
 static mj_pairs *finish_streamed(mj_ctx *ctx, const StreamedPlan &pl, const StreamedDev &dv,
                                  const DevStrings &d, const PartitionParams &pp, hipStream_t s,
                                  mj_stats *stats) {
-    uint64_t hv[10];
+    uint64_t hv[11];
     memcpy(hv, ctx->pinned, sizeof(hv));
     const int64_t R = (int64_t)hv[0], c0h = (int64_t)hv[4], C = (int64_t)hv[5], nout = (int64_t)hv[6];
+    const int64_t M = (int64_t)hv[10];
     if (hv[9]) throw Error(MJ_EINVAL, "a symbol code is not below sigma");
-    if (c0h > pl.ccap || R > pl.scap) return nullptr;  // more than the room left: stage by stage
-    if (R > 1 && (hv[1] & 0xFFFFFFFFu) != (hv[1] >> 32)) throw Error(MJ_EDEVICE, "group boundary mismatch");
+    // more than the room left: stage by stage
+    if (c0h > pl.ccap || R > pl.scap || M > pl.mcap) return nullptr;
+    if (M > 1 && (hv[1] & 0xFFFFFFFFu) != (hv[1] >> 32)) throw Error(MJ_EDEVICE, "group boundary mismatch");
     if (hv[8]) throw Error(MJ_ECAPACITY, "a pair's band exceeds the verifier window");
     mj_pairs *out = new mj_pairs();
     out->alloc = t_dev_alloc;
     out->stream = s;
     out->n = nout;
-    out->d = (uint64_t *)dev_alloc((size_t)(nout + 1) * 8);
+    out->d = (uint64_t *)result_alloc((size_t)(nout + 1) * 8, out->alloc, s);
     if (nout) MJ_HIP(hipMemcpyAsync(out->d, dv.outbuf, (size_t)nout * 8, hipMemcpyDeviceToDevice, s));
     if (stats) {
         memset(stats, 0, sizeof(*stats));
@@ -518,11 +555,14 @@ static mj_pairs *finish_streamed(mj_ctx *ctx, const StreamedPlan &pl, const Stre
         stats->verify_blocks = ctx->tune.best_blocks[ci][npi];
         stats->streamed = 1;
         stats->host_reads = 2;
+        stats->member_filter = pl.members ? 1 : 0;
+        stats->members = M;
     }
     // keep the rates current (capacities of the next join)
     ctx->stream.cand_per_record = (double)c0h / (double)pl.rcap;
     ctx->stream.rec_per_bound = (double)R / (double)pl.rcap;
-    ctx->stream.emit = emit_hints((uint64_t)hv[3], R, d.n);
+    ctx->stream.mem_per_bound = (double)M / (double)pl.rcap;
+    ctx->stream.emit = emit_hints((uint64_t)hv[3], M, d.n);
     return out;
 }
 
@@ -687,7 +727,8 @@ extern "C" mj_status mj_join(mj_ctx *ctx, const mj_strings *strings, const mj_pa
         h.verify_lanes = params->verify_lanes;
         h.cand_per_record = (double)ctx->last_c0 / (double)std::max<int64_t>(ctx->last_rcap, 1);
         h.rec_per_bound = (double)ctx->last_R / (double)std::max<int64_t>(ctx->last_rcap, 1);
-        h.emit = emit_hints((uint64_t)stats->pair_tests, stats->records, strings->n);
+        h.mem_per_bound = (double)ctx->last_M / (double)std::max<int64_t>(ctx->last_rcap, 1);
+        h.emit = emit_hints((uint64_t)stats->pair_tests, stats->members, strings->n);
         h.verify_g = ctx->tune.last_g;
         h.verify_blocks = ctx->tune.last_blocks;
     }
@@ -916,8 +957,7 @@ extern "C" mj_status mj_search(mj_ctx *ctx, const mj_index *ix, const mj_strings
                        : 0;
     tm.mark();  // 3 probe + filter
     uint64_t *uniq = nullptr;
-    int64_t C = dedup_pairs(cand, c0, qd.n, ix->n, ws, s, ctx->pinned, &uniq);
-    struct UFree { uint64_t *p; ~UFree() { dev_free(p); } } uf{uniq};
+    int64_t C = dedup_pairs(cand, c0, qd.n, ix->n, ws, s, ctx->pinned, &uniq, true);
     tm.mark();  // 4 dedup
     uint8_t *flags = ws.get_n<uint8_t>(C + 1);
     run_verify(ctx, uniq, C, qd, id, 1, qparams->k, qparams, flags, s, stats, cells_slot(ctx));
@@ -957,7 +997,7 @@ extern "C" mj_status mj_pairs_copy_to_host(const mj_pairs *p, uint64_t *dst, int
 
 extern "C" void mj_pairs_free(mj_pairs *p) {
     if (!p) return;
-    dev_free(p->d, p->alloc);
+    result_free(p->d, p->alloc, p->stream);
     delete p;
 }
 

@@ -17,6 +17,7 @@ struct StreamHints {
     int64_t k = 0;
     double cand_per_record = 0;  // emitted candidates (before the dedup) per record bound
     double rec_per_bound = 1;    // records per record bound
+    double mem_per_bound = 1;    // records kept by the member filter per record bound
     EmitHints emit;
     int verify_g = 0, verify_blocks = 0;
 };
@@ -27,6 +28,8 @@ struct StreamedPlan {
     SetupInfo si;
     int cmax = 0;
     int64_t rcap = 0, scap = 0, ccap = 0;
+    bool members = false;  // the member filter runs; mcap: room for its records
+    int64_t mcap = 0;
     EmitHints emit;
 };
 struct StreamedDev {
@@ -60,13 +63,15 @@ struct mj_ctx {
     // configuration instead of timing the choices on a live call
     bool no_tuning = false;
     int64_t pair_test_pass = (int64_t)1 << 28;  // record-pair tests per emission pass
+    int64_t member_min = (int64_t)1 << 23;      // records from which the member filter runs
+    uint32_t member_big = 1u << 16;             // its buckets above this are kept whole
     int streaming = 1;  // 0 stage by stage, 1 streamed, 2 streamed and captured (mj_ctx_set_streaming)
     StreamHints stream;
     JoinGraph graph;
     hipStream_t cap_stream = nullptr;  // the stream graphs are captured on
     int streamed_joins = 0, stream_fallbacks = 0;
     // the last stage-by-stage join's emitted candidates, records and record bound
-    int64_t last_c0 = 0, last_R = 0, last_rcap = 0;
+    int64_t last_c0 = 0, last_R = 0, last_rcap = 0, last_M = 0;
 };
 
 struct mj_pairs {

@@ -373,9 +373,13 @@ __global__ void k_unpack_pairs(uint64_t *p, int64_t n, int b) {
 }
 
 int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t n_first, int32_t n_second, Workspace &ws,
-                    hipStream_t s, uint64_t *host_scratch, uint64_t **result) {
+                    hipStream_t s, uint64_t *host_scratch, uint64_t **result, bool to_ws) {
+    auto out_buf = [&](int64_t count) {
+        return to_ws ? ws.get_n<uint64_t>(count + 1)
+                     : (uint64_t *)result_alloc((size_t)(count + 1) * 8, t_dev_alloc, s);
+    };
     if (n == 0) {
-        *result = (uint64_t *)dev_alloc(16);
+        *result = out_buf(0);
         return 0;
     }
     // pair = first << 32 | second with first < 2^bf and second < 2^bs.  The radix sort
@@ -398,7 +402,7 @@ int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t n_first, int32_t n_secon
     MJ_LAUNCH_CHECK();
     int64_t *idx = ws.get_n<int64_t>(n + 1);
     int64_t u = compact_flags(f, n, idx, ws, s, host_scratch);
-    uint64_t *res = (uint64_t *)dev_alloc((size_t)(u + 1) * 8);
+    uint64_t *res = out_buf(u);
     gather_u64(pairs, idx, res, u, s);
     if (pack && u > 0) {
         hipLaunchKernelGGL(k_unpack_pairs, dim3(grid_for(u, 256, 16384)), dim3(256), 0, s, res, u, bs);

@@ -69,6 +69,13 @@ void dev_free(void *p, const mj_allocator &a);
 // From / to the current thread's allocator.
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
+// Buffers handed to the caller (result pairs): from the caller's allocator when there is
+// one, else stream-ordered (hipMallocFromPoolAsync on `s` from a per-device pool that keeps
+// up to RESULT_POOL_KEEP bytes of freed blocks), so neither taking nor freeing one waits
+// for the device.  result_free orders the free after the work queued on `s`.
+constexpr uint64_t RESULT_POOL_KEEP = 1ull << 30;
+void *result_alloc(size_t bytes, const mj_allocator &a, hipStream_t s);
+void result_free(void *p, const mj_allocator &a, hipStream_t s);
 
 // ---------------------------------------------------------------- workspace
 // Grow-only cache of device blocks; blocks handed out during one call are released
@@ -159,12 +166,23 @@ constexpr size_t HOST_SCRATCH_BYTES = 16384;
 // Stable sort of keys (and an optional payload) ascending, in place.  key_mask has a 1
 // at every bit that may be set in some key (the others must be zero in all keys).
 // n_dev (nullable): the element count on the device, n then being its capacity.
+// k2 / v2 (nullable): second buffers of n elements (else taken from the workspace).
 void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Workspace &ws,
-                hipStream_t s, const int64_t *n_dev = nullptr);
+                hipStream_t s, const int64_t *n_dev = nullptr, uint64_t *k2 = nullptr,
+                uint64_t *v2 = nullptr);
 // Records (key, payload) sorted by the full 64-bit key, in place; equal keys keep their
 // order only up to the runs that the repair step reorders.
 void sort_records(uint64_t *key, uint64_t *val, int64_t n, Workspace &ws, hipStream_t s,
                   uint64_t *host_scratch, const int64_t *n_dev = nullptr);
+// Records that may share their key with another record (a superset of every group of
+// two or more; see prims.hip): their (key, payload) into mkey / mval, in index order, at
+// most mcap of them; *m_dev = their count (on the device; a count above mcap means the
+// arrays were too small).  n_dev (nullable): the record count on the device, n then
+// being its capacity.  Buckets (records of equal top 16 key bits) of more than `big`
+// records are kept whole.
+void group_members(const uint64_t *key, const uint64_t *val, int64_t n, const int64_t *n_dev,
+                   uint64_t *mkey, uint64_t *mval, int64_t mcap, int64_t *m_dev, uint32_t big,
+                   Workspace &ws, hipStream_t s);
 // Gather: dst[i] = src[idx[i]] for i < n (or < *n_dev when given).
 void gather_u64(const uint64_t *src, const int64_t *idx, uint64_t *dst, int64_t n, hipStream_t s,
                 const uint32_t *n_dev = nullptr);
@@ -308,8 +326,10 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
                         uint64_t t_end = 0);
 // Sorted unique copy of pairs (first << 32 | second, first < n_first, second <
 // n_second) in *result (owned allocation); sorts `pairs` in place; returns the count.
+// The distinct pairs in *result: a workspace block when to_ws, else a result buffer
+// (result_alloc with the thread's allocator on s) that the caller owns.
 int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t n_first, int32_t n_second, Workspace &ws,
-                    hipStream_t s, uint64_t *host_scratch, uint64_t **result);
+                    hipStream_t s, uint64_t *host_scratch, uint64_t **result, bool to_ws);
 // Search: probe sorted index keys with sorted query records.
 int64_t probe_candidates(const uint64_t *qkey, const uint64_t *qval, int64_t RQ,
                          const uint64_t *ikey, const uint64_t *ival, int64_t RI,

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "mj_common.h"
 
@@ -35,6 +36,49 @@ void dev_free(void *p, const mj_allocator &a) {
 
 void *dev_alloc(size_t bytes) { return dev_alloc(bytes, t_dev_alloc); }
 void dev_free(void *p) { dev_free(p, t_dev_alloc); }
+
+// One pool per device, made on first use and kept for the life of the process.
+static hipMemPool_t result_pool(int dev) {
+    static std::mutex mu;
+    static std::vector<hipMemPool_t> pools;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)pools.size() <= dev) pools.resize(dev + 1, nullptr);
+    if (!pools[dev]) {
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t p = nullptr;
+        if (hipMemPoolCreate(&p, &props) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(MJ_EDEVICE, "result memory pool creation failed");
+        }
+        uint64_t keep = RESULT_POOL_KEEP;
+        (void)hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+        pools[dev] = p;
+    }
+    return pools[dev];
+}
+
+void *result_alloc(size_t bytes, const mj_allocator &a, hipStream_t s) {
+    if (a.alloc) return dev_alloc(bytes, a);
+    if (bytes == 0) bytes = 16;
+    int dev = 0;
+    MJ_HIP(hipGetDevice(&dev));
+    void *p = nullptr;
+    if (hipMallocFromPoolAsync(&p, bytes, result_pool(dev), s) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(MJ_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+}
+
+void result_free(void *p, const mj_allocator &a, hipStream_t s) {
+    if (!p) return;
+    if (a.alloc) a.free(p, a.user);
+    else (void)hipFreeAsync(p, s);
+}
 
 Workspace::~Workspace() {
     for (auto &b : blocks_) dev_free(b.p, alloc);
@@ -606,8 +650,9 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
 // consecutive lanes write consecutive addresses of a digit's run.  Keys and payloads
 // take turns in one LDS buffer (38 KB per workgroup instead of 70 KB), and the payloads
 // are loaded only once the keys are ranked, which keeps the kernel within 128 registers:
-// four workgroups fit a CU where two did.
-template <bool HASV>
+// four workgroups fit a CU where two did.  BUILD (keys only): each input key k at index i
+// is written as (top half of k) << 32 | i, the narrow element of the member filter.
+template <bool HASV, bool BUILD = false>
 __global__ __launch_bounds__(RS_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const uint64_t *__restrict__ vin, uint64_t *__restrict__ kout,
     uint64_t *__restrict__ vout, int64_t n, int shift, int64_t ntiles,
@@ -633,6 +678,7 @@ __global__ __launch_bounds__(RS_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
         const int64_t i = base + (int64_t)c * 64 + lane;
         const bool ok = i < n;
         k[c] = ok ? kin[i] : 0;
+        if (BUILD) k[c] = (k[c] & 0xFFFFFFFF00000000ull) | (uint64_t)(uint32_t)i;
         const uint32_t d = (uint32_t)(k[c] >> shift) & 255u;
         const uint64_t peers = digit_peers(d, __ballot(ok));
         const uint32_t before = wc[wave][d];
@@ -700,7 +746,7 @@ __global__ __launch_bounds__(RS_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
 }
 
 void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Workspace &ws,
-                hipStream_t s, const int64_t *n_dev) {
+                hipStream_t s, const int64_t *n_dev, uint64_t *k2, uint64_t *v2) {
     if (n <= 1) return;
     if (n > 0xFFFFFFF0LL) throw Error(MJ_ECAPACITY, "sort of more than 2^32 elements");
     int passes[8], np = 0;
@@ -712,8 +758,8 @@ void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Work
         throw Error(MJ_ECAPACITY, "radix_sort: too many tiles");
     uint32_t *cnt = ws.get_n<uint32_t>(256 * ntiles + 1);
     uint32_t *off = ws.get_n<uint32_t>(256 * ntiles + 1);
-    uint64_t *k2 = ws.get_n<uint64_t>(n);
-    uint64_t *v2 = val ? ws.get_n<uint64_t>(n) : nullptr;
+    if (!k2) k2 = ws.get_n<uint64_t>(n);
+    if (val && !v2) v2 = ws.get_n<uint64_t>(n);
     uint64_t *ka = key, *va = val, *kb = k2, *vb = v2;
     for (int t = 0; t < np; t++) {
         const int shift = 8 * passes[t];
@@ -743,14 +789,15 @@ void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Work
 // runs are rare (about n^2 / 2^33 pairs of keys share a top half).  k_run_bits marks, one
 // bit per record, where a run starts and where the key changes inside a run; k_mixed_runs
 // (read-only) lets the first change of each run record the run's bounds, found by
-// scanning those bitmaps 64 records per step; k_sort_runs then orders each listed run by
-// the full key (insertion sort: the runs are short, and a run that holds a frequent key
-// has few inversions).  The run list is split into RUN_SEGS segments, segment j taking
-// the runs whose first change lies in its share of bitmap words, each with a counter on
-// a line of its own (device-scope atomics on one address serialise: 64 segments left the
-// repair at 0.9 ms on 78 M text records, 1,024 took 0.4 ms off the sort).  Two runs are
-// disjoint and hold two records each around their first change, so W words of 64
-// positions hold at most 32 W + 1 first changes: a segment can never overflow.
+// scanning those bitmaps 64 records per step; k_sort_runs_short and k_sort_runs_long
+// then order each listed run by the full key (insertion sort, a thread per short run and
+// a wave per long one: a run that holds a frequent key has few inversions).  The run list
+// is split into RUN_SEGS segments, segment j taking the runs whose first change lies in
+// its share of bitmap words, each with a counter on a line of its own (device-scope
+// atomics on one address serialise: 64 segments left the repair at 0.9 ms on 78 M text
+// records, 1,024 took 0.4 ms off the sort).  Two runs are disjoint and hold two records
+// each around their first change, so W words of 64 positions hold at most 32 W + 1 first
+// changes: a segment can never overflow.
 constexpr int RUN_SEGS = 1024;
 constexpr int RUN_CSTRIDE = 64;  // uint64 words between two segment counters
 __global__ void k_run_bits(const uint64_t *__restrict__ key, int64_t n, uint64_t *__restrict__ rsb,
@@ -823,8 +870,10 @@ __global__ void k_mixed_runs(const uint64_t *__restrict__ rsb, const uint64_t *_
     }
 }
 
-// grid.y = segment
-__global__ void k_sort_runs(uint64_t *__restrict__ key, uint64_t *__restrict__ val,
+constexpr int64_t RUN_SHORT = 64;
+
+// grid.y = segment; one thread per run of at most RUN_SHORT records
+__global__ void k_sort_runs_short(uint64_t *__restrict__ key, uint64_t *__restrict__ val,
                             const int64_t *__restrict__ runs, int64_t seg_cap,
                             const unsigned long long *count) {
     const int64_t seg = blockIdx.y;
@@ -833,6 +882,7 @@ __global__ void k_sort_runs(uint64_t *__restrict__ key, uint64_t *__restrict__ v
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nr;
          r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t rs = sr[2 * r], re = sr[2 * r + 1];
+        if (re - rs > RUN_SHORT) continue;  // k_sort_runs_long's
         // Mixed runs are mostly one frequent key and a rare colliding one, so nearly every
         // record is already in place.  The largest key of the sorted prefix stays in a
         // register and keys are loaded RS_FIX at a time (all in flight together): an
@@ -867,10 +917,174 @@ __global__ void k_sort_runs(uint64_t *__restrict__ key, uint64_t *__restrict__ v
     }
 }
 
+// grid.y = segment; one wave per run of more than RUN_SHORT records.  The records of a
+// run share the key's top half, and a mixed run is mostly one frequent key and a few
+// colliding ones, met in any order: the wave sorts it by counting.  Pass 1 lists the
+// run's distinct keys (at most RUN_KEYS) in LDS and counts each; their order gives each
+// key's first position; pass 2 writes every record to its position in the scratch arrays
+// (ranks among equal keys of 64 records from ballots, so equal keys keep their order);
+// pass 3 copies the run back.  A run with more distinct keys is insertion-sorted instead
+// (k_insert_run).
+constexpr int RUN_KEYS = 64;
+
+__device__ void k_insert_run(uint64_t *__restrict__ key, uint64_t *__restrict__ val, int64_t rs,
+                             int64_t re, int lane) {
+    // Keys below the largest key before them (a max-scan over the lanes, seeded with the
+    // sorted prefix's largest key) are inserted into the sorted prefix: a binary search for
+    // the place, then the wave moves the keys between the place and the old position up
+    // by one, 64 at a time from the top (a chunk's loads complete before its stores, and
+    // each chunk writes only above the next chunk's range).  An insertion writes only
+    // positions <= its old one, so the keys held for later lanes stay current.
+    uint64_t top = key[rs];
+    for (int64_t j0 = rs + 1; j0 < re; j0 += 64) {
+        const bool ok = j0 + lane < re;
+        const uint64_t k = ok ? key[j0 + lane] : 0;
+        uint64_t incl = k;  // largest key of lanes <= this one
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t o = shfl_up_t(incl, d);
+            if (lane >= d) incl = o > incl ? o : incl;
+        }
+        uint64_t before = shfl_up_t(incl, 1);
+        if (lane == 0) before = 0;
+        if (top > before) before = top;
+        uint64_t bad = __ballot(ok && k < before);
+        const uint64_t cmax = (uint64_t)__shfl((long long)incl, 63, 64);
+        while (bad) {
+            const int b = __ffsll((unsigned long long)bad) - 1;
+            bad &= bad - 1;
+            const int64_t jb = j0 + b;
+            const uint64_t kb = (uint64_t)__shfl((long long)k, b, 64);
+            const uint64_t vb = val[jb];
+            int64_t a = rs, z = jb;  // the place: the first key of the prefix above kb
+            while (a < z) {
+                const int64_t mid = (a + z) >> 1;
+                if (key[mid] <= kb) a = mid + 1;
+                else z = mid;
+            }
+            for (int64_t hi = jb; hi > a; hi -= 64) {
+                const int64_t lo = max(a, hi - 64), i = lo + lane;
+                uint64_t kk = 0, vv = 0;
+                if (i < hi) {
+                    kk = key[i];
+                    vv = val[i];
+                }
+                if (i < hi) {
+                    key[i + 1] = kk;
+                    val[i + 1] = vv;
+                }
+            }
+            if (lane == 0) {
+                key[a] = kb;
+                val[a] = vb;
+            }
+            __threadfence_block();  // the moves complete before the next search
+        }
+        if (cmax > top) top = cmax;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sort_runs_long(uint64_t *__restrict__ key,
+                                                        uint64_t *__restrict__ val,
+                                                        uint64_t *__restrict__ tk,
+                                                        uint64_t *__restrict__ tv,
+                                                        const int64_t *__restrict__ runs,
+                                                        int64_t seg_cap,
+                                                        const unsigned long long *count) {
+    __shared__ uint64_t tkey[4][RUN_KEYS];
+    __shared__ uint32_t tcnt[4][RUN_KEYS];
+    const int64_t seg = blockIdx.y;
+    const int64_t nr = min((int64_t)count[seg * RUN_CSTRIDE], seg_cap);
+    const int64_t *sr = runs + 2 * seg * seg_cap;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t below = lanes_below();
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    // the wave reads 64 runs' bounds at a time and takes the long ones among them
+    for (int64_t r0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; r0 < nr;
+         r0 += nwaves * 64) {
+        const int64_t rl = r0 + lane;
+        const int64_t rs_l = rl < nr ? sr[2 * rl] : 0, re_l = rl < nr ? sr[2 * rl + 1] : 0;
+        for (uint64_t longs = __ballot(re_l - rs_l > RUN_SHORT); longs; longs &= longs - 1) {
+            const int src = __ffsll((unsigned long long)longs) - 1;
+            const int64_t rs = __shfl((long long)rs_l, src, 64), re = __shfl((long long)re_l, src, 64);
+            // the index of key k in the table of nd distinct keys, or -1
+            auto find = [&](uint64_t k, int nd) {
+                int idx = -1;
+                for (int t = 0; t < nd; t++)
+                    if (tkey[wv][t] == k) idx = t;
+                return idx;
+            };
+            tcnt[wv][lane] = 0;
+            __builtin_amdgcn_wave_barrier();
+            int nd = 0;  // pass 1: the distinct keys and their counts
+            bool over = false;
+            for (int64_t s0 = rs; s0 < re && !over; s0 += 64) {
+                const bool ok = s0 + lane < re;
+                const uint64_t k = ok ? key[s0 + lane] : 0;
+                int idx = ok ? find(k, nd) : 0;
+                for (uint64_t un = __ballot(idx < 0); un; un = __ballot(idx < 0)) {
+                    if (nd == RUN_KEYS) {
+                        over = true;
+                        break;
+                    }
+                    const uint64_t nk = (uint64_t)__shfl((long long)k, __ffsll((unsigned long long)un) - 1, 64);
+                    if (lane == 0) tkey[wv][nd] = nk;
+                    __builtin_amdgcn_wave_barrier();
+                    if (idx < 0 && k == nk) idx = nd;
+                    nd++;
+                }
+                if (over) break;
+                const uint64_t peers = digit_peers((uint32_t)idx, __ballot(ok));
+                if (ok && (peers & below) == 0) tcnt[wv][idx] += (uint32_t)__popcll(peers);
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (over) {
+                k_insert_run(key, val, rs, re, lane);
+                continue;
+            }
+            // each key's first position: the counts of the smaller keys
+            const uint64_t mk = lane < nd ? tkey[wv][lane] : ~0ull;
+            const uint32_t mc = lane < nd ? tcnt[wv][lane] : 0u;
+            uint32_t first = 0;
+            for (int t = 0; t < nd; t++) {
+                const uint64_t ok2 = (uint64_t)__shfl((long long)mk, t, 64);
+                const uint32_t c = (uint32_t)__shfl((int)mc, t, 64);
+                if (ok2 < mk) first += c;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane < nd) tcnt[wv][lane] = first;
+            __builtin_amdgcn_wave_barrier();
+            for (int64_t s0 = rs; s0 < re; s0 += 64) {  // pass 2: records to their places
+                const bool ok = s0 + lane < re;
+                const uint64_t k = ok ? key[s0 + lane] : 0, v = ok ? val[s0 + lane] : 0;
+                const int idx = ok ? find(k, nd) : 0;
+                const uint64_t peers = digit_peers((uint32_t)idx, __ballot(ok));
+                const uint32_t base = tcnt[wv][idx];
+                __builtin_amdgcn_wave_barrier();
+                if (ok) {
+                    const int64_t pos = rs + base + (uint32_t)__popcll(peers & below);
+                    tk[pos] = k;
+                    tv[pos] = v;
+                }
+                if (ok && (peers & below) == 0) tcnt[wv][idx] = base + (uint32_t)__popcll(peers);
+                __builtin_amdgcn_wave_barrier();
+            }
+            __threadfence_block();  // the scratch writes complete before other lanes read them
+            for (int64_t j = rs + lane; j < re; j += 64) {  // pass 3: back
+                key[j] = tk[j];
+                val[j] = tv[j];
+            }
+            __threadfence_block();
+        }
+    }
+}
+
 void sort_records(uint64_t *key, uint64_t *val, int64_t n, Workspace &ws, hipStream_t s,
                   uint64_t *host_scratch, const int64_t *n_dev) {
     if (n <= 1) return;
-    radix_sort(key, val, n, 0xFFFFFFFF00000000ull, ws, s, n_dev);
+    // the radix sort's second buffers, then the long-run repair's
+    uint64_t *k2 = ws.get_n<uint64_t>(n), *v2 = ws.get_n<uint64_t>(n);
+    radix_sort(key, val, n, 0xFFFFFFFF00000000ull, ws, s, n_dev, k2, v2);
     const int64_t nw = (n + 63) / 64;
     const int64_t seg_words = (nw + RUN_SEGS - 1) / RUN_SEGS;
     const int64_t seg_cap = 32 * seg_words + 1;  // first changes a segment can hold
@@ -885,10 +1099,171 @@ void sort_records(uint64_t *key, uint64_t *val, int64_t n, Workspace &ws, hipStr
     hipLaunchKernelGGL(k_mixed_runs, dim3(grid_for(nw, 256, 16384)), dim3(256), 0, s, rsb, brb, n,
                        seg_words, runs, seg_cap, count, n_dev);
     MJ_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sort_runs, dim3(4, RUN_SEGS), dim3(256), 0, s, key, val, runs, seg_cap,
+    hipLaunchKernelGGL(k_sort_runs_short, dim3(4, RUN_SEGS), dim3(256), 0, s, key, val, runs, seg_cap,
                        count);
     MJ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sort_runs_long, dim3(1, RUN_SEGS), dim3(256), 0, s, key, val, k2, v2, runs,
+                       seg_cap, count);
+    MJ_LAUNCH_CHECK();
     (void)host_scratch;
+}
+
+// ---------------------------------------------------------------- group members
+// Only records whose key occurs at least twice can form a group (Alg. 3 pairs records of
+// equal key); on the large workloads they are 5-25% of all records.  The filter keeps a
+// superset of them -- every record whose key's top half occurs twice -- without sorting the
+// full records:
+//  1. two radix passes over narrow elements (top half of the key << 32 | record index,
+//     built by the first pass from the keys) order them by the key's top 16 bits, which
+//     puts each "bucket" of equal top 16 bits in one contiguous range;
+//  2. k_mb_bounds finds each bucket's range (a binary search per bucket), and k_mb_flags
+//     gives each bucket one workgroup with two LDS bitmaps over the next 16 bits (seen /
+//     seen again), flagging the elements whose top half was seen again.  A bucket of more
+//     than `big` elements (default 2^16) is kept whole, which only costs time;
+//  3. the flagged elements are compacted, in order, and their records gathered.
+// The kept records then go through the full record sort; any superset of the group
+// members gives the same groups.
+constexpr int MB_BUCKETS = 1 << 16;
+
+__device__ __forceinline__ uint32_t mb_top16(uint64_t x) { return (uint32_t)(x >> 48); }
+
+// bs[b] = the first index whose top 16 bits are >= b (b = 0..2^16; bs[2^16] = n): one
+// binary search per thread over the sorted elements.  Flags past the count (up to the
+// capacity) are cleared on the way.
+__global__ void k_mb_bounds(const uint64_t *__restrict__ w, int64_t cap, const int64_t *n_dev,
+                            uint32_t *__restrict__ bs, uint8_t *__restrict__ flags) {
+    const int64_t n = n_dev ? min(cap, *n_dev) : cap;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g <= MB_BUCKETS) {
+        int64_t a = 0, z = n;
+        while (a < z) {
+            const int64_t mid = (a + z) >> 1;
+            if (mb_top16(w[mid]) < (uint32_t)g) a = mid + 1;
+            else z = mid;
+        }
+        bs[g] = (uint32_t)a;
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = n + g; i < cap; i += stride) flags[i] = 0;
+}
+
+// One workgroup per bucket [bs[b], bs[b+1]): LDS bitmaps over bits 32..47 (seen / seen
+// again); an element is kept when its bits were seen again, i.e. when its key's top half
+// occurs twice.  A bucket of more than `big` elements is kept whole.
+__global__ __launch_bounds__(256) void k_mb_flags(const uint64_t *__restrict__ w,
+                                                  const uint32_t *__restrict__ bs, uint32_t big,
+                                                  uint8_t *__restrict__ flags) {
+    const uint32_t lo = bs[blockIdx.x], hi = bs[blockIdx.x + 1];
+    if (hi - lo > big) {
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) flags[i] = 1;
+        return;
+    }
+    if (hi <= lo + 1) {  // empty, or one element: not kept
+        if (hi == lo + 1 && threadIdx.x == 0) flags[lo] = 0;
+        return;
+    }
+    __shared__ uint32_t seen[2048], again[2048];
+    for (int j = threadIdx.x; j < 2048; j += 256) {
+        seen[j] = 0;
+        again[j] = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const uint32_t sub = (uint32_t)(w[i] >> 32) & 0xFFFFu, bit = 1u << (sub & 31);
+        if (atomicOr(&seen[sub >> 5], bit) & bit) atomicOr(&again[sub >> 5], bit);
+    }
+    __syncthreads();
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const uint32_t sub = (uint32_t)(w[i] >> 32) & 0xFFFFu;
+        flags[i] = (uint8_t)((again[sub >> 5] >> (sub & 31)) & 1u);
+    }
+}
+
+// mkey[j], mval[j] = the record of the j-th kept element (j < min(count, mcap)); m_dev
+// gets the count (which may exceed mcap: the caller checks).  Four elements per thread,
+// their loads issued together (the record reads are scattered).
+constexpr int MB_GATHER = 4;
+__global__ void k_mb_gather(const int64_t *__restrict__ idx, const uint32_t *__restrict__ count,
+                            const uint64_t *__restrict__ w, const uint64_t *__restrict__ key,
+                            const uint64_t *__restrict__ val, uint64_t *__restrict__ mkey,
+                            uint64_t *__restrict__ mval, int64_t mcap, int64_t *m_dev) {
+    const int64_t m = min((int64_t)*count, mcap);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0) *m_dev = (int64_t)*count;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j0 = g; j0 < m; j0 += stride * MB_GATHER) {
+        uint32_t r[MB_GATHER];
+        int64_t ix[MB_GATHER];
+#pragma unroll
+        for (int u = 0; u < MB_GATHER; u++) {
+            const int64_t j = j0 + u * stride;
+            ix[u] = j < m ? idx[j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < MB_GATHER; u++) r[u] = (uint32_t)w[ix[u]];
+        uint64_t k[MB_GATHER], v[MB_GATHER];
+#pragma unroll
+        for (int u = 0; u < MB_GATHER; u++) {
+            k[u] = key[r[u]];
+            v[u] = val[r[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < MB_GATHER; u++) {
+            const int64_t j = j0 + u * stride;
+            if (j < m) {
+                mkey[j] = k[u];
+                mval[j] = v[u];
+            }
+        }
+    }
+}
+
+static void mb_radix_pass(const uint64_t *kin, uint64_t *kout, int64_t n, int shift, bool build,
+                          Workspace &ws, hipStream_t s, const int64_t *n_dev) {
+    const int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+    uint32_t *cnt = ws.get_n<uint32_t>(256 * ntiles + 1);
+    uint32_t *off = ws.get_n<uint32_t>(256 * ntiles + 1);
+    hipLaunchKernelGGL(k_rs_tile_counts, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, s, kin, n,
+                       shift, ntiles, cnt, n_dev);
+    MJ_LAUNCH_CHECK();
+    exclusive_scan_u32(cnt, off, 256 * ntiles, ws, s);
+    if (build)
+        hipLaunchKernelGGL((k_rs_scatter<false, true>), dim3((unsigned)ntiles), dim3(RS_THREADS), 0,
+                           s, kin, nullptr, kout, nullptr, n, shift, ntiles, off, n_dev);
+    else
+        hipLaunchKernelGGL((k_rs_scatter<false, false>), dim3((unsigned)ntiles), dim3(RS_THREADS), 0,
+                           s, kin, nullptr, kout, nullptr, n, shift, ntiles, off, n_dev);
+    MJ_LAUNCH_CHECK();
+}
+
+void group_members(const uint64_t *key, const uint64_t *val, int64_t n, const int64_t *n_dev,
+                   uint64_t *mkey, uint64_t *mval, int64_t mcap, int64_t *m_dev, uint32_t big,
+                   Workspace &ws, hipStream_t s) {
+    if (big < 1) throw Error(MJ_EINVAL, "member filter bucket limit must be >= 1");
+    if (n > 0xFFFFFFF0LL) throw Error(MJ_ECAPACITY, "member filter of more than 2^32 records");
+    if (n <= 0) {
+        fill_u64(reinterpret_cast<uint64_t *>(m_dev), 0, 1, s);
+        return;
+    }
+    const int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+    if (ntiles > 0x7FFFFFFFLL || 256 * ntiles > 0xFFFFFFF0LL)
+        throw Error(MJ_ECAPACITY, "member filter: too many tiles");
+    uint64_t *w1 = ws.get_n<uint64_t>(n + 1);
+    uint64_t *w2 = ws.get_n<uint64_t>(n + 1);
+    mb_radix_pass(key, w1, n, 48, true, ws, s, n_dev);
+    mb_radix_pass(w1, w2, n, 56, false, ws, s, n_dev);
+    uint8_t *flags = ws.get_n<uint8_t>(n + 16);
+    uint32_t *bs = ws.get_n<uint32_t>(MB_BUCKETS + 1);
+    hipLaunchKernelGGL(k_mb_bounds, dim3(grid_for(std::max<int64_t>(n, MB_BUCKETS + 1), 256, 16384)),
+                       dim3(256), 0, s, w2, n, n_dev, bs, flags);
+    MJ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mb_flags, dim3(MB_BUCKETS), dim3(256), 0, s, w2, bs, big, flags);
+    MJ_LAUNCH_CHECK();
+    int64_t *idx = ws.get_n<int64_t>(n + 1);
+    const uint32_t *count = compact_flags_async(flags, n, idx, ws, s);
+    hipLaunchKernelGGL(k_mb_gather, dim3(grid_for((std::min(n, mcap) + MB_GATHER - 1) / MB_GATHER, 256, 16384)),
+                       dim3(256), 0, s, idx, count, w2, key, val, mkey, mval, mcap, m_dev);
+    MJ_LAUNCH_CHECK();
 }
 
 }  // namespace mj

@@ -551,6 +551,34 @@ def test_captured_join_identical(mj, name):
     ctx.close()
 
 
+@pytest.mark.parametrize("bucket_limit", [0, 1])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_member_filter_identical(mj, name, bucket_limit):
+    """The member filter forced on (every join; with bucket_limit 1 every bucket of two or
+    more records is kept whole): candidates and output equal the oracle's, stage by stage
+    and streamed, with the same groups and pair tests as without the filter."""
+    say("member filter", name, bucket_limit)
+    S, op, gp = run_case(mj, name)
+    cand_w, out_w, _ = oracle.join(S.chars, S.offsets, op)
+    ds = dev(mj, S)
+    ctx0 = mj.Context()
+    ctx0.set_member_filter(-1)
+    _, st0 = mj.join(ds, gp, ctx=ctx0)
+    assert st0["member_filter"] == 0 and st0["members"] == st0["records"]
+    ctx0.close()
+    ctx = mj.Context()
+    ctx.set_member_filter(0, bucket_limit)
+    cand, stc = mj.candidates(ds, gp, ctx=ctx)
+    assert np.array_equal(cand, cand_w) and stc["member_filter"] == 1
+    for streamed in (0, 1):
+        out, st = mj.join(ds, gp, ctx=ctx)
+        assert np.array_equal(out, out_w)
+        assert st["streamed"] == streamed and st["member_filter"] == 1
+        assert st["groups"] == st0["groups"] and st["pair_tests"] == st0["pair_tests"]
+        assert st["records"] == st0["records"] and st["members"] <= st["records"]
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["dna_heavy_clusters", "protein_per_string_K"])
 def test_join_in_emission_passes(mj, name):
     """A join whose record-pair tests exceed one emission pass (here forced down to 1,024
