@@ -41,14 +41,14 @@ __global__ void k_prepare(const int64_t *off, int32_t n, int q, int64_t kuni, co
                           uint32_t *halo, uint32_t *err, unsigned long long *rec_bound,
                           uint32_t *kmax, int32_t *wide_ids, int32_t *wide_r, uint32_t *wide_count,
                           unsigned long long *wide_pos) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t hr = 0;  // this string's contribution to the halo
+    uint32_t hr = 0;  // the strings' contribution to the halo
     // and to the bound on the partitions of one repetition: interior anchors are strict
     // minima of radius r, so two of them are more than r apart, and a string of npos q-gram
     // starts has at most npos / (r + 1) + 2 partitions (one for m < q, none for m = 0)
     unsigned long long bnd = 0;
     uint32_t km = 0;
-    if (i < n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         int64_t m = off[i + 1] - off[i];
         int64_t K = kuni >= 0 ? kuni : (int64_t)kps[i];
         if (m < 0 || m > 0x7FFFFFFFLL) atomicOr(err, 1u);
@@ -65,20 +65,21 @@ __global__ void k_prepare(const int64_t *off, int32_t n, int q, int64_t kuni, co
             if (r > WIDE_R) {
                 wide = true;
                 const uint32_t w = atomicAdd(wide_count, 1u);
-                wide_ids[w] = i;
+                wide_ids[w] = (int32_t)i;
                 wide_r[w] = (int32_t)r;
                 atomicAdd(wide_pos, (unsigned long long)npos);
             } else {
-                hr = (uint32_t)r;
+                hr = max(hr, (uint32_t)r);
             }
         }
         len[i] = (int32_t)m;
         kk[i] = (int32_t)(K < 0 ? 0 : K);
         rr[i] = wide ? WIDE_SENTINEL : (int32_t)std::min<int64_t>(r, 0x7FFFFFFFLL);
-        if (m > 0) bnd = npos <= 0 ? 1ull : (unsigned long long)(npos / (r + 1) + 2);
-        km = (uint32_t)(K < 0 ? 0 : K);
+        if (m > 0) bnd += npos <= 0 ? 1ull : (unsigned long long)(npos / (r + 1) + 2);
+        km = max(km, (uint32_t)(K < 0 ? 0 : K));
     }
-    // one atomic per wave: device-scope atomics on one address serialise
+    // one atomic per workgroup: device-scope atomics on one address serialise (a wave each
+    // took 0.17 ms for 300,000 strings)
     for (int d = 32; d >= 1; d >>= 1) {
         hr = max(hr, (uint32_t)__shfl_xor((int)hr, d, 64));
         km = max(km, (uint32_t)__shfl_xor((int)km, d, 64));
@@ -86,7 +87,21 @@ __global__ void k_prepare(const int64_t *off, int32_t n, int q, int64_t kuni, co
         const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(bnd >> 32), d, 64);
         bnd += ((unsigned long long)hi << 32) | lo;
     }
+    __shared__ uint32_t s_hr[4], s_km[4];
+    __shared__ unsigned long long s_bnd[4];
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        s_hr[wv] = hr;
+        s_km[wv] = km;
+        s_bnd[wv] = bnd;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) {
+            hr = max(hr, s_hr[w]);
+            km = max(km, s_km[w]);
+            bnd += s_bnd[w];
+        }
         if (hr) atomicMax(halo, hr);
         if (km) atomicMax(kmax, km);
         if (bnd) atomicAdd(rec_bound, bnd);
@@ -106,8 +121,9 @@ void prepare_launch(DevStrings &d, const PartitionParams &p, Workspace &ws, hipS
     uint32_t *flags = ws.get_n<uint32_t>(8);
     fill_u32(flags, 0, 8, s);
     if (n > 0) {
-        hipLaunchKernelGGL(k_prepare, dim3((n + 255) / 256), dim3(256), 0, s, d.offsets, n, p.q,
-                           p.k, p.k_per_string, p.t_div, p.t_fixed, d.len, d.kk, d.rr, flags,
+        const unsigned grid = (unsigned)std::min<int64_t>(((int64_t)n + 255) / 256, 128);
+        hipLaunchKernelGGL(k_prepare, dim3(grid), dim3(256), 0, s, d.offsets, n, p.q, p.k,
+                           p.k_per_string, p.t_div, p.t_fixed, d.len, d.kk, d.rr, flags,
                            flags + 1, reinterpret_cast<unsigned long long *>(flags + 2), flags + 4,
                            d.wide_ids, d.wide_r, flags + 5,
                            reinterpret_cast<unsigned long long *>(flags + 6));
@@ -369,9 +385,17 @@ __global__ void k_tile_desc(const int64_t *__restrict__ off, const int32_t *__re
     td[t] = d;
 }
 
-// V = uint64_t: the hash itself (Pi, or the injected table); V = uint32_t: its rank from
-// `rank` (code spaces of at most RANK_MAX_BITS bits), staged in LDS.
-template <int REGION, typename V>
+// Pi of a q-gram code: the injected table's entry (TABLE), else SplitMix64 of code ^ salt.
+template <bool TABLE>
+__device__ __forceinline__ uint64_t pi_of(uint64_t G, uint64_t salt, const uint64_t *table) {
+    if constexpr (TABLE) return table[G];
+    else return mix64(G ^ salt);
+}
+
+// V = uint64_t: the hash itself (Pi, or the injected table when TABLE); V = uint32_t: its
+// rank from `rank` (code spaces of at most RANK_MAX_BITS bits), staged in LDS.  TABLE is a
+// template parameter so that the hashing loop has no branch per position.
+template <int REGION, typename V, bool TABLE>
 __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     const uint8_t *__restrict__ chars, const int64_t *__restrict__ off, int32_t n, int64_t total,
     int q, int bits, uint64_t salt, const uint64_t *__restrict__ table,
@@ -568,7 +592,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             for (int j = 0; j < RUN; j++) {
                 V h;
                 if constexpr (RANKED) h = rank_s[G];
-                else h = table ? table[G] : mix64((uint64_t)G ^ salt);
+                else h = pi_of<TABLE>((uint64_t)G, salt, table);
                 if constexpr (TWO) {
                     const bool in2 = j >= jb;
                     const int32_t i = in2 ? j - jb : i0 + j;
@@ -673,7 +697,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                         }
                         have_end = send;
                         if constexpr (RANKED) h = rank_s[G];
-                        else h = table ? table[G] : mix64(G ^ salt);
+                        else h = pi_of<TABLE>(G, salt, table);
                     } else {
                         have_end = -1;
                     }
@@ -703,7 +727,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         uint64_t G = 0;
         for (int k = 0; k < q; k++) G = (G << bits) | ch[sh + idx + k];
         G &= gmask;
-        return table ? table[G] : mix64(G ^ salt);
+        return pi_of<TABLE>(G, salt, table);
     };
     (void)exact64;
     // ---- window test.  Blocks of B = 2^k positions with B - 1 <= every interior radius of
@@ -1288,15 +1312,17 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
                                p.pi_table, rank);
             MJ_LAUNCH_CHECK();
         }
-#define MJ_ANCHORS(R, V)                                                                        \
-        hipLaunchKernelGGL((k_anchor_tiles<R, V>), dim3((unsigned)ntiles), dim3(AT_THREADS), rank_lds, s, \
+#define MJ_ANCHORS(R, V, T)                                                                     \
+        hipLaunchKernelGGL((k_anchor_tiles<R, V, T>), dim3((unsigned)ntiles), dim3(AT_THREADS), rank_lds, s, \
                            d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, rank, \
                            d.rr, TP, H, ts, aligned4, packed, bitmap[rho], tcount[rho])
         const size_t rank_lds = rank ? ((size_t)2 << code_bits) + 16 : 0;
         if (rank) {
-            if (region == 2048) MJ_ANCHORS(2048, uint32_t); else MJ_ANCHORS(4096, uint32_t);
+            if (region == 2048) MJ_ANCHORS(2048, uint32_t, false); else MJ_ANCHORS(4096, uint32_t, false);
+        } else if (p.pi_table) {
+            if (region == 2048) MJ_ANCHORS(2048, uint64_t, true); else MJ_ANCHORS(4096, uint64_t, true);
         } else {
-            if (region == 2048) MJ_ANCHORS(2048, uint64_t); else MJ_ANCHORS(4096, uint64_t);
+            if (region == 2048) MJ_ANCHORS(2048, uint64_t, false); else MJ_ANCHORS(4096, uint64_t, false);
         }
 #undef MJ_ANCHORS
         MJ_LAUNCH_CHECK();
@@ -1429,14 +1455,16 @@ int64_t partition_records_streamed(const DevStrings &d, const PartitionParams &p
             MJ_LAUNCH_CHECK();
         }
         const size_t rank_lds = rank ? ((size_t)2 << code_bits) + 16 : 0;
-#define MJ_ANCHORS(R, V)                                                                        \
-        hipLaunchKernelGGL((k_anchor_tiles<R, V>), dim3((unsigned)ntiles), dim3(AT_THREADS), rank_lds, s, \
+#define MJ_ANCHORS(R, V, T)                                                                     \
+        hipLaunchKernelGGL((k_anchor_tiles<R, V, T>), dim3((unsigned)ntiles), dim3(AT_THREADS), rank_lds, s, \
                            d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, rank, \
                            d.rr, TP, H, ts, aligned4, packed, bitmap[rho], tcount[rho])
         if (rank) {
-            if (region == 2048) MJ_ANCHORS(2048, uint32_t); else MJ_ANCHORS(4096, uint32_t);
+            if (region == 2048) MJ_ANCHORS(2048, uint32_t, false); else MJ_ANCHORS(4096, uint32_t, false);
+        } else if (p.pi_table) {
+            if (region == 2048) MJ_ANCHORS(2048, uint64_t, true); else MJ_ANCHORS(4096, uint64_t, true);
         } else {
-            if (region == 2048) MJ_ANCHORS(2048, uint64_t); else MJ_ANCHORS(4096, uint64_t);
+            if (region == 2048) MJ_ANCHORS(2048, uint64_t, false); else MJ_ANCHORS(4096, uint64_t, false);
         }
 #undef MJ_ANCHORS
         MJ_LAUNCH_CHECK();
