@@ -87,8 +87,10 @@ typedef struct {
  *   verify_lanes  batched verifier only: 0 lets the context time the choices (the
  *            default); 1, 2, 4 or 8 fixes the lanes per pair that split the band words;
  *            -2 fixes two lanes per pair that split the text columns (one runs forward
- *            over the first half, the other over the reversed second half).  A fixed
- *            choice whose lanes cannot hold the band fails with MJ_ECAPACITY. */
+ *            over the first half, the other over the reversed second half); -3 sizes each
+ *            pair's window by its own band class (2, 4, 8, 16 or 32 words on 1, 1, 2, 4
+ *            or 8 lanes; widest classes first), for per-pair K (bands up to K = 992).  A
+ *            fixed choice whose lanes cannot hold the band fails with MJ_ECAPACITY. */
 typedef struct {
     int32_t q;
     int32_t t_div;
@@ -125,7 +127,8 @@ typedef struct {
     int32_t kernel_launches[4];
     int64_t positions;   /* symbols scanned by the anchor kernel, over all repetitions */
     int32_t verify_group;  /* lanes per pair of the batched verifier (0: plain; -2: two
-                              lanes splitting the text columns, forward and reversed) */
+                              lanes splitting the text columns, forward and reversed; -3:
+                              per-pair band classes) */
     int32_t verify_words;  /* band words per lane of the batched verifier */
     int32_t verify_blocks; /* most workgroups the batched verifier's persistent launch may
                               have (fewer when the pairs need fewer) */

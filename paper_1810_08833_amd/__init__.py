@@ -341,7 +341,8 @@ class Params:
     seed: int = 0
     pi_table: Optional[object] = None       # torch uint64/int64 tensor on the GPU
     verifier: int = VERIFY_BATCHED          # or VERIFY_PLAIN
-    verify_lanes: int = 0                   # batched: 0 timed; 1/2/4/8 word split; -2 column split
+    verify_lanes: int = 0                   # batched: 0 timed; 1/2/4/8 word split; -2 column
+                                            # split; -3 band classes (window per pair)
 
     def struct(self) -> MjParams:
         p = MjParams()

@@ -112,12 +112,28 @@ static int ceil_log2(uint64_t v) {
     return b;
 }
 
+// The verify_lanes / verify_group code of a batched configuration: lanes per pair, -2 for
+// the column split, -3 for the band classes.
+static int lanes_code(int g) {
+    return g == VERIFY_BIDIR ? -2 : g == VERIFY_CLASSES ? -3 : g;
+}
+
+// Band words per lane of configuration g for a band of cmax words (the window holds
+// cmax + 1), 0 when it cannot hold it; the band classes give their widest class's 4.
+static int window_words_per_lane(int g, int cmax) {
+    if (g == VERIFY_CLASSES) return cmax + 1 <= 32 ? 4 : 0;
+    for (int v : {1, 2, 3, 4, 5, 6, 7, 8, 9, 11})
+        if (v * (g == VERIFY_BIDIR ? 1 : g) >= cmax + 1) return v;
+    return 0;
+}
+
 static void check_verifier(const mj_params *p) {
     if (p->verifier != MJ_VERIFY_BATCHED && p->verifier != MJ_VERIFY_PLAIN)
         throw Error(MJ_EINVAL, "verifier must be MJ_VERIFY_BATCHED or MJ_VERIFY_PLAIN");
     if (p->verify_lanes != 0 && p->verify_lanes != 1 && p->verify_lanes != 2 &&
-        p->verify_lanes != 4 && p->verify_lanes != 8 && p->verify_lanes != -2)
-        throw Error(MJ_EINVAL, "verify_lanes must be 0, 1, 2, 4, 8 or -2");
+        p->verify_lanes != 4 && p->verify_lanes != 8 && p->verify_lanes != -2 &&
+        p->verify_lanes != -3)
+        throw Error(MJ_EINVAL, "verify_lanes must be 0, 1, 2, 4, 8, -2 or -3");
 }
 
 static void check_params(const mj_params *p, int sigma, bool need_k) {
@@ -239,7 +255,7 @@ static void run_verify(mj_ctx *ctx, const uint64_t *pairs, int64_t n, const DevS
                              ctx->no_tuning ? nullptr : &ctx->tune, uniform_k, cells_h,
                              p->verify_lanes);
         if (stats) {
-            stats->verify_group = ctx->tune.last_g == VERIFY_BIDIR ? -2 : ctx->tune.last_g;
+            stats->verify_group = lanes_code(ctx->tune.last_g);
             stats->verify_words = ctx->tune.last_nwl;
             stats->verify_blocks = ctx->tune.last_blocks;
         }
@@ -440,11 +456,10 @@ static bool plan_streamed(mj_ctx *ctx, const mj_params *params, const DevStrings
     const int np = verify_planes(d.bits);
     // the configuration the last join used (the small-call one if it verified nothing)
     const int g = params->verify_lanes == -2 ? VERIFY_BIDIR
+                : params->verify_lanes == -3 ? VERIFY_CLASSES
                 : params->verify_lanes ? params->verify_lanes
                 : h.verify_g ? h.verify_g : verify_small_call_lanes(pl.cmax);
-    int nwl = 0;
-    for (int v : {1, 2, 3, 4, 5, 6, 7, 8, 9, 11})
-        if (v * (g == VERIFY_BIDIR ? 1 : g) >= pl.cmax + 1) { nwl = v; break; }
+    const int nwl = window_words_per_lane(g, pl.cmax);
     if (g == 0 || nwl == 0) return false;  // no configuration for this band: stage by stage
     const int ci = std::min(pl.cmax, 63);
     ctx->tune.best_g[ci][np / 2 - 1] = g;
@@ -549,9 +564,8 @@ static mj_pairs *finish_streamed(mj_ctx *ctx, const StreamedPlan &pl, const Stre
         stats->positions = d.total * pp.reps;
         const int ci = std::min(pl.cmax, 63), npi = verify_planes(d.bits) / 2 - 1;
         const int gg = ctx->tune.best_g[ci][npi];
-        stats->verify_group = gg == VERIFY_BIDIR ? -2 : gg;
-        for (int v : {1, 2, 3, 4, 5, 6, 7, 8, 9, 11})
-            if (v * (gg == VERIFY_BIDIR ? 1 : gg) >= pl.cmax + 1) { stats->verify_words = v; break; }
+        stats->verify_group = lanes_code(gg);
+        stats->verify_words = window_words_per_lane(gg, pl.cmax);
         stats->verify_blocks = ctx->tune.best_blocks[ci][npi];
         stats->streamed = 1;
         stats->host_reads = 2;

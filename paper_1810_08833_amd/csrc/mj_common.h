@@ -350,8 +350,10 @@ int verify_planes(int bits);   // planes the verifier needs for b bits per symbo
 // verify_lg.hip: one persistent launch for all pairs (lane groups, longest first).
 // The lane-group width is timed once per (ceil(Kmax/32), planes) and kept in `tune`.
 // VerifyTuning::last_g value of the kernel that splits each pair's text columns over two
-// lanes (forward and reversed halves)
+// lanes (forward and reversed halves), and of the launch that sizes each pair's window by
+// its band class
 constexpr int VERIFY_BIDIR = 3;
+constexpr int VERIFY_CLASSES = 5;
 struct VerifyTuning {
     int best_g[64][4] = {};
     int best_blocks[64][4] = {};

@@ -68,15 +68,13 @@ __device__ __forceinline__ int gshfl_xor(int v, int d) {
 constexpr int QUEUES = 32;
 constexpr int QSTRIDE = 64;  // uint64 words between two sub-queue counters (512 bytes)
 
+// The pairs order[0 .. n) with lane groups of G lanes and NWL window words per lane, taken
+// from the sub-queues whose counters `next` holds; returns when every sub-queue is dry.
 template <int NWL, int G, int NP>
-__global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restrict__ pairs,
-                                                        const int64_t *__restrict__ order,
-                                                        int64_t n, VSet A, VSet B, int kmode,
-                                                        uint8_t *__restrict__ flags,
-                                                        unsigned long long *cells,
-                                                        unsigned long long *next,
-                                                        const uint32_t *__restrict__ ndev) {
-    if (ndev) n = min(n, (int64_t)*ndev);  // the pair count on the device (n: its capacity)
+__device__ __forceinline__ void persist_body(const uint64_t *__restrict__ pairs,
+                                             const int64_t *__restrict__ order, int64_t n, VSet A,
+                                             VSet B, int kmode, uint8_t *__restrict__ flags,
+                                             unsigned long long *cells, unsigned long long *next) {
     constexpr int NW = NWL * G;
     const int lane = threadIdx.x & 63;
     const int g = lane & (G - 1);
@@ -369,6 +367,18 @@ __global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restri
         my_cells += ((uint64_t)hi << 32) | lo;
     }
     if (lane == 0 && my_cells) atomicAdd(cells, (unsigned long long)my_cells);
+}
+
+template <int NWL, int G, int NP>
+__global__ __launch_bounds__(256) void k_verify_persist(const uint64_t *__restrict__ pairs,
+                                                        const int64_t *__restrict__ order,
+                                                        int64_t n, VSet A, VSet B, int kmode,
+                                                        uint8_t *__restrict__ flags,
+                                                        unsigned long long *cells,
+                                                        unsigned long long *next,
+                                                        const uint32_t *__restrict__ ndev) {
+    if (ndev) n = min(n, (int64_t)*ndev);  // the pair count on the device (n: its capacity)
+    persist_body<NWL, G, NP>(pairs, order, n, A, B, kmode, flags, cells, next);
 }
 
 // ---------------------------------------------------------------- split by columns
@@ -732,11 +742,16 @@ __global__ __launch_bounds__(256) void k_verify_bidir(const uint64_t *__restrict
 using PersistKernel = void (*)(const uint64_t *, const int64_t *, int64_t, VSet, VSet, int,
                                uint8_t *, unsigned long long *, unsigned long long *,
                                const uint32_t *);
+using PersistClassKernel = void (*)(const uint64_t *, const int64_t *, const uint32_t *, VSet, VSet,
+                                    int, uint8_t *, unsigned long long *, unsigned long long *);
+constexpr int VCLS_NW_MAX = 32;  // the widest band class's window words
 
 constexpr int NWL_CHOICES[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 11};
-// g == BIDIR: two lanes per pair, split by columns (each lane holds the whole window)
+// g == BIDIR: two lanes per pair, split by columns (each lane holds the whole window);
+// g == CLASSES: lanes per pair and window chosen per pair by its band class
 constexpr int BIDIR = VERIFY_BIDIR;
-constexpr int G_CHOICES[] = {1, 2, BIDIR, 4, 8};
+constexpr int CLASSES = VERIFY_CLASSES;
+constexpr int G_CHOICES[] = {1, 2, BIDIR, 4, 8, CLASSES};
 
 template <int NWL, int G>
 static PersistKernel by_np(int np) {
@@ -800,8 +815,10 @@ static PersistKernel persist_kernel(int nwl, int g, int np) {
     }
 }
 
-// smallest supported NWL with NWL * G >= nw (the whole window per lane for BIDIR), or 0
+// smallest supported NWL with NWL * G >= nw (the whole window per lane for BIDIR), or 0;
+// for CLASSES 4 (the widest class's words per lane) when the widest class holds nw words
 static int nwl_for(int nw, int g) {
+    if (g == CLASSES) return nw <= VCLS_NW_MAX ? 4 : 0;
     const int lanes = g == BIDIR ? 1 : g;
     for (int v : NWL_CHOICES)
         if (v * lanes >= nw) return v;
@@ -817,7 +834,8 @@ int verify_small_call_lanes(int cmax) {
     const int nw = cmax + 1;
     int best = 0;
     for (int g : G_CHOICES)
-        if (g != BIDIR && nwl_for(nw, g) != 0 && (g == 1 || nwl_for(nw, g / 2) > 1)) best = g;
+        if (g != BIDIR && g != CLASSES && nwl_for(nw, g) != 0 && (g == 1 || nwl_for(nw, g / 2) > 1))
+            best = g;
     return best;
 }
 
@@ -846,20 +864,42 @@ __global__ void k_pair_cmax(const uint64_t *pairs, int64_t n, VSet A, VSet B, in
     if ((threadIdx.x & 63) == 0) atomicMax(cmax, m);
 }
 
-__device__ __forceinline__ int lpt_bin(const uint64_t pr, const VSet &A, const VSet &B) {
-    int32_t nt = min(A.len[(uint32_t)(pr >> 32)], B.len[(uint32_t)pr]);
-    return LPT_BINS - 1 - min(nt >> 4, LPT_BINS - 1);  // longest first
+// Band classes: windows of 2, 4, 8, 16 and 32 words (2 words on one lane, 4 on one, then
+// 4 words per lane on 2, 4 and 8 lanes).  A pair's class is the smallest whose window
+// holds its band, ceil(K/32) + 1 words.  (Eight classes, adding 3-word lanes for windows
+// of 3, 6 and 12 words, made the launch slower: 1.54 against 1.44 ms on protein.)
+constexpr int VCLS = 5;
+constexpr int VCLS_NW[VCLS] = {2, 4, 8, 16, 32};
+constexpr int VCLS_BINS = 512;  // length bins per class
+static_assert(VCLS * VCLS_BINS <= LPT_BINS, "class bins");
+static_assert(VCLS_NW[VCLS - 1] == VCLS_NW_MAX, "widest class");
+
+__device__ __forceinline__ int pair_class(int32_t K) {
+    const int nw = ((K + 31) >> 5) + 1;
+    int c = 0;
+    while (c + 1 < VCLS && VCLS_NW[c] < nw) c++;
+    return c;
 }
 
-__global__ void k_lpt_hist(const uint64_t *pairs, int64_t n, VSet A, VSet B, uint32_t *cnt,
-                           const uint32_t *ndev) {
+// The bin of a pair: longest first, or (classes) widest class first, then longest first.
+__device__ __forceinline__ int lpt_bin(const uint64_t pr, const VSet &A, const VSet &B, int kmode,
+                                       int classes) {
+    const uint32_t ia = (uint32_t)(pr >> 32), ib = (uint32_t)pr;
+    int32_t nt = min(A.len[ia], B.len[ib]);
+    if (!classes) return LPT_BINS - 1 - min(nt >> 4, LPT_BINS - 1);
+    const int32_t K = kmode == 0 ? max(A.kk[ia], B.kk[ib]) : A.kk[ia];
+    return (VCLS - 1 - pair_class(K)) * VCLS_BINS + VCLS_BINS - 1 - min(nt >> 4, VCLS_BINS - 1);
+}
+
+__global__ void k_lpt_hist(const uint64_t *pairs, int64_t n, VSet A, VSet B, int kmode,
+                           int classes, uint32_t *cnt, const uint32_t *ndev) {
     if (ndev) n = min(n, (int64_t)*ndev);
     __shared__ uint32_t h[LPT_BINS];
     for (int t = threadIdx.x; t < LPT_BINS; t += blockDim.x) h[t] = 0;
     __syncthreads();
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) atomicAdd(&h[lpt_bin(pairs[i], A, B)], 1u);
+    for (; i < n; i += stride) atomicAdd(&h[lpt_bin(pairs[i], A, B, kmode, classes)], 1u);
     __syncthreads();
     for (int t = threadIdx.x; t < LPT_BINS; t += blockDim.x)
         if (h[t]) atomicAdd(&cnt[t], h[t]);
@@ -870,7 +910,8 @@ __global__ void k_lpt_hist(const uint64_t *pairs, int64_t n, VSet A, VSet B, uin
 // a few bins, so per-pair global atomics would serialise on them).
 constexpr int LPT_ITEMS = 16;
 __global__ __launch_bounds__(256) void k_lpt_scatter(const uint64_t *pairs, int64_t n, VSet A,
-                                                     VSet B, const uint32_t *off, uint32_t *fill,
+                                                     VSet B, int kmode, int classes,
+                                                     const uint32_t *off, uint32_t *fill,
                                                      int64_t *order, const uint32_t *ndev) {
     if (ndev) n = min(n, (int64_t)*ndev);
     __shared__ uint32_t cnt[LPT_BINS];
@@ -886,7 +927,7 @@ __global__ __launch_bounds__(256) void k_lpt_scatter(const uint64_t *pairs, int6
         bin[k] = 0;
         rank[k] = 0;
         if (i < n) {
-            bin[k] = lpt_bin(pairs[i], A, B);
+            bin[k] = lpt_bin(pairs[i], A, B, kmode, classes);
             rank[k] = atomicAdd(&cnt[bin[k]], 1u);
         }
     }
@@ -901,17 +942,78 @@ __global__ __launch_bounds__(256) void k_lpt_scatter(const uint64_t *pairs, int6
     }
 }
 
+// One persistent launch over band classes: a wave takes the pairs of the widest class
+// first (with that class's lanes per pair and window) and moves to the next narrower class
+// when the current one is dry, so each pair's window fits its own band instead of the
+// widest band of the call.  The order holds the classes from the widest down, each
+// longest first; off[] (the bin offsets of that order) gives each class's range.
+template <int NP>
+__global__ __launch_bounds__(256) void k_verify_classes(const uint64_t *__restrict__ pairs,
+                                                        const int64_t *__restrict__ order,
+                                                        const uint32_t *__restrict__ off, VSet A,
+                                                        VSet B, int kmode,
+                                                        uint8_t *__restrict__ flags,
+                                                        unsigned long long *cells,
+                                                        unsigned long long *next) {
+    for (int c = VCLS - 1; c >= 0; c--) {
+        const int b0 = (VCLS - 1 - c) * VCLS_BINS;
+        const int64_t base = off[b0], cnt = (int64_t)off[b0 + VCLS_BINS] - base;
+        if (cnt <= 0) continue;
+        unsigned long long *nx = next + (int64_t)c * QUEUES * QSTRIDE;
+        const int64_t *oc = order + base;
+        switch (c) {
+            case 0: persist_body<2, 1, NP>(pairs, oc, cnt, A, B, kmode, flags, cells, nx); break;
+            case 1: persist_body<4, 1, NP>(pairs, oc, cnt, A, B, kmode, flags, cells, nx); break;
+            case 2: persist_body<4, 2, NP>(pairs, oc, cnt, A, B, kmode, flags, cells, nx); break;
+            case 3: persist_body<4, 4, NP>(pairs, oc, cnt, A, B, kmode, flags, cells, nx); break;
+            default: persist_body<4, 8, NP>(pairs, oc, cnt, A, B, kmode, flags, cells, nx); break;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
+// The pairs in bin order (longest first; class-major when classes) and the bins' offsets
+// off[0 .. LPT_BINS]; cnt and fill (LPT_BINS + 4 words each) must be zero.
+static void build_order(const uint64_t *pairs, int64_t n, const VSet &va, const VSet &vb,
+                        int kmode, int classes, uint32_t *cnt, uint32_t *fill, uint32_t *off,
+                        int64_t *order, Workspace &ws, hipStream_t s, const uint32_t *ndev) {
+    hipLaunchKernelGGL(k_lpt_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, pairs, n, va, vb,
+                       kmode, classes, cnt, ndev);
+    MJ_LAUNCH_CHECK();
+    exclusive_scan_u32(cnt, off, LPT_BINS, ws, s);
+    const int64_t sblocks = (n + 256 * LPT_ITEMS - 1) / (256 * LPT_ITEMS);
+    if (sblocks > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many pairs for one verification");
+    hipLaunchKernelGGL(k_lpt_scatter, dim3((unsigned)sblocks), dim3(256), 0, s, pairs, n, va, vb,
+                       kmode, classes, off, fill, order, ndev);
+    MJ_LAUNCH_CHECK();
+}
+
+static PersistClassKernel classes_kernel(int np) {
+    switch (np) {
+        case 2: return k_verify_classes<2>;
+        case 4: return k_verify_classes<4>;
+        case 6: return k_verify_classes<6>;
+        default: return k_verify_classes<8>;
+    }
+}
+
+// order / off: the longest-first order and its bin offsets (class-major for CLASSES)
 static void launch_persist(int nwl, int g, int np, int max_blocks, const uint64_t *pairs,
                            const int64_t *order, int64_t n, const VSet &va, const VSet &vb,
                            int kmode, uint8_t *flags, unsigned long long *cells,
                            unsigned long long *next, hipStream_t s, bool next_zero = false,
-                           const uint32_t *ndev = nullptr) {
-    if (!next_zero) fill_u64((uint64_t *)next, 0, QUEUES * QSTRIDE, s);
+                           const uint32_t *ndev = nullptr, const uint32_t *off = nullptr) {
+    if (!next_zero) fill_u64((uint64_t *)next, 0, (int64_t)VCLS * QUEUES * QSTRIDE, s);
     // at most max_blocks resident workgroups, and no more than the pairs need
-    int64_t groups_per_block = 256 / (g == BIDIR ? 2 : g);
+    int64_t groups_per_block = 256 / (g == BIDIR ? 2 : g == CLASSES ? 1 : g);
     int64_t blocks = (n + groups_per_block - 1) / groups_per_block;
     blocks = std::min<int64_t>(blocks, max_blocks);
+    if (g == CLASSES) {
+        hipLaunchKernelGGL(classes_kernel(np), dim3((unsigned)std::max<int64_t>(blocks, 1)),
+                           dim3(256), 0, s, pairs, order, off, va, vb, kmode, flags, cells, next);
+        MJ_LAUNCH_CHECK();
+        return;
+    }
     hipLaunchKernelGGL(persist_kernel(nwl, g, np), dim3((unsigned)std::max<int64_t>(blocks, 1)),
                        dim3(256), 0, s, pairs, order, n, va, vb, kmode, flags, cells, next, ndev);
     MJ_LAUNCH_CHECK();
@@ -926,20 +1028,31 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     if (A.planes == nullptr || B.planes == nullptr) throw Error(MJ_EINVAL, "strings not packed");
     const int np = verify_planes(std::max(A.bits, B.bits));
     VSet va = vset(A), vb = vset(B);
-    // one block cleared by one launch: the sub-queue counters, the band-cell counter, the
-    // K pass's two words and the two length-bin counter arrays
-    constexpr int64_t ZNEXT = 2 * QUEUES * QSTRIDE, ZCNT = LPT_BINS + 4;
-    uint32_t *zb = ws.get_n<uint32_t>(ZNEXT + 4 + 4 + 2 * ZCNT);
+    // one block cleared by one launch: the sub-queue counters (one set per band class), the
+    // band-cell counter, the K pass's two words and two pairs of length-bin counter arrays
+    // (longest-first and class-major orders)
+    constexpr int64_t ZNEXT = 2 * VCLS * QUEUES * QSTRIDE, ZCNT = LPT_BINS + 4;
+    uint32_t *zb = ws.get_n<uint32_t>(ZNEXT + 4 + 4 + 4 * ZCNT);
     unsigned long long *next = (unsigned long long *)zb;
     unsigned long long *cells = (unsigned long long *)(zb + ZNEXT);
     uint32_t *cm = zb + ZNEXT + 4;
     // longest pairs first
     uint32_t *cnt = zb + ZNEXT + 8;
     uint32_t *fillc = cnt + ZCNT;
-    fill_u32(zb, 0, ZNEXT + 8 + 2 * ZCNT, s);
+    fill_u32(zb, 0, ZNEXT + 8 + 4 * ZCNT, s);
     bool next_zero = true;
     uint32_t *off = ws.get_n<uint32_t>(LPT_BINS + 1);
     int64_t *order = ws.get_n<int64_t>(n);
+    // the class-major order, built when the band classes are timed or chosen
+    uint32_t *off_c = nullptr;
+    int64_t *order_c = nullptr;
+    auto class_order = [&]() {
+        if (order_c) return;
+        off_c = ws.get_n<uint32_t>(LPT_BINS + 1);
+        order_c = ws.get_n<int64_t>(n);
+        build_order(pairs, n, va, vb, kmode, 1, fillc + ZCNT, fillc + 2 * ZCNT, off_c, order_c, ws,
+                    s, nullptr);
+    };
     int cmax;
     if (uniform_k >= 0) {
         // every pair's K is known (and its ids valid): no pass over the pairs
@@ -957,27 +1070,21 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
     }
     if (cmax > persist_max_c())
         throw Error(MJ_ECAPACITY, "threshold K above the batched verifier's band limit (K <= 2047)");
-    hipLaunchKernelGGL(k_lpt_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, pairs, n, va, vb, cnt,
-                       (const uint32_t *)nullptr);
-    MJ_LAUNCH_CHECK();
-    exclusive_scan_u32(cnt, off, LPT_BINS, ws, s);
-    const int64_t sblocks = (n + 256 * LPT_ITEMS - 1) / (256 * LPT_ITEMS);
-    if (sblocks > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many pairs for one verification");
-    hipLaunchKernelGGL(k_lpt_scatter, dim3((unsigned)sblocks), dim3(256), 0, s, pairs, n, va, vb,
-                       off, fillc, order, (const uint32_t *)nullptr);
-    MJ_LAUNCH_CHECK();
-
     const int nw = cmax + 1;
+    // band classes pay off only where the pairs' K differ
+    const bool classes_ok = uniform_k < 0 && nwl_for(nw, CLASSES) != 0;
     const int npi = np / 2 - 1;
     const int ci = std::min(cmax, 63);
     int best_g = tune ? tune->best_g[ci][npi] : 0;
     int best_blocks = tune ? tune->best_blocks[ci][npi] : 0;
     if (force_lanes != 0) {
-        best_g = force_lanes == -2 ? BIDIR : force_lanes;
+        best_g = force_lanes == -2 ? BIDIR : force_lanes == -3 ? CLASSES : force_lanes;
         best_blocks = 512;
         if (nwl_for(nw, best_g) == 0)
             throw Error(MJ_ECAPACITY, "verify_lanes: the lanes of a pair cannot hold this band");
     }
+    if (best_g == CLASSES) class_order();
+    else build_order(pairs, n, va, vb, kmode, 0, cnt, fillc, off, order, ws, s, nullptr);
     if (best_g == 0 && (n < TUNE_MIN_PAIRS || !tune)) {
         // a small call leaves most of the chip idle: the most lanes per pair (shortest
         // path per pair); timing the choices would cost more than the work.  Without a
@@ -998,15 +1105,17 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
         best_g = 0;
         for (int g : G_CHOICES) {
             int nwl = nwl_for(nw, g);
-            if (nwl == 0) continue;
+            if (nwl == 0 || (g == CLASSES && !classes_ok)) continue;
+            if (g == CLASSES) class_order();
             int step = 0;
             for (int mb : {256, 512, 768, 1024, 2048}) {
                 const float penalty = 1.0f + 0.03f * (float)step++;
                 float ms = 1e30f;
                 for (int rep = 0; rep < 2; rep++) {  // best of two: timing noise
                     MJ_HIP(hipEventRecord(e0, s));
-                    launch_persist(nwl, g, np, mb, pairs, order, n, va, vb, kmode, flags, cells, next, s,
-                                   next_zero);
+                    launch_persist(nwl, g, np, mb, pairs, g == CLASSES ? order_c : order, n, va, vb,
+                                   kmode, flags, cells, next, s, next_zero, nullptr,
+                                   g == CLASSES ? off_c : off);
                     next_zero = false;
                     MJ_HIP(hipEventRecord(e1, s));
                     MJ_HIP(hipEventSynchronize(e1));
@@ -1030,8 +1139,10 @@ int64_t verify_pairs_batched(const uint64_t *pairs, int64_t n, const DevStrings 
         fill_u64((uint64_t *)cells, 0, 1, s);
     }
     int th = kt ? kt->begin(KTimer::VERIFY, s) : -1;
-    launch_persist(nwl_for(nw, best_g), best_g, np, best_blocks, pairs, order, n, va, vb, kmode,
-                   flags, cells, next, s, next_zero);
+    if (best_g == CLASSES) class_order();
+    launch_persist(nwl_for(nw, best_g), best_g, np, best_blocks, pairs,
+                   best_g == CLASSES ? order_c : order, n, va, vb, kmode, flags, cells, next, s,
+                   next_zero, nullptr, best_g == CLASSES ? off_c : off);
     if (kt) kt->end(th, s);
     if (tune) {
         tune->last_g = best_g;
@@ -1065,7 +1176,7 @@ void verify_pairs_batched_streamed(const uint64_t *pairs, int64_t cap, const uin
     const int np = verify_planes(std::max(A.bits, B.bits));
     VSet va = vset(A), vb = vset(B);
     cap = std::max<int64_t>(cap, 1);
-    constexpr int64_t ZNEXT = 2 * QUEUES * QSTRIDE, ZCNT = LPT_BINS + 4;
+    constexpr int64_t ZNEXT = 2 * VCLS * QUEUES * QSTRIDE, ZCNT = LPT_BINS + 4;
     uint32_t *zb = ws.get_n<uint32_t>(ZNEXT + 4 + 4 + 2 * ZCNT);
     unsigned long long *next = (unsigned long long *)zb;
     unsigned long long *cells = (unsigned long long *)(zb + ZNEXT);
@@ -1078,28 +1189,20 @@ void verify_pairs_batched_streamed(const uint64_t *pairs, int64_t cap, const uin
     int64_t *order = ws.get_n<int64_t>(cap);
     if (cmax > persist_max_c())
         throw Error(MJ_ECAPACITY, "threshold K above the batched verifier's band limit (K <= 2047)");
-    hipLaunchKernelGGL(k_lpt_hist, dim3(grid_for(cap, 256, 1024)), dim3(256), 0, s, pairs, cap, va, vb,
-                       cnt, n_dev);
-    MJ_LAUNCH_CHECK();
-    exclusive_scan_u32(cnt, off, LPT_BINS, ws, s);
-    const int64_t sblocks = (cap + 256 * LPT_ITEMS - 1) / (256 * LPT_ITEMS);
-    if (sblocks > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many pairs for one verification");
-    hipLaunchKernelGGL(k_lpt_scatter, dim3((unsigned)sblocks), dim3(256), 0, s, pairs, cap, va, vb,
-                       off, fillc, order, n_dev);
-    MJ_LAUNCH_CHECK();
     const int nw = cmax + 1;
     const int npi = np / 2 - 1;
     const int ci = std::min(cmax, 63);
     int g = tune.best_g[ci][npi], blocks = tune.best_blocks[ci][npi];
     if (force_lanes != 0) {
-        g = force_lanes == -2 ? BIDIR : force_lanes;
+        g = force_lanes == -2 ? BIDIR : force_lanes == -3 ? CLASSES : force_lanes;
         blocks = 512;
     }
     if (g == 0 || nwl_for(nw, g) == 0)
         throw Error(MJ_EINVAL, "no verifier configuration for this band size");
+    build_order(pairs, cap, va, vb, kmode, g == CLASSES ? 1 : 0, cnt, fillc, off, order, ws, s, n_dev);
     int th = kt ? kt->begin(KTimer::VERIFY, s) : -1;
     launch_persist(nwl_for(nw, g), g, np, blocks, pairs, order, cap, va, vb, kmode, flags, cells, next,
-                   s, true, n_dev);
+                   s, true, n_dev, off);
     if (kt) kt->end(th, s);
 }
 

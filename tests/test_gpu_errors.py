@@ -64,6 +64,20 @@ def test_search_rejects_bad_verifier_arguments(mj):
     index.close()
 
 
+def test_band_classes_refuse_bands_wider_than_their_widest_window(mj):
+    """verify_lanes -3 holds bands of up to 32 window words (K <= 992): a call with K = 1500
+    fails with ECAPACITY; the same call with the timed layout verifies."""
+    say("band classes, K = 1500")
+    rng = np.random.default_rng(9)
+    x = rng.integers(0, 4, 3000).astype(np.uint8)
+    S = dg.from_list([x, dg.mutate(rng, x, 0.2, 4)], 4)
+    pairs = np.array([1], dtype=np.uint64)  # (0, 1)
+    p = mj.Params(q=4, k=1500, t_div=1, verify_lanes=-3)
+    assert status_of(lambda: mj.verify(dev(mj, S), p, pairs)) == mj.MJ_ECAPACITY
+    p.verify_lanes = 0
+    assert mj.verify(dev(mj, S), p, pairs).tolist() == [1]
+
+
 def test_out_of_range_symbols_are_rejected(mj):
     say("symbol codes >= sigma")
     S = dg.dna_small(seed=5, n_clusters=3, copies=3)

@@ -295,8 +295,11 @@ def test_verify_each_lane_layout_matches_banded_oracle(mj, K, lanes):
     assert 0 < want.sum() < len(want)
 
 
-@pytest.mark.parametrize("verifier", ["batched", "plain"])
+@pytest.mark.parametrize("verifier", ["batched", "plain", "classes"])
 def test_verify_per_pair_thresholds_across_bins(mj, verifier):
+    """Per-string K from 3 to 520 (band windows of 2 to 18 words): the batched verifier in
+    its small-call layout, the band classes (each pair in the window of its own class:
+    2, 4, 8, 16 or 32 words) and the plain verifier all decide like the oracle."""
     import torch
     say("verify mixed K bins", verifier)
     rng = np.random.default_rng(77)
@@ -313,11 +316,29 @@ def test_verify_per_pair_thresholds_across_bins(mj, verifier):
     S = dg.from_list(strs, 25)
     kq = np.array(ks, dtype=np.int32)
     pairs = np.array(pairs, dtype=np.uint64)
-    v = mj.VERIFY_BATCHED if verifier == "batched" else mj.VERIFY_PLAIN
-    got = mj.verify(dev(mj, S), mj.Params(q=3, k_per_string=torch.from_numpy(kq).cuda(), verifier=v),
-                    pairs)
+    v = mj.VERIFY_PLAIN if verifier == "plain" else mj.VERIFY_BATCHED
+    lanes = -3 if verifier == "classes" else 0
+    got = mj.verify(dev(mj, S), mj.Params(q=3, k_per_string=torch.from_numpy(kq).cuda(), verifier=v,
+                                          verify_lanes=lanes), pairs)
     want = oracle.verify_list(S.chars, S.offsets, oracle.make_params(3, 25, k_per_string=kq), pairs)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("name", ["protein_per_string_K", "dna_mixed_T_from_K"])
+def test_join_with_band_classes(mj, name):
+    """The batched verifier with the band classes fixed (verify_lanes -3), stage by stage and
+    streamed: the output equals the oracle's; a uniform K puts every pair in one class."""
+    say("band classes", name)
+    S, op, gp = run_case(mj, name)
+    _, out_w, _ = oracle.join(S.chars, S.offsets, op)
+    gp.verify_lanes = -3
+    ctx = mj.Context()
+    ds = dev(mj, S)
+    for streamed in (0, 1):
+        out, st = mj.join(ds, gp, ctx=ctx)
+        assert np.array_equal(out, out_w)
+        assert st["verify_group"] == -3 and st["streamed"] == streamed
+    ctx.close()
 
 
 # ---------------------------------------------------------------- search
@@ -342,6 +363,9 @@ def test_search_matches_oracle(mj):
     got3, st3 = index.search(dev(mj, Q), k_per_query=torch.from_numpy(kq).cuda(),
                              verifier=mj.VERIFY_PLAIN)
     assert np.array_equal(got3, want) and st3["verify_group"] == 0
+    # and so do the band classes (per-query K: windows sized per pair)
+    got4, st4 = index.search(dev(mj, Q), k_per_query=torch.from_numpy(kq).cuda(), verify_lanes=-3)
+    assert np.array_equal(got4, want) and st4["verify_group"] == -3
     index.close()
 
 
