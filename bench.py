@@ -230,8 +230,10 @@ def copy_calibration(gib):
 
 def serve(args):
     """Serving: a resident index over uniform random DNA strings (lengths U[1000,10000]),
-    queries replayed at their Poisson arrival times into the continuous-batching server.
-    Prints one JSON line with queries/s and p50/p99 latency."""
+    queries replayed at their Poisson arrival times into the continuous-batching server, at
+    each offered rate of the sweep.  Prints one JSON line: the capacity (the highest offered
+    rate served at 90% or more with p99 within the bound), its latency, every rate's figures,
+    and each batch's admission estimate against the device memory it used."""
     import torch
     import paper_1810_08833_amd as mj
     from paper_1810_08833_amd import datagen as dg
@@ -260,50 +262,105 @@ def serve(args):
     truth = {int(mut[i]): int(src[mut[i]]) for i in range(len(mut)) if within[i]}
     server = mj.Server(index, workers=args.serve_workers, max_batch=4096,
                        memory_budget=args.serve_budget_gib << 30)
-    # warm-up (workspaces, verifier tuning) outside the measured replay
+    # warm-up (workspaces, verifier tuning) outside the measured replays
     for t in range(min(64, Q.n)):
         server.submit(Q.get(t), int(kq[t]), 1 << 40 | t)
     got = 0
     while got < min(64, Q.n):
         got += len(server.poll(timeout_ms=60000))
-    replies = []
-    t0 = time.perf_counter()
-    for i in range(Q.n):
-        target = t0 + arrivals[i] - arrivals[0]
-        while True:
-            now = time.perf_counter()
-            if now >= target:
-                break
-            replies += server.poll(timeout_ms=0)
-            if target - now > 0.0003:
-                time.sleep(min(0.0005, target - now - 0.0002))
-        server.submit(Q.get(i), int(kq[i]), i)
-    while len(replies) < Q.n:
-        replies += server.poll(timeout_ms=60000)
+    rates = [int(r) for r in (args.serve_rates or str(args.serve_rate)).split(",")]
+    p99_bound = args.serve_p99_ms
+
+    def replay(rate):
+        """The queries submitted at their Poisson arrival times, scaled to `rate`."""
+        arr = (arrivals - arrivals[0]) * (args.serve_rate / rate)
+        replies = []
+        t0 = time.perf_counter()
+        for i in range(Q.n):
+            target = t0 + arr[i]
+            while True:
+                now = time.perf_counter()
+                if now >= target:
+                    break
+                replies += server.poll(timeout_ms=0)
+                if target - now > 0.0003:
+                    time.sleep(min(0.0005, target - now - 0.0002))
+            server.submit(Q.get(i), int(kq[i]), i)
+        while len(replies) < Q.n:
+            replies += server.poll(timeout_ms=60000)
+        lat = np.array([r["done_ms"] - r["submit_ms"] for r in replies])
+        first = min(r["submit_ms"] for r in replies)
+        last = max(r["done_ms"] for r in replies)
+        found = sum(1 for r in replies if r["tag"] in truth and truth[r["tag"]] in set(r["ids"].tolist()))
+        # batches: (worker, start); their estimate against the device memory they used, and
+        # the largest sum over batches in flight together
+        batches = {}
+        for r in replies:
+            batches[(r["worker"], r["start_ms"])] = (r["done_ms"], r["batch_estimate"], r["batch_device"])
+        events = sorted([(st, 1, e, d) for (w, st), (dn, e, d) in batches.items()] +
+                        [(dn, -1, e, d) for (w, st), (dn, e, d) in batches.items()],
+                        key=lambda x: (x[0], x[1]))
+        cur_e = cur_d = peak_e = peak_d = 0
+        for _, sign, e, d in events:
+            cur_e += sign * e
+            cur_d += sign * d
+            peak_e, peak_d = max(peak_e, cur_e), max(peak_d, cur_d)
+        ratio = max(d / e for (_, e, d) in batches.values())
+        # the batches' query symbols and device bytes: a least-squares line
+        # device = a + b * symbols
+        qlen = Q.lengths()
+        symd = {}
+        for r in replies:
+            k = (r["worker"], r["start_ms"])
+            symd[k] = symd.get(k, 0) + int(qlen[r["tag"]])
+        sym = np.array([symd[k] for k in batches], dtype=np.float64)
+        dev = np.array([d for (_, _, d) in batches.values()], dtype=np.float64)
+        fit_b, fit_a = np.polyfit(sym, dev, 1) if len(sym) > 1 else (0.0, float(dev[0]))
+        return {"offered_qps": rate, "qps": Q.n / ((last - first) * 1e-3),
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_batch": float(np.mean([r["batch_size"] for r in replies])),
+                "max_batch": int(max(r["batch_size"] for r in replies)),
+                "recall": found / max(1, len(truth)),
+                "batches": len(batches),
+                "max_device_over_estimate": float(ratio),
+                "device_fit_bytes": {"per_batch": float(fit_a), "per_symbol": float(fit_b),
+                                     "max_residual": float(np.max(dev - (fit_a + fit_b * sym)))},
+                "batch_symbols_max": int(sym.max()),
+                "peak_inflight_estimate_bytes": int(peak_e),
+                "peak_inflight_device_bytes": int(peak_d)}
+
+    sweep = []
+    for rate in rates:
+        m = replay(rate)
+        sweep.append(m)
+        print("[serve] offered %d q/s: %.0f q/s, p50 %.1f ms, p99 %.1f ms, mean batch %.1f, "
+              "device/estimate <= %.2f" % (rate, m["qps"], m["p50_ms"], m["p99_ms"], m["mean_batch"],
+                                           m["max_device_over_estimate"]),
+              file=sys.stderr, flush=True)
     server.close()
-    lat = np.array([r["done_ms"] - r["submit_ms"] for r in replies])
-    first = min(r["submit_ms"] for r in replies)
-    last = max(r["done_ms"] for r in replies)
-    found = sum(1 for r in replies if r["tag"] in truth and truth[r["tag"]] in set(r["ids"].tolist()))
+    # capacity: the highest offered rate served at 90% or more of it with p99 within the bound
+    ok = [m for m in sweep if m["qps"] >= 0.9 * m["offered_qps"] and m["p99_ms"] <= p99_bound]
+    best = max(ok, key=lambda m: m["offered_qps"]) if ok else sweep[0]
     line = {
         "metric": "serving: queries/s with p50/p99 latency (continuous batching)",
-        "value": Q.n / ((last - first) * 1e-3),
+        "value": best["qps"],
         "unit": "queries/s",
         "n_gpus": 1,
         "higher_is_better": True,
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "dna_index: %d uniform DNA strings, lengths U[1000,10000]; %d queries "
-                               "(half mutated copies at 5-15%%, half random), Poisson %d/s, "
-                               "K=ceil(0.1|q|), q=5, T=ceil(K/%d)" % (S.n, Q.n, args.serve_rate,
-                                                                      args.serve_t_div),
+                               "(half mutated copies at 5-15%%, half random), Poisson arrivals, "
+                               "K=ceil(0.1|q|), q=5, T=ceil(K/%d)" % (S.n, Q.n, args.serve_t_div),
                    "workers": args.serve_workers, "memory_budget_gib": args.serve_budget_gib},
-        "p50_ms": float(np.percentile(lat, 50)),
-        "p99_ms": float(np.percentile(lat, 99)),
-        "mean_batch": float(np.mean([r["batch_size"] for r in replies])),
-        "max_batch": int(max(r["batch_size"] for r in replies)),
-        "recall": found / max(1, len(truth)),
+        "capacity_qps": best["offered_qps"] if ok else None,
+        "p99_bound_ms": p99_bound,
+        "p50_ms": best["p50_ms"],
+        "p99_ms": best["p99_ms"],
+        "recall": best["recall"],
         "true_pairs": len(truth),
+        "sweep": sweep,
+        "admission_estimate": "8 MiB per batch + 96 bytes per query symbol + 4 KiB per query",
         "index_records": index.records,
         "index_device_bytes": index.device_bytes,
         "index_build_s": build_s,
@@ -540,6 +597,10 @@ def main():
     ap.add_argument("--serve-strings", type=int, default=1_000_000)
     ap.add_argument("--serve-queries", type=int, default=4096)
     ap.add_argument("--serve-rate", type=int, default=2000)
+    ap.add_argument("--serve-rates", default=None,
+                    help="comma-separated offered rates (q/s) swept in turn; default --serve-rate")
+    ap.add_argument("--serve-p99-ms", type=float, default=50.0,
+                    help="p99 latency bound of the capacity figure")
     ap.add_argument("--serve-t-div", type=int, default=2)
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=int, default=32)

@@ -279,7 +279,8 @@ typedef struct mj_server mj_server;
 typedef struct {
     int32_t workers;        /* batches in flight at once, 1..16 */
     int32_t max_batch;      /* queries per batch, 1..65536 */
-    int64_t memory_budget;  /* bytes; a request's estimate is 96 bytes per symbol + 4 KiB */
+    int64_t memory_budget;  /* bytes; a batch's estimate is 8 MiB plus 96 bytes per query
+                               symbol and 4 KiB per query */
 } mj_server_config;
 
 typedef struct {
@@ -292,6 +293,9 @@ typedef struct {
     double submit_ms;       /* times in ms since the server started */
     double start_ms;        /* its batch was admitted */
     double done_ms;         /* its batch completed */
+    int64_t batch_estimate; /* the admission estimate of its batch (bytes) */
+    int64_t batch_device;   /* device memory its batch used: the search's workspace blocks
+                               and the batch's query buffers (bytes) */
 } mj_reply;
 
 /* The index must outlive the server.  EINVAL on bad config. */

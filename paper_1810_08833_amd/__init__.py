@@ -81,7 +81,8 @@ class MjReply(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("count", ctypes.c_int32),
                 ("offset", ctypes.c_int64), ("batch_size", ctypes.c_int32),
                 ("worker", ctypes.c_int32), ("submit_ms", ctypes.c_double),
-                ("start_ms", ctypes.c_double), ("done_ms", ctypes.c_double)]
+                ("start_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
+                ("batch_estimate", ctypes.c_int64), ("batch_device", ctypes.c_int64)]
 
 
 EXPORTS = ["mj_ctx_create", "mj_ctx_destroy", "mj_ctx_set_streaming", "mj_ctx_set_pair_test_pass",
@@ -496,8 +497,9 @@ class Server:
         return load_library().mj_server_pending(self.handle)
 
     def poll(self, timeout_ms: int = -1, max_replies: int = 4096, ids_cap: int = 1 << 20):
-        """Returns a list of dicts: tag, ids (np.uint32), batch_size, worker, status and
-        submit/start/done times in ms."""
+        """Returns a list of dicts: tag, ids (np.uint32), batch_size, worker, status,
+        submit/start/done times in ms, and the batch's admission estimate and measured device
+        bytes."""
         L = load_library()
         reps = (MjReply * max_replies)()
         ids = np.zeros(ids_cap, dtype=np.uint32)
@@ -508,7 +510,8 @@ class Server:
         for r in reps[:nr.value]:
             out.append({"tag": r.tag, "status": r.status, "ids": ids[r.offset:r.offset + r.count].copy(),
                         "batch_size": r.batch_size, "worker": r.worker, "submit_ms": r.submit_ms,
-                        "start_ms": r.start_ms, "done_ms": r.done_ms})
+                        "start_ms": r.start_ms, "done_ms": r.done_ms,
+                        "batch_estimate": r.batch_estimate, "batch_device": r.batch_device})
         return out
 
     def close(self):

@@ -89,6 +89,8 @@ class Workspace {
     template <class T> T *get_n(size_t n) { return static_cast<T *>(get(n * sizeof(T) + 16)); }
     void release_all();
     size_t bytes_held() const { return held_; }
+    // bytes of the blocks the last call used (measured by release_all)
+    size_t last_call_bytes() const { return last_used_; }
     // Arena mode: every block comes from the fixed device region [base, base + bytes)
     // (bump allocation, reset by release_all; MJ_ECAPACITY when it is exhausted) and the
     // workspace never allocates or frees device memory.  The region's first
@@ -118,7 +120,7 @@ class Workspace {
     struct Block { void *p; size_t n; bool used; bool held; };
     bool holding_ = false;
     std::vector<Block> blocks_;
-    size_t held_ = 0;
+    size_t held_ = 0, last_used_ = 0;
     uint8_t *arena_base_ = nullptr;
     size_t arena_bytes_ = 0, arena_used_ = 0;
 };

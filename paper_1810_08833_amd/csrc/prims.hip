@@ -133,8 +133,12 @@ void *Workspace::get(size_t bytes) {
 }
 
 void Workspace::release_all() {
-    for (auto &b : blocks_)
+    size_t used = 0;
+    for (auto &b : blocks_) {
+        if (b.used) used += b.n;
         if (!b.held) b.used = false;
+    }
+    last_used_ = arena() ? arena_used_ : used;
     if (arena()) arena_used_ = ARENA_SCAN_BYTES;
 }
 

@@ -32,6 +32,10 @@ struct Done {
     std::vector<uint32_t> ids;
 };
 
+// Admission estimate: BATCH_BYTES for a batch plus request_bytes for each of its queries.
+// Measured (one worker's search workspace and query buffers, 1M-string DNA index): 1.6-2.9
+// MB per batch plus 18-39 bytes per query symbol, within 4.8 MB of that line.
+constexpr int64_t BATCH_BYTES = 8 << 20;
 int64_t request_bytes(int64_t len) { return 96 * len + 4096; }
 
 }  // namespace
@@ -54,7 +58,8 @@ struct mj_server {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     bool can_admit() const {
-        return !queue.empty() && (inflight_bytes == 0 || inflight_bytes + queue.front().est <= cfg.memory_budget);
+        return !queue.empty() &&
+               (inflight_bytes == 0 || inflight_bytes + BATCH_BYTES + queue.front().est <= cfg.memory_budget);
     }
     void worker(int w);
 };
@@ -75,7 +80,7 @@ void mj_server::worker(int w) {
     int64_t cap_chars = 0, cap_n = 0;
     for (;;) {
         std::vector<Request> batch;
-        int64_t bytes = 0;
+        int64_t bytes = BATCH_BYTES;
         {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] { return stop || can_admit(); });
@@ -90,13 +95,18 @@ void mj_server::worker(int w) {
             }
             inflight_bytes += bytes;
         }
-        if (batch.empty()) continue;
+        if (batch.empty()) {
+            std::lock_guard<std::mutex> lk(mu);
+            inflight_bytes -= bytes;
+            continue;
+        }
         const double start = now_ms();
         const int32_t n = (int32_t)batch.size();
         int64_t total = 0;
         for (auto &r : batch) total += (int64_t)r.codes.size();
         mj_status status = MJ_OK;
         std::vector<uint64_t> pairs;
+        int64_t used = 0;
         // host staging and device buffers grow to the largest batch seen
         if (total + 16 > cap_chars || n + 1 > cap_n) {
             int64_t nc = std::max<int64_t>(total + 16, cap_chars), nn = std::max<int64_t>(n + 1, cap_n);
@@ -145,6 +155,8 @@ void mj_server::worker(int w) {
             qp.verifier = MJ_VERIFY_BATCHED;
             mj_pairs *res = nullptr;
             status = mj_search(ctx, ix, &qs, &qp, (void *)st, &res, nullptr);
+            used = (int64_t)ctx->ws.last_call_bytes() + total + (int64_t)(n + 1) * 12 +
+                   (res ? (int64_t)res->n * 8 : 0);
             if (status == MJ_OK) {
                 pairs.resize((size_t)mj_pairs_count(res));
                 status = mj_pairs_copy_to_host(res, pairs.data(), (int64_t)pairs.size());
@@ -164,6 +176,8 @@ void mj_server::worker(int w) {
             r.submit_ms = batch[i].submit_ms;
             r.start_ms = start;
             r.done_ms = end;
+            r.batch_estimate = bytes;
+            r.batch_device = used;
         }
         if (status == MJ_OK)
             for (uint64_t p : pairs) out[(size_t)(p >> 32)].ids.push_back((uint32_t)p);  // pairs are sorted
@@ -215,7 +229,8 @@ extern "C" mj_status mj_server_submit(mj_server *srv, const uint8_t *codes, int3
         if ((int32_t)codes[i] >= srv->ix->sigma)
             return mj_fail(MJ_EINVAL, "query symbol code is not below the index alphabet");
     int64_t est = request_bytes(len);
-    if (est > srv->cfg.memory_budget) return mj_fail(MJ_EINVAL, "query exceeds the memory budget");
+    if (BATCH_BYTES + est > srv->cfg.memory_budget)
+        return mj_fail(MJ_EINVAL, "query exceeds the memory budget");
     Request r;
     r.tag = tag;
     r.codes.assign(codes, codes + len);

@@ -99,12 +99,13 @@ def test_server_refuses_requests_it_cannot_admit(mj):
     say("server admission limits")
     S = dg.random_strings(92, 50, 200, 400)
     index = mj.Index(dev(mj, S), mj.Params(q=4, k=20, t_div=1))
-    srv = mj.Server(index, workers=1, max_batch=4, memory_budget=8192)
-    # the estimate is 96 bytes per symbol + 4 KiB: 100 symbols (13.4 KiB) exceed 8 KiB
+    srv = mj.Server(index, workers=1, max_batch=4, memory_budget=(8 << 20) + 8192)
+    # a batch's estimate is 8 MiB plus 96 bytes per symbol + 4 KiB per query: one query of
+    # 100 symbols (8 MiB + 13.4 KiB) exceeds the budget
     assert status_of(lambda: srv.submit(S.get(0)[:100], 10, 1)) == mj.MJ_EINVAL
     assert status_of(lambda: srv.submit(np.array([0, 1, 9], np.uint8), 1, 2)) == mj.MJ_EINVAL
     assert status_of(lambda: srv.submit(S.get(0)[:10], 4000, 3)) == mj.MJ_EINVAL
-    srv.submit(S.get(0)[:20], 2, 4)  # 20 symbols: 5.9 KiB fits
+    srv.submit(S.get(0)[:20], 2, 4)  # 20 symbols: 8 MiB + 5.9 KiB fits
     rep = []
     while not rep:
         rep = srv.poll(timeout_ms=10000)
