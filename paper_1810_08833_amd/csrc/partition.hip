@@ -739,122 +739,134 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     // block's end), the two partial blocks through one suffix and one prefix minimum.
     if (rmin_s != 0x7FFFFFFF) {  // some tile position is interior
         constexpr int RUN = REGION / AT_THREADS;
-        const int B = min(RUN, 1 << (31 - __clz(rmin_s + 1)));
-        const int bm = B - 1;
-        const int idx0 = tid * RUN;
-        KT v[RUN];
-        {
-            uint4 raw[RUN * sizeof(S) / 16];
+        const int Bv = min(RUN, 1 << (31 - __clz(rmin_s + 1)));
+        // the block size as a compile-time constant, so that the block-boundary selects of
+        // the prefix and suffix minima and the block loops fold away
+        auto window = [&](auto bconst) {
+            constexpr int B = decltype(bconst)::value;
+            constexpr int bm = B - 1;
+            const int idx0 = tid * RUN;
+            KT v[RUN];
+            {
+                uint4 raw[RUN * sizeof(S) / 16];
 #pragma unroll
-            for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++) raw[i] = reinterpret_cast<const uint4 *>(bufA + idx0)[i];
-            const uint32_t *w = reinterpret_cast<const uint32_t *>(raw);
+                for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++) raw[i] = reinterpret_cast<const uint4 *>(bufA + idx0)[i];
+                const uint32_t *w = reinterpret_cast<const uint32_t *>(raw);
 #pragma unroll
-            for (int j = 0; j < RUN; j++) {
-                if constexpr (RANKED) v[j] = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-                else v[j] = w[j];
-            }
-        }
-        KT pre[RUN], suf[RUN];
-#pragma unroll
-        for (int j = 0; j < RUN; j++) pre[j] = (j & bm) == 0 ? v[j] : min(pre[j > 0 ? j - 1 : 0], v[j]);
-#pragma unroll
-        for (int j = RUN - 1; j >= 0; j--)
-            suf[j] = ((j + 1) & bm) == 0 ? v[j] : min(suf[j + 1 < RUN ? j + 1 : j], v[j]);
-        // bit j: v[j] is strictly below every other key of its block
-        uint32_t cand = 0;
-#pragma unroll
-        for (int j = 0; j < RUN; j++) {
-            const KT before = (j & bm) == 0 ? (KT)~0u : pre[j > 0 ? j - 1 : 0];
-            const KT after = ((j + 1) & bm) == 0 ? (KT)~0u : suf[j + 1 < RUN ? j + 1 : j];
-            cand |= (v[j] < before && v[j] < after) ? 1u << j : 0u;
-        }
-        if constexpr (!RANKED) {
-            // blocks whose minimum top half several positions hold: their unique minimum,
-            // if any, by the full hashes of those positions
-            uint32_t tied = 0;
-#pragma unroll
-            for (int j = 0; j < RUN; j++) tied |= v[j] == min(pre[j], suf[j]) ? 1u << j : 0u;
-            const uint32_t bbits = B >= 32 ? ~0u : (1u << B) - 1u;
-            for (int b0 = 0; b0 < RUN; b0 += B) {
-                uint32_t tb = tied & (bbits << b0);
-                if (__popc(tb) < 2) continue;
-                uint64_t e = ~0ull;
-                int je = -1;
-                bool dup = false;
-                for (; tb; tb &= tb - 1) {
-                    const int j = __ffs(tb) - 1;
-                    const uint64_t x = exact64(idx0 + j);
-                    if (x < e) {
-                        e = x;
-                        je = j;
-                        dup = false;
-                    } else if (x == e) {
-                        dup = true;
-                    }
-                }
-                if (!dup && e != ~0ull) cand |= 1u << je;
-            }
-        }
-        {
-            uint32_t pw[RUN * sizeof(S) / 4], sw[RUN * sizeof(S) / 4];
-#pragma unroll
-            for (int j = 0; j < RUN; j++) {
-                if constexpr (RANKED) {
-                    if (j & 1) {
-                        pw[j >> 1] |= (uint32_t)pre[j] << 16;
-                        sw[j >> 1] |= (uint32_t)suf[j] << 16;
-                    } else {
-                        pw[j >> 1] = (uint32_t)pre[j];
-                        sw[j >> 1] = (uint32_t)suf[j];
-                    }
-                } else {
-                    pw[j] = pre[j];
-                    sw[j] = suf[j];
+                for (int j = 0; j < RUN; j++) {
+                    if constexpr (RANKED) v[j] = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+                    else v[j] = w[j];
                 }
             }
+            KT pre[RUN], suf[RUN];
 #pragma unroll
-            for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++) {
-                reinterpret_cast<uint4 *>(bufB + idx0)[i] = make_uint4(pw[4 * i], pw[4 * i + 1], pw[4 * i + 2], pw[4 * i + 3]);
-                reinterpret_cast<uint4 *>(bufA + idx0)[i] = make_uint4(sw[4 * i], sw[4 * i + 1], sw[4 * i + 2], sw[4 * i + 3]);
+            for (int j = 0; j < RUN; j++) pre[j] = (j & bm) == 0 ? v[j] : min(pre[j > 0 ? j - 1 : 0], v[j]);
+#pragma unroll
+            for (int j = RUN - 1; j >= 0; j--)
+                suf[j] = ((j + 1) & bm) == 0 ? v[j] : min(suf[j + 1 < RUN ? j + 1 : j], v[j]);
+            // bit j: v[j] is strictly below every other key of its block
+            uint32_t cand = 0;
+#pragma unroll
+            for (int j = 0; j < RUN; j++) {
+                const KT before = (j & bm) == 0 ? (KT)~0u : pre[j > 0 ? j - 1 : 0];
+                const KT after = ((j + 1) & bm) == 0 ? (KT)~0u : suf[j + 1 < RUN ? j + 1 : j];
+                cand |= (v[j] < before && v[j] < after) ? 1u << j : 0u;
             }
-        }
-        __syncthreads();
-        const int lb2 = 31 - __clz(B);  // log2 B
-        for (; cand; cand &= cand - 1) {
-            const int p = idx0 + __ffs(cand) - 1;
-            if (p < H || p >= H + TP) continue;  // not a tile position
-            const int r = pinfo[p] & 0x3FFF;
-            if (r == 0) continue;  // not an interior position
-            const KT hv = bufA[p];  // its key: the suffix minimum from a block's minimum
-            const int bk = p >> lb2;
-            // strictly below every other key of the window: an anchor; above one: not;
-            // equal to one (ranks: equal hashes, not strict): hashes decide by full value
-            bool below = false, tie = false;
-            auto see = [&](KT x) {
-                below |= x < hv;
-                tie |= x == hv;
-            };
-            const int L = p - r, lb = L >> lb2;
-            if (lb < bk) {
-                see(bufA[L]);
-                for (int b2 = lb + 1; !below && b2 < bk; b2++) see(bufB[(b2 << lb2) + bm]);
-            }
-            const int R = p + r, rb = R >> lb2;
-            if (!below && rb > bk) {
-                for (int b2 = bk + 1; !below && b2 < rb; b2++) see(bufB[(b2 << lb2) + bm]);
-                if (!below) see(bufB[R]);
-            }
-            bool ok = !below && !tie;
             if constexpr (!RANKED) {
-                if (!below && tie) {
-                    const uint64_t ep = exact64(p);
-                    ok = true;
-                    for (int dd = 1; ok && dd <= r; dd++) ok = exact64(p - dd) > ep && exact64(p + dd) > ep;
+                // blocks whose minimum top half several positions hold: their unique minimum,
+                // if any, by the full hashes of those positions
+                uint32_t tied = 0;
+#pragma unroll
+                for (int j = 0; j < RUN; j++) tied |= v[j] == min(pre[j], suf[j]) ? 1u << j : 0u;
+                constexpr uint32_t bbits = B >= 32 ? ~0u : (1u << B) - 1u;
+                for (int b0 = 0; b0 < RUN; b0 += B) {
+                    uint32_t tb = tied & (bbits << b0);
+                    if (__popc(tb) < 2) continue;
+                    uint64_t e = ~0ull;
+                    int je = -1;
+                    bool dup = false;
+                    for (; tb; tb &= tb - 1) {
+                        const int j = __ffs(tb) - 1;
+                        const uint64_t x = exact64(idx0 + j);
+                        if (x < e) {
+                            e = x;
+                            je = j;
+                            dup = false;
+                        } else if (x == e) {
+                            dup = true;
+                        }
+                    }
+                    if (!dup && e != ~0ull) cand |= 1u << je;
                 }
             }
-            if (ok) atomicOr(&aflag[(p - H) >> 5], 1u << ((p - H) & 31));
+            {
+                uint32_t pw[RUN * sizeof(S) / 4], sw[RUN * sizeof(S) / 4];
+#pragma unroll
+                for (int j = 0; j < RUN; j++) {
+                    if constexpr (RANKED) {
+                        if (j & 1) {
+                            pw[j >> 1] |= (uint32_t)pre[j] << 16;
+                            sw[j >> 1] |= (uint32_t)suf[j] << 16;
+                        } else {
+                            pw[j >> 1] = (uint32_t)pre[j];
+                            sw[j >> 1] = (uint32_t)suf[j];
+                        }
+                    } else {
+                        pw[j] = pre[j];
+                        sw[j] = suf[j];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++) {
+                    reinterpret_cast<uint4 *>(bufB + idx0)[i] = make_uint4(pw[4 * i], pw[4 * i + 1], pw[4 * i + 2], pw[4 * i + 3]);
+                    reinterpret_cast<uint4 *>(bufA + idx0)[i] = make_uint4(sw[4 * i], sw[4 * i + 1], sw[4 * i + 2], sw[4 * i + 3]);
+                }
+            }
+            __syncthreads();
+            constexpr int lb2 = B >= 16 ? 4 : B >= 8 ? 3 : B >= 4 ? 2 : B >= 2 ? 1 : 0;  // log2 B
+            for (; cand; cand &= cand - 1) {
+                const int p = idx0 + __ffs(cand) - 1;
+                if (p < H || p >= H + TP) continue;  // not a tile position
+                const int r = pinfo[p] & 0x3FFF;
+                if (r == 0) continue;  // not an interior position
+                const KT hv = bufA[p];  // its key: the suffix minimum from a block's minimum
+                const int bk = p >> lb2;
+                // strictly below every other key of the window: an anchor; above one: not;
+                // equal to one (ranks: equal hashes, not strict): hashes decide by full value
+                bool below = false, tie = false;
+                auto see = [&](KT x) {
+                    below |= x < hv;
+                    tie |= x == hv;
+                };
+                const int L = p - r, lb = L >> lb2;
+                if (lb < bk) {
+                    see(bufA[L]);
+                    for (int b2 = lb + 1; !below && b2 < bk; b2++) see(bufB[(b2 << lb2) + bm]);
+                }
+                const int R = p + r, rb = R >> lb2;
+                if (!below && rb > bk) {
+                    for (int b2 = bk + 1; !below && b2 < rb; b2++) see(bufB[(b2 << lb2) + bm]);
+                    if (!below) see(bufB[R]);
+                }
+                bool ok = !below && !tie;
+                if constexpr (!RANKED) {
+                    if (!below && tie) {
+                        const uint64_t ep = exact64(p);
+                        ok = true;
+                        for (int dd = 1; ok && dd <= r; dd++) ok = exact64(p - dd) > ep && exact64(p + dd) > ep;
+                    }
+                }
+                if (ok) atomicOr(&aflag[(p - H) >> 5], 1u << ((p - H) & 31));
+            }
+            __syncthreads();
+        };
+        switch (Bv) {
+            case 1: window(std::integral_constant<int, 1>{}); break;
+            case 2: window(std::integral_constant<int, 2>{}); break;
+            case 4: window(std::integral_constant<int, 4>{}); break;
+            case 8: window(std::integral_constant<int, 8>{}); break;
+            default: window(std::integral_constant<int, RUN>{}); break;  // 16 (RUN == 16)
         }
-        __syncthreads();
     }
     // one bit per position: string start or anchor (TP is a multiple of 64)
     const int rem = (int)min<int64_t>(total - tile_start, (int64_t)TP);  // tile positions in the input
