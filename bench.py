@@ -159,6 +159,8 @@ def roofline(kernel, stats, kms, kln, bits, q, workload):
         planes = {1: 2, 2: 2, 3: 4, 4: 4, 5: 6, 6: 6}.get(bits, 8)
         if last["verify_group"] == -2:  # two lanes per pair, split by text columns
             kname, vcfg = "k_verify_bidir", "<%d, %d>" % (last["verify_words"], planes)
+        elif last["verify_group"] == -3:  # each pair's window by its band class
+            kname, vcfg = "k_verify_classes", "<%d>" % planes
         else:
             kname = "k_verify_persist"
             vcfg = "<%d, %d, %d>" % (last["verify_words"], last["verify_group"], planes)
