@@ -338,6 +338,11 @@ def test_join_with_band_classes(mj, name):
         out, st = mj.join(ds, gp, ctx=ctx)
         assert np.array_equal(out, out_w)
         assert st["verify_group"] == -3 and st["streamed"] == streamed
+    ctx.set_streaming(2)  # captured into HIP graphs, then replayed
+    for _ in range(2):
+        out, st = mj.join(ds, gp, ctx=ctx)
+        assert np.array_equal(out, out_w)
+    assert st["streamed"] == 2
     ctx.close()
 
 
@@ -600,6 +605,11 @@ def test_member_filter_identical(mj, name, bucket_limit):
         assert st["streamed"] == streamed and st["member_filter"] == 1
         assert st["groups"] == st0["groups"] and st["pair_tests"] == st0["pair_tests"]
         assert st["records"] == st0["records"] and st["members"] <= st["records"]
+    ctx.set_streaming(2)  # captured into HIP graphs, then replayed
+    for _ in range(2):
+        out, st = mj.join(ds, gp, ctx=ctx)
+        assert np.array_equal(out, out_w)
+    assert st["streamed"] == 2
     ctx.close()
 
 
