@@ -1122,9 +1122,12 @@ void sort_records(uint64_t *key, uint64_t *val, int64_t n, Workspace &ws, hipStr
 //     puts each "bucket" of equal top 16 bits in one contiguous range;
 //  2. k_mb_bounds finds each bucket's range (a binary search per bucket), and k_mb_flags
 //     gives each bucket one workgroup with two LDS bitmaps over the next 16 bits (seen /
-//     seen again), flagging the elements whose top half was seen again.  A bucket of more
-//     than `big` elements (default 2^16) is kept whole, which only costs time;
-//  3. the flagged elements are compacted, in order, and their records gathered.
+//     seen again), flagging the records whose key's top half was seen again in a byte
+//     array indexed by record (a bucket of more than `big` elements, default 2^16, is kept
+//     whole, which only costs time);
+//  3. the flagged records are compacted in record order and gathered: ascending reads of
+//     the key and payload arrays (gathering them in bucket order read lines at random,
+//     fetching 20 times the bytes kept).
 // The kept records then go through the full record sort; any superset of the group
 // members gives the same groups.
 constexpr int MB_BUCKETS = 1 << 16;
@@ -1132,8 +1135,8 @@ constexpr int MB_BUCKETS = 1 << 16;
 __device__ __forceinline__ uint32_t mb_top16(uint64_t x) { return (uint32_t)(x >> 48); }
 
 // bs[b] = the first index whose top 16 bits are >= b (b = 0..2^16; bs[2^16] = n): one
-// binary search per thread over the sorted elements.  Flags past the count (up to the
-// capacity) are cleared on the way.
+// binary search per thread over the sorted elements.  Every record flag (up to the
+// capacity) is cleared on the way.
 __global__ void k_mb_bounds(const uint64_t *__restrict__ w, int64_t cap, const int64_t *n_dev,
                             uint32_t *__restrict__ bs, uint8_t *__restrict__ flags) {
     const int64_t n = n_dev ? min(cap, *n_dev) : cap;
@@ -1148,24 +1151,22 @@ __global__ void k_mb_bounds(const uint64_t *__restrict__ w, int64_t cap, const i
         bs[g] = (uint32_t)a;
     }
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = n + g; i < cap; i += stride) flags[i] = 0;
+    for (int64_t i = g; i < cap; i += stride) flags[i] = 0;
 }
 
 // One workgroup per bucket [bs[b], bs[b+1]): LDS bitmaps over bits 32..47 (seen / seen
 // again); an element is kept when its bits were seen again, i.e. when its key's top half
-// occurs twice.  A bucket of more than `big` elements is kept whole.
+// occurs twice, by setting its record's flag (flags are indexed by record: the element's
+// low half).  A bucket of more than `big` elements is kept whole.
 __global__ __launch_bounds__(256) void k_mb_flags(const uint64_t *__restrict__ w,
                                                   const uint32_t *__restrict__ bs, uint32_t big,
                                                   uint8_t *__restrict__ flags) {
     const uint32_t lo = bs[blockIdx.x], hi = bs[blockIdx.x + 1];
     if (hi - lo > big) {
-        for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) flags[i] = 1;
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) flags[(uint32_t)w[i]] = 1;
         return;
     }
-    if (hi <= lo + 1) {  // empty, or one element: not kept
-        if (hi == lo + 1 && threadIdx.x == 0) flags[lo] = 0;
-        return;
-    }
+    if (hi <= lo + 1) return;  // empty, or one element: not kept
     __shared__ uint32_t seen[2048], again[2048];
     for (int j = threadIdx.x; j < 2048; j += 256) {
         seen[j] = 0;
@@ -1178,33 +1179,31 @@ __global__ __launch_bounds__(256) void k_mb_flags(const uint64_t *__restrict__ w
     }
     __syncthreads();
     for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
-        const uint32_t sub = (uint32_t)(w[i] >> 32) & 0xFFFFu;
-        flags[i] = (uint8_t)((again[sub >> 5] >> (sub & 31)) & 1u);
+        const uint64_t x = w[i];
+        const uint32_t sub = (uint32_t)(x >> 32) & 0xFFFFu;
+        if ((again[sub >> 5] >> (sub & 31)) & 1u) flags[(uint32_t)x] = 1;
     }
 }
 
-// mkey[j], mval[j] = the record of the j-th kept element (j < min(count, mcap)); m_dev
-// gets the count (which may exceed mcap: the caller checks).  Four elements per thread,
-// their loads issued together (the record reads are scattered).
+// mkey[j], mval[j] = the record of the j-th kept record (j < min(count, mcap)), idx
+// holding kept record indices in ascending order; m_dev gets the count (which may exceed
+// mcap: the caller checks).  Four records per thread, their loads issued together.
 constexpr int MB_GATHER = 4;
 __global__ void k_mb_gather(const int64_t *__restrict__ idx, const uint32_t *__restrict__ count,
-                            const uint64_t *__restrict__ w, const uint64_t *__restrict__ key,
-                            const uint64_t *__restrict__ val, uint64_t *__restrict__ mkey,
-                            uint64_t *__restrict__ mval, int64_t mcap, int64_t *m_dev) {
+                            const uint64_t *__restrict__ key, const uint64_t *__restrict__ val,
+                            uint64_t *__restrict__ mkey, uint64_t *__restrict__ mval, int64_t mcap,
+                            int64_t *m_dev) {
     const int64_t m = min((int64_t)*count, mcap);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g == 0) *m_dev = (int64_t)*count;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j0 = g; j0 < m; j0 += stride * MB_GATHER) {
-        uint32_t r[MB_GATHER];
-        int64_t ix[MB_GATHER];
+        int64_t r[MB_GATHER];
 #pragma unroll
         for (int u = 0; u < MB_GATHER; u++) {
             const int64_t j = j0 + u * stride;
-            ix[u] = j < m ? idx[j] : 0;
+            r[u] = j < m ? idx[j] : 0;
         }
-#pragma unroll
-        for (int u = 0; u < MB_GATHER; u++) r[u] = (uint32_t)w[ix[u]];
         uint64_t k[MB_GATHER], v[MB_GATHER];
 #pragma unroll
         for (int u = 0; u < MB_GATHER; u++) {
@@ -1266,7 +1265,7 @@ void group_members(const uint64_t *key, const uint64_t *val, int64_t n, const in
     int64_t *idx = ws.get_n<int64_t>(n + 1);
     const uint32_t *count = compact_flags_async(flags, n, idx, ws, s);
     hipLaunchKernelGGL(k_mb_gather, dim3(grid_for((std::min(n, mcap) + MB_GATHER - 1) / MB_GATHER, 256, 16384)),
-                       dim3(256), 0, s, idx, count, w2, key, val, mkey, mval, mcap, m_dev);
+                       dim3(256), 0, s, idx, count, key, val, mkey, mval, mcap, m_dev);
     MJ_LAUNCH_CHECK();
 }
 
