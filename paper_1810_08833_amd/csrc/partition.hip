@@ -356,19 +356,21 @@ __global__ __launch_bounds__(256) void k_rank_table(int ncodes, uint64_t salt,
 // Per-tile descriptor: the strings overlapping the tile's region (first id, count), and
 // for up to TD_STR of them their offsets and radii, so that the anchor kernel reads all
 // it needs about string boundaries in one coalesced load.  One thread per tile: the
-// binary searches' latency overlaps across tiles.
+// binary searches' latency overlaps across tiles.  rmin: the smallest radius of an
+// interior position of the tile (0x7FFFFFFF: none), known when ns >= 0.
 constexpr int TD_STR = 8;
 struct TileDesc {
     int32_t s0, ns;             // ns = -1: more than TD_STR strings (search per position)
     int64_t off[TD_STR + 1];
     int32_t r[TD_STR];
-    int32_t pad[4];             // 128 bytes
+    int32_t rmin;
+    int32_t pad[3];             // 128 bytes
 };
 static_assert(sizeof(TileDesc) == 128, "tile descriptor size");
 
 __global__ void k_tile_desc(const int64_t *__restrict__ off, const int32_t *__restrict__ rr,
                             int32_t n, int64_t total, int64_t ntiles, int TP, int H, int NR,
-                            TileDesc *__restrict__ td) {
+                            int q, TileDesc *__restrict__ td) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
     int64_t base = t * TP - H;
@@ -381,7 +383,18 @@ __global__ void k_tile_desc(const int64_t *__restrict__ off, const int32_t *__re
     d.ns = (s1 - s0 + 1 <= TD_STR) ? (s1 - s0 + 1) : -1;
     for (int k = 0; k <= TD_STR; k++) d.off[k] = (d.ns >= 0 && k <= d.ns) ? off[s0 + k] : 0;
     for (int k = 0; k < TD_STR; k++) d.r[k] = (d.ns >= 0 && k < d.ns) ? rr[s0 + k] : 0;
-    for (int k = 0; k < 4; k++) d.pad[k] = 0;
+    // interior positions of a string: i in [r, npos - r) with npos = m - q + 1 full
+    // q-grams (none on the wide path); those in the tile's own positions set rmin
+    const int64_t c0 = t * TP, c1 = min(c0 + TP, total);
+    int32_t rmin = 0x7FFFFFFF;
+    for (int k = 0; d.ns >= 0 && k < d.ns; k++) {
+        const int32_t r = d.r[k];
+        if (r >= WIDE_SENTINEL) continue;
+        const int64_t npos = d.off[k + 1] - d.off[k] - q + 1;
+        if (max(d.off[k] + r, c0) < min(d.off[k] + npos - r, c1)) rmin = min(rmin, r);
+    }
+    d.rmin = rmin;
+    for (int k = 0; k < 3; k++) d.pad[k] = 0;
     td[t] = d;
 }
 
@@ -393,15 +406,22 @@ __device__ __forceinline__ uint64_t pi_of(uint64_t G, uint64_t salt, const uint6
 }
 
 // V = uint64_t: the hash itself (Pi, or the injected table when TABLE); V = uint32_t: its
-// rank from `rank` (code spaces of at most RANK_MAX_BITS bits), staged in LDS.  TABLE is a
-// template parameter so that the hashing loop has no branch per position.
+// rank from the repetition's rank table (code spaces of at most RANK_MAX_BITS bits), staged
+// in LDS.  TABLE is a template parameter so that the hashing loop has no branch per position.
+// One launch covers every repetition rho < reps: the region's symbols, its string bounds and
+// (on the fast paths) the q-gram codes are staged once, then hashed with each repetition's
+// salt mix64(seed + rho + GAMMA) (rank table rho at rank + rho * rstride); repetition rho's
+// flags go to bitmap + rho * bm_stride and its tile counts to tile_count + rho * tc_stride.
 template <int REGION, typename V, bool TABLE>
-__global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
+__global__ __launch_bounds__(AT_THREADS)
+// as many resident waves as the LDS allows (7 workgroups per CU for the smaller region):
+// the register budget that leaves
+__attribute__((amdgpu_waves_per_eu(REGION == 2048 ? 7 : 3))) void k_anchor_tiles(
     const uint8_t *__restrict__ chars, const int64_t *__restrict__ off, int32_t n, int64_t total,
-    int q, int bits, uint64_t salt, const uint64_t *__restrict__ table,
-    const uint16_t *__restrict__ rank, const int32_t *__restrict__ rr, int TP, int H,
+    int q, int bits, uint64_t seed, int reps, const uint64_t *__restrict__ table,
+    const uint16_t *__restrict__ rank, int rstride, const int32_t *__restrict__ rr, int TP, int H,
     const TileDesc *__restrict__ tdesc, int aligned4, int packed, uint64_t *__restrict__ bitmap,
-    uint32_t *__restrict__ tile_count) {
+    int64_t bm_stride, uint32_t *__restrict__ tile_count, int64_t tc_stride) {
     constexpr bool RANKED = sizeof(V) == 4;
     // LDS slots hold keys: ranks as 16 bits (ranks < 2^12; the sentinel 0xFFFF is above
     // them all), hashes by their top 32 bits (sentinel 0xFFFFFFFF).  Compact slots leave
@@ -410,11 +430,12 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     // full hashes, recomputed from the staged symbols, decide (exact64 below).
     using S = typename std::conditional<RANKED, uint16_t, uint32_t>::type;
     using KT = uint32_t;  // keys in registers
+    using Code = typename std::conditional<RANKED, uint32_t, uint64_t>::type;
     // keys, then the suffix (bufA) and prefix (bufB) minima within window-test blocks
     __shared__ __align__(16) S bufA[REGION];
     __shared__ __align__(16) S bufB[REGION];
-    // per region slot: bits 0-13 the radius if the position is interior (else 0), bit 14
-    // set where a full q-gram starts
+    // per region slot, written by threads on the general path only: the radius if the
+    // position is interior, else 0 (threads on the fast paths keep theirs in registers)
     __shared__ __align__(16) uint16_t pinfo[REGION];
     // symbols, one byte each, word-aligned with the input: NR + q - 1 bytes from offset
     // sh (< 4; < 16 for 2-bit packed input, where q <= 32), read as whole words (and up to
@@ -439,18 +460,29 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
     // workgroup waits for one memory round trip rather than one per copy loop trip.
     uint32_t tdw = 0;
     if (tid < 32) tdw = reinterpret_cast<const uint32_t *>(tdesc + blockIdx.x)[tid];
-    // rank table: 16-byte copies (the table is a workspace block: 16-byte aligned, with 16
-    // bytes of slack past its end)
+    // rank tables: 16-byte copies (each starts on a 16-byte boundary of a workspace block
+    // with 16 bytes of slack past its end)
     constexpr int RK = RANKED ? ((1 << RANK_MAX_BITS) / 8 + AT_THREADS - 1) / AT_THREADS : 1;
     uint4 rk[RK];
     const int nr8 = RANKED ? ((1 << (q * bits)) + 7) / 8 : 0;
-    if constexpr (RANKED) {
+    auto load_rank = [&](int rho) {
+        if constexpr (RANKED) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(rank + (int64_t)rho * rstride);
 #pragma unroll
-        for (int i = 0; i < RK; i++) {
-            const int c = tid + AT_THREADS * i;
-            rk[i] = c < nr8 ? reinterpret_cast<const uint4 *>(rank)[c] : make_uint4(0, 0, 0, 0);
+            for (int i = 0; i < RK; i++) {
+                const int c = tid + AT_THREADS * i;
+                rk[i] = c < nr8 ? src[c] : make_uint4(0, 0, 0, 0);
+            }
         }
-    }
+    };
+    auto store_rank = [&]() {
+        if constexpr (RANKED) {
+#pragma unroll
+            for (int i = 0; i < RK; i++)
+                if (tid + AT_THREADS * i < nr8) reinterpret_cast<uint4 *>(rank_s)[tid + AT_THREADS * i] = rk[i];
+        }
+    };
+    load_rank(0);
     // symbols of the region: byte sh + idx of ch holds global position base + idx, with
     // ch starting at a 4-byte boundary of the input (16 symbols: a 32-bit word of 2-bit
     // packed input) so whole words are copied
@@ -487,9 +519,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
             cw[i] = w;
         }
     }
-    if (tid == 0) {
-        rmin_s = 0x7FFFFFFF;
-    }
+    if (tid == 0) rmin_s = 0x7FFFFFFF;
     for (int w = tid; w < REGION / 32; w += AT_THREADS) aflag[w] = 0;
     if (tid < 32) reinterpret_cast<uint32_t *>(&td)[tid] = tdw;
     if (packed) {
@@ -512,11 +542,7 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         for (int i = 0; i < CW; i++)
             if (tid + AT_THREADS * i < nwords) ch32[tid + AT_THREADS * i] = cw[i];
     }
-    if constexpr (RANKED) {
-#pragma unroll
-        for (int i = 0; i < RK; i++)
-            if (tid + AT_THREADS * i < nr8) reinterpret_cast<uint4 *>(rank_s)[tid + AT_THREADS * i] = rk[i];
-    }
+    store_rank();
     __syncthreads();
     const int32_t ns = td.ns;
     // string starts inside the tile are flagged like anchors (a few per tile)
@@ -524,28 +550,42 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
         if (idx >= H && idx < H + TP) atomicOr(&aflag[(idx - H) >> 5], 1u << ((idx - H) & 31));
     };
     const uint64_t gmask = (q * bits >= 64) ? ~0ull : ((1ull << (q * bits)) - 1);
-    // hashes: each thread rolls the packed q-gram code over RUN consecutive positions
+    constexpr int RUN = REGION / AT_THREADS;
+    static_assert(RUN == 8 || RUN == 16, "positions per thread");
+    // Each thread takes RUN consecutive region positions.  On the fast paths it keeps, for
+    // every repetition: the q-gram codes (Gs), which positions are interior tile positions
+    // (bit j of imask for position idx0 + j), their radius (rA for j < jbv, else rB) and
+    // the string starts among them (fs0, fs1; -1: none).  The general path (slowp) does all
+    // of it per repetition, with the radii in pinfo.
+    Code Gs[RUN];
+    uint32_t imask = 0;
+    int32_t rA = 0, rB = 0;
+    int jbv = RUN, fs0 = -1, fs1 = -1;
+    bool slowp = false;
+    // bits lo .. hi - 1 of a run mask
+    auto span = [](int lo, int hi) -> uint32_t {
+        lo = max(lo, 0);
+        hi = min(hi, RUN);
+        return lo < hi ? (0xFFFFFFFFu >> (32 - hi)) & ~((1u << lo) - 1u) : 0u;
+    };
+    const int idx0 = tid * RUN;
+    const int64_t g0 = base + idx0;
+    int t = 0;
+    int64_t sb0 = 0, se0 = -1;
+    if (ns >= 0) {
+        for (int k = 1; k < ns; k++) t += (td.off[k] <= g0) ? 1 : 0;
+        sb0 = td.off[t];
+        se0 = td.off[t + 1];
+    }
     {
-        constexpr int RUN = REGION / AT_THREADS;
-        static_assert(RUN == 8 || RUN == 16, "positions per thread");
-        int lrmin = 0x7FFFFFFF;
-        const int idx0 = tid * RUN;
-        const int64_t g0 = base + idx0;
-        int t = 0;
-        int64_t sb0 = 0, se0 = -1;
-        if (ns >= 0) {
-            for (int k = 1; k < ns; k++) t += (td.off[k] <= g0) ? 1 : 0;
-            sb0 = td.off[t];
-            se0 = td.off[t + 1];
-        }
         // fast paths: the RUN positions lie in string t (fast1: all of them start full
         // q-grams), or in strings t and t + 1 (fast2: positions from jb on belong to t + 1,
-        // and positions whose q-gram runs past their string's end hold the sentinel)
+        // and some q-grams may run past their string's end)
         const bool in_t = ns >= 0 && q <= 9 && g0 >= sb0 && idx0 + RUN <= NR;
         const bool fast1 = in_t && g0 + RUN + q - 1 <= se0;
         const int64_t se1 = (in_t && t + 1 < ns) ? td.off[t + 2] : se0;
         const bool fast2 = in_t && !fast1 && (se0 >= g0 + RUN || (t + 1 < ns && g0 + RUN <= se1));
-        auto hash_run = [&](auto two) {
+        auto codes = [&](auto two) {
             constexpr bool TWO = decltype(two)::value;
             // bytes idx0 .. idx0 + RUN + 7 of the region (the first q-gram and the rest),
             // and the RUN - 1 symbols entering the window, idx0 + q .. idx0 + q + RUN - 2
@@ -567,100 +607,100 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 for (int i = 0; i < RUN / 4; i++)
                     N[i] = __builtin_amdgcn_alignbit(W2[i + 1], W2[i], 8 * (o2 & 3));
             }
-            using Code = typename std::conditional<RANKED, uint32_t, uint64_t>::type;
             const Code cmask = (Code)gmask;
+            // the first code from its q symbols, q a compile-time constant per case
             Code G = 0;
+            auto first = [&](auto qc) {
+                constexpr int Q = decltype(qc)::value;
 #pragma unroll
-            for (int k = 0; k < 9; k++)
-                if (k < q) G = (G << bits) | ((A[k >> 2] >> (8 * (k & 3))) & 0xFFu);
+                for (int k = 0; k < Q; k++) G = (G << bits) | ((A[k >> 2] >> (8 * (k & 3))) & 0xFFu);
+            };
+            switch (q) {
+                case 1: first(std::integral_constant<int, 1>{}); break;
+                case 2: first(std::integral_constant<int, 2>{}); break;
+                case 3: first(std::integral_constant<int, 3>{}); break;
+                case 4: first(std::integral_constant<int, 4>{}); break;
+                case 5: first(std::integral_constant<int, 5>{}); break;
+                case 6: first(std::integral_constant<int, 6>{}); break;
+                case 7: first(std::integral_constant<int, 7>{}); break;
+                case 8: first(std::integral_constant<int, 8>{}); break;
+                default: first(std::integral_constant<int, 9>{}); break;  // q <= 9 here
+            }
             G &= cmask;  // the code indexes the rank table: never past its 2^(q b) entries
+#pragma unroll
+            for (int j = 0; j < RUN; j++) {
+                Gs[j] = G;
+                if (j + 1 < RUN) G = ((G << bits) | ((N[j >> 2] >> (8 * (j & 3))) & 0xFFu)) & cmask;
+            }
             // positions inside a string fit in 32 bits (m < 2^31)
             const int32_t i0 = (int32_t)(g0 - sb0);
             const int32_t npos = (int32_t)(se0 - sb0) - q + 1;
             const int32_t r = td.r[t];
-            // interior i in [r, npos-1-r]  <=>  (unsigned)(i - r) < ibound; none for a
-            // string on the wide path
-            const uint32_t ibound = r >= WIDE_SENTINEL ? 0u : (uint32_t)max(npos - 2 * r, 0);
             // string t + 1 (fast2): its first run index jb, positions, radius
             const int jb = TWO ? (int)min<int64_t>(se0 - g0, RUN) : RUN;
             const int32_t npos1 = TWO ? (int32_t)(se1 - se0) - q + 1 : 0;
             const int32_t r1 = (TWO && t + 1 < ns) ? td.r[t + 1] : r;
-            const uint32_t ibound1 = r1 >= WIDE_SENTINEL ? 0u : (uint32_t)max(npos1 - 2 * r1, 0);
-            V hv[RUN];
-            uint16_t inf[RUN];
-#pragma unroll
-            for (int j = 0; j < RUN; j++) {
-                V h;
-                if constexpr (RANKED) h = rank_s[G];
-                else h = pi_of<TABLE>((uint64_t)G, salt, table);
-                if constexpr (TWO) {
-                    const bool in2 = j >= jb;
-                    const int32_t i = in2 ? j - jb : i0 + j;
-                    const int32_t rj = in2 ? r1 : r;
-                    const bool interior = (uint32_t)(i - rj) < (in2 ? ibound1 : ibound);
-                    const bool vq = i < (in2 ? npos1 : npos);
-                    hv[j] = vq ? h : (V)~0ull;
-                    inf[j] = (uint16_t)((interior ? rj : 0) | (vq ? 0x4000 : 0));
-                } else {
-                    hv[j] = h;
-                    inf[j] = (uint16_t)(((uint32_t)(i0 + j - r) < ibound ? r : 0) | 0x4000);
-                }
-                if (j + 1 < RUN) G = ((G << bits) | ((N[j >> 2] >> (8 * (j & 3))) & 0xFFu)) & cmask;
-            }
-            // radii of the interior tile positions of the run: run indices [lo, hi) of a
-            // string with radius rr
-            auto radii = [&](int lo, int hi, int32_t rr) {
-                lo = max(lo, H - idx0);
-                hi = min(hi, H + TP - idx0);
-                if (lo < hi) {
-                    lrmin = min(lrmin, rr);
-                }
-            };
-            radii(max(r - i0, 0), min(npos - r - i0, jb), r);  // string t: i = i0 + j
-            if (i0 == 0) flag_start(idx0);
+            // Every position's hash is kept, also where its q-gram runs past its string's
+            // end: a window-test block holding such a position holds no interior position
+            // (an interior position's block lies in its window, inside its string's full
+            // q-grams), so its value decides nothing.
+            // Interior positions i in [r, npos - r) of string t (i = i0 + j, j < jb) and of
+            // string t + 1 (i = j - jb), none on the wide path; tile positions only.
+            uint32_t im = r >= WIDE_SENTINEL ? 0u : span(r - i0, min(npos - r - i0, jb));
+            if (i0 == 0) fs0 = idx0;
             if constexpr (TWO) {
-                if (jb < RUN) {  // string t + 1 from run index jb: i = j - jb
-                    radii(jb + r1, min(jb + npos1 - r1, RUN), r1);
-                    flag_start(idx0 + jb);
+                if (jb < RUN) {
+                    if (r1 < WIDE_SENTINEL) im |= span(jb + r1, jb + npos1 - r1);
+                    fs1 = idx0 + jb;
                 }
             }
-            // 16-byte stores of the thread's RUN hash slots and RUN info slots
-            {
-                uint32_t hw[RUN * sizeof(S) / 4];
-#pragma unroll
-                for (int j = 0; j < RUN; j++) {
-                    if constexpr (RANKED) {
-                        if (j & 1) hw[j >> 1] |= (uint32_t)hv[j] << 16;
-                        else hw[j >> 1] = (uint32_t)hv[j] & 0xFFFFu;
-                    } else {
-                        hw[j] = (uint32_t)((uint64_t)hv[j] >> 32);
-                    }
-                }
-                uint4 *dst = reinterpret_cast<uint4 *>(bufA + idx0);
-#pragma unroll
-                for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++)
-                    dst[i] = make_uint4(hw[4 * i], hw[4 * i + 1], hw[4 * i + 2], hw[4 * i + 3]);
-                uint32_t iw[RUN / 2];
-#pragma unroll
-                for (int j = 0; j < RUN / 2; j++) iw[j] = (uint32_t)inf[2 * j] | ((uint32_t)inf[2 * j + 1] << 16);
-                uint4 *di = reinterpret_cast<uint4 *>(pinfo + idx0);
-#pragma unroll
-                for (int i = 0; i < RUN / 8; i++)
-                    di[i] = make_uint4(iw[4 * i], iw[4 * i + 1], iw[4 * i + 2], iw[4 * i + 3]);
-            }
+            imask = im & span(H - idx0, H + TP - idx0);
+            rA = r;
+            rB = r1;
+            jbv = jb;
         };
         // one body per wave: where a lane needs fast2, every fast lane of the wave takes it
         // (it covers the fast1 case), so the wave does not run both
         const bool wave_two = __any(fast2);
-        if (fast1 && !wave_two) {
-            hash_run(std::false_type{});
-        } else if (fast1 || fast2) {
-            hash_run(std::true_type{});
-        } else {
-            uint64_t G = 0;
-            int64_t have_end = -1;  // G is valid for the previous position in the same string
+        if (fast1 && !wave_two) codes(std::false_type{});
+        else if (fast1 || fast2) codes(std::true_type{});
+        else slowp = true;
+    }
+    int lrmin = 0x7FFFFFFF;
+    for (int rho = 0; rho < reps; rho++) {
+        const uint64_t salt = mix64(seed + (uint64_t)rho + GAMMA);
+        if (rho > 0) {
+            load_rank(rho);
+            __syncthreads();  // the previous repetition is done with the flags, keys and table
+            for (int w = tid; w < REGION / 32; w += AT_THREADS) aflag[w] = 0;
+            store_rank();
+            __syncthreads();
+        }
+        // hashes of the thread's RUN positions into LDS
+        if (!slowp) {
+            uint32_t hw[RUN * sizeof(S) / 4];
 #pragma unroll
             for (int j = 0; j < RUN; j++) {
+                if constexpr (RANKED) {
+                    const uint32_t h = rank_s[Gs[j]];
+                    if (j & 1) hw[j >> 1] |= h << 16;
+                    else hw[j >> 1] = h;
+                } else {
+                    hw[j] = (uint32_t)(pi_of<TABLE>((uint64_t)Gs[j], salt, table) >> 32);
+                }
+            }
+            uint4 *dst = reinterpret_cast<uint4 *>(bufA + idx0);
+#pragma unroll
+            for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++)
+                dst[i] = make_uint4(hw[4 * i], hw[4 * i + 1], hw[4 * i + 2], hw[4 * i + 3]);
+            if (fs0 >= 0) flag_start(fs0);
+            if (fs1 >= 0) flag_start(fs1);
+        } else {
+            int ts = t;
+            uint64_t G = 0;
+            int64_t have_end = -1;  // G is valid for the previous position in the same string
+#pragma unroll 1
+            for (int j = 0; j < RUN; j++) {  // rolled: few threads take this path
                 const int idx = idx0 + j;
                 if (idx >= NR) {  // region padding: a sentinel that is never a strict minimum
                     bufA[idx] = (S)~0ull;
@@ -674,10 +714,10 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 int64_t sbeg = 0, send = 0;
                 bool valid = g >= 0 && g < total;
                 if (ns >= 0) {
-                    while (t + 1 < ns && td.off[t + 1] <= g) t++;
-                    sbeg = td.off[t];
-                    send = td.off[t + 1];
-                    r = td.r[t];
+                    while (ts + 1 < ns && td.off[ts + 1] <= g) ts++;
+                    sbeg = td.off[ts];
+                    send = td.off[ts + 1];
+                    r = td.r[ts];
                 } else if (valid) {
                     int32_t sidx = owner_of(off, n, g);
                     sbeg = off[sidx];
@@ -702,10 +742,11 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                         have_end = -1;
                     }
                     const bool interior = r < WIDE_SENTINEL && (i >= r) && (i <= npos - 1 - r);
-                    info = (uint16_t)((interior ? r : 0) | (i < npos ? 0x4000 : 0));
+                    info = (uint16_t)(interior ? r : 0);
                     if (i == 0) flag_start(idx);
                     if (interior && idx >= H && idx < H + TP) {
                         lrmin = min(lrmin, r);
+                        imask |= 1u << j;
                     }
                 } else {
                     have_end = -1;
@@ -715,172 +756,176 @@ __global__ __launch_bounds__(AT_THREADS) void k_anchor_tiles(
                 pinfo[idx] = info;
             }
         }
-        // one LDS atomic per wave: the lanes' atomics on one address would serialise
-        for (int d = 32; d >= 1; d >>= 1) lrmin = min(lrmin, __shfl_xor(lrmin, d, 64));
-        if ((tid & 63) == 0 && lrmin < 0x7FFFFFFF) atomicMin(&rmin_s, lrmin);
-    }
-    __syncthreads();
-    // the full hash of region slot idx (~0 where no full q-gram starts): the tie-break of
-    // equal top halves
-    auto exact64 = [&](int idx) -> uint64_t {
-        if (((pinfo[idx] >> 14) & 1u) == 0) return ~0ull;
-        uint64_t G = 0;
-        for (int k = 0; k < q; k++) G = (G << bits) | ch[sh + idx + k];
-        G &= gmask;
-        return pi_of<TABLE>(G, salt, table);
-    };
-    (void)exact64;
-    // ---- window test.  Blocks of B = 2^k positions with B - 1 <= every interior radius of
-    // the tile and B <= RUN (so a block is a part of one thread's run): a block lies inside
-    // the window of each of its positions, so an anchor is the unique minimum of its block.
-    // Each thread finds the unique minima of its blocks and stores the prefix minima (bufB)
-    // and suffix minima (bufA) within blocks; each such candidate is then checked against
-    // the rest of its window: whole blocks through their minima (the prefix minimum at the
-    // block's end), the two partial blocks through one suffix and one prefix minimum.
-    if (rmin_s != 0x7FFFFFFF) {  // some tile position is interior
-        constexpr int RUN = REGION / AT_THREADS;
-        const int Bv = min(RUN, 1 << (31 - __clz(rmin_s + 1)));
-        // the block size as a compile-time constant, so that the block-boundary selects of
-        // the prefix and suffix minima and the block loops fold away
-        auto window = [&](auto bconst) {
-            constexpr int B = decltype(bconst)::value;
-            constexpr int bm = B - 1;
-            const int idx0 = tid * RUN;
-            KT v[RUN];
-            {
-                uint4 raw[RUN * sizeof(S) / 16];
-#pragma unroll
-                for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++) raw[i] = reinterpret_cast<const uint4 *>(bufA + idx0)[i];
-                const uint32_t *w = reinterpret_cast<const uint32_t *>(raw);
-#pragma unroll
-                for (int j = 0; j < RUN; j++) {
-                    if constexpr (RANKED) v[j] = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-                    else v[j] = w[j];
-                }
+        if (rho == 0) {
+            // the smallest interior radius (the same in every repetition): the tile
+            // descriptor's, else (more strings than it holds: every thread on the general
+            // path) reduced over the block, one LDS atomic per wave, as the lanes' atomics
+            // on one address would serialise
+            if (ns < 0) {
+                for (int d = 32; d >= 1; d >>= 1) lrmin = min(lrmin, __shfl_xor(lrmin, d, 64));
+                if ((tid & 63) == 0 && lrmin < 0x7FFFFFFF) atomicMin(&rmin_s, lrmin);
+            } else if (tid == 0) {
+                rmin_s = td.rmin;
             }
-            KT pre[RUN], suf[RUN];
-#pragma unroll
-            for (int j = 0; j < RUN; j++) pre[j] = (j & bm) == 0 ? v[j] : min(pre[j > 0 ? j - 1 : 0], v[j]);
-#pragma unroll
-            for (int j = RUN - 1; j >= 0; j--)
-                suf[j] = ((j + 1) & bm) == 0 ? v[j] : min(suf[j + 1 < RUN ? j + 1 : j], v[j]);
-            // bit j: v[j] is strictly below every other key of its block
-            uint32_t cand = 0;
-#pragma unroll
-            for (int j = 0; j < RUN; j++) {
-                const KT before = (j & bm) == 0 ? (KT)~0u : pre[j > 0 ? j - 1 : 0];
-                const KT after = ((j + 1) & bm) == 0 ? (KT)~0u : suf[j + 1 < RUN ? j + 1 : j];
-                cand |= (v[j] < before && v[j] < after) ? 1u << j : 0u;
-            }
-            if constexpr (!RANKED) {
-                // blocks whose minimum top half several positions hold: their unique minimum,
-                // if any, by the full hashes of those positions
-                uint32_t tied = 0;
-#pragma unroll
-                for (int j = 0; j < RUN; j++) tied |= v[j] == min(pre[j], suf[j]) ? 1u << j : 0u;
-                constexpr uint32_t bbits = B >= 32 ? ~0u : (1u << B) - 1u;
-                for (int b0 = 0; b0 < RUN; b0 += B) {
-                    uint32_t tb = tied & (bbits << b0);
-                    if (__popc(tb) < 2) continue;
-                    uint64_t e = ~0ull;
-                    int je = -1;
-                    bool dup = false;
-                    for (; tb; tb &= tb - 1) {
-                        const int j = __ffs(tb) - 1;
-                        const uint64_t x = exact64(idx0 + j);
-                        if (x < e) {
-                            e = x;
-                            je = j;
-                            dup = false;
-                        } else if (x == e) {
-                            dup = true;
-                        }
-                    }
-                    if (!dup && e != ~0ull) cand |= 1u << je;
-                }
-            }
-            {
-                uint32_t pw[RUN * sizeof(S) / 4], sw[RUN * sizeof(S) / 4];
-#pragma unroll
-                for (int j = 0; j < RUN; j++) {
-                    if constexpr (RANKED) {
-                        if (j & 1) {
-                            pw[j >> 1] |= (uint32_t)pre[j] << 16;
-                            sw[j >> 1] |= (uint32_t)suf[j] << 16;
-                        } else {
-                            pw[j >> 1] = (uint32_t)pre[j];
-                            sw[j >> 1] = (uint32_t)suf[j];
-                        }
-                    } else {
-                        pw[j] = pre[j];
-                        sw[j] = suf[j];
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++) {
-                    reinterpret_cast<uint4 *>(bufB + idx0)[i] = make_uint4(pw[4 * i], pw[4 * i + 1], pw[4 * i + 2], pw[4 * i + 3]);
-                    reinterpret_cast<uint4 *>(bufA + idx0)[i] = make_uint4(sw[4 * i], sw[4 * i + 1], sw[4 * i + 2], sw[4 * i + 3]);
-                }
-            }
-            __syncthreads();
-            constexpr int lb2 = B >= 16 ? 4 : B >= 8 ? 3 : B >= 4 ? 2 : B >= 2 ? 1 : 0;  // log2 B
-            for (; cand; cand &= cand - 1) {
-                const int p = idx0 + __ffs(cand) - 1;
-                if (p < H || p >= H + TP) continue;  // not a tile position
-                const int r = pinfo[p] & 0x3FFF;
-                if (r == 0) continue;  // not an interior position
-                const KT hv = bufA[p];  // its key: the suffix minimum from a block's minimum
-                const int bk = p >> lb2;
-                // strictly below every other key of the window: an anchor; above one: not;
-                // equal to one (ranks: equal hashes, not strict): hashes decide by full value
-                bool below = false, tie = false;
-                auto see = [&](KT x) {
-                    below |= x < hv;
-                    tie |= x == hv;
-                };
-                const int L = p - r, lb = L >> lb2;
-                if (lb < bk) {
-                    see(bufA[L]);
-                    for (int b2 = lb + 1; !below && b2 < bk; b2++) see(bufB[(b2 << lb2) + bm]);
-                }
-                const int R = p + r, rb = R >> lb2;
-                if (!below && rb > bk) {
-                    for (int b2 = bk + 1; !below && b2 < rb; b2++) see(bufB[(b2 << lb2) + bm]);
-                    if (!below) see(bufB[R]);
-                }
-                bool ok = !below && !tie;
-                if constexpr (!RANKED) {
-                    if (!below && tie) {
-                        const uint64_t ep = exact64(p);
-                        ok = true;
-                        for (int dd = 1; ok && dd <= r; dd++) ok = exact64(p - dd) > ep && exact64(p + dd) > ep;
-                    }
-                }
-                if (ok) atomicOr(&aflag[(p - H) >> 5], 1u << ((p - H) & 31));
-            }
-            __syncthreads();
+        }
+        __syncthreads();
+        // the full hash of region slot idx: the tie-break of equal top halves (only blocks
+        // and windows of interior positions, where every slot starts a full q-gram, use it)
+        auto exact64 = [&](int idx) -> uint64_t {
+            uint64_t G = 0;
+            for (int k = 0; k < q; k++) G = (G << bits) | ch[sh + idx + k];
+            G &= gmask;
+            return pi_of<TABLE>(G, salt, table);
         };
-        switch (Bv) {
-            case 1: window(std::integral_constant<int, 1>{}); break;
-            case 2: window(std::integral_constant<int, 2>{}); break;
-            case 4: window(std::integral_constant<int, 4>{}); break;
-            case 8: window(std::integral_constant<int, 8>{}); break;
-            default: window(std::integral_constant<int, RUN>{}); break;  // 16 (RUN == 16)
+        (void)exact64;
+        // ---- window test.  Blocks of B = 2^k positions with B - 1 <= every interior radius
+        // of the tile and B <= RUN (so a block is a part of one thread's run): a block lies
+        // inside the window of each of its positions, so an anchor is the unique minimum of
+        // its block.  Each thread finds the unique minima of its blocks and stores the
+        // prefix minima (bufB) and suffix minima (bufA) within blocks; each such candidate
+        // is then checked against the rest of its window: whole blocks through their minima
+        // (the prefix minimum at the block's end), the two partial blocks through one suffix
+        // and one prefix minimum.
+        if (rmin_s != 0x7FFFFFFF) {  // some tile position is interior
+            const int Bv = min(RUN, 1 << (31 - __clz(rmin_s + 1)));
+            // the block size as a compile-time constant, so that the block-boundary selects
+            // of the prefix and suffix minima and the block loops fold away
+            auto window = [&](auto bconst) {
+                constexpr int B = decltype(bconst)::value;
+                constexpr int bm = B - 1;
+                KT v[RUN];
+                {
+                    uint4 raw[RUN * sizeof(S) / 16];
+#pragma unroll
+                    for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++) raw[i] = reinterpret_cast<const uint4 *>(bufA + idx0)[i];
+                    const uint32_t *w = reinterpret_cast<const uint32_t *>(raw);
+#pragma unroll
+                    for (int j = 0; j < RUN; j++) {
+                        if constexpr (RANKED) v[j] = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+                        else v[j] = w[j];
+                    }
+                }
+                KT pre[RUN], suf[RUN];
+#pragma unroll
+                for (int j = 0; j < RUN; j++) pre[j] = (j & bm) == 0 ? v[j] : min(pre[j > 0 ? j - 1 : 0], v[j]);
+#pragma unroll
+                for (int j = RUN - 1; j >= 0; j--)
+                    suf[j] = ((j + 1) & bm) == 0 ? v[j] : min(suf[j + 1 < RUN ? j + 1 : j], v[j]);
+                // bit j: v[j] is strictly below every other key of its block, that is the
+                // only key of the block equal to the block's minimum (its last prefix minimum)
+                uint32_t cand = 0;
+#pragma unroll
+                for (int b0 = 0; b0 < RUN; b0 += B) {
+                    uint32_t eq = 0;
+#pragma unroll
+                    for (int j = b0; j < b0 + B; j++) eq |= v[j] == pre[b0 + bm] ? 1u << j : 0u;
+                    if (__popc(eq) == 1) {
+                        cand |= eq;
+                    } else if constexpr (!RANKED) {
+                        // several positions hold the minimum top half: their unique minimum,
+                        // if any, by their full hashes (equal ranks are equal hashes: none)
+                        uint64_t e = ~0ull;
+                        int je = -1;
+                        bool dup = false;
+                        for (; eq; eq &= eq - 1) {
+                            const int j = __ffs(eq) - 1;
+                            const uint64_t x = exact64(idx0 + j);
+                            if (x < e) {
+                                e = x;
+                                je = j;
+                                dup = false;
+                            } else if (x == e) {
+                                dup = true;
+                            }
+                        }
+                        if (!dup && e != ~0ull) cand |= 1u << je;
+                    }
+                }
+                cand &= imask;  // interior tile positions only
+                {
+                    uint32_t pw[RUN * sizeof(S) / 4], sw[RUN * sizeof(S) / 4];
+#pragma unroll
+                    for (int j = 0; j < RUN; j++) {
+                        if constexpr (RANKED) {
+                            if (j & 1) {
+                                pw[j >> 1] |= (uint32_t)pre[j] << 16;
+                                sw[j >> 1] |= (uint32_t)suf[j] << 16;
+                            } else {
+                                pw[j >> 1] = (uint32_t)pre[j];
+                                sw[j >> 1] = (uint32_t)suf[j];
+                            }
+                        } else {
+                            pw[j] = pre[j];
+                            sw[j] = suf[j];
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < (int)(RUN * sizeof(S) / 16); i++) {
+                        reinterpret_cast<uint4 *>(bufB + idx0)[i] = make_uint4(pw[4 * i], pw[4 * i + 1], pw[4 * i + 2], pw[4 * i + 3]);
+                        reinterpret_cast<uint4 *>(bufA + idx0)[i] = make_uint4(sw[4 * i], sw[4 * i + 1], sw[4 * i + 2], sw[4 * i + 3]);
+                    }
+                }
+                __syncthreads();
+                constexpr int lb2 = B >= 16 ? 4 : B >= 8 ? 3 : B >= 4 ? 2 : B >= 2 ? 1 : 0;  // log2 B
+                for (; cand; cand &= cand - 1) {
+                    const int j = __ffs(cand) - 1;
+                    const int p = idx0 + j;
+                    const int r = slowp ? (int)pinfo[p] : (j < jbv ? rA : rB);
+                    if (r == 0) continue;  // radii are at least 1: kept as a guard
+                    const KT hv = bufA[p];  // its key: the suffix minimum from a block's minimum
+                    const int bk = p >> lb2;
+                    // strictly below every other key of the window: an anchor; above one:
+                    // not; equal to one (ranks: equal hashes, not strict): hashes decide by
+                    // full value
+                    bool below = false, tie = false;
+                    auto see = [&](KT x) {
+                        below |= x < hv;
+                        tie |= x == hv;
+                    };
+                    const int L = p - r, lb = L >> lb2;
+                    if (lb < bk) {
+                        see(bufA[L]);
+                        for (int b2 = lb + 1; !below && b2 < bk; b2++) see(bufB[(b2 << lb2) + bm]);
+                    }
+                    const int R = p + r, rb = R >> lb2;
+                    if (!below && rb > bk) {
+                        for (int b2 = bk + 1; !below && b2 < rb; b2++) see(bufB[(b2 << lb2) + bm]);
+                        if (!below) see(bufB[R]);
+                    }
+                    bool ok = !below && !tie;
+                    if constexpr (!RANKED) {
+                        if (!below && tie) {
+                            const uint64_t ep = exact64(p);
+                            ok = true;
+                            for (int dd = 1; ok && dd <= r; dd++) ok = exact64(p - dd) > ep && exact64(p + dd) > ep;
+                        }
+                    }
+                    if (ok) atomicOr(&aflag[(p - H) >> 5], 1u << ((p - H) & 31));
+                }
+                __syncthreads();
+            };
+            switch (Bv) {
+                case 1: window(std::integral_constant<int, 1>{}); break;
+                case 2: window(std::integral_constant<int, 2>{}); break;
+                case 4: window(std::integral_constant<int, 4>{}); break;
+                case 8: window(std::integral_constant<int, 8>{}); break;
+                default: window(std::integral_constant<int, RUN>{}); break;  // 16 (RUN == 16)
+            }
         }
-    }
-    // one bit per position: string start or anchor (TP is a multiple of 64)
-    const int rem = (int)min<int64_t>(total - tile_start, (int64_t)TP);  // tile positions in the input
-    // TP / 64 < 64 words: the first wave writes them all and adds up their bits
-    if (tid < 64) {
-        uint32_t mine = 0;
-        if (64 * tid < rem) {
-            uint64_t v = (uint64_t)aflag[2 * tid] | ((uint64_t)aflag[2 * tid + 1] << 32);
-            if (rem - 64 * tid < 64) v &= (1ull << (rem - 64 * tid)) - 1ull;
-            bitmap[(tile_start >> 6) + tid] = v;
-            mine = (uint32_t)__popcll(v);
+        // one bit per position: string start or anchor (TP is a multiple of 64)
+        const int rem = (int)min<int64_t>(total - tile_start, (int64_t)TP);  // tile positions in the input
+        // TP / 64 < 64 words: the first wave writes them all and adds up their bits
+        if (tid < 64) {
+            uint32_t mine = 0;
+            if (64 * tid < rem) {
+                uint64_t v = (uint64_t)aflag[2 * tid] | ((uint64_t)aflag[2 * tid + 1] << 32);
+                if (rem - 64 * tid < 64) v &= (1ull << (rem - 64 * tid)) - 1ull;
+                bitmap[(int64_t)rho * bm_stride + (tile_start >> 6) + tid] = v;
+                mine = (uint32_t)__popcll(v);
+            }
+            for (int d = 32; d >= 1; d >>= 1) mine += (uint32_t)__shfl_xor((int)mine, d, 64);
+            if (tid == 0) tile_count[(int64_t)rho * tc_stride + blockIdx.x] = mine;
         }
-        for (int d = 32; d >= 1; d >>= 1) mine += (uint32_t)__shfl_xor((int)mine, d, 64);
-        if (tid == 0) tile_count[blockIdx.x] = mine;
     }
 }
 
@@ -1284,6 +1329,55 @@ void RecBuf::release() {
     key = val = nullptr; len = nullptr; cap = count = 0;
 }
 
+// Anchors and string starts of every repetition: their bitmaps (nw + 1 words each) and
+// per-tile counts (ntiles + 1 each) in one workspace block apiece, filled by one launch of
+// the tile kernel over all repetitions, then by the wide-radius kernels per repetition.
+static void anchor_launch(const DevStrings &d, const PartitionParams &p, int reps, int TP, int H,
+                          int region, int64_t ntiles, const TileDesc *ts, Workspace &ws,
+                          hipStream_t s, std::vector<uint64_t *> &bitmap,
+                          std::vector<uint32_t *> &tcount) {
+    const int64_t nw = (d.total + 63) / 64;
+    const int code_bits = p.q * d.bits;
+    const int aligned4 = ((uintptr_t)d.chars & 3) == 0 ? 1 : 0;
+    const int packed = d.packing == MJ_PACK_2BIT ? 1 : 0;
+    uint64_t *bm_all = ws.get_n<uint64_t>((size_t)reps * (nw + 1));
+    uint32_t *tc_all = ws.get_n<uint32_t>((size_t)reps * (ntiles + 1));
+    for (int rho = 0; rho < reps; rho++) {
+        bitmap[rho] = bm_all + (int64_t)rho * (nw + 1);
+        tcount[rho] = tc_all + (int64_t)rho * (ntiles + 1);
+    }
+    // rank tables one after another, each on a 16-byte boundary (with 16 bytes of slack)
+    const int rstride = code_bits <= RANK_MAX_BITS ? ((1 << code_bits) + 7) & ~7 : 0;
+    uint16_t *rank = rstride ? ws.get_n<uint16_t>((size_t)reps * rstride + 8) : nullptr;
+    if (rank) {
+        const int nc = 1 << code_bits;
+        for (int rho = 0; rho < reps; rho++) {
+            const uint64_t salt = mix64(p.seed + (uint64_t)rho + GAMMA);
+            hipLaunchKernelGGL(k_rank_table, dim3((nc + 3) / 4), dim3(256), 0, s, nc, salt,
+                               p.pi_table, rank + (int64_t)rho * rstride);
+            MJ_LAUNCH_CHECK();
+        }
+    }
+    const size_t rank_lds = rank ? ((size_t)2 << code_bits) + 16 : 0;
+#define MJ_ANCHORS(R, V, T)                                                                     \
+    hipLaunchKernelGGL((k_anchor_tiles<R, V, T>), dim3((unsigned)ntiles), dim3(AT_THREADS), rank_lds, s, \
+                       d.chars, d.offsets, d.n, d.total, p.q, d.bits, p.seed, reps, p.pi_table, \
+                       rank, rstride, d.rr, TP, H, ts, aligned4, packed, bm_all, nw + 1, tc_all, \
+                       ntiles + 1)
+    if (rank) {
+        if (region == 2048) MJ_ANCHORS(2048, uint32_t, false); else MJ_ANCHORS(4096, uint32_t, false);
+    } else if (p.pi_table) {
+        if (region == 2048) MJ_ANCHORS(2048, uint64_t, true); else MJ_ANCHORS(4096, uint64_t, true);
+    } else {
+        if (region == 2048) MJ_ANCHORS(2048, uint64_t, false); else MJ_ANCHORS(4096, uint64_t, false);
+    }
+#undef MJ_ANCHORS
+    MJ_LAUNCH_CHECK();
+    const WideBufs wb = wide_setup(d, p.q, ws, s);
+    for (int rho = 0; rho < reps; rho++)
+        wide_anchors(d, wb, p, mix64(p.seed + (uint64_t)rho + GAMMA), TP, bitmap[rho], tcount[rho], s);
+}
+
 int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t halo, RecBuf &out,
                           Workspace &ws, hipStream_t s, uint64_t *host_scratch, KTimer *kt) {
     if (d.total == 0) return 0;
@@ -1308,39 +1402,12 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
     TileDesc *ts = ws.get_n<TileDesc>(ntiles + 1);
     hipLaunchKernelGGL(k_tile_desc, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s,
-                       d.offsets, d.rr, d.n, d.total, ntiles, TP, H, region, ts);
+                       d.offsets, d.rr, d.n, d.total, ntiles, TP, H, region, p.q, ts);
     MJ_LAUNCH_CHECK();
     std::vector<uint64_t *> bitmap(reps);
     std::vector<uint32_t *> tcount(reps), pre(reps);  // per tile: flagged positions, their scan
-    uint16_t *rank = code_bits <= RANK_MAX_BITS ? ws.get_n<uint16_t>((size_t)1 << code_bits) : nullptr;
-    const WideBufs wb = wide_setup(d, p.q, ws, s);
-    for (int rho = 0; rho < reps; rho++) {
-        const uint64_t salt = mix64(p.seed + (uint64_t)rho + GAMMA);
-        bitmap[rho] = ws.get_n<uint64_t>(nw + 1);
-        tcount[rho] = ws.get_n<uint32_t>(ntiles + 1);
-        if (rank) {
-            const int nc = 1 << code_bits;
-            hipLaunchKernelGGL(k_rank_table, dim3((nc + 3) / 4), dim3(256), 0, s, nc, salt,
-                               p.pi_table, rank);
-            MJ_LAUNCH_CHECK();
-        }
-#define MJ_ANCHORS(R, V, T)                                                                     \
-        hipLaunchKernelGGL((k_anchor_tiles<R, V, T>), dim3((unsigned)ntiles), dim3(AT_THREADS), rank_lds, s, \
-                           d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, rank, \
-                           d.rr, TP, H, ts, aligned4, packed, bitmap[rho], tcount[rho])
-        const size_t rank_lds = rank ? ((size_t)2 << code_bits) + 16 : 0;
-        if (rank) {
-            if (region == 2048) MJ_ANCHORS(2048, uint32_t, false); else MJ_ANCHORS(4096, uint32_t, false);
-        } else if (p.pi_table) {
-            if (region == 2048) MJ_ANCHORS(2048, uint64_t, true); else MJ_ANCHORS(4096, uint64_t, true);
-        } else {
-            if (region == 2048) MJ_ANCHORS(2048, uint64_t, false); else MJ_ANCHORS(4096, uint64_t, false);
-        }
-#undef MJ_ANCHORS
-        MJ_LAUNCH_CHECK();
-        wide_anchors(d, wb, p, salt, TP, bitmap[rho], tcount[rho], s);
-    }
-    if (kt) kt->end(th, s, reps);
+    anchor_launch(d, p, reps, TP, H, region, ntiles, ts, ws, s, bitmap, tcount);
+    if (kt) kt->end(th, s, 1);
     for (int rho = 0; rho < reps; rho++) {
         pre[rho] = ws.get_n<uint32_t>(ntiles + 1);
         exclusive_scan_u32(tcount[rho], pre[rho], ntiles, ws, s);
@@ -1449,40 +1516,13 @@ int64_t partition_records_streamed(const DevStrings &d, const PartitionParams &p
     int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
     TileDesc *ts = ws.get_n<TileDesc>(ntiles + 1);
     hipLaunchKernelGGL(k_tile_desc, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s,
-                       d.offsets, d.rr, d.n, d.total, ntiles, TP, H, region, ts);
+                       d.offsets, d.rr, d.n, d.total, ntiles, TP, H, region, p.q, ts);
     MJ_LAUNCH_CHECK();
     std::vector<uint64_t *> bitmap(reps);
     std::vector<uint32_t *> tcount(reps);
     uint32_t *pre_all = ws.get_n<uint32_t>((size_t)reps * (ntiles + 1));
-    uint16_t *rank = code_bits <= RANK_MAX_BITS ? ws.get_n<uint16_t>((size_t)1 << code_bits) : nullptr;
-    const WideBufs wb = wide_setup(d, p.q, ws, s);
-    for (int rho = 0; rho < reps; rho++) {
-        const uint64_t salt = mix64(p.seed + (uint64_t)rho + GAMMA);
-        bitmap[rho] = ws.get_n<uint64_t>(nw + 1);
-        tcount[rho] = ws.get_n<uint32_t>(ntiles + 1);
-        if (rank) {
-            const int nc = 1 << code_bits;
-            hipLaunchKernelGGL(k_rank_table, dim3((nc + 3) / 4), dim3(256), 0, s, nc, salt,
-                               p.pi_table, rank);
-            MJ_LAUNCH_CHECK();
-        }
-        const size_t rank_lds = rank ? ((size_t)2 << code_bits) + 16 : 0;
-#define MJ_ANCHORS(R, V, T)                                                                     \
-        hipLaunchKernelGGL((k_anchor_tiles<R, V, T>), dim3((unsigned)ntiles), dim3(AT_THREADS), rank_lds, s, \
-                           d.chars, d.offsets, d.n, d.total, p.q, d.bits, salt, p.pi_table, rank, \
-                           d.rr, TP, H, ts, aligned4, packed, bitmap[rho], tcount[rho])
-        if (rank) {
-            if (region == 2048) MJ_ANCHORS(2048, uint32_t, false); else MJ_ANCHORS(4096, uint32_t, false);
-        } else if (p.pi_table) {
-            if (region == 2048) MJ_ANCHORS(2048, uint64_t, true); else MJ_ANCHORS(4096, uint64_t, true);
-        } else {
-            if (region == 2048) MJ_ANCHORS(2048, uint64_t, false); else MJ_ANCHORS(4096, uint64_t, false);
-        }
-#undef MJ_ANCHORS
-        MJ_LAUNCH_CHECK();
-        wide_anchors(d, wb, p, salt, TP, bitmap[rho], tcount[rho], s);
-    }
-    if (kt) kt->end(th, s, reps);
+    anchor_launch(d, p, reps, TP, H, region, ntiles, ts, ws, s, bitmap, tcount);
+    if (kt) kt->end(th, s, 1);
     for (int rho = 0; rho < reps; rho++)
         exclusive_scan_u32(tcount[rho], pre_all + (int64_t)rho * (ntiles + 1), ntiles, ws, s);
     int64_t *base_dev = ws.get_n<int64_t>(reps + 1);
