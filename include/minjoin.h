@@ -120,9 +120,9 @@ typedef struct {
     int64_t band_cells;  /* (columns processed) x (K + 1 band diagonals), summed over candidates */
     float stage_ms[8];
     /* Device time of the hot kernels, summed over their launches in the call (HIP events
-     * recorded on the call's stream around the launches), and the launch counts: 0 anchors
-     * (one launch covers every repetition), 1 partition records (one per repetition),
-     * 2 candidate emission, 3 verification. */
+     * recorded on the call's stream around the launches), and the launch counts: 0 anchors,
+     * 1 partition records (each one launch, or one pair of launches, covering every
+     * repetition), 2 candidate emission, 3 verification. */
     float kernel_ms[4];
     int32_t kernel_launches[4];
     int64_t positions;   /* symbols scanned by the anchor kernel, over all repetitions */

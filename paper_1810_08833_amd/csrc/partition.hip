@@ -1075,14 +1075,13 @@ __global__ __launch_bounds__(64) void k_anchor_scatter(const uint64_t *__restric
     if (t == ntiles - 1 && lane == 63) apos[tile_pre[ntiles]] = total;
 }
 
+// ---------------------------------------------------------------- partition records
 // Partition records between consecutive flagged positions: key f = M(Phi xor S) with
 // Phi the Karp-Rabin polynomial of the content over GF(2^61-1), length folded in as the
-// leading coefficient; payload (string id << 32 | start position).  The owning string
-// comes from the descriptor of the tile holding the partition's first position.
-// Horner's rule takes 8 symbols per step: Phi <- Phi * B^8 + sum_k (x_k + 1) B^(7-k), the
-// sum read from tables in LDS, and a shorter tail 4 symbols and then 1 symbol at a time.
-// Modular arithmetic is exact, so this is the same Phi as one symbol per step.  Symbols
-// come four at a time from aligned 32-bit words; codes are taken modulo 2^b.
+// leading coefficient, Phi = L B^L + sum_{g0 <= i < g1} (x_i + 1) B^(g1-1-i) for the
+// partition [g0, g1) of length L (Horner's rule started from L); payload (string id << 32 |
+// start position).  The owning string comes from the descriptor of the tile holding the
+// partition's first position; symbol codes are taken modulo 2^b.
 __device__ __forceinline__ uint64_t horner_step(uint64_t h, uint64_t B, uint32_t c) {
     h = mulmod61(h, B) + (uint64_t)c + 1;
     return h >= P61 ? h - P61 : h;
@@ -1119,16 +1118,27 @@ __global__ void k_phi_table(int nc, int bits, uint64_t B, int pt, int lsb, uint6
 constexpr int REC_THREADS = 256;
 constexpr int REC_STAGE_WORDS = 6144;  // 24 KB: the symbols of a block's records
 
-// One thread per record; a block takes 256 consecutive records per sweep.  STAGED (long
-// partitions): their symbols form one contiguous range, which the block first copies to
-// LDS with coalesced word loads (a lane reading its own partition directly touches a line
-// per lane and load); a range longer than the stage is read from global memory instead.
-// Short partitions are read directly: the copy and its barriers would cost more.
+// Horner's rule over partitions, one thread each, 8 symbols per step: Phi <- Phi B^8 +
+// sum_k (x_k + 1) B^(7-k), the sum read from tables in LDS, a shorter tail 4 symbols and
+// then 1 symbol at a time (modular arithmetic is exact: the same Phi as one symbol per
+// step).  Symbols come four at a time from aligned 32-bit words.  Two uses:
+//  - every partition of one repetition, between consecutive positions of apos (R of them,
+//    or *Rdev on the device; records from *base_dev when given), a block taking 256
+//    consecutive records per sweep.  STAGED (long partitions): their symbols form one
+//    contiguous range, which the block first copies to LDS with coalesced word loads (a
+//    lane reading its own partition directly touches a line per lane and load); a range
+//    longer than the stage is read from global memory instead.  Short partitions are read
+//    directly: the copy and its barriers would cost more.
+//  - CROSS: the partitions that run past the tile of their first position, from the slots
+//    k_records_tiles fills (per repetition and tile: first position, record index; -1:
+//    none; ntiles slots per repetition): the partition ends at the next flagged position
+//    of the repetition's bitmap, or at the input's end.
 // PACKED: 2-bit input (four symbols per byte, the first in the low bits); a packed byte is
 // a 4-symbol chunk and, with the chunk tables built in that order, its own table index.
-template <bool STAGED, bool PACKED>
+template <bool STAGED, bool PACKED, bool CROSS = false>
 __global__ __launch_bounds__(REC_THREADS) void k_records(
-    const int64_t *__restrict__ apos, int64_t R, const int64_t *__restrict__ off, int32_t n,
+    const int64_t *__restrict__ apos, int64_t R, int64_t ntiles, const uint64_t *__restrict__ bitmap,
+    int64_t bm_stride, const int64_t *__restrict__ off, int32_t n,
     const uint8_t *__restrict__ chars, int64_t total, int aligned4,
     const TileDesc *__restrict__ td, int TP, uint64_t B, uint64_t salt_f,
     const uint64_t *__restrict__ table, int pt, int bits, uint64_t B4, uint64_t B8, uint64_t *key,
@@ -1234,6 +1244,37 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
             sbeg = off[sidx];
         }
     };
+    if constexpr (CROSS) {
+        static_assert(!STAGED, "partitions that run past their tile are read directly");
+        __syncthreads();  // the table is in place
+        const int64_t nw = (total + 63) / 64;
+        for (int64_t c = (int64_t)blockIdx.x * REC_THREADS + threadIdx.x; c < R;
+             c += (int64_t)gridDim.x * REC_THREADS) {
+            const int64_t g0 = apos[2 * c], k = apos[2 * c + 1], rho = c / ntiles;
+            if (g0 < 0) continue;  // a tile without flags
+            // the next flagged position after g0 (past its tile), else the end of the input
+            const uint64_t *bm = bitmap + rho * bm_stride;
+            int64_t wd = g0 >> 6, g1 = total;
+            uint64_t bw = (g0 & 63) == 63 ? 0ull : bm[wd] & (~0ull << ((g0 & 63) + 1));
+            while (true) {
+                if (bw) {
+                    g1 = 64 * wd + __ffsll((unsigned long long)bw) - 1;
+                    break;
+                }
+                if (++wd >= nw) break;
+                bw = bm[wd];
+            }
+            int32_t sidx;
+            int64_t sbeg;
+            owner(g0, sidx, sbeg);
+            const int64_t L = g1 - g0;
+            const uint64_t h = hash((uint64_t)L, g0, g1, gend, gsym, gword);  // L < 2^31 < p
+            key[k] = mix64(h ^ salt_f);
+            val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
+            if (len) len[k] = (uint32_t)L;
+        }
+        return;
+    }
     if constexpr (!STAGED) {
         __syncthreads();  // the table is in place
         for (int64_t k = (int64_t)blockIdx.x * REC_THREADS + threadIdx.x; k < R;
@@ -1243,7 +1284,7 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
             int64_t sbeg;
             owner(g0, sidx, sbeg);
             const int64_t L = g1 - g0;
-            const uint64_t h = hash((uint64_t)L % P61, g0, g1, gend, gsym, gword);
+            const uint64_t h = hash((uint64_t)L, g0, g1, gend, gsym, gword);  // L < 2^31 < p
             key[k] = mix64(h ^ salt_f);
             val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
             if (len) len[k] = (uint32_t)L;
@@ -1282,7 +1323,7 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
         int64_t sbeg;
         owner(g0, sidx, sbeg);
         const int64_t L = g1 - g0;
-        uint64_t h = (uint64_t)L % P61;
+        uint64_t h = (uint64_t)L;  // L < 2^31 < p: already reduced
         if (staged) {
             const uint8_t *sbytes = reinterpret_cast<const uint8_t *>(stage);
             auto ssym = [&](int64_t g) -> uint32_t {
@@ -1300,6 +1341,224 @@ __global__ __launch_bounds__(REC_THREADS) void k_records(
         key[k] = mix64(h ^ salt_f);
         val[k] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
         if (len) len[k] = (uint32_t)L;
+    }
+}
+
+// Field helpers for values below p = 2^61 - 1.
+__device__ __forceinline__ uint64_t addmod61(uint64_t a, uint64_t b) {
+    const uint64_t x = a + b;
+    return x >= P61 ? x - P61 : x;
+}
+__device__ __forceinline__ uint64_t submod61(uint64_t a, uint64_t b) {
+    return a >= b ? a - b : a + P61 - b;
+}
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t x, int d) {
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// pq[d] = B^d and pq[n + 1 + d] = B^-d (binv = B^-1 modulo p), d <= n: square and multiply.
+__global__ void k_pow_tables(uint64_t B, uint64_t binv, int n, uint64_t *__restrict__ pq) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d > n) return;
+    uint64_t pw = 1, qw = 1, b = B, bi = binv;
+    for (int e = d; e; e >>= 1) {
+        if (e & 1) {
+            pw = mulmod61(pw, b);
+            qw = mulmod61(qw, bi);
+        }
+        b = mulmod61(b, b);
+        bi = mulmod61(bi, bi);
+    }
+    pq[d] = pw;
+    pq[n + 1 + d] = qw;
+}
+
+// Partition records of every repetition from one pass over the anchor tiles (TP positions
+// each, TP < REGION).  Over a tile, with tile-relative positions, the field prefix sums
+// U[j] = sum_{i < j} (x_i + 1) B^-i are computed once and serve every repetition: a
+// partition [a, b) inside the tile has sum_{a <= i < b} (x_i + 1) B^(b-1-i) =
+// B^(b-1) (U[b] - U[a]), so Phi = L B^L + B^(b-1) (U[b] - U[a]) with L = b - a, the same
+// field element as Horner's rule gives.  Then each wave takes whole repetitions (wave w:
+// repetitions w, w + 4, ...): lane l holds the tile's flag word l, the lanes' count
+// prefixes rank the flags, which the lanes list in order in the wave's LDS list, and lane
+// i makes the record of flags i and i + 1, at the repetition's base (rbase, on the device)
+// plus the tile's count prefix (pre) plus i.  The partition of the tile's last flag runs
+// past the tile: it goes to the tile's slot of the list for k_records_cross (first
+// position, record index; -1: the tile has no flag).  Blocks stay resident and take tiles
+// in turn, loading the next tile's symbols, descriptor, flags (of the wave's first two
+// repetitions) and record bases while they work on this one.  A thread always takes the
+// same tile positions, so it keeps their powers B^-j in registers; B^d (d <= REGION) is
+// copied to LDS once per block.  U is stored with one unused slot after every 8 (index
+// j + j / 8), so that the lanes' runs of 8 consecutive positions meet different LDS banks.
+constexpr int RT_THREADS = 256;
+constexpr int RT_WAVES = RT_THREADS / 64;
+
+// a c modulo p for a < p and c < 2^32 (2^64 = 8 modulo p)
+__device__ __forceinline__ uint64_t mulsmall61(uint64_t a, uint32_t c) {
+    const uint64_t lo = a * (uint64_t)c, hi = __umul64hi(a, (uint64_t)c);
+    const uint64_t r = (lo & P61) + (lo >> 61) + (hi << 3);
+    return r >= P61 ? r - P61 : r;
+}
+
+// LDS writes of a wave's lanes visible to the wave's other lanes
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int REGION, bool PACKED>
+__global__ __launch_bounds__(RT_THREADS)
+__attribute__((amdgpu_waves_per_eu(REGION == 2048 ? 3 : 1))) void k_records_tiles(
+    const uint8_t *__restrict__ chars, int64_t total, int aligned4, const int64_t *__restrict__ off,
+    int32_t n, const TileDesc *__restrict__ tdesc, int64_t ntiles, int TP, int bits,
+    const uint64_t *__restrict__ bitmap, int64_t bm_stride, const uint32_t *__restrict__ pre,
+    int64_t pre_stride, const int64_t *__restrict__ rbase, int reps,
+    const uint64_t *__restrict__ pq, uint64_t salt_f, uint64_t *__restrict__ key,
+    uint64_t *__restrict__ val, uint32_t *__restrict__ len, int64_t *__restrict__ cross) {
+    constexpr int RUN = REGION / RT_THREADS;  // positions per thread: 8 or 16
+    static_assert(RUN == 8 || RUN == 16, "positions per thread");
+    static_assert(REGION / 64 <= 64, "a tile's flag words fit a wave");
+    constexpr int PADN = REGION + 1 + REGION / 8 + 1;  // padded slots of U
+    __shared__ uint64_t Pt[REGION + 1], U[PADN];
+    __shared__ uint16_t flist[RT_WAVES][REGION];  // each wave's list of flagged positions
+    __shared__ int64_t r0s[64];                    // the tile's record bases, repetitions < 64
+    __shared__ uint64_t wtot[RT_WAVES];
+    __shared__ TileDesc td;
+    auto pad = [](int j) { return j + (j >> 3); };
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i <= REGION; i += RT_THREADS) Pt[i] = pq[i];
+    const uint32_t m = (1u << bits) - 1u;
+    const int nwt = TP / 64;  // TP is a multiple of 64
+    const int64_t nw = (total + 63) / 64;
+    const int j0 = tid * RUN;  // the thread's first tile position
+    uint64_t q[RUN];           // B^-(j0 + k)
+#pragma unroll
+    for (int k = 0; k < RUN; k++) q[k] = pq[REGION + 1 + j0 + k];
+    // loads of one tile: the thread's symbols (0 outside the input), the descriptor's words
+    // (threads < 32), the record base of repetition `tid` (threads < 64), and the tile's
+    // flag word `lane` of repetitions `wave` and `wave + RT_WAVES`
+    uint32_t x[RUN], tdw = 0;
+    int64_t r0l = 0;
+    uint64_t bw0 = 0, bw1 = 0;
+    auto load = [&](int64_t tile) {
+        const int64_t g = tile * TP + j0;
+        if constexpr (PACKED) {
+            // 16 symbols per 32-bit word, the first in the low bits; g is a multiple of 8
+            // and the caller holds whole words
+            const uint32_t *wp = reinterpret_cast<const uint32_t *>(chars);
+            const uint32_t wv = (g >> 4) < ((total + 15) >> 4) ? wp[g >> 4] : 0u;
+            const int sh = (int)(g & 15) * 2;
+#pragma unroll
+            for (int k = 0; k < RUN; k++) x[k] = (wv >> (sh + 2 * k)) & 3u;
+        } else if (aligned4 && g + RUN <= total) {
+            const uint32_t *wp = reinterpret_cast<const uint32_t *>(chars + g);
+#pragma unroll
+            for (int i = 0; i < RUN / 4; i++) {
+                const uint32_t wv = wp[i];
+#pragma unroll
+                for (int k = 0; k < 4; k++) x[4 * i + k] = (wv >> (8 * k)) & 0xFFu;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < RUN; k++) x[k] = g + k < total ? (uint32_t)chars[g + k] : 0u;
+        }
+        if (tid < 32) tdw = reinterpret_cast<const uint32_t *>(tdesc + tile)[tid];
+        if (tid < 64) r0l = tid < reps ? rbase[tid] + (int64_t)pre[tid * pre_stride + tile] : 0;
+        const int64_t w = tile * TP / 64 + lane;
+        const bool ok = lane < nwt && w < nw;
+        bw0 = (wave < reps && ok) ? bitmap[wave * bm_stride + w] : 0ull;
+        bw1 = (wave + RT_WAVES < reps && ok) ? bitmap[(wave + RT_WAVES) * bm_stride + w] : 0ull;
+    };
+    if ((int64_t)blockIdx.x < ntiles) load(blockIdx.x);
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t ts = tile * TP;
+        __syncthreads();  // the previous tile is done with U, td and the bases
+        if (tid < 32) reinterpret_cast<uint32_t *>(&td)[tid] = tdw;
+        if (tid < 64) r0s[tid] = r0l;
+        const uint64_t bc0 = bw0, bc1 = bw1;
+        // U: inclusive sums over the thread's positions, then over the wave, then the block
+        uint64_t v[RUN];
+        uint64_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < RUN; k++) {
+            const uint64_t u = j0 + k < TP ? mulsmall61(q[k], (x[k] & m) + 1u) : 0ull;
+            acc = addmod61(acc, u);
+            v[k] = acc;
+        }
+        // every register of this tile's loads is consumed: the next tile's are issued now
+        // and stay in flight while this one is worked on
+        if (tile + gridDim.x < ntiles) load(tile + gridDim.x);
+        uint64_t incl = acc;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t y = shfl_up64(incl, d);
+            if (lane >= d) incl = addmod61(incl, y);
+        }
+        if (lane == 63) wtot[wave] = incl;
+        __syncthreads();
+        uint64_t before = submod61(incl, acc);
+        for (int w = 0; w < wave; w++) before = addmod61(before, wtot[w]);
+        if (tid == 0) U[pad(0)] = 0;
+#pragma unroll
+        for (int k = 0; k < RUN; k++) U[pad(j0 + k + 1)] = addmod61(before, v[k]);
+        __syncthreads();  // U, td and the bases in place
+        uint16_t *fl = flist[wave];
+        for (int rho = wave, round = 0; rho < reps; rho += RT_WAVES, round++) {
+            // lane l: flag word l of the tile, its count prefix, and the tile's flag count
+            const int64_t w = ts / 64 + lane;
+            const uint64_t b = round == 0 ? bc0
+                             : round == 1 ? bc1
+                                          : ((lane < nwt && w < nw) ? bitmap[rho * bm_stride + w] : 0ull);
+            const int64_t r0 = rho < 64 ? r0s[rho] : rbase[rho] + (int64_t)pre[rho * pre_stride + tile];
+            const uint32_t c = (uint32_t)__popcll(b);
+            uint32_t ic = c;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t y = (uint32_t)__shfl_up((int)ic, d, 64);
+                if (lane >= d) ic += y;
+            }
+            const int nf = __shfl((int)ic, 63, 64);
+            // the last flag's partition runs past the tile: the tile's slot of the list
+            const uint64_t nz = __ballot(b != 0);
+            int64_t *slot = cross + 2 * ((int64_t)rho * ntiles + tile);
+            if (nz == 0) {
+                if (lane == 0) slot[0] = -1;
+            } else if (lane == 63 - __clzll((long long)nz)) {
+                slot[0] = ts + 64 * lane + 63 - __clzll((long long)b);
+                slot[1] = r0 + ic - 1;  // the tile's flags before it: all but itself
+            }
+            // the flags in order
+            {
+                int rk = (int)(ic - c);
+                for (uint64_t f = b; f; f &= f - 1) fl[rk++] = (uint16_t)(64 * lane + __ffsll((unsigned long long)f) - 1);
+            }
+            wave_sync();
+            for (int i = lane; i + 1 < nf; i += 64) {
+                const int a = fl[i], bb = fl[i + 1], L = bb - a;
+                const uint64_t phi = addmod61(mulsmall61(Pt[L], (uint32_t)L),
+                                              mulmod61(Pt[bb - 1], submod61(U[pad(bb)], U[pad(a)])));
+                const int64_t g0 = ts + a;
+                int32_t sidx;
+                int64_t sbeg;
+                if (td.ns >= 0) {
+                    int t = 0;
+                    for (int j = 1; j < td.ns; j++) t += (td.off[j] <= g0) ? 1 : 0;
+                    sidx = td.s0 + t;
+                    sbeg = td.off[t];
+                } else {
+                    sidx = owner_of(off, n, g0);
+                    sbeg = off[sidx];
+                }
+                const int64_t rec = r0 + i;
+                key[rec] = mix64(phi ^ salt_f);
+                val[rec] = ((uint64_t)(uint32_t)sidx << 32) | (uint64_t)(uint32_t)(g0 - sbeg);
+                if (len) len[rec] = (uint32_t)L;
+            }
+            wave_sync();  // the list is read before the wave's next repetition replaces it
+        }
     }
 }
 
@@ -1378,6 +1637,106 @@ static void anchor_launch(const DevStrings &d, const PartitionParams &p, int rep
         wide_anchors(d, wb, p, mix64(p.seed + (uint64_t)rho + GAMMA), TP, bitmap[rho], tcount[rho], s);
 }
 
+// Record bases of the repetitions and the record total, from the repetitions' scanned
+// anchor-tile counts (pre_all holds reps arrays of ntiles + 1 words, the last one each
+// repetition's count).
+__global__ void k_rep_bases(const uint32_t *pre_all, int reps, int64_t ntiles, int64_t *base,
+                            int64_t *total) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int64_t acc = 0;
+    for (int r = 0; r < reps; r++) {
+        base[r] = acc;
+        acc += pre_all[(int64_t)r * (ntiles + 1) + ntiles];
+    }
+    *total = acc;
+}
+
+// Persistent grid of a kernel: the workgroups that fit the device at once.
+template <class K>
+static unsigned resident_grid(K kern, int threads) {
+    int dev = 0, cus = 0, per = 0;
+    MJ_HIP(hipGetDevice(&dev));
+    MJ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MJ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, threads, 0));
+    return (unsigned)std::max(1, cus * std::max(1, per));
+}
+
+// Records of every repetition.  bm_all / pre_all hold the repetitions' anchor bitmaps and
+// tile count prefixes one after another (strides nw + 1 and ntiles + 1); rbase their first
+// record indices (device).  Several repetitions: the tile kernel, which takes the symbols
+// once for all of them, then the partitions that run past their tile.  One repetition:
+// the flagged positions in order, then Horner's rule per partition (8 symbols per step from
+// chunk tables: cheaper per symbol than the tile kernel's prefix sums when nothing is
+// shared); rcap bounds its partitions and stage says whether to stage their symbols.
+static void records_launch(const DevStrings &d, const PartitionParams &p, int reps, int TP,
+                           int region, int64_t ntiles, const TileDesc *ts, const uint64_t *bm_all,
+                           const uint32_t *pre_all, const int64_t *rbase, int64_t rcap, bool stage,
+                           uint64_t *key, uint64_t *val, uint32_t *len, Workspace &ws,
+                           hipStream_t s) {
+    const int64_t nw = (d.total + 63) / 64;
+    const int aligned4 = ((uintptr_t)d.chars & 3) == 0 ? 1 : 0;
+    const int packed = d.packing == MJ_PACK_2BIT ? 1 : 0;
+    const uint64_t B = 2 + mix64(p.seed ^ GAMMA_B) % (P61 - 3);
+    const uint64_t salt_f = mix64(p.seed + GAMMA);
+    auto mulp = [](uint64_t a, uint64_t b) { return (uint64_t)(((unsigned __int128)a * b) % P61); };
+    // Horner steps of 8 symbols (see k_phi_table): power tables, and for b <= 2 tables of
+    // all 4-symbol chunks before them (at most 2,048 entries)
+    // (2-bit packed input with b = 1 has chunks of 2-bit fields, not 4-bit codes: the
+    // power tables serve it)
+    const int pt = (d.bits > 2 || (packed && d.bits != 2)) ? 1 : 0;
+    uint64_t B4 = 1;
+    for (int i = 0; i < 4; i++) B4 = mulp(B4, B);
+    const uint64_t B8 = mulp(B4, B4);
+    const int nc = (pt ? 0 : 2 << (4 * d.bits)) + (8 << d.bits);
+    uint64_t *phi_table = ws.get_n<uint64_t>(nc);
+    hipLaunchKernelGGL(k_phi_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, d.bits, B, pt,
+                       packed, phi_table);
+    MJ_LAUNCH_CHECK();
+    if (reps == 1) {
+        int64_t *apos = ws.get_n<int64_t>(rcap + 1);
+        hipLaunchKernelGGL(k_anchor_scatter, dim3((unsigned)ntiles), dim3(64), 0, s, bm_all, nw,
+                           TP / 64, pre_all, ntiles, apos, d.total);
+        MJ_LAUNCH_CHECK();
+        auto kern = packed ? (stage ? k_records<true, true> : k_records<false, true>)
+                           : (stage ? k_records<true, false> : k_records<false, false>);
+        hipLaunchKernelGGL(kern, dim3(grid_for(rcap, REC_THREADS, 65535)), dim3(REC_THREADS),
+                           (size_t)nc * 8, s, apos, rcap, (int64_t)0, (const uint64_t *)nullptr,
+                           (int64_t)0, d.offsets, d.n, d.chars, d.total, aligned4, ts, TP, B, salt_f,
+                           phi_table, pt, d.bits, B4, B8, key, val, len, pre_all + ntiles, rbase);
+        MJ_LAUNCH_CHECK();
+        return;
+    }
+    uint64_t binv = 1;  // B^(p - 2) = B^-1 (p prime)
+    for (uint64_t e = P61 - 2, bb = B; e; e >>= 1, bb = mulp(bb, bb))
+        if (e & 1) binv = mulp(binv, bb);
+    uint64_t *pq = ws.get_n<uint64_t>(2 * ((size_t)region + 1));
+    hipLaunchKernelGGL(k_pow_tables, dim3((region + 256) / 256), dim3(256), 0, s, B, binv, region, pq);
+    MJ_LAUNCH_CHECK();
+    const int64_t cap = (int64_t)reps * ntiles;  // one partition per tile and repetition, at most
+    int64_t *cross = ws.get_n<int64_t>(2 * (size_t)cap + 2);
+#define MJ_RT(R, PK)                                                                              \
+    do {                                                                                          \
+        static const unsigned grid_ = resident_grid(k_records_tiles<R, PK>, RT_THREADS);          \
+        hipLaunchKernelGGL((k_records_tiles<R, PK>), dim3((unsigned)std::min<int64_t>(ntiles, grid_)), \
+                           dim3(RT_THREADS), 0, s, d.chars, d.total, aligned4, d.offsets, d.n, ts, \
+                           ntiles, TP, d.bits, bm_all, nw + 1, pre_all, ntiles + 1, rbase, reps, pq, \
+                           salt_f, key, val, len, cross);                                         \
+    } while (0)
+    if (region == 2048) {
+        if (packed) MJ_RT(2048, true); else MJ_RT(2048, false);
+    } else {
+        if (packed) MJ_RT(4096, true); else MJ_RT(4096, false);
+    }
+#undef MJ_RT
+    MJ_LAUNCH_CHECK();
+    auto kern = packed ? k_records<false, true, true> : k_records<false, false, true>;
+    hipLaunchKernelGGL(kern, dim3(grid_for(cap, REC_THREADS, 65535)), dim3(REC_THREADS),
+                       (size_t)nc * 8, s, cross, cap, ntiles, bm_all, nw + 1, d.offsets, d.n,
+                       d.chars, d.total, aligned4, ts, TP, B, salt_f, phi_table, pt, d.bits, B4,
+                       B8, key, val, len, (const uint32_t *)nullptr, (const int64_t *)nullptr);
+    MJ_LAUNCH_CHECK();
+}
+
 int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t halo, RecBuf &out,
                           Workspace &ws, hipStream_t s, uint64_t *host_scratch, KTimer *kt) {
     if (d.total == 0) return 0;
@@ -1387,16 +1746,12 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
     const int region = (2048 - 2 * H >= 1024) ? 2048 : 4096;
     int TP = ((region - 2 * H) / 64) * 64;  // whole bitmap words per tile
     int64_t ntiles = (d.total + TP - 1) / TP;
-    int64_t nw = (d.total + 63) / 64;
     if (ntiles > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many tiles");
     // flagged positions are string starts plus strict minima of radius >= 1 (at most every
     // other position); their ranks are 32-bit
     if ((int64_t)d.n + d.total / 2 + 2 > 0xFFFFFFF0LL)
         throw Error(MJ_ECAPACITY, "more than 2^32 partitions per repetition");
     if ((size_t)reps * 4 + 4 > HOST_SCRATCH_BYTES / 2) throw Error(MJ_EINVAL, "too many repetitions");
-    const int code_bits = p.q * d.bits;
-    const int aligned4 = ((uintptr_t)d.chars & 3) == 0 ? 1 : 0;
-    const int packed = d.packing == MJ_PACK_2BIT ? 1 : 0;
 
     // phase 1: anchors of every repetition (Pi seeded with seed + rho), their counts
     int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
@@ -1405,13 +1760,15 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
                        d.offsets, d.rr, d.n, d.total, ntiles, TP, H, region, p.q, ts);
     MJ_LAUNCH_CHECK();
     std::vector<uint64_t *> bitmap(reps);
-    std::vector<uint32_t *> tcount(reps), pre(reps);  // per tile: flagged positions, their scan
+    std::vector<uint32_t *> tcount(reps);  // per tile: flagged positions
     anchor_launch(d, p, reps, TP, H, region, ntiles, ts, ws, s, bitmap, tcount);
     if (kt) kt->end(th, s, 1);
+    // their scans, one after another (ntiles + 1 words each, the last the repetition's count)
+    uint32_t *pre_all = ws.get_n<uint32_t>((size_t)reps * (ntiles + 1));
     for (int rho = 0; rho < reps; rho++) {
-        pre[rho] = ws.get_n<uint32_t>(ntiles + 1);
-        exclusive_scan_u32(tcount[rho], pre[rho], ntiles, ws, s);
-        MJ_HIP(hipMemcpyAsync((uint8_t *)host_scratch + 4 * rho, pre[rho] + ntiles, 4,
+        uint32_t *pre = pre_all + (int64_t)rho * (ntiles + 1);
+        exclusive_scan_u32(tcount[rho], pre, ntiles, ws, s);
+        MJ_HIP(hipMemcpyAsync((uint8_t *)host_scratch + 4 * rho, pre + ntiles, 4,
                               hipMemcpyDeviceToHost, s));
     }
     // the symbol check of the plane packing comes back with the counts
@@ -1430,66 +1787,23 @@ int64_t partition_records(const DevStrings &d, const PartitionParams &p, int32_t
         total += v;
     }
 
-    // phase 2: one reservation, then the records of each repetition
+    // phase 2: one reservation, then the records of every repetition
     const int64_t base0 = out.count;
     out.reserve(base0 + total + 1, s);
-    const uint64_t B = 2 + mix64(p.seed ^ GAMMA_B) % (P61 - 3);
-    const uint64_t salt_f = mix64(p.seed + GAMMA);
-    // Horner steps of 8 symbols (see k_phi_table): power tables, and for b <= 2 tables of
-    // all 4-symbol chunks before them (at most 2,048 entries)
-    // (2-bit packed input with b = 1 has chunks of 2-bit fields, not 4-bit codes: the
-    // power tables serve it)
-    const int pt = (d.bits > 2 || (packed && d.bits != 2)) ? 1 : 0;
-    uint64_t B4 = 1;
-    for (int i = 0; i < 4; i++) B4 = (uint64_t)(((unsigned __int128)B4 * B) % P61);
-    const uint64_t B8 = (uint64_t)(((unsigned __int128)B4 * B4) % P61);
-    const int nc = (pt ? 0 : 2 << (4 * d.bits)) + (8 << d.bits);
-    uint64_t *phi_table = ws.get_n<uint64_t>(nc);
-    hipLaunchKernelGGL(k_phi_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, d.bits, B, pt,
-                       packed, phi_table);
+    int64_t *base_dev = ws.get_n<int64_t>(reps + 2);
+    hipLaunchKernelGGL(k_rep_bases, dim3(1), dim3(64), 0, s, pre_all, reps, ntiles, base_dev,
+                       base_dev + reps + 1);
     MJ_LAUNCH_CHECK();
-    int64_t maxR = 0;
-    for (int rho = 0; rho < reps; rho++) maxR = std::max(maxR, R[rho]);
-    int64_t *apos = ws.get_n<int64_t>(maxR + 1);
-    int64_t base = base0;
-    for (int rho = 0; rho < reps; rho++) {
-        hipLaunchKernelGGL(k_anchor_scatter, dim3((unsigned)ntiles), dim3(64), 0, s, bitmap[rho], nw,
-                           TP / 64, pre[rho], ntiles, apos, d.total);
-        MJ_LAUNCH_CHECK();
-        if (R[rho] > 0) {
-            int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
-            // stage the symbols when partitions average 24 symbols or more
-            const bool stg = d.total >= 24 * R[rho];
-            auto kern = packed ? (stg ? k_records<true, true> : k_records<false, true>)
-                               : (stg ? k_records<true, false> : k_records<false, false>);
-            hipLaunchKernelGGL(kern,
-                               dim3(grid_for(R[rho], REC_THREADS, 65535)), dim3(REC_THREADS),
-                               (size_t)nc * 8, s, apos, R[rho], d.offsets, d.n, d.chars, d.total,
-                               aligned4, ts, TP, B, salt_f, phi_table, pt, d.bits, B4, B8,
-                               out.key + base, out.val + base,
-                               out.with_len ? out.len + base : nullptr, (const uint32_t *)nullptr,
-                               (const int64_t *)nullptr);
-            MJ_LAUNCH_CHECK();
-            if (kt) kt->end(tr, s);
-        }
-        base += R[rho];
+    if (total > 0) {
+        int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
+        // stage the symbols when partitions average 24 symbols or more
+        records_launch(d, p, reps, TP, region, ntiles, ts, bitmap[0], pre_all, base_dev, total,
+                       d.total >= 24 * total, out.key + base0, out.val + base0,
+                       out.with_len ? out.len + base0 : nullptr, ws, s);
+        if (kt) kt->end(tr, s, 1);
     }
-    out.count = base;
+    out.count = base0 + total;
     return total;
-}
-
-// Record bases of the repetitions and the record total, from the repetitions' scanned
-// anchor-tile counts (pre_all holds reps arrays of ntiles + 1 words, the last one each
-// repetition's count).
-__global__ void k_rep_bases(const uint32_t *pre_all, int reps, int64_t ntiles, int64_t *base,
-                            int64_t *total) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    int64_t acc = 0;
-    for (int r = 0; r < reps; r++) {
-        base[r] = acc;
-        acc += pre_all[(int64_t)r * (ntiles + 1) + ntiles];
-    }
-    *total = acc;
 }
 
 int64_t partition_records_streamed(const DevStrings &d, const PartitionParams &p, const SetupInfo &si,
@@ -1505,13 +1819,9 @@ int64_t partition_records_streamed(const DevStrings &d, const PartitionParams &p
     const int region = (2048 - 2 * H >= 1024) ? 2048 : 4096;
     int TP = ((region - 2 * H) / 64) * 64;
     int64_t ntiles = (d.total + TP - 1) / TP;
-    int64_t nw = (d.total + 63) / 64;
     if (ntiles > 0x7FFFFFFFLL) throw Error(MJ_ECAPACITY, "too many tiles");
     if ((int64_t)d.n + d.total / 2 + 2 > 0xFFFFFFF0LL)
         throw Error(MJ_ECAPACITY, "more than 2^32 partitions per repetition");
-    const int code_bits = p.q * d.bits;
-    const int aligned4 = ((uintptr_t)d.chars & 3) == 0 ? 1 : 0;
-    const int packed = d.packing == MJ_PACK_2BIT ? 1 : 0;
 
     int th = kt ? kt->begin(KTimer::ANCHORS, s) : -1;
     TileDesc *ts = ws.get_n<TileDesc>(ntiles + 1);
@@ -1529,36 +1839,12 @@ int64_t partition_records_streamed(const DevStrings &d, const PartitionParams &p
     hipLaunchKernelGGL(k_rep_bases, dim3(1), dim3(64), 0, s, pre_all, reps, ntiles, base_dev, R_dev);
     MJ_LAUNCH_CHECK();
 
-    const uint64_t B = 2 + mix64(p.seed ^ GAMMA_B) % (P61 - 3);
-    const uint64_t salt_f = mix64(p.seed + GAMMA);
-    const int pt = (d.bits > 2 || (packed && d.bits != 2)) ? 1 : 0;
-    uint64_t B4 = 1;
-    for (int i = 0; i < 4; i++) B4 = (uint64_t)(((unsigned __int128)B4 * B) % P61);
-    const uint64_t B8 = (uint64_t)(((unsigned __int128)B4 * B4) % P61);
-    const int nc = (pt ? 0 : 2 << (4 * d.bits)) + (8 << d.bits);
-    uint64_t *phi_table = ws.get_n<uint64_t>(nc);
-    hipLaunchKernelGGL(k_phi_table, dim3((nc + 255) / 256), dim3(256), 0, s, nc, d.bits, B, pt,
-                       packed, phi_table);
-    MJ_LAUNCH_CHECK();
-    int64_t *apos = ws.get_n<int64_t>(bound + 1);
+    int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
     // partitions average about half the bound's length (the bound counts anchors r + 1
     // apart, Lemma 1 expects them 2r + 1 apart): stage the symbols when that is 24 or more
-    const bool stg = d.total >= 12 * bound;
-    auto kern = packed ? (stg ? k_records<true, true> : k_records<false, true>)
-                       : (stg ? k_records<true, false> : k_records<false, false>);
-    for (int rho = 0; rho < reps; rho++) {
-        const uint32_t *pre = pre_all + (int64_t)rho * (ntiles + 1);
-        hipLaunchKernelGGL(k_anchor_scatter, dim3((unsigned)ntiles), dim3(64), 0, s, bitmap[rho], nw,
-                           TP / 64, pre, ntiles, apos, d.total);
-        MJ_LAUNCH_CHECK();
-        int tr = kt ? kt->begin(KTimer::RECORDS, s) : -1;
-        hipLaunchKernelGGL(kern, dim3(grid_for(bound, REC_THREADS, 65535)), dim3(REC_THREADS),
-                           (size_t)nc * 8, s, apos, bound, d.offsets, d.n, d.chars, d.total,
-                           aligned4, ts, TP, B, salt_f, phi_table, pt, d.bits, B4, B8, key, val,
-                           (uint32_t *)nullptr, pre + ntiles, base_dev + rho);
-        MJ_LAUNCH_CHECK();
-        if (kt) kt->end(tr, s);
-    }
+    records_launch(d, p, reps, TP, region, ntiles, ts, bitmap[0], pre_all, base_dev, bound,
+                   d.total >= 12 * bound, key, val, nullptr, ws, s);
+    if (kt) kt->end(tr, s, 1);
     return bound * reps;
 }
 

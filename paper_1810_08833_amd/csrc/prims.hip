@@ -1172,16 +1172,39 @@ __global__ __launch_bounds__(256) void k_mb_flags(const uint64_t *__restrict__ w
         seen[j] = 0;
         again[j] = 0;
     }
-    __syncthreads();
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
-        const uint32_t sub = (uint32_t)(w[i] >> 32) & 0xFFFFu, bit = 1u << (sub & 31);
-        if (atomicOr(&seen[sub >> 5], bit) & bit) atomicOr(&again[sub >> 5], bit);
+    // a bucket of up to MB_KEEP * 256 elements is read once, its elements kept in registers
+    // between the two sweeps (loads issued before the bitmaps are cleared)
+    constexpr int MB_KEEP = 8;
+    const bool keep = hi - lo <= MB_KEEP * 256;
+    uint64_t x[MB_KEEP];
+    if (keep) {
+#pragma unroll
+        for (int u = 0; u < MB_KEEP; u++) {
+            const uint32_t i = lo + threadIdx.x + 256 * u;
+            x[u] = i < hi ? w[i] : 0;
+        }
     }
     __syncthreads();
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
-        const uint64_t x = w[i];
-        const uint32_t sub = (uint32_t)(x >> 32) & 0xFFFFu;
-        if ((again[sub >> 5] >> (sub & 31)) & 1u) flags[(uint32_t)x] = 1;
+    auto see = [&](uint64_t e) {
+        const uint32_t sub = (uint32_t)(e >> 32) & 0xFFFFu, bit = 1u << (sub & 31);
+        if (atomicOr(&seen[sub >> 5], bit) & bit) atomicOr(&again[sub >> 5], bit);
+    };
+    auto mark = [&](uint64_t e) {
+        const uint32_t sub = (uint32_t)(e >> 32) & 0xFFFFu;
+        if ((again[sub >> 5] >> (sub & 31)) & 1u) flags[(uint32_t)e] = 1;
+    };
+    if (keep) {
+#pragma unroll
+        for (int u = 0; u < MB_KEEP; u++)
+            if (lo + threadIdx.x + 256 * u < hi) see(x[u]);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < MB_KEEP; u++)
+            if (lo + threadIdx.x + 256 * u < hi) mark(x[u]);
+    } else {
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) see(w[i]);
+        __syncthreads();
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) mark(w[i]);
     }
 }
 
