@@ -1411,7 +1411,7 @@ __device__ __forceinline__ void wave_sync() {
 
 template <int REGION, bool PACKED>
 __global__ __launch_bounds__(RT_THREADS)
-__attribute__((amdgpu_waves_per_eu(REGION == 2048 ? 3 : 1))) void k_records_tiles(
+__attribute__((amdgpu_waves_per_eu(REGION == 2048 ? 4 : 2))) void k_records_tiles(
     const uint8_t *__restrict__ chars, int64_t total, int aligned4, const int64_t *__restrict__ off,
     int32_t n, const TileDesc *__restrict__ tdesc, int64_t ntiles, int TP, int bits,
     const uint64_t *__restrict__ bitmap, int64_t bm_stride, const uint32_t *__restrict__ pre,
@@ -1422,14 +1422,14 @@ __attribute__((amdgpu_waves_per_eu(REGION == 2048 ? 3 : 1))) void k_records_tile
     static_assert(RUN == 8 || RUN == 16, "positions per thread");
     static_assert(REGION / 64 <= 64, "a tile's flag words fit a wave");
     constexpr int PADN = REGION + 1 + REGION / 8 + 1;  // padded slots of U
-    __shared__ uint64_t Pt[REGION + 1], U[PADN];
+    __shared__ uint64_t U[PADN];
     __shared__ uint16_t flist[RT_WAVES][REGION];  // each wave's list of flagged positions
     __shared__ int64_t r0s[64];                    // the tile's record bases, repetitions < 64
     __shared__ uint64_t wtot[RT_WAVES];
     __shared__ TileDesc td;
     auto pad = [](int j) { return j + (j >> 3); };
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i <= REGION; i += RT_THREADS) Pt[i] = pq[i];
+    const uint64_t *__restrict__ Pt = pq;  // B^d: a small table, read through the caches
     const uint32_t m = (1u << bits) - 1u;
     const int nwt = TP / 64;  // TP is a multiple of 64
     const int64_t nw = (total + 63) / 64;
