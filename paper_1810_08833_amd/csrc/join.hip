@@ -149,6 +149,15 @@ __device__ __forceinline__ bool pass_filter(int64_t mi, int64_t pi, int64_t mj, 
     return (d1 > d2 ? d1 : d2) <= K;
 }
 
+// The same test in 32-bit arithmetic, for inputs of fewer than 2^29 symbols: then
+// m, pos < 2^29, 2 pos - m lies in (-2^29, 2^30), and both differences fit an int32.
+__device__ __forceinline__ bool pass_filter32(int32_t mi, int32_t pi, int32_t mj, int32_t pj,
+                                              uint32_t K) {
+    const int32_t d1 = abs(mi - mj);
+    const int32_t d2 = abs((2 * pi - mi) - (2 * pj - mj));
+    return (uint32_t)max(d1, d2) <= K;
+}
+
 // Passing tests of one block's sweep are staged in LDS and written out with one
 // device-wide atomic per block and sweep: a single counter bumped by every wave of all
 // XCDs serialises (device-scope atomics are not served by an XCD's own L2).
@@ -207,8 +216,8 @@ __global__ void k_record_meta(const uint64_t *__restrict__ val, int64_t R,
 
 // LAZY: no meta array; a record's (m, K) word is gathered by its string id at each use
 // (fewer pair tests than records, as on text and DNA), from lk if given, else from the
-// length and K arrays.
-template <bool LAZY>
+// length and K arrays.  SMALL: the input holds fewer than 2^29 symbols (32-bit filter).
+template <bool LAZY, bool SMALL>
 __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict__ val,
                                               const uint64_t *__restrict__ meta,
                                               const uint64_t *__restrict__ lk,
@@ -249,21 +258,21 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
             while ((b + 1) * b / 2 <= u) b++;
             a = u - b * (b - 1) / 2;
         }
-        // the group start and record b's words change only when b or the group does:
-        // loaded then, not at every test
-        int64_t s0 = 0, cached_g = -1, cached_b = -1;
+        // the group's first record and the first test of the next group, and record b's
+        // words, change only when the group or b does: loaded then, not at every test
+        int64_t s0 = 0, cached_b = -1;
+        uint64_t gend = 0;
         uint64_t vb = 0, xb = 0;
+        if (active) {
+            s0 = gs[g];
+            gend = ts[g + 1];
+        }
         for (int c = 0; c < chunk; c++) {
             uint64_t t = t0 + c;
             bool live = active && t < P;
             bool pass = false;
             uint64_t pairkey = 0;
             if (live) {
-                if (g != cached_g) {
-                    s0 = gs[g];
-                    cached_g = g;
-                    cached_b = -1;
-                }
                 auto meta_of = [&](int64_t i, uint64_t v) -> uint64_t {
                     if constexpr (LAZY) {
                         const int32_t sid = (int32_t)(v >> 32);
@@ -281,22 +290,32 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
                 const uint64_t va = val[s0 + (int64_t)a], xa = meta_of(s0 + (int64_t)a, va);
                 int32_t ia = (int32_t)(va >> 32), ib = (int32_t)(vb >> 32);
                 if (ia != ib) {
-                    const int64_t ma = (int64_t)(xa >> 32), mb = (int64_t)(xb >> 32);
-                    const int64_t K = max((int64_t)(uint32_t)xa, (int64_t)(uint32_t)xb);
-                    pass = pass_filter(ma, (int64_t)(uint32_t)va, mb, (int64_t)(uint32_t)vb, K);
+                    if constexpr (SMALL) {
+                        pass = pass_filter32((int32_t)(xa >> 32), (int32_t)(uint32_t)va,
+                                             (int32_t)(xb >> 32), (int32_t)(uint32_t)vb,
+                                             max((uint32_t)xa, (uint32_t)xb));
+                    } else {
+                        const int64_t ma = (int64_t)(xa >> 32), mb = (int64_t)(xb >> 32);
+                        const int64_t K = max((int64_t)(uint32_t)xa, (int64_t)(uint32_t)xb);
+                        pass = pass_filter(ma, (int64_t)(uint32_t)va, mb, (int64_t)(uint32_t)vb, K);
+                    }
                     uint64_t lo = (uint64_t)min(ia, ib), hi = (uint64_t)max(ia, ib);
                     pairkey = (lo << 32) | hi;
                 }
-                // next test: (a+1, b); else (0, b+1); a group of z records ends at b = z,
-                // which is when b(b-1)/2 equals its test count
+                // next test: (a+1, b); else (0, b+1); the group ends where the next group's
+                // tests start (every group has at least one test)
                 a++;
                 if (a == b) {
                     a = 0;
                     b++;
-                    if (b * (b - 1) / 2 == ts[g + 1] - ts[g]) {
-                        g++;
-                        b = 1;
-                    }
+                }
+                if (t + 1 == gend && g + 1 < G) {
+                    g++;
+                    a = 0;
+                    b = 1;
+                    s0 = gs[g];
+                    gend = ts[g + 1];
+                    cached_b = -1;
                 }
             }
             stage(pass, pairkey, st);
@@ -341,7 +360,10 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
     while (chunk < 4 * EMIT_CHUNK && tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
     uint64_t threads = (tests + chunk - 1) / chunk;
     unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, 1u << 16);
-    hipLaunchKernelGGL(lazy ? k_emit<true> : k_emit<false>, dim3(grid), dim3(EMIT_BLOCK), 0, s, val,
+    const bool small = d.total < (1ll << 29);
+    hipLaunchKernelGGL(lazy ? (small ? k_emit<true, true> : k_emit<true, false>)
+                            : (small ? k_emit<false, true> : k_emit<false, false>),
+                       dim3(grid), dim3(EMIT_BLOCK), 0, s, val,
                        meta, lk, d.len, d.kk, g.gstart, g.tstart, g.groups, t_end, out, cap, counter,
                        chunk, (const uint64_t *)nullptr, t_begin);
     MJ_LAUNCH_CHECK();
@@ -437,7 +459,10 @@ void emit_candidates_streamed(const uint64_t *val, int64_t R_cap, const int64_t 
     }
     const int chunk = std::max(EMIT_CHUNK, h.chunk);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(h.blocks, 1 << 16));
-    hipLaunchKernelGGL(h.lazy ? k_emit<true> : k_emit<false>, dim3(grid), dim3(EMIT_BLOCK), 0, s,
+    const bool small = d.total < (1ll << 29);
+    hipLaunchKernelGGL(h.lazy ? (small ? k_emit<true, true> : k_emit<true, false>)
+                              : (small ? k_emit<false, true> : k_emit<false, false>),
+                       dim3(grid), dim3(EMIT_BLOCK), 0, s,
                        val, meta, lk, d.len, d.kk, g.gstart, g.tstart, (int64_t)0, (uint64_t)0, out,
                        cap, count, chunk, (const uint64_t *)g.slot, (uint64_t)0);
     MJ_LAUNCH_CHECK();
