@@ -418,14 +418,16 @@ int64_t dedup_pairs(uint64_t *pairs, int64_t n, int32_t n_first, int32_t n_secon
         MJ_LAUNCH_CHECK();
     }
     auto ones = [](int b) { return b >= 64 ? ~0ull : ((1ull << b) - 1); };
-    radix_sort(pairs, nullptr, n, pack ? ones(bf + bs) : (ones(bf) << 32) | ones(bs), ws, s);
+    uint64_t *sorted = pairs;  // where the sorted keys end up (no copy back)
+    radix_sort(pairs, nullptr, n, pack ? ones(bf + bs) : (ones(bf) << 32) | ones(bs), ws, s,
+               nullptr, nullptr, nullptr, &sorted);
     uint8_t *f = ws.get_n<uint8_t>(n);
-    hipLaunchKernelGGL(k_unique_flags, dim3(pgrid), dim3(256), 0, s, pairs, n, f);
+    hipLaunchKernelGGL(k_unique_flags, dim3(pgrid), dim3(256), 0, s, sorted, n, f);
     MJ_LAUNCH_CHECK();
     int64_t *idx = ws.get_n<int64_t>(n + 1);
     int64_t u = compact_flags(f, n, idx, ws, s, host_scratch);
     uint64_t *res = out_buf(u);
-    gather_u64(pairs, idx, res, u, s);
+    gather_u64(sorted, idx, res, u, s);
     if (pack && u > 0) {
         hipLaunchKernelGGL(k_unpack_pairs, dim3(grid_for(u, 256, 16384)), dim3(256), 0, s, res, u, bs);
         MJ_LAUNCH_CHECK();
@@ -523,14 +525,16 @@ const uint32_t *dedup_pairs_streamed(uint64_t *pairs, int64_t cap, const unsigne
         MJ_LAUNCH_CHECK();
     }
     auto ones = [](int b) { return b >= 64 ? ~0ull : ((1ull << b) - 1); };
-    radix_sort(pairs, nullptr, cap, pack ? ones(bf + bs) : (ones(bf) << 32) | ones(bs), ws, s, n_dev);
+    uint64_t *sorted = pairs;  // where the sorted keys end up (no copy back)
+    radix_sort(pairs, nullptr, cap, pack ? ones(bf + bs) : (ones(bf) << 32) | ones(bs), ws, s, n_dev,
+               nullptr, nullptr, &sorted);
     uint8_t *f = ws.get_n<uint8_t>(cap);
-    hipLaunchKernelGGL(k_unique_flags_dev, dim3(pgrid), dim3(256), 0, s, pairs, cap, n_dev, f);
+    hipLaunchKernelGGL(k_unique_flags_dev, dim3(pgrid), dim3(256), 0, s, sorted, cap, n_dev, f);
     MJ_LAUNCH_CHECK();
     int64_t *idx = ws.get_n<int64_t>(cap + 1);
     const uint32_t *u = compact_flags_async(f, cap, idx, ws, s);
     uint64_t *res = ws.get_n<uint64_t>(cap + 1);
-    gather_u64(pairs, idx, res, cap, s, u);
+    gather_u64(sorted, idx, res, cap, s, u);
     if (pack) {
         hipLaunchKernelGGL(k_pack_pairs_dev, dim3(pgrid), dim3(256), 0, s, res, n_dev, cap, bs, 1, u);
         MJ_LAUNCH_CHECK();

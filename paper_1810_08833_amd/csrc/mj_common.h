@@ -169,9 +169,11 @@ constexpr size_t HOST_SCRATCH_BYTES = 16384;
 // at every bit that may be set in some key (the others must be zero in all keys).
 // n_dev (nullable): the element count on the device, n then being its capacity.
 // k2 / v2 (nullable): second buffers of n elements (else taken from the workspace).
+// sorted_keys (nullable, keys only): receives the buffer that holds the sorted keys (key
+// or the second buffer) instead of a copy back into key after an odd number of passes.
 void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Workspace &ws,
                 hipStream_t s, const int64_t *n_dev = nullptr, uint64_t *k2 = nullptr,
-                uint64_t *v2 = nullptr);
+                uint64_t *v2 = nullptr, uint64_t **sorted_keys = nullptr);
 // Records (key, payload) sorted by the full 64-bit key, in place; equal keys keep their
 // order only up to the runs that the repair step reorders.
 void sort_records(uint64_t *key, uint64_t *val, int64_t n, Workspace &ws, hipStream_t s,

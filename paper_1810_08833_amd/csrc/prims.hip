@@ -750,7 +750,12 @@ __global__ __launch_bounds__(RS_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
 }
 
 void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Workspace &ws,
-                hipStream_t s, const int64_t *n_dev, uint64_t *k2, uint64_t *v2) {
+                hipStream_t s, const int64_t *n_dev, uint64_t *k2, uint64_t *v2,
+                uint64_t **sorted_keys) {
+    if (sorted_keys) {
+        if (val) throw Error(MJ_EINVAL, "radix_sort: sorted_keys is for keys only");
+        *sorted_keys = key;
+    }
     if (n <= 1) return;
     if (n > 0xFFFFFFF0LL) throw Error(MJ_ECAPACITY, "sort of more than 2^32 elements");
     int passes[8], np = 0;
@@ -782,6 +787,10 @@ void radix_sort(uint64_t *key, uint64_t *val, int64_t n, uint64_t key_mask, Work
         std::swap(va, vb);
     }
     if (ka != key) {
+        if (sorted_keys) {
+            *sorted_keys = ka;
+            return;
+        }
         MJ_HIP(hipMemcpyAsync(key, ka, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
         if (val) MJ_HIP(hipMemcpyAsync(val, va, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
     }
