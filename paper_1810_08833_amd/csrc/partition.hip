@@ -1352,10 +1352,35 @@ __device__ __forceinline__ uint64_t addmod61(uint64_t a, uint64_t b) {
 __device__ __forceinline__ uint64_t submod61(uint64_t a, uint64_t b) {
     return a >= b ? a - b : a + P61 - b;
 }
-__device__ __forceinline__ uint64_t shfl_up64(uint64_t x, int d) {
-    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
-    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
-    return ((uint64_t)hi << 32) | lo;
+// Inclusive scans over a wave of 64 lanes by DPP moves: row shifts by 1, 2, 4 and 8
+// within rows of 16 lanes, then the row totals broadcast (lane 15 into rows 1 and 3, lane
+// 31 into rows 2 and 3).  A lane whose source is outside its row, or a row outside the
+// move's row mask, receives 0, the identity of the scans' operations.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp0(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, true);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp0_64(uint64_t v) {
+    return ((uint64_t)dpp0<CTRL, ROWS>((uint32_t)(v >> 32)) << 32) | dpp0<CTRL, ROWS>((uint32_t)v);
+}
+__device__ __forceinline__ uint32_t wave_scan_add(uint32_t x) {
+    x += dpp0<0x111, 0xF>(x);
+    x += dpp0<0x112, 0xF>(x);
+    x += dpp0<0x114, 0xF>(x);
+    x += dpp0<0x118, 0xF>(x);
+    x += dpp0<0x142, 0xA>(x);
+    x += dpp0<0x143, 0xC>(x);
+    return x;
+}
+__device__ __forceinline__ uint64_t wave_scan_addmod61(uint64_t x) {
+    x = addmod61(x, dpp0_64<0x111, 0xF>(x));
+    x = addmod61(x, dpp0_64<0x112, 0xF>(x));
+    x = addmod61(x, dpp0_64<0x114, 0xF>(x));
+    x = addmod61(x, dpp0_64<0x118, 0xF>(x));
+    x = addmod61(x, dpp0_64<0x142, 0xA>(x));
+    x = addmod61(x, dpp0_64<0x143, 0xC>(x));
+    return x;
 }
 
 // pq[d] = B^d and pq[n + 1 + d] = B^-d (binv = B^-1 modulo p), d <= n: square and multiply.
@@ -1491,12 +1516,7 @@ __attribute__((amdgpu_waves_per_eu(REGION == 2048 ? 4 : 2))) void k_records_tile
         // every register of this tile's loads is consumed: the next tile's are issued now
         // and stay in flight while this one is worked on
         if (tile + gridDim.x < ntiles) load(tile + gridDim.x);
-        uint64_t incl = acc;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint64_t y = shfl_up64(incl, d);
-            if (lane >= d) incl = addmod61(incl, y);
-        }
+        const uint64_t incl = wave_scan_addmod61(acc);
         if (lane == 63) wtot[wave] = incl;
         __syncthreads();
         uint64_t before = submod61(incl, acc);
@@ -1514,13 +1534,8 @@ __attribute__((amdgpu_waves_per_eu(REGION == 2048 ? 4 : 2))) void k_records_tile
                                           : ((lane < nwt && w < nw) ? bitmap[rho * bm_stride + w] : 0ull);
             const int64_t r0 = rho < 64 ? r0s[rho] : rbase[rho] + (int64_t)pre[rho * pre_stride + tile];
             const uint32_t c = (uint32_t)__popcll(b);
-            uint32_t ic = c;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t y = (uint32_t)__shfl_up((int)ic, d, 64);
-                if (lane >= d) ic += y;
-            }
-            const int nf = __shfl((int)ic, 63, 64);
+            const uint32_t ic = wave_scan_add(c);
+            const int nf = __builtin_amdgcn_readlane((int)ic, 63);
             // the last flag's partition runs past the tile: the tile's slot of the list
             const uint64_t nz = __ballot(b != 0);
             int64_t *slot = cross + 2 * ((int64_t)rho * ntiles + tile);
