@@ -106,12 +106,6 @@ extern "C" mj_status mj_ctx_set_streaming(mj_ctx *ctx, int mode) {
 }
 
 // ---------------------------------------------------------------- helpers
-static int ceil_log2(uint64_t v) {
-    int b = 0;
-    while (b < 63 && (1ull << b) < v) b++;
-    return b;
-}
-
 // The verify_lanes / verify_group code of a batched configuration: lanes per pair, -2 for
 // the column split, -3 for the band classes.
 static int lanes_code(int g) {
