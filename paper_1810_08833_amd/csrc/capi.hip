@@ -376,6 +376,8 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     }
     ctx->last_R = R;
     ctx->last_M = M;
+    ctx->last_small_tests = g.small_tests;
+    ctx->last_units = g.units;
     ctx->last_rcap = std::max<int64_t>(si.rec_bound * pp.reps, 2);
     tm.mark();  // 4 dedup
     if (stats) {
@@ -433,6 +435,8 @@ __global__ void k_collect(const int64_t *R, const uint64_t *slot, const unsigned
     dst[6] = *outn;
     dst[7] = cells[0];
     dst[8] = cells[1];
+    dst[11] = slot ? slot[3] : 0;
+    dst[12] = slot ? slot[4] : 0;
 }
 
 static bool hints_match(const StreamHints &h, const mj_strings *st, const mj_params *p) {
@@ -523,7 +527,7 @@ static StreamedDev launch_streamed_main(mj_ctx *ctx, DevStrings &d, const Partit
     hipLaunchKernelGGL(k_collect, dim3(1), dim3(64), 0, s, R_dev, g.slot, c0, u, on, cells,
                        (const uint32_t *)d.symbol_err, M_dev, res);
     MJ_LAUNCH_CHECK();
-    MJ_HIP(hipMemcpyAsync(ctx->pinned, res, 11 * 8, hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipMemcpyAsync(ctx->pinned, res, 13 * 8, hipMemcpyDeviceToHost, s));
     return dv;
 }
 
@@ -532,7 +536,7 @@ static StreamedDev launch_streamed_main(mj_ctx *ctx, DevStrings &d, const Partit
 static mj_pairs *finish_streamed(mj_ctx *ctx, const StreamedPlan &pl, const StreamedDev &dv,
                                  const DevStrings &d, const PartitionParams &pp, hipStream_t s,
                                  mj_stats *stats) {
-    uint64_t hv[11];
+    uint64_t hv[13];
     memcpy(hv, ctx->pinned, sizeof(hv));
     const int64_t R = (int64_t)hv[0], c0h = (int64_t)hv[4], C = (int64_t)hv[5], nout = (int64_t)hv[6];
     const int64_t M = (int64_t)hv[10];
@@ -570,7 +574,7 @@ static mj_pairs *finish_streamed(mj_ctx *ctx, const StreamedPlan &pl, const Stre
     ctx->stream.cand_per_record = (double)c0h / (double)pl.rcap;
     ctx->stream.rec_per_bound = (double)R / (double)pl.rcap;
     ctx->stream.mem_per_bound = (double)M / (double)pl.rcap;
-    ctx->stream.emit = emit_hints((uint64_t)hv[3], M, d.n);
+    ctx->stream.emit = emit_hints((uint64_t)hv[3], (uint64_t)hv[11], (uint64_t)hv[12], M, d.n);
     return out;
 }
 
@@ -736,7 +740,8 @@ extern "C" mj_status mj_join(mj_ctx *ctx, const mj_strings *strings, const mj_pa
         h.cand_per_record = (double)ctx->last_c0 / (double)std::max<int64_t>(ctx->last_rcap, 1);
         h.rec_per_bound = (double)ctx->last_R / (double)std::max<int64_t>(ctx->last_rcap, 1);
         h.mem_per_bound = (double)ctx->last_M / (double)std::max<int64_t>(ctx->last_rcap, 1);
-        h.emit = emit_hints((uint64_t)stats->pair_tests, stats->members, strings->n);
+        h.emit = emit_hints((uint64_t)stats->pair_tests, ctx->last_small_tests, ctx->last_units,
+                            stats->members, strings->n);
         h.verify_g = ctx->tune.last_g;
         h.verify_blocks = ctx->tune.last_blocks;
     }

@@ -70,8 +70,10 @@ struct mj_ctx {
     JoinGraph graph;
     hipStream_t cap_stream = nullptr;  // the stream graphs are captured on
     int streamed_joins = 0, stream_fallbacks = 0;
-    // the last stage-by-stage join's emitted candidates, records and record bound
+    // the last stage-by-stage join's emitted candidates, records and record bound, and its
+    // pair tests of the small groups and tile pairs of the large ones
     int64_t last_c0 = 0, last_R = 0, last_rcap = 0, last_M = 0;
+    uint64_t last_small_tests = 0, last_units = 0;
 };
 
 struct mj_pairs {

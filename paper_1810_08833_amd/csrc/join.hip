@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 #include "mj_common.h"
@@ -47,10 +48,14 @@ __global__ void k_group_flags(const uint64_t *key, int64_t R, uint8_t *fs, uint8
     }
 }
 
-// Pair tests of each group.  The group counts c1 (starts) and c2 (ends) are device
-// values: slot[0] = c1 | c2 << 32 and slot[1] = min(c1, c2), the groups scanned.
+// Pair tests of each group: all of them (cnt), those of the groups below EMIT_TILE
+// records (csmall, 0 for the others) and the tile pairs I <= J of the groups of EMIT_TILE
+// or more (cunits, 0 for the others; nt tiles of EMIT_TILE records give nt (nt + 1) / 2).
+// The group counts c1 (starts) and c2 (ends) are device values: slot[0] = c1 | c2 << 32
+// and slot[1] = min(c1, c2), the groups scanned.
 __global__ void k_group_tests(const int64_t *gs, const int64_t *ge, const uint32_t *c1,
-                              const uint32_t *c2, uint64_t *cnt, uint64_t *slot) {
+                              const uint32_t *c2, uint64_t *cnt, uint64_t *csmall,
+                              uint64_t *cunits, uint64_t *slot) {
     const int64_t G = min(*c1, *c2);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         slot[0] = (uint64_t)*c1 | ((uint64_t)*c2 << 32);
@@ -59,52 +64,22 @@ __global__ void k_group_tests(const int64_t *gs, const int64_t *ge, const uint32
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; g < G; g += stride) {
-        uint64_t sz = (uint64_t)(ge[g] - gs[g] + 1);
-        cnt[g] = sz * (sz - 1) / 2;
+        const uint64_t sz = (uint64_t)(ge[g] - gs[g] + 1);
+        const uint64_t all = sz * (sz - 1) / 2;
+        const bool big = sz >= (uint64_t)EMIT_TILE;
+        const uint64_t nt = (sz + EMIT_TILE - 1) / EMIT_TILE;
+        cnt[g] = all;
+        csmall[g] = big ? 0 : all;
+        cunits[g] = big ? nt * (nt + 1) / 2 : 0;
     }
 }
 
-GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t s,
-                      uint64_t *host_scratch) {
+// Group boundaries and the three prefixes over the groups, with the group counts on the
+// device: the arrays are sized by the bound R / 2 (a group holds >= 2 records) and the
+// totals land in slot[2..4].
+static GroupInfo group_tests(const uint64_t *key, int64_t R, const int64_t *R_dev, Workspace &ws,
+                             hipStream_t s) {
     GroupInfo gi;
-    if (R < 2) return gi;
-    uint8_t *fs = ws.get_n<uint8_t>(R);
-    uint8_t *fe = ws.get_n<uint8_t>(R);
-    hipLaunchKernelGGL(k_group_flags, dim3(grid_for(R, 256, 16384)), dim3(256), 0, s, key, R, fs, fe,
-                       (const int64_t *)nullptr);
-    MJ_LAUNCH_CHECK();
-    int64_t *gs = ws.get_n<int64_t>(R / 2 + 2);
-    int64_t *ge = ws.get_n<int64_t>(R / 2 + 2);
-    const uint32_t *c1 = compact_flags_async(fs, R, gs, ws, s);
-    const uint32_t *c2 = compact_flags_async(fe, R, ge, ws, s);
-    // the group counts stay on the device: test counts and their scan are sized by the
-    // bound R / 2 (a group holds >= 2 records), and one read brings back both counts and
-    // the total
-    const int64_t gmax = R / 2;
-    uint64_t *cnt = ws.get_n<uint64_t>(gmax + 1);
-    gi.tstart = ws.get_n<uint64_t>(gmax + 1);
-    uint64_t *slot = ws.get_n<uint64_t>(3);
-    hipLaunchKernelGGL(k_group_tests, dim3(grid_for(gmax, 256, 16384)), dim3(256), 0, s, gs, ge, c1,
-                       c2, cnt, slot);
-    MJ_LAUNCH_CHECK();
-    exclusive_scan_u64_dev(cnt, gi.tstart, gmax, reinterpret_cast<const uint32_t *>(slot + 1),
-                           slot + 2, ws, s);
-    MJ_HIP(hipMemcpyAsync(host_scratch, slot, 24, hipMemcpyDeviceToHost, s));
-    MJ_HIP(hipStreamSynchronize(s));
-    uint64_t hs[3];
-    memcpy(hs, host_scratch, 24);
-    const int64_t G1 = (int64_t)(hs[0] & 0xFFFFFFFFu), G2 = (int64_t)(hs[0] >> 32);
-    if (G1 != G2) throw Error(MJ_EDEVICE, "group boundary mismatch");
-    gi.groups = G1;
-    gi.gstart = gs;
-    gi.tests = G1 > 0 ? hs[2] : 0;
-    return gi;
-}
-
-GroupInfo find_groups_streamed(const uint64_t *key, int64_t R_cap, const int64_t *R_dev,
-                               Workspace &ws, hipStream_t s) {
-    GroupInfo gi;
-    const int64_t R = std::max<int64_t>(R_cap, 2);
     uint8_t *fs = ws.get_n<uint8_t>(R);
     uint8_t *fe = ws.get_n<uint8_t>(R);
     hipLaunchKernelGGL(k_group_flags, dim3(grid_for(R, 256, 16384)), dim3(256), 0, s, key, R, fs, fe,
@@ -116,17 +91,49 @@ GroupInfo find_groups_streamed(const uint64_t *key, int64_t R_cap, const int64_t
     const uint32_t *c2 = compact_flags_async(fe, R, ge, ws, s);
     const int64_t gmax = R / 2;
     uint64_t *cnt = ws.get_n<uint64_t>(gmax + 1);
+    uint64_t *csmall = ws.get_n<uint64_t>(gmax + 1);
+    uint64_t *cunits = ws.get_n<uint64_t>(gmax + 1);
     gi.tstart = ws.get_n<uint64_t>(gmax + 1);
-    uint64_t *slot = ws.get_n<uint64_t>(3);
+    gi.tsmall = ws.get_n<uint64_t>(gmax + 1);
+    gi.ustart = ws.get_n<uint64_t>(gmax + 1);
+    uint64_t *slot = ws.get_n<uint64_t>(5);
     hipLaunchKernelGGL(k_group_tests, dim3(grid_for(gmax, 256, 16384)), dim3(256), 0, s, gs, ge, c1,
-                       c2, cnt, slot);
+                       c2, cnt, csmall, cunits, slot);
     MJ_LAUNCH_CHECK();
-    exclusive_scan_u64_dev(cnt, gi.tstart, gmax, reinterpret_cast<const uint32_t *>(slot + 1),
-                           slot + 2, ws, s);
-    gi.groups = -1;  // on the device: slot[0] = c1 | c2 << 32, slot[1] = groups, slot[2] = tests
+    const uint32_t *G_dev = reinterpret_cast<const uint32_t *>(slot + 1);
+    exclusive_scan_u64_dev(cnt, gi.tstart, gmax, G_dev, slot + 2, ws, s);
+    exclusive_scan_u64_dev(csmall, gi.tsmall, gmax, G_dev, slot + 3, ws, s);
+    exclusive_scan_u64_dev(cunits, gi.ustart, gmax, G_dev, slot + 4, ws, s);
     gi.gstart = gs;
+    gi.gend = ge;
     gi.slot = slot;
     gi.gmax = gmax;
+    return gi;
+}
+
+GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t s,
+                      uint64_t *host_scratch) {
+    if (R < 2) return GroupInfo();
+    GroupInfo gi = group_tests(key, R, nullptr, ws, s);
+    // one read brings back both group counts and the totals
+    MJ_HIP(hipMemcpyAsync(host_scratch, gi.slot, 40, hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipStreamSynchronize(s));
+    uint64_t hs[5];
+    memcpy(hs, host_scratch, 40);
+    const int64_t G1 = (int64_t)(hs[0] & 0xFFFFFFFFu), G2 = (int64_t)(hs[0] >> 32);
+    if (G1 != G2) throw Error(MJ_EDEVICE, "group boundary mismatch");
+    gi.groups = G1;
+    gi.tests = G1 > 0 ? hs[2] : 0;
+    gi.small_tests = G1 > 0 ? hs[3] : 0;
+    gi.units = G1 > 0 ? hs[4] : 0;
+    gi.slot = nullptr;
+    return gi;
+}
+
+GroupInfo find_groups_streamed(const uint64_t *key, int64_t R_cap, const int64_t *R_dev,
+                               Workspace &ws, hipStream_t s) {
+    GroupInfo gi = group_tests(key, std::max<int64_t>(R_cap, 2), R_dev, ws, s);
+    gi.groups = -1;  // on the device, in slot
     return gi;
 }
 
@@ -134,7 +141,9 @@ GroupInfo find_groups_streamed(const uint64_t *key, int64_t R_cap, const int64_t
 // Pair tests are numbered consecutively across groups; each thread takes a run of
 // consecutive tests (EMIT_CHUNK, or a multiple of it in k_emit), so a huge group is
 // spread over many threads.  Inside a group of
-// size z, test u is the pair (a, b), a < b, with u = b(b-1)/2 + a.
+// size z, test u is the pair (a, b), a < b, with u = b(b-1)/2 + a.  In a join emitted in
+// one pass, the groups of EMIT_TILE records or more have no tests in this numbering (their
+// prefix does not grow): k_emit_big takes them by tile pairs.
 // Filter (Alg. 3): |m_i - m_j| <= K and |pos_i - pos_j| + |(m_i-pos_i) - (m_j-pos_j)| <= K,
 // evaluated as max(|m_i - m_j|, |(2pos_i - m_i) - (2pos_j - m_j)|) <= K (the same test,
 // since |u| + |v| = max(|u + v|, |u - v|)).
@@ -162,6 +171,9 @@ __device__ __forceinline__ bool pass_filter32(int32_t mi, int32_t pi, int32_t mj
 // device-wide atomic per block and sweep: a single counter bumped by every wave of all
 // XCDs serialises (device-scope atomics are not served by an XCD's own L2).
 constexpr int EMIT_BLOCK = 256;
+// k_emit's workgroups, at most: as many as stay resident (four 33 KB stages per CU), each
+// looping over sweeps with its stage kept across them
+constexpr unsigned EMIT_MAX_BLOCKS = 1024;
 struct EmitStage {
     uint64_t buf[EMIT_BLOCK * EMIT_CHUNK];
     uint32_t n;
@@ -179,11 +191,13 @@ __device__ __forceinline__ void stage(bool pass, uint64_t v, EmitStage &st) {
     if (pass) st.buf[base + __popcll(mask & ((1ull << lane) - 1))] = v;
 }
 
-// Block-uniform: every thread of the block calls it after the same sweep.
+// Block-uniform: every thread of the block calls it at the same point.  The stage is
+// written out when it holds more than `keep` pairs (0: whenever it holds any).
 __device__ __forceinline__ void flush(EmitStage &st, unsigned long long *counter, uint64_t *out,
-                                      int64_t cap) {
+                                      int64_t cap, uint32_t keep = 0) {
     __syncthreads();
-    const uint32_t n = st.n;
+    const uint32_t n0 = st.n;
+    const uint32_t n = n0 > keep ? n0 : 0;
     if (threadIdx.x == 0 && n) st.base = atomicAdd(counter, (unsigned long long)n);
     __syncthreads();
     if (n) {
@@ -228,10 +242,11 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
                                               uint64_t P, uint64_t *out, int64_t cap,
                                               unsigned long long *counter, int chunk,
                                               const uint64_t *__restrict__ slot, uint64_t tb) {
-    // group and test counts on the device (the streamed join): slot[1], slot[2]
+    // group and test counts on the device (the streamed join): slot[1], and the tests of
+    // the groups below EMIT_TILE records, slot[3]
     if (slot) {
         G = (int64_t)slot[1];
-        P = G > 0 ? slot[2] : 0;
+        P = G > 0 ? slot[3] : 0;
     }
     // tests [tb, P): the whole range, or one pass of a join emitted in passes
     __shared__ EmitStage st;
@@ -303,26 +318,300 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
                     pairkey = (lo << 32) | hi;
                 }
                 // next test: (a+1, b); else (0, b+1); the group ends where the next group's
-                // tests start (every group has at least one test)
+                // tests start, and groups with no tests in this numbering are passed over
                 a++;
                 if (a == b) {
                     a = 0;
                     b++;
                 }
                 if (t + 1 == gend && g + 1 < G) {
-                    g++;
+                    do {
+                        g++;
+                        gend = ts[g + 1];
+                    } while (gend == t + 1 && g + 1 < G);
                     a = 0;
                     b = 1;
                     s0 = gs[g];
-                    gend = ts[g + 1];
                     cached_b = -1;
                 }
             }
             stage(pass, pairkey, st);
-            // the stage holds EMIT_CHUNK tests per thread (chunk is a multiple of it)
-            if ((c & (EMIT_CHUNK - 1)) == EMIT_CHUNK - 1) flush(st, counter, out, cap);
+            // the stage holds EMIT_CHUNK tests per thread and is written out once more than
+            // half full (checked every 8 tests: at most half of it added in between), so a
+            // block takes the shared counter about once per 2,048 passing pairs and once at
+            // the end, not once per sweep
+            if ((c & 7) == 7) flush(st, counter, out, cap, EMIT_BLOCK * EMIT_CHUNK / 2);
         }
     }
+    flush(st, counter, out, cap);
+}
+
+// Pair tests of the groups of EMIT_TILE records or more, by tile pairs.  A group of z
+// records is cut into nt = ceil(z / 64) tiles; tile pair u = J (J + 1) / 2 + I, I <= J,
+// tests records a = 64 I + l against b = 64 J + j (a < b: l < j when I = J), the same
+// pairs as the group's tests in k_emit, each once.  A wave takes a tile pair: lane l holds
+// record a, the 64 records of tile J are broadcast one by one from the lanes that loaded
+// them, so the inner loop reads no memory.  Wave k takes the tile pairs [k per, (k + 1) per)
+// in order (one group search, then a walk).  The kernel runs twice with the same grid:
+// COUNT writes each wave's passing pairs to wcnt[k]; after an exclusive scan of those
+// (wpre) WRITE stores them at out[*wbase + wpre[k] ..), staged per wave in LDS: no shared
+// counter (a device atomic on one address, taken by every wave, serialises).
+constexpr int EB_WAVES = 4;   // waves per workgroup
+constexpr int EB_BUF = 512;   // staged pairs per wave
+
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Largest g in [lo, hi) with us[g] <= w, given us[lo] <= w (us non-decreasing): a 64-way
+// search by the whole wave (one coalesced probe of 64 entries per level).  lo, hi and w are
+// wave-uniform, and so is the result.
+__device__ __forceinline__ int64_t group_of_unit(const uint64_t *__restrict__ us, int64_t lo,
+                                                 int64_t hi, uint64_t w) {
+    const int lane = threadIdx.x & 63;
+    while (hi - lo > 1) {
+        const int64_t step = (hi - lo + 63) / 64;
+        const int64_t idx = lo + (int64_t)lane * step;
+        const bool le = idx < hi && us[idx] <= w;
+        const int c = __popcll(__ballot(le));  // a prefix of the lanes: lane 0 always
+        const int64_t nlo = lo + (int64_t)(c - 1) * step;
+        hi = min(hi, nlo + step);
+        lo = nlo;
+    }
+    return lo;
+}
+
+// The next group with tiles after g (the first g' > g with us[g'] <= w < us[g' + 1], where
+// w = us[g + 1]): a forward scan by the whole wave, 64 entries per probe, the common case
+// being a short gap of groups without tiles.
+__device__ __forceinline__ int64_t next_group_of_unit(const uint64_t *__restrict__ us, int64_t g,
+                                                      int64_t G, uint64_t w) {
+    const int lane = threadIdx.x & 63;
+    int64_t lo = g + 1;  // us[lo] <= w
+    for (;;) {
+        const int64_t idx = lo + 1 + lane;
+        const bool le = idx < G && us[idx] <= w;
+        const int c = __popcll(__ballot(le));
+        if (c < 64) return lo + c;
+        lo += 64;
+    }
+}
+
+template <bool LAZY, bool SMALL, bool WRITE>
+__global__ __launch_bounds__(64 * EB_WAVES) void k_emit_big(const uint64_t *__restrict__ val,
+                                                           const uint64_t *__restrict__ meta,
+                                                           const uint64_t *__restrict__ lk,
+                                                           const int32_t *__restrict__ len,
+                                                           const int32_t *__restrict__ kk,
+                                                           const int64_t *__restrict__ gs,
+                                                           const int64_t *__restrict__ ge,
+                                                           const uint64_t *__restrict__ us,
+                                                           int64_t G, uint64_t U, uint64_t *wcnt,
+                                                           const uint64_t *__restrict__ wbase,
+                                                           uint64_t *out, int64_t cap,
+                                                           const uint64_t *__restrict__ slot) {
+    // group and tile-pair counts on the device (the streamed join): slot[1], slot[4]
+    if (slot) {
+        G = (int64_t)slot[1];
+        U = G > 0 ? slot[4] : 0;
+    }
+    __shared__ uint64_t buf[WRITE ? EB_WAVES : 1][WRITE ? EB_BUF : 1];
+    // tile J's records, one 16-byte entry each, read by the whole wave at one address:
+    // SMALL {string id, -m, -(2 pos - m), K'}, else {string id, m, pos, K}, where
+    // K' = min(K, 2^31 - 1) as an unsigned word (the same test: |x| < 2^31 below)
+    __shared__ int4 tileJ[EB_WAVES][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
+    const uint64_t wid = (uint64_t)blockIdx.x * EB_WAVES + wave;
+    const uint64_t nwaves = (uint64_t)gridDim.x * EB_WAVES;
+    const uint64_t per = (U + nwaves - 1) / nwaves;
+    uint64_t w = wid * per;
+    const uint64_t wend = min(U, w + per);
+    uint64_t *wb = buf[WRITE ? wave : 0];
+    int4 *tj = tileJ[wave];
+    uint64_t pos = 0;  // WRITE: where the next flushed pair goes
+    if constexpr (WRITE) pos = *wbase + wcnt[wid];
+    uint64_t npass = 0;  // passing pairs so far (COUNT) or staged (WRITE); wave-uniform
+    auto meta_of = [&](int64_t i, uint64_t v) -> uint64_t {
+        if constexpr (LAZY) {
+            const int32_t sid = (int32_t)(v >> 32);
+            if (lk) return lk[sid];
+            return ((uint64_t)(uint32_t)len[sid] << 32) | (uint32_t)kk[sid];
+        } else {
+            return meta[i];
+        }
+    };
+    if (w < wend) {
+        int64_t g = group_of_unit(us, 0, G, w);
+        const uint64_t u = w - us[g];
+        uint64_t J = (uint64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+        while (J > 0 && J * (J + 1) / 2 > u) J--;
+        while ((J + 1) * (J + 2) / 2 <= u) J++;
+        uint64_t I = u - J * (J + 1) / 2;
+        int64_t s0 = gs[g], z = ge[g] - s0 + 1;
+        uint64_t nt = (uint64_t)(z + 63) / 64;
+        int64_t loadedJ = -1;
+        for (;;) {
+            const int64_t ra = (int64_t)I * 64 + lane;
+            const bool ha = ra < z;
+            uint64_t va = 0, xa = 0;
+            if (ha) {
+                va = val[s0 + ra];
+                xa = meta_of(s0 + ra, va);
+            }
+            if ((int64_t)J != loadedJ) {
+                const int64_t rb = (int64_t)J * 64 + lane;
+                uint64_t vb = 0, xb = 0;
+                if (rb < z) {
+                    vb = val[s0 + rb];
+                    xb = meta_of(s0 + rb, vb);
+                }
+                const int32_t mb = (int32_t)(xb >> 32), pb = (int32_t)(uint32_t)vb;
+                wave_fence();  // the previous tile's reads are done
+                if constexpr (SMALL)
+                    tj[lane] = make_int4((int32_t)(vb >> 32), -mb, mb - 2 * pb,
+                                         (int32_t)min((uint32_t)xb, 0x7FFFFFFFu));
+                else
+                    tj[lane] = make_int4((int32_t)(vb >> 32), mb, pb, (int32_t)(uint32_t)xb);
+                wave_fence();  // the tile is in place for every lane
+                loadedJ = (int64_t)J;
+            }
+            const int nb = (int)min<int64_t>(64, z - (int64_t)J * 64);
+            const bool diag = I == J;
+            const uint64_t hmask = __ballot(ha);  // lanes holding a record
+            const int32_t ia = (int32_t)(va >> 32);
+            const int32_t ma = (int32_t)(xa >> 32), pa = (int32_t)(uint32_t)va;
+            const int32_t qa = 2 * pa - ma;
+            const uint32_t ka = SMALL ? min((uint32_t)xa, 0x7FFFFFFFu) : (uint32_t)xa;
+            // the columns j of tile J against every lane's record a; DIAG (I = J): only lanes
+            // l < j (records a < b, which exist as b does)
+            auto columns = [&](auto diag_tag) {
+                constexpr bool DIAG = decltype(diag_tag)::value;
+                uint64_t ok = DIAG ? 0ull : hmask;  // lanes that pair with the column
+                uint32_t cnt = 0;                   // COUNT: passing pairs of the tile pair
+                auto step = [&](int j, const int4 e) {
+                    uint64_t fm;
+                    if constexpr (SMALL) {
+                        // |x| <= K  <=>  x + K <= 2K in 32-bit unsigned arithmetic, exact for
+                        // |x| < 2^31 and K < 2^31: with fewer than 2^29 symbols |m_a - m_b| <
+                        // 2^29 and |(2 pos_a - m_a) - (2 pos_b - m_b)| < 1.5 * 2^30 (the test
+                        // of pass_filter32; a clamped K' passes every such x, as K >= 2^31 does)
+                        const uint32_t K = max(ka, (uint32_t)e.w);
+                        const uint32_t t1 = (uint32_t)(ma + e.y) + K, t2 = (uint32_t)(qa + e.z) + K;
+                        fm = __ballot(max(t1, t2) <= 2 * K);
+                    } else {
+                        fm = __ballot(pass_filter((int64_t)(uint32_t)ma, (int64_t)(uint32_t)pa,
+                                                  (int64_t)(uint32_t)e.y, (int64_t)(uint32_t)e.z,
+                                                  (int64_t)max(ka, (uint32_t)e.w)));
+                    }
+                    const uint64_t mask = fm & __ballot(ia != e.x) & ok;  // the strings differ
+                    if constexpr (DIAG) ok = (ok << 1) | 1ull;            // lanes < j + 1
+                    if constexpr (WRITE) {
+                        if (mask) {
+                            if ((mask >> lane) & 1) {
+                                const uint64_t plo = (uint64_t)min(ia, e.x), phi = (uint64_t)max(ia, e.x);
+                                wb[npass + __popcll(mask & ((1ull << lane) - 1))] = (plo << 32) | phi;
+                            }
+                            npass += (uint64_t)__popcll(mask);
+                            if (npass > EB_BUF - 64) {
+                                wave_fence();  // the lanes' staged writes are in place
+                                for (uint32_t i = lane; i < (uint32_t)npass; i += 64)
+                                    if ((int64_t)(pos + i) < cap) out[pos + i] = wb[i];
+                                pos += npass;
+                                npass = 0;
+                                wave_fence();  // read before the buffer is refilled
+                            }
+                        }
+                    } else {
+                        cnt += (uint32_t)__popcll(mask);
+                    }
+                };
+                // every lane reads the same entries; four at a time, then the rest
+                int j = 0;
+                for (; j + 4 <= nb; j += 4) {
+                    const int4 e0 = tj[j], e1 = tj[j + 1], e2 = tj[j + 2], e3 = tj[j + 3];
+                    step(j, e0);
+                    step(j + 1, e1);
+                    step(j + 2, e2);
+                    step(j + 3, e3);
+                }
+                for (; j < nb; j++) step(j, tj[j]);
+                if constexpr (!WRITE) npass += cnt;
+            };
+            if (diag) columns(std::true_type{});
+            else columns(std::false_type{});
+            // the next tile pair: (I + 1, J), else (0, J + 1), else the next group with tiles
+            if (++w >= wend) break;
+            if (++I > J) {
+                I = 0;
+                if (++J >= nt) {
+                    g = next_group_of_unit(us, g, G, w);
+                    J = 0;
+                    s0 = gs[g];
+                    z = ge[g] - s0 + 1;
+                    nt = (uint64_t)(z + 63) / 64;
+                    loadedJ = -1;
+                }
+            }
+        }
+    }
+    if constexpr (WRITE) {
+        if (npass) {
+            wave_fence();
+            for (uint32_t i = lane; i < (uint32_t)npass; i += 64)
+                if ((int64_t)(pos + i) < cap) out[pos + i] = wb[i];
+        }
+    } else {
+        if (lane == 0) wcnt[wid] = npass;
+    }
+}
+
+// base[0] = the pairs emitted so far (*counter), then *counter += the tile pairs' total
+__global__ void k_emit_big_base(unsigned long long *counter, const uint64_t *total, uint64_t *base) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        base[0] = *counter;
+        *counter += *total;
+    }
+}
+
+// The tile-pair emission: count, scan, base, write (see k_emit_big).  U and G are host
+// values, or taken from slot on the device when slot is given.
+using EmitBigFn = void (*)(const uint64_t *, const uint64_t *, const uint64_t *, const int32_t *,
+                           const int32_t *, const int64_t *, const int64_t *, const uint64_t *,
+                           int64_t, uint64_t, uint64_t *, const uint64_t *, uint64_t *, int64_t,
+                           const uint64_t *);
+template <bool WRITE>
+static EmitBigFn emit_big_fn(bool lazy, bool small) {
+    return lazy ? (small ? k_emit_big<true, true, WRITE> : k_emit_big<true, false, WRITE>)
+                : (small ? k_emit_big<false, true, WRITE> : k_emit_big<false, false, WRITE>);
+}
+// workgroups for U tile pairs: about 2 per wave, at most EB_MAX_BLOCKS (8 waves per SIMD)
+constexpr int64_t EB_MAX_BLOCKS = 2048;
+static int64_t tile_blocks_for(uint64_t units) {
+    return (int64_t)std::max<uint64_t>(
+        1, std::min<uint64_t>((units + 2 * EB_WAVES - 1) / (2 * EB_WAVES), EB_MAX_BLOCKS));
+}
+static void emit_big(const uint64_t *val, const uint64_t *meta, const uint64_t *lk, const DevStrings &d,
+                     const GroupInfo &g, int64_t G, uint64_t U, const uint64_t *slot, bool lazy,
+                     bool small, int64_t blocks, uint64_t *out, int64_t cap,
+                     unsigned long long *counter, Workspace &ws, hipStream_t s) {
+    const int64_t nw = blocks * EB_WAVES;
+    uint64_t *wcnt = ws.get_n<uint64_t>(nw + 1);
+    uint64_t *wpre = ws.get_n<uint64_t>(nw + 1);
+    uint64_t *tot = ws.get_n<uint64_t>(2);
+    hipLaunchKernelGGL(emit_big_fn<false>(lazy, small), dim3((unsigned)blocks), dim3(64 * EB_WAVES), 0,
+                       s, val, meta, lk, d.len, d.kk, g.gstart, g.gend, g.ustart, G, U, wcnt,
+                       (const uint64_t *)nullptr, out, cap, slot);
+    MJ_LAUNCH_CHECK();
+    exclusive_scan_u64_dev(wcnt, wpre, nw, nullptr, tot, ws, s);
+    hipLaunchKernelGGL(k_emit_big_base, dim3(1), dim3(64), 0, s, counter, (const uint64_t *)tot, tot + 1);
+    MJ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(emit_big_fn<true>(lazy, small), dim3((unsigned)blocks), dim3(64 * EB_WAVES), 0,
+                       s, val, meta, lk, d.len, d.kk, g.gstart, g.gend, g.ustart, G, U, wpre,
+                       (const uint64_t *)(tot + 1), out, cap, slot);
+    MJ_LAUNCH_CHECK();
 }
 
 int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, const DevStrings &d,
@@ -331,7 +620,11 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
     if (g.groups == 0 || g.tests == 0) return 0;
     if (t_end == 0 || t_end > g.tests) t_end = g.tests;
     if (t_begin >= t_end) return 0;
-    const uint64_t tests = t_end - t_begin;  // this pass
+    // the whole join in one pass: the small groups test by test, the large ones by tile
+    // pairs; a pass of a join emitted in passes: its range of all groups' tests
+    const bool split = t_begin == 0 && t_end == g.tests;
+    const uint64_t tb = split ? 0 : t_begin, te = split ? g.small_tests : t_end;
+    const uint64_t tests = te - tb;  // test by test
     unsigned long long *counter = (unsigned long long *)ws.get_n<uint64_t>(2);
     fill_u64((uint64_t *)counter, 0, 1, s);
     // the (m, K) words of all records in one pass when the pair tests outnumber the
@@ -354,19 +647,24 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
                            lk, meta, (const int64_t *)nullptr);
         MJ_LAUNCH_CHECK();
     }
-    // a thread locates its first test by a binary search over the groups; with tests
-    // enough for 2^20 threads it takes longer runs (up to 4 x EMIT_CHUNK) per search
-    int chunk = EMIT_CHUNK;
-    while (chunk < 4 * EMIT_CHUNK && tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
-    uint64_t threads = (tests + chunk - 1) / chunk;
-    unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, 1u << 16);
     const bool small = d.total < (1ll << 29);
-    hipLaunchKernelGGL(lazy ? (small ? k_emit<true, true> : k_emit<true, false>)
-                            : (small ? k_emit<false, true> : k_emit<false, false>),
-                       dim3(grid), dim3(EMIT_BLOCK), 0, s, val,
-                       meta, lk, d.len, d.kk, g.gstart, g.tstart, g.groups, t_end, out, cap, counter,
-                       chunk, (const uint64_t *)nullptr, t_begin);
-    MJ_LAUNCH_CHECK();
+    if (tests > 0) {
+        // a thread locates its first test by a binary search over the groups; with tests
+        // enough for 2^20 threads it takes longer runs (up to 4 x EMIT_CHUNK) per search
+        int chunk = EMIT_CHUNK;
+        while (chunk < 4 * EMIT_CHUNK && tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
+        uint64_t threads = (tests + chunk - 1) / chunk;
+        unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, EMIT_MAX_BLOCKS);
+        hipLaunchKernelGGL(lazy ? (small ? k_emit<true, true> : k_emit<true, false>)
+                                : (small ? k_emit<false, true> : k_emit<false, false>),
+                           dim3(grid), dim3(EMIT_BLOCK), 0, s, val, meta, lk, d.len, d.kk, g.gstart,
+                           split ? g.tsmall : g.tstart, g.groups, te, out, cap, counter, chunk,
+                           (const uint64_t *)nullptr, tb);
+        MJ_LAUNCH_CHECK();
+    }
+    if (split && g.units > 0)
+        emit_big(val, meta, lk, d, g, g.groups, g.units, nullptr, lazy, small,
+                 tile_blocks_for(g.units), out, cap, counter, ws, s);
     if (kt) kt->end(th, s);
     uint64_t c = read_back<uint64_t>((const uint64_t *)counter, s, host_scratch);
     if ((int64_t)c > cap) throw Error(MJ_ECAPACITY, "candidate buffer overflow");
@@ -460,27 +758,31 @@ void emit_candidates_streamed(const uint64_t *val, int64_t R_cap, const int64_t 
         MJ_LAUNCH_CHECK();
     }
     const int chunk = std::max(EMIT_CHUNK, h.chunk);
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(h.blocks, 1 << 16));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(h.blocks, EMIT_MAX_BLOCKS));
     const bool small = d.total < (1ll << 29);
+    // the small groups test by test, the large ones by tile pairs (counts in g.slot)
     hipLaunchKernelGGL(h.lazy ? (small ? k_emit<true, true> : k_emit<true, false>)
                               : (small ? k_emit<false, true> : k_emit<false, false>),
                        dim3(grid), dim3(EMIT_BLOCK), 0, s,
-                       val, meta, lk, d.len, d.kk, g.gstart, g.tstart, (int64_t)0, (uint64_t)0, out,
+                       val, meta, lk, d.len, d.kk, g.gstart, g.tsmall, (int64_t)0, (uint64_t)0, out,
                        cap, count, chunk, (const uint64_t *)g.slot, (uint64_t)0);
     MJ_LAUNCH_CHECK();
+    emit_big(val, meta, lk, d, g, 0, 0, g.slot, h.lazy, small,
+             std::max<int64_t>(1, std::min<int64_t>(h.tile_blocks, EB_MAX_BLOCKS)), out, cap, count, ws, s);
     if (kt) kt->end(th, s);
 }
 
-EmitHints emit_hints(uint64_t tests, int64_t R, int32_t n) {
+EmitHints emit_hints(uint64_t tests, uint64_t small_tests, uint64_t units, int64_t R, int32_t n) {
     EmitHints h;
     h.lazy = tests < (uint64_t)R;
     h.string_words = tests >= 16 * (uint64_t)std::max(n, 1);
     int chunk = EMIT_CHUNK;
-    while (chunk < 4 * EMIT_CHUNK && tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
+    while (chunk < 4 * EMIT_CHUNK && small_tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
     h.chunk = chunk;
-    const uint64_t threads = (tests + chunk - 1) / chunk;
+    const uint64_t threads = (small_tests + chunk - 1) / chunk;
     h.blocks = (int64_t)std::max<uint64_t>(1, std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK,
-                                                                  1u << 16));
+                                                                  EMIT_MAX_BLOCKS));
+    h.tile_blocks = tile_blocks_for(units);
     return h;
 }
 

@@ -293,23 +293,34 @@ int64_t partition_records_streamed(const DevStrings &d, const PartitionParams &p
                                    hipStream_t s, KTimer *kt = nullptr);
 
 // join.hip
+// Groups of at least EMIT_TILE records have their pair tests taken by tile pairs (64 x 64
+// records, one wave each); the smaller ones test by test.
+constexpr int EMIT_TILE = 64;
 struct GroupInfo {
     int64_t groups = 0;          // -1: on the device (slot)
-    uint64_t tests = 0;
+    uint64_t tests = 0;          // pair tests of all groups
+    uint64_t small_tests = 0;    // of the groups below EMIT_TILE records
+    uint64_t units = 0;          // tile pairs of the groups of EMIT_TILE or more
     int64_t *gstart = nullptr;   // group start index in the sorted records
-    uint64_t *tstart = nullptr;  // exclusive prefix of pair tests, groups + 1 entries
-    uint64_t *slot = nullptr;    // streamed: [0] c1 | c2 << 32, [1] groups, [2] tests
+    int64_t *gend = nullptr;     // group end index (inclusive)
+    uint64_t *tstart = nullptr;  // exclusive prefix of pair tests, all groups
+    uint64_t *tsmall = nullptr;  // exclusive prefix of pair tests, 0 for the large groups
+    uint64_t *ustart = nullptr;  // exclusive prefix of tile pairs, 0 for the small groups
+    // streamed: [0] c1 | c2 << 32, [1] groups, [2] tests, [3] small tests, [4] tile pairs
+    uint64_t *slot = nullptr;
     int64_t gmax = 0;            // streamed: capacity of the group arrays
 };
-// Speed-only choices of the emission kernel (see emit_candidates): gather (m, K) by string
-// id at each use (lazy), one packed (m, K) word per string, tests per thread, workgroups.
+// Speed-only choices of the emission kernels (see emit_candidates): gather (m, K) by string
+// id at each use (lazy), one packed (m, K) word per string, tests per thread, workgroups of
+// the test-by-test kernel and of the tile-pair kernel.
 struct EmitHints {
     bool lazy = true;
     bool string_words = false;
     int chunk = 16;
     int64_t blocks = 4096;
+    int64_t tile_blocks = 1024;
 };
-EmitHints emit_hints(uint64_t tests, int64_t R, int32_t n);
+EmitHints emit_hints(uint64_t tests, uint64_t small_tests, uint64_t units, int64_t R, int32_t n);
 GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t s,
                       uint64_t *host_scratch);
 // The same with the record count on the device (*R_dev <= R_cap); no host read.

@@ -70,6 +70,28 @@ def heavy_cluster_collection(seed):
     return dg.from_list(strs, 4)
 
 
+def big_group_collection(seed, sigma):
+    """Near-copy clusters of 64, 65, 100, 129 and 200 strings (0.5% edits), strings of
+    tandem repeats of three units at random phases and lengths, and unrelated strings:
+    groups of 64 records and more, whose tests the join takes by 64 x 64 tile pairs, with
+    ragged last tiles, records of one string several times in a group, and pairs that the
+    length and position filter rejects."""
+    rng = np.random.default_rng(seed)
+    strs = []
+    for c, copies in enumerate([64, 65, 100, 129, 200]):
+        base = rng.integers(0, sigma, int(rng.integers(300, 600))).astype(np.uint8)
+        strs += [dg.mutate(np.random.default_rng(seed * 10000 + c * 1000 + i), base, 0.005, sigma)
+                 for i in range(copies)]
+    units = [rng.integers(0, sigma, int(rng.integers(3, 30))).astype(np.uint8) for _ in range(3)]
+    for i in range(60):
+        unit, m = units[i % 3], int(rng.integers(300, 600))
+        ph = int(rng.integers(0, len(unit)))
+        strs.append(np.tile(unit, m // len(unit) + 2)[ph:ph + m])
+    strs += [rng.integers(0, sigma, int(rng.integers(300, 600))).astype(np.uint8) for _ in range(100)]
+    order = np.random.default_rng(seed + 1).permutation(len(strs))
+    return dg.from_list([strs[i] for i in order], sigma)
+
+
 def wide_radius_collection(seed, sigma, n=60):
     """Lengths 50..6000 at T = 2: radii from 7 to ~1000 (regions of 4096 positions, window
     blocks of 8 and 16), plus a homopolymer run (equal q-grams across whole windows)."""
@@ -128,6 +150,9 @@ CASES = {
                                  t_div=1),
     "text_q6": dict(make=lambda: dg.text(seed=7, n=1500), q=6, k=120, t_div=2),
     "dna_heavy_clusters": dict(make=lambda: heavy_cluster_collection(77), q=4, k=20, t_div=1),
+    "dna_big_groups": dict(make=lambda: big_group_collection(91, 4), q=4, k=20, t_div=1),
+    "protein_big_groups": dict(make=lambda: big_group_collection(92, 20), q=3, k_frac=(5, 100),
+                               t_div=2),
     "dna_wide_radius": dict(make=lambda: wide_radius_collection(31, 4), q=4, k=60, t_fixed=2),
     "text_wide_radius_hashed": dict(make=lambda: wide_radius_collection(32, 37), q=6, k=60,
                                     t_fixed=2),
@@ -548,7 +573,7 @@ def test_streamed_join_falls_back_when_candidates_outgrow_the_room(mj):
 
 
 @pytest.mark.parametrize("name", ["dna_mixed_T_from_K", "protein_per_string_K", "text_q6", "dna_reps3",
-                                  "dna_T1_long_reps2"])
+                                  "dna_T1_long_reps2", "protein_big_groups"])
 def test_captured_join_identical(mj, name):
     """Streamed joins captured into HIP graphs (mj_ctx_set_streaming 2) and replayed: each
     replay equals the oracle, also after the strings' content changes in place (same
@@ -614,7 +639,7 @@ def test_member_filter_identical(mj, name, bucket_limit):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["dna_heavy_clusters", "protein_per_string_K"])
+@pytest.mark.parametrize("name", ["dna_heavy_clusters", "protein_per_string_K", "dna_big_groups"])
 def test_join_in_emission_passes(mj, name):
     """A join whose record-pair tests exceed one emission pass (here forced down to 1,024
     tests per pass) emits and deduplicates them in passes: candidates and output equal the
