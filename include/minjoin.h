@@ -177,6 +177,15 @@ mj_status mj_ctx_set_pair_test_pass(mj_ctx *ctx, int64_t tests);
  * group); the filter saves time when most records are unique.  EINVAL for a NULL context,
  * min_records < -1 or bucket_limit < 0. */
 mj_status mj_ctx_set_member_filter(mj_ctx *ctx, int64_t min_records, int32_t bucket_limit);
+/* Candidate emission by tile pairs (Alg. 3's pair tests within a bucket of D): in a join
+ * whose groups of 64 records or more hold at least min_tile_pairs tile pairs of 64 x 64
+ * records (default 32,768; 0: every join with such groups; -1: none), those groups' record
+ * pairs are tested a tile pair per wavefront and the smaller groups' test by test; else
+ * every group's test by test.  Results are the same either way (the same pairs are tested
+ * with the same filter); tile pairs save time when there are many of them.  A streamed
+ * join follows the choice of the last join of its shape.  EINVAL for a NULL context or
+ * min_tile_pairs < -1. */
+mj_status mj_ctx_set_tile_emission(mj_ctx *ctx, int64_t min_tile_pairs);
 
 /* How joins after the first (see mj_join) run: 0 stage by stage, each stage sized exactly
  * from a read-back (the least memory); 1 streamed (the default: stages sized on the device

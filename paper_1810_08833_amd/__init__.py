@@ -86,7 +86,7 @@ class MjReply(ctypes.Structure):
 
 
 EXPORTS = ["mj_ctx_create", "mj_ctx_destroy", "mj_ctx_set_streaming", "mj_ctx_set_pair_test_pass",
-           "mj_ctx_set_member_filter",
+           "mj_ctx_set_member_filter", "mj_ctx_set_tile_emission",
            "mj_last_error", "mj_version", "mj_join",
            "mj_partition", "mj_candidates", "mj_verify", "mj_index_build", "mj_index_free",
            "mj_index_records", "mj_index_bytes", "mj_search", "mj_pairs_count", "mj_pairs_device",
@@ -122,6 +122,8 @@ def load_library(path: str = LIB_PATH):
     L.mj_ctx_set_pair_test_pass.restype = ctypes.c_int
     L.mj_ctx_set_member_filter.argtypes = [VP, ctypes.c_int64, ctypes.c_int32]
     L.mj_ctx_set_member_filter.restype = ctypes.c_int
+    L.mj_ctx_set_tile_emission.argtypes = [VP, ctypes.c_int64]
+    L.mj_ctx_set_tile_emission.restype = ctypes.c_int
     L.mj_last_error.restype = ctypes.c_char_p
     L.mj_version.restype = ctypes.c_char_p
     L.mj_join.argtypes = [VP, P(MjStrings), P(MjParams), VP, P(VP), P(MjStats)]
@@ -237,6 +239,11 @@ class Context:
     def set_pair_test_pass(self, tests: int):
         """Record-pair tests per emission pass (joins with more run in passes)."""
         _check(load_library().mj_ctx_set_pair_test_pass(self.handle, int(tests)))
+
+    def set_tile_emission(self, min_tile_pairs: int):
+        """Joins whose groups of 64 records or more hold at least min_tile_pairs 64 x 64
+        tile pairs (0: every such join, -1: none) test those groups by tile pairs."""
+        _check(load_library().mj_ctx_set_tile_emission(self.handle, int(min_tile_pairs)))
 
     def set_member_filter(self, min_records: int, bucket_limit: int = 0):
         """Joins with at least min_records records sort only the records that may share

@@ -80,6 +80,13 @@ extern "C" mj_status mj_ctx_set_pair_test_pass(mj_ctx *ctx, int64_t tests) {
     return MJ_OK;
 }
 
+extern "C" mj_status mj_ctx_set_tile_emission(mj_ctx *ctx, int64_t min_tile_pairs) {
+    if (!ctx) return fail(MJ_EINVAL, "ctx is NULL");
+    if (min_tile_pairs < -1) return fail(MJ_EINVAL, "min_tile_pairs must be >= -1");
+    ctx->tile_min = min_tile_pairs;
+    return MJ_OK;
+}
+
 extern "C" mj_status mj_ctx_set_member_filter(mj_ctx *ctx, int64_t min_records,
                                               int32_t bucket_limit) {
     if (!ctx) return fail(MJ_EINVAL, "ctx is NULL");
@@ -343,7 +350,8 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
     if (g.tests <= pass_tests) {
         int64_t cap = (int64_t)g.tests;
         uint64_t *cand = ws.get_n<uint64_t>(cap + 1);
-        int64_t c0 = emit_candidates(gval, M, g, d, cand, cap, ws, s, ctx->pinned, &ctx->kt);
+        int64_t c0 = emit_candidates(gval, M, g, d, cand, cap, ws, s, ctx->pinned, ctx->tile_min,
+                                     &ctx->kt);
         ctx->last_c0 = c0;
         tm.mark();  // 3 group + filter
         C = dedup_pairs(cand, c0, d.n, d.n, ws, s, ctx->pinned, &uniq, upto != 1);
@@ -356,7 +364,7 @@ static mj_pairs *run_join(mj_ctx *ctx, const mj_strings *strings, const mj_param
         for (uint64_t t0 = 0; t0 < g.tests; t0 += pass_tests) {
             const uint64_t t1 = std::min(g.tests, t0 + pass_tests);
             int64_t c0 = emit_candidates(gval, M, g, d, cand, (int64_t)pass_tests, ws, s,
-                                         ctx->pinned, &ctx->kt, t0, t1);
+                                         ctx->pinned, ctx->tile_min, &ctx->kt, t0, t1);
             uint64_t *u = nullptr;
             const int64_t nu = dedup_pairs(cand, c0, d.n, d.n, ws, s, ctx->pinned, &u, true);
             parts.push_back({u, nu});
@@ -574,7 +582,8 @@ static mj_pairs *finish_streamed(mj_ctx *ctx, const StreamedPlan &pl, const Stre
     ctx->stream.cand_per_record = (double)c0h / (double)pl.rcap;
     ctx->stream.rec_per_bound = (double)R / (double)pl.rcap;
     ctx->stream.mem_per_bound = (double)M / (double)pl.rcap;
-    ctx->stream.emit = emit_hints((uint64_t)hv[3], (uint64_t)hv[11], (uint64_t)hv[12], M, d.n);
+    ctx->stream.emit = emit_hints((uint64_t)hv[3], (uint64_t)hv[11], (uint64_t)hv[12], M, d.n,
+                                  ctx->tile_min);
     return out;
 }
 
@@ -741,7 +750,7 @@ extern "C" mj_status mj_join(mj_ctx *ctx, const mj_strings *strings, const mj_pa
         h.rec_per_bound = (double)ctx->last_R / (double)std::max<int64_t>(ctx->last_rcap, 1);
         h.mem_per_bound = (double)ctx->last_M / (double)std::max<int64_t>(ctx->last_rcap, 1);
         h.emit = emit_hints((uint64_t)stats->pair_tests, ctx->last_small_tests, ctx->last_units,
-                            stats->members, strings->n);
+                            stats->members, strings->n, ctx->tile_min);
         h.verify_g = ctx->tune.last_g;
         h.verify_blocks = ctx->tune.last_blocks;
     }

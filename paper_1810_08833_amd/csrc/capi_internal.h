@@ -63,6 +63,7 @@ struct mj_ctx {
     // configuration instead of timing the choices on a live call
     bool no_tuning = false;
     int64_t pair_test_pass = (int64_t)1 << 28;  // record-pair tests per emission pass
+    int64_t tile_min = EMIT_SPLIT_UNITS;          // tile pairs for the tile emission (-1: never)
     int64_t member_min = (int64_t)1 << 23;      // records from which the member filter runs
     uint32_t member_big = 1u << 16;             // its buckets above this are kept whole
     int streaming = 1;  // 0 stage by stage, 1 streamed, 2 streamed and captured (mj_ctx_set_streaming)

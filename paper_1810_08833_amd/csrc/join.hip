@@ -48,29 +48,152 @@ __global__ void k_group_flags(const uint64_t *key, int64_t R, uint8_t *fs, uint8
     }
 }
 
-// Pair tests of each group: all of them (cnt), those of the groups below EMIT_TILE
-// records (csmall, 0 for the others) and the tile pairs I <= J of the groups of EMIT_TILE
-// or more (cunits, 0 for the others; nt tiles of EMIT_TILE records give nt (nt + 1) / 2).
-// The group counts c1 (starts) and c2 (ends) are device values: slot[0] = c1 | c2 << 32
-// and slot[1] = min(c1, c2), the groups scanned.
-__global__ void k_group_tests(const int64_t *gs, const int64_t *ge, const uint32_t *c1,
-                              const uint32_t *c2, uint64_t *cnt, uint64_t *csmall,
-                              uint64_t *cunits, uint64_t *slot) {
+// Per group: its pair tests (all), the same for the groups below EMIT_TILE records and 0
+// for the others (small), and the tile pairs I <= J of the groups of EMIT_TILE records or
+// more, 0 for the others (units; nt tiles of EMIT_TILE records give nt (nt + 1) / 2).
+struct GroupCounts {
+    uint64_t all, small, units;
+    __device__ GroupCounts &operator+=(const GroupCounts &o) {
+        all += o.all;
+        small += o.small;
+        units += o.units;
+        return *this;
+    }
+};
+
+__device__ __forceinline__ GroupCounts group_counts(const int64_t *gs, const int64_t *ge, int64_t g) {
+    const uint64_t sz = (uint64_t)(ge[g] - gs[g] + 1);
+    const uint64_t nt = (sz + EMIT_TILE - 1) / EMIT_TILE;
+    const bool big = sz >= (uint64_t)EMIT_TILE;
+    GroupCounts c;
+    c.all = sz * (sz - 1) / 2;
+    c.small = big ? 0 : c.all;
+    c.units = big ? nt * (nt + 1) / 2 : 0;
+    return c;
+}
+
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int d) {
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, d, 64);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), d, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Exclusive scan of one GroupCounts per thread over the block (GS_THREADS threads); the
+// block total goes to *total.
+constexpr int GS_THREADS = 256, GS_ITEMS = 8, GS_TILE = GS_THREADS * GS_ITEMS;
+__device__ GroupCounts block_scan_counts(GroupCounts v, GroupCounts *smem /* [4] */,
+                                         GroupCounts *total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    GroupCounts inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        GroupCounts o;
+        o.all = shfl_up_u64(inc.all, d);
+        o.small = shfl_up_u64(inc.small, d);
+        o.units = shfl_up_u64(inc.units, d);
+        if (lane >= d) inc += o;
+    }
+    if (lane == 63) smem[wv] = inc;
+    __syncthreads();
+    GroupCounts pre = {0, 0, 0}, tot = {0, 0, 0};
+    for (int w = 0; w < GS_THREADS / 64; w++) {
+        if (w < wv) pre += smem[w];
+        tot += smem[w];
+    }
+    __syncthreads();
+    *total = tot;
+    pre += inc;
+    pre.all -= v.all;
+    pre.small -= v.small;
+    pre.units -= v.units;
+    return pre;
+}
+
+// The three exclusive prefixes over the groups, with the group counts c1 (starts) and c2
+// (ends) on the device, in three launches: per-tile sums of GS_TILE groups, a scan of
+// those (one workgroup; totals to slot[2..4] and to the prefixes' entry G), and the
+// prefixes (each group's counts computed again).  slot[0] = c1 | c2 << 32, slot[1] =
+// G = min(c1, c2).
+__global__ __launch_bounds__(GS_THREADS) void k_gscan_reduce(const int64_t *__restrict__ gs,
+                                                            const int64_t *__restrict__ ge,
+                                                            const uint32_t *c1, const uint32_t *c2,
+                                                            GroupCounts *part, uint64_t *slot) {
+    __shared__ GroupCounts smem[GS_THREADS / 64];
     const int64_t G = min(*c1, *c2);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         slot[0] = (uint64_t)*c1 | ((uint64_t)*c2 << 32);
         slot[1] = (uint64_t)G;
     }
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; g < G; g += stride) {
-        const uint64_t sz = (uint64_t)(ge[g] - gs[g] + 1);
-        const uint64_t all = sz * (sz - 1) / 2;
-        const bool big = sz >= (uint64_t)EMIT_TILE;
-        const uint64_t nt = (sz + EMIT_TILE - 1) / EMIT_TILE;
-        cnt[g] = all;
-        csmall[g] = big ? 0 : all;
-        cunits[g] = big ? nt * (nt + 1) / 2 : 0;
+    const int64_t base = (int64_t)blockIdx.x * GS_TILE;
+    if (base >= G) return;  // block-uniform
+    GroupCounts v = {0, 0, 0};
+    for (int k = 0; k < GS_ITEMS; k++) {
+        const int64_t g = base + (int64_t)k * GS_THREADS + threadIdx.x;
+        if (g < G) v += group_counts(gs, ge, g);
+    }
+    GroupCounts tot;
+    block_scan_counts(v, smem, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(GS_THREADS) void k_gscan_top(GroupCounts *part, const uint32_t *c1,
+                                                         const uint32_t *c2, uint64_t *slot,
+                                                         uint64_t *tstart, uint64_t *tsmall,
+                                                         uint64_t *ustart) {
+    __shared__ GroupCounts smem[GS_THREADS / 64];
+    const int64_t G = min(*c1, *c2);
+    const int64_t nb = (G + GS_TILE - 1) / GS_TILE;
+    const int64_t per = (nb + GS_THREADS - 1) / GS_THREADS;  // consecutive tiles per thread
+    const int64_t b0 = (int64_t)threadIdx.x * per, b1 = min(nb, b0 + per);
+    GroupCounts v = {0, 0, 0};
+    for (int64_t b = b0; b < b1; b++) v += part[b];
+    GroupCounts tot;
+    GroupCounts run = block_scan_counts(v, smem, &tot);
+    for (int64_t b = b0; b < b1; b++) {
+        const GroupCounts x = part[b];
+        part[b] = run;
+        run += x;
+    }
+    if (threadIdx.x == 0) {
+        slot[2] = tot.all;
+        slot[3] = tot.small;
+        slot[4] = tot.units;
+        tstart[G] = tot.all;
+        tsmall[G] = tot.small;
+        ustart[G] = tot.units;
+    }
+}
+
+__global__ __launch_bounds__(GS_THREADS) void k_gscan_apply(const int64_t *__restrict__ gs,
+                                                           const int64_t *__restrict__ ge,
+                                                           const uint32_t *c1, const uint32_t *c2,
+                                                           const GroupCounts *__restrict__ part,
+                                                           uint64_t *tstart, uint64_t *tsmall,
+                                                           uint64_t *ustart) {
+    __shared__ GroupCounts smem[GS_THREADS / 64];
+    const int64_t G = min(*c1, *c2);
+    const int64_t base = (int64_t)blockIdx.x * GS_TILE;
+    if (base >= G) return;  // block-uniform
+    // the thread's GS_ITEMS consecutive groups
+    const int64_t g0 = base + (int64_t)threadIdx.x * GS_ITEMS;
+    GroupCounts c[GS_ITEMS], v = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < GS_ITEMS; k++) {
+        c[k] = {0, 0, 0};
+        if (g0 + k < G) c[k] = group_counts(gs, ge, g0 + k);
+        v += c[k];
+    }
+    GroupCounts tot;
+    GroupCounts run = block_scan_counts(v, smem, &tot);
+    run += part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < GS_ITEMS; k++) {
+        if (g0 + k < G) {
+            tstart[g0 + k] = run.all;
+            tsmall[g0 + k] = run.small;
+            ustart[g0 + k] = run.units;
+        }
+        run += c[k];
     }
 }
 
@@ -90,20 +213,21 @@ static GroupInfo group_tests(const uint64_t *key, int64_t R, const int64_t *R_de
     const uint32_t *c1 = compact_flags_async(fs, R, gs, ws, s);
     const uint32_t *c2 = compact_flags_async(fe, R, ge, ws, s);
     const int64_t gmax = R / 2;
-    uint64_t *cnt = ws.get_n<uint64_t>(gmax + 1);
-    uint64_t *csmall = ws.get_n<uint64_t>(gmax + 1);
-    uint64_t *cunits = ws.get_n<uint64_t>(gmax + 1);
+    const int64_t nb = std::max<int64_t>(1, (gmax + GS_TILE - 1) / GS_TILE);
+    GroupCounts *part = reinterpret_cast<GroupCounts *>(ws.get_n<uint64_t>(3 * (nb + 1)));
     gi.tstart = ws.get_n<uint64_t>(gmax + 1);
     gi.tsmall = ws.get_n<uint64_t>(gmax + 1);
     gi.ustart = ws.get_n<uint64_t>(gmax + 1);
     uint64_t *slot = ws.get_n<uint64_t>(5);
-    hipLaunchKernelGGL(k_group_tests, dim3(grid_for(gmax, 256, 16384)), dim3(256), 0, s, gs, ge, c1,
-                       c2, cnt, csmall, cunits, slot);
+    hipLaunchKernelGGL(k_gscan_reduce, dim3((unsigned)nb), dim3(GS_THREADS), 0, s, gs, ge, c1, c2, part,
+                       slot);
     MJ_LAUNCH_CHECK();
-    const uint32_t *G_dev = reinterpret_cast<const uint32_t *>(slot + 1);
-    exclusive_scan_u64_dev(cnt, gi.tstart, gmax, G_dev, slot + 2, ws, s);
-    exclusive_scan_u64_dev(csmall, gi.tsmall, gmax, G_dev, slot + 3, ws, s);
-    exclusive_scan_u64_dev(cunits, gi.ustart, gmax, G_dev, slot + 4, ws, s);
+    hipLaunchKernelGGL(k_gscan_top, dim3(1), dim3(GS_THREADS), 0, s, part, c1, c2, slot, gi.tstart,
+                       gi.tsmall, gi.ustart);
+    MJ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gscan_apply, dim3((unsigned)nb), dim3(GS_THREADS), 0, s, gs, ge, c1, c2,
+                       (const GroupCounts *)part, gi.tstart, gi.tsmall, gi.ustart);
+    MJ_LAUNCH_CHECK();
     gi.gstart = gs;
     gi.gend = ge;
     gi.slot = slot;
@@ -171,9 +295,6 @@ __device__ __forceinline__ bool pass_filter32(int32_t mi, int32_t pi, int32_t mj
 // device-wide atomic per block and sweep: a single counter bumped by every wave of all
 // XCDs serialises (device-scope atomics are not served by an XCD's own L2).
 constexpr int EMIT_BLOCK = 256;
-// k_emit's workgroups, at most: as many as stay resident (four 33 KB stages per CU), each
-// looping over sweeps with its stage kept across them
-constexpr unsigned EMIT_MAX_BLOCKS = 1024;
 struct EmitStage {
     uint64_t buf[EMIT_BLOCK * EMIT_CHUNK];
     uint32_t n;
@@ -191,13 +312,11 @@ __device__ __forceinline__ void stage(bool pass, uint64_t v, EmitStage &st) {
     if (pass) st.buf[base + __popcll(mask & ((1ull << lane) - 1))] = v;
 }
 
-// Block-uniform: every thread of the block calls it at the same point.  The stage is
-// written out when it holds more than `keep` pairs (0: whenever it holds any).
+// Block-uniform: every thread of the block calls it after the same sweep.
 __device__ __forceinline__ void flush(EmitStage &st, unsigned long long *counter, uint64_t *out,
-                                      int64_t cap, uint32_t keep = 0) {
+                                      int64_t cap) {
     __syncthreads();
-    const uint32_t n0 = st.n;
-    const uint32_t n = n0 > keep ? n0 : 0;
+    const uint32_t n = st.n;
     if (threadIdx.x == 0 && n) st.base = atomicAdd(counter, (unsigned long long)n);
     __syncthreads();
     if (n) {
@@ -228,6 +347,24 @@ __global__ void k_record_meta(const uint64_t *__restrict__ val, int64_t R,
     for (; i < R; i += stride) meta[i] = lk[(int32_t)(val[i] >> 32)];
 }
 
+// Largest g in [lo, hi) with us[g] <= w, given us[lo] <= w (us non-decreasing): a 64-way
+// search by the whole wave (one probe of 64 entries per level; every lane of the wave
+// takes part).  lo, hi and w are wave-uniform, and so is the result.
+__device__ __forceinline__ int64_t last_le_wave(const uint64_t *__restrict__ us, int64_t lo,
+                                                int64_t hi, uint64_t w) {
+    const int lane = threadIdx.x & 63;
+    while (hi - lo > 1) {
+        const int64_t step = (hi - lo + 63) / 64;
+        const int64_t idx = lo + (int64_t)lane * step;
+        const bool le = idx < hi && us[idx] <= w;
+        const int c = __popcll(__ballot(le));  // a prefix of the lanes: lane 0 always
+        const int64_t nlo = lo + (int64_t)(c - 1) * step;
+        hi = min(hi, nlo + step);
+        lo = nlo;
+    }
+    return lo;
+}
+
 // LAZY: no meta array; a record's (m, K) word is gathered by its string id at each use
 // (fewer pair tests than records, as on text and DNA), from lk if given, else from the
 // length and K arrays.  SMALL: the input holds fewer than 2^29 symbols (32-bit filter).
@@ -241,12 +378,13 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
                                               const uint64_t *__restrict__ ts, int64_t G,
                                               uint64_t P, uint64_t *out, int64_t cap,
                                               unsigned long long *counter, int chunk,
-                                              const uint64_t *__restrict__ slot, uint64_t tb) {
+                                              const uint64_t *__restrict__ slot, int pslot,
+                                              uint64_t tb) {
     // group and test counts on the device (the streamed join): slot[1], and the tests of
-    // the groups below EMIT_TILE records, slot[3]
+    // all groups (pslot 2) or of the groups below EMIT_TILE records (pslot 3)
     if (slot) {
         G = (int64_t)slot[1];
-        P = G > 0 ? slot[3] : 0;
+        P = G > 0 ? slot[pslot] : 0;
     }
     // tests [tb, P): the whole range, or one pass of a join emitted in passes
     __shared__ EmitStage st;
@@ -336,14 +474,10 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
                 }
             }
             stage(pass, pairkey, st);
-            // the stage holds EMIT_CHUNK tests per thread and is written out once more than
-            // half full (checked every 8 tests: at most half of it added in between), so a
-            // block takes the shared counter about once per 2,048 passing pairs and once at
-            // the end, not once per sweep
-            if ((c & 7) == 7) flush(st, counter, out, cap, EMIT_BLOCK * EMIT_CHUNK / 2);
+            // the stage holds EMIT_CHUNK tests per thread (chunk is a multiple of it)
+            if ((c & (EMIT_CHUNK - 1)) == EMIT_CHUNK - 1) flush(st, counter, out, cap);
         }
     }
-    flush(st, counter, out, cap);
 }
 
 // Pair tests of the groups of EMIT_TILE records or more, by tile pairs.  A group of z
@@ -363,24 +497,6 @@ __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Largest g in [lo, hi) with us[g] <= w, given us[lo] <= w (us non-decreasing): a 64-way
-// search by the whole wave (one coalesced probe of 64 entries per level).  lo, hi and w are
-// wave-uniform, and so is the result.
-__device__ __forceinline__ int64_t group_of_unit(const uint64_t *__restrict__ us, int64_t lo,
-                                                 int64_t hi, uint64_t w) {
-    const int lane = threadIdx.x & 63;
-    while (hi - lo > 1) {
-        const int64_t step = (hi - lo + 63) / 64;
-        const int64_t idx = lo + (int64_t)lane * step;
-        const bool le = idx < hi && us[idx] <= w;
-        const int c = __popcll(__ballot(le));  // a prefix of the lanes: lane 0 always
-        const int64_t nlo = lo + (int64_t)(c - 1) * step;
-        hi = min(hi, nlo + step);
-        lo = nlo;
-    }
-    return lo;
 }
 
 // The next group with tiles after g (the first g' > g with us[g'] <= w < us[g' + 1], where
@@ -444,7 +560,7 @@ __global__ __launch_bounds__(64 * EB_WAVES) void k_emit_big(const uint64_t *__re
         }
     };
     if (w < wend) {
-        int64_t g = group_of_unit(us, 0, G, w);
+        int64_t g = last_le_wave(us, 0, G, w);
         const uint64_t u = w - us[g];
         uint64_t J = (uint64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
         while (J > 0 && J * (J + 1) / 2 > u) J--;
@@ -576,6 +692,12 @@ __global__ void k_emit_big_base(unsigned long long *counter, const uint64_t *tot
     }
 }
 
+// Whether the large groups go by tile pairs (tile_min: -1 never, else at least
+// max(tile_min, 1) tile pairs).
+static bool split_pays(uint64_t units, int64_t tile_min) {
+    return tile_min >= 0 && units >= (uint64_t)std::max<int64_t>(tile_min, 1);
+}
+
 // The tile-pair emission: count, scan, base, write (see k_emit_big).  U and G are host
 // values, or taken from slot on the device when slot is given.
 using EmitBigFn = void (*)(const uint64_t *, const uint64_t *, const uint64_t *, const int32_t *,
@@ -616,13 +738,15 @@ static void emit_big(const uint64_t *val, const uint64_t *meta, const uint64_t *
 
 int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, const DevStrings &d,
                         uint64_t *out, int64_t cap, Workspace &ws, hipStream_t s,
-                        uint64_t *host_scratch, KTimer *kt, uint64_t t_begin, uint64_t t_end) {
+                        uint64_t *host_scratch, int64_t tile_min, KTimer *kt, uint64_t t_begin,
+                        uint64_t t_end) {
     if (g.groups == 0 || g.tests == 0) return 0;
     if (t_end == 0 || t_end > g.tests) t_end = g.tests;
     if (t_begin >= t_end) return 0;
-    // the whole join in one pass: the small groups test by test, the large ones by tile
-    // pairs; a pass of a join emitted in passes: its range of all groups' tests
-    const bool split = t_begin == 0 && t_end == g.tests;
+    // the whole join in one pass: the small groups test by test and the large ones by
+    // tile pairs, when those are many enough; else (and for a pass of a join emitted in
+    // passes) the range of all groups' tests, test by test
+    const bool split = t_begin == 0 && t_end == g.tests && split_pays(g.units, tile_min);
     const uint64_t tb = split ? 0 : t_begin, te = split ? g.small_tests : t_end;
     const uint64_t tests = te - tb;  // test by test
     unsigned long long *counter = (unsigned long long *)ws.get_n<uint64_t>(2);
@@ -654,12 +778,12 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
         int chunk = EMIT_CHUNK;
         while (chunk < 4 * EMIT_CHUNK && tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
         uint64_t threads = (tests + chunk - 1) / chunk;
-        unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, EMIT_MAX_BLOCKS);
+        unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, 1u << 16);
         hipLaunchKernelGGL(lazy ? (small ? k_emit<true, true> : k_emit<true, false>)
                                 : (small ? k_emit<false, true> : k_emit<false, false>),
                            dim3(grid), dim3(EMIT_BLOCK), 0, s, val, meta, lk, d.len, d.kk, g.gstart,
                            split ? g.tsmall : g.tstart, g.groups, te, out, cap, counter, chunk,
-                           (const uint64_t *)nullptr, tb);
+                           (const uint64_t *)nullptr, 0, tb);
         MJ_LAUNCH_CHECK();
     }
     if (split && g.units > 0)
@@ -758,30 +882,37 @@ void emit_candidates_streamed(const uint64_t *val, int64_t R_cap, const int64_t 
         MJ_LAUNCH_CHECK();
     }
     const int chunk = std::max(EMIT_CHUNK, h.chunk);
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(h.blocks, EMIT_MAX_BLOCKS));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(h.blocks, 1 << 16));
     const bool small = d.total < (1ll << 29);
-    // the small groups test by test, the large ones by tile pairs (counts in g.slot)
+    // split (as the last join of this shape chose): the small groups test by test, the
+    // large ones by tile pairs; else every group test by test (counts in g.slot)
     hipLaunchKernelGGL(h.lazy ? (small ? k_emit<true, true> : k_emit<true, false>)
                               : (small ? k_emit<false, true> : k_emit<false, false>),
                        dim3(grid), dim3(EMIT_BLOCK), 0, s,
-                       val, meta, lk, d.len, d.kk, g.gstart, g.tsmall, (int64_t)0, (uint64_t)0, out,
-                       cap, count, chunk, (const uint64_t *)g.slot, (uint64_t)0);
+                       val, meta, lk, d.len, d.kk, g.gstart, h.split ? g.tsmall : g.tstart, (int64_t)0,
+                       (uint64_t)0, out, cap, count, chunk, (const uint64_t *)g.slot, h.split ? 3 : 2,
+                       (uint64_t)0);
     MJ_LAUNCH_CHECK();
-    emit_big(val, meta, lk, d, g, 0, 0, g.slot, h.lazy, small,
-             std::max<int64_t>(1, std::min<int64_t>(h.tile_blocks, EB_MAX_BLOCKS)), out, cap, count, ws, s);
+    if (h.split)
+        emit_big(val, meta, lk, d, g, 0, 0, g.slot, h.lazy, small,
+                 std::max<int64_t>(1, std::min<int64_t>(h.tile_blocks, EB_MAX_BLOCKS)), out, cap, count,
+                 ws, s);
     if (kt) kt->end(th, s);
 }
 
-EmitHints emit_hints(uint64_t tests, uint64_t small_tests, uint64_t units, int64_t R, int32_t n) {
+EmitHints emit_hints(uint64_t tests, uint64_t small_tests, uint64_t units, int64_t R, int32_t n,
+                     int64_t tile_min) {
     EmitHints h;
     h.lazy = tests < (uint64_t)R;
     h.string_words = tests >= 16 * (uint64_t)std::max(n, 1);
+    h.split = split_pays(units, tile_min);
+    const uint64_t tt = h.split ? small_tests : tests;  // test by test
     int chunk = EMIT_CHUNK;
-    while (chunk < 4 * EMIT_CHUNK && small_tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
+    while (chunk < 4 * EMIT_CHUNK && tt / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
     h.chunk = chunk;
-    const uint64_t threads = (small_tests + chunk - 1) / chunk;
+    const uint64_t threads = (tt + chunk - 1) / chunk;
     h.blocks = (int64_t)std::max<uint64_t>(1, std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK,
-                                                                  EMIT_MAX_BLOCKS));
+                                                                  1u << 16));
     h.tile_blocks = tile_blocks_for(units);
     return h;
 }

@@ -294,8 +294,12 @@ int64_t partition_records_streamed(const DevStrings &d, const PartitionParams &p
 
 // join.hip
 // Groups of at least EMIT_TILE records have their pair tests taken by tile pairs (64 x 64
-// records, one wave each); the smaller ones test by test.
+// records, one wave each) in a join with at least EMIT_SPLIT_UNITS such tile pairs (a
+// context setting); the smaller groups test by test.  With fewer tile pairs the two tile
+// passes sit at their latency floor (about 75 us each) and the smaller groups gain little
+// (measured: text, 9.5e3 tile pairs, loses 0.05 ms; protein, about 1e5, gains 0.4 ms).
 constexpr int EMIT_TILE = 64;
+constexpr int64_t EMIT_SPLIT_UNITS = (int64_t)1 << 15;
 struct GroupInfo {
     int64_t groups = 0;          // -1: on the device (slot)
     uint64_t tests = 0;          // pair tests of all groups
@@ -311,16 +315,20 @@ struct GroupInfo {
     int64_t gmax = 0;            // streamed: capacity of the group arrays
 };
 // Speed-only choices of the emission kernels (see emit_candidates): gather (m, K) by string
-// id at each use (lazy), one packed (m, K) word per string, tests per thread, workgroups of
-// the test-by-test kernel and of the tile-pair kernel.
+// id at each use (lazy), one packed (m, K) word per string, the large groups by tile pairs
+// (split), tests per thread, workgroups of the test-by-test kernel and of the tile-pair
+// kernel.
 struct EmitHints {
     bool lazy = true;
     bool string_words = false;
+    bool split = false;
     int chunk = 16;
     int64_t blocks = 4096;
     int64_t tile_blocks = 1024;
 };
-EmitHints emit_hints(uint64_t tests, uint64_t small_tests, uint64_t units, int64_t R, int32_t n);
+// tile_min: the context's threshold (tile pairs; -1: never by tile pairs)
+EmitHints emit_hints(uint64_t tests, uint64_t small_tests, uint64_t units, int64_t R, int32_t n,
+                     int64_t tile_min);
 GroupInfo find_groups(const uint64_t *key, int64_t R, Workspace &ws, hipStream_t s,
                       uint64_t *host_scratch);
 // The same with the record count on the device (*R_dev <= R_cap); no host read.
@@ -335,10 +343,11 @@ const uint32_t *dedup_pairs_streamed(uint64_t *pairs, int64_t cap, const unsigne
                                      uint64_t **result);
 // Emit candidate pair keys for all pair tests; returns count emitted (<= cap).
 // Tests [t_begin, t_end) only when t_end > 0 (a join emitted in passes).
+// tile_min as for emit_hints.
 int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, const DevStrings &d,
                         uint64_t *out, int64_t cap, Workspace &ws, hipStream_t s,
-                        uint64_t *host_scratch, KTimer *kt = nullptr, uint64_t t_begin = 0,
-                        uint64_t t_end = 0);
+                        uint64_t *host_scratch, int64_t tile_min, KTimer *kt = nullptr,
+                        uint64_t t_begin = 0, uint64_t t_end = 0);
 // Sorted unique copy of pairs (first << 32 | second, first < n_first, second <
 // n_second) in *result (owned allocation); sorts `pairs` in place; returns the count.
 // The distinct pairs in *result: a workspace block when to_ws, else a result buffer

@@ -639,6 +639,35 @@ def test_member_filter_identical(mj, name, bucket_limit):
     ctx.close()
 
 
+@pytest.mark.parametrize("tile_min", [0, -1])
+@pytest.mark.parametrize("name", ["dna_big_groups", "protein_big_groups", "dna_heavy_clusters",
+                                  "text_q6"])
+def test_tile_emission_identical(mj, name, tile_min):
+    """Candidate emission with the groups of 64 records or more tested by 64 x 64 tile
+    pairs (mj_ctx_set_tile_emission 0: whenever there is one) or every group test by test
+    (-1): candidates and output equal the oracle's, stage by stage, streamed and captured."""
+    say("tile emission", name, tile_min)
+    S, op, gp = run_case(mj, name)
+    cand_w, out_w, st_w = oracle.join(S.chars, S.offsets, op)
+    ctx = mj.Context()
+    ctx.set_tile_emission(tile_min)
+    ds = dev(mj, S)
+    cand, st = mj.candidates(ds, gp, ctx=ctx)
+    assert np.array_equal(cand, cand_w) and st["pair_tests"] == st_w["pair_tests"]
+    modes = []
+    for _ in range(2):
+        out, st = mj.join(ds, gp, ctx=ctx)
+        assert np.array_equal(out, out_w) and st["pair_tests"] == st_w["pair_tests"]
+        modes.append(st["streamed"])
+    assert modes == [0, 1]
+    ctx.set_streaming(2)
+    for _ in range(2):
+        out, st = mj.join(ds, gp, ctx=ctx)
+        assert np.array_equal(out, out_w)
+    assert st["streamed"] == 2
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["dna_heavy_clusters", "protein_per_string_K", "dna_big_groups"])
 def test_join_in_emission_passes(mj, name):
     """A join whose record-pair tests exceed one emission pass (here forced down to 1,024
