@@ -171,29 +171,50 @@ __global__ __launch_bounds__(GS_THREADS) void k_gscan_apply(const int64_t *__res
                                                            uint64_t *tstart, uint64_t *tsmall,
                                                            uint64_t *ustart) {
     __shared__ GroupCounts smem[GS_THREADS / 64];
+    __shared__ uint64_t zs[GS_TILE];  // group sizes of the tile, read coalesced
     const int64_t G = min(*c1, *c2);
     const int64_t base = (int64_t)blockIdx.x * GS_TILE;
     if (base >= G) return;  // block-uniform
+    for (int k = 0; k < GS_ITEMS; k++) {
+        const int i = k * GS_THREADS + threadIdx.x;
+        zs[i] = base + i < G ? (uint64_t)(ge[base + i] - gs[base + i] + 1) : 0;
+    }
+    __syncthreads();
     // the thread's GS_ITEMS consecutive groups
-    const int64_t g0 = base + (int64_t)threadIdx.x * GS_ITEMS;
+    const int i0 = threadIdx.x * GS_ITEMS;
     GroupCounts c[GS_ITEMS], v = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < GS_ITEMS; k++) {
-        c[k] = {0, 0, 0};
-        if (g0 + k < G) c[k] = group_counts(gs, ge, g0 + k);
+        const uint64_t sz = zs[i0 + k];
+        const uint64_t nt = (sz + EMIT_TILE - 1) / EMIT_TILE;
+        const bool big = sz >= (uint64_t)EMIT_TILE;
+        c[k].all = sz ? sz * (sz - 1) / 2 : 0;
+        c[k].small = big ? 0 : c[k].all;
+        c[k].units = big ? nt * (nt + 1) / 2 : 0;
         v += c[k];
     }
     GroupCounts tot;
     GroupCounts run = block_scan_counts(v, smem, &tot);
     run += part[blockIdx.x];
+    GroupCounts pre[GS_ITEMS];
 #pragma unroll
     for (int k = 0; k < GS_ITEMS; k++) {
-        if (g0 + k < G) {
-            tstart[g0 + k] = run.all;
-            tsmall[g0 + k] = run.small;
-            ustart[g0 + k] = run.units;
-        }
+        pre[k] = run;
         run += c[k];
+    }
+    // each prefix through the LDS tile, then stored coalesced
+    uint64_t *const dst[3] = {tstart, tsmall, ustart};
+#pragma unroll
+    for (int f = 0; f < 3; f++) {
+        __syncthreads();  // the tile's previous contents are read
+#pragma unroll
+        for (int k = 0; k < GS_ITEMS; k++)
+            zs[i0 + k] = f == 0 ? pre[k].all : f == 1 ? pre[k].small : pre[k].units;
+        __syncthreads();
+        for (int k = 0; k < GS_ITEMS; k++) {
+            const int i = k * GS_THREADS + threadIdx.x;
+            if (base + i < G) dst[f][base + i] = zs[i];
+        }
     }
 }
 
@@ -365,6 +386,28 @@ __device__ __forceinline__ int64_t last_le_wave(const uint64_t *__restrict__ us,
     return lo;
 }
 
+// Largest g in [lo, hi) with a[g] <= w, given a[lo] <= w (a non-decreasing), for
+// wave-uniform arguments: a binary search whose loads are the same for every lane.
+__device__ __forceinline__ int64_t last_le_uniform(const uint64_t *__restrict__ a, int64_t lo,
+                                                   int64_t hi, uint64_t w) {
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] <= w) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// The same, galloping up from lo (for a w close above a[lo]).
+__device__ __forceinline__ int64_t last_le_gallop(const uint64_t *__restrict__ a, int64_t lo,
+                                                  int64_t hi, uint64_t w) {
+    int64_t step = 1;
+    while (lo + step < hi && a[lo + step] <= w) {
+        lo += step;
+        step <<= 1;
+    }
+    return last_le_uniform(a, lo, min(hi, lo + step), w);
+}
+
 // LAZY: no meta array; a record's (m, K) word is gathered by its string id at each use
 // (fewer pair tests than records, as on text and DNA), from lk if given, else from the
 // length and K arrays.  SMALL: the input holds fewer than 2^29 symbols (32-bit filter).
@@ -398,8 +441,20 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
         bool active = t0 < P;
         int64_t g = 0;
         uint64_t a = 0, b = 1;
+        // The groups of the wave's first and last runs (lane 0's t0 and lane 63's, at most
+        // P - 1), by one search with the same loads for every lane (a binary search, then a
+        // gallop); each lane then searches that short range.  Searches of 64 far-apart
+        // groups per wave missed the caches at their deeper levels.
+        int64_t gA = 0, gB = G;
+        const uint64_t tw0 = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t0)) |
+                             ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t0 >> 32)) << 32);
+        if (tw0 < P) {  // wave-uniform
+            const uint64_t twl = min(P - 1, tw0 + (uint64_t)63 * chunk);
+            gA = last_le_uniform(ts, 0, G, tw0);
+            gB = last_le_gallop(ts, gA, G, twl) + 1;
+        }
         if (active) {
-            int64_t lo = 0, hi = G;  // largest g with ts[g] <= t0
+            int64_t lo = gA, hi = gB;  // largest g with ts[g] <= t0
             while (hi - lo > 1) {
                 int64_t mid = (lo + hi) >> 1;
                 if (ts[mid] <= t0) lo = mid; else hi = mid;
@@ -774,9 +829,13 @@ int64_t emit_candidates(const uint64_t *val, int64_t R, const GroupInfo &g, cons
     const bool small = d.total < (1ll << 29);
     if (tests > 0) {
         // a thread locates its first test by a binary search over the groups; with tests
-        // enough for 2^20 threads it takes longer runs (up to 4 x EMIT_CHUNK) per search
+        // enough for 2^20 threads it takes longer runs (up to 4 x EMIT_CHUNK) per search,
+        // but not when only the groups below EMIT_TILE records are left (split): there
+        // every lane of a wave walks other groups' records, and longer runs put more
+        // records in flight than an XCD's L2 holds
         int chunk = EMIT_CHUNK;
-        while (chunk < 4 * EMIT_CHUNK && tests / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
+        while (!split && chunk < 4 * EMIT_CHUNK && tests / (uint64_t)(2 * chunk) >= (1ull << 20))
+            chunk *= 2;
         uint64_t threads = (tests + chunk - 1) / chunk;
         unsigned grid = (unsigned)std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK, 1u << 16);
         hipLaunchKernelGGL(lazy ? (small ? k_emit<true, true> : k_emit<true, false>)
@@ -907,8 +966,8 @@ EmitHints emit_hints(uint64_t tests, uint64_t small_tests, uint64_t units, int64
     h.string_words = tests >= 16 * (uint64_t)std::max(n, 1);
     h.split = split_pays(units, tile_min);
     const uint64_t tt = h.split ? small_tests : tests;  // test by test
-    int chunk = EMIT_CHUNK;
-    while (chunk < 4 * EMIT_CHUNK && tt / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
+    int chunk = EMIT_CHUNK;  // as in emit_candidates
+    while (!h.split && chunk < 4 * EMIT_CHUNK && tt / (uint64_t)(2 * chunk) >= (1ull << 20)) chunk *= 2;
     h.chunk = chunk;
     const uint64_t threads = (tt + chunk - 1) / chunk;
     h.blocks = (int64_t)std::max<uint64_t>(1, std::min<uint64_t>((threads + EMIT_BLOCK - 1) / EMIT_BLOCK,
