@@ -43,6 +43,9 @@ def test_null_arguments_are_rejected_before_any_device_work():
     bad = mj.MjAllocator()  # an allocator without alloc/free
     assert lib.mj_ctx_create(0, ctypes.byref(bad), ctypes.byref(out)) == mj.MJ_EINVAL
     assert lib.mj_pairs_copy_to_host(None, None, 0) == mj.MJ_EINVAL
+    assert lib.mj_ctx_set_pair_test_pass(None, 1 << 20) == mj.MJ_EINVAL
+    assert lib.mj_ctx_set_member_filter(None, 0, 0) == mj.MJ_EINVAL
+    assert lib.mj_ctx_set_tile_emission(None, 0) == mj.MJ_EINVAL
     assert lib.mj_pairs_count(None) == 0
     assert lib.mj_records_count(None) == 0
     lib.mj_pairs_free(None)

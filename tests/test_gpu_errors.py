@@ -138,3 +138,20 @@ def test_index_keeps_its_own_pi_table(mj):
     assert len(want) > 0 and np.array_equal(got, want)
     del junk
     index.close()
+
+
+def test_context_settings_reject_bad_values(mj):
+    """The context's tuning switches reject out-of-range values with EINVAL and keep
+    working afterwards."""
+    say("context settings")
+    ctx = mj.Context()
+    assert status_of(lambda: ctx.set_tile_emission(-2)) == mj.MJ_EINVAL
+    assert status_of(lambda: ctx.set_pair_test_pass(1023)) == mj.MJ_EINVAL
+    assert status_of(lambda: ctx.set_member_filter(-2)) == mj.MJ_EINVAL
+    ctx.set_tile_emission(-1)
+    ctx.set_tile_emission(0)
+    S = dg.dna_small(seed=5, n_clusters=4, copies=3)
+    out, st = mj.join(dev(mj, S), mj.Params(q=4, k=20, t_div=1), ctx=ctx)
+    assert st["candidates"] >= out.size
+    ctx.close()
+
