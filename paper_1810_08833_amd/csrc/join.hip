@@ -539,12 +539,13 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
 // records is cut into nt = ceil(z / 64) tiles; tile pair u = J (J + 1) / 2 + I, I <= J,
 // tests records a = 64 I + l against b = 64 J + j (a < b: l < j when I = J), the same
 // pairs as the group's tests in k_emit, each once.  A wave takes a tile pair: lane l holds
-// record a, the 64 records of tile J are broadcast one by one from the lanes that loaded
-// them, so the inner loop reads no memory.  Wave k takes the tile pairs [k per, (k + 1) per)
-// in order (one group search, then a walk).  The kernel runs twice with the same grid:
-// COUNT writes each wave's passing pairs to wcnt[k]; after an exclusive scan of those
-// (wpre) WRITE stores them at out[*wbase + wpre[k] ..), staged per wave in LDS: no shared
-// counter (a device atomic on one address, taken by every wave, serialises).
+// record a, tile J's records are staged in LDS and read by the whole wave at one address
+// per column, so the inner loop reads no global memory.  Wave k takes the tile pairs
+// [k per, (k + 1) per) in order (one group search, then a walk).  The kernel runs twice
+// with the same grid: COUNT writes the number of each wave's passing pairs to wcnt[k];
+// after an exclusive scan of those (wpre) WRITE stores the pairs at out[*wbase + wpre[k]
+// ..), staged per wave in LDS: no shared counter (a device atomic on one address, taken
+// by every wave, serialises).
 constexpr int EB_WAVES = 4;   // waves per workgroup
 constexpr int EB_BUF = 512;   // staged pairs per wave
 
