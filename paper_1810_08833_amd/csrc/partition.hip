@@ -1463,8 +1463,9 @@ __attribute__((amdgpu_waves_per_eu(REGION == 2048 ? 4 : 2))) void k_records_tile
 #pragma unroll
     for (int k = 0; k < RUN; k++) q[k] = pq[REGION + 1 + j0 + k];
     // loads of one tile: the thread's symbols (0 outside the input), the descriptor's words
-    // (threads < 32), the record base of repetition `tid` (threads < 64), and the tile's
-    // flag word `lane` of repetitions `wave` and `wave + RT_WAVES`
+    // (threads < 32), the record base of repetition `tid` (threads < 64), and flag word
+    // `lane` of the region (the tile's words, then the halo's) of repetitions `wave` and
+    // `wave + RT_WAVES`
     uint32_t x[RUN], tdw = 0;
     int64_t r0l = 0;
     uint64_t bw0 = 0, bw1 = 0;
@@ -1493,7 +1494,7 @@ __attribute__((amdgpu_waves_per_eu(REGION == 2048 ? 4 : 2))) void k_records_tile
         if (tid < 32) tdw = reinterpret_cast<const uint32_t *>(tdesc + tile)[tid];
         if (tid < 64) r0l = tid < reps ? rbase[tid] + (int64_t)pre[tid * pre_stride + tile] : 0;
         const int64_t w = tile * TP / 64 + lane;
-        const bool ok = lane < nwt && w < nw;
+        const bool ok = lane < REGION / 64 && w < nw;
         bw0 = (wave < reps && ok) ? bitmap[wave * bm_stride + w] : 0ull;
         bw1 = (wave + RT_WAVES < reps && ok) ? bitmap[(wave + RT_WAVES) * bm_stride + w] : 0ull;
     };
@@ -1504,12 +1505,14 @@ __attribute__((amdgpu_waves_per_eu(REGION == 2048 ? 4 : 2))) void k_records_tile
         if (tid < 32) reinterpret_cast<uint32_t *>(&td)[tid] = tdw;
         if (tid < 64) r0s[tid] = r0l;
         const uint64_t bc0 = bw0, bc1 = bw1;
-        // U: inclusive sums over the thread's positions, then over the wave, then the block
+        // U: inclusive sums over the thread's positions, then over the wave, then the block;
+        // over the whole region, the halo past the tile included (the partition that runs
+        // past the tile usually ends there)
         uint64_t v[RUN];
         uint64_t acc = 0;
 #pragma unroll
         for (int k = 0; k < RUN; k++) {
-            const uint64_t u = j0 + k < TP ? mulsmall61(q[k], (x[k] & m) + 1u) : 0ull;
+            const uint64_t u = mulsmall61(q[k], (x[k] & m) + 1u);
             acc = addmod61(acc, u);
             v[k] = acc;
         }
@@ -1527,20 +1530,35 @@ __attribute__((amdgpu_waves_per_eu(REGION == 2048 ? 4 : 2))) void k_records_tile
         __syncthreads();  // U, td and the bases in place
         uint16_t *fl = flist[wave];
         for (int rho = wave, round = 0; rho < reps; rho += RT_WAVES, round++) {
-            // lane l: flag word l of the tile, its count prefix, and the tile's flag count
+            // lane l: flag word l of the region; the tile's words (lanes < nwt), their count
+            // prefix and the tile's flag count
             const int64_t w = ts / 64 + lane;
-            const uint64_t b = round == 0 ? bc0
-                             : round == 1 ? bc1
-                                          : ((lane < nwt && w < nw) ? bitmap[rho * bm_stride + w] : 0ull);
+            const uint64_t rw = round == 0 ? bc0
+                              : round == 1 ? bc1
+                                           : ((lane < REGION / 64 && w < nw) ? bitmap[rho * bm_stride + w] : 0ull);
+            const uint64_t b = lane < nwt ? rw : 0ull;
             const int64_t r0 = rho < 64 ? r0s[rho] : rbase[rho] + (int64_t)pre[rho * pre_stride + tile];
             const uint32_t c = (uint32_t)__popcll(b);
             const uint32_t ic = wave_scan_add(c);
             const int nf = __builtin_amdgcn_readlane((int)ic, 63);
-            // the last flag's partition runs past the tile: the tile's slot of the list
+            // The last flag's partition runs past the tile.  When the next flag lies in the
+            // region's halo (flag words nwt .. REGION / 64 - 1, the symbols' U in LDS) it is
+            // appended to the list, which makes that partition the list's last one; else the
+            // tile's slot lists it (-1: done, or no flag) for the per-partition kernel.
             const uint64_t nz = __ballot(b != 0);
+            const uint64_t hnz = __ballot(lane >= nwt && rw != 0);
             int64_t *slot = cross + 2 * ((int64_t)rho * ntiles + tile);
-            if (nz == 0) {
+            int nl = nf;  // entries of the list
+            if (nz == 0 || hnz) {
                 if (lane == 0) slot[0] = -1;
+                if (nz != 0) {
+                    const int hl = __ffsll((unsigned long long)hnz) - 1;
+                    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)rw, hl);
+                    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(rw >> 32), hl);
+                    const uint64_t hbw = ((uint64_t)hi << 32) | lo;
+                    if (lane == 0) fl[nf] = (uint16_t)(64 * hl + __ffsll((unsigned long long)hbw) - 1);
+                    nl = nf + 1;
+                }
             } else if (lane == 63 - __clzll((long long)nz)) {
                 slot[0] = ts + 64 * lane + 63 - __clzll((long long)b);
                 slot[1] = r0 + ic - 1;  // the tile's flags before it: all but itself
@@ -1551,7 +1569,7 @@ __attribute__((amdgpu_waves_per_eu(REGION == 2048 ? 4 : 2))) void k_records_tile
                 for (uint64_t f = b; f; f &= f - 1) fl[rk++] = (uint16_t)(64 * lane + __ffsll((unsigned long long)f) - 1);
             }
             wave_sync();
-            for (int i = lane; i + 1 < nf; i += 64) {
+            for (int i = lane; i + 1 < nl; i += 64) {
                 const int a = fl[i], bb = fl[i + 1], L = bb - a;
                 const uint64_t phi = addmod61(mulsmall61(Pt[L], (uint32_t)L),
                                               mulmod61(Pt[bb - 1], submod61(U[pad(bb)], U[pad(a)])));
