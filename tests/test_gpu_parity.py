@@ -92,6 +92,19 @@ def big_group_collection(seed, sigma):
     return dg.from_list([strs[i] for i in order], sigma)
 
 
+def lazy_big_group_collection(seed, copies):
+    """One cluster of near-copies (0.5% edits) among 3,000 unrelated strings: a few groups
+    of 64 records or more, but fewer pair tests than records, so emission gathers each
+    record's (m, K) by string id (with 70 copies from the length and K arrays, with 80
+    from one packed word per string)."""
+    rng = np.random.default_rng(seed)
+    base = rng.integers(0, 4, 400).astype(np.uint8)
+    strs = [dg.mutate(np.random.default_rng(seed * 1000 + i), base, 0.005, 4) for i in range(copies)]
+    strs += [rng.integers(0, 4, int(rng.integers(600, 1000))).astype(np.uint8) for _ in range(3000)]
+    order = np.random.default_rng(seed + 1).permutation(len(strs))
+    return dg.from_list([strs[i] for i in order], 4)
+
+
 def wide_radius_collection(seed, sigma, n=60):
     """Lengths 50..6000 at T = 2: radii from 7 to ~1000 (regions of 4096 positions, window
     blocks of 8 and 16), plus a homopolymer run (equal q-grams across whole windows)."""
@@ -153,6 +166,9 @@ CASES = {
     "dna_big_groups": dict(make=lambda: big_group_collection(91, 4), q=4, k=20, t_div=1),
     "protein_big_groups": dict(make=lambda: big_group_collection(92, 20), q=3, k_frac=(5, 100),
                                t_div=2),
+    "dna_lazy_big_group": dict(make=lambda: lazy_big_group_collection(93, 70), q=4, k=20, t_div=1),
+    "dna_lazy_big_group_lk": dict(make=lambda: lazy_big_group_collection(93, 80), q=4, k=20,
+                                  t_div=1),
     "dna_wide_radius": dict(make=lambda: wide_radius_collection(31, 4), q=4, k=60, t_fixed=2),
     "text_wide_radius_hashed": dict(make=lambda: wide_radius_collection(32, 37), q=6, k=60,
                                     t_fixed=2),
@@ -641,7 +657,7 @@ def test_member_filter_identical(mj, name, bucket_limit):
 
 @pytest.mark.parametrize("tile_min", [0, -1])
 @pytest.mark.parametrize("name", ["dna_big_groups", "protein_big_groups", "dna_heavy_clusters",
-                                  "text_q6"])
+                                  "text_q6", "dna_lazy_big_group", "dna_lazy_big_group_lk"])
 def test_tile_emission_identical(mj, name, tile_min):
     """Candidate emission with the groups of 64 records or more tested by 64 x 64 tile
     pairs (mj_ctx_set_tile_emission 0: whenever there is one) or every group test by test
