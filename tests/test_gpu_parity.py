@@ -684,6 +684,36 @@ def test_tile_emission_identical(mj, name, tile_min):
     ctx.close()
 
 
+def test_tile_emission_over_2_29_symbols(mj):
+    """At 2^29 symbols or more both emission kernels take the 64-bit filter: 500 random
+    strings of 1,074,000 symbols (K = 2,000) and a cluster of 70 near-copies of 400
+    symbols (K = 20, groups of 64 records and more); candidates and output equal the
+    oracle's with the tile-pair path forced on and off."""
+    import torch
+    say("tile emission over 2^29 symbols")
+    rng = np.random.default_rng(97)
+    strs = [rng.integers(0, 4, 1_074_000, dtype=np.uint8) for _ in range(500)]
+    base = rng.integers(0, 4, 400).astype(np.uint8)
+    strs += [dg.mutate(np.random.default_rng(97000 + i), base, 0.005, 4) for i in range(70)]
+    S = dg.from_list(strs, 4)
+    del strs
+    assert int(S.offsets[-1]) >= 1 << 29
+    kq = np.where(S.lengths() > 100_000, 2000, 20).astype(np.int32)
+    op = oracle.make_params(4, 4, k_per_string=kq, t_div=1)
+    cand_w, out_w, _ = oracle.join(S.chars, S.offsets, op)
+    assert len(out_w) > 0
+    ds = dev(mj, S)
+    gp = mj.Params(q=4, k_per_string=torch.from_numpy(kq).cuda(), t_div=1)
+    for tile_min in (0, -1):
+        ctx = mj.Context()
+        ctx.set_tile_emission(tile_min)
+        cand, _ = mj.candidates(ds, gp, ctx=ctx)
+        assert np.array_equal(cand, cand_w), tile_min
+        out, _ = mj.join(ds, gp, ctx=ctx)
+        assert np.array_equal(out, out_w), tile_min
+        ctx.close()
+
+
 @pytest.mark.parametrize("name", ["dna_heavy_clusters", "protein_per_string_K", "dna_big_groups"])
 def test_join_in_emission_passes(mj, name):
     """A join whose record-pair tests exceed one emission pass (here forced down to 1,024
