@@ -293,6 +293,7 @@ GroupInfo find_groups_streamed(const uint64_t *key, int64_t R_cap, const int64_t
 // evaluated as max(|m_i - m_j|, |(2pos_i - m_i) - (2pos_j - m_j)|) <= K (the same test,
 // since |u| + |v| = max(|u + v|, |u - v|)).
 constexpr int EMIT_CHUNK = 16;
+constexpr int EMIT_BATCH = 4;  // tests whose loads k_emit issues together (divides EMIT_CHUNK)
 
 __device__ __forceinline__ int64_t iabs64(int64_t v) { return v < 0 ? -v : v; }
 
@@ -466,71 +467,104 @@ __global__ __launch_bounds__(EMIT_BLOCK) void k_emit(const uint64_t *__restrict_
             while ((b + 1) * b / 2 <= u) b++;
             a = u - b * (b - 1) / 2;
         }
-        // the group's first record and the first test of the next group, and record b's
-        // words, change only when the group or b does: loaded then, not at every test
-        int64_t s0 = 0, cached_b = -1;
-        uint64_t gend = 0;
-        uint64_t vb = 0, xb = 0;
+        // The run is taken EMIT_BATCH tests at a time: first the walk over the tests (the
+        // records a and b of each; the group bounds, with the next group's preloaded),
+        // then every load of the batch at once, then the filter and the stage.  A lane's
+        // loads thus overlap instead of waiting one test at a time.
+        int64_t s0 = 0, s0n = 0;
+        uint64_t gend = 0, gendn = 0;
         if (active) {
             s0 = gs[g];
             gend = ts[g + 1];
+            if (g + 1 < G) {
+                s0n = gs[g + 1];
+                gendn = ts[g + 2];
+            }
         }
-        for (int c = 0; c < chunk; c++) {
-            uint64_t t = t0 + c;
-            bool live = active && t < P;
-            bool pass = false;
-            uint64_t pairkey = 0;
-            if (live) {
-                auto meta_of = [&](int64_t i, uint64_t v) -> uint64_t {
-                    if constexpr (LAZY) {
-                        const int32_t sid = (int32_t)(v >> 32);
-                        if (lk) return lk[sid];
-                        return ((uint64_t)(uint32_t)len[sid] << 32) | (uint32_t)kk[sid];
-                    } else {
-                        return meta[i];
+        auto meta_of = [&](int64_t i, uint64_t v) -> uint64_t {
+            if constexpr (LAZY) {
+                const int32_t sid = (int32_t)(v >> 32);
+                if (lk) return lk[sid];
+                return ((uint64_t)(uint32_t)len[sid] << 32) | (uint32_t)kk[sid];
+            } else {
+                return meta[i];
+            }
+        };
+        for (int cb = 0; cb < chunk; cb += EMIT_BATCH) {
+            int64_t ra[EMIT_BATCH], rb[EMIT_BATCH];
+            bool lv[EMIT_BATCH];
+#pragma unroll
+            for (int k = 0; k < EMIT_BATCH; k++) {
+                const uint64_t t = t0 + cb + k;
+                lv[k] = active && t < P;
+                ra[k] = s0 + (int64_t)a;
+                rb[k] = s0 + (int64_t)b;
+                if (lv[k]) {
+                    // next test: (a+1, b); else (0, b+1); the group ends where the next
+                    // group's tests start, and groups with no tests in this numbering are
+                    // passed over
+                    a++;
+                    if (a == b) {
+                        a = 0;
+                        b++;
                     }
-                };
-                if ((int64_t)b != cached_b) {
-                    vb = val[s0 + (int64_t)b];
-                    xb = meta_of(s0 + (int64_t)b, vb);
-                    cached_b = (int64_t)b;
-                }
-                const uint64_t va = val[s0 + (int64_t)a], xa = meta_of(s0 + (int64_t)a, va);
-                int32_t ia = (int32_t)(va >> 32), ib = (int32_t)(vb >> 32);
-                if (ia != ib) {
-                    if constexpr (SMALL) {
-                        pass = pass_filter32((int32_t)(xa >> 32), (int32_t)(uint32_t)va,
-                                             (int32_t)(xb >> 32), (int32_t)(uint32_t)vb,
-                                             max((uint32_t)xa, (uint32_t)xb));
-                    } else {
-                        const int64_t ma = (int64_t)(xa >> 32), mb = (int64_t)(xb >> 32);
-                        const int64_t K = max((int64_t)(uint32_t)xa, (int64_t)(uint32_t)xb);
-                        pass = pass_filter(ma, (int64_t)(uint32_t)va, mb, (int64_t)(uint32_t)vb, K);
-                    }
-                    uint64_t lo = (uint64_t)min(ia, ib), hi = (uint64_t)max(ia, ib);
-                    pairkey = (lo << 32) | hi;
-                }
-                // next test: (a+1, b); else (0, b+1); the group ends where the next group's
-                // tests start, and groups with no tests in this numbering are passed over
-                a++;
-                if (a == b) {
-                    a = 0;
-                    b++;
-                }
-                if (t + 1 == gend && g + 1 < G) {
-                    do {
+                    if (t + 1 == gend && g + 1 < G) {
                         g++;
-                        gend = ts[g + 1];
-                    } while (gend == t + 1 && g + 1 < G);
-                    a = 0;
-                    b = 1;
-                    s0 = gs[g];
-                    cached_b = -1;
+                        s0 = s0n;
+                        gend = gendn;
+                        while (gend == t + 1 && g + 1 < G) {
+                            g++;
+                            s0 = gs[g];
+                            gend = ts[g + 1];
+                        }
+                        if (g + 1 < G) {
+                            s0n = gs[g + 1];
+                            gendn = ts[g + 2];
+                        }
+                        a = 0;
+                        b = 1;
+                    }
                 }
             }
-            stage(pass, pairkey, st);
-            // the stage holds EMIT_CHUNK tests per thread (chunk is a multiple of it)
-            if ((c & (EMIT_CHUNK - 1)) == EMIT_CHUNK - 1) flush(st, counter, out, cap);
+            uint64_t va[EMIT_BATCH], vb[EMIT_BATCH], xa[EMIT_BATCH], xb[EMIT_BATCH];
+#pragma unroll
+            for (int k = 0; k < EMIT_BATCH; k++) {
+                va[k] = lv[k] ? val[ra[k]] : 0ull;
+                vb[k] = lv[k] ? val[rb[k]] : 0ull;
+                if constexpr (!LAZY) {
+                    xa[k] = lv[k] ? meta[ra[k]] : 0ull;
+                    xb[k] = lv[k] ? meta[rb[k]] : 0ull;
+                }
+            }
+            if constexpr (LAZY) {
+#pragma unroll
+                for (int k = 0; k < EMIT_BATCH; k++) {
+                    xa[k] = lv[k] ? meta_of(ra[k], va[k]) : 0ull;
+                    xb[k] = lv[k] ? meta_of(rb[k], vb[k]) : 0ull;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < EMIT_BATCH; k++) {
+                bool pass = false;
+                uint64_t pairkey = 0;
+                const int32_t ia = (int32_t)(va[k] >> 32), ib = (int32_t)(vb[k] >> 32);
+                if (lv[k] && ia != ib) {
+                    if constexpr (SMALL) {
+                        pass = pass_filter32((int32_t)(xa[k] >> 32), (int32_t)(uint32_t)va[k],
+                                             (int32_t)(xb[k] >> 32), (int32_t)(uint32_t)vb[k],
+                                             max((uint32_t)xa[k], (uint32_t)xb[k]));
+                    } else {
+                        const int64_t ma = (int64_t)(xa[k] >> 32), mb = (int64_t)(xb[k] >> 32);
+                        const int64_t K = max((int64_t)(uint32_t)xa[k], (int64_t)(uint32_t)xb[k]);
+                        pass = pass_filter(ma, (int64_t)(uint32_t)va[k], mb, (int64_t)(uint32_t)vb[k], K);
+                    }
+                    const uint64_t lo = (uint64_t)min(ia, ib), hi = (uint64_t)max(ia, ib);
+                    pairkey = (lo << 32) | hi;
+                }
+                stage(pass, pairkey, st);
+                // the stage holds EMIT_CHUNK tests per thread (chunk is a multiple of it)
+                if (((cb + k) & (EMIT_CHUNK - 1)) == EMIT_CHUNK - 1) flush(st, counter, out, cap);
+            }
         }
     }
 }
